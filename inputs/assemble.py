@@ -139,6 +139,7 @@ class Problem:
         vred = np.nonzero(~isD5)[0]
         self.red_of_full = -np.ones(self.Nv, np.int64)
         self.red_of_full[vred] = np.arange(len(vred))
+        self.full_of_red = vred
         self.Nvr = len(vred)
         self.Nr = self.Nvr + m.nK  # + one constant pressure per element
         self.red_dir = np.zeros(self.Nr, bool)

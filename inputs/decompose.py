@@ -131,7 +131,7 @@ class Decomposition:
         pb, m, L = self.pb, self.pb.mesh, self.pb.L
         info = {}
         for r in self.iface_red:
-            full = np.nonzero(pb.red_of_full == r)[0][0]
+            full = pb.full_of_red[r]
             if full < pb.offE:
                 v = full // 3
                 idx = m.vidx[v]
@@ -160,7 +160,7 @@ class Decomposition:
         self.ent_con_tag = []
         for e, dofs in enumerate(self.ent_dofs):
             red = self.iface_red[dofs]
-            full = np.array([np.nonzero(pb.red_of_full == r)[0][0] for r in red])
+            full = pb.full_of_red[red]
             nd = len(dofs)
             rows, tags = [], []
             kind = self.ent_kind[e]
@@ -180,7 +180,7 @@ class Decomposition:
                             v = fdof // 3
                             # adjacent element edges of the macro edge
                             acc = 0.0
-                            for ee in np.nonzero((m.edge_verts[:, 0] == v) | (m.edge_verts[:, 1] == v))[0]:
+                            for ee in self._edges_of_vertex(v):
                                 if self._edge_in_entity(ee, e):
                                     ln = np.linalg.norm(m.verts[m.edge_verts[ee, 1]] - m.verts[m.edge_verts[ee, 0]])
                                     acc += ln * (wl[0] if m.edge_verts[ee, 0] == v else wl[-1])
@@ -222,6 +222,18 @@ class Decomposition:
                     tags.append("flux")
             self.ent_con.append(np.array(rows).reshape(len(rows), nd))
             self.ent_con_tag.append(tags)
+
+    def _edges_of_vertex(self, v):
+        m = self.pb.mesh
+        if not hasattr(self, "_v2e"):
+            ev = m.edge_verts
+            order = np.argsort(np.concatenate([ev[:, 0], ev[:, 1]]), kind="stable")
+            eids = np.concatenate([np.arange(m.nE), np.arange(m.nE)])[order]
+            vs = np.concatenate([ev[:, 0], ev[:, 1]])[order]
+            ptr = np.searchsorted(vs, np.arange(m.nV + 1))
+            self._v2e = (ptr, eids)
+        ptr, eids = self._v2e
+        return eids[ptr[v]:ptr[v + 1]]
 
     def _entity_edges(self, e):
         """Element edges lying inside macro edge e."""

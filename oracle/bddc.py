@@ -1,0 +1,279 @@
+"""FP64 reference BDDC for the interface saddle-point problem (Sec. 4).
+
+Input: the plain-data workload (per-subdomain reduced local saddle matrices
+in CSR, DoF kinds, global interface ids, element volumes of the pressure
+DoFs, local right-hand sides; per-entity constraint functionals).
+
+Steps, in the paper's order:
+
+* interior/interface split and Q = Q_I + Q_0 (eq. discVQ): element-constant
+  pressures of subdomain i are split into the volume-weighted mean-zero part
+  Q_I and the constant p0_i.  Here Q_I is imposed with a Lagrange multiplier
+  on the weighted mean, which spans the same space as any explicit basis;
+* Dirichlet problems (eq. uipi) and the local Stokes Schur complement
+  S_Gamma^(i) (eq. firstSchur), formed densely from sparse-LU solves;
+  condensed right-hand side g (eq. globInt);
+* the global interface operator S_hat = sum R^T [[S, B0^T],[B0, 0]] R
+  (eqs. globInt, ScapGdef);
+* change of basis making each primal functional an explicit DoF (Sec. 4.3):
+  per entity an orthonormal [Q_Pi Q_Delta] from the SVD of its constraint
+  rows, dependent rows dropped (Sec. 5.1);
+* scaling: deluxe D_E^(m) = (sum_l Sbar_E^(l))^-1 Sbar_E^(m) on the dual
+  coordinates of each entity (Sec. 6), or counting 1/card (eq. pseudoinv);
+* M^-1 = Rt_D^T St^-1 Rt_D (eq. BDDCprec), split into local constrained
+  Neumann solves and a coarse saddle problem in the primal variables and
+  p0; with no-slip boundaries the coarse problem inherits the constant-p0
+  kernel and is bordered with the constraint sum |Omega_i| p0_i = 0.
+"""
+import numpy as np
+import scipy.sparse as sp
+import scipy.linalg as sla
+from scipy.sparse.linalg import splu
+
+KIND_INTERIOR, KIND_INTERFACE, KIND_PRESSURE = 0, 1, 2
+
+
+class LocalSchur:
+    """Static condensation of one subdomain (eqs. uipi, firstSchur)."""
+
+    def __init__(self, sd):
+        n = len(sd["kind"])
+        K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(n, n))
+        kind = sd["kind"]
+        self.iv = np.nonzero(kind == KIND_INTERIOR)[0]
+        self.ig = np.nonzero(kind == KIND_INTERFACE)[0]
+        self.ip = np.nonzero(kind == KIND_PRESSURE)[0]
+        self.gid = sd["gid"][self.ig]
+        w = sd["pweight"][self.ip]
+        self.w = w
+        nv, npr = len(self.iv), len(self.ip)
+        A_II = K[self.iv][:, self.iv]
+        Bp_I = K[self.ip][:, self.iv]
+        A_IG = K[self.iv][:, self.ig]
+        Bp_G = K[self.ip][:, self.ig]
+        self.A_GG = K[self.ig][:, self.ig].toarray()
+        # K_II' = [[A, Bp^T, 0], [Bp, 0, w], [0, w^T, 0]]: pressures in Q_I
+        Kii = sp.bmat([[A_II, Bp_I.T, None],
+                       [Bp_I, None, sp.csr_matrix(w[:, None])],
+                       [None, sp.csr_matrix(w[None, :]), None]]).tocsc()
+        self.lu = splu(Kii)
+        self.nv, self.npr = nv, npr
+        C = sp.vstack([A_IG, Bp_G, sp.csr_matrix((1, len(self.ig)))]).toarray()
+        self.C = C
+        X = self.lu.solve(C)
+        self.S = self.A_GG - C.T @ X
+        rhs = sd["rhs"]
+        self.f_I = rhs[self.iv]
+        self.f_G = rhs[self.ig]
+        self.h_p = rhs[self.ip]
+        xb = self.lu.solve(np.concatenate([self.f_I, self.h_p, [0.0]]))
+        self.g = self.f_G - C.T @ xb
+        # p0 row: B0_Gamma = sum of the element flux rows on the interface
+        self.B0 = np.asarray(Bp_G.sum(axis=0)).ravel()
+        self.g0 = float(self.h_p.sum())
+        self.vol = float(w.sum())
+
+    def recover(self, uG, p0):
+        """Interior velocity and element pressures from (u_Gamma, p0)."""
+        rhs = np.concatenate([self.f_I, self.h_p, [0.0]]) - self.C @ uG
+        x = self.lu.solve(rhs)
+        uI = x[: self.nv]
+        c = x[self.nv: self.nv + self.npr] + p0
+        return uI, c
+
+
+class OracleBDDC:
+    def __init__(self, wl, scaling="deluxe", adaptive_theta=0.0, svd_tol=1e-10):
+        self.wl = wl
+        self.nG = wl["n_iface"]
+        self.loc = [LocalSchur(sd) for sd in wl["subs"]]
+        self.N = len(self.loc)
+        self.n = self.nG + self.N  # global interface vector: u_Gamma then p0
+        self.svd_tol = svd_tol
+        self.scaling = scaling
+        self.adaptive_theta = adaptive_theta
+        # entities
+        self.ents = wl["ents"]
+        self.ent_of_gid = np.zeros(self.nG, np.int64)
+        for e, E in enumerate(self.ents):
+            self.ent_of_gid[E["gids"]] = e
+        self.ent_subs = [[] for _ in self.ents]
+        for i, L in enumerate(self.loc):
+            for e in np.unique(self.ent_of_gid[L.gid]):
+                self.ent_subs[e].append(i)
+        self.extra_rows = [None] * len(self.ents)
+        self._setup_basis()
+        if adaptive_theta > 0:
+            from .adaptive import adaptive_rows
+            self.eig_info = adaptive_rows(self, adaptive_theta)
+            self._setup_basis()
+        self._setup_scaling()
+        self._setup_coarse()
+
+    # ------------------------------------------------------------------ basis
+    def _setup_basis(self):
+        """Per entity: orthonormal [Q_Pi | Q_Delta] from the SVD of the
+        constraint rows (dependent rows dropped, Sec. 5.1)."""
+        self.Q = []
+        self.npi = []
+        for e, E in enumerate(self.ents):
+            C = E["con"]
+            if self.extra_rows[e] is not None:
+                C = np.vstack([C, self.extra_rows[e]]) if C.size else self.extra_rows[e]
+            nE = len(E["gids"])
+            if C.shape[0] == 0:
+                self.Q.append(np.eye(nE))
+                self.npi.append(0)
+                continue
+            U, s, Vt = np.linalg.svd(C, full_matrices=True)
+            r = int(np.sum(s > self.svd_tol * s[0]))
+            self.Q.append(Vt.T.copy())  # first r columns span the constraints
+            self.npi.append(r)
+        # global transformed coordinates: per entity [primal | dual]
+        self.T = np.zeros((self.nG, self.nG))
+        self.pi_idx, self.de_idx = [], []
+        for e, E in enumerate(self.ents):
+            g = E["gids"]
+            self.T[np.ix_(g, g)] = self.Q[e]
+            self.pi_idx.append(g[: self.npi[e]])
+            self.de_idx.append(g[self.npi[e]:])
+        # (transformed coordinate j of entity e is stored at position gids[j])
+        self.is_primal = np.zeros(self.nG, bool)
+        for e in range(len(self.ents)):
+            self.is_primal[self.pi_idx[e]] = True
+        for L in self.loc:
+            Tl = self.T[np.ix_(L.gid, L.gid)]
+            L.St = Tl.T @ L.S @ Tl
+            L.B0t = L.B0 @ Tl
+            L.prim = self.is_primal[L.gid]
+            L.gt = Tl.T @ L.g
+
+    # ---------------------------------------------------------------- scaling
+    def _setup_scaling(self):
+        """D_E^(m) per entity and subdomain on the dual coordinates."""
+        self.D = {}
+        for e, E in enumerate(self.ents):
+            dual = self.de_idx[e]
+            if len(dual) == 0:
+                continue
+            subs = self.ent_subs[e]
+            blocks = {}
+            for i in subs:
+                L = self.loc[i]
+                pos = np.searchsorted(L.gid, dual) if np.all(np.diff(L.gid) > 0) else \
+                    np.array([np.nonzero(L.gid == d)[0][0] for d in dual])
+                blocks[i] = (pos, L.St[np.ix_(pos, pos)])
+            if self.scaling == "deluxe":
+                Ssum = sum(b[1] for b in blocks.values())
+                for i in subs:
+                    self.D[(e, i)] = (blocks[i][0], np.linalg.solve(Ssum, blocks[i][1]))
+            else:
+                for i in subs:
+                    self.D[(e, i)] = (blocks[i][0], np.eye(len(dual)) / len(subs))
+
+    # ----------------------------------------------------------------- coarse
+    def _setup_coarse(self):
+        """Local constrained Neumann factors and the bordered coarse matrix."""
+        gprim = np.nonzero(self.is_primal)[0]
+        self.nc = len(gprim)
+        cidx = -np.ones(self.nG, np.int64)
+        cidx[gprim] = np.arange(self.nc)
+        self.cidx = cidx
+        Kc = np.zeros((self.nc + self.N + 1, self.nc + self.N + 1))
+        for i, L in enumerate(self.loc):
+            P = np.nonzero(L.prim)[0]
+            Dl = np.nonzero(~L.prim)[0]
+            L.P, L.Dl = P, Dl
+            S_DD = L.St[np.ix_(Dl, Dl)]
+            S_DP = L.St[np.ix_(Dl, P)]
+            L.cho = sla.cho_factor(S_DD) if len(Dl) else None
+            L.Phi = -sla.cho_solve(L.cho, S_DP) if len(Dl) else np.zeros((0, len(P)))
+            SPi = L.St[np.ix_(P, P)] + S_DP.T @ L.Phi
+            c = cidx[L.gid[P]]
+            Kc[np.ix_(c, c)] += SPi
+            # B0 in primal coordinates (the dual part vanishes: Assumption 1)
+            Kc[self.nc + i, c] += L.B0t[P]
+            Kc[c, self.nc + i] += L.B0t[P]
+            L.B0_dual_norm = np.abs(L.B0t[Dl]).max() if len(Dl) else 0.0
+        vol = np.array([L.vol for L in self.loc])
+        Kc[-1, self.nc: self.nc + self.N] = vol
+        Kc[self.nc: self.nc + self.N, -1] = vol
+        self.Kc = Kc
+        self.Kc_lu = sla.lu_factor(Kc)
+
+    # ------------------------------------------------------------- operators
+    def rhs(self):
+        """g_hat (eq. globInt) in original coordinates."""
+        g = np.zeros(self.n)
+        for i, L in enumerate(self.loc):
+            np.add.at(g, L.gid, L.g)
+            g[self.nG + i] = L.g0
+        return g
+
+    def apply_S(self, x):
+        """S_hat x in original coordinates."""
+        y = np.zeros(self.n)
+        for i, L in enumerate(self.loc):
+            xl = x[L.gid]
+            p0 = x[self.nG + i]
+            np.add.at(y, L.gid, L.S @ xl + L.B0 * p0)
+            y[self.nG + i] = L.B0 @ xl
+        return y
+
+    def apply_M(self, r):
+        """z = M^-1 r (eq. BDDCprec) in original coordinates."""
+        rt = np.concatenate([self.T.T @ r[: self.nG], r[self.nG:]])
+        # restriction: primal and p0 pass through, duals scaled
+        rc = np.zeros(self.nc + self.N + 1)
+        gpr = np.nonzero(self.is_primal)[0]
+        rc[self.cidx[gpr]] = rt[gpr]
+        rc[self.nc: self.nc + self.N] = rt[self.nG:]
+        gD = []
+        for i, L in enumerate(self.loc):
+            g = np.zeros(len(L.Dl))
+            gD.append(g)
+        for (e, i), (pos, D) in self.D.items():
+            L = self.loc[i]
+            dual = self.de_idx[e]
+            # local dual position of pos within L.Dl
+            loc_in_D = np.searchsorted(L.Dl, pos)
+            gD[i][loc_in_D] += D.T @ rt[dual]
+        for i, L in enumerate(self.loc):
+            if len(L.Dl):
+                c = self.cidx[L.gid[L.P]]
+                np.add.at(rc, c, L.Phi.T @ gD[i])
+        uc = sla.lu_solve(self.Kc_lu, rc)
+        zt = np.zeros(self.n)
+        zt[gpr] = uc[self.cidx[gpr]]
+        zt[self.nG:] = uc[self.nc: self.nc + self.N]
+        wD = []
+        for i, L in enumerate(self.loc):
+            if len(L.Dl):
+                c = self.cidx[L.gid[L.P]]
+                w = sla.cho_solve(L.cho, gD[i]) + L.Phi @ uc[c]
+            else:
+                w = np.zeros(0)
+            wD.append(w)
+        for (e, i), (pos, D) in self.D.items():
+            L = self.loc[i]
+            dual = self.de_idx[e]
+            loc_in_D = np.searchsorted(L.Dl, pos)
+            zt[dual] += D @ wD[i][loc_in_D]
+        return np.concatenate([self.T @ zt[: self.nG], zt[self.nG:]])
+
+    def recover(self, x):
+        """Per-subdomain (u_I, element pressures) from the interface solution."""
+        out = []
+        for i, L in enumerate(self.loc):
+            out.append(L.recover(x[L.gid], x[self.nG + i]))
+        return out
+
+    def dense_S(self):
+        """Dense S_hat (tiny problems only)."""
+        S = np.zeros((self.n, self.n))
+        for i, L in enumerate(self.loc):
+            g = L.gid
+            S[np.ix_(g, g)] += L.S
+            S[self.nG + i, g] += L.B0
+            S[g, self.nG + i] += L.B0
+        return S

@@ -1,0 +1,213 @@
+"""Pins of the workload generator (virtual element discretisation, Sec. 3)
+against what the paper and the mathematics fix."""
+import os
+from math import factorial
+
+import numpy as np
+import pytest
+
+from inputs.mesh import CubeMesh
+from inputs.quadrature import tet_rule, triangle_rule
+from inputs.vem import element_matrices, interpolate, element_quadrature
+from inputs.poly import mono3, eval3, dim3
+from inputs.assemble import Problem, u_curl, grad_u_curl
+from inputs.decompose import Decomposition, regular_cuts, random_cuts
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def closed_form_dofs(n, k):
+    """3(N_V + (k-1)N_E + dim P_{k-2}(f) N_F) + (D4 + D5 + dim P_{k-1}) N_K."""
+    d3 = lambda m: 0 if m < 0 else (m + 1) * (m + 2) * (m + 3) // 6
+    nV, nE, nF, nK = (n + 1) ** 3, 3 * n * (n + 1) ** 2, 3 * n * n * (n + 1), n ** 3
+    d4 = 3 * d3(k - 3) - d3(k - 4)
+    d5 = d3(k - 1) - 1
+    return 3 * (nV + (k - 1) * nE + (k * (k - 1) // 2) * nF) + (d4 + d5 + d3(k - 1)) * nK
+
+
+def _rows():
+    out = []
+    for line in open(os.path.join(GOLDEN, "paper_cube_dofs.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        p = line.split()
+        out.append((int(p[0]), int(p[1]), int(p[2])))
+    return out
+
+
+def test_quadrature_exact_on_monomials():
+    P = np.array([[0, 0, 0], [1, 0, 0], [0, 1, 0], [0, 0, 1.0]])
+    lam, w = tet_rule(7)
+    X = lam @ P
+    for a, b, c in [(3, 2, 2), (0, 0, 7), (1, 4, 2)]:
+        ex = factorial(a) * factorial(b) * factorial(c) / factorial(a + b + c + 3)
+        assert abs((w / 6 * X[:, 0] ** a * X[:, 1] ** b * X[:, 2] ** c).sum() - ex) < 1e-15
+    lam, w = triangle_rule(6)
+    X = lam @ P[:3, :2]
+    for a, b in [(3, 3), (6, 0)]:
+        ex = factorial(a) * factorial(b) / factorial(a + b + 2)
+        assert abs((w / 2 * X[:, 0] ** a * X[:, 1] ** b).sum() - ex) < 1e-15
+
+
+def test_dof_counts_match_paper_tables():
+    for n, k, printed in _rows():
+        cf = closed_form_dofs(n, k)
+        if (n, k) == (20, 2):
+            assert printed - cf == 1000  # the one row read as a typo
+        else:
+            assert cf == printed, (n, k)
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_generator_counts_equal_closed_form(k):
+    pb = Problem(CubeMesh(8), k)
+    assert pb.Nv + pb.Np == closed_form_dofs(8, k)
+
+
+def test_jittered_mesh_planar_faces_and_bound():
+    m = CubeMesh(6, jitter=0.15, seed=4)
+    X = m.verts[m.face_verts]
+    plan = np.abs(np.einsum("fqi,fi->fq", X - X[:, :1], m.face_normal)).max()
+    assert plan < 1e-14
+    assert np.abs(m.verts - m.vidx * m.h).max() <= 0.15 * m.h + 1e-15
+    assert abs(m.elem_vol.sum() - 1.0) < 1e-13
+
+
+def _poly_field(k, seed):
+    rng = np.random.default_rng(seed)
+    ex = np.array(mono3(k))
+    C = rng.standard_normal((3, len(ex)))
+
+    def u(X):
+        return np.stack([X[..., 0] ** a * X[..., 1] ** b * X[..., 2] ** c for a, b, c in ex], -1) @ C.T
+
+    def grad(X):
+        G = np.zeros(X.shape[:-1] + (3, 3))
+        for d in range(3):
+            e = ex.copy()
+            f = e[:, d].copy()
+            e[:, d] = np.maximum(e[:, d] - 1, 0)
+            P = np.stack([X[..., 0] ** a * X[..., 1] ** b * X[..., 2] ** c for a, b, c in e], -1) * f
+            G[..., :, d] = P @ C.T
+        return G
+
+    def div(X):
+        return np.einsum("...cc->...", grad(X))
+
+    return u, grad, div
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_projections_reproduce_polynomials(k):
+    m = CubeMesh(3, jitter=0.15, seed=1)
+    el = np.arange(m.nK)
+    out = element_matrices(m, k, el, 1.0, keep=True)
+    u, grad, div = _poly_field(k, 0)
+    d = interpolate(m, k, el, u, div)
+    rng = np.random.default_rng(5)
+    X = m.elem_xbar[:, None, :] + 0.02 * rng.standard_normal((m.nK, 4, 3))
+    Mx = eval3((X - m.elem_centroid[:, None]) / m.elem_diam[:, None, None], k)
+    for key in ("PiN", "P0"):
+        c = np.einsum("ecbn,en->ecb", out[key], d)
+        assert np.abs(np.einsum("eqb,ecb->eqc", Mx, c) - u(X)).max() < 1e-12
+    # Pi^0_{k-1} grad v = grad v
+    Mg = eval3((X - m.elem_centroid[:, None]) / m.elem_diam[:, None, None], k - 1)
+    G = np.einsum("ecdan,en->ecda", out["Gc"], d)
+    assert np.abs(np.einsum("eqa,ecda->eqcd", Mg, G) - grad(X)).max() < 1e-11
+    # divergence reconstruction
+    dv = np.einsum("ean,en->ea", out["div"], d)
+    assert np.abs(np.einsum("eqa,ea->eq", Mg, dv) - div(X)).max() < 1e-11
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_element_stiffness_rigid_kernel_and_consistency(k):
+    m = CubeMesh(3, jitter=0.15, seed=2)
+    el = np.arange(m.nK)
+    out = element_matrices(m, k, el, 1.0, keep=True)
+    A = out["A"]
+    assert np.abs(A - A.transpose(0, 2, 1)).max() < 1e-12 * np.abs(A).max()
+    ev = np.linalg.eigvalsh(A)
+    scale = ev[:, -1:]
+    assert np.all(np.abs(ev[:, :6]) < 1e-12 * scale)  # exactly the 6 rigid modes
+    assert np.all(ev[:, 6] > 1e-8 * scale[:, 0])
+    u1, g1, d1 = _poly_field(k, 1)
+    u2, g2, d2 = _poly_field(k, 2)
+    a1 = interpolate(m, k, el, u1, d1)
+    a2 = interpolate(m, k, el, u2, d2)
+    P, W = element_quadrature(m, el, 2 * k + 2)
+    e1 = g1(P)
+    e2 = g2(P)
+    e1 = 0.5 * (e1 + np.swapaxes(e1, -1, -2))
+    e2 = 0.5 * (e2 + np.swapaxes(e2, -1, -2))
+    exact = np.einsum("eq,eqcd,eqcd->e", W, e1, e2)
+    ah = np.einsum("en,enm,em->e", a1, A, a2)
+    assert np.abs(ah - exact).max() < 1e-11
+    # divergence rows are exact: b(v, m_a) = int div v m_a
+    Mq = eval3((P - m.elem_centroid[:, None]) / m.elem_diam[:, None, None], k - 1)
+    exB = np.einsum("eq,eq,eqa->ea", W, d1(P), Mq)
+    assert np.abs(np.einsum("ean,en->ea", out["B"], a1) - exB).max() < 1e-13
+
+
+@pytest.mark.parametrize("k", [2, 3])
+def test_patch_test_reduced_and_full(k):
+    """u=(y^2,z^2,x^2), p=x+y+z-3/2 (div u = 0) solve -div(nu eps(u)) - grad p = f
+    with f = -(nu+1)(1,1,1); the discrete solution is the interpolant."""
+    m = CubeMesh(3, jitter=0.15, seed=3)
+    u = lambda X: np.stack([X[..., 1] ** 2, X[..., 2] ** 2, X[..., 0] ** 2], -1)
+    zero = lambda X: 0 * X[..., 0]
+    f = lambda P, el: -2.0 * np.ones(P.shape)
+    pb = Problem(m, k, 1.0, force=f, uD=u, divD=zero, keep_full=True, workers=1)
+    x = pb.solve_reduced_direct()
+    el = np.arange(m.nK)
+    d = interpolate(m, k, el, u, zero)
+    ui = np.zeros(pb.Nv)
+    ui[pb.gmap.ravel()] = d.ravel()
+    assert np.abs(x[: pb.Nvr] - ui[pb.full_of_red]).max() < 1e-10
+    assert np.abs(x[pb.Nvr:] - (m.elem_centroid.sum(1) - 1.5)).max() < 1e-9
+    uf, pf = pb.full_system_direct()
+    assert np.abs(uf[pb.full_of_red] - x[: pb.Nvr]).max() < 1e-10
+
+
+def test_discrete_velocity_divergence_free():
+    """div V_h in Q_h: D5(u_h) = 0 and every element flux vanishes."""
+    m = CubeMesh(4, jitter=0.15, seed=0)
+    pb = Problem(m, 2, 1.0, keep_full=True, workers=1)
+    uf, pf = pb.full_system_direct()
+    scale = np.abs(uf).max()
+    isD5 = np.ones(pb.Nv, bool)
+    isD5[pb.full_of_red] = False
+    assert np.abs(uf[isD5]).max() < 1e-10 * scale  # round-off of the direct solve
+    fl = np.einsum("en,en->e", pb.full["B"][:, 0, :], uf[pb.gmap])
+    assert np.abs(fl).max() < 1e-10 * scale
+
+
+def test_h_convergence_rate():
+    """eq. teoConv: |u - Pi u_h|_{1,h} and ||p - p_h||_0 decay like h^k (k=2)."""
+    from oracle.postprocess import errors
+    eu, ep = [], []
+    for n in (2, 4, 8):
+        pb = Problem(CubeMesh(n), 2, 1.0, keep_full=True, workers=1)
+        uf, pf = pb.full_system_direct()
+        a, b = errors(pb, uf, pf, grad_u_curl, lambda X: 0 * X[..., 0])
+        eu.append(a)
+        ep.append(b)
+    ru = np.log2(eu[1] / eu[2])
+    rp = np.log2(ep[1] / ep[2])
+    assert 1.8 < ru < 2.6, eu
+    assert rp > 1.7, ep
+
+
+def test_decomposition_sizes_c1():
+    pb = Problem(CubeMesh(8), 2)
+    dec = Decomposition(pb, regular_cuts(8, (2, 2, 2)), ("vertex", "edge", "flux"))
+    assert dec.n_iface == 1893
+    kinds = np.array(dec.ent_kind)
+    assert (kinds == 0).sum() == 1 and (kinds == 1).sum() == 6 and (kinds == 2).sum() == 12
+    for sd in dec.subs:
+        assert ((sd.kind == 0).sum(), (sd.kind == 1).sum(), (sd.kind == 2).sum()) == (837, 507, 64)
+
+
+def test_random_cuts_seed0():
+    c = random_cuts(48, 4, 12, 6, 0)
+    assert [list(x) for x in c] == [[0, 7, 15, 24, 31, 36, 48], [0, 10, 21, 25, 34, 42, 48],
+                                    [0, 10, 18, 24, 28, 36, 48]]

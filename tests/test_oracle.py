@@ -1,0 +1,192 @@
+"""Pins of the CPU oracle (BDDC + PCG, Sec. 4-5) against what the paper and
+the mathematics fix: brute-force dense Schur complements and direct solves
+on tiny meshes, the kernel of S_hat, Assumption 1, the all-primal special
+case, the minimum eigenvalue 1 of Theorem teoEst, symmetry of M^-1 and the
+(1 + log(H/h))^2 trend."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+from inputs.mesh import CubeMesh
+from inputs.assemble import Problem
+from inputs.decompose import Decomposition, regular_cuts
+from oracle.bddc import OracleBDDC
+from oracle.pcg import pcg, lanczos_extremes
+
+MIN = ("vertex", "edge", "flux")
+FULL = ("vertex", "edge", "face", "flux")
+
+
+def _setup(n, parts, cons, jitter=0.0, seed=0, scaling="deluxe"):
+    pb = Problem(CubeMesh(n, jitter=jitter, seed=seed), 2, 1.0, workers=1)
+    dec = Decomposition(pb, regular_cuts(n, parts), cons)
+    return pb, dec, OracleBDDC(dec.workload(), scaling=scaling)
+
+
+@pytest.fixture(scope="module")
+def tiny():
+    return _setup(4, (2, 2, 2), MIN)
+
+
+@pytest.fixture(scope="module")
+def tiny_jit():
+    return _setup(4, (2, 2, 2), FULL, jitter=0.15, seed=7)
+
+
+def _dense_interface_schur(pb, dec):
+    """Brute force: eliminate all interior velocities and the Q_I pressures
+    of the assembled global reduced system; the remaining unknowns are
+    (u_Gamma, p0).  Q_I basis per subdomain from an explicit null space."""
+    K, g, free = pb.reduced_system()
+    K = K.toarray()
+    Nvr = pb.Nvr
+    pos = {r: i for i, r in enumerate(free)}
+    n_free = len(free)
+    iface = [pos[r] for r in dec.iface_red]
+    vel_int = [i for i, r in enumerate(free) if r < Nvr and dec.gid_of_red[r] < 0]
+    # pressure change of basis c = sum_i (QI_i q_i + 1 p0_i)
+    cols_q, cols_p0 = [], []
+    for i, sd in enumerate(dec.subs):
+        el = sd.elems
+        w = pb.mesh.elem_vol[el]
+        QI = sla.null_space(w[None, :])
+        for j in range(QI.shape[1]):
+            v = np.zeros(n_free)
+            v[[pos[Nvr + e] for e in el]] = QI[:, j]
+            cols_q.append(v)
+        v = np.zeros(n_free)
+        v[[pos[Nvr + e] for e in el]] = 1.0
+        cols_p0.append(v)
+    E = np.zeros((n_free, 0))
+    basis = []
+    for i in vel_int:
+        v = np.zeros(n_free)
+        v[i] = 1.0
+        basis.append(v)
+    nI = len(basis) + len(cols_q)
+    basis += cols_q
+    for i in iface:
+        v = np.zeros(n_free)
+        v[i] = 1.0
+        basis.append(v)
+    basis += cols_p0
+    T = np.array(basis).T
+    Kt = T.T @ K @ T
+    gt = T.T @ g
+    A, B, C, D = Kt[:nI, :nI], Kt[:nI, nI:], Kt[nI:, :nI], Kt[nI:, nI:]
+    S = D - C @ np.linalg.solve(A, B)
+    gs = gt[nI:] - C @ np.linalg.solve(A, gt[:nI])
+    return S, gs
+
+
+def test_schur_and_rhs_match_brute_force(tiny_jit):
+    pb, dec, o = tiny_jit
+    S, gs = _dense_interface_schur(pb, dec)
+    Sd = o.dense_S()
+    assert np.abs(Sd - S).max() < 1e-11 * np.abs(S).max()
+    assert np.abs(o.rhs() - gs).max() < 1e-11 * np.abs(gs).max()
+
+
+def test_kernel_of_S_hat_is_constant_p0(tiny):
+    pb, dec, o = tiny
+    S = o.dense_S()
+    ev, V = np.linalg.eigh(S)
+    small = np.abs(ev) < 1e-10 * np.abs(ev).max()
+    assert small.sum() == 1
+    v = V[:, np.argmin(np.abs(ev))]
+    assert np.abs(v[: o.nG]).max() < 1e-8
+    assert np.allclose(np.abs(v[o.nG:]), np.abs(v[o.nG:]).mean(), rtol=1e-8)
+
+
+def test_floating_subdomain_schur_has_rigid_kernel():
+    pb, dec, o = _setup(6, (3, 3, 3), MIN)
+    mid = 13  # the subdomain not touching the boundary
+    S = o.loc[mid].S
+    assert np.abs(S - S.T).max() < 1e-12 * np.abs(S).max()
+    ev = np.linalg.eigvalsh(S)
+    assert np.all(np.abs(ev[:6]) < 1e-10 * ev[-1]) and ev[6] > 1e-6 * ev[-1]
+    ev0 = np.linalg.eigvalsh(o.loc[0].S)  # touches the Dirichlet boundary: SPD
+    assert ev0[0] > 1e-8 * ev0[-1]
+
+
+def test_assumption1_flux_vanishes_on_dual(tiny_jit):
+    pb, dec, o = tiny_jit
+    for L in o.loc:
+        assert L.B0_dual_norm < 1e-13 * np.abs(L.B0).max()
+
+
+def test_deluxe_partition_of_unity(tiny_jit):
+    pb, dec, o = tiny_jit
+    for e in range(len(o.ents)):
+        mats = [D for (ee, i), (pos, D) in o.D.items() if ee == e]
+        if mats:
+            assert np.abs(sum(mats) - np.eye(mats[0].shape[0])).max() < 1e-12
+
+
+def test_preconditioner_symmetric(tiny_jit):
+    pb, dec, o = tiny_jit
+    rng = np.random.default_rng(0)
+    a, b = rng.standard_normal(o.n), rng.standard_normal(o.n)
+    a[o.nG:] -= a[o.nG:].mean()
+    b[o.nG:] -= b[o.nG:].mean()
+    lhs, rhs = a @ o.apply_M(b), b @ o.apply_M(a)
+    assert abs(lhs - rhs) < 1e-12 * (abs(lhs) + abs(rhs))
+
+
+def test_pcg_matches_direct_solve(tiny_jit):
+    pb, dec, o = tiny_jit
+    g = o.rhs()
+    x, info = pcg(o.apply_S, o.apply_M, g, tol=1e-12)
+    uG, p0 = dec.interface_solution(pb.solve_reduced_direct())
+    ref = np.concatenate([uG, p0])
+    assert np.linalg.norm(x - ref) < 1e-10 * np.linalg.norm(ref)
+
+
+def test_all_primal_converges_in_one_iteration():
+    pb = Problem(CubeMesh(4), 2, 1.0, workers=1)
+    dec = Decomposition(pb, regular_cuts(4, (2, 2, 2)), MIN)
+    wl = dec.workload()
+    for E in wl["ents"]:
+        E["con"] = np.eye(len(E["gids"]))
+    o = OracleBDDC(wl)
+    x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-10)
+    assert info["iters"] == 1
+
+
+def test_min_eigenvalue_is_one_dense(tiny):
+    """Theorem teoEst: on the benign space lambda_min(M^-1 S_hat) = 1."""
+    pb, dec, o = tiny
+    n = o.n
+    M = np.array([o.apply_M(e) for e in np.eye(n)]).T
+    S = o.dense_S()
+    # nonzero spectrum of M S = spectrum of the symmetric S^1/2 M S^1/2
+    es, V = np.linalg.eigh(S)
+    Sh = (V * np.sqrt(np.maximum(es, 0.0))) @ V.T
+    Ms = 0.5 * (M + M.T)
+    ev = np.linalg.eigvalsh(Sh @ Ms @ Sh)
+    nz = ev[np.abs(ev) > 1e-8]
+    assert nz.min() > 1 - 1e-10
+    assert np.sum(np.abs(nz - 1) < 1e-8) >= o.nc  # eigenvalue-1 cluster of at least the coarse size
+
+
+def test_ritz_lambda_min_and_log_trend():
+    """Ritz values of the CG-Lanczos matrix stay >= 1 and, for the minimal
+    coarse space, k_2 / (1 + log(H/h))^2 does not grow along H/h = 2,4,6."""
+    ratios = []
+    for n in (4, 8, 12):
+        pb, dec, o = _setup(n, (2, 2, 2), MIN)
+        x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-10)
+        lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+        assert lmin > 1 - 1e-8
+        ratios.append((lmax / lmin) / (1 + np.log(n / 2)) ** 2)
+    assert ratios[-1] < 1.5 * max(ratios[:-1])
+
+
+def test_counting_scaling_converges_to_same_solution():
+    pb, dec, od = _setup(8, (2, 2, 2), FULL, jitter=0.15, seed=1)
+    oc = OracleBDDC(dec.workload(), scaling="counting")
+    g = od.rhs()
+    xd, idl = pcg(od.apply_S, od.apply_M, g, tol=1e-8)
+    xc, ic = pcg(oc.apply_S, oc.apply_M, g, tol=1e-8)
+    assert ic["iters"] < 200
+    assert np.linalg.norm(xd - xc) < 1e-6 * np.linalg.norm(xd)
