@@ -1,0 +1,170 @@
+/*
+ * vembddc -- BDDC-preconditioned CG for the interface saddle-point problem of
+ * divergence-free virtual element discretisations of 3D Stokes, on MI355X.
+ *
+ * The method (Bevilacqua, Dassi, Zampini, Scacchi, "BDDC preconditioners for
+ * virtual element approximations of the three-dimensional Stokes
+ * equations"):
+ *   - subdomain saddle matrices glued by the interface restrictions R_Gamma^(i)
+ *     (Sec. 4.2, eqs. discMat, ScapGdef);
+ *   - static condensation of interior velocity and mean-zero pressure by
+ *     Dirichlet solves (eq. uipi) onto the interface problem
+ *     S_hat u_hat = g_hat (eq. globInt) with S_Gamma^(i) of eq. firstSchur;
+ *   - the BDDC preconditioner M^-1 = Rt_D^T St^-1 Rt_D (eq. BDDCprec) with the
+ *     primal recipe of Sec. 5.1 (vertices, averages, face fluxes; change of
+ *     basis; dependent constraints dropped) and deluxe scaling (Sec. 6);
+ *   - preconditioned CG to a relative residual (Sec. 7) and recovery of the
+ *     interior unknowns (eq. uipi).
+ *
+ * Conventions (all entry points):
+ *   - every call returns VB_OK (0) or a negative VB_ERR_* code and never
+ *     throws; vb_last_error() gives a message;
+ *   - host arrays passed in are copied; the caller keeps ownership;
+ *   - "device" pointers are HIP device memory owned by the caller, accessed in
+ *     stream order on the context's stream (vb_options.stream);
+ *   - calls must be ordered create -> assemble (every subdomain) -> setup ->
+ *     (apply | schur_apply | pcg_solve | get_local_solution)*; otherwise
+ *     VB_ERR_STATE;
+ *   - a context is not thread-safe.
+ *
+ * The global interface vector layout (all vectors of length vb_interface_size)
+ * is [u_Gamma (n_iface entries, indexed by global interface id) | p0 (one
+ * per subdomain, in subdomain order)].
+ */
+#ifndef VEMBDDC_H
+#define VEMBDDC_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  VB_OK = 0,
+  VB_ERR_ARG = -1,             /* invalid argument or inconsistent sizes */
+  VB_ERR_STATE = -2,           /* call out of order */
+  VB_ERR_OOM = -3,             /* device allocation failed */
+  VB_ERR_DEVICE = -4,          /* a HIP runtime call failed */
+  VB_ERR_NOT_SPD = -5,         /* a pivot of a local factorisation had the wrong sign */
+  VB_ERR_SINGULAR_COARSE = -6, /* the coarse problem could not be factorised */
+  VB_ERR_BREAKDOWN = -7,       /* p^T S p <= 0 or NaN inside PCG */
+  VB_ERR_NOT_CONVERGED = -8    /* maxit reached; the last iterate is returned */
+};
+
+enum { VB_PREC_FP64 = 0, VB_PREC_MIXED = 1 };
+enum { VB_SCALING_DELUXE = 0, VB_SCALING_COUNTING = 1 };
+enum { VB_KIND_INTERIOR = 0, VB_KIND_INTERFACE = 1, VB_KIND_PRESSURE = 2 };
+enum { VB_ENT_VERTEX = 0, VB_ENT_EDGE = 1, VB_ENT_FACE = 2 };
+
+typedef struct vb_options {
+  int precision;     /* VB_PREC_FP64 or VB_PREC_MIXED */
+  int scaling;       /* VB_SCALING_DELUXE (Sec. 6) or VB_SCALING_COUNTING (eq. pseudoinv) */
+  double tol;        /* PCG relative residual ||g - S x|| <= tol ||g|| (default 1e-8) */
+  int maxit;         /* PCG iteration cap (default 1000) */
+  double svd_tol;    /* relative rank tolerance for dependent constraints (default 1e-10) */
+  int panel;         /* dense factorisation panel width, 0 = library default */
+  void *stream;      /* hipStream_t for all work; NULL = default stream */
+} vb_options;
+
+/* One subdomain's reduced local saddle problem (Sec. 4.2, eq. discMat):
+ * rows/cols are the local DoFs, CSR with both triangles.  Velocity DoFs are
+ * interior (VB_KIND_INTERIOR) or on the interface (VB_KIND_INTERFACE, with
+ * their global interface id in gid); pressure DoFs (VB_KIND_PRESSURE) are
+ * one constant per element with its volume |K| in pweight.  Dirichlet DoFs
+ * must already be eliminated into rhs. */
+typedef struct vb_subdomain {
+  int32_t n;              /* number of local DoFs */
+  int64_t nnz;
+  const int64_t *indptr;  /* [n+1] */
+  const int64_t *indices; /* [nnz] */
+  const double *data;     /* [nnz] */
+  const int32_t *kind;    /* [n] VB_KIND_* */
+  const int64_t *gid;     /* [n] global interface id, -1 if not interface */
+  const double *pweight;  /* [n] element volume for pressure DoFs, else ignored */
+  const double *rhs;      /* [n] local right-hand side */
+} vb_subdomain;
+
+/* One interface entity (macro vertex, edge or face; Sec. 5.1): its global
+ * interface ids (all DoFs shared by the same set of subdomains) and a dense
+ * row-major block of candidate primal functionals over those DoFs. */
+typedef struct vb_entity {
+  int32_t kind;           /* VB_ENT_* */
+  int32_t n;              /* number of DoFs */
+  const int64_t *gids;    /* [n] */
+  int32_t n_con;          /* number of constraint rows (may be 0) */
+  const double *con;      /* [n_con * n] row-major */
+} vb_entity;
+
+typedef struct vb_solve_info {
+  int iterations;
+  double rel_residual;       /* recursive relative residual at exit */
+  double true_rel_residual;  /* ||g - S x|| / ||g|| recomputed at exit */
+  double lambda_min, lambda_max; /* Lanczos estimates of M^-1 S on the benign space */
+  int n_coarse;              /* primal coarse dimension (+ one p0 per subdomain) */
+  double setup_ms, solve_ms; /* device times of the last vb_setup / vb_pcg_solve */
+  int status;                /* VB_OK or VB_ERR_* */
+} vb_solve_info;
+
+typedef struct vb_ctx vb_ctx;
+
+/* Create a context; opt may be NULL for defaults. */
+int vb_create(vb_ctx **ctx, const vb_options *opt);
+void vb_destroy(vb_ctx *ctx);
+const char *vb_last_error(const vb_ctx *ctx);
+
+/* Copy one problem: n_sub subdomains and n_ent entities covering every
+ * global interface id 0..n_iface-1 exactly once (Sec. 4.2: R_Gamma^(i)).
+ * Builds the interface numbering and uploads the local matrices. */
+int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
+                int n_ent, const vb_entity *ents);
+
+/* Everything the iteration needs (Sec. 4.2-4.3, 5.1, 6): local Dirichlet
+ * factorisations and Schur complements S_Gamma^(i) with the condensed
+ * right-hand side, change of basis, deluxe (or counting) scaling, local
+ * constrained Neumann operators and the coarse problem.  Returns
+ * VB_ERR_NOT_SPD (subdomain index in vb_last_error) on a pivot breakdown. */
+int vb_setup(vb_ctx *ctx);
+
+/* Length of the global interface vector: n_iface + n_sub. */
+int64_t vb_interface_size(const vb_ctx *ctx);
+
+/* g_dev <- g_hat (eq. globInt) in the global interface layout (device). */
+int vb_rhs(vb_ctx *ctx, double *g_dev);
+
+/* y_dev <- S_hat x_dev (eq. globInt) (device vectors, global layout). */
+int vb_schur_apply(vb_ctx *ctx, const double *x_dev, double *y_dev);
+
+/* z_dev <- M^-1 r_dev (eq. BDDCprec) (device vectors, global layout). */
+int vb_apply(vb_ctx *ctx, const double *r_dev, double *z_dev);
+
+/* PCG on S_hat u = g_hat from x0 = x_dev (Sec. 7); x_dev receives the
+ * solution (also on VB_ERR_NOT_CONVERGED).  info may be NULL. */
+int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info);
+
+/* Interior recovery (eq. uipi) for subdomain `sub` from the interface
+ * solution x_dev: writes the local DoF vector (the subdomain's own CSR DoF
+ * order: velocities, then element pressures = Q_I part + p0) to u_host. */
+int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_host);
+
+/* Interior recovery for every subdomain at once: out_dev (device, may be
+ * NULL to only refresh the internal copy) receives the concatenation over
+ * subdomains of their local DoF vectors, each in its own CSR DoF order. */
+int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
+
+/* Batched dense partial signed LDL^T (the kernel under the Dirichlet and
+ * Neumann solves).  For each of `batch` column-major matrices A_b (size n_b,
+ * leading dimension ld_b, lower triangle referenced) eliminate the first
+ * e_b columns with pivot sign +1 for columns < p_b and -1 for columns in
+ * [p_b, e_b).  On return the lower triangle holds L (eliminated columns) and
+ * the Schur complement A22 - L21 D L21^T in the trailing block.  All
+ * pointers (A[], n[], ld[], e[], p[], info[]) are device arrays of length
+ * batch; info[b] = 0 or 1 + the column of a wrong-signed pivot. */
+int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n,
+                   const int32_t *ld, const int32_t *e, const int32_t *p,
+                   int32_t *info, int max_n, int max_e);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,74 @@
+"""Seeded synthetic workloads shaped like the paper's CUBE tests (Sec. 7).
+
+Each recipe fixes mesh size n, jitter, degree k, viscosity, subdomain cuts
+and the candidate primal functionals; ``make_workload`` returns the plain
+data the hot path consumes plus the generator objects (for tests).
+
+  c1  8^3 cube elements, k=2, nu=1, 2x2x2 subdomains, vertex + edge
+      averages + face flux
+  c2  32^3, plane jitter 0.15h (seed 0), k=2, nu=1, 4x4x4 subdomains,
+      vertex + edge + face averages (+ flux, dependent)
+  c3  48^3, plane jitter 0.15h (seed 0), k=2, nu=1, 6x6x6 uneven
+      subdomains (4..12 elements per side, cuts seed 0)
+  c4  32^3 cube elements, k=2, 8 spheres of radius 0.1 with nu=1e4 inside
+      (centres uniform, seed 0), 4x4x4 subdomains
+  c5  one of 32 problems: 24^3, plane jitter 0.15h, k=3, 3x3x3 subdomains,
+      nu constant per subdomain, log-uniform in [1e-3, 1e3] (seed p)
+Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3).
+"""
+import numpy as np
+
+from .mesh import CubeMesh
+from .assemble import Problem
+from .decompose import Decomposition, regular_cuts, random_cuts
+
+MIN = ("vertex", "edge", "flux")
+FULL = ("vertex", "edge", "face", "flux")
+
+
+def sinker_viscosity(mesh, n_sinkers=8, radius=0.1, nu_in=1e4, nu_out=1.0, seed=0):
+    rng = np.random.default_rng(seed)
+    centres = rng.uniform(0.0, 1.0, size=(n_sinkers, 3))
+    d = np.linalg.norm(mesh.elem_centroid[:, None, :] - centres[None], axis=2)
+    return np.where(np.any(d <= radius, axis=1), nu_in, nu_out)
+
+
+def subdomain_viscosity(mesh, cuts, seed):
+    rng = np.random.default_rng(seed)
+    parts = [len(c) - 1 for c in cuts]
+    nsub = parts[0] * parts[1] * parts[2]
+    nu_sub = 10.0 ** rng.uniform(-3.0, 3.0, size=nsub)
+    seg = [np.searchsorted(cuts[a], mesh.eidx[:, a], side="right") - 1 for a in range(3)]
+    sid = seg[0] + parts[0] * (seg[1] + parts[1] * seg[2])
+    return nu_sub[sid]
+
+
+RECIPES = {
+    "c1": dict(n=8, jitter=0.0, k=2, parts=(2, 2, 2), cons=MIN),
+    "c2": dict(n=32, jitter=0.15, k=2, parts=(4, 4, 4), cons=FULL),
+    "c3": dict(n=48, jitter=0.15, k=2, random_cuts=(4, 12, 6), cons=FULL),
+    "c4": dict(n=32, jitter=0.0, k=2, parts=(4, 4, 4), cons=FULL, sinkers=True),
+    "c5": dict(n=24, jitter=0.15, k=3, parts=(3, 3, 3), cons=FULL, nu_per_sub=True),
+    "t8j": dict(n=8, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
+    "t12": dict(n=12, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),
+    "t16": dict(n=16, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
+}
+
+
+def make_workload(name, seed=0, workers=None, **over):
+    r = dict(RECIPES[name])
+    r.update(over)
+    mesh = CubeMesh(r["n"], jitter=r["jitter"], seed=seed)
+    if "random_cuts" in r:
+        lo, hi, parts = r["random_cuts"]
+        cuts = random_cuts(r["n"], lo, hi, parts, seed)
+    else:
+        cuts = regular_cuts(r["n"], r["parts"])
+    nu = 1.0
+    if r.get("sinkers"):
+        nu = sinker_viscosity(mesh, seed=seed)
+    if r.get("nu_per_sub"):
+        nu = subdomain_viscosity(mesh, cuts, seed)
+    pb = Problem(mesh, r["k"], nu, workers=workers)
+    dec = Decomposition(pb, cuts, r["cons"])
+    return dec.workload(), {"recipe": r, "problem": pb, "decomposition": dec, "name": name}

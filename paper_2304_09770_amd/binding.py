@@ -1,0 +1,205 @@
+"""ctypes binding of libvembddc (include/vembddc.h): argument marshalling only.
+
+Every function has the name of the C entry point it calls.  Device vectors
+are torch CUDA tensors (float64) or raw device addresses; the library does
+all the arithmetic.  The binding refuses to run without the built library
+(there is no CPU fallback).
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libvembddc.so")
+
+VB_OK = 0
+ERRORS = {-1: "VB_ERR_ARG", -2: "VB_ERR_STATE", -3: "VB_ERR_OOM", -4: "VB_ERR_DEVICE",
+          -5: "VB_ERR_NOT_SPD", -6: "VB_ERR_SINGULAR_COARSE", -7: "VB_ERR_BREAKDOWN",
+          -8: "VB_ERR_NOT_CONVERGED"}
+VB_PREC_FP64, VB_PREC_MIXED = 0, 1
+VB_SCALING_DELUXE, VB_SCALING_COUNTING = 0, 1
+
+
+class vb_options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("scaling", C.c_int), ("tol", C.c_double),
+                ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
+                ("stream", C.c_void_p)]
+
+
+class vb_subdomain(C.Structure):
+    _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("indptr", C.POINTER(C.c_int64)),
+                ("indices", C.POINTER(C.c_int64)), ("data", C.POINTER(C.c_double)),
+                ("kind", C.POINTER(C.c_int32)), ("gid", C.POINTER(C.c_int64)),
+                ("pweight", C.POINTER(C.c_double)), ("rhs", C.POINTER(C.c_double))]
+
+
+class vb_entity(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("n", C.c_int32), ("gids", C.POINTER(C.c_int64)),
+                ("n_con", C.c_int32), ("con", C.POINTER(C.c_double))]
+
+
+class vb_solve_info(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("rel_residual", C.c_double),
+                ("true_rel_residual", C.c_double), ("lambda_min", C.c_double),
+                ("lambda_max", C.c_double), ("n_coarse", C.c_int), ("setup_ms", C.c_double),
+                ("solve_ms", C.c_double), ("status", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load():
+    """Load the built library (raises if it was not built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libvembddc.so is not built (run __graft_entry__.build())")
+    lib = C.CDLL(LIB_PATH)
+    P = C.c_void_p
+    sig = {
+        "vb_create": (C.c_int, [C.POINTER(P), C.POINTER(vb_options)]),
+        "vb_destroy": (None, [P]),
+        "vb_last_error": (C.c_char_p, [P]),
+        "vb_assemble": (C.c_int, [P, C.c_int64, C.c_int, C.POINTER(vb_subdomain), C.c_int,
+                                  C.POINTER(vb_entity)]),
+        "vb_setup": (C.c_int, [P]),
+        "vb_interface_size": (C.c_int64, [P]),
+        "vb_rhs": (C.c_int, [P, P]),
+        "vb_schur_apply": (C.c_int, [P, P, P]),
+        "vb_apply": (C.c_int, [P, P, P]),
+        "vb_pcg_solve": (C.c_int, [P, P, C.POINTER(vb_solve_info)]),
+        "vb_get_local_solution": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_double)]),
+        "vb_recover_all": (C.c_int, [P, P, P]),
+        "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def exported_symbols():
+    return ["vb_create", "vb_destroy", "vb_last_error", "vb_assemble", "vb_setup",
+            "vb_interface_size", "vb_rhs", "vb_schur_apply", "vb_apply", "vb_pcg_solve",
+            "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl"]
+
+
+class VBError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s: %s" % (ERRORS.get(code, code), msg))
+        self.code = code
+
+
+def _ptr(t):
+    """Device address of a torch tensor or an int."""
+    if t is None:
+        return None
+    if isinstance(t, int):
+        return t
+    return t.data_ptr()
+
+
+def _np(a, dt):
+    a = np.ascontiguousarray(a, dtype=dt)
+    return a, a.ctypes.data_as(C.POINTER(np.ctypeslib.as_ctypes_type(dt)))
+
+
+def _check(ctx, rc):
+    if rc != VB_OK:
+        raise VBError(rc, load().vb_last_error(ctx).decode())
+
+
+# ------------------------------------------------------------- C-ABI names
+def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
+              svd_tol=1e-10, panel=0, stream=None):
+    lib = load()
+    opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream)
+    ctx = C.c_void_p()
+    rc = lib.vb_create(C.byref(ctx), C.byref(opt))
+    if rc != VB_OK:
+        raise VBError(rc, "vb_create")
+    return ctx
+
+
+def vb_destroy(ctx):
+    load().vb_destroy(ctx)
+
+
+def vb_assemble(ctx, workload):
+    """workload: dict(n_iface, subs=[dict(indptr, indices, data, kind, gid,
+    pweight, rhs)], ents=[dict(kind, gids, con)]) (numpy arrays)."""
+    keep = []
+    subs = (vb_subdomain * len(workload["subs"]))()
+    for i, sd in enumerate(workload["subs"]):
+        ip, ipp = _np(sd["indptr"], np.int64)
+        ix, ixp = _np(sd["indices"], np.int64)
+        dv, dvp = _np(sd["data"], np.float64)
+        kd, kdp = _np(sd["kind"], np.int32)
+        gd, gdp = _np(sd["gid"], np.int64)
+        pw, pwp = _np(sd["pweight"], np.float64)
+        rh, rhp = _np(sd["rhs"], np.float64)
+        keep += [ip, ix, dv, kd, gd, pw, rh]
+        subs[i] = vb_subdomain(len(kd), len(ix), ipp, ixp, dvp, kdp, gdp, pwp, rhp)
+    ents = (vb_entity * max(1, len(workload["ents"])))()
+    for e, E in enumerate(workload["ents"]):
+        g, gp = _np(E["gids"], np.int64)
+        con = np.ascontiguousarray(E["con"], dtype=np.float64).reshape(-1, len(g))
+        c, cp = _np(con.ravel(), np.float64)
+        keep += [g, c]
+        ents[e] = vb_entity(int(E["kind"]), len(g), gp, con.shape[0], cp)
+    rc = load().vb_assemble(ctx, int(workload["n_iface"]), len(workload["subs"]), subs,
+                            len(workload["ents"]), ents)
+    _check(ctx, rc)
+
+
+def vb_setup(ctx):
+    _check(ctx, load().vb_setup(ctx))
+
+
+def vb_interface_size(ctx):
+    return int(load().vb_interface_size(ctx))
+
+
+def vb_rhs(ctx, g):
+    _check(ctx, load().vb_rhs(ctx, _ptr(g)))
+
+
+def vb_schur_apply(ctx, x, y):
+    _check(ctx, load().vb_schur_apply(ctx, _ptr(x), _ptr(y)))
+
+
+def vb_apply(ctx, r, z):
+    _check(ctx, load().vb_apply(ctx, _ptr(r), _ptr(z)))
+
+
+def vb_pcg_solve(ctx, x, raise_on_error=True):
+    info = vb_solve_info()
+    rc = load().vb_pcg_solve(ctx, _ptr(x), C.byref(info))
+    if raise_on_error:
+        _check(ctx, rc)
+    return info.as_dict()
+
+
+def vb_get_local_solution(ctx, x, sub, n):
+    out = np.zeros(n)
+    rc = load().vb_get_local_solution(ctx, _ptr(x), int(sub),
+                                      out.ctypes.data_as(C.POINTER(C.c_double)))
+    _check(ctx, rc)
+    return out
+
+
+def vb_recover_all(ctx, x, out):
+    _check(ctx, load().vb_recover_all(ctx, _ptr(x), _ptr(out)))
+
+
+def vb_batched_ldl(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
+    rc = load().vb_batched_ldl(ctx, len(n), _ptr(ptrs), _ptr(n), _ptr(ld), _ptr(e), _ptr(p),
+                               _ptr(info), int(max_n), int(max_e))
+    _check(ctx, rc)

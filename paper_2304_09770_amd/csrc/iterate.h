@@ -1,0 +1,63 @@
+// Per-iteration kernel launchers and job descriptors.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace vb {
+
+enum { SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_GG, SC_FLAG, SC_TMP, SC_COUNT };
+constexpr int DOT_BLOCKS = 512;
+
+struct GemvJob {
+  const double *A;
+  int64_t lda;
+  int m, n;            // A is m x n
+  const double *x;     // gathered through xidx when given
+  const int64_t *xidx;
+  const double *base;  // gemv_n: y = base + A x
+  double *y;
+  double alpha;        // gemv_t: y = alpha A^T x (+ y if acc)
+  int acc;
+};
+
+struct ExtPart {
+  const double *D;  // m x m column-major (null: counting weight `scale`)
+  int64_t ld;
+  int64_t woff;     // offset of this subdomain's entity block in w
+  double scale;
+};
+struct ExtJob {
+  int m;
+  int nparts;
+  int part0;
+  const int64_t *gids;  // m global positions
+};
+
+struct RecJob {
+  int sub, n, nv, nel;
+  const int32_t *kind;
+  const int32_t *pos;
+  const int64_t *gid;
+  const double *hv;
+  const double *z;   // interior solution in dense order
+  double *out;
+};
+
+hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);
+hipError_t gemv_n(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);
+hipError_t owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
+                     const int64_t *bidx, const double *bsrc, double *y, hipStream_t s);
+hipError_t scatter_copy(int n, const double *src, const int64_t *sidx, const int64_t *dst,
+                        double *y, double scale, hipStream_t s);
+hipError_t extend(const ExtJob *d_jobs, int njobs, int max_m, const ExtPart *d_parts,
+                  const double *w, double *z, hipStream_t s);
+hipError_t dot(int64_t n, const double *a, const double *b, double *part, double *sc, int mode,
+               int it, double *hist_a, double *hist_b, hipStream_t s);
+hipError_t update_xr(int64_t n, const double *sc, double *x, double *r, const double *p,
+                     const double *q, double *part, double *scw, hipStream_t s);
+hipError_t update_p(int64_t n, const double *sc, double *p, const double *z, hipStream_t s);
+hipError_t vsub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
+hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,
+                       hipStream_t s);
+
+}  // namespace vb

@@ -1,0 +1,318 @@
+// Per-iteration kernels of PCG + BDDC (HBM-bound dense GEMVs, gathers,
+// deterministic interface assembly and the CG recurrences).
+#include "common.h"
+#include "iterate.h"
+
+namespace vb {
+
+// y_b[j] = alpha * sum_i A_b[i + j*lda] x_b[i] (+ y_b[j] if accumulate), one
+// wave per column, x_b staged in LDS (gathered through xidx if given).
+// Columns are contiguous in HBM: every wave streams one column.
+template <int CPB>
+__global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
+  const GemvJob J = jobs[blockIdx.y];
+  const int j0 = blockIdx.x * CPB;
+  if (j0 >= J.n) return;
+  extern __shared__ double xs[];
+  for (int i = threadIdx.x; i < J.m; i += blockDim.x)
+    xs[i] = J.xidx ? J.x[J.xidx[i]] : J.x[i];
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int jj = w; jj < CPB; jj += 4) {
+    const int j = j0 + jj;
+    if (j >= J.n) break;
+    const double *col = J.A + (int64_t)j * J.lda;
+    double s0 = 0.0, s1 = 0.0;
+    int i = l;
+    for (; i + 64 < J.m; i += 128) {
+      s0 += col[i] * xs[i];
+      s1 += col[i + 64] * xs[i + 64];
+    }
+    if (i < J.m) s0 += col[i] * xs[i];
+    double s = warp_sum(s0 + s1);
+    if (l == 0) {
+      double v = J.alpha * s;
+      if (J.acc) v += J.y[j];
+      J.y[j] = v;
+    }
+  }
+}
+
+// y_b[i] = base_b[i] + sum_j A_b[i + j*lda] x_b[j], one thread per row,
+// x_b (length n, gathered through xidx) staged in LDS.
+__global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
+  const GemvJob J = jobs[blockIdx.y];
+  extern __shared__ double xs[];
+  for (int j = threadIdx.x; j < J.n; j += blockDim.x)
+    xs[j] = J.xidx ? J.x[J.xidx[j]] : J.x[j];
+  __syncthreads();
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= J.m) return;
+  double s = J.base ? J.base[i] : 0.0;
+  const double *a = J.A + i;
+  for (int j = 0; j < J.n; ++j) s += a[(int64_t)j * J.lda] * xs[j];
+  J.y[i] = s;
+}
+
+// The staged vectors can exceed the default 64 KB of dynamic LDS; CDNA4 has
+// 160 KB per CU.
+static hipError_t allow_big_lds() {
+  static int done = 0;
+  if (done) return hipSuccess;
+  hipError_t e = hipFuncSetAttribute((const void *)k_gemv_t<32>,
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+  if (e == hipSuccess)
+    e = hipFuncSetAttribute((const void *)k_gemv_n, hipFuncAttributeMaxDynamicSharedMemorySize,
+                            160 * 1024);
+  if (e == hipSuccess) done = 1;
+  return e;
+}
+
+hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {
+  if (!batch || !max_n) return hipSuccess;
+  size_t lds = (size_t)max_m * sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_gemv_t<32>), dim3((max_n + 31) / 32, batch), dim3(256), lds, s, d_jobs);
+  return hipGetLastError();
+}
+
+hipError_t gemv_n(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {
+  if (!batch || !max_m) return hipSuccess;
+  size_t lds = (size_t)(max_n > 0 ? max_n : 1) * sizeof(double);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (lds > 64 * 1024) {
+    hipError_t e = allow_big_lds();
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(k_gemv_n, dim3((max_m + 255) / 256, batch), dim3(256), lds, s, d_jobs);
+  return hipGetLastError();
+}
+
+// y[g] = (bidx ? bsrc[bidx[g]] : 0) + sum_{t in [ptr[g], ptr[g+1])} src[idx[t]]
+// (deterministic assembly of subdomain contributions, fixed order).
+__global__ void k_owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
+                            const int64_t *bidx, const double *bsrc, double *y) {
+  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (g >= n) return;
+  double s = bidx ? bsrc[bidx[g]] : 0.0;
+  for (int64_t t = ptr[g]; t < ptr[g + 1]; ++t) s += src[idx[t]];
+  y[g] = s;
+}
+
+hipError_t owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
+                     const int64_t *bidx, const double *bsrc, double *y, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_owner_sum, dim3((n + 255) / 256), dim3(256), 0, s, n, ptr, idx, src, bidx,
+                     bsrc, y);
+  return hipGetLastError();
+}
+
+// y[dst[i]] = scale * src[sidx ? sidx[i] : i]
+__global__ void k_scatter_copy(int n, const double *src, const int64_t *sidx, const int64_t *dst,
+                               double *y, double scale) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  y[dst ? dst[i] : i] = scale * src[sidx ? sidx[i] : i];
+}
+
+hipError_t scatter_copy(int n, const double *src, const int64_t *sidx, const int64_t *dst,
+                        double *y, double scale, hipStream_t s) {
+  if (!n) return hipSuccess;
+  hipLaunchKernelGGL(k_scatter_copy, dim3((n + 255) / 256), dim3(256), 0, s, n, src, sidx, dst, y,
+                     scale);
+  return hipGetLastError();
+}
+
+// Deluxe extension: z[gid[m]] = sum_q (D_q w_q)[m] over the subdomains of
+// the entity (D_q = null: counting weights 1/card).  One thread per row.
+__global__ void k_extend(const ExtJob *jobs, const ExtPart *parts, const double *w, double *z) {
+  const ExtJob J = jobs[blockIdx.y];
+  const int m = blockIdx.x * blockDim.x + threadIdx.x;
+  if (m >= J.m) return;
+  double s = 0.0;
+  for (int q = 0; q < J.nparts; ++q) {
+    const ExtPart P = parts[J.part0 + q];
+    const double *wq = w + P.woff;
+    if (P.D) {
+      const double *a = P.D + m;
+      for (int l = 0; l < J.m; ++l) s += a[(int64_t)l * P.ld] * wq[l];
+    } else {
+      s += wq[m] * P.scale;
+    }
+  }
+  z[J.gids[m]] = s;
+}
+
+hipError_t extend(const ExtJob *d_jobs, int njobs, int max_m, const ExtPart *d_parts,
+                  const double *w, double *z, hipStream_t s) {
+  if (!njobs || !max_m) return hipSuccess;
+  hipLaunchKernelGGL(k_extend, dim3((max_m + 127) / 128, njobs), dim3(128), 0, s, d_jobs, d_parts,
+                     w, z);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------- CG recurrences
+// Partial dot products of (a,b) and optionally (c,d): part[2*blk + {0,1}].
+__global__ __launch_bounds__(256) void k_dot2(int64_t n, const double *a, const double *b,
+                                              const double *c, const double *d, double *part) {
+  __shared__ double red[16];
+  double s0 = 0.0, s1 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    s0 += a[i] * b[i];
+    if (c) s1 += c[i] * d[i];
+  }
+  s0 = block_sum(s0, red);
+  s1 = block_sum(s1, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s0;
+    part[2 * blockIdx.x + 1] = s1;
+  }
+}
+
+// Final reduction (fixed order) and scalar bookkeeping of PCG.
+//  mode 0: sc[PQ] = s0; alpha = sc[RZ]/pq, history
+//  mode 1: sc[RR] = s0
+//  mode 2: rz_new = s0; beta = rz_new / sc[RZ]; sc[RZ] = rz_new, history
+//  mode 3: sc[RZ] = s0 (first iteration); mode 4: sc[GG] = s0 ; mode 5: sc[TMP] = s0
+__global__ void k_dot_final(int nblk, const double *part, double *sc, int mode, int it,
+                            double *hist_a, double *hist_b) {
+  if (threadIdx.x != 0) return;
+  double s0 = 0.0;
+  for (int i = 0; i < nblk; ++i) s0 += part[2 * i];
+  switch (mode) {
+    case 0: {
+      sc[SC_PQ] = s0;
+      const double a = sc[SC_RZ] / s0;
+      sc[SC_ALPHA] = a;
+      if (!(s0 > 0.0) || !(a == a)) sc[SC_FLAG] = 1.0;
+      if (hist_a) hist_a[it] = a;
+      break;
+    }
+    case 1: sc[SC_RR] = s0; break;
+    case 2: {
+      const double b = s0 / sc[SC_RZ];
+      sc[SC_BETA] = b;
+      sc[SC_RZ] = s0;
+      if (hist_b) hist_b[it] = b;
+      break;
+    }
+    case 3: sc[SC_RZ] = s0; break;
+    case 4: sc[SC_GG] = s0; break;
+    default: sc[SC_TMP] = s0; break;
+  }
+}
+
+hipError_t dot(int64_t n, const double *a, const double *b, double *part, double *sc, int mode,
+               int it, double *hist_a, double *hist_b, hipStream_t s) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL(k_dot2, dim3(nblk), dim3(256), 0, s, n, a, b, (const double *)nullptr,
+                     (const double *)nullptr, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, nblk, part, sc, mode, it, hist_a, hist_b);
+  return hipGetLastError();
+}
+
+// x += alpha p ; r -= alpha q ; partial r.r
+__global__ __launch_bounds__(256) void k_update_xr(int64_t n, const double *sc, double *x, double *r,
+                                                   const double *p, const double *q, double *part) {
+  __shared__ double red[16];
+  const double a = sc[SC_ALPHA];
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    part[2 * blockIdx.x] = s;
+    part[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+hipError_t update_xr(int64_t n, const double *sc, double *x, double *r, const double *p,
+                     const double *q, double *part, double *scw, hipStream_t s) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL(k_update_xr, dim3(nblk), dim3(256), 0, s, n, sc, x, r, p, q, part);
+  hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, nblk, part, scw, 1, 0,
+                     (double *)nullptr, (double *)nullptr);
+  return hipGetLastError();
+}
+
+// p = z + beta p (beta = 0 on the first iteration via sc[SC_BETA] reset)
+__global__ void k_update_p(int64_t n, const double *sc, double *p, const double *z) {
+  const double b = sc[SC_BETA];
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = z[i] + b * p[i];
+}
+
+hipError_t update_p(int64_t n, const double *sc, double *p, const double *z, hipStream_t s) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL(k_update_p, dim3(nblk), dim3(256), 0, s, n, sc, p, z);
+  return hipGetLastError();
+}
+
+// y = a - b (elementwise)
+__global__ void k_sub(int64_t n, const double *a, const double *b, double *y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = a[i] - b[i];
+}
+
+hipError_t vsub(int64_t n, const double *a, const double *b, double *y, hipStream_t s) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, s, n, a, b, y);
+  return hipGetLastError();
+}
+
+// Recovery output: local DoF vector in CSR order.  Velocities from the
+// interior solve or the interface solution, pressures c = H [p_I; 0] + p0.
+__global__ void k_recover_out(const RecJob *jobs, const double *x_orig, int64_t nG) {
+  const RecJob J = jobs[blockIdx.x];
+  __shared__ double red[16];
+  // v^T [p_I; 0]
+  double t = 0.0;
+  for (int k = threadIdx.x; k < J.nel - 1; k += blockDim.x) t += J.hv[k] * J.z[J.nv + k];
+  t = block_sum(t, red);
+  const double tau = J.hv[J.nel];
+  const double p0 = x_orig[nG + J.sub];
+  for (int i = threadIdx.x; i < J.n; i += blockDim.x) {
+    const int k = J.kind[i];
+    const int p = J.pos[i];
+    double v;
+    if (k == 0) {
+      v = J.z[p];
+    } else if (k == 1) {
+      v = x_orig[J.gid[i]];
+    } else {
+      const int q = p - J.nv;
+      const double pi = (q < J.nel - 1) ? J.z[p] : 0.0;
+      v = pi - tau * J.hv[q] * t + p0;
+    }
+    J.out[i] = v;
+  }
+}
+
+hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,
+                       hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_recover_out, dim3(nsub), dim3(256), 0, s, d_jobs, x_orig, nG);
+  return hipGetLastError();
+}
+
+}  // namespace vb

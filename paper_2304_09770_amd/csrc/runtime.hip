@@ -1,0 +1,1241 @@
+// vembddc runtime: the C-ABI of include/vembddc.h.
+//
+// Host code only orchestrates: index bookkeeping of the caller's data
+// (interface numbering, entity membership, offsets) and kernel launches.
+// Every arithmetic step of setup, preconditioner, PCG and recovery runs in
+// the HIP kernels of dense.hip, setup.hip and iterate.hip.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/vembddc.h"
+#include "common.h"
+#include "iterate.h"
+#include "kernels.h"
+
+using namespace vb;
+
+namespace {
+
+constexpr int NB = 64;  // panel width of the dense factorisations
+
+int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+struct SubH {
+  int n = 0;
+  std::vector<int64_t> indptr;
+  std::vector<int32_t> indices;
+  std::vector<double> vals, rhs;
+  std::vector<int32_t> kind;
+  std::vector<int64_t> gid;
+  int nv = 0, nel = 0, ng = 0, N = 0, e = 0;
+  int64_t ld = 0;
+  std::vector<int32_t> pos;
+  std::vector<double> pw;       // element volumes in dense pressure order
+  std::vector<int64_t> gidl;    // local interface index -> global id
+  std::vector<int32_t> ents, ent_off;
+  double vol = 0.0;
+  // filled in setup
+  std::vector<int32_t> pl, dl, cidx;
+  std::vector<int64_t> doff;    // per local entity: offset of its dual block in the local dual vector
+  int npi = 0, ndl = 0;
+  // device
+  int64_t W_off = 0, inv_off = 0, b0_off = 0, hv_off = 0, y_off = 0;
+  int64_t *d_indptr = nullptr;
+  int32_t *d_indices = nullptr, *d_pos = nullptr, *d_kind = nullptr;
+  double *d_vals = nullptr, *d_rhs = nullptr, *d_pw = nullptr;
+  int64_t *d_gidl = nullptr, *d_gid = nullptr;
+  int32_t *d_ents = nullptr, *d_entoff = nullptr;
+  double *Nmat = nullptr;
+  int64_t Nld = 0;
+  int Nn = 0;
+  double *G1 = nullptr;
+};
+
+struct EntH {
+  int kind = 0, n = 0, ncon = 0;
+  std::vector<int64_t> gids;
+  std::vector<double> con;
+  std::vector<int> subs;  // subdomains sharing the entity (ascending)
+  int rank = 0;
+  int64_t *d_gids = nullptr;
+  double *d_con = nullptr, *d_V = nullptr, *d_tau = nullptr, *d_work = nullptr;
+  int *d_rank = nullptr;
+  // deluxe
+  double *Daug = nullptr;
+  int64_t Dld = 0;
+  std::vector<double *> D;  // per sharing subdomain
+  std::vector<double *> Sbar;
+  int64_t *d_dual_gids = nullptr;
+};
+
+}  // namespace
+
+struct vb_ctx {
+  vb_options opt{};
+  hipStream_t stream = nullptr;
+  std::string err;
+  int state = 0;  // 0 created, 1 assembled, 2 set up
+  std::vector<void *> allocs;
+  std::vector<void *> setup_allocs;
+
+  int64_t nG = 0;
+  int nS = 0;
+  std::vector<SubH> subs;
+  std::vector<EntH> ents;
+  int max_n_csr = 0, max_N = 0, max_e = 0, max_ng = 0, max_ent = 0;
+
+  // device buffers
+  double *W = nullptr;
+  double *invL = nullptr;
+  double *b0 = nullptr, *hv = nullptr;
+  int *info = nullptr;
+  SubDev *d_subdev = nullptr;
+  EntDev *d_entdev = nullptr;
+  std::vector<SubDev> subdev;
+  std::vector<EntDev> entdev;
+
+  // iteration structures
+  int nC = 0, nCS = 0;
+  double *Kaug = nullptr, *Gc = nullptr;
+  int64_t Kld = 0;
+  double *g = nullptr;  // transformed right-hand side (global layout)
+  double *x = nullptr, *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *tmp = nullptr;
+  double *yloc = nullptr, *gD = nullptr, *wv = nullptr, *tv = nullptr, *rc = nullptr, *uc = nullptr;
+  double *sc = nullptr, *part = nullptr, *hist_a = nullptr, *hist_b = nullptr;
+  GemvJob *j_schur = nullptr, *j_restrict = nullptr, *j_neu1 = nullptr, *j_coarse = nullptr,
+          *j_neu2 = nullptr;
+  int n_restrict = 0, max_rm = 0;
+  ExtJob *j_ext = nullptr;
+  ExtPart *j_extpart = nullptr;
+  int n_ext = 0, max_ext_m = 0;
+  int64_t *own_ptr = nullptr, *own_idx = nullptr;        // S_hat assembly
+  int64_t *g_ptr = nullptr, *g_idx = nullptr;            // g~ assembly (offsets into W)
+  int64_t *c_ptr = nullptr, *c_idx = nullptr, *c_base = nullptr;  // coarse rhs
+  int64_t *uc_dst = nullptr;                             // primal/p0 positions of uc
+  int64_t *p0_src = nullptr, *p0_dst = nullptr;
+  int max_gt_m = 0, max_gt_n = 0, max_ndl = 0, max_npi = 0, max_nt = 0;
+  int64_t n_yloc = 0, n_gD = 0, n_tv = 0;
+  // recovery
+  double *yrec = nullptr, *rec_out = nullptr;
+  int64_t *d_yoff = nullptr, *d_invoff = nullptr;
+  RecJob *j_rec = nullptr;
+  std::vector<int64_t> rec_off;
+  const double *rec_x = nullptr;
+  int rec_valid = 0;
+
+  double setup_ms = 0.0;
+  hipEvent_t ev0 = nullptr, ev1 = nullptr;
+
+  int fail(int code, const std::string &m) {
+    err = m;
+    return code;
+  }
+  template <class T>
+  hipError_t dalloc(T **p, size_t count, bool setup_scope = false) {
+    *p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    if (e == hipSuccess) (setup_scope ? setup_allocs : allocs).push_back(*p);
+    return e;
+  }
+  template <class T>
+  hipError_t upload(T **p, const std::vector<T> &v, bool setup_scope = false) {
+    hipError_t e = dalloc(p, v.size(), setup_scope);
+    if (e != hipSuccess) return e;
+    if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+  }
+};
+
+#define CHK(x)                                                                        \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess)                                                             \
+      return ctx->fail(e_ == hipErrorOutOfMemory ? VB_ERR_OOM : VB_ERR_DEVICE,        \
+                       std::string(#x) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+
+extern "C" {
+
+int vb_create(vb_ctx **out, const vb_options *opt) {
+  if (!out) return VB_ERR_ARG;
+  vb_ctx *ctx = new vb_ctx();
+  vb_options d{};
+  d.precision = VB_PREC_FP64;
+  d.scaling = VB_SCALING_DELUXE;
+  d.tol = 1e-8;
+  d.maxit = 1000;
+  d.svd_tol = 1e-10;
+  d.panel = NB;
+  d.stream = nullptr;
+  if (opt) {
+    d = *opt;
+    if (d.tol <= 0) d.tol = 1e-8;
+    if (d.maxit <= 0) d.maxit = 1000;
+    if (d.svd_tol <= 0) d.svd_tol = 1e-10;
+    if (d.panel <= 0) d.panel = NB;
+  }
+  if (d.panel != 64 && d.panel != 32) {
+    delete ctx;
+    return VB_ERR_ARG;
+  }
+  if (d.precision != VB_PREC_FP64) {
+    delete ctx;
+    return VB_ERR_ARG;  // mixed precision is not built in this library version
+  }
+  ctx->opt = d;
+  ctx->stream = (hipStream_t)d.stream;
+  if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
+    delete ctx;
+    return VB_ERR_DEVICE;
+  }
+  *out = ctx;
+  return VB_OK;
+}
+
+static void free_list(std::vector<void *> &v) {
+  for (void *p : v) (void)hipFree(p);
+  v.clear();
+}
+
+void vb_destroy(vb_ctx *ctx) {
+  if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  free_list(ctx->setup_allocs);
+  free_list(ctx->allocs);
+  if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
+  delete ctx;
+}
+
+const char *vb_last_error(const vb_ctx *ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+int64_t vb_interface_size(const vb_ctx *ctx) { return ctx ? ctx->nG + ctx->nS : 0; }
+
+int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs, int n_ent,
+                const vb_entity *ents) {
+  if (!ctx) return VB_ERR_ARG;
+  if (ctx->state != 0) return ctx->fail(VB_ERR_STATE, "vb_assemble: already assembled");
+  if (n_iface < 0 || n_sub <= 0 || !subs || n_ent < 0 || (n_ent > 0 && !ents))
+    return ctx->fail(VB_ERR_ARG, "vb_assemble: bad sizes");
+  ctx->nG = n_iface;
+  ctx->nS = n_sub;
+  // entities
+  std::vector<int32_t> ent_of(n_iface, -1), pos_in(n_iface, -1);
+  ctx->ents.resize(n_ent);
+  for (int e = 0; e < n_ent; ++e) {
+    const vb_entity &E = ents[e];
+    if (E.n <= 0 || !E.gids || E.n_con < 0 || (E.n_con > 0 && !E.con) || E.n_con > 1024)
+      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad entity " + std::to_string(e));
+    EntH &H = ctx->ents[e];
+    H.kind = E.kind;
+    H.n = E.n;
+    H.ncon = E.n_con;
+    H.gids.assign(E.gids, E.gids + E.n);
+    H.con.assign(E.con, E.con + (size_t)E.n_con * E.n);
+    for (int j = 0; j < E.n; ++j) {
+      int64_t g = E.gids[j];
+      if (g < 0 || g >= n_iface || ent_of[g] >= 0)
+        return ctx->fail(VB_ERR_ARG, "vb_assemble: entity ids must cover each interface id once");
+      ent_of[g] = e;
+      pos_in[g] = j;
+    }
+  }
+  for (int64_t g = 0; g < n_iface; ++g)
+    if (ent_of[g] < 0) return ctx->fail(VB_ERR_ARG, "vb_assemble: interface id not in any entity");
+  // subdomains
+  ctx->subs.resize(n_sub);
+  for (int s = 0; s < n_sub; ++s) {
+    const vb_subdomain &D = subs[s];
+    SubH &S = ctx->subs[s];
+    if (D.n <= 0 || !D.indptr || !D.indices || !D.data || !D.kind || !D.gid || !D.pweight || !D.rhs)
+      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad subdomain " + std::to_string(s));
+    S.n = D.n;
+    S.indptr.assign(D.indptr, D.indptr + D.n + 1);
+    if (S.indptr[0] != 0 || S.indptr[D.n] != D.nnz)
+      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad indptr in subdomain " + std::to_string(s));
+    S.indices.resize(D.nnz);
+    for (int64_t q = 0; q < D.nnz; ++q) {
+      if (D.indices[q] < 0 || D.indices[q] >= D.n)
+        return ctx->fail(VB_ERR_ARG, "vb_assemble: column index out of range");
+      S.indices[q] = (int32_t)D.indices[q];
+    }
+    S.vals.assign(D.data, D.data + D.nnz);
+    S.rhs.assign(D.rhs, D.rhs + D.n);
+    S.kind.assign(D.kind, D.kind + D.n);
+    S.gid.assign(D.gid, D.gid + D.n);
+    std::vector<std::pair<int64_t, int>> iface;
+    S.nv = S.nel = 0;
+    for (int i = 0; i < D.n; ++i) {
+      if (S.kind[i] == VB_KIND_INTERIOR) S.nv++;
+      else if (S.kind[i] == VB_KIND_PRESSURE) S.nel++;
+      else if (S.kind[i] == VB_KIND_INTERFACE) {
+        int64_t g = S.gid[i];
+        if (g < 0 || g >= n_iface) return ctx->fail(VB_ERR_ARG, "vb_assemble: bad gid");
+        iface.push_back({((int64_t)ent_of[g] << 32) | pos_in[g], i});
+      } else
+        return ctx->fail(VB_ERR_ARG, "vb_assemble: bad kind");
+    }
+    if (S.nel < 2) return ctx->fail(VB_ERR_ARG, "vb_assemble: a subdomain needs >= 2 pressures");
+    std::sort(iface.begin(), iface.end());
+    S.ng = (int)iface.size();
+    S.N = S.nv + S.nel + S.ng + 1;
+    S.e = S.nv + S.nel - 1;
+    S.ld = round_up(S.N, 32);
+    S.pos.assign(D.n, -1);
+    int cv = 0, cp = 0;
+    S.pw.clear();
+    for (int i = 0; i < D.n; ++i) {
+      if (S.kind[i] == VB_KIND_INTERIOR) S.pos[i] = cv++;
+      else if (S.kind[i] == VB_KIND_PRESSURE) {
+        S.pos[i] = S.nv + cp++;
+        S.pw.push_back(D.pweight[i]);
+        S.vol += D.pweight[i];
+      }
+    }
+    S.gidl.resize(S.ng);
+    S.ents.clear();
+    S.ent_off.clear();
+    for (int l = 0; l < S.ng; ++l) {
+      int i = iface[l].second;
+      S.pos[i] = S.nv + S.nel + l;
+      S.gidl[l] = S.gid[i];
+      int e = ent_of[S.gid[i]];
+      if (S.ents.empty() || S.ents.back() != e) {
+        S.ents.push_back(e);
+        S.ent_off.push_back(l);
+      }
+    }
+    for (size_t q = 0; q < S.ents.size(); ++q) {
+      int e = S.ents[q];
+      int cnt = (q + 1 < S.ents.size() ? S.ent_off[q + 1] : S.ng) - S.ent_off[q];
+      if (cnt != ctx->ents[e].n)
+        return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(s) +
+                                         " holds only part of entity " + std::to_string(e));
+      ctx->ents[e].subs.push_back(s);
+    }
+    ctx->max_n_csr = std::max(ctx->max_n_csr, S.n);
+    ctx->max_N = std::max(ctx->max_N, S.N);
+    ctx->max_e = std::max(ctx->max_e, S.e);
+    ctx->max_ng = std::max(ctx->max_ng, S.ng);
+    ctx->max_ent = std::max(ctx->max_ent, (int)S.ents.size());
+  }
+  // ---- device copies of the caller's data and the dense workspace
+  int64_t wtot = 0, itot = 0, btot = 0, htot = 0;
+  for (auto &S : ctx->subs) {
+    S.W_off = wtot;
+    wtot += S.ld * S.N;
+    S.inv_off = itot;
+    itot += (int64_t)((S.e + NB - 1) / NB) * NB * NB;
+    S.b0_off = btot;
+    btot += S.ng + 1;
+    S.hv_off = htot;
+    htot += S.nel + 1;
+  }
+  CHK(ctx->dalloc(&ctx->W, wtot));
+  CHK(ctx->dalloc(&ctx->invL, itot));
+  CHK(ctx->dalloc(&ctx->b0, btot));
+  CHK(ctx->dalloc(&ctx->hv, htot));
+  CHK(ctx->dalloc(&ctx->info, 4 * (size_t)n_sub + 64 + 4 * (size_t)n_ent));
+  ctx->subdev.resize(n_sub);
+  for (int s = 0; s < n_sub; ++s) {
+    SubH &S = ctx->subs[s];
+    CHK(ctx->upload(&S.d_indptr, S.indptr));
+    CHK(ctx->upload(&S.d_indices, S.indices));
+    CHK(ctx->upload(&S.d_vals, S.vals));
+    CHK(ctx->upload(&S.d_rhs, S.rhs));
+    CHK(ctx->upload(&S.d_pos, S.pos));
+    CHK(ctx->upload(&S.d_kind, S.kind));
+    CHK(ctx->upload(&S.d_gid, S.gid));
+    CHK(ctx->upload(&S.d_pw, S.pw));
+    std::vector<int64_t> gext(S.gidl);
+    gext.push_back(n_iface + s);
+    CHK(ctx->upload(&S.d_gidl, gext));
+    CHK(ctx->upload(&S.d_ents, S.ents));
+    CHK(ctx->upload(&S.d_entoff, S.ent_off));
+    SubDev &D = ctx->subdev[s];
+    D.W = ctx->W + S.W_off;
+    D.ld = S.ld;
+    D.nv = S.nv;
+    D.nel = S.nel;
+    D.ng = S.ng;
+    D.N = S.N;
+    D.e = S.e;
+    D.n_csr = S.n;
+    D.indptr = S.d_indptr;
+    D.indices = S.d_indices;
+    D.vals = S.d_vals;
+    D.rhs = S.d_rhs;
+    D.pos = S.d_pos;
+    D.pweight = S.d_pw;
+    D.hv = ctx->hv + S.hv_off;
+    D.b0 = ctx->b0 + S.b0_off;
+    D.gidl = S.d_gidl;
+    D.n_ent = (int)S.ents.size();
+    D.ent = S.d_ents;
+    D.ent_off = S.d_entoff;
+  }
+  CHK(ctx->upload(&ctx->d_subdev, ctx->subdev));
+  ctx->entdev.resize(n_ent);
+  for (int e = 0; e < n_ent; ++e) {
+    EntH &H = ctx->ents[e];
+    CHK(ctx->upload(&H.d_gids, H.gids));
+    CHK(ctx->upload(&H.d_con, H.con));
+    int rmax = std::max(1, std::min(H.ncon, H.n));
+    CHK(ctx->dalloc(&H.d_V, (size_t)H.n * rmax));
+    CHK(ctx->dalloc(&H.d_tau, (size_t)rmax));
+    CHK(ctx->dalloc(&H.d_work, (size_t)H.n * std::max(1, H.ncon)));
+    H.d_rank = ctx->info + 4 * n_sub + 64 + e;
+    EntDev &D = ctx->entdev[e];
+    D.n = H.n;
+    D.n_con = H.ncon;
+    D.con = H.d_con;
+    D.gids = H.d_gids;
+    D.V = H.d_V;
+    D.tau = H.d_tau;
+    D.rank = H.d_rank;
+    D.work = H.d_work;
+  }
+  CHK(ctx->upload(&ctx->d_entdev, ctx->entdev));
+  ctx->state = 1;
+  return VB_OK;
+}
+
+// ------------------------------------------------------------------ setup
+static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<double>> &jobs, int max_n, int max_e) {
+  if (jobs.empty()) return VB_OK;
+  LdlJob<double> *dj = nullptr;
+  CHK(ctx->upload(&dj, jobs, true));
+  CHK(ldl_batched<double>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream));
+  return VB_OK;
+}
+
+static int run_gather(vb_ctx *ctx, const std::vector<GatherJob> &jobs, int max_m, int max_n) {
+  if (jobs.empty()) return VB_OK;
+  GatherJob *dj = nullptr;
+  CHK(ctx->upload(&dj, jobs, true));
+  CHK(gather_blocks(dj, (int)jobs.size(), max_m, max_n, ctx->stream));
+  return VB_OK;
+}
+
+static int run_diag(vb_ctx *ctx, const std::vector<DiagJob> &jobs, int max_cnt) {
+  if (jobs.empty()) return VB_OK;
+  DiagJob *dj = nullptr;
+  CHK(ctx->upload(&dj, jobs, true));
+  CHK(set_diag(dj, (int)jobs.size(), max_cnt, ctx->stream));
+  return VB_OK;
+}
+
+static int run_symm(vb_ctx *ctx, const std::vector<double *> &m, const std::vector<int64_t> &ld,
+                    const std::vector<int32_t> &n, bool transpose = false) {
+  if (m.empty()) return VB_OK;
+  double **dm = nullptr;
+  int64_t *dld = nullptr;
+  int32_t *dn = nullptr;
+  CHK(ctx->upload(&dm, m, true));
+  CHK(ctx->upload(&dld, ld, true));
+  CHK(ctx->upload(&dn, n, true));
+  int mx = *std::max_element(n.begin(), n.end());
+  if (transpose)
+    CHK(transpose_sq(dm, dld, dn, (int)m.size(), mx, ctx->stream));
+  else
+    CHK(symmetrize(dm, dld, dn, (int)m.size(), mx, ctx->stream));
+  return VB_OK;
+}
+
+static int check_info(vb_ctx *ctx, int count, int code, const char *what) {
+  std::vector<int> h(count);
+  CHK(hipMemcpyAsync(h.data(), ctx->info, count * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  CHK(hipStreamSynchronize(ctx->stream));
+  for (int i = 0; i < count; ++i)
+    if (h[i] != 0)
+      return ctx->fail(code, std::string(what) + ": pivot breakdown in block " + std::to_string(i) +
+                                 " at column " + std::to_string(h[i] - 1));
+  return VB_OK;
+}
+
+int vb_setup(vb_ctx *ctx) {
+  if (!ctx) return VB_ERR_ARG;
+  if (ctx->state != 1) return ctx->fail(VB_ERR_STATE, "vb_setup: call vb_assemble first (once)");
+  hipStream_t st = ctx->stream;
+  const int nS = ctx->nS;
+  const int64_t nG = ctx->nG;
+  CHK(hipEventRecord(ctx->ev0, st));
+  // ---- 1. local dense bordered matrices, flux rows, pressure split
+  int64_t wtot = 0;
+  for (auto &S : ctx->subs) wtot += S.ld * S.N;
+  CHK(hipMemsetAsync(ctx->W, 0, wtot * sizeof(double), st));
+  CHK(hipMemsetAsync(ctx->info, 0, (4 * (size_t)nS + 64 + 4 * ctx->ents.size()) * sizeof(int), st));
+  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, st));
+  CHK(flux_rows(ctx->d_subdev, nS, ctx->max_ng, st));
+  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, st));
+  // ---- 2. Dirichlet factorisation + Schur complement (eqs. uipi, firstSchur)
+  {
+    std::vector<LdlJob<double>> jobs(nS);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      jobs[s] = {ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0, ctx->invL + S.inv_off, ctx->info + s};
+    }
+    int rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
+    if (rc) return rc;
+    rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index)");
+    if (rc) return rc;
+  }
+  // ---- 3. primal constraints: QR with column pivoting per entity
+  const int nE = (int)ctx->ents.size();
+  {
+    int rmax = 1;
+    for (auto &H : ctx->ents) rmax = std::max(rmax, std::min(H.ncon, H.n));
+    CHK(entity_qr(ctx->d_entdev, nE, rmax, ctx->opt.svd_tol, st));
+    std::vector<int> rk(nE);
+    if (nE) {
+      CHK(hipMemcpyAsync(rk.data(), ctx->info + 4 * nS + 64, nE * sizeof(int), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+    }
+    for (int e = 0; e < nE; ++e) ctx->ents[e].rank = rk[e];
+  }
+  // coarse numbering
+  std::vector<int32_t> cstart(nE + 1, 0);
+  for (int e = 0; e < nE; ++e) cstart[e + 1] = cstart[e] + ctx->ents[e].rank;
+  ctx->nC = cstart[nE];
+  ctx->nCS = ctx->nC + nS;
+  for (int s = 0; s < nS; ++s) {
+    SubH &S = ctx->subs[s];
+    S.pl.clear();
+    S.dl.clear();
+    S.cidx.clear();
+    S.doff.clear();
+    for (size_t q = 0; q < S.ents.size(); ++q) {
+      const EntH &H = ctx->ents[S.ents[q]];
+      S.doff.push_back((int64_t)S.dl.size());
+      for (int j = 0; j < H.n; ++j) {
+        if (j < H.rank) {
+          S.pl.push_back(S.ent_off[q] + j);
+          S.cidx.push_back(cstart[S.ents[q]] + j);
+        } else {
+          S.dl.push_back(S.ent_off[q] + j);
+        }
+      }
+    }
+    S.npi = (int)S.pl.size();
+    S.ndl = (int)S.dl.size();
+  }
+  // ---- 4. change of basis on the bordered interface block: X <- T^T X T
+  {
+    std::vector<double *> m(nS);
+    std::vector<int64_t> ld(nS);
+    std::vector<int32_t> n(nS);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      m[s] = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+      ld[s] = S.ld;
+      n[s] = S.ng + 1;
+    }
+    int rc = run_symm(ctx, m, ld, n);
+    if (rc) return rc;
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, st));
+    rc = run_symm(ctx, m, ld, n, true);
+    if (rc) return rc;
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, st));
+    CHK(transform_b0(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ent, st));
+  }
+  // ---- 5. transformed right-hand side g~ (owner sums over the rhs columns)
+  const int64_t nTot = nG + nS;
+  CHK(ctx->dalloc(&ctx->g, nTot));
+  {
+    std::vector<std::vector<int64_t>> own(nG);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      for (int l = 0; l < S.ng; ++l)
+        own[S.gidl[l]].push_back(S.W_off + (S.e + 1 + l) + (int64_t)(S.e + 1 + S.ng) * S.ld);
+    }
+    std::vector<int64_t> ptr(nG + 1, 0), idx;
+    for (int64_t g = 0; g < nG; ++g) {
+      ptr[g + 1] = ptr[g] + own[g].size();
+      idx.insert(idx.end(), own[g].begin(), own[g].end());
+    }
+    CHK(ctx->upload(&ctx->g_ptr, ptr, true));
+    CHK(ctx->upload(&ctx->g_idx, idx, true));
+    CHK(owner_sum((int)nG, ctx->g_ptr, ctx->g_idx, ctx->W, nullptr, nullptr, ctx->g, st));
+    std::vector<int64_t> src(nS), dst(nS);
+    for (int s = 0; s < nS; ++s) {
+      src[s] = ctx->subs[s].b0_off + ctx->subs[s].ng;
+      dst[s] = nG + s;
+    }
+    CHK(ctx->upload(&ctx->p0_src, src, true));
+    CHK(ctx->upload(&ctx->p0_dst, dst, true));
+    CHK(scatter_copy(nS, ctx->b0, ctx->p0_src, ctx->p0_dst, ctx->g, 1.0, st));
+  }
+  // border of X becomes the transformed flux row: X_s = [[S~, b0~], [b0~^T, 0]]
+  {
+    std::vector<GatherJob> jobs;
+    std::vector<DiagJob> dj;
+    std::vector<int32_t> iota(ctx->max_ng + 1);
+    std::iota(iota.begin(), iota.end(), 0);
+    int32_t *d_iota = nullptr;
+    CHK(ctx->upload(&d_iota, iota, true));
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+      double *b0 = ctx->b0 + S.b0_off;
+      // last column: X[l, ng] = b0[l]  (in: b0 as an ng x 1 matrix)
+      jobs.push_back({b0, 1, X + (int64_t)S.ng * S.ld, S.ld, d_iota, d_iota, S.ng, 1, 1.0, 0});
+      // last row: X[ng, l] = b0[l]  (in: b0 as a 1 x ng matrix, ld 1)
+      jobs.push_back({b0, 1, X + S.ng, S.ld, d_iota, d_iota, 1, S.ng, 1.0, 0});
+      dj.push_back({X, S.ld, S.ng, S.ng, 1, 0.0});
+    }
+    int rc = run_gather(ctx, jobs, ctx->max_ng, ctx->max_ng);
+    if (rc) return rc;
+    rc = run_diag(ctx, dj, 1);
+    if (rc) return rc;
+  }
+  // ---- 6. local constrained Neumann problems: eliminate the duals of
+  //         [[S_DD, S_DP, I], [S_PD, S_PP, 0], [I, 0, 0]] -> [[S_Pi, .], [Phi, -S_DD^-1]]
+  {
+    std::vector<GatherJob> gj;
+    std::vector<DiagJob> dj;
+    std::vector<LdlJob<double>> lj;
+    int max_m = 0, max_e = 0, mxg = 0;
+    int64_t ntot = 0;
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      S.Nn = 2 * S.ndl + S.npi;
+      S.Nld = round_up(std::max(S.Nn, 1), 32);
+      ntot += S.Nld * std::max(S.Nn, 1);
+    }
+    double *Nall = nullptr;
+    CHK(ctx->dalloc(&Nall, ntot, true));
+    CHK(hipMemsetAsync(Nall, 0, ntot * sizeof(double), st));
+    int64_t off = 0, itot = 0;
+    for (auto &S : ctx->subs) itot += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
+    double *invN = nullptr;
+    CHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
+    int64_t ioff = 0;
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      S.Nmat = Nall + off;
+      off += S.Nld * std::max(S.Nn, 1);
+      std::vector<int32_t> idx(S.dl);
+      idx.insert(idx.end(), S.pl.begin(), S.pl.end());
+      int32_t *d_idx = nullptr;
+      CHK(ctx->upload(&d_idx, idx, true));
+      const double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+      int m = S.ndl + S.npi;
+      gj.push_back({X, S.ld, S.Nmat, S.Nld, d_idx, d_idx, m, m, 1.0, 0});
+      mxg = std::max(mxg, m);
+      if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0});
+      lj.push_back({S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, invN + ioff, ctx->info + s});
+      ioff += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
+      max_m = std::max(max_m, S.Nn);
+      max_e = std::max(max_e, S.ndl);
+      ctx->max_ndl = std::max(ctx->max_ndl, S.ndl);
+      ctx->max_npi = std::max(ctx->max_npi, S.npi);
+    }
+    int rc = run_gather(ctx, gj, mxg, mxg);
+    if (rc) return rc;
+    rc = run_diag(ctx, dj, ctx->max_ndl);
+    if (rc) return rc;
+    CHK(hipMemsetAsync(ctx->info, 0, nS * sizeof(int), st));
+    rc = run_ldl(ctx, lj, max_m, max_e);
+    if (rc) return rc;
+    rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Neumann factorisation (subdomain index)");
+    if (rc) return rc;
+    // symmetrize the trailing block, then G1 = [S_DD^-1 | Phi]
+    std::vector<double *> m;
+    std::vector<int64_t> ld;
+    std::vector<int32_t> n;
+    for (auto &S : ctx->subs) {
+      m.push_back(S.Nmat + S.ndl + S.ndl * S.Nld);
+      ld.push_back(S.Nld);
+      n.push_back(S.npi + S.ndl);
+    }
+    rc = run_symm(ctx, m, ld, n);
+    if (rc) return rc;
+    int64_t gtot = 0;
+    for (auto &S : ctx->subs) gtot += (int64_t)S.ndl * (S.ndl + S.npi);
+    double *G1all = nullptr;
+    CHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1)));
+    std::vector<GatherJob> ej;
+    int64_t goff = 0;
+    int mxr = 0, mxc = 0;
+    for (auto &S : ctx->subs) {
+      S.G1 = G1all + goff;
+      goff += (int64_t)S.ndl * (S.ndl + S.npi);
+      if (!S.ndl) continue;
+      std::vector<int32_t> rows(S.ndl), cols(S.ndl), pc(S.npi);
+      for (int a = 0; a < S.ndl; ++a) rows[a] = cols[a] = S.npi + a;
+      for (int a = 0; a < S.npi; ++a) pc[a] = a;
+      int32_t *dr = nullptr, *dpc = nullptr;
+      CHK(ctx->upload(&dr, rows, true));
+      CHK(ctx->upload(&dpc, pc, true));
+      const double *T = S.Nmat + S.ndl + S.ndl * S.Nld;
+      ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0});
+      if (S.npi) ej.push_back({T, S.Nld, S.G1 + (int64_t)S.ndl * S.ndl, S.ndl, dr, dpc, S.ndl, S.npi, 1.0, 0});
+      mxr = std::max(mxr, S.ndl);
+      mxc = std::max(mxc, std::max(S.ndl, S.npi));
+    }
+    rc = run_gather(ctx, ej, mxr, mxc);
+    if (rc) return rc;
+  }
+  // ---- 7. coarse problem
+  {
+    const int nCS = ctx->nCS;
+    ctx->Kld = round_up(2 * nCS, 32);
+    CHK(ctx->dalloc(&ctx->Kaug, ctx->Kld * 2 * nCS, true));
+    CHK(hipMemsetAsync(ctx->Kaug, 0, ctx->Kld * 2 * nCS * sizeof(double), st));
+    std::vector<CoarseSub> cs(nS);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      int32_t *dc = nullptr, *dp = nullptr;
+      CHK(ctx->upload(&dc, S.cidx, true));
+      CHK(ctx->upload(&dp, S.pl, true));
+      cs[s] = {S.Nmat + S.ndl + S.ndl * S.Nld, S.Nld, S.npi, dc, dp, ctx->b0 + S.b0_off};
+    }
+    CoarseSub *dcs = nullptr;
+    CHK(ctx->upload(&dcs, cs, true));
+    double vn = 0.0;
+    for (auto &S : ctx->subs) vn += S.vol * S.vol;
+    vn = std::sqrt(vn);
+    std::vector<double> w(nS);
+    for (int s = 0; s < nS; ++s) w[s] = ctx->subs[s].vol / vn;
+    double *dw = nullptr;
+    CHK(ctx->upload(&dw, w, true));
+    CHK(coarse_assemble(dcs, nS, ctx->Kaug, ctx->Kld, ctx->nC, dw, st));
+    std::vector<DiagJob> dj{{ctx->Kaug, ctx->Kld, nCS, 0, nCS, 1.0}};
+    int rc = run_diag(ctx, dj, nCS);
+    if (rc) return rc;
+    double *invC = nullptr;
+    CHK(ctx->dalloc(&invC, (int64_t)((nCS + NB - 1) / NB) * NB * NB, true));
+    std::vector<LdlJob<double>> lj{{ctx->Kaug, ctx->Kld, 2 * nCS, nCS, ctx->nC, 0, invC,
+                                    ctx->info + nS}};
+    rc = run_ldl(ctx, lj, 2 * nCS, nCS);
+    if (rc) return rc;
+    {
+      std::vector<int> h(1);
+      CHK(hipMemcpyAsync(h.data(), ctx->info + nS, sizeof(int), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      if (h[0]) return ctx->fail(VB_ERR_SINGULAR_COARSE, "coarse factorisation: pivot breakdown at column " + std::to_string(h[0] - 1));
+    }
+    std::vector<double *> m{ctx->Kaug + nCS + nCS * ctx->Kld};
+    std::vector<int64_t> ld{ctx->Kld};
+    std::vector<int32_t> n{nCS};
+    rc = run_symm(ctx, m, ld, n);
+    if (rc) return rc;
+    CHK(ctx->dalloc(&ctx->Gc, (int64_t)nCS * nCS));
+    std::vector<int32_t> iota(nCS);
+    std::iota(iota.begin(), iota.end(), 0);
+    int32_t *di = nullptr;
+    CHK(ctx->upload(&di, iota, true));
+    std::vector<GatherJob> gj{{m[0], ctx->Kld, ctx->Gc, nCS, di, di, nCS, nCS, -1.0, 0}};
+    rc = run_gather(ctx, gj, nCS, nCS);
+    if (rc) return rc;
+  }
+  // ---- 8. scaling: deluxe D_E^(s) = (sum_l Sbar^(l))^-1 Sbar^(s) on the duals
+  {
+    std::vector<LdlJob<double>> lj;
+    std::vector<GemmJob<double>> mj;
+    std::vector<DiagJob> dj;
+    std::vector<std::vector<GatherJob>> rounds;
+    std::vector<GatherJob> sb;
+    int max_m = 0;
+    int64_t itot = 0;
+    for (auto &H : ctx->ents) {
+      int m = H.n - H.rank;
+      if (m > 0) itot += (int64_t)((m + NB - 1) / NB) * NB * NB;
+    }
+    double *invD = nullptr;
+    CHK(ctx->dalloc(&invD, std::max<int64_t>(itot, 1), true));
+    int64_t ioff = 0;
+    int cnt = 0;
+    for (int e = 0; e < nE; ++e) {
+      EntH &H = ctx->ents[e];
+      const int m = H.n - H.rank;
+      H.D.assign(H.subs.size(), nullptr);
+      H.Sbar.assign(H.subs.size(), nullptr);
+      std::vector<int64_t> dg(H.gids.begin() + H.rank, H.gids.end());
+      CHK(ctx->upload(&H.d_dual_gids, dg));
+      if (m <= 0) continue;
+      max_m = std::max(max_m, m);
+      for (size_t q = 0; q < H.subs.size(); ++q) CHK(ctx->dalloc(&H.D[q], (int64_t)m * m));
+      if (ctx->opt.scaling == VB_SCALING_COUNTING) {
+        for (size_t q = 0; q < H.subs.size(); ++q) {
+          CHK(hipMemsetAsync(H.D[q], 0, (size_t)m * m * sizeof(double), st));
+          dj.push_back({H.D[q], m, 0, 0, m, 1.0 / H.subs.size()});
+        }
+        continue;
+      }
+      H.Dld = round_up(2 * m, 32);
+      CHK(ctx->dalloc(&H.Daug, H.Dld * 2 * m, true));
+      CHK(hipMemsetAsync(H.Daug, 0, H.Dld * 2 * m * sizeof(double), st));
+      for (size_t q = 0; q < H.subs.size(); ++q) {
+        const int s = H.subs[q];
+        SubH &S = ctx->subs[s];
+        int qq = (int)(std::find(S.ents.begin(), S.ents.end(), e) - S.ents.begin());
+        std::vector<int32_t> idx(m);
+        for (int a = 0; a < m; ++a) idx[a] = S.ent_off[qq] + H.rank + a;
+        int32_t *d_idx = nullptr;
+        CHK(ctx->upload(&d_idx, idx, true));
+        const double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+        if (rounds.size() <= q) rounds.resize(q + 1);
+        rounds[q].push_back({X, S.ld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1});
+        CHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
+        sb.push_back({X, S.ld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0});
+        mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, m, m, m, m, 0, -1.0, 0.0});
+      }
+      dj.push_back({H.Daug, H.Dld, m, 0, m, 1.0});
+      lj.push_back({H.Daug, H.Dld, 2 * m, m, m, 0, invD + ioff, ctx->info + 2 * nS + 2 + (cnt % 16)});
+      ioff += (int64_t)((m + NB - 1) / NB) * NB * NB;
+      ++cnt;
+    }
+    for (auto &rj : rounds) {
+      int rc = run_gather(ctx, rj, max_m, max_m);
+      if (rc) return rc;
+    }
+    int rc = run_gather(ctx, sb, max_m, max_m);
+    if (rc) return rc;
+    rc = run_diag(ctx, dj, max_m);
+    if (rc) return rc;
+    if (!lj.empty()) {
+      CHK(hipMemsetAsync(ctx->info + 2 * nS + 2, 0, 16 * sizeof(int), st));
+      rc = run_ldl(ctx, lj, 2 * max_m, max_m);
+      if (rc) return rc;
+      std::vector<int> h(16);
+      CHK(hipMemcpyAsync(h.data(), ctx->info + 2 * nS + 2, 16 * sizeof(int), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      for (int v : h)
+        if (v) return ctx->fail(VB_ERR_NOT_SPD, "deluxe scaling: sum of face/edge Schur blocks not SPD");
+      std::vector<double *> m;
+      std::vector<int64_t> ld;
+      std::vector<int32_t> n;
+      for (auto &H : ctx->ents)
+        if (H.Daug) {
+          int mm = H.n - H.rank;
+          m.push_back(H.Daug + mm + mm * H.Dld);
+          ld.push_back(H.Dld);
+          n.push_back(mm);
+        }
+      rc = run_symm(ctx, m, ld, n);
+      if (rc) return rc;
+      GemmJob<double> *dmj = nullptr;
+      CHK(ctx->upload(&dmj, mj, true));
+      CHK(gemm_nt_batched<double>(dmj, (int)mj.size(), max_m, max_m, st));
+    }
+  }
+  // ---- 9. iteration structures
+  {
+    // vectors
+    CHK(ctx->dalloc(&ctx->x, nTot));
+    CHK(ctx->dalloc(&ctx->r, nTot));
+    CHK(ctx->dalloc(&ctx->z, nTot));
+    CHK(ctx->dalloc(&ctx->p, nTot));
+    CHK(ctx->dalloc(&ctx->q, nTot));
+    CHK(ctx->dalloc(&ctx->tmp, nTot));
+    CHK(ctx->dalloc(&ctx->sc, SC_COUNT));
+    CHK(ctx->dalloc(&ctx->part, 2 * DOT_BLOCKS));
+    CHK(ctx->dalloc(&ctx->hist_a, ctx->opt.maxit + 2));
+    CHK(ctx->dalloc(&ctx->hist_b, ctx->opt.maxit + 2));
+    // S_hat: per-subdomain bordered GEMV (reads p) + owner sums (into q)
+    std::vector<GemvJob> js(nS);
+    int64_t yoff = 0;
+    std::vector<std::vector<int64_t>> own(nTot);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      S.y_off = yoff;
+      js[s] = {ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld, S.ld, S.ng + 1, S.ng + 1, ctx->p,
+               S.d_gidl, nullptr, nullptr, 1.0, 0};
+      for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff + l);
+      own[nG + s].push_back(yoff + S.ng);
+      yoff += S.ng + 1;
+    }
+    ctx->n_yloc = yoff;
+    CHK(ctx->dalloc(&ctx->yloc, yoff));
+    for (int s = 0; s < nS; ++s) js[s].y = ctx->yloc + ctx->subs[s].y_off;
+    std::vector<int64_t> ptr(nTot + 1, 0), idx;
+    for (int64_t gg = 0; gg < nTot; ++gg) {
+      ptr[gg + 1] = ptr[gg] + own[gg].size();
+      idx.insert(idx.end(), own[gg].begin(), own[gg].end());
+    }
+    CHK(ctx->upload(&ctx->own_ptr, ptr));
+    CHK(ctx->upload(&ctx->own_idx, idx));
+    // dual vectors: gD (restricted), wv (Neumann output), tv (Neumann [t1; t2])
+    int64_t goff = 0, toff = 0;
+    std::vector<int64_t> sgo(nS), sto(nS);
+    for (int s = 0; s < nS; ++s) {
+      sgo[s] = goff;
+      sto[s] = toff;
+      goff += ctx->subs[s].ndl;
+      toff += ctx->subs[s].ndl + ctx->subs[s].npi;
+    }
+    ctx->n_gD = goff;
+    ctx->n_tv = toff;
+    CHK(ctx->dalloc(&ctx->gD, goff));
+    CHK(ctx->dalloc(&ctx->wv, goff));
+    CHK(ctx->dalloc(&ctx->tv, toff));
+    CHK(ctx->dalloc(&ctx->rc, ctx->nCS));
+    CHK(ctx->dalloc(&ctx->uc, ctx->nCS));
+    // restriction jobs per (entity, subdomain) with duals
+    std::vector<GemvJob> jr;
+    std::vector<ExtJob> ej;
+    std::vector<ExtPart> ep;
+    for (int e = 0; e < nE; ++e) {
+      EntH &H = ctx->ents[e];
+      const int m = H.n - H.rank;
+      if (m <= 0) continue;
+      ExtJob J{m, (int)H.subs.size(), (int)ep.size(), H.d_dual_gids};
+      for (size_t qd = 0; qd < H.subs.size(); ++qd) {
+        const int s = H.subs[qd];
+        SubH &S = ctx->subs[s];
+        int qq = (int)(std::find(S.ents.begin(), S.ents.end(), e) - S.ents.begin());
+        const int64_t wo = sgo[s] + S.doff[qq];
+        jr.push_back({H.D[qd], m, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wo, 1.0, 0});
+        ep.push_back({H.D[qd], m, wo, 0.0});
+      }
+      ej.push_back(J);
+      ctx->max_rm = std::max(ctx->max_rm, m);
+    }
+    ctx->n_restrict = (int)jr.size();
+    ctx->n_ext = (int)ej.size();
+    ctx->max_ext_m = ctx->max_rm;
+    CHK(ctx->upload(&ctx->j_restrict, jr));
+    CHK(ctx->upload(&ctx->j_ext, ej));
+    CHK(ctx->upload(&ctx->j_extpart, ep));
+    // Neumann jobs
+    std::vector<GemvJob> jn1(nS), jn2(nS);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      std::vector<int64_t> ci(S.cidx.begin(), S.cidx.end());
+      int64_t *dci = nullptr;
+      CHK(ctx->upload(&dci, ci));
+      jn1[s] = {S.G1, std::max(S.ndl, 1), S.ndl, S.ndl + S.npi, ctx->gD + sgo[s], nullptr, nullptr,
+                ctx->tv + sto[s], 1.0, 0};
+      jn2[s] = {S.G1 + (int64_t)S.ndl * S.ndl, std::max(S.ndl, 1), S.ndl, S.npi, ctx->uc, dci,
+                ctx->tv + sto[s], ctx->wv + sgo[s], 1.0, 0};
+    }
+    CHK(ctx->upload(&ctx->j_schur, js));
+    CHK(ctx->upload(&ctx->j_neu1, jn1));
+    CHK(ctx->upload(&ctx->j_neu2, jn2));
+    std::vector<GemvJob> jc{{ctx->Gc, ctx->nCS, ctx->nCS, ctx->nCS, ctx->rc, nullptr, nullptr,
+                             ctx->uc, 1.0, 0}};
+    CHK(ctx->upload(&ctx->j_coarse, jc));
+    // coarse rhs: base = r at the primal positions (or p0), owners = Phi^T g contributions
+    std::vector<int64_t> base(ctx->nCS), dst(ctx->nCS);
+    std::vector<std::vector<int64_t>> cown(ctx->nCS);
+    for (int e = 0; e < nE; ++e) {
+      EntH &H = ctx->ents[e];
+      for (int j = 0; j < H.rank; ++j) base[cstart[e] + j] = H.gids[j];
+    }
+    for (int s = 0; s < nS; ++s) base[ctx->nC + s] = nG + s;
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      for (int a = 0; a < S.npi; ++a) cown[S.cidx[a]].push_back(sto[s] + S.ndl + a);
+    }
+    std::vector<int64_t> cptr(ctx->nCS + 1, 0), cidx;
+    for (int c = 0; c < ctx->nCS; ++c) {
+      cptr[c + 1] = cptr[c] + cown[c].size();
+      cidx.insert(cidx.end(), cown[c].begin(), cown[c].end());
+    }
+    CHK(ctx->upload(&ctx->c_ptr, cptr));
+    CHK(ctx->upload(&ctx->c_idx, cidx));
+    CHK(ctx->upload(&ctx->c_base, base));
+    CHK(ctx->upload(&ctx->uc_dst, base));
+    for (auto &S : ctx->subs) {
+      ctx->max_gt_m = std::max(ctx->max_gt_m, S.ng + 1);
+      ctx->max_nt = std::max(ctx->max_nt, S.ndl + S.npi);
+    }
+  }
+  // ---- 10. recovery structures
+  {
+    std::vector<int64_t> yoff(nS), invoff(nS);
+    int64_t tot = 0, otot = 0;
+    ctx->rec_off.assign(nS + 1, 0);
+    for (int s = 0; s < nS; ++s) {
+      yoff[s] = tot;
+      tot += ctx->subs[s].e + 1;
+      invoff[s] = ctx->subs[s].inv_off;
+      ctx->rec_off[s + 1] = ctx->rec_off[s] + ctx->subs[s].n;
+    }
+    otot = ctx->rec_off[nS];
+    CHK(ctx->dalloc(&ctx->yrec, tot));
+    CHK(ctx->dalloc(&ctx->rec_out, otot));
+    CHK(ctx->upload(&ctx->d_yoff, yoff));
+    CHK(ctx->upload(&ctx->d_invoff, invoff));
+    std::vector<RecJob> rj(nS);
+    for (int s = 0; s < nS; ++s) {
+      SubH &S = ctx->subs[s];
+      rj[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
+               ctx->yrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
+    }
+    CHK(ctx->upload(&ctx->j_rec, rj));
+  }
+  CHK(hipEventRecord(ctx->ev1, st));
+  CHK(hipEventSynchronize(ctx->ev1));
+  float ms = 0.f;
+  CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->setup_ms = ms;
+  // release setup-only workspace (Neumann/deluxe augmented matrices, job arrays)
+  free_list(ctx->setup_allocs);
+  for (auto &H : ctx->ents) {
+    H.Daug = nullptr;
+    H.Sbar.clear();
+  }
+  for (auto &S : ctx->subs) S.Nmat = nullptr;
+  ctx->Kaug = nullptr;
+  ctx->state = 2;
+  return VB_OK;
+}
+
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ operators
+static int apply_S_internal(vb_ctx *ctx) {  // q <- S~ p
+  CHK(gemv_t(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m, ctx->stream));
+  CHK(owner_sum((int)(ctx->nG + ctx->nS), ctx->own_ptr, ctx->own_idx, ctx->yloc, nullptr, nullptr,
+                ctx->q, ctx->stream));
+  return VB_OK;
+}
+
+static int apply_M_internal(vb_ctx *ctx) {  // z <- M~^-1 r
+  hipStream_t st = ctx->stream;
+  if (ctx->n_restrict) CHK(gemv_t(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm, st));
+  CHK(gemv_t(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, st));
+  CHK(owner_sum(ctx->nCS, ctx->c_ptr, ctx->c_idx, ctx->tv, ctx->c_base, ctx->r, ctx->rc, st));
+  CHK(gemv_t(ctx->j_coarse, 1, ctx->nCS, ctx->nCS, st));
+  if (ctx->max_ndl) CHK(gemv_n(ctx->j_neu2, ctx->nS, ctx->max_ndl, ctx->max_npi, st));
+  if (ctx->n_ext) CHK(extend(ctx->j_ext, ctx->n_ext, ctx->max_ext_m, ctx->j_extpart, ctx->wv, ctx->z, st));
+  CHK(scatter_copy(ctx->nCS, ctx->uc, nullptr, ctx->uc_dst, ctx->z, 1.0, st));
+  return VB_OK;
+}
+
+extern "C" {
+
+int vb_rhs(vb_ctx *ctx, double *g_dev) {
+  if (!ctx || !g_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_rhs: call vb_setup first");
+  const int64_t n = ctx->nG + ctx->nS;
+  CHK(hipMemcpyAsync(g_dev, ctx->g, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  CHK(transform_vec(ctx->d_entdev, (int)ctx->ents.size(), g_dev, -1, ctx->stream));
+  return VB_OK;
+}
+
+int vb_schur_apply(vb_ctx *ctx, const double *x_dev, double *y_dev) {
+  if (!ctx || !x_dev || !y_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_schur_apply: call vb_setup first");
+  const int64_t n = ctx->nG + ctx->nS;
+  CHK(hipMemcpyAsync(ctx->p, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  CHK(transform_vec(ctx->d_entdev, (int)ctx->ents.size(), ctx->p, +1, ctx->stream));
+  int rc = apply_S_internal(ctx);
+  if (rc) return rc;
+  CHK(hipMemcpyAsync(y_dev, ctx->q, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  CHK(transform_vec(ctx->d_entdev, (int)ctx->ents.size(), y_dev, -1, ctx->stream));
+  return VB_OK;
+}
+
+int vb_apply(vb_ctx *ctx, const double *r_dev, double *z_dev) {
+  if (!ctx || !r_dev || !z_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_apply: call vb_setup first");
+  const int64_t n = ctx->nG + ctx->nS;
+  CHK(hipMemcpyAsync(ctx->r, r_dev, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  CHK(transform_vec(ctx->d_entdev, (int)ctx->ents.size(), ctx->r, +1, ctx->stream));
+  int rc = apply_M_internal(ctx);
+  if (rc) return rc;
+  CHK(hipMemcpyAsync(z_dev, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
+  CHK(transform_vec(ctx->d_entdev, (int)ctx->ents.size(), z_dev, -1, ctx->stream));
+  return VB_OK;
+}
+
+}  // extern "C"
+
+// extreme eigenvalues of the symmetric tridiagonal CG-Lanczos matrix
+// (T_jj = 1/a_j + b_{j-1}/a_{j-1}, T_j,j+1 = sqrt(b_j)/a_j) by bisection.
+static void lanczos_extremes(const std::vector<double> &a, const std::vector<double> &b,
+                             double *lmin, double *lmax) {
+  const int m = (int)a.size();
+  *lmin = *lmax = NAN;
+  if (m == 0) return;
+  std::vector<double> d(m), e(m, 0.0);
+  for (int j = 0; j < m; ++j) {
+    d[j] = 1.0 / a[j] + (j > 0 ? b[j - 1] / a[j - 1] : 0.0);
+    if (j + 1 < m) e[j] = std::sqrt(std::fabs(b[j])) / a[j];
+  }
+  double lo = 1e300, hi = -1e300;
+  for (int j = 0; j < m; ++j) {
+    double rad = (j > 0 ? std::fabs(e[j - 1]) : 0.0) + (j + 1 < m ? std::fabs(e[j]) : 0.0);
+    lo = std::min(lo, d[j] - rad);
+    hi = std::max(hi, d[j] + rad);
+  }
+  auto count_below = [&](double x) {  // Sturm count of eigenvalues < x
+    int c = 0;
+    double q = d[0] - x;
+    if (q < 0) c++;
+    for (int j = 1; j < m; ++j) {
+      if (q == 0.0) q = 1e-300;
+      q = d[j] - x - e[j - 1] * e[j - 1] / q;
+      if (q < 0) c++;
+    }
+    return c;
+  };
+  auto kth = [&](int k) {  // k-th smallest (0-based)
+    double l = lo, h = hi;
+    for (int it = 0; it < 200; ++it) {
+      double mid = 0.5 * (l + h);
+      if (count_below(mid) > k) h = mid; else l = mid;
+    }
+    return 0.5 * (l + h);
+  };
+  *lmin = kth(0);
+  *lmax = kth(m - 1);
+}
+
+extern "C" {
+
+int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
+  if (!ctx || !x_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_pcg_solve: call vb_setup first");
+  hipStream_t st = ctx->stream;
+  const int64_t n = ctx->nG + ctx->nS;
+  const int nE = (int)ctx->ents.size();
+  double hs[SC_COUNT];
+  CHK(hipEventRecord(ctx->ev0, st));
+  CHK(hipMemsetAsync(ctx->sc, 0, SC_COUNT * sizeof(double), st));
+  // x~ = T^T x0 ; r = g - S x~
+  CHK(hipMemcpyAsync(ctx->x, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  CHK(transform_vec(ctx->d_entdev, nE, ctx->x, +1, st));
+  CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int rc = apply_S_internal(ctx);
+  if (rc) return rc;
+  CHK(vsub(n, ctx->g, ctx->q, ctx->r, st));
+  CHK(dot(n, ctx->g, ctx->g, ctx->part, ctx->sc, 4, 0, nullptr, nullptr, st));
+  CHK(dot(n, ctx->r, ctx->r, ctx->part, ctx->sc, 1, 0, nullptr, nullptr, st));
+  CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  const double gn = std::sqrt(hs[SC_GG]);
+  double rel = gn > 0 ? std::sqrt(hs[SC_RR]) / gn : 0.0;
+  int it = 0, status = VB_OK;
+  if (rel > ctx->opt.tol) {
+    rc = apply_M_internal(ctx);
+    if (rc) return rc;
+    CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 3, 0, nullptr, nullptr, st));
+    CHK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    while (true) {
+      rc = apply_S_internal(ctx);
+      if (rc) return rc;
+      CHK(dot(n, ctx->p, ctx->q, ctx->part, ctx->sc, 0, it, ctx->hist_a, nullptr, st));
+      CHK(update_xr(n, ctx->sc, ctx->x, ctx->r, ctx->p, ctx->q, ctx->part, ctx->sc, st));
+      CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      ++it;
+      if (hs[SC_FLAG] != 0.0) {
+        status = VB_ERR_BREAKDOWN;
+        break;
+      }
+      rel = std::sqrt(hs[SC_RR]) / gn;
+      if (rel <= ctx->opt.tol) break;
+      if (it >= ctx->opt.maxit) {
+        status = VB_ERR_NOT_CONVERGED;
+        break;
+      }
+      rc = apply_M_internal(ctx);
+      if (rc) return rc;
+      CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 2, it - 1, nullptr, ctx->hist_b, st));
+      CHK(update_p(n, ctx->sc, ctx->p, ctx->z, st));
+    }
+  }
+  // true residual
+  CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  rc = apply_S_internal(ctx);
+  if (rc) return rc;
+  CHK(vsub(n, ctx->g, ctx->q, ctx->tmp, st));
+  CHK(dot(n, ctx->tmp, ctx->tmp, ctx->part, ctx->sc, 5, 0, nullptr, nullptr, st));
+  CHK(hipMemcpyAsync(x_dev, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  CHK(transform_vec(ctx->d_entdev, nE, x_dev, -1, st));
+  CHK(hipEventRecord(ctx->ev1, st));
+  CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  float ms = 0.f;
+  CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  if (info) {
+    info->iterations = it;
+    info->rel_residual = rel;
+    info->true_rel_residual = gn > 0 ? std::sqrt(hs[SC_TMP]) / gn : 0.0;
+    info->n_coarse = ctx->nCS;
+    info->setup_ms = ctx->setup_ms;
+    info->solve_ms = ms;
+    info->status = status;
+    std::vector<double> a(it), b(it > 0 ? it - 1 : 0);
+    if (it) CHK(hipMemcpy(a.data(), ctx->hist_a, it * sizeof(double), hipMemcpyDeviceToHost));
+    if (it > 1) CHK(hipMemcpy(b.data(), ctx->hist_b, (it - 1) * sizeof(double), hipMemcpyDeviceToHost));
+    lanczos_extremes(a, b, &info->lambda_min, &info->lambda_max);
+  }
+  if (status == VB_ERR_BREAKDOWN) return ctx->fail(status, "PCG breakdown: p^T S p <= 0 or NaN");
+  if (status == VB_ERR_NOT_CONVERGED) return ctx->fail(status, "PCG reached maxit");
+  return VB_OK;
+}
+
+int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
+  if (!ctx || !x_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_recover_all: call vb_setup first");
+  hipStream_t st = ctx->stream;
+  CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, ctx->nS, ctx->max_e, st));
+  const int nb = ctx->opt.panel;  // the panel width the factorisation used
+  for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->d_yoff, ctx->nS,
+                          j0, nb, st));
+  CHK(recover_out(ctx->j_rec, ctx->nS, x_dev, ctx->nG, st));
+  if (out_dev)
+    CHK(hipMemcpyAsync(out_dev, ctx->rec_out, ctx->rec_off[ctx->nS] * sizeof(double),
+                       hipMemcpyDeviceToDevice, st));
+  return VB_OK;
+}
+
+int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_host) {
+  if (!ctx || !x_dev || !u_host || sub < 0 || sub >= ctx->nS) return VB_ERR_ARG;
+  int rc = vb_recover_all(ctx, x_dev, nullptr);
+  if (rc) return rc;
+  CHK(hipMemcpyAsync(u_host, ctx->rec_out + ctx->rec_off[sub], ctx->subs[sub].n * sizeof(double),
+                     hipMemcpyDeviceToHost, ctx->stream));
+  CHK(hipStreamSynchronize(ctx->stream));
+  return VB_OK;
+}
+
+int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, const int32_t *ld,
+                   const int32_t *e, const int32_t *p, int32_t *info, int max_n, int max_e) {
+  if (!ctx || batch < 0 || (batch > 0 && (!A || !n || !ld || !e || !p || !info)))
+    return VB_ERR_ARG;
+  if (batch == 0) return VB_OK;
+  std::vector<double *> hA(batch);
+  std::vector<int32_t> hn(batch), hld(batch), he(batch), hp(batch);
+  hipStream_t st = ctx->stream;
+  CHK(hipMemcpyAsync(hA.data(), A, batch * sizeof(double *), hipMemcpyDeviceToHost, st));
+  CHK(hipMemcpyAsync(hn.data(), n, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CHK(hipMemcpyAsync(hld.data(), ld, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CHK(hipMemcpyAsync(he.data(), e, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CHK(hipMemcpyAsync(hp.data(), p, batch * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  for (int b = 0; b < batch; ++b)
+    if (hn[b] < 0 || hn[b] > max_n || he[b] < 0 || he[b] > hn[b] || he[b] > max_e || hld[b] < hn[b])
+      return ctx->fail(VB_ERR_ARG, "vb_batched_ldl: inconsistent sizes for matrix " + std::to_string(b));
+  const int64_t per = (int64_t)((max_e + NB - 1) / NB) * NB * NB;
+  double *scratch = nullptr;
+  CHK(hipMalloc(&scratch, std::max<int64_t>(per * batch, 1) * sizeof(double)));
+  std::vector<LdlJob<double>> jobs(batch);
+  for (int b = 0; b < batch; ++b)
+    jobs[b] = {hA[b], hld[b], hn[b], he[b], hp[b], 0, scratch + per * b, info + b};
+  LdlJob<double> *dj = nullptr;
+  hipError_t err = hipMalloc(&dj, batch * sizeof(LdlJob<double>));
+  if (err == hipSuccess) err = hipMemcpy(dj, jobs.data(), batch * sizeof(LdlJob<double>), hipMemcpyHostToDevice);
+  if (err == hipSuccess) err = hipMemsetAsync(info, 0, batch * sizeof(int32_t), st);
+  if (err == hipSuccess) err = ldl_batched<double>(dj, batch, max_n, max_e, ctx->opt.panel, st);
+  if (err == hipSuccess) err = hipStreamSynchronize(st);
+  (void)hipFree(dj);
+  (void)hipFree(scratch);
+  if (err != hipSuccess) return ctx->fail(VB_ERR_DEVICE, std::string("vb_batched_ldl: ") + hipGetErrorString(err));
+  return VB_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,474 @@
+// Setup kernels: local dense matrices, the Q_I / Q_0 pressure split, the
+// primal change of basis and block gathers.
+#include "common.h"
+#include "kernels.h"
+
+namespace vb {
+
+// Scatter the local CSR (both triangles) and the right-hand side into the
+// dense bordered matrix [[K, r], [r^T, 0]] with the DoF order
+// [interior velocity | element pressures | interface | rhs].
+__global__ void k_densify(const SubDev *subs) {
+  const SubDev S = subs[blockIdx.y];
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= S.n_csr) return;
+  const int pr = S.pos[row];
+  for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) {
+    const int pc = S.pos[S.indices[q]];
+    S.W[(int64_t)pr + (int64_t)pc * S.ld] = S.vals[q];
+  }
+  const int last = S.N - 1;
+  S.W[(int64_t)pr + (int64_t)last * S.ld] = S.rhs[row];
+  S.W[(int64_t)last + (int64_t)pr * S.ld] = S.rhs[row];
+}
+
+hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_densify, dim3((max_rows + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  return hipGetLastError();
+}
+
+// B0_Gamma^(i) = sum of the element flux rows over the interface columns and
+// the p0 right-hand side (the sum of the pressure right-hand sides): the
+// equation tested with the constant pressure on the subdomain (eq. discMat).
+__global__ void k_flux_rows(const SubDev *subs) {
+  const SubDev S = subs[blockIdx.y];
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c > S.ng) return;
+  const double *col = S.W + (int64_t)(S.nv + S.nel + c) * S.ld + S.nv;
+  double s = 0.0;
+  for (int r = 0; r < S.nel; ++r) s += col[r];
+  S.b0[c] = s;
+}
+
+hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_ng, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_flux_rows, dim3((max_ng + 1 + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  return hipGetLastError();
+}
+
+// Householder reflector H = I - tau v v^T with H w = -sign(w_last)|w| e_last
+// for the element volumes w: columns 0..nel-2 of H span Q_I (volume-weighted
+// mean zero, eq. discVQ), the last coordinate is the w direction.
+__global__ void k_house_vec(const SubDev *subs) {
+  const SubDev S = subs[blockIdx.x];
+  __shared__ double red[16];
+  double ss = 0.0;
+  for (int i = threadIdx.x; i < S.nel; i += blockDim.x) ss += S.pweight[i] * S.pweight[i];
+  ss = block_sum(ss, red);
+  const double nrm = sqrt(ss);
+  const double wl = S.pweight[S.nel - 1];
+  const double alpha = (wl >= 0.0) ? -nrm : nrm;
+  for (int i = threadIdx.x; i < S.nel; i += blockDim.x)
+    S.hv[i] = S.pweight[i] - ((i == S.nel - 1) ? alpha : 0.0);
+  __syncthreads();
+  double vv = 0.0;
+  for (int i = threadIdx.x; i < S.nel; i += blockDim.x) vv += S.hv[i] * S.hv[i];
+  vv = block_sum(vv, red);
+  if (threadIdx.x == 0) S.hv[S.nel] = (vv > 0.0) ? 2.0 / vv : 0.0;
+}
+
+// rows: W[p, j] <- H W[p, j] for every column j (one wave per column)
+__global__ void k_house_rows(const SubDev *subs) {
+  const SubDev S = subs[blockIdx.y];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + w;
+  if (j >= S.N) return;
+  double *col = S.W + (int64_t)j * S.ld + S.nv;
+  const double tau = S.hv[S.nel];
+  double s = 0.0;
+  for (int r = l; r < S.nel; r += 64) s += S.hv[r] * col[r];
+  s = warp_sum(s);
+  for (int r = l; r < S.nel; r += 64) col[r] -= tau * S.hv[r] * s;
+}
+
+// cols: W[i, p] <- W[i, p] H for every row i (one thread per row, coalesced)
+__global__ void k_house_cols(const SubDev *subs) {
+  const SubDev S = subs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= S.N) return;
+  const double tau = S.hv[S.nel];
+  double *base = S.W + i + (int64_t)S.nv * S.ld;
+  double s = 0.0;
+  for (int c = 0; c < S.nel; ++c) s += base[(int64_t)c * S.ld] * S.hv[c];
+  for (int c = 0; c < S.nel; ++c) base[(int64_t)c * S.ld] -= tau * s * S.hv[c];
+}
+
+hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_house_vec, dim3(nsub), dim3(256), 0, s, d_subs);
+  hipLaunchKernelGGL(k_house_rows, dim3((max_N + 3) / 4, nsub), dim3(256), 0, s, d_subs);
+  hipLaunchKernelGGL(k_house_cols, dim3((max_N + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  return hipGetLastError();
+}
+
+// Householder QR with column pivoting of C^T (n x n_con) per entity: the
+// first `rank` reflectors map the constraint span onto the leading
+// coordinates; columns whose residual norm falls below tol * (largest
+// initial norm) are dependent and dropped (Sec. 5.1).  One block per entity.
+__global__ void k_entity_qr(const EntDev *ents, int rmax, double tol) {
+  const EntDev E = ents[blockIdx.x];
+  const int n = E.n, r = E.n_con;
+  double *M = E.work;          // n x r column-major working copy of C^T
+  __shared__ double nrm[1024]; // residual column norms^2 (r <= 1024)
+  __shared__ double red[16];
+  __shared__ int piv;
+  for (int idx = threadIdx.x; idx < n * r; idx += blockDim.x) {
+    int i = idx % n, c = idx / n;
+    M[idx] = E.con[(int64_t)c * n + i];
+  }
+  __syncthreads();
+  double maxn0 = 0.0;
+  for (int c = 0; c < r; ++c) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) s += M[i + c * n] * M[i + c * n];
+    s = block_sum(s, red);
+    if (threadIdx.x == 0) nrm[c] = s;
+    maxn0 = fmax(maxn0, s);
+    __syncthreads();
+  }
+  int rank = 0;
+  const int kmax = min(min(r, n), rmax);
+  for (int k = 0; k < kmax; ++k) {
+    if (threadIdx.x == 0) {
+      int best = k;
+      for (int c = k + 1; c < r; ++c)
+        if (nrm[c] > nrm[best]) best = c;
+      piv = best;
+    }
+    __syncthreads();
+    const int p = piv;
+    // exact residual norm of the pivot column rows k..n-1
+    double s = 0.0;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) s += M[i + p * n] * M[i + p * n];
+    s = block_sum(s, red);
+    if (!(s > tol * tol * maxn0) || maxn0 == 0.0) break;
+    if (p != k) {
+      for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        double t = M[i + k * n];
+        M[i + k * n] = M[i + p * n];
+        M[i + p * n] = t;
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        double t = nrm[k];
+        nrm[k] = nrm[p];
+        nrm[p] = t;
+      }
+    }
+    __syncthreads();
+    const double sig = sqrt(s);
+    const double x0 = M[k + k * n];
+    const double alpha = (x0 >= 0.0) ? -sig : sig;
+    // v = x - alpha e_k (rows k..n-1), tau = 2 / v^T v
+    double *V = E.V + (int64_t)k * n;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) V[i] = (i < k) ? 0.0 : M[i + k * n] - ((i == k) ? alpha : 0.0);
+    __syncthreads();
+    double vv = 0.0;
+    for (int i = k + threadIdx.x; i < n; i += blockDim.x) vv += V[i] * V[i];
+    vv = block_sum(vv, red);
+    const double tau = 2.0 / vv;
+    if (threadIdx.x == 0) E.tau[k] = tau;
+    // apply to the remaining columns
+    for (int c = k + 1; c < r; ++c) {
+      double d = 0.0;
+      for (int i = k + threadIdx.x; i < n; i += blockDim.x) d += V[i] * M[i + c * n];
+      d = block_sum(d, red);
+      for (int i = k + threadIdx.x; i < n; i += blockDim.x) M[i + c * n] -= tau * d * V[i];
+      __syncthreads();
+      double t = 0.0;
+      for (int i = k + 1 + threadIdx.x; i < n; i += blockDim.x) t += M[i + c * n] * M[i + c * n];
+      t = block_sum(t, red);
+      if (threadIdx.x == 0) nrm[c] = t;
+      __syncthreads();
+    }
+    rank = k + 1;
+  }
+  if (threadIdx.x == 0) *E.rank = rank;
+}
+
+hipError_t entity_qr(const EntDev *d_ents, int nent, int rmax, double tol, hipStream_t s) {
+  if (!nent) return hipSuccess;
+  hipLaunchKernelGGL(k_entity_qr, dim3(nent), dim3(256), 0, s, d_ents, rmax, tol);
+  return hipGetLastError();
+}
+
+// A_b[(r0 + i) + (c0 + i) * ld] = val for i < cnt (identity blocks).
+__global__ void k_set_diag(const DiagJob *jobs) {
+  const DiagJob J = jobs[blockIdx.y];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < J.cnt) J.A[(int64_t)(J.r0 + i) + (int64_t)(J.c0 + i) * J.ld] = J.val;
+}
+
+hipError_t set_diag(const DiagJob *d_jobs, int batch, int max_cnt, hipStream_t s) {
+  if (!batch || !max_cnt) return hipSuccess;
+  hipLaunchKernelGGL(k_set_diag, dim3((max_cnt + 255) / 256, batch), dim3(256), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+// Coarse matrix of the partially assembled problem (eq. BDDCprec):
+// [[sum_i R_Pi^T S_Pi^(i) R_Pi, B0_Pi^T], [B0_Pi, -w w^T]] with w the
+// normalised subdomain volumes (removes the constant-p0 kernel of the
+// no-slip problem), bordered with the identity for the inverse.  Single
+// block, subdomains in order: the sums are deterministic.
+__global__ void k_coarse_assemble(const CoarseSub *cs, int nsub, double *K, int64_t ld, int nC,
+                                  const double *w) {
+  for (int s = 0; s < nsub; ++s) {
+    const CoarseSub C = cs[s];
+    const int m = C.npi;
+    for (int idx = threadIdx.x; idx < m * m; idx += blockDim.x) {
+      const int a = idx % m, b = idx / m;
+      K[(int64_t)C.cidx[a] + (int64_t)C.cidx[b] * ld] += C.SPi[(int64_t)a + (int64_t)b * C.ld];
+    }
+    for (int a = threadIdx.x; a < m; a += blockDim.x) {
+      const double v = C.b0[C.pl[a]];
+      K[(int64_t)(nC + s) + (int64_t)C.cidx[a] * ld] = v;
+      K[(int64_t)C.cidx[a] + (int64_t)(nC + s) * ld] = v;
+    }
+    __syncthreads();
+  }
+  for (int idx = threadIdx.x; idx < nsub * nsub; idx += blockDim.x) {
+    const int a = idx % nsub, b = idx / nsub;
+    K[(int64_t)(nC + a) + (int64_t)(nC + b) * ld] = -w[a] * w[b];
+  }
+}
+
+hipError_t coarse_assemble(const CoarseSub *d_cs, int nsub, double *K, int64_t ld, int nC,
+                           const double *w, hipStream_t s) {
+  hipLaunchKernelGGL(k_coarse_assemble, dim3(1), dim3(1024), 0, s, d_cs, nsub, K, ld, nC, w);
+  return hipGetLastError();
+}
+
+// Symmetrize square blocks: upper <- lower.
+__global__ void k_symmetrize(double *const *mats, const int64_t *lds, const int32_t *ns) {
+  double *A = mats[blockIdx.z];
+  const int64_t ld = lds[blockIdx.z];
+  const int n = ns[blockIdx.z];
+  __shared__ double t[32][33];
+  const int bi = blockIdx.x, bj = blockIdx.y;  // tile (bi, bj) with bi > bj is the source
+  if (bi < bj) return;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  for (int yy = ty; yy < 32; yy += 8) {
+    int r = bi * 32 + tx, c = bj * 32 + yy;
+    t[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int r = bj * 32 + tx, c = bi * 32 + yy;  // destination (r, c) = source (c, r)
+    if (r < n && c < n && c > r) A[r + c * ld] = t[tx][yy];
+  }
+}
+
+hipError_t symmetrize(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                      int max_n, hipStream_t s) {
+  if (!batch || !max_n) return hipSuccess;
+  int nt = (max_n + 31) / 32;
+  hipLaunchKernelGGL(k_symmetrize, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  return hipGetLastError();
+}
+
+// In-place transpose of square blocks (swap tiles (bi,bj) and (bj,bi)).
+__global__ void k_transpose_sq(double *const *mats, const int64_t *lds, const int32_t *ns) {
+  double *A = mats[blockIdx.z];
+  const int64_t ld = lds[blockIdx.z];
+  const int n = ns[blockIdx.z];
+  const int bi = blockIdx.x, bj = blockIdx.y;
+  if (bi < bj) return;
+  __shared__ double ta[32][33], tb[32][33];
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+  for (int yy = ty; yy < 32; yy += 8) {
+    int r = bi * 32 + tx, c = bj * 32 + yy;
+    ta[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+    r = bj * 32 + tx;
+    c = bi * 32 + yy;
+    tb[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+  }
+  __syncthreads();
+  for (int yy = ty; yy < 32; yy += 8) {
+    int r = bj * 32 + tx, c = bi * 32 + yy;
+    if (r < n && c < n) A[r + c * ld] = ta[tx][yy];
+    r = bi * 32 + tx;
+    c = bj * 32 + yy;
+    if (r < n && c < n) A[r + c * ld] = tb[tx][yy];
+  }
+}
+
+hipError_t transpose_sq(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                        int max_n, hipStream_t s) {
+  if (!batch || !max_n) return hipSuccess;
+  int nt = (max_n + 31) / 32;
+  hipLaunchKernelGGL(k_transpose_sq, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  return hipGetLastError();
+}
+
+// X <- X T for the bordered interface block X = W[e+1.., e+1..] (size ng+1):
+// for every local entity, apply its reflectors H_0, H_1, ... to the entity's
+// columns.  One thread per row.
+__global__ void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
+  const SubDev S = subs[blockIdx.z];
+  if ((int)blockIdx.y >= S.n_ent) return;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int nx = S.ng + 1;
+  if (i >= nx) return;
+  const EntDev E = ents[S.ent[blockIdx.y]];
+  const int o = S.ent_off[blockIdx.y];
+  const int rk = *E.rank;
+  double *X = S.W + (int64_t)(S.e + 1) + (int64_t)(S.e + 1) * S.ld;
+  double *row = X + i;
+  for (int k = 0; k < rk; ++k) {
+    const double *v = E.V + (int64_t)k * E.n;
+    const double tau = E.tau[k];
+    double t = 0.0;
+    for (int c = k; c < E.n; ++c) t += row[(int64_t)(o + c) * S.ld] * v[c];
+    t *= tau;
+    for (int c = k; c < E.n; ++c) row[(int64_t)(o + c) * S.ld] -= t * v[c];
+  }
+}
+
+hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
+                        int max_ent, hipStream_t s) {
+  if (!nsub || !max_ent) return hipSuccess;
+  hipLaunchKernelGGL(k_apply_T_cols, dim3((max_ng + 1 + 127) / 128, max_ent, nsub), dim3(128), 0, s,
+                     d_subs, d_ents);
+  return hipGetLastError();
+}
+
+// b0~ = T^T b0 (per local entity, reflectors in order H_0, H_1, ...).
+__global__ void k_transform_b0(const SubDev *subs, const EntDev *ents) {
+  const SubDev S = subs[blockIdx.x];
+  __shared__ double red[16];
+  for (int q = 0; q < S.n_ent; ++q) {
+    const EntDev E = ents[S.ent[q]];
+    const int o = S.ent_off[q];
+    const int rk = *E.rank;
+    for (int k = 0; k < rk; ++k) {
+      const double *v = E.V + (int64_t)k * E.n;
+      double t = 0.0;
+      for (int c = k + threadIdx.x; c < E.n; c += blockDim.x) t += S.b0[o + c] * v[c];
+      t = block_sum(t, red) * E.tau[k];
+      for (int c = k + threadIdx.x; c < E.n; c += blockDim.x) S.b0[o + c] -= t * v[c];
+      __syncthreads();
+    }
+  }
+}
+
+hipError_t transform_b0(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ent,
+                        hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_transform_b0, dim3(nsub), dim3(256), 0, s, d_subs, d_ents);
+  return hipGetLastError();
+}
+
+// Global vector in the entity blocks: dir=+1 x <- T^T x, dir=-1 x <- T x.
+__global__ void k_transform_vec(const EntDev *ents, double *x, int dir) {
+  const EntDev E = ents[blockIdx.x];
+  __shared__ double red[16];
+  const int rk = *E.rank;
+  for (int kk = 0; kk < rk; ++kk) {
+    const int k = (dir > 0) ? kk : rk - 1 - kk;
+    const double *v = E.V + (int64_t)k * E.n;
+    double t = 0.0;
+    for (int c = k + threadIdx.x; c < E.n; c += blockDim.x) t += x[E.gids[c]] * v[c];
+    t = block_sum(t, red) * E.tau[k];
+    for (int c = k + threadIdx.x; c < E.n; c += blockDim.x) x[E.gids[c]] -= t * v[c];
+    __syncthreads();
+  }
+}
+
+hipError_t transform_vec(const EntDev *d_ents, int nent, double *x, int dir, hipStream_t s) {
+  if (!nent) return hipSuccess;
+  hipLaunchKernelGGL(k_transform_vec, dim3(nent), dim3(256), 0, s, d_ents, x, dir);
+  return hipGetLastError();
+}
+
+// out[i + j*ldo] (+)= scale * in[ri[i] + ci[j]*ldi]; an index < 0 selects the
+// identity (1 if ri[i] == ci[j] as negative codes, else 0).
+__global__ void k_gather_blocks(const GatherJob *jobs) {
+  const GatherJob J = jobs[blockIdx.z];
+  const int i = blockIdx.x * 64 + (threadIdx.x & 63);
+  const int j0 = blockIdx.y * 64;
+  if (i >= J.m) return;
+  const int ri = J.ri[i];
+  for (int jj = threadIdx.x >> 6; jj < 64; jj += blockDim.x >> 6) {
+    const int j = j0 + jj;
+    if (j >= J.n) break;
+    const int cj = J.ci[j];
+    double v;
+    if (ri >= 0 && cj >= 0)
+      v = J.in[(int64_t)ri + (int64_t)cj * J.ldi];
+    else
+      v = (ri < 0 && ri == cj) ? 1.0 : 0.0;
+    v *= J.scale;
+    double *o = J.out + (int64_t)i + (int64_t)j * J.ldo;
+    if (J.add) *o += v; else *o = v;
+  }
+}
+
+hipError_t gather_blocks(const GatherJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {
+  if (!batch || !max_m || !max_n) return hipSuccess;
+  hipLaunchKernelGGL(k_gather_blocks, dim3((max_m + 63) / 64, (max_n + 63) / 64, batch), dim3(256),
+                     0, s, d_jobs);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- recovery
+// y = L_rI^T - L_GammaI^T u_Gamma over the eliminated columns (eq. uipi after
+// the factorisation: K_II^-1 (r_I - C u_Gamma) = L_II^-T y).  One wave per column.
+__global__ void k_recover_rhs(const SubDev *subs, const double *x, double *y, const int64_t *yoff) {
+  const SubDev S = subs[blockIdx.y];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + w;
+  if (j >= S.e) return;
+  const double *col = S.W + (int64_t)j * S.ld + (S.e + 1);
+  double s = 0.0;
+  for (int r = l; r < S.ng; r += 64) s += col[r] * x[S.gidl[r]];
+  s = warp_sum(s);
+  if (l == 0) y[yoff[blockIdx.y] + j] = col[S.ng] - s;
+}
+
+hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, const int64_t *yoff,
+                       int nsub, int max_e, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_recover_rhs, dim3((max_e + 3) / 4, nsub), dim3(256), 0, s, d_subs, x_orig, y,
+                     yoff);
+  return hipGetLastError();
+}
+
+// Block back substitution L_II^T z = y, block j (columns [j0, j0+b)):
+// z_j = inv(L_jj)^T (y_j - sum_{r >= j0+b} L[r, j-block]^T z_r).
+__global__ void k_recover_back(const SubDev *subs, const double *invL, const int64_t *invoff,
+                               double *y, const int64_t *yoff, int j0, int nb) {
+  const SubDev S = subs[blockIdx.x];
+  if (j0 >= S.e) return;
+  const int b = min(nb, S.e - j0);
+  double *z = y + yoff[blockIdx.x];
+  __shared__ double t[64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  for (int c = w; c < b; c += blockDim.x >> 6) {
+    const double *col = S.W + (int64_t)(j0 + c) * S.ld;
+    double s = 0.0;
+    for (int r = j0 + b + l; r < S.e; r += 64) s += col[r] * z[r];
+    s = warp_sum(s);
+    if (l == 0) t[c] = z[j0 + c] - s;
+  }
+  __syncthreads();
+  const double *inv = invL + invoff[blockIdx.x] + (int64_t)(j0 / nb) * nb * nb;
+  if (threadIdx.x < b) {
+    const int c = threadIdx.x;
+    // (inv^T t)_c = sum_r inv[r][c] t[r], inv lower triangular -> r >= c
+    double s = 0.0;
+    for (int r = c; r < b; ++r) s += inv[r + c * nb] * t[r];
+    z[j0 + c] = s;
+  }
+}
+
+hipError_t recover_backsolve(const SubDev *d_subs, const double *invL, const int64_t *invoff,
+                             double *y, const int64_t *yoff, int nsub, int j0, int nb,
+                             hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_recover_back, dim3(nsub), dim3(256), 0, s, d_subs, invL, invoff, y, yoff, j0,
+                     nb);
+  return hipGetLastError();
+}
+
+}  // namespace vb
