@@ -1,0 +1,173 @@
+"""Benchmark: PCG+BDDC solves per second on one MI355X.
+
+A solve runs from vb_setup entry (the subdomain matrices already resident in
+device memory) through PCG to a 1e-8 relative residual and the interior
+recovery of every subdomain.  The workload (synthetic, seeded) is the
+32^3 jittered-cube configuration: divergence-free VEM k=2, nu=1, 4x4x4
+subdomains, vertex + edge + face primal constraints, deluxe scaling, FP64.
+
+Prints one JSON line (see the design doc for the fields).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+WORKLOADS = {
+    "c2": "32^3 jittered cube (0.15h), VEM k=2, nu=1, 4x4x4 subdomains, vertex+edge+face, deluxe",
+    "c1": "8^3 cube, VEM k=2, nu=1, 2x2x2 subdomains, vertex+edge+flux, deluxe",
+}
+PEAK_FP64_TFLOPS = 78.6
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(wl, nsample, budget_s=30.0):
+    """The oracle's local Schur complement (sparse LU + one solve per
+    interface column) on `nsample` subdomains, scaled to all subdomains:
+    the dominant part of the oracle's setup; everything else the oracle does
+    is left out, so this over-estimates its solves/s."""
+    from oracle.bddc import LocalSchur
+    try:
+        from threadpoolctl import threadpool_info
+        threads = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
+    except Exception:
+        threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    done = 0
+    for s in range(nsample):
+        LocalSchur(wl["subs"][s])
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    dt = (time.perf_counter() - t0) / done
+    nsub = len(wl["subs"])
+    return {"value": 1.0 / (dt * nsub), "unit": "solves/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": "local Schur complements (sparse LU, one solve per interface column) of "
+                      "%d of %d subdomains, %.2f s each, scaled x%d; oracle coarse/deluxe/PCG "
+                      "work not included" % (done, nsub, dt, nsub)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="c2", choices=sorted(WORKLOADS))
+    ap.add_argument("--cache", default=None, help="workload .npz (generated if missing)")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=1)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    # ---- workload (before any GPU initialisation)
+    from inputs.workloads import make_workload, save_workload, load_workload
+    t = time.perf_counter()
+    if args.cache and os.path.exists(args.cache):
+        wl = load_workload(args.cache)
+        log("loaded workload %s (%.1f s)" % (args.cache, time.perf_counter() - t))
+    else:
+        wl, _ = make_workload(args.config, workers=min(16, os.cpu_count() or 1))
+        log("generated workload %s (%.1f s)" % (args.config, time.perf_counter() - t))
+        if args.cache:
+            save_workload(args.cache, wl)
+    nsub = len(wl["subs"])
+    # ---- CPU baseline (oracle, bounded sample)
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(wl, args.cpu_sample)
+        log("cpu baseline: %s" % cpu["sample"])
+    # ---- GPU
+    import torch
+    from paper_2304_09770_amd import binding as vb
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    ctx = vb.vb_create(tol=1e-8, stream=stream.cuda_stream, profile=1)
+    vb.vb_assemble(ctx, wl)
+    n = vb.vb_interface_size(ctx)
+    nloc = sum(len(sd["kind"]) for sd in wl["subs"])
+    x = torch.zeros(n, dtype=torch.float64, device=dev)
+    u = torch.zeros(nloc, dtype=torch.float64, device=dev)
+
+    def solve():
+        vb.vb_setup(ctx)
+        x.zero_()
+        info = vb.vb_pcg_solve(ctx, x)
+        vb.vb_recover_all(ctx, x, u)
+        return info
+
+    with torch.cuda.stream(stream):
+        for w in range(args.warmup):
+            info = solve()
+            stream.synchronize()
+            log("warmup %d: %d iterations, setup %.1f ms, pcg %.1f ms"
+                % (w, info["iterations"], info["setup_ms"], info["solve_ms"]))
+        vb.vb_kernel_stats(ctx, 0, reset=True)
+        vb.vb_kernel_stats(ctx, 1, reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        infos = []
+        for k in range(args.steps):
+            infos.append(solve())
+        stream.synchronize()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    dt = t1 - t0
+    ldl = vb.vb_kernel_stats(ctx, 0)
+    gmv = vb.vb_kernel_stats(ctx, 1)
+    vb.vb_destroy(ctx)
+    last = infos[-1]
+    log("timed %d solves in %.3f s: %d iterations, true residual %.2e"
+        % (args.steps, dt, last["iterations"], last["true_rel_residual"]))
+    assert last["true_rel_residual"] <= 1e-8 * 1.01, last
+    achieved = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
+    gbs = gmv["work"] / (gmv["total_ms"] * 1e-3) / 1e9 if gmv["total_ms"] > 0 else None
+    out = {
+        "metric": "PCG+BDDC solves/s at 1e-8 rel. residual, mixed/batched vs FP64 GPU",
+        "value": args.steps / dt,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * dt / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": args.config + ": " + WORKLOADS[args.config], "precision": "fp64",
+                   "subdomains": nsub, "interface_unknowns": n},
+        "roofline": {"bound": "mfma", "kernel": "k_ldl_update (dense LDL^T trailing update)",
+                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
+                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
+                     "traffic": None, "launches": ldl["launches"],
+                     "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)},
+        "iteration_kernel": {"kernel": "k_gemv_t (S_hat p, bordered local Schur GEMV)",
+                             "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": (gbs / PEAK_HBM_GBS) if gbs else None,
+                             "launches": gmv["launches"],
+                             "avg_launch_ms": gmv["total_ms"] / max(gmv["launches"], 1)},
+        "iterations": last["iterations"],
+        "true_rel_residual": last["true_rel_residual"],
+        "lambda_min": last["lambda_min"], "lambda_max": last["lambda_max"],
+        "setup_ms": last["setup_ms"], "pcg_ms": last["solve_ms"],
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

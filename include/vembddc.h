@@ -63,9 +63,18 @@ typedef struct vb_options {
   double tol;        /* PCG relative residual ||g - S x|| <= tol ||g|| (default 1e-8) */
   int maxit;         /* PCG iteration cap (default 1000) */
   double svd_tol;    /* relative rank tolerance for dependent constraints (default 1e-10) */
-  int panel;         /* dense factorisation panel width, 0 = library default */
+  int panel;         /* dense factorisation panel width (32 or 64), 0 = default 64 */
   void *stream;      /* hipStream_t for all work; NULL = default stream */
+  int profile;       /* nonzero: time every launch of the dominant kernels with HIP
+                        events on `stream` (see vb_kernel_stats) */
 } vb_options;
+
+/* Device-time statistics of one kernel, accumulated over its launches. */
+typedef struct vb_kernel_stat {
+  int launches;
+  double total_ms;   /* sum of the launch durations (HIP events) */
+  double work;       /* algorithmic flops (which = 0) or bytes (which = 1) */
+} vb_kernel_stat;
 
 /* One subdomain's reduced local saddle problem (Sec. 4.2, eq. discMat):
  * rows/cols are the local DoFs, CSR with both triangles.  Velocity DoFs are
@@ -151,6 +160,13 @@ int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_h
  * NULL to only refresh the internal copy) receives the concatenation over
  * subdomains of their local DoF vectors, each in its own CSR DoF order. */
 int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
+
+/* Statistics of the kernels timed with vb_options.profile: which = 0 the
+ * trailing update of the dense LDL^T (the setup's dominant kernel, work in
+ * flops: b*m*(m+1) per matrix and panel of width b with m trailing rows),
+ * which = 1 the bordered local Schur GEMV of S_hat p (the iteration's
+ * dominant kernel, work in bytes read/written).  reset != 0 clears them. */
+int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out);
 
 /* Batched dense partial signed LDL^T (the kernel under the Dirichlet and
  * Neumann solves).  For each of `batch` column-major matrices A_b (size n_b,

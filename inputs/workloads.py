@@ -72,3 +72,30 @@ def make_workload(name, seed=0, workers=None, **over):
     pb = Problem(mesh, r["k"], nu, workers=workers)
     dec = Decomposition(pb, cuts, r["cons"])
     return dec.workload(), {"recipe": r, "problem": pb, "decomposition": dec, "name": name}
+
+
+def save_workload(path, wl):
+    """Store a workload as one .npz of plain arrays (no pickles)."""
+    arrs = {"n_iface": np.array([wl["n_iface"]]), "nsub": np.array([len(wl["subs"])]),
+            "nent": np.array([len(wl["ents"])])}
+    for i, sd in enumerate(wl["subs"]):
+        for k, v in sd.items():
+            arrs["s%d_%s" % (i, k)] = v
+    for e, E in enumerate(wl["ents"]):
+        arrs["e%d_kind" % e] = np.array([E["kind"]])
+        arrs["e%d_gids" % e] = E["gids"]
+        arrs["e%d_con" % e] = E["con"]
+    np.savez(path, **arrs)
+
+
+def load_workload(path):
+    z = np.load(path, allow_pickle=False)
+    subs = []
+    for i in range(int(z["nsub"][0])):
+        subs.append({k: z["s%d_%s" % (i, k)] for k in
+                     ("indptr", "indices", "data", "kind", "gid", "pweight", "rhs")})
+    ents = []
+    for e in range(int(z["nent"][0])):
+        ents.append({"kind": int(z["e%d_kind" % e][0]), "gids": z["e%d_gids" % e],
+                     "con": z["e%d_con" % e]})
+    return {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents}

@@ -24,7 +24,11 @@ VB_SCALING_DELUXE, VB_SCALING_COUNTING = 0, 1
 class vb_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("scaling", C.c_int), ("tol", C.c_double),
                 ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
-                ("stream", C.c_void_p)]
+                ("stream", C.c_void_p), ("profile", C.c_int)]
+
+
+class vb_kernel_stat(C.Structure):
+    _fields_ = [("launches", C.c_int), ("total_ms", C.c_double), ("work", C.c_double)]
 
 
 class vb_subdomain(C.Structure):
@@ -76,6 +80,7 @@ def load():
         "vb_get_local_solution": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_double)]),
         "vb_recover_all": (C.c_int, [P, P, P]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
+        "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -88,7 +93,7 @@ def load():
 def exported_symbols():
     return ["vb_create", "vb_destroy", "vb_last_error", "vb_assemble", "vb_setup",
             "vb_interface_size", "vb_rhs", "vb_schur_apply", "vb_apply", "vb_pcg_solve",
-            "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl"]
+            "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl", "vb_kernel_stats"]
 
 
 class VBError(RuntimeError):
@@ -118,9 +123,9 @@ def _check(ctx, rc):
 
 # ------------------------------------------------------------- C-ABI names
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
-              svd_tol=1e-10, panel=0, stream=None):
+              svd_tol=1e-10, panel=0, stream=None, profile=0):
     lib = load()
-    opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream)
+    opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -203,3 +208,9 @@ def vb_batched_ldl(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
     rc = load().vb_batched_ldl(ctx, len(n), _ptr(ptrs), _ptr(n), _ptr(ld), _ptr(e), _ptr(p),
                                _ptr(info), int(max_n), int(max_e))
     _check(ctx, rc)
+
+
+def vb_kernel_stats(ctx, which, reset=False):
+    st = vb_kernel_stat()
+    _check(ctx, load().vb_kernel_stats(ctx, int(which), int(bool(reset)), C.byref(st)))
+    return {"launches": st.launches, "total_ms": st.total_ms, "work": st.work}

@@ -13,6 +13,8 @@
 //   panel : L_ij = A_ij inv(L_jj)^T D_j for every row block below;
 //   update: A_ik -= L_ij D_j L_kj^T on the lower triangle of the trailing
 //           matrix, 64x64 tiles on the 16x16x4 matrix cores.
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -240,9 +242,20 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const GemmJob<T> *jobs) {
 // ---------------------------------------------------------------- launchers
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
-                       hipStream_t s) {
+                       hipStream_t s, KTimer *timer, const std::vector<int> *hn,
+                       const std::vector<int> *he) {
   if (batch == 0 || max_e == 0) return hipSuccess;
   for (int j0 = 0; j0 < max_e; j0 += nb) {
+    // algorithmic flops of this trailing update: b * m (m + 1) per matrix
+    // (symmetric rank-b update of the m x m lower triangle)
+    double flops = 0.0;
+    if (timer && hn && he)
+      for (size_t q = 0; q < hn->size(); ++q) {
+        if (j0 >= (*he)[q]) continue;
+        const double b = std::min(nb, (*he)[q] - j0);
+        const double m = (*hn)[q] - j0 - b;
+        if (m > 0) flops += b * m * (m + 1.0);
+      }
     const int rows = max_n - j0;  // upper bound on rows below the panel start
     const int rt = (rows + TILE - 1) / TILE;
     const int nt = rt * (rt + 1) / 2;
@@ -251,7 +264,9 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
       hipLaunchKernelGGL((k_ldl_diag<T, 64>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
       if (rt > 0) {
         hipLaunchKernelGGL((k_ldl_panel<T, 64>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
+        if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
         hipLaunchKernelGGL((k_ldl_update<T, 64>), dim3(nt, batch), dim3(256), 0, s, d_jobs, j0);
+        if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
       }
     } else {
       hipLaunchKernelGGL((k_ldl_diag<T, 32>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
@@ -275,8 +290,10 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
   return hipGetLastError();
 }
 
-template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t);
-template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t);
+template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t,
+                                        KTimer *, const std::vector<int> *, const std::vector<int> *);
+template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t,
+                                       KTimer *, const std::vector<int> *, const std::vector<int> *);
 template hipError_t gemm_nt_batched<double>(const GemmJob<double> *, int, int, int, hipStream_t);
 template hipError_t gemm_nt_batched<float>(const GemmJob<float> *, int, int, int, hipStream_t);
 

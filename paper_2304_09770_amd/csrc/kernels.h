@@ -2,14 +2,57 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <vector>
 #include "common.h"
 
 namespace vb {
 
+// Device timing of individual kernel launches with HIP events on the
+// launching stream; `work` is the algorithmic flops or bytes of the launch.
+struct KTimer {
+  std::vector<hipEvent_t> ev;
+  std::vector<double> work;
+  int used = 0;
+  hipError_t begin(hipStream_t s, double w) {
+    if ((int)ev.size() < 2 * (used + 1)) {
+      for (int i = 0; i < 2; ++i) {
+        hipEvent_t e;
+        hipError_t r = hipEventCreate(&e);
+        if (r != hipSuccess) return r;
+        ev.push_back(e);
+      }
+    }
+    if ((int)work.size() <= used) work.push_back(0.0);
+    work[used] = w;
+    return hipEventRecord(ev[2 * used], s);
+  }
+  hipError_t end(hipStream_t s) { return hipEventRecord(ev[2 * used++ + 1], s); }
+  hipError_t collect(int *n, double *ms, double *w) {
+    *n = used;
+    *ms = 0.0;
+    *w = 0.0;
+    for (int i = 0; i < used; ++i) {
+      float t = 0.f;
+      hipError_t r = hipEventElapsedTime(&t, ev[2 * i], ev[2 * i + 1]);
+      if (r != hipSuccess) return r;
+      *ms += t;
+      *w += work[i];
+    }
+    return hipSuccess;
+  }
+  void reset() { used = 0; }
+  void destroy() {
+    for (auto e : ev) (void)hipEventDestroy(e);
+    ev.clear();
+    used = 0;
+  }
+};
+
 // ---------------------------------------------------------------- dense
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
-                       hipStream_t s);
+                       hipStream_t s, KTimer *timer = nullptr,
+                       const std::vector<int> *hn = nullptr, const std::vector<int> *he = nullptr);
 template <typename T>
 hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int max_n,
                            hipStream_t s);
@@ -101,7 +144,7 @@ hipError_t gather_blocks(const GatherJob *d_jobs, int batch, int max_m, int max_
 hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, const int64_t *yoff,
                        int nsub, int max_e, hipStream_t s);
 hipError_t recover_backsolve(const SubDev *d_subs, const double *invL, const int64_t *invoff,
-                             double *y, const int64_t *yoff, int nsub, int j0, int nb,
+                             double *y, double *z, const int64_t *yoff, int nsub, int i0, int nb,
                              hipStream_t s);
 
 }  // namespace vb

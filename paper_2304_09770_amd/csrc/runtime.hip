@@ -80,8 +80,11 @@ struct vb_ctx {
   hipStream_t stream = nullptr;
   std::string err;
   int state = 0;  // 0 created, 1 assembled, 2 set up
-  std::vector<void *> allocs;
-  std::vector<void *> setup_allocs;
+  std::vector<void *> allocs;        // assemble scope (until destroy)
+  std::vector<void *> setup_allocs;  // setup scratch (freed when setup ends)
+  std::vector<void *> setup_keep;    // setup results (freed by the next setup)
+  int cur_scope = 0;                 // 0: allocs, 2: setup_keep
+  KTimer t_ldl, t_gemv;              // per-launch device timing of the dominant kernels
 
   int64_t nG = 0;
   int nS = 0;
@@ -120,8 +123,9 @@ struct vb_ctx {
   int64_t *p0_src = nullptr, *p0_dst = nullptr;
   int max_gt_m = 0, max_gt_n = 0, max_ndl = 0, max_npi = 0, max_nt = 0;
   int64_t n_yloc = 0, n_gD = 0, n_tv = 0;
+  double schur_bytes = 0.0;  // algorithmic bytes of one S~ GEMV launch
   // recovery
-  double *yrec = nullptr, *rec_out = nullptr;
+  double *yrec = nullptr, *zrec = nullptr, *rec_out = nullptr;
   int64_t *d_yoff = nullptr, *d_invoff = nullptr;
   RecJob *j_rec = nullptr;
   std::vector<int64_t> rec_off;
@@ -140,7 +144,8 @@ struct vb_ctx {
     *p = nullptr;
     if (count == 0) count = 1;
     hipError_t e = hipMalloc((void **)p, count * sizeof(T));
-    if (e == hipSuccess) (setup_scope ? setup_allocs : allocs).push_back(*p);
+    if (e == hipSuccess)
+      (setup_scope ? setup_allocs : (cur_scope == 2 ? setup_keep : allocs)).push_back(*p);
     return e;
   }
   template <class T>
@@ -173,6 +178,7 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
   d.svd_tol = 1e-10;
   d.panel = NB;
   d.stream = nullptr;
+  d.profile = 0;
   if (opt) {
     d = *opt;
     if (d.tol <= 0) d.tol = 1e-8;
@@ -207,6 +213,9 @@ void vb_destroy(vb_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
   free_list(ctx->setup_allocs);
+  free_list(ctx->setup_keep);
+  ctx->t_ldl.destroy();
+  ctx->t_gemv.destroy();
   free_list(ctx->allocs);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
@@ -411,7 +420,13 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<double>> &jobs, int max_n, in
   if (jobs.empty()) return VB_OK;
   LdlJob<double> *dj = nullptr;
   CHK(ctx->upload(&dj, jobs, true));
-  CHK(ldl_batched<double>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream));
+  std::vector<int> hn(jobs.size()), he(jobs.size());
+  for (size_t b = 0; b < jobs.size(); ++b) {
+    hn[b] = jobs[b].n;
+    he[b] = jobs[b].e;
+  }
+  CHK(ldl_batched<double>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
+                          ctx->opt.profile ? &ctx->t_ldl : nullptr, &hn, &he));
   return VB_OK;
 }
 
@@ -459,9 +474,31 @@ static int check_info(vb_ctx *ctx, int count, int code, const char *what) {
   return VB_OK;
 }
 
+static int setup_impl(vb_ctx *ctx);
+
 int vb_setup(vb_ctx *ctx) {
   if (!ctx) return VB_ERR_ARG;
-  if (ctx->state != 1) return ctx->fail(VB_ERR_STATE, "vb_setup: call vb_assemble first (once)");
+  if (ctx->state < 1) return ctx->fail(VB_ERR_STATE, "vb_setup: call vb_assemble first");
+  if (ctx->state == 2) {  // a new setup replaces the previous one
+    CHK(hipStreamSynchronize(ctx->stream));
+    free_list(ctx->setup_keep);
+    for (auto &H : ctx->ents) {
+      H.D.clear();
+      H.d_dual_gids = nullptr;
+    }
+    ctx->state = 1;
+  }
+  ctx->n_restrict = ctx->n_ext = 0;
+  ctx->max_rm = ctx->max_ext_m = ctx->max_gt_m = ctx->max_gt_n = 0;
+  ctx->max_ndl = ctx->max_npi = ctx->max_nt = 0;
+  ctx->cur_scope = 2;
+  int rc = setup_impl(ctx);
+  ctx->cur_scope = 0;
+  free_list(ctx->setup_allocs);
+  return rc;
+}
+
+static int setup_impl(vb_ctx *ctx) {
   hipStream_t st = ctx->stream;
   const int nS = ctx->nS;
   const int64_t nG = ctx->nG;
@@ -853,6 +890,9 @@ int vb_setup(vb_ctx *ctx) {
       yoff += S.ng + 1;
     }
     ctx->n_yloc = yoff;
+    ctx->schur_bytes = 0.0;
+    for (auto &S : ctx->subs)  // the bordered matrix once + x gather + y write
+      ctx->schur_bytes += 8.0 * ((double)(S.ng + 1) * (S.ng + 1) + 2.0 * (S.ng + 1));
     CHK(ctx->dalloc(&ctx->yloc, yoff));
     for (int s = 0; s < nS; ++s) js[s].y = ctx->yloc + ctx->subs[s].y_off;
     std::vector<int64_t> ptr(nTot + 1, 0), idx;
@@ -961,6 +1001,7 @@ int vb_setup(vb_ctx *ctx) {
     }
     otot = ctx->rec_off[nS];
     CHK(ctx->dalloc(&ctx->yrec, tot));
+    CHK(ctx->dalloc(&ctx->zrec, tot));
     CHK(ctx->dalloc(&ctx->rec_out, otot));
     CHK(ctx->upload(&ctx->d_yoff, yoff));
     CHK(ctx->upload(&ctx->d_invoff, invoff));
@@ -968,7 +1009,7 @@ int vb_setup(vb_ctx *ctx) {
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       rj[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
-               ctx->yrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
+               ctx->zrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
     }
     CHK(ctx->upload(&ctx->j_rec, rj));
   }
@@ -977,8 +1018,8 @@ int vb_setup(vb_ctx *ctx) {
   float ms = 0.f;
   CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->setup_ms = ms;
-  // release setup-only workspace (Neumann/deluxe augmented matrices, job arrays)
-  free_list(ctx->setup_allocs);
+  // setup-only workspace (Neumann/deluxe augmented matrices, job arrays) is
+  // released by the caller of setup_impl
   for (auto &H : ctx->ents) {
     H.Daug = nullptr;
     H.Sbar.clear();
@@ -994,7 +1035,10 @@ int vb_setup(vb_ctx *ctx) {
 
 // ------------------------------------------------------------------ operators
 static int apply_S_internal(vb_ctx *ctx) {  // q <- S~ p
+  KTimer *t = ctx->opt.profile ? &ctx->t_gemv : nullptr;
+  if (t) CHK(t->begin(ctx->stream, ctx->schur_bytes));
   CHK(gemv_t(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m, ctx->stream));
+  if (t) CHK(t->end(ctx->stream));
   CHK(owner_sum((int)(ctx->nG + ctx->nS), ctx->own_ptr, ctx->own_idx, ctx->yloc, nullptr, nullptr,
                 ctx->q, ctx->stream));
   return VB_OK;
@@ -1184,8 +1228,8 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
   CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, ctx->nS, ctx->max_e, st));
   const int nb = ctx->opt.panel;  // the panel width the factorisation used
   for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
-    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->d_yoff, ctx->nS,
-                          j0, nb, st));
+    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->zrec,
+                          ctx->d_yoff, ctx->nS, j0, nb, st));
   CHK(recover_out(ctx->j_rec, ctx->nS, x_dev, ctx->nG, st));
   if (out_dev)
     CHK(hipMemcpyAsync(out_dev, ctx->rec_out, ctx->rec_off[ctx->nS] * sizeof(double),
@@ -1235,6 +1279,25 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
   (void)hipFree(dj);
   (void)hipFree(scratch);
   if (err != hipSuccess) return ctx->fail(VB_ERR_DEVICE, std::string("vb_batched_ldl: ") + hipGetErrorString(err));
+  return VB_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out) {
+  if (!ctx || !out || which < 0 || which > 1) return VB_ERR_ARG;
+  KTimer &t = which == 0 ? ctx->t_ldl : ctx->t_gemv;
+  CHK(hipStreamSynchronize(ctx->stream));
+  double ms = 0.0, work = 0.0;
+  int n = 0;
+  hipError_t e = t.collect(&n, &ms, &work);
+  if (e != hipSuccess) return ctx->fail(VB_ERR_DEVICE, "vb_kernel_stats: event query failed");
+  out->launches = n;
+  out->total_ms = ms;
+  out->work = work;
+  if (reset) t.reset();
   return VB_OK;
 }
 

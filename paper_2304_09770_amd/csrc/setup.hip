@@ -434,40 +434,52 @@ hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, co
   return hipGetLastError();
 }
 
-// Block back substitution L_II^T z = y, block j (columns [j0, j0+b)):
-// z_j = inv(L_jj)^T (y_j - sum_{r >= j0+b} L[r, j-block]^T z_r).
-__global__ void k_recover_back(const SubDev *subs, const double *invL, const int64_t *invoff,
-                               double *y, const int64_t *yoff, int j0, int nb) {
-  const SubDev S = subs[blockIdx.x];
-  if (j0 >= S.e) return;
-  const int b = min(nb, S.e - j0);
-  double *z = y + yoff[blockIdx.x];
-  __shared__ double t[64];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int c = w; c < b; c += blockDim.x >> 6) {
-    const double *col = S.W + (int64_t)(j0 + c) * S.ld;
-    double s = 0.0;
-    for (int r = j0 + b + l; r < S.e; r += 64) s += col[r] * z[r];
-    s = warp_sum(s);
-    if (l == 0) t[c] = z[j0 + c] - s;
-  }
+// Right-looking block back substitution for L_II^T z = y, step for the block
+// i = [i0, i0+b): z_i = inv(L_ii)^T y_i (every workgroup recomputes it from
+// the cached inverse; workgroup 0 stores it), then y_k -= L[i-block, k]^T z_i
+// for all columns k < i0, one wave per column (the block rows are contiguous
+// in the column-major factor).
+__global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const double *invL,
+                                                      const int64_t *invoff, double *y,
+                                                      double *z, const int64_t *yoff, int i0,
+                                                      int nb) {
+  const SubDev S = subs[blockIdx.y];
+  if (i0 >= S.e) return;
+  const int b = min(nb, S.e - i0);
+  double *ys = y + yoff[blockIdx.y];
+  double *zs = z + yoff[blockIdx.y];
+  __shared__ double yi[64], zi[64];
+  const double *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
+  if (threadIdx.x < b) yi[threadIdx.x] = ys[i0 + threadIdx.x];
   __syncthreads();
-  const double *inv = invL + invoff[blockIdx.x] + (int64_t)(j0 / nb) * nb * nb;
   if (threadIdx.x < b) {
     const int c = threadIdx.x;
-    // (inv^T t)_c = sum_r inv[r][c] t[r], inv lower triangular -> r >= c
-    double s = 0.0;
-    for (int r = c; r < b; ++r) s += inv[r + c * nb] * t[r];
-    z[j0 + c] = s;
+    double s = 0.0;  // (inv^T y)_c = sum_{r >= c} inv[r][c] y_r
+    for (int r = c; r < b; ++r) s += inv[r + c * nb] * yi[r];
+    zi[c] = s;
+    if (blockIdx.x == 0) zs[i0 + c] = s;
+  }
+  __syncthreads();
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const double zl = (l < b) ? zi[l] : 0.0;
+  const int k0 = blockIdx.x * 64;
+  for (int kk = w; kk < 64; kk += 4) {
+    const int k = k0 + kk;
+    if (k >= i0) break;
+    const double *col = S.W + (int64_t)k * S.ld + i0;
+    double s = (l < b) ? col[l] * zl : 0.0;
+    s = warp_sum(s);
+    if (l == 0) ys[k] -= s;
   }
 }
 
 hipError_t recover_backsolve(const SubDev *d_subs, const double *invL, const int64_t *invoff,
-                             double *y, const int64_t *yoff, int nsub, int j0, int nb,
-                             hipStream_t s) {
+                             double *y, double *z, const int64_t *yoff, int nsub, int i0,
+                             int nb, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  hipLaunchKernelGGL(k_recover_back, dim3(nsub), dim3(256), 0, s, d_subs, invL, invoff, y, yoff, j0,
-                     nb);
+  const int gx = i0 > 0 ? (i0 + 63) / 64 : 1;
+  hipLaunchKernelGGL(k_recover_step, dim3(gx, nsub), dim3(256), 0, s, d_subs, invL, invoff, y, z,
+                     yoff, i0, nb);
   return hipGetLastError();
 }
 
