@@ -67,6 +67,8 @@ def main():
     ap.add_argument("--cache", default=None, help="workload .npz (generated if missing)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1)
+    ap.add_argument("--prepare-only", action="store_true",
+                    help="generate and store the workload (--cache) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
@@ -83,6 +85,8 @@ def main():
         log("generated workload %s (%.1f s)" % (args.config, time.perf_counter() - t))
         if args.cache:
             save_workload(args.cache, wl)
+    if args.prepare_only:
+        return
     nsub = len(wl["subs"])
     # ---- CPU baseline (oracle, bounded sample)
     cpu = None
