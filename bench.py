@@ -154,7 +154,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.config + ": " + WORKLOADS[args.config], "precision": "fp64",
                    "subdomains": nsub, "interface_unknowns": n},
-        "roofline": {"bound": "mfma", "kernel": "k_ldl_update (dense LDL^T trailing update)",
+        "roofline": {"bound": "mfma", "kernel": "k_ldl_update_wide (rank-256 trailing update of the dense LDL^T)",
                      "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
                      "traffic": None, "launches": ldl["launches"],

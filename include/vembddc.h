@@ -162,8 +162,9 @@ int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_h
 int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
 
 /* Statistics of the kernels timed with vb_options.profile: which = 0 the
- * trailing update of the dense LDL^T (the setup's dominant kernel, work in
- * flops: b*m*(m+1) per matrix and panel of width b with m trailing rows),
+ * super-panel trailing update of the dense LDL^T (the setup's dominant
+ * kernel, work in flops: K*m*(m+1) per matrix and super-panel of K columns
+ * with m trailing rows),
  * which = 1 the bordered local Schur GEMV of S_hat p (the iteration's
  * dominant kernel, work in bytes read/written).  reset != 0 clears them. */
 int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out);

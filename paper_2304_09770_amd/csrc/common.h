@@ -28,6 +28,14 @@ template <> struct Mfma<float> {
   static __device__ __forceinline__ int row(int g, int r) { return 4 * g + r; }
 };
 
+// Pointers read from job descriptors are generic; loads through them become
+// flat loads, which also count on lgkmcnt and so serialise with LDS reads.
+// Device memory is the global address space: say so.
+template <typename T>
+__device__ __forceinline__ const __attribute__((address_space(1))) T *gptr(const T *p) {
+  return (const __attribute__((address_space(1))) T *)p;
+}
+
 // Dense partial LDL^T job: column-major A (n x n, leading dimension ld),
 // eliminate columns [0, e), pivot sign +1 for columns < p, -1 otherwise.
 template <typename T> struct LdlJob {

@@ -125,24 +125,24 @@ __global__ __launch_bounds__(256) void k_ldl_panel(const LdlJob<T> *jobs, int j0
   }
 }
 
-// A_ik -= L_ij D_j L_kj^T on lower-triangle 64x64 tiles of the trailing matrix.
+// A_ik -= L_ij D_j L_kj^T on 64x64 tiles of the trailing matrix, restricted
+// to columns < col_end (the rest of the current super-panel): tile (ti, tk)
+// with ti >= tk from a rectangular grid of nt x ntk tiles.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j0) {
+__global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j0, int col_end,
+                                                    int ntk_max) {
   typedef Mfma<T> M;
   const LdlJob<T> J = jobs[blockIdx.y];
   if (j0 >= J.e) return;
   const int b = min(NB, J.e - j0);
   const int m0 = j0 + b;
+  const int ce = min(col_end, J.e);
+  if (m0 >= J.n || m0 >= ce) return;
   const int nt = (J.n - m0 + TILE - 1) / TILE;
-  const int t = blockIdx.x;
-  if (m0 >= J.n) return;
-  // tile index -> (ti, tk), ti >= tk
-  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  while (ti * (ti + 1) / 2 > t) --ti;
-  const int tk = t - ti * (ti + 1) / 2;
-  if (ti >= nt) return;
+  const int ti = blockIdx.x / ntk_max, tk = blockIdx.x % ntk_max;
+  if (ti >= nt || tk > ti) return;
   const int i0 = m0 + ti * TILE, k0 = m0 + tk * TILE;
+  if (k0 >= ce) return;
   constexpr int KC = 32;
   __shared__ T Pi[KC][TILE];
   __shared__ T Pk[KC][TILE];
@@ -153,18 +153,27 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
   for (int a = 0; a < 2; ++a)
     for (int c = 0; c < 2; ++c) acc[a][c] = M::zero();
   const int lr = l & 15, lk = l >> 4;
+  const int r = tid & (TILE - 1), c4 = tid >> 6;  // staging: row r, columns c4 + 4q
+  const int ri = min(i0 + r, J.n - 1), rk = min(k0 + r, J.n - 1);
+  const bool oki = (i0 + r < J.n), okk = (k0 + r < ce);
   for (int cc = 0; cc < NB; cc += KC) {
+    T vi[KC / 4], vk[KC / 4];
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+      const int c = cc + c4 + 4 * q;
+      const int cl = j0 + min(c, b - 1);
+      const auto col = gptr(J.A + (int64_t)cl * J.ld);
+      const T a0 = col[ri], a1 = col[rk];
+      const bool okc = c < b;
+      const T d = (j0 + c < J.p) ? T(1) : T(-1);
+      vi[q] = (okc && oki) ? a0 : T(0);
+      vk[q] = (okc && okk) ? a1 * d : T(0);
+    }
     __syncthreads();
-    for (int idx = tid; idx < TILE * KC; idx += blockDim.x) {
-      int r = idx % TILE, c = idx / TILE;
-      T vi = 0, vk = 0;
-      if (cc + c < b) {
-        const T *col = J.A + (int64_t)(j0 + cc + c) * J.ld;
-        if (i0 + r < J.n) vi = col[i0 + r];
-        if (k0 + r < J.n) vk = col[k0 + r] * ((j0 + cc + c < J.p) ? T(1) : T(-1));
-      }
-      Pi[c][r] = vi;
-      Pk[c][r] = vk;
+#pragma unroll
+    for (int q = 0; q < KC / 4; ++q) {
+      Pi[c4 + 4 * q][r] = vi[q];
+      Pk[c4 + 4 * q][r] = vk[q];
     }
     __syncthreads();
     for (int c0 = 0; c0 < KC; c0 += 4) {
@@ -183,6 +192,101 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
       if (row >= J.n) continue;
       for (int q = 0; q < 4; ++q) {
         const int col = k0 + 32 * wk + 16 * bk + M::row(lk, q);
+        if (col < ce) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
+      }
+    }
+}
+
+// Rank-(super-panel) trailing update A_ik -= sum_{c in [kb, ke)} L_ic d_c L_kc
+// on the lower triangle beyond the super-panel, 128x128 tiles (each wave a
+// 64x64 block of 4x4 matrix-core tiles).  The panel columns are staged
+// through LDS in chunks of KW; the next chunk is loaded into registers
+// (branch-free, clamped addresses) while the current one is multiplied.
+constexpr int WT = 128;
+constexpr int KW = 16;
+template <typename T>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide(const LdlJob<T> *jobs, int J0, int SB) {
+  typedef Mfma<T> M;
+  const LdlJob<T> J = jobs[blockIdx.y];
+  const int kb = J0, ke = min(J0 + SB, J.e);
+  if (kb >= ke) return;
+  const int m0 = ke;
+  if (m0 >= J.n) return;
+  const int nt = (J.n - m0 + WT - 1) / WT;
+  const int t = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tk = t - ti * (ti + 1) / 2;
+  if (ti >= nt) return;
+  const int i0 = m0 + ti * WT, k0 = m0 + tk * WT;
+  extern __shared__ unsigned char smem_raw[];
+  T *Pi = reinterpret_cast<T *>(smem_raw);
+  T *Pk = Pi + KW * WT;
+  const int tid = threadIdx.x;
+  const int w = tid >> 6, l = tid & 63;
+  const int wi = w >> 1, wk = w & 1;
+  const int lr = l & 15, lk = l >> 4;
+  // staging map: row r (128), columns c = c0 + 2q (q < KW/2)
+  const int r = tid & (WT - 1), c0 = tid >> 7;
+  const int ri = min(i0 + r, J.n - 1), rk = min(k0 + r, J.n - 1);
+  const bool oki = (i0 + r < J.n), okk = (k0 + r < J.n);
+  constexpr int NQ = KW / 2;
+  T bi_[NQ], bk_[NQ];
+  // raw loads only: the masks and pivot signs are applied when the values are
+  // stored to LDS, after the current chunk's products, so every load of a
+  // chunk stays in flight while the matrix cores work
+  auto load = [&](int cc) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int cl = min(cc + c0 + 2 * q, ke - 1);
+      const auto col = gptr(J.A + (int64_t)cl * J.ld);
+      bi_[q] = col[ri];
+      bk_[q] = col[rk];
+    }
+  };
+  typename M::acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = M::zero();
+  load(kb);
+  for (int cc = kb; cc < ke; cc += KW) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = cc + c0 + 2 * q;
+      const bool okc = c < ke;
+      const T d = (c < J.p) ? T(1) : T(-1);
+      Pi[(c0 + 2 * q) * WT + r] = (okc && oki) ? bi_[q] : T(0);
+      Pk[(c0 + 2 * q) * WT + r] = (okc && okk) ? bk_[q] * d : T(0);
+    }
+    __syncthreads();
+    if (cc + KW < ke) load(cc + KW);
+#pragma unroll 2
+    for (int s0 = 0; s0 < KW; s0 += 4) {
+      T av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = Pk[(s0 + lk) * WT + 64 * wk + 16 * q + lr];
+        bv[q] = Pi[(s0 + lk) * WT + 64 * wi + 16 * q + lr];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bk = 0; bk < 4; ++bk) acc[bi][bk] = M::mma(av[bk], bv[bi], acc[bi][bk]);
+    }
+  }
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < 4; ++bk) {
+      const int row = i0 + 64 * wi + 16 * bi + lr;
+      if (row >= J.n) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = k0 + 64 * wk + 16 * bk + M::row(lk, q);
         if (col < J.n) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
       }
     }
@@ -240,40 +344,67 @@ __global__ __launch_bounds__(256) void k_gemm_nt(const GemmJob<T> *jobs) {
 }
 
 // ---------------------------------------------------------------- launchers
+template <typename T, int NB>
+static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, int j0, int col_end,
+                                 hipStream_t s) {
+  const int rows = max_n - j0;
+  const int pt = (rows + PROWS - 1) / PROWS;
+  const int rt = (rows + TILE - 1) / TILE;
+  const int ntk = (col_end - j0 + TILE - 1) / TILE;
+  hipLaunchKernelGGL((k_ldl_diag<T, NB>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
+  if (rows > 0) {
+    hipLaunchKernelGGL((k_ldl_panel<T, NB>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
+    if (ntk > 0)
+      hipLaunchKernelGGL((k_ldl_update<T, NB>), dim3(rt * ntk, batch), dim3(256), 0, s, d_jobs,
+                         j0, col_end, ntk);
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer, const std::vector<int> *hn,
                        const std::vector<int> *he) {
   if (batch == 0 || max_e == 0) return hipSuccess;
-  for (int j0 = 0; j0 < max_e; j0 += nb) {
-    // algorithmic flops of this trailing update: b * m (m + 1) per matrix
-    // (symmetric rank-b update of the m x m lower triangle)
+  static bool attr = false;
+  const size_t lds = 2 * (size_t)KW * WT * sizeof(T);
+  if (!attr) {
+    hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide<double>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void *)k_ldl_update_wide<float>,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r != hipSuccess) return r;
+    attr = true;
+  }
+  const int SB = 4 * nb;  // super-panel width
+  for (int J0 = 0; J0 < max_e; J0 += SB) {
+    const int jend = std::min(J0 + SB, max_e);
+    for (int j0 = J0; j0 < jend; j0 += nb) {
+      hipError_t r = (nb == 64) ? ldl_panel_step<T, 64>(d_jobs, batch, max_n, j0, J0 + SB, s)
+                                : ldl_panel_step<T, 32>(d_jobs, batch, max_n, j0, J0 + SB, s);
+      if (r != hipSuccess) return r;
+    }
+    // algorithmic flops of the wide update: K * m * (m + 1) per matrix
+    // (symmetric rank-K update of the m x m lower triangle)
     double flops = 0.0;
     if (timer && hn && he)
       for (size_t q = 0; q < hn->size(); ++q) {
-        if (j0 >= (*he)[q]) continue;
-        const double b = std::min(nb, (*he)[q] - j0);
-        const double m = (*hn)[q] - j0 - b;
-        if (m > 0) flops += b * m * (m + 1.0);
+        if (J0 >= (*he)[q]) continue;
+        const double K = std::min(J0 + SB, (*he)[q]) - J0;
+        const double m = (*hn)[q] - std::min(J0 + SB, (*he)[q]);
+        if (m > 0) flops += K * m * (m + 1.0);
       }
-    const int rows = max_n - j0;  // upper bound on rows below the panel start
-    const int rt = (rows + TILE - 1) / TILE;
-    const int nt = rt * (rt + 1) / 2;
-    const int pt = (rows + PROWS - 1) / PROWS;
-    if (nb == 64) {
-      hipLaunchKernelGGL((k_ldl_diag<T, 64>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
-      if (rt > 0) {
-        hipLaunchKernelGGL((k_ldl_panel<T, 64>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
-        if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
-        hipLaunchKernelGGL((k_ldl_update<T, 64>), dim3(nt, batch), dim3(256), 0, s, d_jobs, j0);
-        if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
-      }
-    } else {
-      hipLaunchKernelGGL((k_ldl_diag<T, 32>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
-      if (rt > 0) {
-        hipLaunchKernelGGL((k_ldl_panel<T, 32>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
-        hipLaunchKernelGGL((k_ldl_update<T, 32>), dim3(nt, batch), dim3(256), 0, s, d_jobs, j0);
-      }
+    // a job whose elimination ends inside this super-panel has n - e_job
+    // trailing rows: size the grid by the upper bound max_n - J0
+    const int rows = max_n - J0;
+    if (rows > 0) {
+      const int wt = (rows + WT - 1) / WT;
+      const int ntiles = wt * (wt + 1) / 2;
+      if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
+      hipLaunchKernelGGL((k_ldl_update_wide<T>), dim3(ntiles, batch), dim3(256), lds, s, d_jobs,
+                         J0, SB);
+      if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
     }
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
   for (int jj = w; jj < CPB; jj += 4) {
     const int j = j0 + jj;
     if (j >= J.n) break;
-    const double *col = J.A + (int64_t)j * J.lda;
+    const auto col = gptr(J.A + (int64_t)j * J.lda);
     double s0 = 0.0, s1 = 0.0;
     int i = l;
     for (; i + 64 < J.m; i += 128) {
@@ -49,7 +49,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= J.m) return;
   double s = J.base ? J.base[i] : 0.0;
-  const double *a = J.A + i;
+  const auto a = gptr(J.A + i);
   for (int j = 0; j < J.n; ++j) s += a[(int64_t)j * J.lda] * xs[j];
   J.y[i] = s;
 }
@@ -138,7 +138,7 @@ __global__ void k_extend(const ExtJob *jobs, const ExtPart *parts, const double 
     const ExtPart P = parts[J.part0 + q];
     const double *wq = w + P.woff;
     if (P.D) {
-      const double *a = P.D + m;
+      const auto a = gptr(P.D + m);
       for (int l = 0; l < J.m; ++l) s += a[(int64_t)l * P.ld] * wq[l];
     } else {
       s += wq[m] * P.scale;

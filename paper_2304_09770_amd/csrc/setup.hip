@@ -466,7 +466,7 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
   for (int kk = w; kk < 64; kk += 4) {
     const int k = k0 + kk;
     if (k >= i0) break;
-    const double *col = S.W + (int64_t)k * S.ld + i0;
+    const auto col = gptr(S.W + (int64_t)k * S.ld + i0);
     double s = (l < b) ? col[l] * zl : 0.0;
     s = warp_sum(s);
     if (l == 0) ys[k] -= s;
