@@ -58,7 +58,10 @@ enum { VB_KIND_INTERIOR = 0, VB_KIND_INTERFACE = 1, VB_KIND_PRESSURE = 2 };
 enum { VB_ENT_VERTEX = 0, VB_ENT_EDGE = 1, VB_ENT_FACE = 2 };
 
 typedef struct vb_options {
-  int precision;     /* VB_PREC_FP64 or VB_PREC_MIXED */
+  int precision;     /* VB_PREC_FP64, or VB_PREC_MIXED: local factors and Schur
+                        operators stored in FP32 (FP64 accumulation), FP64
+                        residuals of the local systems drive an iterative
+                        refinement of the whole saddle system (see vb_pcg_solve) */
   int scaling;       /* VB_SCALING_DELUXE (Sec. 6) or VB_SCALING_COUNTING (eq. pseudoinv) */
   double tol;        /* PCG relative residual ||g - S x|| <= tol ||g|| (default 1e-8) */
   int maxit;         /* PCG iteration cap (default 1000) */
@@ -113,6 +116,7 @@ typedef struct vb_solve_info {
   int n_coarse;              /* primal coarse dimension (+ one p0 per subdomain) */
   double setup_ms, solve_ms; /* device times of the last vb_setup / vb_pcg_solve */
   int status;                /* VB_OK or VB_ERR_* */
+  int refinement_steps;      /* VB_PREC_MIXED: outer refinement steps taken (0 for FP64) */
 } vb_solve_info;
 
 typedef struct vb_ctx vb_ctx;
@@ -148,7 +152,17 @@ int vb_schur_apply(vb_ctx *ctx, const double *x_dev, double *y_dev);
 int vb_apply(vb_ctx *ctx, const double *r_dev, double *z_dev);
 
 /* PCG on S_hat u = g_hat from x0 = x_dev (Sec. 7); x_dev receives the
- * solution (also on VB_ERR_NOT_CONVERGED).  info may be NULL. */
+ * solution (also on VB_ERR_NOT_CONVERGED).  info may be NULL.
+ * VB_PREC_MIXED: iterative refinement.  Each step forms the FP64 residual of
+ * every local system at the current (x, interior) iterate, condenses it with
+ * the FP32 factor (eq. globInt applied to the residual), solves the interface
+ * correction by PCG on the FP32 operators to a loose relative tolerance
+ * (max(1e-4, tol/2 relative to the current residual)), recovers the interior
+ * correction (eq. uipi) and updates.  It stops when the condensed FP64
+ * residual has dropped to tol times the first one; rel_residual and
+ * true_rel_residual both report that ratio, iterations the total inner PCG
+ * iterations, refinement_steps the outer steps, lambda_* the first inner
+ * solve.  The interior iterate is kept for vb_recover_all. */
 int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info);
 
 /* Interior recovery (eq. uipi) for subdomain `sub` from the interface
@@ -158,7 +172,9 @@ int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_h
 
 /* Interior recovery for every subdomain at once: out_dev (device, may be
  * NULL to only refresh the internal copy) receives the concatenation over
- * subdomains of their local DoF vectors, each in its own CSR DoF order. */
+ * subdomains of their local DoF vectors, each in its own CSR DoF order.
+ * VB_PREC_MIXED: the FP32-factor recovery is followed by FP64 refinement of
+ * the interior equations with the interface data fixed at x_dev. */
 int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
 
 /* Statistics of the kernels timed with vb_options.profile: which = 0 the

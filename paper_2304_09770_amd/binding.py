@@ -47,7 +47,7 @@ class vb_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("rel_residual", C.c_double),
                 ("true_rel_residual", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("n_coarse", C.c_int), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double), ("status", C.c_int)]
+                ("solve_ms", C.c_double), ("status", C.c_int), ("refinement_steps", C.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}

@@ -9,7 +9,7 @@ enum { SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_GG, SC_FLAG, SC_TMP, SC_CO
 constexpr int DOT_BLOCKS = 512;
 
 struct GemvJob {
-  const double *A;
+  const void *A;       // double, or float if a_f32 (FP32 storage, FP64 accumulation)
   int64_t lda;
   int m, n;            // A is m x n
   const double *x;     // gathered through xidx when given
@@ -18,6 +18,7 @@ struct GemvJob {
   double *y;
   double alpha;        // gemv_t: y = alpha A^T x (+ y if acc)
   int acc;
+  int a_f32;
 };
 
 struct ExtPart {
@@ -57,6 +58,7 @@ hipError_t update_xr(int64_t n, const double *sc, double *x, double *r, const do
                      const double *q, double *part, double *scw, hipStream_t s);
 hipError_t update_p(int64_t n, const double *sc, double *p, const double *z, hipStream_t s);
 hipError_t vsub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
+hipError_t axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
 hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,
                        hipStream_t s);
 

@@ -21,14 +21,24 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
   for (int jj = w; jj < CPB; jj += 4) {
     const int j = j0 + jj;
     if (j >= J.n) break;
-    const auto col = gptr(J.A + (int64_t)j * J.lda);
     double s0 = 0.0, s1 = 0.0;
-    int i = l;
-    for (; i + 64 < J.m; i += 128) {
-      s0 += col[i] * xs[i];
-      s1 += col[i + 64] * xs[i + 64];
+    if (J.a_f32) {
+      const auto col = gptr((const float *)J.A + (int64_t)j * J.lda);
+      int i = l;
+      for (; i + 64 < J.m; i += 128) {
+        s0 += (double)col[i] * xs[i];
+        s1 += (double)col[i + 64] * xs[i + 64];
+      }
+      if (i < J.m) s0 += (double)col[i] * xs[i];
+    } else {
+      const auto col = gptr((const double *)J.A + (int64_t)j * J.lda);
+      int i = l;
+      for (; i + 64 < J.m; i += 128) {
+        s0 += col[i] * xs[i];
+        s1 += col[i + 64] * xs[i + 64];
+      }
+      if (i < J.m) s0 += col[i] * xs[i];
     }
-    if (i < J.m) s0 += col[i] * xs[i];
     double s = warp_sum(s0 + s1);
     if (l == 0) {
       double v = J.alpha * s;
@@ -49,8 +59,13 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= J.m) return;
   double s = J.base ? J.base[i] : 0.0;
-  const auto a = gptr(J.A + i);
-  for (int j = 0; j < J.n; ++j) s += a[(int64_t)j * J.lda] * xs[j];
+  if (J.a_f32) {
+    const auto a = gptr((const float *)J.A + i);
+    for (int j = 0; j < J.n; ++j) s += (double)a[(int64_t)j * J.lda] * xs[j];
+  } else {
+    const auto a = gptr((const double *)J.A + i);
+    for (int j = 0; j < J.n; ++j) s += a[(int64_t)j * J.lda] * xs[j];
+  }
   J.y[i] = s;
 }
 
@@ -277,6 +292,21 @@ hipError_t vsub(int64_t n, const double *a, const double *b, double *y, hipStrea
   if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
   if (nblk < 1) nblk = 1;
   hipLaunchKernelGGL(k_sub, dim3(nblk), dim3(256), 0, s, n, a, b, y);
+  return hipGetLastError();
+}
+
+// y += a x (elementwise)
+__global__ void k_axpy(int64_t n, double a, const double *x, double *y) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += a * x[i];
+}
+
+hipError_t axpy(int64_t n, double a, const double *x, double *y, hipStream_t s) {
+  int nblk = (int)((n + 255) / 256);
+  if (nblk > DOT_BLOCKS) nblk = DOT_BLOCKS;
+  if (nblk < 1) nblk = 1;
+  hipLaunchKernelGGL(k_axpy, dim3(nblk), dim3(256), 0, s, n, a, x, y);
   return hipGetLastError();
 }
 

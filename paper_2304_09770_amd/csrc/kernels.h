@@ -60,7 +60,7 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 // ---------------------------------------------------------------- setup
 // Per-subdomain description shared by the setup and recovery kernels.
 struct SubDev {
-  double *W;        // dense local matrix, column-major, ld
+  void *W;          // dense local matrix (double or float), column-major, ld
   int64_t ld;
   int nv, nel, ng;  // interior velocity, element pressures, interface DoFs
   int N;            // nv + nel + ng + 1 (last row/col: right-hand side)
@@ -92,10 +92,11 @@ struct EntDev {
 };
 
 struct DiagJob {
-  double *A;
+  void *A;  // double, or float if f32
   int64_t ld;
   int r0, c0, cnt;
   double val;
+  int f32;
 };
 hipError_t set_diag(const DiagJob *d_jobs, int batch, int max_cnt, hipStream_t s);
 
@@ -110,16 +111,17 @@ struct CoarseSub {
 hipError_t coarse_assemble(const CoarseSub *d_cs, int nsub, double *K, int64_t ld, int nC,
                            const double *w, hipStream_t s);
 
-hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s);
-hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_ng, hipStream_t s);
-hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, hipStream_t s);
+// fp32: the dense local matrices W are float (mixed precision), else double
+hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, bool fp32, hipStream_t s);
+hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s);
+hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, bool fp32, hipStream_t s);
 hipError_t entity_qr(const EntDev *d_ents, int nent, int rmax, double tol, hipStream_t s);
-hipError_t symmetrize(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
-                      int max_n, hipStream_t s);
-hipError_t transpose_sq(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
-                        int max_n, hipStream_t s);
+hipError_t symmetrize(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                      int max_n, bool fp32, hipStream_t s);
+hipError_t transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                        int max_n, bool fp32, hipStream_t s);
 hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
-                        int max_ent, hipStream_t s);
+                        int max_ent, bool fp32, hipStream_t s);
 hipError_t transform_b0(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ent,
                         hipStream_t s);
 // global vector <-> transformed coordinates (dir = +1: x~ = T^T x, -1: x = T x~)
@@ -128,23 +130,43 @@ hipError_t transform_vec(const EntDev *d_ents, int nent, double *x, int dir, hip
 // gather / scatter of dense sub-blocks by index lists:
 // out_b[i + j*ldo] = in_b[ri[i] + ci[j]*ldi] (ri/ci < 0 -> value (ri==ci? diag : 0))
 struct GatherJob {
-  const double *in;
+  const void *in;  // double, or float if in_f32
   int64_t ldi;
-  double *out;
+  void *out;       // double, or float if out_f32
   int64_t ldo;
   const int32_t *ri;
   const int32_t *ci;
   int m, n;
   double scale;
   int add;  // accumulate into out
+  int in_f32, out_f32;
 };
 hipError_t gather_blocks(const GatherJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);
 
 // ---------------------------------------------------------------- recovery
 hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, const int64_t *yoff,
-                       int nsub, int max_e, hipStream_t s);
-hipError_t recover_backsolve(const SubDev *d_subs, const double *invL, const int64_t *invoff,
+                       int nsub, int max_e, bool fp32, hipStream_t s);
+// invL: double or float (fp32) inverse diagonal blocks of the factorisation
+hipError_t recover_backsolve(const SubDev *d_subs, const void *invL, const int64_t *invoff,
                              double *y, double *z, const int64_t *yoff, int nsub, int i0, int nb,
+                             bool fp32, hipStream_t s);
+
+// ---- mixed-precision refinement (FP64 residuals, FP32 factors)
+// R = f - K u for every subdomain's local system (CSR order, FP64)
+hipError_t local_residual(const SubDev *d_subs, const double *u, const int64_t *uoff, double *R,
+                          int nsub, int max_rows, hipStream_t s);
+// y (dense order, length N-1) from R: permutation + pressure reflector;
+// r0[s] = sum of the pressure residuals (the p0 equation)
+hipError_t residual_to_dense(const SubDev *d_subs, const double *R, const int64_t *roff,
+                             double *y, const int64_t *yoff, double *r0, int nsub, int max_rows,
                              hipStream_t s);
+// forward substitution step for the block [i0, i0+nb): z_i = inv(L_ii) y_i,
+// y_r -= L[r, i-block] z_i for r in [i0+b, N-1)
+hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *invoff, double *y,
+                        double *z, const int64_t *yoff, int nsub, int i0, int nb, int max_N,
+                        bool fp32, hipStream_t s);
+// back-substitution right-hand side: y2_j = d_j z_j - sum_l L[e+1+l, j] dx[gid_l]
+hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
+                    const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s);
 
 }  // namespace vb

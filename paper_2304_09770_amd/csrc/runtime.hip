@@ -93,8 +93,10 @@ struct vb_ctx {
   int max_n_csr = 0, max_N = 0, max_e = 0, max_ng = 0, max_ent = 0;
 
   // device buffers
-  double *W = nullptr;
-  double *invL = nullptr;
+  bool fp32 = false;      // mixed precision: FP32 local Dirichlet factors
+  size_t wsz = 8;         // bytes per entry of W and invL
+  void *W = nullptr;
+  void *invL = nullptr;
   double *b0 = nullptr, *hv = nullptr;
   int *info = nullptr;
   SubDev *d_subdev = nullptr;
@@ -129,8 +131,16 @@ struct vb_ctx {
   int64_t *d_yoff = nullptr, *d_invoff = nullptr;
   RecJob *j_rec = nullptr;
   std::vector<int64_t> rec_off;
-  const double *rec_x = nullptr;
-  int rec_valid = 0;
+  // mixed-precision refinement buffers
+  double *u_loc = nullptr, *R_loc = nullptr, *y_ir = nullptr, *z_ir = nullptr, *r0 = nullptr;
+  double *dgv = nullptr, *dx = nullptr, *zst = nullptr;
+  int64_t *d_uoff = nullptr, *d_yoff2 = nullptr;
+  int64_t *ir_ptr = nullptr, *ir_idx = nullptr;  // condensed residual assembly (offsets in y_ir)
+  RecJob *j_rec_ir = nullptr;                    // local vector from (zst, x)
+  int64_t n_ir = 0;                              // length of y_ir / z_ir / zst
+  std::vector<int64_t> uoff;
+  int last_outer = 0, last_inner = 0;
+  int recover_steps = 4;  // interior refinement passes of vb_recover_all (mixed)
 
   double setup_ms = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -190,11 +200,13 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
     delete ctx;
     return VB_ERR_ARG;
   }
-  if (d.precision != VB_PREC_FP64) {
+  if (d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) {
     delete ctx;
-    return VB_ERR_ARG;  // mixed precision is not built in this library version
+    return VB_ERR_ARG;
   }
   ctx->opt = d;
+  ctx->fp32 = (d.precision == VB_PREC_MIXED);
+  ctx->wsz = ctx->fp32 ? sizeof(float) : sizeof(double);
   ctx->stream = (hipStream_t)d.stream;
   if (hipEventCreate(&ctx->ev0) != hipSuccess || hipEventCreate(&ctx->ev1) != hipSuccess) {
     delete ctx;
@@ -346,8 +358,13 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     S.hv_off = htot;
     htot += S.nel + 1;
   }
-  CHK(ctx->dalloc(&ctx->W, wtot));
-  CHK(ctx->dalloc(&ctx->invL, itot));
+  {
+    char *w = nullptr, *iv = nullptr;
+    CHK(ctx->dalloc(&w, (size_t)wtot * ctx->wsz));
+    CHK(ctx->dalloc(&iv, (size_t)itot * ctx->wsz));
+    ctx->W = w;
+    ctx->invL = iv;
+  }
   CHK(ctx->dalloc(&ctx->b0, btot));
   CHK(ctx->dalloc(&ctx->hv, htot));
   CHK(ctx->dalloc(&ctx->info, 4 * (size_t)n_sub + 64 + 4 * (size_t)n_ent));
@@ -368,7 +385,7 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     CHK(ctx->upload(&S.d_ents, S.ents));
     CHK(ctx->upload(&S.d_entoff, S.ent_off));
     SubDev &D = ctx->subdev[s];
-    D.W = ctx->W + S.W_off;
+    D.W = (char *)ctx->W + S.W_off * ctx->wsz;
     D.ld = S.ld;
     D.nv = S.nv;
     D.nel = S.nel;
@@ -415,18 +432,21 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
   return VB_OK;
 }
 
+}  // extern "C"
+
 // ------------------------------------------------------------------ setup
-static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<double>> &jobs, int max_n, int max_e) {
+template <typename T>
+static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max_e) {
   if (jobs.empty()) return VB_OK;
-  LdlJob<double> *dj = nullptr;
+  LdlJob<T> *dj = nullptr;
   CHK(ctx->upload(&dj, jobs, true));
   std::vector<int> hn(jobs.size()), he(jobs.size());
   for (size_t b = 0; b < jobs.size(); ++b) {
     hn[b] = jobs[b].n;
     he[b] = jobs[b].e;
   }
-  CHK(ldl_batched<double>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
-                          ctx->opt.profile ? &ctx->t_ldl : nullptr, &hn, &he));
+  CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
+                     ctx->opt.profile ? &ctx->t_ldl : nullptr, &hn, &he));
   return VB_OK;
 }
 
@@ -446,10 +466,10 @@ static int run_diag(vb_ctx *ctx, const std::vector<DiagJob> &jobs, int max_cnt) 
   return VB_OK;
 }
 
-static int run_symm(vb_ctx *ctx, const std::vector<double *> &m, const std::vector<int64_t> &ld,
-                    const std::vector<int32_t> &n, bool transpose = false) {
+static int run_symm(vb_ctx *ctx, const std::vector<void *> &m, const std::vector<int64_t> &ld,
+                    const std::vector<int32_t> &n, bool transpose = false, bool fp32 = false) {
   if (m.empty()) return VB_OK;
-  double **dm = nullptr;
+  void **dm = nullptr;
   int64_t *dld = nullptr;
   int32_t *dn = nullptr;
   CHK(ctx->upload(&dm, m, true));
@@ -457,9 +477,9 @@ static int run_symm(vb_ctx *ctx, const std::vector<double *> &m, const std::vect
   CHK(ctx->upload(&dn, n, true));
   int mx = *std::max_element(n.begin(), n.end());
   if (transpose)
-    CHK(transpose_sq(dm, dld, dn, (int)m.size(), mx, ctx->stream));
+    CHK(transpose_sq(dm, dld, dn, (int)m.size(), mx, fp32, ctx->stream));
   else
-    CHK(symmetrize(dm, dld, dn, (int)m.size(), mx, ctx->stream));
+    CHK(symmetrize(dm, dld, dn, (int)m.size(), mx, fp32, ctx->stream));
   return VB_OK;
 }
 
@@ -473,6 +493,8 @@ static int check_info(vb_ctx *ctx, int count, int code, const char *what) {
                                  " at column " + std::to_string(h[i] - 1));
   return VB_OK;
 }
+
+extern "C" {
 
 static int setup_impl(vb_ctx *ctx);
 
@@ -506,19 +528,35 @@ static int setup_impl(vb_ctx *ctx) {
   // ---- 1. local dense bordered matrices, flux rows, pressure split
   int64_t wtot = 0;
   for (auto &S : ctx->subs) wtot += S.ld * S.N;
-  CHK(hipMemsetAsync(ctx->W, 0, wtot * sizeof(double), st));
+  CHK(hipMemsetAsync(ctx->W, 0, wtot * ctx->wsz, st));
+  const bool f32 = ctx->fp32;
+  auto Xptr = [&](const SubH &S) -> void * {
+    return (char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
+  };
   CHK(hipMemsetAsync(ctx->info, 0, (4 * (size_t)nS + 64 + 4 * ctx->ents.size()) * sizeof(int), st));
-  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, st));
-  CHK(flux_rows(ctx->d_subdev, nS, ctx->max_ng, st));
-  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, st));
+  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, f32, st));
+  CHK(flux_rows(ctx->d_subdev, nS, ctx->max_n_csr, st));
+  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, f32, st));
   // ---- 2. Dirichlet factorisation + Schur complement (eqs. uipi, firstSchur)
   {
-    std::vector<LdlJob<double>> jobs(nS);
-    for (int s = 0; s < nS; ++s) {
-      SubH &S = ctx->subs[s];
-      jobs[s] = {ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0, ctx->invL + S.inv_off, ctx->info + s};
+    int rc;
+    if (f32) {
+      std::vector<LdlJob<float>> jobs(nS);
+      for (int s = 0; s < nS; ++s) {
+        SubH &S = ctx->subs[s];
+        jobs[s] = {(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
+                   (float *)ctx->invL + S.inv_off, ctx->info + s};
+      }
+      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
+    } else {
+      std::vector<LdlJob<double>> jobs(nS);
+      for (int s = 0; s < nS; ++s) {
+        SubH &S = ctx->subs[s];
+        jobs[s] = {(double *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
+                   (double *)ctx->invL + S.inv_off, ctx->info + s};
+      }
+      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
     }
-    int rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
     if (rc) return rc;
     rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index)");
     if (rc) return rc;
@@ -564,33 +602,49 @@ static int setup_impl(vb_ctx *ctx) {
   }
   // ---- 4. change of basis on the bordered interface block: X <- T^T X T
   {
-    std::vector<double *> m(nS);
+    std::vector<void *> m(nS);
     std::vector<int64_t> ld(nS);
     std::vector<int32_t> n(nS);
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
-      m[s] = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+      m[s] = Xptr(S);
       ld[s] = S.ld;
       n[s] = S.ng + 1;
     }
-    int rc = run_symm(ctx, m, ld, n);
+    int rc = run_symm(ctx, m, ld, n, false, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, st));
-    rc = run_symm(ctx, m, ld, n, true);
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, f32, st));
+    rc = run_symm(ctx, m, ld, n, true, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, st));
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, f32, st));
     CHK(transform_b0(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ent, st));
   }
   // ---- 5. transformed right-hand side g~ (owner sums over the rhs columns)
   const int64_t nTot = nG + nS;
   CHK(ctx->dalloc(&ctx->g, nTot));
   {
+    // condensed local right-hand sides (border column of X) -> flat FP64 buffer
+    std::vector<int32_t> iota(ctx->max_ng + 1);
+    std::iota(iota.begin(), iota.end(), 0);
+    int32_t *d_iota = nullptr;
+    CHK(ctx->upload(&d_iota, iota, true));
+    int64_t ftot = 0;
+    for (auto &S : ctx->subs) ftot += S.ng;
+    double *gl = nullptr;
+    CHK(ctx->dalloc(&gl, std::max<int64_t>(ftot, 1), true));
+    std::vector<GatherJob> gj;
     std::vector<std::vector<int64_t>> own(nG);
+    int64_t fo = 0;
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
-      for (int l = 0; l < S.ng; ++l)
-        own[S.gidl[l]].push_back(S.W_off + (S.e + 1 + l) + (int64_t)(S.e + 1 + S.ng) * S.ld);
+      GatherJob J{Xptr(S), S.ld, gl + fo, S.ng, d_iota, d_iota, S.ng, 1, 1.0, 0, f32 ? 1 : 0, 0};
+      J.ci = d_iota + S.ng;  // column ng of X
+      gj.push_back(J);
+      for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(fo + l);
+      fo += S.ng;
     }
+    int rc0 = run_gather(ctx, gj, ctx->max_ng, 1);
+    if (rc0) return rc0;
     std::vector<int64_t> ptr(nG + 1, 0), idx;
     for (int64_t g = 0; g < nG; ++g) {
       ptr[g + 1] = ptr[g] + own[g].size();
@@ -598,7 +652,7 @@ static int setup_impl(vb_ctx *ctx) {
     }
     CHK(ctx->upload(&ctx->g_ptr, ptr, true));
     CHK(ctx->upload(&ctx->g_idx, idx, true));
-    CHK(owner_sum((int)nG, ctx->g_ptr, ctx->g_idx, ctx->W, nullptr, nullptr, ctx->g, st));
+    CHK(owner_sum((int)nG, ctx->g_ptr, ctx->g_idx, gl, nullptr, nullptr, ctx->g, st));
     std::vector<int64_t> src(nS), dst(nS);
     for (int s = 0; s < nS; ++s) {
       src[s] = ctx->subs[s].b0_off + ctx->subs[s].ng;
@@ -618,13 +672,16 @@ static int setup_impl(vb_ctx *ctx) {
     CHK(ctx->upload(&d_iota, iota, true));
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
-      double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+      char *X = (char *)Xptr(S);
       double *b0 = ctx->b0 + S.b0_off;
+      const int o32 = f32 ? 1 : 0;
       // last column: X[l, ng] = b0[l]  (in: b0 as an ng x 1 matrix)
-      jobs.push_back({b0, 1, X + (int64_t)S.ng * S.ld, S.ld, d_iota, d_iota, S.ng, 1, 1.0, 0});
+      jobs.push_back({b0, 1, X + (int64_t)S.ng * S.ld * ctx->wsz, S.ld, d_iota, d_iota, S.ng, 1,
+                      1.0, 0, 0, o32});
       // last row: X[ng, l] = b0[l]  (in: b0 as a 1 x ng matrix, ld 1)
-      jobs.push_back({b0, 1, X + S.ng, S.ld, d_iota, d_iota, 1, S.ng, 1.0, 0});
-      dj.push_back({X, S.ld, S.ng, S.ng, 1, 0.0});
+      jobs.push_back({b0, 1, X + (int64_t)S.ng * ctx->wsz, S.ld, d_iota, d_iota, 1, S.ng, 1.0, 0, 0,
+                      o32});
+      dj.push_back({X, S.ld, S.ng, S.ng, 1, 0.0, o32});
     }
     int rc = run_gather(ctx, jobs, ctx->max_ng, ctx->max_ng);
     if (rc) return rc;
@@ -661,9 +718,8 @@ static int setup_impl(vb_ctx *ctx) {
       idx.insert(idx.end(), S.pl.begin(), S.pl.end());
       int32_t *d_idx = nullptr;
       CHK(ctx->upload(&d_idx, idx, true));
-      const double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
       int m = S.ndl + S.npi;
-      gj.push_back({X, S.ld, S.Nmat, S.Nld, d_idx, d_idx, m, m, 1.0, 0});
+      gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
       mxg = std::max(mxg, m);
       if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0});
       lj.push_back({S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, invN + ioff, ctx->info + s});
@@ -683,7 +739,7 @@ static int setup_impl(vb_ctx *ctx) {
     rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Neumann factorisation (subdomain index)");
     if (rc) return rc;
     // symmetrize the trailing block, then G1 = [S_DD^-1 | Phi]
-    std::vector<double *> m;
+    std::vector<void *> m;
     std::vector<int64_t> ld;
     std::vector<int32_t> n;
     for (auto &S : ctx->subs) {
@@ -758,7 +814,7 @@ static int setup_impl(vb_ctx *ctx) {
       CHK(hipStreamSynchronize(st));
       if (h[0]) return ctx->fail(VB_ERR_SINGULAR_COARSE, "coarse factorisation: pivot breakdown at column " + std::to_string(h[0] - 1));
     }
-    std::vector<double *> m{ctx->Kaug + nCS + nCS * ctx->Kld};
+    std::vector<void *> m{ctx->Kaug + nCS + nCS * ctx->Kld};
     std::vector<int64_t> ld{ctx->Kld};
     std::vector<int32_t> n{nCS};
     rc = run_symm(ctx, m, ld, n);
@@ -768,7 +824,7 @@ static int setup_impl(vb_ctx *ctx) {
     std::iota(iota.begin(), iota.end(), 0);
     int32_t *di = nullptr;
     CHK(ctx->upload(&di, iota, true));
-    std::vector<GatherJob> gj{{m[0], ctx->Kld, ctx->Gc, nCS, di, di, nCS, nCS, -1.0, 0}};
+    std::vector<GatherJob> gj{{m[0], ctx->Kld, ctx->Gc, nCS, di, di, nCS, nCS, -1.0, 0, 0, 0}};
     rc = run_gather(ctx, gj, nCS, nCS);
     if (rc) return rc;
   }
@@ -817,11 +873,11 @@ static int setup_impl(vb_ctx *ctx) {
         for (int a = 0; a < m; ++a) idx[a] = S.ent_off[qq] + H.rank + a;
         int32_t *d_idx = nullptr;
         CHK(ctx->upload(&d_idx, idx, true));
-        const double *X = ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld;
+        const void *X = Xptr(S);
         if (rounds.size() <= q) rounds.resize(q + 1);
-        rounds[q].push_back({X, S.ld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1});
+        rounds[q].push_back({X, S.ld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
         CHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
-        sb.push_back({X, S.ld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0});
+        sb.push_back({X, S.ld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
         mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, m, m, m, m, 0, -1.0, 0.0});
       }
       dj.push_back({H.Daug, H.Dld, m, 0, m, 1.0});
@@ -846,7 +902,7 @@ static int setup_impl(vb_ctx *ctx) {
       CHK(hipStreamSynchronize(st));
       for (int v : h)
         if (v) return ctx->fail(VB_ERR_NOT_SPD, "deluxe scaling: sum of face/edge Schur blocks not SPD");
-      std::vector<double *> m;
+      std::vector<void *> m;
       std::vector<int64_t> ld;
       std::vector<int32_t> n;
       for (auto &H : ctx->ents)
@@ -883,8 +939,8 @@ static int setup_impl(vb_ctx *ctx) {
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       S.y_off = yoff;
-      js[s] = {ctx->W + S.W_off + (S.e + 1) + (S.e + 1) * S.ld, S.ld, S.ng + 1, S.ng + 1, ctx->p,
-               S.d_gidl, nullptr, nullptr, 1.0, 0};
+      js[s] = {Xptr(S), S.ld, S.ng + 1, S.ng + 1, ctx->p, S.d_gidl, nullptr, nullptr, 1.0, 0,
+               f32 ? 1 : 0};
       for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff + l);
       own[nG + s].push_back(yoff + S.ng);
       yoff += S.ng + 1;
@@ -1012,6 +1068,44 @@ static int setup_impl(vb_ctx *ctx) {
                ctx->zrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
     }
     CHK(ctx->upload(&ctx->j_rec, rj));
+    if (ctx->fp32) {  // refinement buffers: dense per-subdomain vectors of length N
+      std::vector<int64_t> yoff2(nS), uoff(nS);
+      int64_t t2 = 0;
+      for (int s = 0; s < nS; ++s) {
+        yoff2[s] = t2;
+        t2 += ctx->subs[s].N;
+        uoff[s] = ctx->rec_off[s];
+      }
+      ctx->n_ir = t2;
+      CHK(ctx->dalloc(&ctx->y_ir, t2));
+      CHK(ctx->dalloc(&ctx->z_ir, t2));
+      CHK(ctx->dalloc(&ctx->zst, t2));
+      CHK(hipMemsetAsync(ctx->y_ir, 0, t2 * sizeof(double), st));
+      CHK(hipMemsetAsync(ctx->z_ir, 0, t2 * sizeof(double), st));
+      CHK(ctx->dalloc(&ctx->u_loc, otot));
+      CHK(ctx->dalloc(&ctx->R_loc, otot));
+      CHK(ctx->dalloc(&ctx->r0, nS));
+      CHK(ctx->dalloc(&ctx->dgv, nG + nS));
+      CHK(ctx->dalloc(&ctx->dx, nG + nS));
+      CHK(ctx->upload(&ctx->d_yoff2, yoff2));
+      CHK(ctx->upload(&ctx->d_uoff, uoff));
+      std::vector<RecJob> rj2(nS);
+      std::vector<std::vector<int64_t>> own(nG);
+      for (int s = 0; s < nS; ++s) {
+        SubH &S = ctx->subs[s];
+        rj2[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
+                  ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]};
+        for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff2[s] + S.e + 1 + l);
+      }
+      CHK(ctx->upload(&ctx->j_rec_ir, rj2));
+      std::vector<int64_t> ptr(nG + 1, 0), idx;
+      for (int64_t g = 0; g < nG; ++g) {
+        ptr[g + 1] = ptr[g] + own[g].size();
+        idx.insert(idx.end(), own[g].begin(), own[g].end());
+      }
+      CHK(ctx->upload(&ctx->ir_ptr, ptr));
+      CHK(ctx->upload(&ctx->ir_idx, idx));
+    }
   }
   CHK(hipEventRecord(ctx->ev1, st));
   CHK(hipEventSynchronize(ctx->ev1));
@@ -1026,6 +1120,8 @@ static int setup_impl(vb_ctx *ctx) {
   }
   for (auto &S : ctx->subs) S.Nmat = nullptr;
   ctx->Kaug = nullptr;
+  ctx->p0_src = ctx->p0_dst = nullptr;
+  ctx->g_ptr = ctx->g_idx = nullptr;
   ctx->state = 2;
   return VB_OK;
 }
@@ -1138,38 +1234,48 @@ static void lanczos_extremes(const std::vector<double> &a, const std::vector<dou
 
 extern "C" {
 
-int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
-  if (!ctx || !x_dev) return VB_ERR_ARG;
-  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_pcg_solve: call vb_setup first");
+}  // extern "C"
+
+// PCG on S~ x~ = b~ in the transformed coordinates (Sec. 7), on ctx->x.
+// x_zero: start from x~ = 0 (r = b) instead of the current ctx->x.
+// record: keep the Lanczos coefficients (alpha_k, beta_k) in hist_a/hist_b.
+struct PcgResult {
+  int it = 0, status = VB_OK;
+  double rel = 0.0, bnorm = 0.0;
+};
+
+static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, double tol, int maxit, bool record,
+                    PcgResult *res) {
   hipStream_t st = ctx->stream;
   const int64_t n = ctx->nG + ctx->nS;
-  const int nE = (int)ctx->ents.size();
   double hs[SC_COUNT];
-  CHK(hipEventRecord(ctx->ev0, st));
   CHK(hipMemsetAsync(ctx->sc, 0, SC_COUNT * sizeof(double), st));
-  // x~ = T^T x0 ; r = g - S x~
-  CHK(hipMemcpyAsync(ctx->x, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  CHK(transform_vec(ctx->d_entdev, nE, ctx->x, +1, st));
-  CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  int rc = apply_S_internal(ctx);
-  if (rc) return rc;
-  CHK(vsub(n, ctx->g, ctx->q, ctx->r, st));
-  CHK(dot(n, ctx->g, ctx->g, ctx->part, ctx->sc, 4, 0, nullptr, nullptr, st));
+  if (x_zero) {
+    CHK(hipMemsetAsync(ctx->x, 0, n * sizeof(double), st));
+    CHK(hipMemcpyAsync(ctx->r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  } else {
+    CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    int rc = apply_S_internal(ctx);
+    if (rc) return rc;
+    CHK(vsub(n, b, ctx->q, ctx->r, st));
+  }
+  CHK(dot(n, b, b, ctx->part, ctx->sc, 4, 0, nullptr, nullptr, st));
   CHK(dot(n, ctx->r, ctx->r, ctx->part, ctx->sc, 1, 0, nullptr, nullptr, st));
   CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
-  const double gn = std::sqrt(hs[SC_GG]);
-  double rel = gn > 0 ? std::sqrt(hs[SC_RR]) / gn : 0.0;
+  const double bn = std::sqrt(hs[SC_GG]);
+  double rel = bn > 0 ? std::sqrt(hs[SC_RR]) / bn : 0.0;
   int it = 0, status = VB_OK;
-  if (rel > ctx->opt.tol) {
-    rc = apply_M_internal(ctx);
+  double *ha = record ? ctx->hist_a : nullptr, *hb = record ? ctx->hist_b : nullptr;
+  if (rel > tol) {
+    int rc = apply_M_internal(ctx);
     if (rc) return rc;
     CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 3, 0, nullptr, nullptr, st));
     CHK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     while (true) {
       rc = apply_S_internal(ctx);
       if (rc) return rc;
-      CHK(dot(n, ctx->p, ctx->q, ctx->part, ctx->sc, 0, it, ctx->hist_a, nullptr, st));
+      CHK(dot(n, ctx->p, ctx->q, ctx->part, ctx->sc, 0, it, ha, nullptr, st));
       CHK(update_xr(n, ctx->sc, ctx->x, ctx->r, ctx->p, ctx->q, ctx->part, ctx->sc, st));
       CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
       CHK(hipStreamSynchronize(st));
@@ -1178,18 +1284,162 @@ int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
         status = VB_ERR_BREAKDOWN;
         break;
       }
-      rel = std::sqrt(hs[SC_RR]) / gn;
-      if (rel <= ctx->opt.tol) break;
-      if (it >= ctx->opt.maxit) {
+      rel = std::sqrt(hs[SC_RR]) / bn;
+      if (rel <= tol) break;
+      if (it >= maxit) {
         status = VB_ERR_NOT_CONVERGED;
         break;
       }
       rc = apply_M_internal(ctx);
       if (rc) return rc;
-      CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 2, it - 1, nullptr, ctx->hist_b, st));
+      CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 2, it - 1, nullptr, hb, st));
       CHK(update_p(n, ctx->sc, ctx->p, ctx->z, st));
     }
   }
+  res->it = it;
+  res->status = status;
+  res->rel = rel;
+  res->bnorm = bn;
+  return VB_OK;
+}
+
+static int fill_lanczos(vb_ctx *ctx, int it, vb_solve_info *info) {
+  std::vector<double> a(it), b(it > 0 ? it - 1 : 0);
+  if (it) CHK(hipMemcpy(a.data(), ctx->hist_a, it * sizeof(double), hipMemcpyDeviceToHost));
+  if (it > 1) CHK(hipMemcpy(b.data(), ctx->hist_b, (it - 1) * sizeof(double), hipMemcpyDeviceToHost));
+  lanczos_extremes(a, b, &info->lambda_min, &info->lambda_max);
+  return VB_OK;
+}
+
+// One pass of the FP64 residual condensation used by the refinement:
+// u = local vectors from (zst, x); R = f - K u (FP64, sparse); y = R in the
+// dense order with rotated pressures; forward substitution with the stored
+// factor over the eliminated columns (eq. uipi); on return the rows e+1.. of
+// y hold the condensed interface residual of every subdomain and r0 the
+// residual of its constant-pressure equation.
+static int condense_residual(vb_ctx *ctx, const double *x_orig) {
+  hipStream_t st = ctx->stream;
+  CHK(recover_out(ctx->j_rec_ir, ctx->nS, x_orig, ctx->nG, st));
+  CHK(local_residual(ctx->d_subdev, ctx->u_loc, ctx->d_uoff, ctx->R_loc, ctx->nS, ctx->max_n_csr,
+                     st));
+  CHK(residual_to_dense(ctx->d_subdev, ctx->R_loc, ctx->d_uoff, ctx->y_ir, ctx->d_yoff2, ctx->r0,
+                        ctx->nS, ctx->max_n_csr, st));
+  const int nb = ctx->opt.panel;
+  for (int i0 = 0; i0 < ctx->max_e; i0 += nb)
+    CHK(forward_step(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir, ctx->d_yoff2,
+                     ctx->nS, i0, nb, ctx->max_N, ctx->fp32, st));
+  return VB_OK;
+}
+
+// Interior correction for an interface correction dx (null: none):
+// K_II dz = y_I - C dx through L^T, then zst += dz.
+static int interior_correction(vb_ctx *ctx, const double *dx) {
+  hipStream_t st = ctx->stream;
+  CHK(back_rhs(ctx->d_subdev, ctx->z_ir, dx, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e,
+               ctx->fp32, st));
+  const int nb = ctx->opt.panel;
+  for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir,
+                          ctx->d_yoff2, ctx->nS, j0, nb, ctx->fp32, st));
+  CHK(axpy(ctx->n_ir, 1.0, ctx->z_ir, ctx->zst, st));
+  return VB_OK;
+}
+
+// Mixed precision (FP32 local factors and Schur operators, FP64 residuals):
+// iterative refinement of the whole saddle system around the BDDC/PCG
+// solve.  Each outer step condenses the FP64 residual of the local systems,
+// solves the interface correction with PCG on the FP32 operators to a loose
+// relative tolerance, recovers the interior correction with the FP32
+// factor and updates (x, interior state).  Stops when the condensed
+// residual has dropped by opt.tol relative to the first one.
+static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
+  hipStream_t st = ctx->stream;
+  const int64_t n = ctx->nG + ctx->nS;
+  const int nE = (int)ctx->ents.size();
+  const int max_outer = 30;
+  const double inner_floor = 1e-4;
+  double hs[SC_COUNT];
+  CHK(hipEventRecord(ctx->ev0, st));
+  CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
+  double r_first = 0.0, rel = 0.0;
+  int outer = 0, inner = 0, status = VB_OK, first_it = 0;
+  while (true) {
+    int rc = condense_residual(ctx, x_dev);
+    if (rc) return rc;
+    CHK(owner_sum((int)ctx->nG, ctx->ir_ptr, ctx->ir_idx, ctx->y_ir, nullptr, nullptr, ctx->dgv,
+                  st));
+    CHK(scatter_copy(ctx->nS, ctx->r0, nullptr, nullptr, ctx->dgv + ctx->nG, 1.0, st));
+    CHK(dot(n, ctx->dgv, ctx->dgv, ctx->part, ctx->sc, 5, 0, nullptr, nullptr, st));
+    CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    const double rn = std::sqrt(hs[SC_TMP]);
+    if (outer == 0) r_first = rn;
+    rel = r_first > 0 ? rn / r_first : 0.0;
+    if (!(rel > ctx->opt.tol)) break;
+    if (outer >= max_outer || inner >= ctx->opt.maxit) {
+      status = VB_ERR_NOT_CONVERGED;
+      break;
+    }
+    // interface correction on the FP32 operators
+    CHK(transform_vec(ctx->d_entdev, nE, ctx->dgv, +1, st));
+    const double tin = std::max(inner_floor, 0.5 * ctx->opt.tol / std::max(rel, 1e-300));
+    PcgResult pr;
+    rc = pcg_core(ctx, ctx->dgv, true, tin, ctx->opt.maxit - inner, outer == 0, &pr);
+    if (rc) return rc;
+    if (outer == 0) first_it = pr.it;
+    inner += pr.it;
+    if (pr.status == VB_ERR_BREAKDOWN) {
+      status = pr.status;
+      break;
+    }
+    CHK(hipMemcpyAsync(ctx->dx, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    CHK(transform_vec(ctx->d_entdev, nE, ctx->dx, -1, st));
+    rc = interior_correction(ctx, ctx->dx);
+    if (rc) return rc;
+    CHK(axpy(n, 1.0, ctx->dx, x_dev, st));
+    ++outer;
+  }
+  CHK(hipEventRecord(ctx->ev1, st));
+  CHK(hipEventSynchronize(ctx->ev1));
+  float ms = 0.f;
+  CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
+  ctx->last_outer = outer;
+  ctx->last_inner = inner;
+  if (info) {
+    info->iterations = inner;
+    info->refinement_steps = outer;
+    info->rel_residual = rel;
+    info->true_rel_residual = rel;
+    info->n_coarse = ctx->nCS;
+    info->setup_ms = ctx->setup_ms;
+    info->solve_ms = ms;
+    info->status = status;
+    int rc = fill_lanczos(ctx, first_it, info);
+    if (rc) return rc;
+  }
+  if (status == VB_ERR_BREAKDOWN) return ctx->fail(status, "PCG breakdown: p^T S p <= 0 or NaN");
+  if (status == VB_ERR_NOT_CONVERGED)
+    return ctx->fail(status, "refinement did not reach the tolerance");
+  return VB_OK;
+}
+
+extern "C" {
+
+int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
+  if (!ctx || !x_dev) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_pcg_solve: call vb_setup first");
+  if (ctx->fp32) return mixed_solve(ctx, x_dev, info);
+  hipStream_t st = ctx->stream;
+  const int64_t n = ctx->nG + ctx->nS;
+  const int nE = (int)ctx->ents.size();
+  double hs[SC_COUNT];
+  CHK(hipEventRecord(ctx->ev0, st));
+  // x~ = T^T x0 ; PCG on S~ x~ = g~
+  CHK(hipMemcpyAsync(ctx->x, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  CHK(transform_vec(ctx->d_entdev, nE, ctx->x, +1, st));
+  PcgResult pr;
+  int rc = pcg_core(ctx, ctx->g, false, ctx->opt.tol, ctx->opt.maxit, true, &pr);
+  if (rc) return rc;
   // true residual
   CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   rc = apply_S_internal(ctx);
@@ -1204,20 +1454,19 @@ int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
   float ms = 0.f;
   CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   if (info) {
-    info->iterations = it;
-    info->rel_residual = rel;
-    info->true_rel_residual = gn > 0 ? std::sqrt(hs[SC_TMP]) / gn : 0.0;
+    info->iterations = pr.it;
+    info->refinement_steps = 0;
+    info->rel_residual = pr.rel;
+    info->true_rel_residual = pr.bnorm > 0 ? std::sqrt(hs[SC_TMP]) / pr.bnorm : 0.0;
     info->n_coarse = ctx->nCS;
     info->setup_ms = ctx->setup_ms;
     info->solve_ms = ms;
-    info->status = status;
-    std::vector<double> a(it), b(it > 0 ? it - 1 : 0);
-    if (it) CHK(hipMemcpy(a.data(), ctx->hist_a, it * sizeof(double), hipMemcpyDeviceToHost));
-    if (it > 1) CHK(hipMemcpy(b.data(), ctx->hist_b, (it - 1) * sizeof(double), hipMemcpyDeviceToHost));
-    lanczos_extremes(a, b, &info->lambda_min, &info->lambda_max);
+    info->status = pr.status;
+    rc = fill_lanczos(ctx, pr.it, info);
+    if (rc) return rc;
   }
-  if (status == VB_ERR_BREAKDOWN) return ctx->fail(status, "PCG breakdown: p^T S p <= 0 or NaN");
-  if (status == VB_ERR_NOT_CONVERGED) return ctx->fail(status, "PCG reached maxit");
+  if (pr.status == VB_ERR_BREAKDOWN) return ctx->fail(pr.status, "PCG breakdown: p^T S p <= 0 or NaN");
+  if (pr.status == VB_ERR_NOT_CONVERGED) return ctx->fail(pr.status, "PCG reached maxit");
   return VB_OK;
 }
 
@@ -1225,11 +1474,29 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
   if (!ctx || !x_dev) return VB_ERR_ARG;
   if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_recover_all: call vb_setup first");
   hipStream_t st = ctx->stream;
-  CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, ctx->nS, ctx->max_e, st));
+  if (ctx->fp32) {
+    // FP32 factor: start from zero interior state and refine the interior
+    // equations in FP64 with the interface data fixed at x
+    CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
+    for (int k = 0; k < ctx->recover_steps; ++k) {
+      int rc = condense_residual(ctx, x_dev);
+      if (rc) return rc;
+      rc = interior_correction(ctx, nullptr);
+      if (rc) return rc;
+    }
+    CHK(recover_out(ctx->j_rec_ir, ctx->nS, x_dev, ctx->nG, st));
+    CHK(hipMemcpyAsync(ctx->rec_out, ctx->u_loc, ctx->rec_off[ctx->nS] * sizeof(double),
+                       hipMemcpyDeviceToDevice, st));
+    if (out_dev)
+      CHK(hipMemcpyAsync(out_dev, ctx->u_loc, ctx->rec_off[ctx->nS] * sizeof(double),
+                         hipMemcpyDeviceToDevice, st));
+    return VB_OK;
+  }
+  CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, ctx->nS, ctx->max_e, ctx->fp32, st));
   const int nb = ctx->opt.panel;  // the panel width the factorisation used
   for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
     CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->zrec,
-                          ctx->d_yoff, ctx->nS, j0, nb, st));
+                          ctx->d_yoff, ctx->nS, j0, nb, ctx->fp32, st));
   CHK(recover_out(ctx->j_rec, ctx->nS, x_dev, ctx->nG, st));
   if (out_dev)
     CHK(hipMemcpyAsync(out_dev, ctx->rec_out, ctx->rec_off[ctx->nS] * sizeof(double),

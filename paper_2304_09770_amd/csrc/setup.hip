@@ -1,49 +1,75 @@
 // Setup kernels: local dense matrices, the Q_I / Q_0 pressure split, the
-// primal change of basis and block gathers.
+// primal change of basis, block gathers, interior recovery and the
+// refinement steps of the mixed-precision path.  The dense local matrices
+// are stored in T = double (FP64 path) or float (mixed path).
 #include "common.h"
 #include "kernels.h"
 
 namespace vb {
 
+template <typename T> __device__ __forceinline__ T *Wp(const SubDev &S) { return (T *)S.W; }
+
 // Scatter the local CSR (both triangles) and the right-hand side into the
 // dense bordered matrix [[K, r], [r^T, 0]] with the DoF order
 // [interior velocity | element pressures | interface | rhs].
+template <typename T>
 __global__ void k_densify(const SubDev *subs) {
   const SubDev S = subs[blockIdx.y];
   const int row = blockIdx.x * blockDim.x + threadIdx.x;
   if (row >= S.n_csr) return;
+  T *W = Wp<T>(S);
   const int pr = S.pos[row];
   for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) {
     const int pc = S.pos[S.indices[q]];
-    S.W[(int64_t)pr + (int64_t)pc * S.ld] = S.vals[q];
+    W[(int64_t)pr + (int64_t)pc * S.ld] = (T)S.vals[q];
   }
   const int last = S.N - 1;
-  S.W[(int64_t)pr + (int64_t)last * S.ld] = S.rhs[row];
-  S.W[(int64_t)last + (int64_t)pr * S.ld] = S.rhs[row];
+  W[(int64_t)pr + (int64_t)last * S.ld] = (T)S.rhs[row];
+  W[(int64_t)last + (int64_t)pr * S.ld] = (T)S.rhs[row];
 }
 
-hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s) {
+hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  hipLaunchKernelGGL(k_densify, dim3((max_rows + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  dim3 g((max_rows + 255) / 256, nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_densify<float>, g, dim3(256), 0, s, d_subs);
+  else
+    hipLaunchKernelGGL(k_densify<double>, g, dim3(256), 0, s, d_subs);
   return hipGetLastError();
 }
 
-// B0_Gamma^(i) = sum of the element flux rows over the interface columns and
-// the p0 right-hand side (the sum of the pressure right-hand sides): the
-// equation tested with the constant pressure on the subdomain (eq. discMat).
+// B0_Gamma^(i): the equation tested with the constant pressure on the
+// subdomain (eq. discMat) is the sum of the element flux rows; by symmetry of
+// the local matrix, entry l is the sum over pressure columns of interface row
+// l.  b0[ng] = the p0 right-hand side (sum of the pressure right-hand sides).
+// Computed from the FP64 CSR, deterministic.
 __global__ void k_flux_rows(const SubDev *subs) {
   const SubDev S = subs[blockIdx.y];
-  const int c = blockIdx.x * blockDim.x + threadIdx.x;
-  if (c > S.ng) return;
-  const double *col = S.W + (int64_t)(S.nv + S.nel + c) * S.ld + S.nv;
-  double s = 0.0;
-  for (int r = 0; r < S.nel; ++r) s += col[r];
-  S.b0[c] = s;
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= S.n_csr) return;
+  const int pr = S.pos[row];
+  const int g0 = S.nv + S.nel;
+  if (pr >= g0) {  // interface row
+    double s = 0.0;
+    for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) {
+      const int pc = S.pos[S.indices[q]];
+      if (pc >= S.nv && pc < g0) s += S.vals[q];
+    }
+    S.b0[pr - g0] = s;
+  }
+  if (row == 0) {
+    double s = 0.0;
+    for (int i = 0; i < S.n_csr; ++i) {
+      const int p = S.pos[i];
+      if (p >= S.nv && p < g0) s += S.rhs[i];
+    }
+    S.b0[S.ng] = s;
+  }
 }
 
-hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_ng, hipStream_t s) {
+hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  hipLaunchKernelGGL(k_flux_rows, dim3((max_ng + 1 + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  hipLaunchKernelGGL(k_flux_rows, dim3((max_rows + 255) / 256, nsub), dim3(256), 0, s, d_subs);
   return hipGetLastError();
 }
 
@@ -69,36 +95,45 @@ __global__ void k_house_vec(const SubDev *subs) {
 }
 
 // rows: W[p, j] <- H W[p, j] for every column j (one wave per column)
+template <typename T>
 __global__ void k_house_rows(const SubDev *subs) {
   const SubDev S = subs[blockIdx.y];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + w;
   if (j >= S.N) return;
-  double *col = S.W + (int64_t)j * S.ld + S.nv;
+  T *col = Wp<T>(S) + (int64_t)j * S.ld + S.nv;
   const double tau = S.hv[S.nel];
   double s = 0.0;
-  for (int r = l; r < S.nel; r += 64) s += S.hv[r] * col[r];
+  for (int r = l; r < S.nel; r += 64) s += S.hv[r] * (double)col[r];
   s = warp_sum(s);
-  for (int r = l; r < S.nel; r += 64) col[r] -= tau * S.hv[r] * s;
+  for (int r = l; r < S.nel; r += 64) col[r] = (T)((double)col[r] - tau * S.hv[r] * s);
 }
 
 // cols: W[i, p] <- W[i, p] H for every row i (one thread per row, coalesced)
+template <typename T>
 __global__ void k_house_cols(const SubDev *subs) {
   const SubDev S = subs[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= S.N) return;
   const double tau = S.hv[S.nel];
-  double *base = S.W + i + (int64_t)S.nv * S.ld;
+  T *base = Wp<T>(S) + i + (int64_t)S.nv * S.ld;
   double s = 0.0;
-  for (int c = 0; c < S.nel; ++c) s += base[(int64_t)c * S.ld] * S.hv[c];
-  for (int c = 0; c < S.nel; ++c) base[(int64_t)c * S.ld] -= tau * s * S.hv[c];
+  for (int c = 0; c < S.nel; ++c) s += (double)base[(int64_t)c * S.ld] * S.hv[c];
+  for (int c = 0; c < S.nel; ++c)
+    base[(int64_t)c * S.ld] = (T)((double)base[(int64_t)c * S.ld] - tau * s * S.hv[c]);
 }
 
-hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, hipStream_t s) {
+hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
   hipLaunchKernelGGL(k_house_vec, dim3(nsub), dim3(256), 0, s, d_subs);
-  hipLaunchKernelGGL(k_house_rows, dim3((max_N + 3) / 4, nsub), dim3(256), 0, s, d_subs);
-  hipLaunchKernelGGL(k_house_cols, dim3((max_N + 255) / 256, nsub), dim3(256), 0, s, d_subs);
+  dim3 gr((max_N + 3) / 4, nsub), gc((max_N + 255) / 256, nsub);
+  if (fp32) {
+    hipLaunchKernelGGL(k_house_rows<float>, gr, dim3(256), 0, s, d_subs);
+    hipLaunchKernelGGL(k_house_cols<float>, gc, dim3(256), 0, s, d_subs);
+  } else {
+    hipLaunchKernelGGL(k_house_rows<double>, gr, dim3(256), 0, s, d_subs);
+    hipLaunchKernelGGL(k_house_cols<double>, gc, dim3(256), 0, s, d_subs);
+  }
   return hipGetLastError();
 }
 
@@ -162,7 +197,8 @@ __global__ void k_entity_qr(const EntDev *ents, int rmax, double tol) {
     const double alpha = (x0 >= 0.0) ? -sig : sig;
     // v = x - alpha e_k (rows k..n-1), tau = 2 / v^T v
     double *V = E.V + (int64_t)k * n;
-    for (int i = threadIdx.x; i < n; i += blockDim.x) V[i] = (i < k) ? 0.0 : M[i + k * n] - ((i == k) ? alpha : 0.0);
+    for (int i = threadIdx.x; i < n; i += blockDim.x)
+      V[i] = (i < k) ? 0.0 : M[i + k * n] - ((i == k) ? alpha : 0.0);
     __syncthreads();
     double vv = 0.0;
     for (int i = k + threadIdx.x; i < n; i += blockDim.x) vv += V[i] * V[i];
@@ -197,7 +233,12 @@ hipError_t entity_qr(const EntDev *d_ents, int nent, int rmax, double tol, hipSt
 __global__ void k_set_diag(const DiagJob *jobs) {
   const DiagJob J = jobs[blockIdx.y];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < J.cnt) J.A[(int64_t)(J.r0 + i) + (int64_t)(J.c0 + i) * J.ld] = J.val;
+  if (i >= J.cnt) return;
+  const int64_t o = (int64_t)(J.r0 + i) + (int64_t)(J.c0 + i) * J.ld;
+  if (J.f32)
+    ((float *)J.A)[o] = (float)J.val;
+  else
+    ((double *)J.A)[o] = J.val;
 }
 
 hipError_t set_diag(const DiagJob *d_jobs, int batch, int max_cnt, hipStream_t s) {
@@ -240,17 +281,18 @@ hipError_t coarse_assemble(const CoarseSub *d_cs, int nsub, double *K, int64_t l
 }
 
 // Symmetrize square blocks: upper <- lower.
-__global__ void k_symmetrize(double *const *mats, const int64_t *lds, const int32_t *ns) {
-  double *A = mats[blockIdx.z];
+template <typename T>
+__global__ void k_symmetrize(void *const *mats, const int64_t *lds, const int32_t *ns) {
+  T *A = (T *)mats[blockIdx.z];
   const int64_t ld = lds[blockIdx.z];
   const int n = ns[blockIdx.z];
-  __shared__ double t[32][33];
+  __shared__ T t[32][33];
   const int bi = blockIdx.x, bj = blockIdx.y;  // tile (bi, bj) with bi > bj is the source
   if (bi < bj) return;
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
   for (int yy = ty; yy < 32; yy += 8) {
     int r = bi * 32 + tx, c = bj * 32 + yy;
-    t[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+    t[yy][tx] = (r < n && c < n) ? A[r + c * ld] : T(0);
   }
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
@@ -259,29 +301,33 @@ __global__ void k_symmetrize(double *const *mats, const int64_t *lds, const int3
   }
 }
 
-hipError_t symmetrize(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
-                      int max_n, hipStream_t s) {
+hipError_t symmetrize(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                      int max_n, bool fp32, hipStream_t s) {
   if (!batch || !max_n) return hipSuccess;
   int nt = (max_n + 31) / 32;
-  hipLaunchKernelGGL(k_symmetrize, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  if (fp32)
+    hipLaunchKernelGGL(k_symmetrize<float>, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  else
+    hipLaunchKernelGGL(k_symmetrize<double>, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
   return hipGetLastError();
 }
 
 // In-place transpose of square blocks (swap tiles (bi,bj) and (bj,bi)).
-__global__ void k_transpose_sq(double *const *mats, const int64_t *lds, const int32_t *ns) {
-  double *A = mats[blockIdx.z];
+template <typename T>
+__global__ void k_transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns) {
+  T *A = (T *)mats[blockIdx.z];
   const int64_t ld = lds[blockIdx.z];
   const int n = ns[blockIdx.z];
   const int bi = blockIdx.x, bj = blockIdx.y;
   if (bi < bj) return;
-  __shared__ double ta[32][33], tb[32][33];
+  __shared__ T ta[32][33], tb[32][33];
   const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
   for (int yy = ty; yy < 32; yy += 8) {
     int r = bi * 32 + tx, c = bj * 32 + yy;
-    ta[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+    ta[yy][tx] = (r < n && c < n) ? A[r + c * ld] : T(0);
     r = bj * 32 + tx;
     c = bi * 32 + yy;
-    tb[yy][tx] = (r < n && c < n) ? A[r + c * ld] : 0.0;
+    tb[yy][tx] = (r < n && c < n) ? A[r + c * ld] : T(0);
   }
   __syncthreads();
   for (int yy = ty; yy < 32; yy += 8) {
@@ -293,17 +339,21 @@ __global__ void k_transpose_sq(double *const *mats, const int64_t *lds, const in
   }
 }
 
-hipError_t transpose_sq(double *const *mats, const int64_t *lds, const int32_t *ns, int batch,
-                        int max_n, hipStream_t s) {
+hipError_t transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
+                        int max_n, bool fp32, hipStream_t s) {
   if (!batch || !max_n) return hipSuccess;
   int nt = (max_n + 31) / 32;
-  hipLaunchKernelGGL(k_transpose_sq, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  if (fp32)
+    hipLaunchKernelGGL(k_transpose_sq<float>, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
+  else
+    hipLaunchKernelGGL(k_transpose_sq<double>, dim3(nt, nt, batch), dim3(256), 0, s, mats, lds, ns);
   return hipGetLastError();
 }
 
 // X <- X T for the bordered interface block X = W[e+1.., e+1..] (size ng+1):
 // for every local entity, apply its reflectors H_0, H_1, ... to the entity's
 // columns.  One thread per row.
+template <typename T>
 __global__ void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
   const SubDev S = subs[blockIdx.z];
   if ((int)blockIdx.y >= S.n_ent) return;
@@ -313,23 +363,27 @@ __global__ void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
   const EntDev E = ents[S.ent[blockIdx.y]];
   const int o = S.ent_off[blockIdx.y];
   const int rk = *E.rank;
-  double *X = S.W + (int64_t)(S.e + 1) + (int64_t)(S.e + 1) * S.ld;
-  double *row = X + i;
+  T *X = Wp<T>(S) + (int64_t)(S.e + 1) + (int64_t)(S.e + 1) * S.ld;
+  T *row = X + i;
   for (int k = 0; k < rk; ++k) {
     const double *v = E.V + (int64_t)k * E.n;
     const double tau = E.tau[k];
     double t = 0.0;
-    for (int c = k; c < E.n; ++c) t += row[(int64_t)(o + c) * S.ld] * v[c];
+    for (int c = k; c < E.n; ++c) t += (double)row[(int64_t)(o + c) * S.ld] * v[c];
     t *= tau;
-    for (int c = k; c < E.n; ++c) row[(int64_t)(o + c) * S.ld] -= t * v[c];
+    for (int c = k; c < E.n; ++c)
+      row[(int64_t)(o + c) * S.ld] = (T)((double)row[(int64_t)(o + c) * S.ld] - t * v[c]);
   }
 }
 
 hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
-                        int max_ent, hipStream_t s) {
+                        int max_ent, bool fp32, hipStream_t s) {
   if (!nsub || !max_ent) return hipSuccess;
-  hipLaunchKernelGGL(k_apply_T_cols, dim3((max_ng + 1 + 127) / 128, max_ent, nsub), dim3(128), 0, s,
-                     d_subs, d_ents);
+  dim3 g((max_ng + 1 + 127) / 128, max_ent, nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_apply_T_cols<float>, g, dim3(128), 0, s, d_subs, d_ents);
+  else
+    hipLaunchKernelGGL(k_apply_T_cols<double>, g, dim3(128), 0, s, d_subs, d_ents);
   return hipGetLastError();
 }
 
@@ -381,8 +435,7 @@ hipError_t transform_vec(const EntDev *d_ents, int nent, double *x, int dir, hip
   return hipGetLastError();
 }
 
-// out[i + j*ldo] (+)= scale * in[ri[i] + ci[j]*ldi]; an index < 0 selects the
-// identity (1 if ri[i] == ci[j] as negative codes, else 0).
+// out[i + j*ldo] (+)= scale * in[ri[i] + ci[j]*ldi]
 __global__ void k_gather_blocks(const GatherJob *jobs) {
   const GatherJob J = jobs[blockIdx.z];
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
@@ -392,15 +445,17 @@ __global__ void k_gather_blocks(const GatherJob *jobs) {
   for (int jj = threadIdx.x >> 6; jj < 64; jj += blockDim.x >> 6) {
     const int j = j0 + jj;
     if (j >= J.n) break;
-    const int cj = J.ci[j];
-    double v;
-    if (ri >= 0 && cj >= 0)
-      v = J.in[(int64_t)ri + (int64_t)cj * J.ldi];
-    else
-      v = (ri < 0 && ri == cj) ? 1.0 : 0.0;
+    const int64_t src = (int64_t)ri + (int64_t)J.ci[j] * J.ldi;
+    double v = J.in_f32 ? (double)((const float *)J.in)[src] : ((const double *)J.in)[src];
     v *= J.scale;
-    double *o = J.out + (int64_t)i + (int64_t)j * J.ldo;
-    if (J.add) *o += v; else *o = v;
+    const int64_t dst = (int64_t)i + (int64_t)j * J.ldo;
+    if (J.out_f32) {
+      float *o = (float *)J.out + dst;
+      *o = J.add ? (float)((double)*o + v) : (float)v;
+    } else {
+      double *o = (double *)J.out + dst;
+      *o = J.add ? *o + v : v;
+    }
   }
 }
 
@@ -414,23 +469,27 @@ hipError_t gather_blocks(const GatherJob *d_jobs, int batch, int max_m, int max_
 // ---------------------------------------------------------------- recovery
 // y = L_rI^T - L_GammaI^T u_Gamma over the eliminated columns (eq. uipi after
 // the factorisation: K_II^-1 (r_I - C u_Gamma) = L_II^-T y).  One wave per column.
+template <typename T>
 __global__ void k_recover_rhs(const SubDev *subs, const double *x, double *y, const int64_t *yoff) {
   const SubDev S = subs[blockIdx.y];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   const int j = blockIdx.x * (blockDim.x >> 6) + w;
   if (j >= S.e) return;
-  const double *col = S.W + (int64_t)j * S.ld + (S.e + 1);
+  const auto col = gptr(Wp<T>(S) + (int64_t)j * S.ld + (S.e + 1));
   double s = 0.0;
-  for (int r = l; r < S.ng; r += 64) s += col[r] * x[S.gidl[r]];
+  for (int r = l; r < S.ng; r += 64) s += (double)col[r] * x[S.gidl[r]];
   s = warp_sum(s);
-  if (l == 0) y[yoff[blockIdx.y] + j] = col[S.ng] - s;
+  if (l == 0) y[yoff[blockIdx.y] + j] = (double)col[S.ng] - s;
 }
 
 hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, const int64_t *yoff,
-                       int nsub, int max_e, hipStream_t s) {
+                       int nsub, int max_e, bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  hipLaunchKernelGGL(k_recover_rhs, dim3((max_e + 3) / 4, nsub), dim3(256), 0, s, d_subs, x_orig, y,
-                     yoff);
+  dim3 g((max_e + 3) / 4, nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_recover_rhs<float>, g, dim3(256), 0, s, d_subs, x_orig, y, yoff);
+  else
+    hipLaunchKernelGGL(k_recover_rhs<double>, g, dim3(256), 0, s, d_subs, x_orig, y, yoff);
   return hipGetLastError();
 }
 
@@ -439,7 +498,8 @@ hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, co
 // the cached inverse; workgroup 0 stores it), then y_k -= L[i-block, k]^T z_i
 // for all columns k < i0, one wave per column (the block rows are contiguous
 // in the column-major factor).
-__global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const double *invL,
+template <typename T>
+__global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const T *invL,
                                                       const int64_t *invoff, double *y,
                                                       double *z, const int64_t *yoff, int i0,
                                                       int nb) {
@@ -449,13 +509,13 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
   double *ys = y + yoff[blockIdx.y];
   double *zs = z + yoff[blockIdx.y];
   __shared__ double yi[64], zi[64];
-  const double *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
+  const T *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
   if (threadIdx.x < b) yi[threadIdx.x] = ys[i0 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x < b) {
     const int c = threadIdx.x;
     double s = 0.0;  // (inv^T y)_c = sum_{r >= c} inv[r][c] y_r
-    for (int r = c; r < b; ++r) s += inv[r + c * nb] * yi[r];
+    for (int r = c; r < b; ++r) s += (double)inv[r + c * nb] * yi[r];
     zi[c] = s;
     if (blockIdx.x == 0) zs[i0 + c] = s;
   }
@@ -466,20 +526,156 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
   for (int kk = w; kk < 64; kk += 4) {
     const int k = k0 + kk;
     if (k >= i0) break;
-    const auto col = gptr(S.W + (int64_t)k * S.ld + i0);
-    double s = (l < b) ? col[l] * zl : 0.0;
+    const auto col = gptr(Wp<T>(S) + (int64_t)k * S.ld + i0);
+    double s = (l < b) ? (double)col[l] * zl : 0.0;
     s = warp_sum(s);
     if (l == 0) ys[k] -= s;
   }
 }
 
-hipError_t recover_backsolve(const SubDev *d_subs, const double *invL, const int64_t *invoff,
-                             double *y, double *z, const int64_t *yoff, int nsub, int i0,
-                             int nb, hipStream_t s) {
+hipError_t recover_backsolve(const SubDev *d_subs, const void *invL, const int64_t *invoff,
+                             double *y, double *z, const int64_t *yoff, int nsub, int i0, int nb,
+                             bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
   const int gx = i0 > 0 ? (i0 + 63) / 64 : 1;
-  hipLaunchKernelGGL(k_recover_step, dim3(gx, nsub), dim3(256), 0, s, d_subs, invL, invoff, y, z,
-                     yoff, i0, nb);
+  if (fp32)
+    hipLaunchKernelGGL(k_recover_step<float>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
+                       (const float *)invL, invoff, y, z, yoff, i0, nb);
+  else
+    hipLaunchKernelGGL(k_recover_step<double>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
+                       (const double *)invL, invoff, y, z, yoff, i0, nb);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------- mixed-precision refinement
+// R = f - K u on every subdomain's local system (CSR order, FP64).
+__global__ void k_local_residual(const SubDev *subs, const double *u, const int64_t *uoff,
+                                 double *R) {
+  const SubDev S = subs[blockIdx.y];
+  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  if (row >= S.n_csr) return;
+  const double *us = u + uoff[blockIdx.y];
+  double s = S.rhs[row];
+  for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) s -= S.vals[q] * us[S.indices[q]];
+  R[uoff[blockIdx.y] + row] = s;
+}
+
+hipError_t local_residual(const SubDev *d_subs, const double *u, const int64_t *uoff, double *R,
+                          int nsub, int max_rows, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_local_residual, dim3((max_rows + 255) / 256, nsub), dim3(256), 0, s, d_subs,
+                     u, uoff, R);
+  return hipGetLastError();
+}
+
+// y[pos[i]] = R[i] (dense order), pressures rotated by the reflector H;
+// r0 = sum of the (unrotated) pressure residuals.  One block per subdomain.
+__global__ void k_residual_to_dense(const SubDev *subs, const double *R, const int64_t *roff,
+                                    double *y, const int64_t *yoff, double *r0) {
+  const SubDev S = subs[blockIdx.x];
+  const double *Rs = R + roff[blockIdx.x];
+  double *ys = y + yoff[blockIdx.x];
+  __shared__ double red[16];
+  double vr = 0.0, sr = 0.0;
+  for (int i = threadIdx.x; i < S.n_csr; i += blockDim.x) {
+    const int p = S.pos[i];
+    ys[p] = Rs[i];
+    if (p >= S.nv && p < S.nv + S.nel) {
+      vr += S.hv[p - S.nv] * Rs[i];
+      sr += Rs[i];
+    }
+  }
+  vr = block_sum(vr, red);
+  sr = block_sum(sr, red);
+  __syncthreads();
+  const double tau = S.hv[S.nel];
+  for (int q = threadIdx.x; q < S.nel; q += blockDim.x) ys[S.nv + q] -= tau * S.hv[q] * vr;
+  if (threadIdx.x == 0) r0[blockIdx.x] = sr;
+}
+
+hipError_t residual_to_dense(const SubDev *d_subs, const double *R, const int64_t *roff,
+                             double *y, const int64_t *yoff, double *r0, int nsub, int max_rows,
+                             hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  hipLaunchKernelGGL(k_residual_to_dense, dim3(nsub), dim3(256), 0, s, d_subs, R, roff, y, yoff, r0);
+  return hipGetLastError();
+}
+
+// Forward substitution step for block [i0, i0+b) of L (all rows below the
+// block, interface rows included): z_i = inv(L_ii) y_i;
+// y_r -= sum_c L[r, i0+c] z_c for r in [i0+b, N-1).  One thread per row.
+template <typename T>
+__global__ __launch_bounds__(256) void k_forward_step(const SubDev *subs, const T *invL,
+                                                      const int64_t *invoff, double *y, double *z,
+                                                      const int64_t *yoff, int i0, int nb) {
+  const SubDev S = subs[blockIdx.y];
+  if (i0 >= S.e) return;
+  const int b = min(nb, S.e - i0);
+  double *ys = y + yoff[blockIdx.y];
+  double *zs = z + yoff[blockIdx.y];
+  __shared__ double yi[64], zi[64];
+  const T *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
+  if (threadIdx.x < b) yi[threadIdx.x] = ys[i0 + threadIdx.x];
+  __syncthreads();
+  if (threadIdx.x < b) {
+    const int r = threadIdx.x;
+    double s = 0.0;  // (inv y)_r = sum_{c <= r} inv[r][c] y_c
+    for (int c = 0; c <= r; ++c) s += (double)inv[r + c * nb] * yi[c];
+    zi[r] = s;
+    if (blockIdx.x == 0) zs[i0 + r] = s;
+  }
+  __syncthreads();
+  const int r = i0 + b + blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= S.N - 1) return;
+  const auto Wb = gptr(Wp<T>(S));
+  double s = 0.0;
+  for (int c = 0; c < b; ++c) s += (double)Wb[(int64_t)r + (int64_t)(i0 + c) * S.ld] * zi[c];
+  ys[r] -= s;
+}
+
+hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *invoff, double *y,
+                        double *z, const int64_t *yoff, int nsub, int i0, int nb, int max_N,
+                        bool fp32, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  const int rows = max_N - i0;
+  const int gx = rows > 0 ? (rows + 255) / 256 : 1;
+  if (fp32)
+    hipLaunchKernelGGL(k_forward_step<float>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
+                       (const float *)invL, invoff, y, z, yoff, i0, nb);
+  else
+    hipLaunchKernelGGL(k_forward_step<double>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
+                       (const double *)invL, invoff, y, z, yoff, i0, nb);
+  return hipGetLastError();
+}
+
+// y2_j = d_j z_j - sum_l L[e+1+l, j] dx[gid_l] over the eliminated columns:
+// the right-hand side of L_II^T du_I = y2 (the interior correction).
+template <typename T>
+__global__ void k_back_rhs(const SubDev *subs, const double *z, const double *dx, double *y2,
+                           const int64_t *yoff) {
+  const SubDev S = subs[blockIdx.y];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const int j = blockIdx.x * (blockDim.x >> 6) + w;
+  if (j >= S.e) return;
+  const auto col = gptr(Wp<T>(S) + (int64_t)j * S.ld + (S.e + 1));
+  double s = 0.0;
+  if (dx)
+    for (int r = l; r < S.ng; r += 64) s += (double)col[r] * dx[S.gidl[r]];
+  s = warp_sum(s);
+  if (l == 0) {
+    const double d = (j < S.nv) ? 1.0 : -1.0;
+    y2[yoff[blockIdx.y] + j] = d * z[yoff[blockIdx.y] + j] - s;
+  }
+}
+
+hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
+                    const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s) {
+  if (!nsub) return hipSuccess;
+  dim3 g((max_e + 3) / 4, nsub);
+  if (fp32)
+    hipLaunchKernelGGL(k_back_rhs<float>, g, dim3(256), 0, s, d_subs, z, dx, y2, yoff);
+  else
+    hipLaunchKernelGGL(k_back_rhs<double>, g, dim3(256), 0, s, d_subs, z, dx, y2, yoff);
   return hipGetLastError();
 }
 

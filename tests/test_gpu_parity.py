@@ -93,10 +93,20 @@ def test_batched_ldl_reports_wrong_signed_pivot(vb):
     assert info.item() == 1  # first column
 
 
+_PROBLEMS = {}
+
+
+def _problem(name):
+    """Workload and oracle, built once per module for both precisions."""
+    if name not in _PROBLEMS:
+        wl, meta = make_workload(name, workers=1)
+        _PROBLEMS[name] = (wl, meta, OracleBDDC(wl))
+    return _PROBLEMS[name]
+
+
 @pytest.fixture(scope="module", params=["c1", "t8j", "t12"])
 def case(request, vb):
-    wl, meta = make_workload(request.param, workers=1)
-    o = OracleBDDC(wl)
+    wl, meta, o = _problem(request.param)
     ctx = vb.vb_create(tol=1e-8)
     vb.vb_assemble(ctx, wl)
     vb.vb_setup(ctx)
@@ -180,3 +190,64 @@ def test_interior_recovery_parity(vb, case):
         both_o = np.concatenate([uI, c])
         assert _rel(both_g, both_o) < 1e-10
         assert _rel(u[kind == 1], xo[sd["gid"][kind == 1]]) < 1e-15
+
+
+# ------------------------------------------------------------ mixed precision
+# FP32 local factors and Schur operators with FP64 refinement.  The refined
+# solution is the FP64 one: the outer residual is formed in FP64 from the
+# sparse local systems, so the tolerance is the FP64 path's (1e-10 relative
+# against the oracle solved to 1e-13), not an FP32 one.
+
+@pytest.fixture(scope="module", params=["c1", "t8j", "t12"])
+def mixed_case(request, vb):
+    wl, meta, o = _problem(request.param)
+    ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12)
+    vb.vb_assemble(ctx, wl)
+    vb.vb_setup(ctx)
+    yield request.param, wl, meta, o, ctx
+    vb.vb_destroy(ctx)
+
+
+def test_mixed_solution_parity(vb, mixed_case):
+    name, wl, meta, o, ctx = mixed_case
+    n = vb.vb_interface_size(ctx)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = vb.vb_pcg_solve(ctx, x)
+    torch.cuda.synchronize()
+    xg = x.cpu().numpy()
+    assert 1 <= info["refinement_steps"] <= 12, info
+    assert info["true_rel_residual"] <= 1e-12
+    # FP64 interface residual of the refined solution, on the oracle's operator
+    g = o.rhs()
+    assert np.linalg.norm(g - o.apply_S(xg)) <= 1e-10 * np.linalg.norm(g)
+    xo, _ = pcg(o.apply_S, o.apply_M, g, tol=1e-13)
+    assert _rel(xg, xo) < 1e-10, _rel(xg, xo)
+
+
+def test_mixed_interior_recovery_parity(vb, mixed_case):
+    name, wl, meta, o, ctx = mixed_case
+    xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-12)
+    xd = _dev(xo)
+    rec = o.recover(xo)
+    for s in (0, len(wl["subs"]) - 1):
+        sd = wl["subs"][s]
+        u = vb.vb_get_local_solution(ctx, xd, s, len(sd["kind"]))
+        kind = sd["kind"]
+        uI, c = rec[s]
+        both_g = np.concatenate([u[kind == 0], u[kind == 2]])
+        both_o = np.concatenate([uI, c])
+        assert _rel(both_g, both_o) < 1e-10
+        assert _rel(u[kind == 1], xo[sd["gid"][kind == 1]]) < 1e-15
+
+
+def test_mixed_operators_are_fp32_roundings(vb, mixed_case):
+    """S_hat from the FP32 factorisation differs from the FP64 one by FP32
+    rounding amplified by the local conditioning, and is not identical."""
+    name, wl, meta, o, ctx = mixed_case
+    n = vb.vb_interface_size(ctx)
+    x = np.random.default_rng(3).standard_normal(n)
+    y = torch.zeros(n, dtype=torch.float64, device=DEV)
+    vb.vb_schur_apply(ctx, _dev(x), y)
+    torch.cuda.synchronize()
+    d = _rel(y.cpu().numpy(), o.apply_S(x))
+    assert 1e-12 < d < 1e-3, d
