@@ -4,7 +4,10 @@ A solve runs from vb_setup entry (the subdomain matrices already resident in
 device memory) through PCG to a 1e-8 relative residual and the interior
 recovery of every subdomain.  The workload (synthetic, seeded) is the
 32^3 jittered-cube configuration: divergence-free VEM k=2, nu=1, 4x4x4
-subdomains, vertex + edge + face primal constraints, deluxe scaling, FP64.
+subdomains, vertex + edge + face primal constraints, deluxe scaling.
+By default both paths are timed: FP64, and mixed (FP32 local factors with
+FP64 refinement); `value` is the mixed one, and the mixed solution's FP64
+interface residual is checked on the FP64 operator.
 
 Prints one JSON line (see the design doc for the fields).
 """
@@ -24,7 +27,10 @@ WORKLOADS = {
     "c1": "8^3 cube, VEM k=2, nu=1, 2x2x2 subdomains, vertex+edge+flux, deluxe",
 }
 PEAK_FP64_TFLOPS = 78.6
+PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PRECISION_NAMES = {"fp64": "fp64",
+                   "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
 
 
 def log(msg):
@@ -67,6 +73,8 @@ def main():
     ap.add_argument("--cache", default=None, help="workload .npz (generated if missing)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1)
+    ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
+                    help="both: time the FP64 path and the mixed path; value = mixed")
     ap.add_argument("--prepare-only", action="store_true",
                     help="generate and store the workload (--cache) and exit")
     args = ap.parse_args()
@@ -99,75 +107,118 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     dev = torch.device("cuda:0")
     stream = torch.cuda.Stream(device=dev)
-    ctx = vb.vb_create(tol=1e-8, stream=stream.cuda_stream, profile=1)
-    vb.vb_assemble(ctx, wl)
-    n = vb.vb_interface_size(ctx)
+    n = None
     nloc = sum(len(sd["kind"]) for sd in wl["subs"])
-    x = torch.zeros(n, dtype=torch.float64, device=dev)
-    u = torch.zeros(nloc, dtype=torch.float64, device=dev)
+    runs = {}
+    order = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    for prec in order:
+        code = vb.VB_PREC_FP64 if prec == "fp64" else vb.VB_PREC_MIXED
+        ctx = vb.vb_create(precision=code, tol=1e-8, stream=stream.cuda_stream, profile=1)
+        vb.vb_assemble(ctx, wl)
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=dev)
+        u = torch.zeros(nloc, dtype=torch.float64, device=dev)
 
-    def solve():
-        vb.vb_setup(ctx)
-        x.zero_()
-        info = vb.vb_pcg_solve(ctx, x)
-        vb.vb_recover_all(ctx, x, u)
-        return info
+        def solve():
+            vb.vb_setup(ctx)
+            x.zero_()
+            info = vb.vb_pcg_solve(ctx, x)
+            vb.vb_recover_all(ctx, x, u)
+            return info
 
-    with torch.cuda.stream(stream):
-        for w in range(args.warmup):
-            info = solve()
+        with torch.cuda.stream(stream):
+            for w in range(args.warmup):
+                info = solve()
+                stream.synchronize()
+                log("%s warmup %d: %d iterations (%d refinement steps), setup %.1f ms, solve %.1f ms"
+                    % (prec, w, info["iterations"], info["refinement_steps"], info["setup_ms"],
+                       info["solve_ms"]))
+            vb.vb_kernel_stats(ctx, 0, reset=True)
+            vb.vb_kernel_stats(ctx, 1, reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            infos = []
+            for k in range(args.steps):
+                infos.append(solve())
             stream.synchronize()
-            log("warmup %d: %d iterations, setup %.1f ms, pcg %.1f ms"
-                % (w, info["iterations"], info["setup_ms"], info["solve_ms"]))
-        vb.vb_kernel_stats(ctx, 0, reset=True)
-        vb.vb_kernel_stats(ctx, 1, reset=True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        infos = []
-        for k in range(args.steps):
-            infos.append(solve())
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+        dt = t1 - t0
+        ldl = vb.vb_kernel_stats(ctx, 0)
+        gmv = vb.vb_kernel_stats(ctx, 1)
+        last = infos[-1]
+        log("%s: timed %d solves in %.3f s: %d iterations, residual %.2e"
+            % (prec, args.steps, dt, last["iterations"], last["true_rel_residual"]))
+        runs[prec] = dict(ctx=ctx, x=x, dt=dt, ldl=ldl, gmv=gmv, info=last)
+    # ---- accuracy of the mixed solution against the FP64 operator and solution
+    check = {}
+    if "mixed" in runs and "fp64" in runs:
+        c64 = runs["fp64"]["ctx"]
+        xm, x64 = runs["mixed"]["x"], runs["fp64"]["x"]
+        g = torch.zeros(n, dtype=torch.float64, device=dev)
+        y = torch.zeros(n, dtype=torch.float64, device=dev)
+        with torch.cuda.stream(stream):
+            vb.vb_rhs(c64, g)
+            vb.vb_schur_apply(c64, xm, y)
         stream.synchronize()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-    dt = t1 - t0
-    ldl = vb.vb_kernel_stats(ctx, 0)
-    gmv = vb.vb_kernel_stats(ctx, 1)
-    vb.vb_destroy(ctx)
-    last = infos[-1]
-    log("timed %d solves in %.3f s: %d iterations, true residual %.2e"
-        % (args.steps, dt, last["iterations"], last["true_rel_residual"]))
-    assert last["true_rel_residual"] <= 1e-8 * 1.01, last
-    achieved = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
-    gbs = gmv["work"] / (gmv["total_ms"] * 1e-3) / 1e9 if gmv["total_ms"] > 0 else None
+        check = {"fp64_interface_rel_residual": float(torch.linalg.norm(g - y) / torch.linalg.norm(g)),
+                 "rel_diff_vs_fp64_solution": float(torch.linalg.norm(xm - x64) / torch.linalg.norm(x64))}
+        log("mixed vs fp64: %s" % check)
+        assert check["fp64_interface_rel_residual"] <= 1e-8 * 1.01, check
+    for r in runs.values():
+        vb.vb_destroy(r["ctx"])
+    head = "mixed" if "mixed" in runs else "fp64"
+    R = runs[head]
+    if head == "fp64":
+        assert R["info"]["true_rel_residual"] <= 1e-8 * 1.01, R["info"]
+    peak = PEAK_FP64_TFLOPS if head == "fp64" else PEAK_FP32_TFLOPS
+
+    def roof(r, pk, dtype):
+        ldl = r["ldl"]
+        a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
+        return {"bound": "mfma",
+                "kernel": "k_ldl_update_wide<%s> (rank-256 trailing update of the dense LDL^T)" % dtype,
+                "achieved": a, "peak": pk, "unit": "TFLOP/s", "frac": (a / pk) if a else None,
+                "traffic": None, "launches": ldl["launches"],
+                "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
+
+    def gemv(r):
+        g = r["gmv"]
+        b = g["work"] / (g["total_ms"] * 1e-3) / 1e9 if g["total_ms"] > 0 else None
+        return {"kernel": "k_gemv_t (S_hat p, bordered local Schur GEMV)", "bound": "hbm",
+                "achieved": b, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                "frac": (b / PEAK_HBM_GBS) if b else None, "launches": g["launches"],
+                "avg_launch_ms": g["total_ms"] / max(g["launches"], 1)}
+
+    def summary(r):
+        i = r["info"]
+        return {"solves_per_s": args.steps / r["dt"], "ms_per_step": 1e3 * r["dt"] / args.steps,
+                "iterations": i["iterations"], "refinement_steps": i["refinement_steps"],
+                "rel_residual": i["true_rel_residual"], "lambda_min": i["lambda_min"],
+                "lambda_max": i["lambda_max"], "setup_ms": i["setup_ms"], "solve_ms": i["solve_ms"]}
+
     out = {
         "metric": "PCG+BDDC solves/s at 1e-8 rel. residual, mixed/batched vs FP64 GPU",
-        "value": args.steps / dt,
+        "value": args.steps / R["dt"],
         "unit": "solves/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": 1e3 * dt / args.steps,
+        "ms_per_step": 1e3 * R["dt"] / args.steps,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if head == "fp64" else "f32+f64",
         "data": "synthetic",
-        "config": {"workload": args.config + ": " + WORKLOADS[args.config], "precision": "fp64",
-                   "subdomains": nsub, "interface_unknowns": n},
-        "roofline": {"bound": "mfma", "kernel": "k_ldl_update_wide (rank-256 trailing update of the dense LDL^T)",
-                     "achieved": achieved, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": (achieved / PEAK_FP64_TFLOPS) if achieved else None,
-                     "traffic": None, "launches": ldl["launches"],
-                     "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)},
-        "iteration_kernel": {"kernel": "k_gemv_t (S_hat p, bordered local Schur GEMV)",
-                             "bound": "hbm", "achieved": gbs, "peak": PEAK_HBM_GBS,
-                             "unit": "GB/s", "frac": (gbs / PEAK_HBM_GBS) if gbs else None,
-                             "launches": gmv["launches"],
-                             "avg_launch_ms": gmv["total_ms"] / max(gmv["launches"], 1)},
-        "iterations": last["iterations"],
-        "true_rel_residual": last["true_rel_residual"],
-        "lambda_min": last["lambda_min"], "lambda_max": last["lambda_max"],
-        "setup_ms": last["setup_ms"], "pcg_ms": last["solve_ms"],
+        "config": {"workload": args.config + ": " + WORKLOADS[args.config],
+                   "precision": PRECISION_NAMES[head], "subdomains": nsub,
+                   "interface_unknowns": n},
+        "roofline": roof(R, peak, "double" if head == "fp64" else "float"),
+        "iteration_kernel": gemv(R),
+        "runs": {k: summary(v) for k, v in runs.items()},
+        "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
+        "mixed_accuracy": check or None,
+        "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "double") if "fp64" in runs else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
