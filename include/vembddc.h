@@ -70,7 +70,18 @@ typedef struct vb_options {
   void *stream;      /* hipStream_t for all work; NULL = default stream */
   int profile;       /* nonzero: time every launch of the dominant kernels with HIP
                         events on `stream` (see vb_kernel_stats) */
+  double adaptive_theta; /* > 0: adaptive face constraints (Sec. 6) with tolerance
+                            theta (nu_tol): eigenvalues below 1/theta of every face
+                            pencil add primal rows; 0 = the given constraints only */
 } vb_options;
+
+/* One face of the adaptive coarse space (Sec. 6), as selected by vb_setup. */
+typedef struct vb_face_info {
+  int entity;        /* entity index (vb_assemble order) */
+  int sub_i, sub_j;  /* the two subdomains sharing the face */
+  int n_dual;        /* dual coordinates of the face in the minimal primal space */
+  int n_selected;    /* eigenvalues below 1/theta (= new primal rows) */
+} vb_face_info;
 
 /* Device-time statistics of one kernel, accumulated over its launches. */
 typedef struct vb_kernel_stat {
@@ -176,6 +187,14 @@ int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_h
  * VB_PREC_MIXED: the FP32-factor recovery is followed by FP64 refinement of
  * the interior equations with the interface data fixed at x_dev. */
 int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
+
+/* Adaptive coarse space of the last vb_setup (Sec. 6): fills up to
+ * max_faces entries of `faces` (may be NULL) and, in face order, the selected
+ * eigenvalues (ascending per face, n_selected each) into up to max_eigs
+ * entries of `eigs` (may be NULL; a face with every eigenvalue selected
+ * contributes none).  Returns the number of faces (>= 0), or VB_ERR_STATE
+ * before setup. */
+int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_eigs, double *eigs);
 
 /* Statistics of the kernels timed with vb_options.profile: which = 0 the
  * super-panel trailing update of the dense LDL^T (the setup's dominant

@@ -14,7 +14,10 @@ data the hot path consumes plus the generator objects (for tests).
       (centres uniform, seed 0), 4x4x4 subdomains
   c5  one of 32 problems: 24^3, plane jitter 0.15h, k=3, 3x3x3 subdomains,
       nu constant per subdomain, log-uniform in [1e-3, 1e3] (seed p)
-Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3).
+Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3);
+adaptive cases: t6f (6^3 jittered, 3x3x3: a floating centre subdomain),
+t8f (8^3 jittered, 4x4x4: faces between two floating subdomains),
+t12s (12^3, 3x3x3, 4 sinkers of radius 0.25 with nu=1e4).
 """
 import numpy as np
 
@@ -52,6 +55,10 @@ RECIPES = {
     "t8j": dict(n=8, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
     "t12": dict(n=12, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),
     "t16": dict(n=16, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
+    "t6f": dict(n=6, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),
+    "t8f": dict(n=8, jitter=0.15, k=2, parts=(4, 4, 4), cons=FULL),
+    "t12s": dict(n=12, jitter=0.0, k=2, parts=(3, 3, 3), cons=FULL, sinkers=True,
+                 sinker_n=4, sinker_r=0.25),
 }
 
 
@@ -66,7 +73,8 @@ def make_workload(name, seed=0, workers=None, **over):
         cuts = regular_cuts(r["n"], r["parts"])
     nu = 1.0
     if r.get("sinkers"):
-        nu = sinker_viscosity(mesh, seed=seed)
+        nu = sinker_viscosity(mesh, n_sinkers=r.get("sinker_n", 8), radius=r.get("sinker_r", 0.1),
+                              seed=seed)
     if r.get("nu_per_sub"):
         nu = subdomain_viscosity(mesh, cuts, seed)
     pb = Problem(mesh, r["k"], nu, workers=workers)

@@ -43,7 +43,18 @@ def schur_onto(S, keep, rtol=PINV_RTOL):
     return 0.5 * (R + R.T)
 
 
-def face_pencil(bddc, e):
+def schur_onto_cholesky(S, keep):
+    """The same Schur complement with the eliminated block factored by
+    Cholesky (it is positive definite whenever the rigid-mode traces on
+    `keep` are independent): a second FP64 evaluation of the formula."""
+    keep = np.asarray(keep)
+    other = np.setdiff1d(np.arange(S.shape[0]), keep)
+    c = sla.cho_factor(S[np.ix_(other, other)])
+    R = S[np.ix_(keep, keep)] - S[np.ix_(other, keep)].T @ sla.cho_solve(c, S[np.ix_(other, keep)])
+    return 0.5 * (R + R.T)
+
+
+def face_pencil(bddc, e, cholesky=False):
     """(At_par, A_par, subs) for face entity e in the current basis."""
     dual = bddc.de_idx[e]
     subs = bddc.ent_subs[e]
@@ -52,7 +63,7 @@ def face_pencil(bddc, e):
         L = bddc.loc[k]
         pos = np.array([np.nonzero(L.gid == d)[0][0] for d in dual], dtype=np.int64)
         A.append(L.St[np.ix_(pos, pos)])
-        At.append(schur_onto(L.St, pos))
+        At.append(schur_onto_cholesky(L.St, pos) if cholesky else schur_onto(L.St, pos))
     return parallel_sum(At[0], At[1]), parallel_sum(A[0], A[1]), subs
 
 

@@ -24,7 +24,12 @@ VB_SCALING_DELUXE, VB_SCALING_COUNTING = 0, 1
 class vb_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("scaling", C.c_int), ("tol", C.c_double),
                 ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
-                ("stream", C.c_void_p), ("profile", C.c_int)]
+                ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double)]
+
+
+class vb_face_info(C.Structure):
+    _fields_ = [("entity", C.c_int), ("sub_i", C.c_int), ("sub_j", C.c_int),
+                ("n_dual", C.c_int), ("n_selected", C.c_int)]
 
 
 class vb_kernel_stat(C.Structure):
@@ -81,6 +86,8 @@ def load():
         "vb_recover_all": (C.c_int, [P, P, P]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
+        "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
+                                       C.POINTER(C.c_double)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -93,7 +100,8 @@ def load():
 def exported_symbols():
     return ["vb_create", "vb_destroy", "vb_last_error", "vb_assemble", "vb_setup",
             "vb_interface_size", "vb_rhs", "vb_schur_apply", "vb_apply", "vb_pcg_solve",
-            "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl", "vb_kernel_stats"]
+            "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl", "vb_kernel_stats",
+            "vb_adaptive_info"]
 
 
 class VBError(RuntimeError):
@@ -123,9 +131,10 @@ def _check(ctx, rc):
 
 # ------------------------------------------------------------- C-ABI names
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
-              svd_tol=1e-10, panel=0, stream=None, profile=0):
+              svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0):
     lib = load()
-    opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile)
+    opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
+                     adaptive_theta)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -214,3 +223,29 @@ def vb_kernel_stats(ctx, which, reset=False):
     st = vb_kernel_stat()
     _check(ctx, load().vb_kernel_stats(ctx, int(which), int(bool(reset)), C.byref(st)))
     return {"launches": st.launches, "total_ms": st.total_ms, "work": st.work}
+
+
+def vb_adaptive_info(ctx):
+    """List of per-face dicts (entity, sub_i, sub_j, n_dual, n_selected,
+    eigenvalues) of the adaptive coarse space of the last setup."""
+    lib = load()
+    nf = lib.vb_adaptive_info(ctx, 0, None, 0, None)
+    if nf < 0:
+        _check(ctx, nf)
+    faces = (vb_face_info * max(nf, 1))()
+    rc = lib.vb_adaptive_info(ctx, nf, faces, 0, None)
+    if rc < 0:
+        _check(ctx, rc)
+    ne = sum(faces[i].n_selected for i in range(nf) if faces[i].n_selected < faces[i].n_dual)
+    eigs = np.zeros(max(ne, 1))
+    rc = lib.vb_adaptive_info(ctx, nf, faces, ne, eigs.ctypes.data_as(C.POINTER(C.c_double)))
+    if rc < 0:
+        _check(ctx, rc)
+    out, o = [], 0
+    for i in range(nf):
+        f = faces[i]
+        k = f.n_selected if f.n_selected < f.n_dual else 0
+        out.append({"entity": f.entity, "subs": (f.sub_i, f.sub_j), "n_dual": f.n_dual,
+                    "n_selected": f.n_selected, "eigenvalues": eigs[o: o + k].copy()})
+        o += k
+    return out

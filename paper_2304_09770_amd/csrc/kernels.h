@@ -169,4 +169,47 @@ hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *i
 hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
                     const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s);
 
+// ---- adaptive face eigenproblems (dense symmetric eigen-solver pieces)
+struct EigJob {
+  double *A;      // n x n full symmetric (column-major); reflectors stored below the subdiagonal
+  int64_t ld;
+  int n;
+  int ncols;      // eigenvectors to back-transform
+  double *d, *e, *tau;  // tridiagonal diagonal, off-diagonal, reflector factors (length n)
+  double *Z;      // n x mcap eigenvectors
+  int64_t ldz;
+  double *lam;    // mcap eigenvalues below sigma, ascending
+  int *count;     // number of eigenvalues below sigma
+  double sigma;
+};
+struct RowJob {
+  const double *L;  // n x n lower triangular
+  int64_t ld;
+  int n, ncols;
+  const double *Z;
+  int64_t ldz;
+  double *R;
+  int64_t ldr;
+};
+struct FaceTJob {
+  double *A;      // rows [off, off + n_E) of columns [0, ncols)
+  int64_t ld;
+  int ncols, off;
+  const EntDev *ent;
+  int dir;        // +1: T_E^T, -1: T_E
+};
+struct SymJob {
+  double *A;
+  int64_t ld;
+  int n;
+};
+hipError_t tridiag(const EigJob *d_jobs, int njobs, int max_n, hipStream_t s);
+hipError_t tridiag_eig(const EigJob *d_jobs, int njobs, int max_n, int mcap, hipStream_t s);
+hipError_t back_transform(const EigJob *d_jobs, int njobs, hipStream_t s);
+hipError_t lower_times(const RowJob *d_jobs, int njobs, int max_n, int max_cols, hipStream_t s);
+hipError_t face_transform(const FaceTJob *d_jobs, int njobs, int max_cols, hipStream_t s);
+hipError_t sym_average(const SymJob *d_jobs, int njobs, int max_n, hipStream_t s);
+hipError_t shift_diag(const SymJob *d_jobs, int njobs, double rel, hipStream_t s);
+hipError_t normalize_cols(const RowJob *d_jobs, int njobs, int max_cols, hipStream_t s);
+
 }  // namespace vb

@@ -65,6 +65,10 @@ struct EntH {
   int64_t *d_gids = nullptr;
   double *d_con = nullptr, *d_V = nullptr, *d_tau = nullptr, *d_work = nullptr;
   int *d_rank = nullptr;
+  // the given constraints (a setup may append adaptive rows to a copy)
+  int ncon0 = 0;
+  std::vector<double> con0;
+  double *d_con0 = nullptr, *d_V0 = nullptr, *d_tau0 = nullptr, *d_work0 = nullptr;
   // deluxe
   double *Daug = nullptr;
   int64_t Dld = 0;
@@ -102,7 +106,10 @@ struct vb_ctx {
   SubDev *d_subdev = nullptr;
   EntDev *d_entdev = nullptr;
   std::vector<SubDev> subdev;
-  std::vector<EntDev> entdev;
+  std::vector<EntDev> entdev, entdev0;
+  // adaptive coarse space of the last setup
+  std::vector<vb_face_info> face_info;
+  std::vector<double> face_eigs;
 
   // iteration structures
   int nC = 0, nCS = 0;
@@ -428,6 +435,15 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     D.work = H.d_work;
   }
   CHK(ctx->upload(&ctx->d_entdev, ctx->entdev));
+  ctx->entdev0 = ctx->entdev;
+  for (auto &H : ctx->ents) {
+    H.ncon0 = H.ncon;
+    H.con0 = H.con;
+    H.d_con0 = H.d_con;
+    H.d_V0 = H.d_V;
+    H.d_tau0 = H.d_tau;
+    H.d_work0 = H.d_work;
+  }
   ctx->state = 1;
   return VB_OK;
 }
@@ -494,6 +510,485 @@ static int check_info(vb_ctx *ctx, int count, int code, const char *what) {
   return VB_OK;
 }
 
+
+static void *x_block(vb_ctx *ctx, const SubH &S) {
+  return (char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
+}
+
+// Householder QR with column pivoting of every entity's constraint rows.
+static int primal_qr(vb_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  const int nE = (int)ctx->ents.size();
+  int rmax = 1;
+  for (auto &H : ctx->ents) rmax = std::max(rmax, std::min(H.ncon, H.n));
+  CHK(entity_qr(ctx->d_entdev, nE, rmax, ctx->opt.svd_tol, st));
+  std::vector<int> rk(nE);
+  if (nE) {
+    CHK(hipMemcpyAsync(rk.data(), ctx->info + 4 * ctx->nS + 64, nE * sizeof(int),
+                       hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+  }
+  for (int e = 0; e < nE; ++e) ctx->ents[e].rank = rk[e];
+  return VB_OK;
+}
+
+template <typename J>
+static int upload_jobs(vb_ctx *ctx, J **d, const std::vector<J> &h) {
+  CHK(ctx->upload(d, h, true));
+  return VB_OK;
+}
+
+// Adaptive face constraints (Sec. 6), one pass over the faces in the bases
+// of the given constraints.  Per face F (subdomains i, j), with n = the dual
+// coordinates of F:
+//  1. P_k = the transformed S_Gamma^(k) with F last (gathered from X, the
+//     face's reflectors applied to its rows and columns): A_k = its dual
+//     block; the partial LDL^T of P_k over every other coordinate leaves
+//     At_k (the Schur complement onto F_Delta).
+//  2. Parallel sums as Schur complements: the trailing block of
+//     [[X+Y, Y], [Y, Y]] after n eliminations is X:Y (A: exact; At: the sum
+//     shifted by 1e-13 max|diag| so that a common kernel of floating
+//     neighbours stays factorable; the product X(..)^-1 Y annihilates it).
+//  3. B = A_i:A_j = L L^T and W = L^-T from the LDL^T of [[B, .], [I, 0]];
+//     C = W^T At_par W (two MFMA GEMMs), symmetrised.
+//  4. C = Q T Q^T, eigenvalues of T below 1/theta by bisection, their
+//     eigenvectors by inverse iteration, y = Q z.
+//  5. New rows (A_i:A_j) psi = L y on F_Delta, embedded in the face block and
+//     taken back to the face's own coordinates with T_F, unit norm, and
+//     appended to the face's constraint rows.
+static int adaptive_stage(vb_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  const bool f32 = ctx->fp32;
+  const double sigma = 1.0 / ctx->opt.adaptive_theta;
+  struct Face {
+    int e, nF, rank, nd;
+    int s[2], off[2];
+    int64_t ld2, o_qb, o_qa, o_qa2, o_m, o_wt, o_t2, o_c, o_d, o_e, o_tau, o_z, o_lam, o_r;
+    int mcap;
+  };
+  std::vector<Face> faces;
+  for (int e = 0; e < (int)ctx->ents.size(); ++e) {
+    EntH &H = ctx->ents[e];
+    if (H.kind != VB_ENT_FACE || H.subs.size() != 2 || H.n - H.rank <= 0) continue;
+    Face f{};
+    f.e = e;
+    f.nF = H.n;
+    f.rank = H.rank;
+    f.nd = H.n - H.rank;
+    for (int k = 0; k < 2; ++k) {
+      SubH &S = ctx->subs[H.subs[k]];
+      f.s[k] = H.subs[k];
+      int qq = (int)(std::find(S.ents.begin(), S.ents.end(), e) - S.ents.begin());
+      f.off[k] = S.ent_off[qq];
+    }
+    faces.push_back(f);
+  }
+  if (faces.empty()) return VB_OK;
+  const int nf = (int)faces.size();
+  {  // the factorisation left S_Gamma^(k) in the lower triangle of X only
+    std::vector<void *> m;
+    std::vector<int64_t> ld;
+    std::vector<int32_t> n;
+    for (auto &S : ctx->subs) {
+      m.push_back(x_block(ctx, S));
+      ld.push_back(S.ld);
+      n.push_back(S.ng + 1);
+    }
+    int rc = run_symm(ctx, m, ld, n, false, f32);
+    if (rc) return rc;
+  }
+  // ---- per-face FP64 arena
+  int64_t tot = 0;
+  int max_nd = 0, max_2nd = 0;
+  for (auto &f : faces) {
+    const int n = f.nd;
+    f.mcap = std::min(n, 256);
+    f.ld2 = round_up(2 * n, 32);
+    auto take = [&](int64_t cnt) {
+      int64_t o = tot;
+      tot += round_up(cnt, 32);
+      return o;
+    };
+    f.o_qb = take(f.ld2 * 2 * n);
+    f.o_qa = take(f.ld2 * 2 * n);
+    f.o_qa2 = take(f.ld2 * 2 * n);
+    f.o_m = take(f.ld2 * 2 * n);
+    f.o_wt = take((int64_t)n * n);
+    f.o_t2 = take((int64_t)n * n);
+    f.o_c = take((int64_t)n * n);
+    f.o_d = take(n);
+    f.o_e = take(n);
+    f.o_tau = take(n);
+    f.o_z = take((int64_t)n * f.mcap);
+    f.o_lam = take(f.mcap);
+    f.o_r = take((int64_t)f.nF * n);
+    max_nd = std::max(max_nd, n);
+    max_2nd = std::max(max_2nd, 2 * n);
+  }
+  double *ar = nullptr;
+  CHK(ctx->dalloc(&ar, tot, true));
+  CHK(hipMemsetAsync(ar, 0, tot * sizeof(double), st));
+  int *iinfo = nullptr;  // LDL pivot reports (2 per face for P, 4 for the pencil) + counts
+  CHK(ctx->dalloc(&iinfo, 7 * (int64_t)nf + 1, true));
+  CHK(hipMemsetAsync(iinfo, 0, (7 * (int64_t)nf + 1) * sizeof(int), st));
+  int *cnt = iinfo + 6 * nf;
+  // ---- 1. P_k per face and side, in chunks bounded in memory
+  {
+    size_t fr = 0, totm = 0;
+    CHK(hipMemGetInfo(&fr, &totm));
+    const double budget = std::min(32.0e9, 0.5 * (double)fr);
+    size_t ci = 0;
+    int32_t *d_dualidx = nullptr;  // [0, max_nd) shifted per job through the out pointer
+    std::vector<int32_t> iota(std::max(max_nd, 1));
+    std::iota(iota.begin(), iota.end(), 0);
+    CHK(ctx->upload(&d_dualidx, iota, true));
+    double *pbuf = nullptr;
+    size_t pcap = 0;
+    while (ci < faces.size()) {
+      size_t cj = ci;
+      double bytes = 0.0;
+      while (cj < faces.size()) {
+        double b = 0.0;
+        for (int k = 0; k < 2; ++k) {
+          const SubH &S = ctx->subs[faces[cj].s[k]];
+          b += 8.0 * (double)round_up(S.ng, 32) * S.ng;
+        }
+        if (cj > ci && bytes + b > budget) break;
+        bytes += b;
+        ++cj;
+      }
+      if ((size_t)bytes > pcap) {
+        if (pbuf) CHK(hipStreamSynchronize(st));
+        CHK(ctx->dalloc(&pbuf, (size_t)(bytes / 8.0) + 64, true));
+        pcap = (size_t)bytes;
+      }
+      std::vector<GatherJob> gp, ga0, ga1, gt0, gt1;
+      std::vector<FaceTJob> ft;
+      std::vector<LdlJob<double>> lj;
+      std::vector<void *> tm;
+      std::vector<int64_t> tld;
+      std::vector<int32_t> tn;
+      int64_t po = 0, invtot = 0;
+      int maxg = 0, maxe = 0;
+      for (size_t q = ci; q < cj; ++q) {
+        const Face &f = faces[q];
+        for (int k = 0; k < 2; ++k) {
+          const SubH &S = ctx->subs[f.s[k]];
+          const int ng = S.ng;
+          const int64_t ldp = round_up(ng, 32);
+          double *P = pbuf + po;
+          po += ldp * ng;
+          std::vector<int32_t> perm;
+          perm.reserve(ng);
+          for (int l = 0; l < ng; ++l)
+            if (l < f.off[k] || l >= f.off[k] + f.nF) perm.push_back(l);
+          for (int l = 0; l < f.nF; ++l) perm.push_back(f.off[k] + l);
+          int32_t *d_perm = nullptr;
+          CHK(ctx->upload(&d_perm, perm, true));
+          gp.push_back({x_block(ctx, S), S.ld, P, ldp, d_perm, d_perm, ng, ng, 1.0, 0, f32 ? 1 : 0, 0});
+          ft.push_back({P, ldp, ng, ng - f.nF, ctx->d_entdev + f.e, +1});
+          tm.push_back(P);
+          tld.push_back(ldp);
+          tn.push_back(ng);
+          // dual block of P: rows/cols [ng - nd, ng)
+          const double *Pd = P + (ng - f.nd) + (int64_t)(ng - f.nd) * ldp;
+          double *QB = ar + f.o_qb, *QA = ar + f.o_qa;
+          const int n = f.nd;
+          if (k == 0) {
+            ga0.push_back({Pd, ldp, QB, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 0, 0, 0});
+            gt0.push_back({Pd, ldp, QA, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 0, 0, 0});
+          } else {
+            ga1.push_back({Pd, ldp, QB, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 1, 0, 0});
+            ga1.push_back({Pd, ldp, QB + n, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 0, 0, 0});
+            ga1.push_back({Pd, ldp, QB + n + (int64_t)n * f.ld2, f.ld2, d_dualidx, d_dualidx, n, n,
+                           1.0, 0, 0, 0});
+            gt1.push_back({Pd, ldp, QA, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 1, 0, 0});
+            gt1.push_back({Pd, ldp, QA + n, f.ld2, d_dualidx, d_dualidx, n, n, 1.0, 0, 0, 0});
+            gt1.push_back({Pd, ldp, QA + n + (int64_t)n * f.ld2, f.ld2, d_dualidx, d_dualidx, n,
+                           n, 1.0, 0, 0, 0});
+          }
+          const int ee = ng - n;
+          lj.push_back({P, ldp, ng, ee, ee, 0, nullptr, iinfo + 2 * q + k});
+          invtot += (int64_t)((ee + NB - 1) / NB) * NB * NB;
+          maxg = std::max(maxg, ng);
+          maxe = std::max(maxe, ee);
+        }
+      }
+      double *invs = nullptr;
+      CHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
+      int64_t io = 0;
+      for (auto &J : lj) {
+        J.invL = invs + io;
+        io += (int64_t)((J.e + NB - 1) / NB) * NB * NB;
+      }
+      int rc = run_gather(ctx, gp, maxg, maxg);
+      if (rc) return rc;
+      FaceTJob *dft = nullptr;
+      rc = upload_jobs(ctx, &dft, ft);
+      if (rc) return rc;
+      CHK(face_transform(dft, (int)ft.size(), maxg, st));
+      rc = run_symm(ctx, tm, tld, tn, true, false);
+      if (rc) return rc;
+      CHK(face_transform(dft, (int)ft.size(), maxg, st));
+      rc = run_gather(ctx, ga0, max_nd, max_nd);
+      if (!rc) rc = run_gather(ctx, ga1, max_nd, max_nd);
+      if (rc) return rc;
+      rc = run_ldl(ctx, lj, maxg, maxe);
+      if (rc) return rc;
+      {  // At_k: lower triangle of the trailing block -> full
+        std::vector<void *> m;
+        std::vector<int64_t> ld;
+        std::vector<int32_t> n;
+        for (size_t t = 0; t < tm.size(); ++t) {
+          const int nd = faces[ci + t / 2].nd;
+          const int ng = tn[t];
+          m.push_back((double *)tm[t] + (ng - nd) + (int64_t)(ng - nd) * tld[t]);
+          ld.push_back(tld[t]);
+          n.push_back(nd);
+        }
+        rc = run_symm(ctx, m, ld, n, false, false);
+        if (rc) return rc;
+      }
+      rc = run_gather(ctx, gt0, max_nd, max_nd);
+      if (!rc) rc = run_gather(ctx, gt1, max_nd, max_nd);
+      if (rc) return rc;
+      ci = cj;
+    }
+  }
+  // ---- 2. parallel sums.  At_i + At_j is singular when the two neighbours
+  // float and share rigid-mode traces on F: such faces (found by a pivot
+  // breakdown of the unshifted sum) are factorised again from a copy with the
+  // sum shifted by 1e-13 max|diag|; the kernel is annihilated by the outer
+  // factors of X (X+Y)^-1 Y either way.
+  {
+    std::vector<LdlJob<double>> lj;
+    std::vector<GatherJob> cp;
+    int32_t *d_ii = nullptr;
+    {
+      std::vector<int32_t> iota(std::max(max_2nd, 1));
+      std::iota(iota.begin(), iota.end(), 0);
+      CHK(ctx->upload(&d_ii, iota, true));
+    }
+    int64_t invtot = 0;
+    for (auto &f : faces) {
+      invtot += 4 * (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
+      cp.push_back({ar + f.o_qa, f.ld2, ar + f.o_qa2, f.ld2, d_ii, d_ii, 2 * f.nd, 2 * f.nd, 1.0,
+                    0, 0, 0});
+    }
+    int rc = run_gather(ctx, cp, max_2nd, max_2nd);
+    if (rc) return rc;
+    double *invs = nullptr;
+    CHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
+    int64_t io = 0;
+    for (int q = 0; q < nf; ++q) {
+      const Face &f = faces[q];
+      const int64_t per = (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
+      lj.push_back({ar + f.o_qb, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 2 * nf + q});
+      io += per;
+      lj.push_back({ar + f.o_qa, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 3 * nf + q});
+      io += per;
+    }
+    rc = run_ldl(ctx, lj, max_2nd, max_nd);
+    if (rc) return rc;
+    std::vector<int> hq(nf);
+    CHK(hipMemcpyAsync(hq.data(), iinfo + 3 * nf, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    std::vector<SymJob> sj;
+    std::vector<LdlJob<double>> lj2;
+    for (int q = 0; q < nf; ++q) {
+      Face &f = faces[q];
+      if (!hq[q]) continue;
+      sj.push_back({ar + f.o_qa2, f.ld2, f.nd});
+      lj2.push_back({ar + f.o_qa2, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 5 * nf + q});
+      io += (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
+      f.o_qa = f.o_qa2;
+    }
+    CHK(hipMemsetAsync(iinfo + 3 * nf, 0, nf * sizeof(int), st));
+    if (!sj.empty()) {
+      SymJob *dsj = nullptr;
+      rc = upload_jobs(ctx, &dsj, sj);
+      if (rc) return rc;
+      CHK(shift_diag(dsj, (int)sj.size(), 1e-13, st));
+      rc = run_ldl(ctx, lj2, max_2nd, max_nd);
+      if (rc) return rc;
+    }
+    // ---- 3. B = L L^T, W = L^-T; C = W^T At_par W
+    std::vector<GatherJob> gm;
+    std::vector<DiagJob> dm;
+    std::vector<LdlJob<double>> lm;
+    std::vector<void *> sm;
+    std::vector<int64_t> sld;
+    std::vector<int32_t> sn;
+    std::vector<GatherJob> gw;
+    std::vector<GemmJob<double>> g1, g2;
+    int32_t *d_dualidx = nullptr;
+    std::vector<int32_t> iota(std::max(max_nd, 1));
+    std::iota(iota.begin(), iota.end(), 0);
+    CHK(ctx->upload(&d_dualidx, iota, true));
+    for (int q = 0; q < nf; ++q) {
+      const Face &f = faces[q];
+      const int n = f.nd;
+      double *QB = ar + f.o_qb, *QA = ar + f.o_qa, *M = ar + f.o_m;
+      gm.push_back({QB + n + (int64_t)n * f.ld2, f.ld2, M, f.ld2, d_dualidx, d_dualidx, n, n, 1.0,
+                    0, 0, 0});
+      dm.push_back({M, f.ld2, n, 0, n, 1.0, 0});
+      lm.push_back({M, f.ld2, 2 * n, n, n, 0, invs + io, iinfo + 4 * nf + q});
+      io += (int64_t)((n + NB - 1) / NB) * NB * NB;
+      sm.push_back(QA + n + (int64_t)n * f.ld2);
+      sld.push_back(f.ld2);
+      sn.push_back(n);
+      // W^T[i][j] = M[n + j][i]: rows i -> i * ld2, columns j -> n + j (ldi 1)
+      std::vector<int32_t> ri(n), cj(n);
+      for (int a = 0; a < n; ++a) {
+        ri[a] = (int32_t)(a * f.ld2);
+        cj[a] = n + a;
+      }
+      int32_t *d_ri = nullptr, *d_cj = nullptr;
+      CHK(ctx->upload(&d_ri, ri, true));
+      CHK(ctx->upload(&d_cj, cj, true));
+      gw.push_back({M, 1, ar + f.o_wt, n, d_ri, d_cj, n, n, 1.0, 0, 0, 0});
+      const double *Ap = QA + n + (int64_t)n * f.ld2;
+      g1.push_back({ar + f.o_wt, Ap, ar + f.o_t2, n, f.ld2, n, n, n, n, 0, 1.0, 0.0});
+      g2.push_back({ar + f.o_t2, ar + f.o_wt, ar + f.o_c, n, n, n, n, n, n, 0, 1.0, 0.0});
+    }
+    rc = run_gather(ctx, gm, max_nd, max_nd);
+    if (!rc) rc = run_diag(ctx, dm, max_nd);
+    if (!rc) rc = run_ldl(ctx, lm, max_2nd, max_nd);
+    if (!rc) rc = run_symm(ctx, sm, sld, sn, false, false);
+    if (!rc) rc = run_gather(ctx, gw, max_nd, max_nd);
+    if (rc) return rc;
+    std::vector<int> h(6 * nf);
+    CHK(hipMemcpyAsync(h.data(), iinfo, 6 * nf * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    static const char *what[] = {"Schur complement onto F_Delta", "parallel sum of the dual minors",
+                                 "parallel sum of the Schur complements", "Cholesky of the pencil",
+                                 "shifted parallel sum of the Schur complements"};
+    for (int q = 0; q < 6 * nf; ++q)
+      if (h[q]) {
+        const int face = q < 2 * nf ? q / 2 : q % nf;
+        const int stage = q < 2 * nf ? 0 : q / nf - 1;
+        return ctx->fail(VB_ERR_NOT_SPD, std::string("adaptive: breakdown in the ") + what[stage] +
+                                             " of face entity " + std::to_string(faces[face].e));
+      }
+    GemmJob<double> *dg1 = nullptr, *dg2 = nullptr;
+    rc = upload_jobs(ctx, &dg1, g1);
+    if (!rc) rc = upload_jobs(ctx, &dg2, g2);
+    if (rc) return rc;
+    CHK(gemm_nt_batched<double>(dg1, nf, max_nd, max_nd, st));
+    CHK(gemm_nt_batched<double>(dg2, nf, max_nd, max_nd, st));
+    std::vector<SymJob> cj;
+    for (auto &f : faces) cj.push_back({ar + f.o_c, f.nd, f.nd});
+    SymJob *dcj = nullptr;
+    rc = upload_jobs(ctx, &dcj, cj);
+    if (rc) return rc;
+    CHK(sym_average(dcj, nf, max_nd, st));
+  }
+  // ---- 4. eigenpairs below sigma
+  std::vector<EigJob> ej(nf);
+  int max_mcap = 1;
+  for (int q = 0; q < nf; ++q) {
+    const Face &f = faces[q];
+    ej[q] = {ar + f.o_c, f.nd, f.nd, 0, ar + f.o_d, ar + f.o_e, ar + f.o_tau, ar + f.o_z, f.nd,
+             ar + f.o_lam, cnt + q, sigma};
+    max_mcap = std::max(max_mcap, f.mcap);
+  }
+  EigJob *dej = nullptr;
+  int rc = upload_jobs(ctx, &dej, ej);
+  if (rc) return rc;
+  CHK(tridiag(dej, nf, max_nd, st));
+  CHK(tridiag_eig(dej, nf, max_nd, max_mcap, st));
+  std::vector<int> hc(nf);
+  CHK(hipMemcpyAsync(hc.data(), cnt, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  std::vector<RowJob> rj, rn;
+  std::vector<FaceTJob> fj;
+  std::vector<DiagJob> dfull;
+  int max_cols = 0, max_nF = 0;
+  for (int q = 0; q < nf; ++q) {
+    Face &f = faces[q];
+    const int m = hc[q];
+    if (m > f.mcap && m < f.nd)
+      return ctx->fail(VB_ERR_ARG, "adaptive: " + std::to_string(m) +
+                                       " eigenvalues below 1/theta on face entity " +
+                                       std::to_string(f.e) + " (at most 256 supported)");
+    const bool full = (m >= f.nd);
+    const int cols = full ? f.nd : m;
+    ej[q].ncols = full ? 0 : m;
+    double *R = ar + f.o_r;  // nF x cols, rows [0, rank) stay zero
+    if (cols > 0) {
+      if (full)
+        dfull.push_back({R, f.nF, f.rank, 0, f.nd, 1.0, 0});
+      else
+        rj.push_back({ar + f.o_m, f.ld2, f.nd, m, ar + f.o_z, f.nd, R + f.rank, f.nF});
+      fj.push_back({R, f.nF, cols, 0, ctx->d_entdev + f.e, -1});
+      rn.push_back({nullptr, 0, f.nF, cols, nullptr, 0, R, f.nF});
+      max_cols = std::max(max_cols, cols);
+      max_nF = std::max(max_nF, f.nF);
+    }
+  }
+  rc = upload_jobs(ctx, &dej, ej);
+  if (rc) return rc;
+  CHK(back_transform(dej, nf, st));
+  if (!rj.empty()) {
+    RowJob *drj = nullptr;
+    rc = upload_jobs(ctx, &drj, rj);
+    if (rc) return rc;
+    CHK(lower_times(drj, (int)rj.size(), max_nd, max_cols, st));
+  }
+  rc = run_diag(ctx, dfull, max_nd);
+  if (rc) return rc;
+  if (!fj.empty()) {
+    FaceTJob *dfj = nullptr;
+    RowJob *drn = nullptr;
+    rc = upload_jobs(ctx, &dfj, fj);
+    if (!rc) rc = upload_jobs(ctx, &drn, rn);
+    if (rc) return rc;
+    CHK(face_transform(dfj, (int)fj.size(), max_cols, st));
+    CHK(normalize_cols(drn, (int)rn.size(), max_cols, st));
+  }
+  // ---- 5. append the rows; record the faces
+  for (int q = 0; q < nf; ++q) {
+    Face &f = faces[q];
+    EntH &H = ctx->ents[f.e];
+    const int m = hc[q];
+    const bool full = (m >= f.nd);
+    const int cols = full ? f.nd : m;
+    vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m};
+    ctx->face_info.push_back(fi);
+    if (!full && m > 0) {
+      std::vector<double> lam(m);
+      CHK(hipMemcpyAsync(lam.data(), ar + f.o_lam, m * sizeof(double), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      ctx->face_eigs.insert(ctx->face_eigs.end(), lam.begin(), lam.end());
+    }
+    if (cols == 0) continue;
+    if (H.ncon + cols > 1024)
+      return ctx->fail(VB_ERR_ARG, "adaptive: more than 1024 constraint rows on face entity " +
+                                       std::to_string(f.e));
+    std::vector<double> R((size_t)f.nF * cols);
+    CHK(hipMemcpyAsync(R.data(), ar + f.o_r, R.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    // R is nF x cols column-major: column c is row c of the constraint block
+    H.con.insert(H.con.end(), R.begin(), R.end());
+    H.ncon += cols;
+    CHK(ctx->upload(&H.d_con, H.con));
+    const int rmax = std::max(1, std::min(H.ncon, H.n));
+    CHK(ctx->dalloc(&H.d_V, (size_t)H.n * rmax));
+    CHK(ctx->dalloc(&H.d_tau, (size_t)rmax));
+    CHK(ctx->dalloc(&H.d_work, (size_t)H.n * std::max(1, H.ncon)));
+    EntDev &D = ctx->entdev[f.e];
+    D.n_con = H.ncon;
+    D.con = H.d_con;
+    D.V = H.d_V;
+    D.tau = H.d_tau;
+    D.work = H.d_work;
+  }
+  CHK(hipMemcpyAsync(ctx->d_entdev, ctx->entdev.data(), ctx->entdev.size() * sizeof(EntDev),
+                     hipMemcpyHostToDevice, st));
+  CHK(hipStreamSynchronize(st));
+  return VB_OK;
+}
+
 extern "C" {
 
 static int setup_impl(vb_ctx *ctx);
@@ -524,6 +1019,20 @@ static int setup_impl(vb_ctx *ctx) {
   hipStream_t st = ctx->stream;
   const int nS = ctx->nS;
   const int64_t nG = ctx->nG;
+  // start from the given constraints
+  for (auto &H : ctx->ents) {
+    H.ncon = H.ncon0;
+    H.con = H.con0;
+    H.d_con = H.d_con0;
+    H.d_V = H.d_V0;
+    H.d_tau = H.d_tau0;
+    H.d_work = H.d_work0;
+  }
+  ctx->entdev = ctx->entdev0;
+  CHK(hipMemcpyAsync(ctx->d_entdev, ctx->entdev.data(), ctx->entdev.size() * sizeof(EntDev),
+                     hipMemcpyHostToDevice, st));
+  ctx->face_info.clear();
+  ctx->face_eigs.clear();
   CHK(hipEventRecord(ctx->ev0, st));
   // ---- 1. local dense bordered matrices, flux rows, pressure split
   int64_t wtot = 0;
@@ -564,15 +1073,15 @@ static int setup_impl(vb_ctx *ctx) {
   // ---- 3. primal constraints: QR with column pivoting per entity
   const int nE = (int)ctx->ents.size();
   {
-    int rmax = 1;
-    for (auto &H : ctx->ents) rmax = std::max(rmax, std::min(H.ncon, H.n));
-    CHK(entity_qr(ctx->d_entdev, nE, rmax, ctx->opt.svd_tol, st));
-    std::vector<int> rk(nE);
-    if (nE) {
-      CHK(hipMemcpyAsync(rk.data(), ctx->info + 4 * nS + 64, nE * sizeof(int), hipMemcpyDeviceToHost, st));
-      CHK(hipStreamSynchronize(st));
+    int rc = primal_qr(ctx);
+    if (rc) return rc;
+    // adaptive enrichment of the face constraints (Sec. 6), then the bases again
+    if (ctx->opt.adaptive_theta > 0.0) {
+      rc = adaptive_stage(ctx);
+      if (rc) return rc;
+      rc = primal_qr(ctx);
+      if (rc) return rc;
     }
-    for (int e = 0; e < nE; ++e) ctx->ents[e].rank = rk[e];
   }
   // coarse numbering
   std::vector<int32_t> cstart(nE + 1, 0);
@@ -1552,6 +2061,17 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
 }  // extern "C"
 
 extern "C" {
+
+int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_eigs, double *eigs) {
+  if (!ctx || max_faces < 0 || max_eigs < 0) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_adaptive_info: call vb_setup first");
+  const int nf = (int)ctx->face_info.size();
+  if (faces)
+    for (int i = 0; i < std::min(nf, max_faces); ++i) faces[i] = ctx->face_info[i];
+  if (eigs)
+    for (int i = 0; i < std::min((int)ctx->face_eigs.size(), max_eigs); ++i) eigs[i] = ctx->face_eigs[i];
+  return nf;
+}
 
 int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out) {
   if (!ctx || !out || which < 0 || which > 1) return VB_ERR_ARG;
