@@ -81,6 +81,12 @@ typedef struct vb_face_info {
   int sub_i, sub_j;  /* the two subdomains sharing the face */
   int n_dual;        /* dual coordinates of the face in the minimal primal space */
   int n_selected;    /* eigenvalues below 1/theta (= new primal rows) */
+  double sum_shift;  /* 0, or the relative diagonal shift (1e-13, 1e-11, ... 1e-1
+                        of max|diag|) that made the sum of the two face Schur
+                        complements factorisable: needed when both neighbours
+                        float and share rigid-mode traces on the face (FP64
+                        factors: <= 1e-11 seen; the FP32 factors of the mixed
+                        path: larger at a contrast inside a subdomain) */
 } vb_face_info;
 
 /* Device-time statistics of one kernel, accumulated over its launches. */

@@ -59,6 +59,7 @@ RECIPES = {
     "t8f": dict(n=8, jitter=0.15, k=2, parts=(4, 4, 4), cons=FULL),
     "t12s": dict(n=12, jitter=0.0, k=2, parts=(3, 3, 3), cons=FULL, sinkers=True,
                  sinker_n=4, sinker_r=0.25),
+    "t16s": dict(n=16, jitter=0.0, k=2, parts=(4, 4, 4), cons=FULL, sinkers=True),
 }
 
 

@@ -29,7 +29,7 @@ class vb_options(C.Structure):
 
 class vb_face_info(C.Structure):
     _fields_ = [("entity", C.c_int), ("sub_i", C.c_int), ("sub_j", C.c_int),
-                ("n_dual", C.c_int), ("n_selected", C.c_int)]
+                ("n_dual", C.c_int), ("n_selected", C.c_int), ("sum_shift", C.c_double)]
 
 
 class vb_kernel_stat(C.Structure):
@@ -246,6 +246,7 @@ def vb_adaptive_info(ctx):
         f = faces[i]
         k = f.n_selected if f.n_selected < f.n_dual else 0
         out.append({"entity": f.entity, "subs": (f.sub_i, f.sub_j), "n_dual": f.n_dual,
-                    "n_selected": f.n_selected, "eigenvalues": eigs[o: o + k].copy()})
+                    "n_selected": f.n_selected, "sum_shift": f.sum_shift,
+                    "eigenvalues": eigs[o: o + k].copy()})
         o += k
     return out

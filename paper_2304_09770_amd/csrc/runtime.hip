@@ -563,8 +563,9 @@ static int adaptive_stage(vb_ctx *ctx) {
   struct Face {
     int e, nF, rank, nd;
     int s[2], off[2];
-    int64_t ld2, o_qb, o_qa, o_qa2, o_m, o_wt, o_t2, o_c, o_d, o_e, o_tau, o_z, o_lam, o_r;
+    int64_t ld2, o_qb, o_qa, o_qa2, o_q0, o_m, o_wt, o_t2, o_c, o_d, o_e, o_tau, o_z, o_lam, o_r;
     int mcap;
+    double shift;
   };
   std::vector<Face> faces;
   for (int e = 0; e < (int)ctx->ents.size(); ++e) {
@@ -612,6 +613,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     f.o_qb = take(f.ld2 * 2 * n);
     f.o_qa = take(f.ld2 * 2 * n);
     f.o_qa2 = take(f.ld2 * 2 * n);
+    f.o_q0 = take(f.ld2 * 2 * n);
     f.o_m = take(f.ld2 * 2 * n);
     f.o_wt = take((int64_t)n * n);
     f.o_t2 = take((int64_t)n * n);
@@ -756,10 +758,12 @@ static int adaptive_stage(vb_ctx *ctx) {
     }
   }
   // ---- 2. parallel sums.  At_i + At_j is singular when the two neighbours
-  // float and share rigid-mode traces on F: such faces (found by a pivot
-  // breakdown of the unshifted sum) are factorised again from a copy with the
-  // sum shifted by 1e-13 max|diag|; the kernel is annihilated by the outer
-  // factors of X (X+Y)^-1 Y either way.
+  // float and share rigid-mode traces on F; in FP64 that common kernel comes
+  // out as pivots of either sign at the level of the cancellation in At.
+  // Faces whose unshifted sum breaks down are factorised again from a
+  // pristine copy with the sum shifted by 1e-13, 1e-11, ... up to 1e-1 times
+  // max|diag| (the first that factorises is kept and reported); the kernel
+  // is annihilated by the outer factors of X (X+Y)^-1 Y either way.
   {
     std::vector<LdlJob<double>> lj;
     std::vector<GatherJob> cp;
@@ -771,47 +775,97 @@ static int adaptive_stage(vb_ctx *ctx) {
     }
     int64_t invtot = 0;
     for (auto &f : faces) {
-      invtot += 4 * (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
-      cp.push_back({ar + f.o_qa, f.ld2, ar + f.o_qa2, f.ld2, d_ii, d_ii, 2 * f.nd, 2 * f.nd, 1.0,
+      f.shift = 0.0;
+      invtot += 3 * (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
+      cp.push_back({ar + f.o_qa, f.ld2, ar + f.o_q0, f.ld2, d_ii, d_ii, 2 * f.nd, 2 * f.nd, 1.0,
                     0, 0, 0});
     }
     int rc = run_gather(ctx, cp, max_2nd, max_2nd);
     if (rc) return rc;
     double *invs = nullptr;
     CHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
+    double *invr = nullptr;  // scratch of the retries (one panel set per face)
+    CHK(ctx->dalloc(&invr, std::max<int64_t>(invtot / 3, 1), true));
     int64_t io = 0;
-    for (int q = 0; q < nf; ++q) {
-      const Face &f = faces[q];
-      const int64_t per = (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
-      lj.push_back({ar + f.o_qb, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 2 * nf + q});
-      io += per;
-      lj.push_back({ar + f.o_qa, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 3 * nf + q});
-      io += per;
+    std::vector<int64_t> roff(nf);
+    {
+      int64_t ro = 0;
+      for (int q = 0; q < nf; ++q) {
+        const Face &f = faces[q];
+        const int64_t per = (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
+        lj.push_back({ar + f.o_qb, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 2 * nf + q});
+        io += per;
+        lj.push_back({ar + f.o_qa, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 3 * nf + q});
+        io += per;
+        roff[q] = ro;
+        ro += per;
+      }
     }
     rc = run_ldl(ctx, lj, max_2nd, max_nd);
     if (rc) return rc;
     std::vector<int> hq(nf);
     CHK(hipMemcpyAsync(hq.data(), iinfo + 3 * nf, nf * sizeof(int), hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
-    std::vector<SymJob> sj;
-    std::vector<LdlJob<double>> lj2;
-    for (int q = 0; q < nf; ++q) {
-      Face &f = faces[q];
-      if (!hq[q]) continue;
-      sj.push_back({ar + f.o_qa2, f.ld2, f.nd});
-      lj2.push_back({ar + f.o_qa2, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invs + io, iinfo + 5 * nf + q});
-      io += (int64_t)((f.nd + NB - 1) / NB) * NB * NB;
-      f.o_qa = f.o_qa2;
-    }
     CHK(hipMemsetAsync(iinfo + 3 * nf, 0, nf * sizeof(int), st));
-    if (!sj.empty()) {
+    // FP64 factors have needed at most 1e-11.  The FP32 factors of the mixed
+    // path carry FP32 error amplified by the local conditioning into At (at
+    // a viscosity contrast inside a subdomain, up to percent level), so the
+    // ladder continues to 1e-1: a shifted face only gets a rougher set of
+    // rows, and any primal enrichment keeps lambda_min >= 1.
+    static const double ladder[] = {1e-13, 1e-11, 1e-9, 1e-7, 1e-5, 1e-3, 1e-1};
+    std::string diag = "unshifted failures:";
+    {
+      int nfail = 0;
+      for (int q = 0; q < nf; ++q) nfail += hq[q] != 0;
+      diag += " " + std::to_string(nfail);
+    }
+    std::vector<int> firstcol(hq);
+    for (double sh : ladder) {
+      std::vector<int> todo;
+      for (int q = 0; q < nf; ++q)
+        if (hq[q]) todo.push_back(q);
+      if (todo.empty()) break;
+      std::vector<GatherJob> cp2;
+      std::vector<SymJob> sj;
+      std::vector<LdlJob<double>> lj2;
+      for (int q : todo) {
+        Face &f = faces[q];
+        cp2.push_back({ar + f.o_q0, f.ld2, ar + f.o_qa2, f.ld2, d_ii, d_ii, 2 * f.nd, 2 * f.nd, 1.0,
+                       0, 0, 0});
+        sj.push_back({ar + f.o_qa2, f.ld2, f.nd});
+        lj2.push_back({ar + f.o_qa2, f.ld2, 2 * f.nd, f.nd, f.nd, 0, invr + roff[q],
+                       iinfo + 5 * nf + q});
+        f.o_qa = f.o_qa2;
+        f.shift = sh;
+      }
+      CHK(hipMemsetAsync(iinfo + 5 * nf, 0, nf * sizeof(int), st));
+      rc = run_gather(ctx, cp2, max_2nd, max_2nd);
+      if (rc) return rc;
       SymJob *dsj = nullptr;
       rc = upload_jobs(ctx, &dsj, sj);
       if (rc) return rc;
-      CHK(shift_diag(dsj, (int)sj.size(), 1e-13, st));
+      CHK(shift_diag(dsj, (int)sj.size(), sh, st));
       rc = run_ldl(ctx, lj2, max_2nd, max_nd);
       if (rc) return rc;
+      CHK(hipMemcpyAsync(hq.data(), iinfo + 5 * nf, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      int nfail = 0;
+      for (int q = 0; q < nf; ++q) nfail += hq[q] != 0;
+      char buf[64];
+      snprintf(buf, sizeof buf, ", after shift %.0e: %d", sh, nfail);
+      diag += buf;
     }
+    CHK(hipMemsetAsync(iinfo + 5 * nf, 0, nf * sizeof(int), st));
+    for (int q = 0; q < nf; ++q)
+      if (hq[q])
+        return ctx->fail(VB_ERR_NOT_SPD,
+                         "adaptive: parallel sum of the face Schur complements not factorisable "
+                         "with a shift up to 1e-1 max|diag| (face entity " +
+                         std::to_string(faces[q].e) + ", subdomains " +
+                         std::to_string(faces[q].s[0]) + "/" + std::to_string(faces[q].s[1]) +
+                         ", unshifted breakdown at column " + std::to_string(firstcol[q] - 1) +
+                         " of " + std::to_string(faces[q].nd) + ", last at column " +
+                         std::to_string(hq[q] - 1) + "; " + diag + ")");
     // ---- 3. B = L L^T, W = L^-T; C = W^T At_par W
     std::vector<GatherJob> gm;
     std::vector<DiagJob> dm;
@@ -953,7 +1007,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     const int m = hc[q];
     const bool full = (m >= f.nd);
     const int cols = full ? f.nd : m;
-    vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m};
+    vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m, f.shift};
     ctx->face_info.push_back(fi);
     if (!full && m > 0) {
       std::vector<double> lam(m);
