@@ -177,7 +177,8 @@ def main():
         ldl = r["ldl"]
         a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
         return {"bound": "mfma",
-                "kernel": "k_ldl_update_wide<%s> (rank-256 trailing update of the dense LDL^T)" % dtype,
+                "kernel": "k_ldl_update_wide_%s (rank-256 trailing update of the local Dirichlet "
+                          "LDL^T)" % dtype,
                 "achieved": a, "peak": pk, "unit": "TFLOP/s", "frac": (a / pk) if a else None,
                 "traffic": None, "launches": ldl["launches"],
                 "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
@@ -213,12 +214,12 @@ def main():
         "config": {"workload": args.config + ": " + WORKLOADS[args.config],
                    "precision": PRECISION_NAMES[head], "subdomains": nsub,
                    "interface_unknowns": n},
-        "roofline": roof(R, peak, "double" if head == "fp64" else "float"),
+        "roofline": roof(R, peak, "f64" if head == "fp64" else "f32"),
         "iteration_kernel": gemv(R),
         "runs": {k: summary(v) for k, v in runs.items()},
         "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
         "mixed_accuracy": check or None,
-        "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "double") if "fp64" in runs else None,
+        "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64") if "fp64" in runs else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

@@ -203,9 +203,10 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
 int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_eigs, double *eigs);
 
 /* Statistics of the kernels timed with vb_options.profile: which = 0 the
- * super-panel trailing update of the dense LDL^T (the setup's dominant
- * kernel, work in flops: K*m*(m+1) per matrix and super-panel of K columns
- * with m trailing rows),
+ * super-panel trailing update of the dense LDL^T of the local Dirichlet
+ * factorisations (the setup's dominant kernel, in the precision of the local
+ * matrices: FP64, or FP32 with VB_PREC_MIXED; work in flops: K*m*(m+1) per
+ * matrix and super-panel of K columns with m trailing rows),
  * which = 1 the bordered local Schur GEMV of S_hat p (the iteration's
  * dominant kernel, work in bytes read/written).  reset != 0 clears them. */
 int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out);

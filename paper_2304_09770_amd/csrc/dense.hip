@@ -203,11 +203,15 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
 // through LDS in chunks of KW; the next chunk is loaded into registers
 // (branch-free, clamped addresses) while the current one is multiplied.
 constexpr int WT = 128;
-constexpr int KW = 16;
+// Panel columns staged per pass: the FP32 products take half the matrix-core
+// time of FP64 ones, so FP32 stages twice as many columns (same LDS bytes) to
+// keep the prefetch of the next chunk hidden behind the current one.
+template <typename T> struct WideKW { static constexpr int value = 16; };
+template <> struct WideKW<float> { static constexpr int value = 32; };
 template <typename T>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_ldl_update_wide(const LdlJob<T> *jobs, int J0, int SB) {
+__device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int J0, int SB) {
   typedef Mfma<T> M;
+  constexpr int KW = WideKW<T>::value;
   const LdlJob<T> J = jobs[blockIdx.y];
   const int kb = J0, ke = min(J0 + SB, J.e);
   if (kb >= ke) return;
@@ -292,6 +296,24 @@ void k_ldl_update_wide(const LdlJob<T> *jobs, int J0, int SB) {
     }
 }
 
+// FP64: 206 VGPRs, two waves per SIMD.  FP32: 124 VGPRs and half the LDS
+// bytes per stage, four waves per SIMD.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_wide_body<double>(jobs, J0, SB);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
+  ldl_update_wide_body<float>(jobs, J0, SB);
+}
+template <typename T> struct WideKernel;
+template <> struct WideKernel<double> {
+  static constexpr auto fn = k_ldl_update_wide_f64;
+};
+template <> struct WideKernel<float> {
+  static constexpr auto fn = k_ldl_update_wide_f32;
+};
+
 // C = alpha A B^T + beta C (column-major), 64x64 tiles, K in chunks of 64.
 template <typename T>
 __global__ __launch_bounds__(256) void k_gemm_nt(const GemmJob<T> *jobs) {
@@ -367,12 +389,12 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
                        const std::vector<int> *he) {
   if (batch == 0 || max_e == 0) return hipSuccess;
   static bool attr = false;
-  const size_t lds = 2 * (size_t)KW * WT * sizeof(T);
+  const size_t lds = 2 * (size_t)WideKW<T>::value * WT * sizeof(T);
   if (!attr) {
-    hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide<double>,
+    hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f64,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
-      r = hipFuncSetAttribute((const void *)k_ldl_update_wide<float>,
+      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f32,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r != hipSuccess) return r;
     attr = true;
@@ -402,8 +424,8 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
       const int wt = (rows + WT - 1) / WT;
       const int ntiles = wt * (wt + 1) / 2;
       if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
-      hipLaunchKernelGGL((k_ldl_update_wide<T>), dim3(ntiles, batch), dim3(256), lds, s, d_jobs,
-                         J0, SB);
+      hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
+                         SB);
       if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
     }
     hipError_t e = hipGetLastError();

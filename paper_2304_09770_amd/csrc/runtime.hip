@@ -452,7 +452,8 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
 
 // ------------------------------------------------------------------ setup
 template <typename T>
-static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max_e) {
+static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max_e,
+                   bool timed = false) {
   if (jobs.empty()) return VB_OK;
   LdlJob<T> *dj = nullptr;
   CHK(ctx->upload(&dj, jobs, true));
@@ -462,7 +463,7 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
     he[b] = jobs[b].e;
   }
   CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
-                     ctx->opt.profile ? &ctx->t_ldl : nullptr, &hn, &he));
+                     (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he));
   return VB_OK;
 }
 
@@ -1110,7 +1111,7 @@ static int setup_impl(vb_ctx *ctx) {
         jobs[s] = {(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
                    (float *)ctx->invL + S.inv_off, ctx->info + s};
       }
-      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
+      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, true);
     } else {
       std::vector<LdlJob<double>> jobs(nS);
       for (int s = 0; s < nS; ++s) {
@@ -1118,7 +1119,7 @@ static int setup_impl(vb_ctx *ctx) {
         jobs[s] = {(double *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
                    (double *)ctx->invL + S.inv_off, ctx->info + s};
       }
-      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e);
+      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, true);
     }
     if (rc) return rc;
     rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index)");
