@@ -108,3 +108,14 @@ def load_workload(path):
         ents.append({"kind": int(z["e%d_kind" % e][0]), "gids": z["e%d_gids" % e],
                      "con": z["e%d_con" % e]})
     return {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents}
+
+
+def mlp_init_params(F, H, seed=0):
+    """Seeded initial weights of the constraint predictor's network
+    (uniform in +-1/sqrt(fan_in), biases zero), float32, in the flat layout
+    [W1 (H x F), b1, W2 (H x H), b2, w3 (H), b3]."""
+    rng = np.random.default_rng(seed)
+    a1, a2 = 1.0 / np.sqrt(F), 1.0 / np.sqrt(H)
+    parts = [rng.uniform(-a1, a1, H * F), np.zeros(H), rng.uniform(-a2, a2, H * H), np.zeros(H),
+             rng.uniform(-a2, a2, H), np.zeros(1)]
+    return np.concatenate(parts).astype(np.float32)
