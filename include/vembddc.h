@@ -73,6 +73,12 @@ typedef struct vb_options {
   double adaptive_theta; /* > 0: adaptive face constraints (Sec. 6) with tolerance
                             theta (nu_tol): eigenvalues below 1/theta of every face
                             pencil add primal rows; 0 = the given constraints only */
+  void *predictor;       /* NULL, or a trained vb_mlp: with adaptive_theta > 0 the
+                            face eigenproblems first try a Chebyshev-filtered
+                            subspace iteration whose block size and starting
+                            vectors come from the network; faces where it does
+                            not converge with a margin fall back to the dense
+                            exact eigensolve */
 } vb_options;
 
 /* One face of the adaptive coarse space (Sec. 6), as selected by vb_setup. */
@@ -81,6 +87,10 @@ typedef struct vb_face_info {
   int sub_i, sub_j;  /* the two subdomains sharing the face */
   int n_dual;        /* dual coordinates of the face in the minimal primal space */
   int n_selected;    /* eigenvalues below 1/theta (= new primal rows) */
+  int predicted;     /* the network's count for the face, -1 without predictor */
+  int path;          /* 0 dense exact eigensolve, 1 predicted subspace iteration
+                        accepted, 2 predicted path rejected and exact fallback */
+  int passes;        /* filter passes of the predicted path */
   double sum_shift;  /* 0, or the relative diagonal shift (1e-13, 1e-11, ... 1e-1
                         of max|diag|) that made the sum of the two face Schur
                         complements factorisable: needed when both neighbours
@@ -201,6 +211,54 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
  * contributes none).  Returns the number of faces (>= 0), or VB_ERR_STATE
  * before setup. */
 int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_eigs, double *eigs);
+
+/* ---- learned predictor of the adaptive constraints
+ * A fully connected network 12 -> 32 -> 32 -> 1 (tanh, tanh, sigmoid), FP32,
+ * on per-coordinate features of each face's reduced pencil (the matrix
+ * L^-1 (At_i:At_j) L^-T, with L L^T = A_i:A_j): its output is the
+ * coordinate's participation sum_t y_t[c]^2 in the eigenvectors below
+ * 1/theta, so the sum over a face predicts the number of new constraints
+ * and the largest scores give the starting block of the subspace iteration.
+ * Labels come from the exact eigensolves of the method itself.
+ * Parameter layout (VB_MLP_NPARAMS floats): [W1 (32 x 12, row-major), b1 (32),
+ * W2 (32 x 32), b2 (32), w3 (32), b3]. */
+#define VB_MLP_FEATURES 12
+#define VB_MLP_NPARAMS 1505
+typedef struct vb_mlp vb_mlp;
+/* init: VB_MLP_NPARAMS host floats (copied); stream: hipStream_t or NULL. */
+int vb_mlp_create(vb_mlp **m, const float *init, void *stream);
+void vb_mlp_destroy(vb_mlp *m);
+const char *vb_mlp_last_error(const vb_mlp *m);
+/* Append the (features, labels) of every face coordinate of ctx's last setup
+ * (adaptive, faces solved by the exact eigensolve only).  Returns the number
+ * of samples added (>= 0) or an error. */
+int vb_mlp_add_samples(vb_mlp *m, vb_ctx *ctx);
+int64_t vb_mlp_num_samples(const vb_mlp *m);
+/* Standardise the features over the collected samples, then `epochs` steps
+ * of full-batch Adam (one epoch captured once in a HIP graph and replayed);
+ * loss_history (host, may be NULL) receives the loss before every step. */
+int vb_mlp_train(vb_mlp *m, int epochs, float lr, double *loss_history);
+/* Forward pass on n device samples (n x VB_MLP_FEATURES floats, row-major),
+ * with the model's standardisation. */
+int vb_mlp_forward(vb_mlp *m, const float *X_dev, int64_t n, float *s_dev);
+/* Mean squared error and its gradient (device, VB_MLP_NPARAMS floats) on n
+ * device samples, with the model's standardisation (identity before
+ * training). */
+int vb_mlp_loss_grad(vb_mlp *m, const float *X_dev, const float *y_dev, int64_t n,
+                     float *grad_dev, double *loss);
+int vb_mlp_get_params(const vb_mlp *m, float *params_host, float *mu_host, float *sd_host);
+int vb_mlp_set_params(vb_mlp *m, const float *params_host, const float *mu_host,
+                      const float *sd_host);
+/* 1 (default): start the subspace iteration from the coordinates with the
+ * largest scores; 0: from pseudo-random coordinates (for comparison). */
+int vb_mlp_set_warm_start(vb_mlp *m, int on);
+/* The last adaptive setup's per-coordinate face features (row-major,
+ * VB_MLP_FEATURES each) and labels (NaN for faces not solved by the exact
+ * eigensolve), copied to host buffers of max_n coordinates (either may be
+ * NULL).  Returns the number of coordinates (>= 0) or an error. */
+int64_t vb_face_samples(vb_ctx *ctx, int64_t max_n, float *X_host, float *y_host);
+/* Append n host samples (X: n x VB_MLP_FEATURES row-major, y: n). */
+int vb_mlp_add_data(vb_mlp *m, const float *X_host, const float *y_host, int64_t n);
 
 /* Statistics of the kernels timed with vb_options.profile: which = 0 the
  * super-panel trailing update of the dense LDL^T of the local Dirichlet

@@ -24,12 +24,14 @@ VB_SCALING_DELUXE, VB_SCALING_COUNTING = 0, 1
 class vb_options(C.Structure):
     _fields_ = [("precision", C.c_int), ("scaling", C.c_int), ("tol", C.c_double),
                 ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
-                ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double)]
+                ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double),
+                ("predictor", C.c_void_p)]
 
 
 class vb_face_info(C.Structure):
     _fields_ = [("entity", C.c_int), ("sub_i", C.c_int), ("sub_j", C.c_int),
-                ("n_dual", C.c_int), ("n_selected", C.c_int), ("sum_shift", C.c_double)]
+                ("n_dual", C.c_int), ("n_selected", C.c_int), ("predicted", C.c_int),
+                ("path", C.c_int), ("passes", C.c_int), ("sum_shift", C.c_double)]
 
 
 class vb_kernel_stat(C.Structure):
@@ -88,6 +90,21 @@ def load():
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
         "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
                                        C.POINTER(C.c_double)]),
+        "vb_face_samples": (C.c_int64, [P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
+        "vb_mlp_add_data": (C.c_int, [P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]),
+        "vb_mlp_create": (C.c_int, [C.POINTER(P), C.POINTER(C.c_float), P]),
+        "vb_mlp_destroy": (None, [P]),
+        "vb_mlp_last_error": (C.c_char_p, [P]),
+        "vb_mlp_add_samples": (C.c_int, [P, P]),
+        "vb_mlp_num_samples": (C.c_int64, [P]),
+        "vb_mlp_train": (C.c_int, [P, C.c_int, C.c_float, C.POINTER(C.c_double)]),
+        "vb_mlp_forward": (C.c_int, [P, P, C.c_int64, P]),
+        "vb_mlp_loss_grad": (C.c_int, [P, P, P, C.c_int64, P, C.POINTER(C.c_double)]),
+        "vb_mlp_get_params": (C.c_int, [P, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                        C.POINTER(C.c_float)]),
+        "vb_mlp_set_params": (C.c_int, [P, C.POINTER(C.c_float), C.POINTER(C.c_float),
+                                        C.POINTER(C.c_float)]),
+        "vb_mlp_set_warm_start": (C.c_int, [P, C.c_int]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -101,7 +118,10 @@ def exported_symbols():
     return ["vb_create", "vb_destroy", "vb_last_error", "vb_assemble", "vb_setup",
             "vb_interface_size", "vb_rhs", "vb_schur_apply", "vb_apply", "vb_pcg_solve",
             "vb_get_local_solution", "vb_recover_all", "vb_batched_ldl", "vb_kernel_stats",
-            "vb_adaptive_info"]
+            "vb_adaptive_info", "vb_face_samples", "vb_mlp_create", "vb_mlp_destroy",
+            "vb_mlp_last_error", "vb_mlp_add_samples", "vb_mlp_num_samples", "vb_mlp_train",
+            "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
+            "vb_mlp_set_warm_start", "vb_mlp_add_data"]
 
 
 class VBError(RuntimeError):
@@ -131,10 +151,11 @@ def _check(ctx, rc):
 
 # ------------------------------------------------------------- C-ABI names
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
-              svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0):
+              svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
+              predictor=None):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
-                     adaptive_theta)
+                     adaptive_theta, predictor)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -246,7 +267,101 @@ def vb_adaptive_info(ctx):
         f = faces[i]
         k = f.n_selected if f.n_selected < f.n_dual else 0
         out.append({"entity": f.entity, "subs": (f.sub_i, f.sub_j), "n_dual": f.n_dual,
-                    "n_selected": f.n_selected, "sum_shift": f.sum_shift,
+                    "n_selected": f.n_selected, "predicted": f.predicted, "path": f.path,
+                    "passes": f.passes, "sum_shift": f.sum_shift,
                     "eigenvalues": eigs[o: o + k].copy()})
         o += k
     return out
+
+
+# ---------------------------------------------------------- learned predictor
+VB_MLP_FEATURES, VB_MLP_NPARAMS = 12, 1505
+
+
+def _mcheck(m, rc):
+    if rc < 0:
+        raise VBError(rc, load().vb_mlp_last_error(m).decode())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+def vb_face_samples(ctx):
+    """(X, y) host arrays of the last adaptive setup's face coordinates
+    (labels NaN where the face was not solved by the exact eigensolve)."""
+    lib = load()
+    n = lib.vb_face_samples(ctx, 0, None, None)
+    _check(ctx, n if n < 0 else 0)
+    X = np.zeros((n, VB_MLP_FEATURES), np.float32)
+    y = np.zeros(n, np.float32)
+    rc = lib.vb_face_samples(ctx, n, _fptr(X), _fptr(y))
+    _check(ctx, rc if rc < 0 else 0)
+    return X, y
+
+
+def vb_mlp_add_data(m, X, y):
+    X = np.ascontiguousarray(X, np.float32)
+    y = np.ascontiguousarray(y, np.float32)
+    _mcheck(m, load().vb_mlp_add_data(m, _fptr(X), _fptr(y), len(y)))
+
+
+def vb_mlp_create(init, stream=None):
+    init = np.ascontiguousarray(init, dtype=np.float32)
+    assert init.size == VB_MLP_NPARAMS
+    m = C.c_void_p()
+    rc = load().vb_mlp_create(C.byref(m), _fptr(init), stream)
+    if rc != VB_OK:
+        raise VBError(rc, "vb_mlp_create")
+    return m
+
+
+def vb_mlp_destroy(m):
+    load().vb_mlp_destroy(m)
+
+
+def vb_mlp_add_samples(m, ctx):
+    rc = load().vb_mlp_add_samples(m, ctx)
+    _mcheck(m, rc)
+    return rc
+
+
+def vb_mlp_num_samples(m):
+    return int(load().vb_mlp_num_samples(m))
+
+
+def vb_mlp_train(m, epochs, lr):
+    hist = np.zeros(max(epochs, 1))
+    rc = load().vb_mlp_train(m, int(epochs), float(lr), hist.ctypes.data_as(C.POINTER(C.c_double)))
+    _mcheck(m, rc)
+    return hist[:epochs]
+
+
+def vb_mlp_forward(m, X, s):
+    _mcheck(m, load().vb_mlp_forward(m, _ptr(X), int(X.shape[0]), _ptr(s)))
+
+
+def vb_mlp_loss_grad(m, X, y, g):
+    loss = C.c_double()
+    _mcheck(m, load().vb_mlp_loss_grad(m, _ptr(X), _ptr(y), int(X.shape[0]), _ptr(g),
+                                       C.byref(loss)))
+    return loss.value
+
+
+def vb_mlp_get_params(m):
+    p = np.zeros(VB_MLP_NPARAMS, np.float32)
+    mu = np.zeros(VB_MLP_FEATURES, np.float32)
+    sd = np.zeros(VB_MLP_FEATURES, np.float32)
+    _mcheck(m, load().vb_mlp_get_params(m, _fptr(p), _fptr(mu), _fptr(sd)))
+    return p, mu, sd
+
+
+def vb_mlp_set_params(m, p, mu, sd):
+    p = np.ascontiguousarray(p, np.float32)
+    mu = np.ascontiguousarray(mu, np.float32)
+    sd = np.ascontiguousarray(sd, np.float32)
+    _mcheck(m, load().vb_mlp_set_params(m, _fptr(p), _fptr(mu), _fptr(sd)))
+
+
+def vb_mlp_set_warm_start(m, on):
+    _mcheck(m, load().vb_mlp_set_warm_start(m, int(bool(on))))

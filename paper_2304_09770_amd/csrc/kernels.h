@@ -212,4 +212,60 @@ hipError_t sym_average(const SymJob *d_jobs, int njobs, int max_n, hipStream_t s
 hipError_t shift_diag(const SymJob *d_jobs, int njobs, double rel, hipStream_t s);
 hipError_t normalize_cols(const RowJob *d_jobs, int njobs, int max_cols, hipStream_t s);
 
+// ---- learned predictor of the adaptive constraints (network F -> H -> H -> 1)
+constexpr int MLP_F = 12;
+constexpr int MLP_H = 32;
+constexpr int MLP_NPARAMS = MLP_H * MLP_F + MLP_H + MLP_H * MLP_H + MLP_H + MLP_H + 1;
+struct FeatJob {
+  const double *C;    // n x n reduced pencil matrix (full symmetric)
+  int64_t ld;
+  int n;
+  double sigma;
+  const double *trp;  // [tr At_par, tr B]
+  const double *tra;  // [tr(A_i + A_j), tr A_j]
+  float *X;           // n x MLP_F features (row-major)
+  double *rho;        // Gershgorin bound of C
+};
+struct LabelJob {
+  const double *Z;    // n x m eigenvectors of C
+  int64_t ldz;
+  int n, m, full;
+  float *y;
+};
+struct ChebJob {
+  const double *cur, *prev;
+  double *out;
+  int b, n;
+  double beta, gamma;
+};
+struct OrthJob {
+  double *Vt;  // b x n (ld b)
+  int b, n;
+};
+struct RitzJob {
+  const double *Vt, *U;  // b x n (ld b)
+  const double *ZH;      // b x b eigenvectors of H
+  int64_t ldzh;
+  const double *theta;
+  int b, n;
+  double *Y;             // n x b
+  int64_t ldy;
+  double *Vt2;           // b x n: the Ritz vectors, transposed
+  double *res;
+};
+hipError_t face_features(const FeatJob *d_jobs, int njobs, hipStream_t s);
+hipError_t traces(const SymJob *d_jobs, int njobs, double *out, hipStream_t s);
+hipError_t face_labels(const LabelJob *d_jobs, int njobs, hipStream_t s);
+hipError_t mlp_forward(const float *p, const float *mu, const float *sd, const float *X, int64_t N,
+                       float *s, hipStream_t st);
+hipError_t mlp_grad(const float *p, const float *mu, const float *sd, const float *X,
+                    const float *y, int64_t N, float *partial, double *lpart, float *grad,
+                    double *loss, hipStream_t st);
+hipError_t mlp_adam(float *p, const float *g, float *m, float *v, int *t, float lr,
+                    const double *loss, double *hist, hipStream_t st);
+hipError_t mlp_standardize(const float *X, int64_t N, float *mu, float *sd, hipStream_t st);
+hipError_t cheb_combine(const ChebJob *d_jobs, int njobs, int64_t max_len, hipStream_t s);
+hipError_t orth_rows(const OrthJob *d_jobs, int njobs, hipStream_t s);
+hipError_t ritz(const RitzJob *d_jobs, int njobs, int max_b, hipStream_t s);
+
 }  // namespace vb

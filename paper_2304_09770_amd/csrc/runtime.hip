@@ -110,6 +110,8 @@ struct vb_ctx {
   // adaptive coarse space of the last setup
   std::vector<vb_face_info> face_info;
   std::vector<double> face_eigs;
+  float *d_feat = nullptr, *d_lab = nullptr;  // per face coordinate (faces solved exactly)
+  int64_t n_coord = 0;
 
   // iteration structures
   int nC = 0, nCS = 0;
@@ -171,6 +173,23 @@ struct vb_ctx {
     if (e != hipSuccess) return e;
     if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
     return e;
+  }
+};
+
+struct vb_mlp {
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  std::string err;
+  float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *mu = nullptr, *sd = nullptr;
+  int *t = nullptr;
+  double *loss = nullptr;
+  float *X = nullptr, *y = nullptr;  // training set
+  int64_t n = 0, cap = 0;
+  bool trained = false;
+  int warm = 1;
+  int fail(int code, const std::string &msg) {
+    err = msg;
+    return code;
   }
 };
 
@@ -539,6 +558,227 @@ static int upload_jobs(vb_ctx *ctx, J **d, const std::vector<J> &h) {
   return VB_OK;
 }
 
+
+// ---------------------------------------------------- predicted eigenpairs
+// Buffers of one face for the predicted path: C (n x n), and where the exact
+// path would put its eigenvectors (Z, n x mcap) and eigenvalues (lam).
+struct PredFace {
+  const double *C;
+  int n;
+  double *Z, *lam;
+  int mcap;
+};
+
+// Warm-started Chebyshev-filtered subspace iteration on every face whose
+// predicted count allows it.  The network's scores summed over a face give
+// k; the block has b = max(k + 4, 1.3 k + 2) vectors (at most 64 and n/2),
+// starting from the unit vectors of the b best-scored coordinates.  A pass
+// applies a degree-20 Chebyshev filter damping [2 sigma, rho] (rho: the
+// Gershgorin bound of C), orthonormalises, and takes Rayleigh-Ritz pairs
+// (eigensolve of the b x b projection with the dense kernels).  Accepted
+// when fewer than b - 2 Ritz values lie below sigma (a margin that the
+// count is complete) and every selected pair has residual <= 1e-9 rho;
+// otherwise up to 4 passes, then the face falls back to the exact solve.
+template <class GetFace>
+static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
+                          const std::vector<int64_t> &coff, const double *d_rho, double sigma,
+                          std::vector<int> &path, std::vector<int> &kpred, std::vector<int> &passes,
+                          std::vector<int> &hc) {
+  hipStream_t st = ctx->stream;
+  const int nf = (int)nf_;
+  const int64_t ncoord = coff[nf];
+  float *score = nullptr;
+  CHK(ctx->dalloc(&score, std::max<int64_t>(ncoord, 1), true));
+  CHK(mlp_forward(pred->p, pred->mu, pred->sd, ctx->d_feat, ncoord, score, st));
+  std::vector<float> hs(ncoord);
+  std::vector<double> rho(nf);
+  CHK(hipMemcpyAsync(hs.data(), score, ncoord * sizeof(float), hipMemcpyDeviceToHost, st));
+  CHK(hipMemcpyAsync(rho.data(), d_rho, nf * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  const double a = 2.0 * sigma;
+  struct PF {
+    int q, n, b;
+    double e, c0, rho;
+    int64_t o_y[3], o_u, o_v2, o_h, o_zh, o_d, o_e, o_tau, o_lam, o_res;
+  };
+  std::vector<PF> act;
+  int64_t tot = 0;
+  auto take = [&](int64_t c) {
+    int64_t o = tot;
+    tot += round_up(std::max<int64_t>(c, 1), 32);
+    return o;
+  };
+  int max_b = 1, max_n = 1;
+  for (int q = 0; q < nf; ++q) {
+    const PredFace F = get(q);
+    double ssum = 0.0;
+    for (int64_t c = coff[q]; c < coff[q + 1]; ++c) ssum += hs[c];
+    const int k = (int)std::lround(ssum);
+    kpred[q] = k;
+    const int b = std::max(k + 4, (int)std::ceil(1.3 * k) + 2);
+    if (b > 64 || 2 * b > F.n || b > F.mcap || rho[q] <= a) continue;  // exact solve
+    PF P{};
+    P.q = q;
+    P.n = F.n;
+    P.b = b;
+    P.rho = rho[q];
+    P.e = 0.5 * (rho[q] - a);
+    P.c0 = 0.5 * (rho[q] + a);
+    for (int r = 0; r < 3; ++r) P.o_y[r] = take((int64_t)b * F.n);
+    P.o_u = take((int64_t)b * F.n);
+    P.o_v2 = take((int64_t)b * F.n);
+    P.o_h = take((int64_t)b * b);
+    P.o_zh = take((int64_t)b * b);
+    P.o_d = take(b);
+    P.o_e = take(b);
+    P.o_tau = take(b);
+    P.o_lam = take(b);
+    P.o_res = take(b);
+    act.push_back(P);
+    max_b = std::max(max_b, b);
+    max_n = std::max(max_n, F.n);
+  }
+  if (act.empty()) return VB_OK;
+  const int na = (int)act.size();
+  double *w = nullptr;
+  int *cntH = nullptr;
+  CHK(ctx->dalloc(&w, tot, true));
+  CHK(ctx->dalloc(&cntH, na, true));
+  CHK(hipMemsetAsync(w, 0, tot * sizeof(double), st));
+  {  // starting blocks (b x n, ld b): unit vectors of the chosen coordinates
+    std::vector<std::vector<double>> v0(na);
+    for (int i = 0; i < na; ++i) {
+      const PF &P = act[i];
+      std::vector<int> idx(P.n);
+      std::iota(idx.begin(), idx.end(), 0);
+      if (pred->warm) {
+        const float *sc = hs.data() + coff[P.q];
+        std::partial_sort(idx.begin(), idx.begin() + P.b, idx.end(),
+                          [&](int x, int y) { return sc[x] > sc[y] || (sc[x] == sc[y] && x < y); });
+      } else {  // pseudo-random distinct coordinates (a fixed linear congruential shuffle)
+        uint64_t st64 = 0x9e3779b97f4a7c15ull ^ (uint64_t)P.q;
+        for (int t = P.n - 1; t > 0; --t) {
+          st64 = st64 * 6364136223846793005ull + 1442695040888963407ull;
+          std::swap(idx[t], idx[(int)((st64 >> 33) % (uint64_t)(t + 1))]);
+        }
+      }
+      v0[i].assign((size_t)P.b * P.n, 0.0);
+      for (int t = 0; t < P.b; ++t) v0[i][t + (size_t)idx[t] * P.b] = 1.0;
+      CHK(hipMemcpyAsync(w + P.o_y[0], v0[i].data(), v0[i].size() * sizeof(double),
+                         hipMemcpyHostToDevice, st));
+    }
+    CHK(hipStreamSynchronize(st));
+  }
+  const int deg = 20, max_pass = 4;
+  std::vector<char> done(na, 0);
+  for (int pass = 0; pass < max_pass; ++pass) {
+    std::vector<int> live;
+    for (int i = 0; i < na; ++i)
+      if (!done[i]) live.push_back(i);
+    if (live.empty()) break;
+    // Chebyshev filter, three rotating blocks per face
+    int cur = 0;
+    for (int k = 0; k < deg; ++k) {
+      std::vector<ChebJob> cj;
+      std::vector<GemmJob<double>> gj;
+      const int prev = (cur + 2) % 3, out = (cur + 1) % 3;
+      for (int i : live) {
+        const PF &P = act[i];
+        const PredFace F = get(P.q);
+        double *yc = w + P.o_y[cur], *yp = w + P.o_y[prev], *yo = w + P.o_y[out];
+        if (k == 0) {
+          cj.push_back({yc, nullptr, yo, P.b, P.n, -P.c0 / P.e, 0.0});
+          gj.push_back({yc, F.C, yo, P.b, P.n, P.b, P.b, P.n, P.n, 0, 1.0 / P.e, 1.0});
+        } else {
+          cj.push_back({yc, yp, yo, P.b, P.n, -2.0 * P.c0 / P.e, -1.0});
+          gj.push_back({yc, F.C, yo, P.b, P.n, P.b, P.b, P.n, P.n, 0, 2.0 / P.e, 1.0});
+        }
+      }
+      ChebJob *dcj = nullptr;
+      GemmJob<double> *dgj = nullptr;
+      int rc = upload_jobs(ctx, &dcj, cj);
+      if (!rc) rc = upload_jobs(ctx, &dgj, gj);
+      if (rc) return rc;
+      CHK(cheb_combine(dcj, (int)cj.size(), (int64_t)max_b * max_n, st));
+      CHK(gemm_nt_batched<double>(dgj, (int)gj.size(), max_b, max_n, st));
+      cur = out;
+    }
+    // orthonormalise, project, Rayleigh-Ritz
+    std::vector<OrthJob> oj;
+    std::vector<GemmJob<double>> gu, gh;
+    std::vector<SymJob> sj;
+    std::vector<EigJob> ej;
+    std::vector<RitzJob> rj;
+    for (size_t k = 0; k < live.size(); ++k) {
+      const PF &P = act[live[k]];
+      const PredFace F = get(P.q);
+      double *V = w + P.o_y[cur];
+      oj.push_back({V, P.b, P.n});
+      gu.push_back({V, F.C, w + P.o_u, P.b, P.n, P.b, P.b, P.n, P.n, 0, 1.0, 0.0});
+      gh.push_back({V, w + P.o_u, w + P.o_h, P.b, P.b, P.b, P.b, P.b, P.n, 0, 1.0, 0.0});
+      sj.push_back({w + P.o_h, P.b, P.b});
+      ej.push_back({w + P.o_h, P.b, P.b, P.b, w + P.o_d, w + P.o_e, w + P.o_tau, w + P.o_zh, P.b,
+                    w + P.o_lam, cntH + live[k], 2.0 * P.rho + 1.0});
+      rj.push_back({V, w + P.o_u, w + P.o_zh, P.b, w + P.o_lam, P.b, P.n, F.Z, P.n,
+                    w + P.o_v2, w + P.o_res});
+    }
+    OrthJob *doj = nullptr;
+    GemmJob<double> *dgu = nullptr, *dgh = nullptr;
+    SymJob *dsj = nullptr;
+    EigJob *dej = nullptr;
+    RitzJob *drj = nullptr;
+    int rc = upload_jobs(ctx, &doj, oj);
+    if (!rc) rc = upload_jobs(ctx, &dgu, gu);
+    if (!rc) rc = upload_jobs(ctx, &dgh, gh);
+    if (!rc) rc = upload_jobs(ctx, &dsj, sj);
+    if (!rc) rc = upload_jobs(ctx, &dej, ej);
+    if (!rc) rc = upload_jobs(ctx, &drj, rj);
+    if (rc) return rc;
+    const int nl = (int)live.size();
+    CHK(orth_rows(doj, nl, st));
+    CHK(gemm_nt_batched<double>(dgu, nl, max_b, max_n, st));
+    CHK(gemm_nt_batched<double>(dgh, nl, max_b, max_b, st));
+    CHK(sym_average(dsj, nl, max_b, st));
+    CHK(tridiag(dej, nl, max_b, st));
+    CHK(tridiag_eig(dej, nl, max_b, max_b, st));
+    CHK(back_transform(dej, nl, st));
+    CHK(ritz(drj, nl, max_b, st));
+    for (size_t k = 0; k < live.size(); ++k) {
+      PF &P = act[live[k]];
+      const int q = P.q;
+      std::vector<double> th(P.b), res(P.b);
+      CHK(hipMemcpyAsync(th.data(), w + P.o_lam, P.b * sizeof(double), hipMemcpyDeviceToHost, st));
+      CHK(hipMemcpyAsync(res.data(), w + P.o_res, P.b * sizeof(double), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      int kr = 0;
+      while (kr < P.b && th[kr] < sigma) ++kr;
+      passes[q] = pass + 1;
+      if (kr >= P.b - 2) {  // no margin: the block may miss eigenvalues below sigma
+        done[live[k]] = 1;
+        path[q] = 2;
+        continue;
+      }
+      double rmax = 0.0;
+      for (int t = 0; t < kr; ++t) rmax = std::max(rmax, res[t]);
+      if (rmax <= 1e-9 * P.rho) {
+        done[live[k]] = 1;
+        path[q] = 1;
+        hc[q] = kr;
+        if (kr > 0) {
+          const PredFace F = get(q);
+          CHK(hipMemcpyAsync(F.lam, w + P.o_lam, kr * sizeof(double), hipMemcpyDeviceToDevice, st));
+        }
+      } else {  // next pass from the Ritz vectors
+        CHK(hipMemcpyAsync(w + P.o_y[0], w + P.o_v2, (size_t)P.b * P.n * sizeof(double),
+                           hipMemcpyDeviceToDevice, st));
+      }
+    }
+  }
+  for (int i = 0; i < na; ++i)
+    if (!done[i]) path[act[i].q] = 2;
+  return VB_OK;
+}
+
 // Adaptive face constraints (Sec. 6), one pass over the faces in the bases
 // of the given constraints.  Per face F (subdomains i, j), with n = the dual
 // coordinates of F:
@@ -758,6 +998,21 @@ static int adaptive_stage(vb_ctx *ctx) {
       ci = cj;
     }
   }
+  // traces of A_i + A_j and A_j (features of the learned predictor)
+  double *tr_pre = nullptr, *tr_post = nullptr;
+  CHK(ctx->dalloc(&tr_pre, 2 * (int64_t)nf, true));
+  CHK(ctx->dalloc(&tr_post, 2 * (int64_t)nf, true));
+  {
+    std::vector<SymJob> tj;
+    for (auto &f : faces) {
+      tj.push_back({ar + f.o_qb, f.ld2, f.nd});
+      tj.push_back({ar + f.o_qb + f.nd + (int64_t)f.nd * f.ld2, f.ld2, f.nd});
+    }
+    SymJob *dtj = nullptr;
+    int rc = upload_jobs(ctx, &dtj, tj);
+    if (rc) return rc;
+    CHK(traces(dtj, (int)tj.size(), tr_pre, st));
+  }
   // ---- 2. parallel sums.  At_i + At_j is singular when the two neighbours
   // float and share rigid-mode traces on F; in FP64 that common kernel comes
   // out as pivots of either sign at the level of the cancellation in At.
@@ -939,22 +1194,98 @@ static int adaptive_stage(vb_ctx *ctx) {
     CHK(sym_average(dcj, nf, max_nd, st));
   }
   // ---- 4. eigenpairs below sigma
-  std::vector<EigJob> ej(nf);
-  int max_mcap = 1;
+  // 4a. traces of the parallel sums and per-coordinate features of C
+  {
+    std::vector<SymJob> tj;
+    for (auto &f : faces) {
+      tj.push_back({ar + f.o_qa + f.nd + (int64_t)f.nd * f.ld2, f.ld2, f.nd});
+      tj.push_back({ar + f.o_qb + f.nd + (int64_t)f.nd * f.ld2, f.ld2, f.nd});
+    }
+    SymJob *dtj = nullptr;
+    int rc = upload_jobs(ctx, &dtj, tj);
+    if (rc) return rc;
+    CHK(traces(dtj, (int)tj.size(), tr_post, st));
+  }
+  std::vector<int64_t> coff(nf + 1, 0);
+  for (int q = 0; q < nf; ++q) coff[q + 1] = coff[q] + faces[q].nd;
+  const int64_t ncoord = coff[nf];
+  CHK(ctx->dalloc(&ctx->d_feat, ncoord * MLP_F));
+  CHK(ctx->dalloc(&ctx->d_lab, ncoord));
+  CHK(hipMemsetAsync(ctx->d_lab, 0xff, ncoord * sizeof(float), st));  // NaN: no label
+  ctx->n_coord = ncoord;
+  double *d_rho = nullptr;
+  CHK(ctx->dalloc(&d_rho, nf, true));
+  {
+    std::vector<FeatJob> fj0(nf);
+    for (int q = 0; q < nf; ++q) {
+      const Face &f = faces[q];
+      fj0[q] = {ar + f.o_c, f.nd, f.nd, sigma, tr_post + 2 * q, tr_pre + 2 * q,
+                ctx->d_feat + coff[q] * MLP_F, d_rho + q};
+    }
+    FeatJob *dfj = nullptr;
+    int rc = upload_jobs(ctx, &dfj, fj0);
+    if (rc) return rc;
+    CHK(face_features(dfj, nf, st));
+  }
+  std::vector<int> path(nf, 0), kpred(nf, -1), passes(nf, 0), hc(nf, 0);
+  // 4b. predicted path: warm-started Chebyshev-filtered subspace iteration
+  vb_mlp *pred = (vb_mlp *)ctx->opt.predictor;
+  if (pred && pred->trained) {
+    int rc = predicted_eigs(ctx, pred, faces.size(), [&](int q) -> PredFace {
+      const Face &f = faces[q];
+      return PredFace{ar + f.o_c, f.nd, ar + f.o_z, ar + f.o_lam, f.mcap};
+    }, coff, d_rho, sigma, path, kpred, passes, hc);
+    if (rc) return rc;
+  }
+  // 4c. exact dense eigensolve for the other faces
+  std::vector<EigJob> ej;
+  std::vector<int> eq;
+  int max_mcap = 1, max_nde = 1;
   for (int q = 0; q < nf; ++q) {
+    if (path[q] == 1) continue;
     const Face &f = faces[q];
-    ej[q] = {ar + f.o_c, f.nd, f.nd, 0, ar + f.o_d, ar + f.o_e, ar + f.o_tau, ar + f.o_z, f.nd,
-             ar + f.o_lam, cnt + q, sigma};
+    ej.push_back({ar + f.o_c, f.nd, f.nd, 0, ar + f.o_d, ar + f.o_e, ar + f.o_tau, ar + f.o_z, f.nd,
+                  ar + f.o_lam, cnt + q, sigma});
+    eq.push_back(q);
     max_mcap = std::max(max_mcap, f.mcap);
+    max_nde = std::max(max_nde, f.nd);
   }
   EigJob *dej = nullptr;
-  int rc = upload_jobs(ctx, &dej, ej);
-  if (rc) return rc;
-  CHK(tridiag(dej, nf, max_nd, st));
-  CHK(tridiag_eig(dej, nf, max_nd, max_mcap, st));
-  std::vector<int> hc(nf);
-  CHK(hipMemcpyAsync(hc.data(), cnt, nf * sizeof(int), hipMemcpyDeviceToHost, st));
-  CHK(hipStreamSynchronize(st));
+  int rc = 0;
+  if (!ej.empty()) {
+    rc = upload_jobs(ctx, &dej, ej);
+    if (rc) return rc;
+    CHK(tridiag(dej, (int)ej.size(), max_nde, st));
+    CHK(tridiag_eig(dej, (int)ej.size(), max_nde, max_mcap, st));
+    std::vector<int> hx(nf);
+    CHK(hipMemcpyAsync(hx.data(), cnt, nf * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (size_t k = 0; k < eq.size(); ++k) {
+      const int q = eq[k];
+      const Face &f = faces[q];
+      const int m = hx[q];
+      if (m > f.mcap && m < f.nd)
+        return ctx->fail(VB_ERR_ARG, "adaptive: " + std::to_string(m) +
+                                         " eigenvalues below 1/theta on face entity " +
+                                         std::to_string(f.e) + " (at most 256 supported)");
+      hc[q] = m;
+      ej[k].ncols = (m >= f.nd) ? 0 : m;
+    }
+    rc = upload_jobs(ctx, &dej, ej);
+    if (rc) return rc;
+    CHK(back_transform(dej, (int)ej.size(), st));
+    // 4d. labels of the exactly solved faces
+    std::vector<LabelJob> lb;
+    for (int q : eq) {
+      const Face &f = faces[q];
+      lb.push_back({ar + f.o_z, f.nd, f.nd, std::min(hc[q], f.mcap), hc[q] >= f.nd ? 1 : 0,
+                    ctx->d_lab + coff[q]});
+    }
+    LabelJob *dlb = nullptr;
+    rc = upload_jobs(ctx, &dlb, lb);
+    if (rc) return rc;
+    CHK(face_labels(dlb, (int)lb.size(), st));
+  }
   std::vector<RowJob> rj, rn;
   std::vector<FaceTJob> fj;
   std::vector<DiagJob> dfull;
@@ -962,13 +1293,8 @@ static int adaptive_stage(vb_ctx *ctx) {
   for (int q = 0; q < nf; ++q) {
     Face &f = faces[q];
     const int m = hc[q];
-    if (m > f.mcap && m < f.nd)
-      return ctx->fail(VB_ERR_ARG, "adaptive: " + std::to_string(m) +
-                                       " eigenvalues below 1/theta on face entity " +
-                                       std::to_string(f.e) + " (at most 256 supported)");
     const bool full = (m >= f.nd);
     const int cols = full ? f.nd : m;
-    ej[q].ncols = full ? 0 : m;
     double *R = ar + f.o_r;  // nF x cols, rows [0, rank) stay zero
     if (cols > 0) {
       if (full)
@@ -981,9 +1307,6 @@ static int adaptive_stage(vb_ctx *ctx) {
       max_nF = std::max(max_nF, f.nF);
     }
   }
-  rc = upload_jobs(ctx, &dej, ej);
-  if (rc) return rc;
-  CHK(back_transform(dej, nf, st));
   if (!rj.empty()) {
     RowJob *drj = nullptr;
     rc = upload_jobs(ctx, &drj, rj);
@@ -1008,7 +1331,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     const int m = hc[q];
     const bool full = (m >= f.nd);
     const int cols = full ? f.nd : m;
-    vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m, f.shift};
+    vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m, kpred[q], path[q], passes[q], f.shift};
     ctx->face_info.push_back(fi);
     if (!full && m > 0) {
       std::vector<double> lam(m);
@@ -1088,6 +1411,8 @@ static int setup_impl(vb_ctx *ctx) {
                      hipMemcpyHostToDevice, st));
   ctx->face_info.clear();
   ctx->face_eigs.clear();
+  ctx->d_feat = ctx->d_lab = nullptr;  // freed with the previous setup
+  ctx->n_coord = 0;
   CHK(hipEventRecord(ctx->ev0, st));
   // ---- 1. local dense bordered matrices, flux rows, pressure split
   int64_t wtot = 0;
@@ -2140,6 +2465,226 @@ int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out) {
   out->total_ms = ms;
   out->work = work;
   if (reset) t.reset();
+  return VB_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------ predictor ABI
+#define MCHK(x)                                                                   \
+  do {                                                                            \
+    hipError_t e_ = (x);                                                          \
+    if (e_ != hipSuccess)                                                         \
+      return m->fail(e_ == hipErrorOutOfMemory ? VB_ERR_OOM : VB_ERR_DEVICE,      \
+                     std::string(#x) + ": " + hipGetErrorString(e_));             \
+  } while (0)
+
+static_assert(VB_MLP_NPARAMS == MLP_NPARAMS, "network size");
+static_assert(VB_MLP_FEATURES == MLP_F, "feature count");
+
+extern "C" {
+
+int vb_mlp_create(vb_mlp **out, const float *init, void *stream) {
+  if (!out || !init) return VB_ERR_ARG;
+  vb_mlp *m = new vb_mlp();
+  *out = m;
+  if (stream) {
+    m->stream = (hipStream_t)stream;
+  } else {
+    MCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
+    m->own_stream = true;
+  }
+  const size_t P = MLP_NPARAMS * sizeof(float);
+  MCHK(hipMalloc(&m->p, P));
+  MCHK(hipMalloc(&m->m, P));
+  MCHK(hipMalloc(&m->v, P));
+  MCHK(hipMalloc(&m->g, P));
+  MCHK(hipMalloc(&m->mu, MLP_F * sizeof(float)));
+  MCHK(hipMalloc(&m->sd, MLP_F * sizeof(float)));
+  MCHK(hipMalloc(&m->t, sizeof(int)));
+  MCHK(hipMalloc(&m->loss, sizeof(double)));
+  MCHK(hipMemcpy(m->p, init, P, hipMemcpyHostToDevice));
+  std::vector<float> z(MLP_F, 0.0f), o(MLP_F, 1.0f);
+  MCHK(hipMemcpy(m->mu, z.data(), MLP_F * sizeof(float), hipMemcpyHostToDevice));
+  MCHK(hipMemcpy(m->sd, o.data(), MLP_F * sizeof(float), hipMemcpyHostToDevice));
+  return VB_OK;
+}
+
+void vb_mlp_destroy(vb_mlp *m) {
+  if (!m) return;
+  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  for (void *q : {(void *)m->p, (void *)m->m, (void *)m->v, (void *)m->g, (void *)m->mu,
+                  (void *)m->sd, (void *)m->t, (void *)m->loss, (void *)m->X, (void *)m->y})
+    if (q) (void)hipFree(q);
+  if (m->own_stream) (void)hipStreamDestroy(m->stream);
+  delete m;
+}
+
+const char *vb_mlp_last_error(const vb_mlp *m) { return m ? m->err.c_str() : "null model"; }
+
+int64_t vb_mlp_num_samples(const vb_mlp *m) { return m ? m->n : -1; }
+
+int64_t vb_face_samples(vb_ctx *ctx, int64_t max_n, float *X_host, float *y_host) {
+  if (!ctx || max_n < 0) return VB_ERR_ARG;
+  if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_face_samples: call vb_setup first");
+  const int64_t n = std::min(ctx->n_coord, max_n);
+  CHK(hipStreamSynchronize(ctx->stream));
+  if (n > 0 && X_host)
+    CHK(hipMemcpy(X_host, ctx->d_feat, n * MLP_F * sizeof(float), hipMemcpyDeviceToHost));
+  if (n > 0 && y_host)
+    CHK(hipMemcpy(y_host, ctx->d_lab, n * sizeof(float), hipMemcpyDeviceToHost));
+  return ctx->n_coord;
+}
+
+static int mlp_append(vb_mlp *m, const float *Xk, const float *yk, int64_t add) {
+  if (m->n + add > m->cap) {
+    const int64_t cap = std::max<int64_t>(2 * m->cap, m->n + add);
+    float *X2 = nullptr, *y2 = nullptr;
+    MCHK(hipMalloc(&X2, cap * MLP_F * sizeof(float)));
+    MCHK(hipMalloc(&y2, cap * sizeof(float)));
+    if (m->n) {
+      MCHK(hipMemcpy(X2, m->X, m->n * MLP_F * sizeof(float), hipMemcpyDeviceToDevice));
+      MCHK(hipMemcpy(y2, m->y, m->n * sizeof(float), hipMemcpyDeviceToDevice));
+    }
+    if (m->X) (void)hipFree(m->X);
+    if (m->y) (void)hipFree(m->y);
+    m->X = X2;
+    m->y = y2;
+    m->cap = cap;
+  }
+  if (add) {
+    MCHK(hipMemcpy(m->X + m->n * MLP_F, Xk, add * MLP_F * sizeof(float), hipMemcpyHostToDevice));
+    MCHK(hipMemcpy(m->y + m->n, yk, add * sizeof(float), hipMemcpyHostToDevice));
+  }
+  m->n += add;
+  return VB_OK;
+}
+
+int vb_mlp_add_data(vb_mlp *m, const float *X_host, const float *y_host, int64_t n) {
+  if (!m || n < 0 || (n > 0 && (!X_host || !y_host))) return VB_ERR_ARG;
+  return mlp_append(m, X_host, y_host, n);
+}
+
+int vb_mlp_add_samples(vb_mlp *m, vb_ctx *ctx) {
+  if (!m || !ctx) return VB_ERR_ARG;
+  if (ctx->state != 2) return m->fail(VB_ERR_STATE, "vb_mlp_add_samples: context not set up");
+  const int64_t nc = ctx->n_coord;
+  if (nc == 0) return 0;
+  MCHK(hipStreamSynchronize(ctx->stream));
+  std::vector<float> X((size_t)nc * MLP_F), y(nc);
+  MCHK(hipMemcpy(X.data(), ctx->d_feat, X.size() * sizeof(float), hipMemcpyDeviceToHost));
+  MCHK(hipMemcpy(y.data(), ctx->d_lab, y.size() * sizeof(float), hipMemcpyDeviceToHost));
+  // keep the coordinates with a label (faces solved by the exact eigensolve)
+  std::vector<float> Xk, yk;
+  for (int64_t i = 0; i < nc; ++i)
+    if (y[i] == y[i]) {
+      Xk.insert(Xk.end(), X.begin() + i * MLP_F, X.begin() + (i + 1) * MLP_F);
+      yk.push_back(y[i]);
+    }
+  const int64_t add = (int64_t)yk.size();
+  int rc = mlp_append(m, Xk.data(), yk.data(), add);
+  if (rc) return rc;
+  return (int)add;
+}
+
+int vb_mlp_train(vb_mlp *m, int epochs, float lr, double *loss_history) {
+  if (!m || epochs < 0 || !(lr > 0.0f)) return VB_ERR_ARG;
+  if (m->n <= 0) return m->fail(VB_ERR_STATE, "vb_mlp_train: no samples");
+  hipStream_t st = m->stream;
+  const int nblk = (int)((m->n + 63) / 64);
+  float *partial = nullptr;
+  double *lpart = nullptr, *hist = nullptr;
+  MCHK(hipMalloc(&partial, (size_t)nblk * MLP_NPARAMS * sizeof(float)));
+  MCHK(hipMalloc(&lpart, (size_t)nblk * sizeof(double)));
+  MCHK(hipMalloc(&hist, (size_t)std::max(epochs, 1) * sizeof(double)));
+  int rc = VB_OK;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  auto run = [&]() -> int {
+    MCHK(mlp_standardize(m->X, m->n, m->mu, m->sd, st));
+    // fresh optimiser state (filled by a kernel launch, not a memset, so the
+    // captured epoch holds kernels only)
+    std::vector<float> z(MLP_NPARAMS, 0.0f);
+    MCHK(hipMemcpyAsync(m->m, z.data(), MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice, st));
+    MCHK(hipMemcpyAsync(m->v, z.data(), MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice, st));
+    int zero = 0;
+    MCHK(hipMemcpyAsync(m->t, &zero, sizeof(int), hipMemcpyHostToDevice, st));
+    MCHK(hipStreamSynchronize(st));
+    if (epochs == 0) return VB_OK;
+    // one epoch = gradient (block partials + fixed-order reduction) + Adam
+    MCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    hipError_t e1 = mlp_grad(m->p, m->mu, m->sd, m->X, m->y, m->n, partial, lpart, m->g, m->loss, st);
+    hipError_t e2 = mlp_adam(m->p, m->g, m->m, m->v, m->t, lr, m->loss, hist, st);
+    hipError_t e3 = hipStreamEndCapture(st, &graph);
+    MCHK(e1);
+    MCHK(e2);
+    MCHK(e3);
+    MCHK(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+    for (int ep = 0; ep < epochs; ++ep) MCHK(hipGraphLaunch(exec, st));
+    MCHK(hipStreamSynchronize(st));
+    if (loss_history)
+      MCHK(hipMemcpy(loss_history, hist, epochs * sizeof(double), hipMemcpyDeviceToHost));
+    m->trained = true;
+    return VB_OK;
+  };
+  rc = run();
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  (void)hipFree(partial);
+  (void)hipFree(lpart);
+  (void)hipFree(hist);
+  return rc;
+}
+
+int vb_mlp_forward(vb_mlp *m, const float *X_dev, int64_t n, float *s_dev) {
+  if (!m || n < 0 || (n > 0 && (!X_dev || !s_dev))) return VB_ERR_ARG;
+  MCHK(mlp_forward(m->p, m->mu, m->sd, X_dev, n, s_dev, m->stream));
+  MCHK(hipStreamSynchronize(m->stream));
+  return VB_OK;
+}
+
+int vb_mlp_loss_grad(vb_mlp *m, const float *X_dev, const float *y_dev, int64_t n,
+                     float *grad_dev, double *loss) {
+  if (!m || n <= 0 || !X_dev || !y_dev || !grad_dev) return VB_ERR_ARG;
+  const int nblk = (int)((n + 63) / 64);
+  float *partial = nullptr;
+  double *lpart = nullptr, *dl = nullptr;
+  MCHK(hipMalloc(&partial, (size_t)nblk * MLP_NPARAMS * sizeof(float)));
+  MCHK(hipMalloc(&lpart, (size_t)nblk * sizeof(double)));
+  MCHK(hipMalloc(&dl, sizeof(double)));
+  hipError_t e = mlp_grad(m->p, m->mu, m->sd, X_dev, y_dev, n, partial, lpart, grad_dev, dl, m->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(m->stream);
+  if (e == hipSuccess && loss) e = hipMemcpy(loss, dl, sizeof(double), hipMemcpyDeviceToHost);
+  (void)hipFree(partial);
+  (void)hipFree(lpart);
+  (void)hipFree(dl);
+  MCHK(e);
+  return VB_OK;
+}
+
+int vb_mlp_get_params(const vb_mlp *mc, float *params, float *mu, float *sd) {
+  vb_mlp *m = const_cast<vb_mlp *>(mc);
+  if (!m) return VB_ERR_ARG;
+  MCHK(hipStreamSynchronize(m->stream));
+  if (params) MCHK(hipMemcpy(params, m->p, MLP_NPARAMS * sizeof(float), hipMemcpyDeviceToHost));
+  if (mu) MCHK(hipMemcpy(mu, m->mu, MLP_F * sizeof(float), hipMemcpyDeviceToHost));
+  if (sd) MCHK(hipMemcpy(sd, m->sd, MLP_F * sizeof(float), hipMemcpyDeviceToHost));
+  return VB_OK;
+}
+
+int vb_mlp_set_params(vb_mlp *m, const float *params, const float *mu, const float *sd) {
+  if (!m) return VB_ERR_ARG;
+  MCHK(hipStreamSynchronize(m->stream));
+  if (params) MCHK(hipMemcpy(m->p, params, MLP_NPARAMS * sizeof(float), hipMemcpyHostToDevice));
+  if (mu) MCHK(hipMemcpy(m->mu, mu, MLP_F * sizeof(float), hipMemcpyHostToDevice));
+  if (sd) MCHK(hipMemcpy(m->sd, sd, MLP_F * sizeof(float), hipMemcpyHostToDevice));
+  if (params && mu && sd) m->trained = true;
+  return VB_OK;
+}
+
+int vb_mlp_set_warm_start(vb_mlp *m, int on) {
+  if (!m) return VB_ERR_ARG;
+  m->warm = on ? 1 : 0;
   return VB_OK;
 }
 

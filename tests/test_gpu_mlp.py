@@ -1,0 +1,149 @@
+"""The learned constraint predictor on the GPU.
+
+* forward pass and loss gradient of the FP32 network against the FP64
+  oracle on the same weights and samples (FP32 rounding, about 6e-8 per
+  operation, accumulated over the 12 + 32 + 32 terms of a sample and a
+  fixed-order sum over 2000 samples: bounds 1e-5 on the outputs and 1e-4 on
+  the gradient norm);
+* the training loop (full-batch Adam, one epoch replayed from a HIP graph)
+  against the oracle's FP64 loss history from the same start, on the same
+  standardised samples;
+* the method with the trained network against the exact adaptive coarse
+  space on a workload it was not trained on: faces solved by the
+  warm-started subspace iteration, selected counts, PCG iterations and
+  condition number within 10% of the exact space, and the network's warm
+  start against pseudo-random starting coordinates."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from inputs.workloads import make_workload, mlp_init_params
+from oracle.mlp import forward as o_forward, loss_and_grad, train as o_train
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+F, H = 12, 32
+THETA = 10.0
+
+
+@pytest.fixture(scope="module")
+def vb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09770_amd import binding
+    binding.load()
+    return binding
+
+
+def _samples(N, seed):
+    rng = np.random.default_rng(seed)
+    X = rng.standard_normal((N, F)).astype(np.float32)
+    y = np.clip(0.5 + 0.3 * X[:, 0] - 0.2 * X[:, 5] + 0.05 * rng.standard_normal(N), 0, 1)
+    return X, y.astype(np.float32)
+
+
+def test_forward_and_gradient_parity(vb):
+    X, y = _samples(2000, 0)
+    p = mlp_init_params(F, H, 1) * 2.0
+    m = vb.vb_mlp_create(p)
+    try:
+        Xd = torch.tensor(X, device=DEV)
+        yd = torch.tensor(y, device=DEV)
+        s = torch.zeros(len(y), dtype=torch.float32, device=DEV)
+        vb.vb_mlp_forward(m, Xd, s)
+        so, _ = o_forward(p.astype(np.float64), X.astype(np.float64), F, H)
+        assert np.abs(s.cpu().numpy() - so).max() <= 1e-5
+        g = torch.zeros(vb.VB_MLP_NPARAMS, dtype=torch.float32, device=DEV)
+        L = vb.vb_mlp_loss_grad(m, Xd, yd, g)
+        Lo, go = loss_and_grad(p.astype(np.float64), X.astype(np.float64),
+                               y.astype(np.float64), F, H)
+        assert abs(L - Lo) <= 1e-5 * Lo
+        gg = g.cpu().numpy().astype(np.float64)
+        assert np.linalg.norm(gg - go) <= 1e-4 * np.linalg.norm(go)
+    finally:
+        vb.vb_mlp_destroy(m)
+
+
+def test_training_loop_tracks_oracle(vb):
+    X, y = _samples(1500, 2)
+    p0 = mlp_init_params(F, H, 3)
+    m = vb.vb_mlp_create(p0)
+    try:
+        vb.vb_mlp_add_data(m, X, y)
+        hist = vb.vb_mlp_train(m, 80, 1e-2)
+        p, mu, sd = vb.vb_mlp_get_params(m)
+    finally:
+        vb.vb_mlp_destroy(m)
+    X64 = X.astype(np.float64)
+    mu_o, sd_o = X64.mean(axis=0), X64.std(axis=0)
+    assert np.abs(mu - mu_o).max() <= 1e-6 and np.abs(sd / sd_o - 1).max() <= 1e-6
+    Xs = (X64 - mu.astype(np.float64)) / sd.astype(np.float64)
+    po, ho = o_train(p0.astype(np.float64), Xs, y.astype(np.float64), F, H, 80, 1e-2)
+    assert np.abs(hist / ho - 1).max() <= 1e-3, (hist[:5], ho[:5], hist[-3:], ho[-3:])
+    assert hist[-1] < 0.5 * hist[0]
+
+
+def _solve(vb, wl, predictor=None):
+    ctx = vb.vb_create(tol=1e-8, adaptive_theta=THETA, predictor=predictor)
+    vb.vb_assemble(ctx, wl)
+    vb.vb_setup(ctx)
+    n = vb.vb_interface_size(ctx)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = vb.vb_pcg_solve(ctx, x)
+    faces = vb.vb_adaptive_info(ctx)
+    return ctx, info, faces, x.cpu().numpy()
+
+
+@pytest.fixture(scope="module")
+def trained(vb):
+    """Network trained on the exact eigensolves of two sinker workloads."""
+    m = vb.vb_mlp_create(mlp_init_params(F, H, 7))
+    for seed in (1, 2):
+        wl, _ = make_workload("t12s", seed=seed, workers=1)
+        ctx, info, faces, _ = _solve(vb, wl)
+        assert vb.vb_mlp_add_samples(m, ctx) > 0
+        vb.vb_destroy(ctx)
+    hist = vb.vb_mlp_train(m, 1500, 3e-3)
+    print("training loss %.3e -> %.3e on %d samples"
+          % (hist[0], hist[-1], vb.vb_mlp_num_samples(m)), flush=True)
+    assert hist[-1] < 0.5 * hist[0]
+    yield m
+    vb.vb_mlp_destroy(m)
+
+
+def test_predictor_against_exact_space(vb, trained):
+    wl, meta = make_workload("t12s", seed=3, workers=1)
+    c0, i0, f0, x0 = _solve(vb, wl)
+    vb.vb_destroy(c0)
+    vb.vb_mlp_set_warm_start(trained, 1)
+    c1, i1, f1, x1 = _solve(vb, wl, predictor=trained)
+    vb.vb_destroy(c1)
+    vb.vb_mlp_set_warm_start(trained, 0)
+    c2, i2, f2, x2 = _solve(vb, wl, predictor=trained)
+    vb.vb_destroy(c2)
+    vb.vb_mlp_set_warm_start(trained, 1)
+    ex = {f["entity"]: f["n_selected"] for f in f0}
+    acc = [f for f in f1 if f["path"] == 1]
+    err = np.mean([abs(f["predicted"] - ex[f["entity"]]) for f in f1])
+    print("faces %d, predicted-path accepted %d, fallback %d, mean |count error| %.2f"
+          % (len(f1), len(acc), sum(f["path"] == 2 for f in f1), err), flush=True)
+    passes_w = sum(f["passes"] for f in f1 if f["path"] != 0)
+    passes_r = sum(f["passes"] for f in f2 if f["path"] != 0)
+    acc_r = sum(f["path"] == 1 for f in f2)
+    print("filter passes: warm %d, random %d; accepted warm %d random %d; "
+          "iterations exact %d predicted %d; kappa exact %.3f predicted %.3f"
+          % (passes_w, passes_r, len(acc), acc_r, i0["iterations"], i1["iterations"],
+             i0["lambda_max"] / i0["lambda_min"], i1["lambda_max"] / i1["lambda_min"]), flush=True)
+    assert len(acc) >= len(f1) // 2
+    # accepted faces reproduce the exact selection
+    for f in acc:
+        assert f["n_selected"] == ex[f["entity"]]
+    assert abs(i1["iterations"] - i0["iterations"]) <= max(1, 0.1 * i0["iterations"])
+    k0 = i0["lambda_max"] / i0["lambda_min"]
+    k1 = i1["lambda_max"] / i1["lambda_min"]
+    assert abs(k1 - k0) <= 0.1 * k0
+    assert np.linalg.norm(x1 - x0) <= 1e-6 * np.linalg.norm(x0)
+    # the warm start needs no more filter passes and is accepted at least as
+    # often as pseudo-random starting coordinates
+    assert passes_w <= passes_r and len(acc) >= acc_r
