@@ -29,6 +29,11 @@ WORKLOADS = {
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+# HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE (scaled by the readings of a 1 GiB device copy: x2.0, x1.0), per
+# workload and path; to be cleared whenever the kernel changes.
+TRAFFIC_BYTES = {("c2", "mixed"): 4.0655e10}
+TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
 
@@ -77,11 +82,24 @@ def main():
                     help="both: time the FP64 path and the mixed path; value = mixed")
     ap.add_argument("--prepare-only", action="store_true",
                     help="generate and store the workload (--cache) and exit")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="copy a 1 GiB device buffer three times and exit (reference for the "
+                         "HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on exactly one GPU: this build has no multi-GPU path "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.calibrate_copy:
+        import torch
+        a = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device="cuda:0")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read_per_launch": a.numel() * 4,
+                          "bytes_written_per_launch": a.numel() * 4, "launches": 3}), flush=True)
+        return
     # ---- workload (before any GPU initialisation)
     from inputs.workloads import make_workload, save_workload, load_workload
     t = time.perf_counter()
@@ -173,14 +191,16 @@ def main():
         assert R["info"]["true_rel_residual"] <= 1e-8 * 1.01, R["info"]
     peak = PEAK_FP64_TFLOPS if head == "fp64" else PEAK_FP32_TFLOPS
 
-    def roof(r, pk, dtype):
+    def roof(r, pk, dtype, prec):
         ldl = r["ldl"]
         a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
         return {"bound": "mfma",
                 "kernel": "k_ldl_update_wide_%s (rank-256 trailing update of the local Dirichlet "
                           "LDL^T)" % dtype,
                 "achieved": a, "peak": pk, "unit": "TFLOP/s", "frac": (a / pk) if a else None,
-                "traffic": None, "launches": ldl["launches"],
+                "traffic": TRAFFIC_BYTES.get((args.config, prec)),
+                "traffic_source": TRAFFIC_SOURCE if (args.config, prec) in TRAFFIC_BYTES else None,
+                "launches": ldl["launches"],
                 "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
 
     def gemv(r):
@@ -214,12 +234,12 @@ def main():
         "config": {"workload": args.config + ": " + WORKLOADS[args.config],
                    "precision": PRECISION_NAMES[head], "subdomains": nsub,
                    "interface_unknowns": n},
-        "roofline": roof(R, peak, "f64" if head == "fp64" else "f32"),
+        "roofline": roof(R, peak, "f64" if head == "fp64" else "f32", head),
         "iteration_kernel": gemv(R),
         "runs": {k: summary(v) for k, v in runs.items()},
         "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
         "mixed_accuracy": check or None,
-        "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64") if "fp64" in runs else None,
+        "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64", "fp64") if "fp64" in runs else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
