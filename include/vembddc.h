@@ -144,6 +144,9 @@ typedef struct vb_solve_info {
   double setup_ms, solve_ms; /* device times of the last vb_setup / vb_pcg_solve */
   int status;                /* VB_OK or VB_ERR_* */
   int refinement_steps;      /* VB_PREC_MIXED: outer refinement steps taken (0 for FP64) */
+  double latency_ms;         /* device clock from the start of the solve to this
+                                problem's convergence (per problem, see
+                                vb_problem_solve_info); the largest for the whole */
 } vb_solve_info;
 
 typedef struct vb_ctx vb_ctx;
@@ -154,8 +157,13 @@ void vb_destroy(vb_ctx *ctx);
 const char *vb_last_error(const vb_ctx *ctx);
 
 /* Copy one problem: n_sub subdomains and n_ent entities covering every
- * global interface id 0..n_iface-1 exactly once (Sec. 4.2: R_Gamma^(i)).
- * Builds the interface numbering and uploads the local matrices. */
+ * interface id 0..n_iface-1 of the problem exactly once (Sec. 4.2:
+ * R_Gamma^(i)).  Called again before vb_setup, it appends another,
+ * independent problem: the context then solves all of them together (every
+ * setup and iteration launch covers the subdomains of all problems; PCG keeps
+ * separate scalars and convergence per problem).  Problem p's interface ids
+ * are offset by the interface sizes of the problems before it, its
+ * subdomains by their subdomain counts (see vb_problem_layout). */
 int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
                 int n_ent, const vb_entity *ents);
 
@@ -166,8 +174,22 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
  * VB_ERR_NOT_SPD (subdomain index in vb_last_error) on a pivot breakdown. */
 int vb_setup(vb_ctx *ctx);
 
-/* Length of the global interface vector: n_iface + n_sub. */
+/* Length of the global interface vector: the interface ids of all problems
+ * (problem order), then one p0 entry per subdomain (subdomain order). */
 int64_t vb_interface_size(const vb_ctx *ctx);
+
+/* Where problem `problem` sits in the global vectors and subdomain list. */
+typedef struct vb_problem {
+  int64_t iface_offset, n_iface;  /* its interface ids [offset, offset + n) */
+  int64_t p0_offset;              /* its subdomains' p0 entries [p0_offset, + n_sub) */
+  int sub_offset, n_sub;          /* its subdomains [sub_offset, + n_sub) */
+} vb_problem;
+int vb_num_problems(const vb_ctx *ctx);
+int vb_problem_layout(const vb_ctx *ctx, int problem, vb_problem *out);
+/* Per-problem result of the last vb_pcg_solve (the info that call returns
+ * combines them: largest iteration count, residual and latency, extreme
+ * Lanczos values, worst status). */
+int vb_problem_solve_info(const vb_ctx *ctx, int problem, vb_solve_info *out);
 
 /* g_dev <- g_hat (eq. globInt) in the global interface layout (device). */
 int vb_rhs(vb_ctx *ctx, double *g_dev);

@@ -28,6 +28,14 @@ class vb_options(C.Structure):
                 ("predictor", C.c_void_p)]
 
 
+class vb_problem(C.Structure):
+    _fields_ = [("iface_offset", C.c_int64), ("n_iface", C.c_int64), ("p0_offset", C.c_int64),
+                ("sub_offset", C.c_int), ("n_sub", C.c_int)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class vb_face_info(C.Structure):
     _fields_ = [("entity", C.c_int), ("sub_i", C.c_int), ("sub_j", C.c_int),
                 ("n_dual", C.c_int), ("n_selected", C.c_int), ("predicted", C.c_int),
@@ -54,7 +62,8 @@ class vb_solve_info(C.Structure):
     _fields_ = [("iterations", C.c_int), ("rel_residual", C.c_double),
                 ("true_rel_residual", C.c_double), ("lambda_min", C.c_double),
                 ("lambda_max", C.c_double), ("n_coarse", C.c_int), ("setup_ms", C.c_double),
-                ("solve_ms", C.c_double), ("status", C.c_int), ("refinement_steps", C.c_int)]
+                ("solve_ms", C.c_double), ("status", C.c_int), ("refinement_steps", C.c_int),
+                ("latency_ms", C.c_double)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -90,6 +99,9 @@ def load():
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
         "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
                                        C.POINTER(C.c_double)]),
+        "vb_num_problems": (C.c_int, [P]),
+        "vb_problem_layout": (C.c_int, [P, C.c_int, C.POINTER(vb_problem)]),
+        "vb_problem_solve_info": (C.c_int, [P, C.c_int, C.POINTER(vb_solve_info)]),
         "vb_face_samples": (C.c_int64, [P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
         "vb_mlp_add_data": (C.c_int, [P, C.POINTER(C.c_float), C.POINTER(C.c_float), C.c_int64]),
         "vb_mlp_create": (C.c_int, [C.POINTER(P), C.POINTER(C.c_float), P]),
@@ -121,7 +133,8 @@ def exported_symbols():
             "vb_adaptive_info", "vb_face_samples", "vb_mlp_create", "vb_mlp_destroy",
             "vb_mlp_last_error", "vb_mlp_add_samples", "vb_mlp_num_samples", "vb_mlp_train",
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
-            "vb_mlp_set_warm_start", "vb_mlp_add_data"]
+            "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
+            "vb_problem_solve_info"]
 
 
 class VBError(RuntimeError):
@@ -365,3 +378,20 @@ def vb_mlp_set_params(m, p, mu, sd):
 
 def vb_mlp_set_warm_start(m, on):
     _mcheck(m, load().vb_mlp_set_warm_start(m, int(bool(on))))
+
+
+# ------------------------------------------------------------ several problems
+def vb_num_problems(ctx):
+    return int(load().vb_num_problems(ctx))
+
+
+def vb_problem_layout(ctx, problem):
+    out = vb_problem()
+    _check(ctx, load().vb_problem_layout(ctx, int(problem), C.byref(out)))
+    return out.as_dict()
+
+
+def vb_problem_solve_info(ctx, problem):
+    out = vb_solve_info()
+    _check(ctx, load().vb_problem_solve_info(ctx, int(problem), C.byref(out)))
+    return out.as_dict()

@@ -5,8 +5,26 @@
 
 namespace vb {
 
-enum { SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_GG, SC_FLAG, SC_TMP, SC_COUNT };
+// Per-problem PCG scalars: SC_STRIDE doubles per problem.
+enum {
+  SC_RZ = 0, SC_PQ, SC_ALPHA, SC_BETA, SC_RR, SC_GG, SC_FLAG, SC_TMP,
+  SC_DONE,    // 1 once converged, stopped at maxit or broken down
+  SC_ACTIVE,  // 1 if the problem took part in the current iteration
+  SC_IT,      // iterations taken
+  SC_TOL,     // relative tolerance on ||r|| / ||b||
+  SC_MAXIT,
+  SC_T0,      // device clock at the start of the solve
+  SC_TDONE,   // device clock when SC_DONE was set
+  SC_COUNT
+};
+constexpr int SC_STRIDE = 16;
+static_assert(SC_COUNT <= SC_STRIDE, "scalar slots");
 constexpr int DOT_BLOCKS = 512;
+
+// A problem's entries of the global interface vector: [a0, a0+n0) then [a1, a1+n1).
+struct Seg {
+  int64_t a0, n0, a1, n1;
+};
 
 struct GemvJob {
   const void *A;       // double, or float if a_f32 (FP32 storage, FP64 accumulation)
@@ -59,6 +77,19 @@ hipError_t update_xr(int64_t n, const double *sc, double *x, double *r, const do
 hipError_t update_p(int64_t n, const double *sc, double *p, const double *z, hipStream_t s);
 hipError_t vsub(int64_t n, const double *a, const double *b, double *y, hipStream_t s);
 hipError_t axpy(int64_t n, double a, const double *x, double *y, hipStream_t s);
+
+// ---- PCG over several independent problems (segments), scalars per problem.
+// mode 0: PQ, alpha (0 when done), history;  1: RR after the update, iteration
+// count, convergence / maxit;  2: beta, RZ, history;  3: RZ;  4: GG;  5: TMP;
+// 6: RR at the start with the initial convergence test.
+hipError_t sdot(const Seg *segs, int P, int G, const double *a, const double *b, double *part,
+                double *sc, int mode, double *hist_a, double *hist_b, int hist_ld, hipStream_t s);
+hipError_t supdate_xr(const Seg *segs, int P, int G, double *sc, double *x, double *r,
+                      const double *p, const double *q, double *part, hipStream_t s);
+hipError_t supdate_p(const Seg *segs, int P, int G, const double *sc, double *p, const double *z,
+                     hipStream_t s);
+// per-problem scalar initialisation: zero, TOL = tol[p], MAXIT, T0 = device clock
+hipError_t sinit(int P, const double *tol, int maxit, double *sc, hipStream_t s);
 hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,
                        hipStream_t s);
 

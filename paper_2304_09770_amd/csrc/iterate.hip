@@ -345,4 +345,170 @@ hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int
   return hipGetLastError();
 }
 
+
+// ------------------------------------------ PCG over several problems
+__device__ __forceinline__ int64_t seg_index(const Seg &S, int64_t k) {
+  return (k < S.n0) ? S.a0 + k : S.a1 + (k - S.n0);
+}
+
+// part[p * G + c] = sum over problem p's entries handled by block c of a.b
+__global__ __launch_bounds__(256) void k_sdot(const Seg *segs, const double *a, const double *b,
+                                              double *part) {
+  const Seg S = segs[blockIdx.y];
+  const int G = gridDim.x;
+  __shared__ double red[16];
+  const int64_t n = S.n0 + S.n1;
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)G * blockDim.x) {
+    const int64_t i = seg_index(S, k);
+    s += a[i] * b[i];
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * G + blockIdx.x] = s;
+}
+
+// One thread per problem: fixed-order sum of its G partials, then the
+// scalar bookkeeping of the mode.
+__global__ void k_sfinal(int P, int G, const double *part, double *sc, int mode, double *hist_a,
+                         double *hist_b, int hist_ld) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double s0 = 0.0;
+  for (int c = 0; c < G; ++c) s0 += part[(int64_t)p * G + c];
+  double *q = sc + (int64_t)p * SC_STRIDE;
+  const bool done = q[SC_DONE] != 0.0;
+  switch (mode) {
+    case 0: {
+      q[SC_PQ] = s0;
+      q[SC_ACTIVE] = done ? 0.0 : 1.0;
+      if (done) {
+        q[SC_ALPHA] = 0.0;
+        break;
+      }
+      const double a = q[SC_RZ] / s0;
+      if (!(s0 > 0.0) || !(a == a)) {  // breakdown: stop this problem
+        q[SC_FLAG] = 1.0;
+        q[SC_ALPHA] = 0.0;
+        q[SC_ACTIVE] = 0.0;
+        q[SC_DONE] = 1.0;
+        q[SC_TDONE] = (double)wall_clock64();
+        break;
+      }
+      q[SC_ALPHA] = a;
+      if (hist_a) hist_a[(int64_t)p * hist_ld + (int64_t)q[SC_IT]] = a;
+      break;
+    }
+    case 1: {
+      if (q[SC_ACTIVE] == 0.0) break;
+      q[SC_RR] = s0;
+      q[SC_IT] += 1.0;
+      if (sqrt(s0) <= q[SC_TOL] * sqrt(q[SC_GG])) {
+        q[SC_DONE] = 1.0;
+        q[SC_TDONE] = (double)wall_clock64();
+      } else if (q[SC_IT] >= q[SC_MAXIT]) {
+        q[SC_FLAG] = 2.0;
+        q[SC_DONE] = 1.0;
+        q[SC_TDONE] = (double)wall_clock64();
+      }
+      break;
+    }
+    case 2: {
+      if (done) {
+        q[SC_BETA] = 0.0;
+        break;
+      }
+      const double b = s0 / q[SC_RZ];
+      q[SC_BETA] = b;
+      q[SC_RZ] = s0;
+      if (hist_b) hist_b[(int64_t)p * hist_ld + (int64_t)q[SC_IT] - 1] = b;
+      break;
+    }
+    case 3: q[SC_RZ] = s0; break;
+    case 4: q[SC_GG] = s0; break;
+    case 5: q[SC_TMP] = s0; break;
+    default: {
+      q[SC_RR] = s0;
+      if (!(sqrt(s0) > q[SC_TOL] * sqrt(q[SC_GG]))) {
+        q[SC_DONE] = 1.0;
+        q[SC_TDONE] = (double)wall_clock64();
+      }
+      break;
+    }
+  }
+}
+
+hipError_t sdot(const Seg *segs, int P, int G, const double *a, const double *b, double *part,
+                double *sc, int mode, double *hist_a, double *hist_b, int hist_ld, hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sdot, dim3(G, P), dim3(256), 0, s, segs, a, b, part);
+  hipLaunchKernelGGL(k_sfinal, dim3((P + 63) / 64), dim3(64), 0, s, P, G, part, sc, mode, hist_a,
+                     hist_b, hist_ld);
+  return hipGetLastError();
+}
+
+// x += alpha_p p ; r -= alpha_p q ; partial r.r per (problem, block)
+__global__ __launch_bounds__(256) void k_supdate_xr(const Seg *segs, const double *sc, double *x,
+                                                    double *r, const double *p, const double *q,
+                                                    double *part) {
+  const Seg S = segs[blockIdx.y];
+  const int G = gridDim.x;
+  __shared__ double red[16];
+  const double a = sc[(int64_t)blockIdx.y * SC_STRIDE + SC_ALPHA];
+  const int64_t n = S.n0 + S.n1;
+  double s = 0.0;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)G * blockDim.x) {
+    const int64_t i = seg_index(S, k);
+    x[i] += a * p[i];
+    const double ri = r[i] - a * q[i];
+    r[i] = ri;
+    s += ri * ri;
+  }
+  s = block_sum(s, red);
+  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * G + blockIdx.x] = s;
+}
+
+hipError_t supdate_xr(const Seg *segs, int P, int G, double *sc, double *x, double *r,
+                      const double *p, const double *q, double *part, hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_supdate_xr, dim3(G, P), dim3(256), 0, s, segs, sc, x, r, p, q, part);
+  hipLaunchKernelGGL(k_sfinal, dim3((P + 63) / 64), dim3(64), 0, s, P, G, part, sc, 1,
+                     (double *)nullptr, (double *)nullptr, 0);
+  return hipGetLastError();
+}
+
+__global__ void k_supdate_p(const Seg *segs, const double *sc, double *p, const double *z) {
+  const Seg S = segs[blockIdx.y];
+  const double b = sc[(int64_t)blockIdx.y * SC_STRIDE + SC_BETA];
+  const int64_t n = S.n0 + S.n1;
+  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = seg_index(S, k);
+    p[i] = z[i] + b * p[i];
+  }
+}
+
+hipError_t supdate_p(const Seg *segs, int P, int G, const double *sc, double *p, const double *z,
+                     hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_supdate_p, dim3(G, P), dim3(256), 0, s, segs, sc, p, z);
+  return hipGetLastError();
+}
+
+__global__ void k_sinit(int P, const double *tol, int maxit, double *sc) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= P) return;
+  double *q = sc + (int64_t)p * SC_STRIDE;
+  for (int k = 0; k < SC_STRIDE; ++k) q[k] = 0.0;
+  q[SC_TOL] = tol[p];
+  q[SC_MAXIT] = (double)maxit;
+  q[SC_T0] = (double)wall_clock64();
+}
+
+hipError_t sinit(int P, const double *tol, int maxit, double *sc, hipStream_t s) {
+  if (P <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_sinit, dim3((P + 63) / 64), dim3(64), 0, s, P, tol, maxit, sc);
+  return hipGetLastError();
+}
 }  // namespace vb

@@ -107,6 +107,25 @@ struct vb_ctx {
   EntDev *d_entdev = nullptr;
   std::vector<SubDev> subdev;
   std::vector<EntDev> entdev, entdev0;
+  // independent problems assembled into this context (appended by vb_assemble)
+  struct Prob {
+    int64_t g0 = 0, ng = 0;  // interface ids [g0, g0 + ng)
+    int s0 = 0, ns = 0;      // subdomains [s0, s0 + ns); p0 entries at nG + s
+    int e0 = 0, ne = 0;      // entities [e0, e0 + ne)
+    int cbase = 0, nprim = 0;  // coarse block [cbase, cbase + nprim + ns)
+  };
+  std::vector<Prob> probs;
+  bool finalized = false;
+  Seg *d_segs = nullptr;
+  int seg_G = 1;
+  double *d_tol = nullptr;
+  int max_ncs = 0;
+  std::vector<int32_t> ent_cbase, sub_cp0;
+  std::vector<int64_t> gc_off;  // per problem: offset of its coarse inverse in Gc
+  hipGraph_t it_graph = nullptr;
+  hipGraphExec_t it_exec = nullptr;
+  std::vector<vb_solve_info> pinfo;  // per problem, last solve
+  double clock_khz = 0.0;
   // adaptive coarse space of the last setup
   std::vector<vb_face_info> face_info;
   std::vector<double> face_eigs;
@@ -250,6 +269,8 @@ static void free_list(std::vector<void *> &v) {
 void vb_destroy(vb_ctx *ctx) {
   if (!ctx) return;
   (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->it_exec) (void)hipGraphExecDestroy(ctx->it_exec);
+  if (ctx->it_graph) (void)hipGraphDestroy(ctx->it_graph);
   free_list(ctx->setup_allocs);
   free_list(ctx->setup_keep);
   ctx->t_ldl.destroy();
@@ -267,23 +288,31 @@ int64_t vb_interface_size(const vb_ctx *ctx) { return ctx ? ctx->nG + ctx->nS : 
 int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs, int n_ent,
                 const vb_entity *ents) {
   if (!ctx) return VB_ERR_ARG;
-  if (ctx->state != 0) return ctx->fail(VB_ERR_STATE, "vb_assemble: already assembled");
+  if (ctx->state > 1 || ctx->finalized)
+    return ctx->fail(VB_ERR_STATE, "vb_assemble: problems can only be added before vb_setup");
   if (n_iface < 0 || n_sub <= 0 || !subs || n_ent < 0 || (n_ent > 0 && !ents))
     return ctx->fail(VB_ERR_ARG, "vb_assemble: bad sizes");
-  ctx->nG = n_iface;
-  ctx->nS = n_sub;
+  vb_ctx::Prob P;
+  P.g0 = ctx->nG;
+  P.ng = n_iface;
+  P.s0 = ctx->nS;
+  P.ns = n_sub;
+  P.e0 = (int)ctx->ents.size();
+  P.ne = n_ent;
+  const int64_t g0 = P.g0;
+  const int s0 = P.s0, e0 = P.e0;
   // entities
   std::vector<int32_t> ent_of(n_iface, -1), pos_in(n_iface, -1);
-  ctx->ents.resize(n_ent);
+  ctx->ents.resize(e0 + n_ent);
   for (int e = 0; e < n_ent; ++e) {
     const vb_entity &E = ents[e];
     if (E.n <= 0 || !E.gids || E.n_con < 0 || (E.n_con > 0 && !E.con) || E.n_con > 1024)
       return ctx->fail(VB_ERR_ARG, "vb_assemble: bad entity " + std::to_string(e));
-    EntH &H = ctx->ents[e];
+    EntH &H = ctx->ents[e0 + e];
     H.kind = E.kind;
     H.n = E.n;
     H.ncon = E.n_con;
-    H.gids.assign(E.gids, E.gids + E.n);
+    H.gids.resize(E.n);
     H.con.assign(E.con, E.con + (size_t)E.n_con * E.n);
     for (int j = 0; j < E.n; ++j) {
       int64_t g = E.gids[j];
@@ -291,21 +320,23 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
         return ctx->fail(VB_ERR_ARG, "vb_assemble: entity ids must cover each interface id once");
       ent_of[g] = e;
       pos_in[g] = j;
+      H.gids[j] = g0 + g;
     }
   }
   for (int64_t g = 0; g < n_iface; ++g)
     if (ent_of[g] < 0) return ctx->fail(VB_ERR_ARG, "vb_assemble: interface id not in any entity");
   // subdomains
-  ctx->subs.resize(n_sub);
-  for (int s = 0; s < n_sub; ++s) {
-    const vb_subdomain &D = subs[s];
+  ctx->subs.resize(s0 + n_sub);
+  for (int sl = 0; sl < n_sub; ++sl) {
+    const int s = s0 + sl;
+    const vb_subdomain &D = subs[sl];
     SubH &S = ctx->subs[s];
     if (D.n <= 0 || !D.indptr || !D.indices || !D.data || !D.kind || !D.gid || !D.pweight || !D.rhs)
-      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad subdomain " + std::to_string(s));
+      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad subdomain " + std::to_string(sl));
     S.n = D.n;
     S.indptr.assign(D.indptr, D.indptr + D.n + 1);
     if (S.indptr[0] != 0 || S.indptr[D.n] != D.nnz)
-      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad indptr in subdomain " + std::to_string(s));
+      return ctx->fail(VB_ERR_ARG, "vb_assemble: bad indptr in subdomain " + std::to_string(sl));
     S.indices.resize(D.nnz);
     for (int64_t q = 0; q < D.nnz; ++q) {
       if (D.indices[q] < 0 || D.indices[q] >= D.n)
@@ -325,6 +356,7 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
         int64_t g = S.gid[i];
         if (g < 0 || g >= n_iface) return ctx->fail(VB_ERR_ARG, "vb_assemble: bad gid");
         iface.push_back({((int64_t)ent_of[g] << 32) | pos_in[g], i});
+        S.gid[i] = g0 + g;
       } else
         return ctx->fail(VB_ERR_ARG, "vb_assemble: bad kind");
     }
@@ -337,6 +369,7 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     S.pos.assign(D.n, -1);
     int cv = 0, cp = 0;
     S.pw.clear();
+    S.vol = 0.0;
     for (int i = 0; i < D.n; ++i) {
       if (S.kind[i] == VB_KIND_INTERIOR) S.pos[i] = cv++;
       else if (S.kind[i] == VB_KIND_PRESSURE) {
@@ -352,7 +385,7 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
       int i = iface[l].second;
       S.pos[i] = S.nv + S.nel + l;
       S.gidl[l] = S.gid[i];
-      int e = ent_of[S.gid[i]];
+      int e = e0 + ent_of[S.gid[i] - g0];
       if (S.ents.empty() || S.ents.back() != e) {
         S.ents.push_back(e);
         S.ent_off.push_back(l);
@@ -362,8 +395,8 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
       int e = S.ents[q];
       int cnt = (q + 1 < S.ents.size() ? S.ent_off[q + 1] : S.ng) - S.ent_off[q];
       if (cnt != ctx->ents[e].n)
-        return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(s) +
-                                         " holds only part of entity " + std::to_string(e));
+        return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(sl) +
+                                         " holds only part of entity " + std::to_string(e - e0));
       ctx->ents[e].subs.push_back(s);
     }
     ctx->max_n_csr = std::max(ctx->max_n_csr, S.n);
@@ -372,6 +405,21 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     ctx->max_ng = std::max(ctx->max_ng, S.ng);
     ctx->max_ent = std::max(ctx->max_ent, (int)S.ents.size());
   }
+  ctx->nG += n_iface;
+  ctx->nS += n_sub;
+  ctx->probs.push_back(P);
+  ctx->state = 1;
+  return VB_OK;
+}
+
+}  // extern "C"
+
+// Device copies of every assembled problem and the dense workspace (run by
+// the first vb_setup, once all problems are known).
+static int finalize_device(vb_ctx *ctx) {
+  const int n_sub = ctx->nS;
+  const int n_ent = (int)ctx->ents.size();
+  const int64_t n_iface = ctx->nG;
   // ---- device copies of the caller's data and the dense workspace
   int64_t wtot = 0, itot = 0, btot = 0, htot = 0;
   for (auto &S : ctx->subs) {
@@ -463,9 +511,24 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     H.d_tau0 = H.d_tau;
     H.d_work0 = H.d_work;
   }
-  ctx->state = 1;
+  // problem segments of the global interface vector
+  std::vector<Seg> segs;
+  int64_t maxn = 1;
+  for (auto &P : ctx->probs) {
+    segs.push_back({P.g0, P.ng, ctx->nG + P.s0, P.ns});
+    maxn = std::max<int64_t>(maxn, P.ng + P.ns);
+  }
+  CHK(ctx->upload(&ctx->d_segs, segs));
+  ctx->seg_G = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (maxn + 255) / 256));
+  CHK(ctx->dalloc(&ctx->d_tol, ctx->probs.size()));
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) == hipSuccess)
+    ctx->clock_khz = khz;
+  ctx->finalized = true;
   return VB_OK;
 }
+
+extern "C" {
 
 }  // extern "C"
 
@@ -1374,6 +1437,16 @@ static int setup_impl(vb_ctx *ctx);
 int vb_setup(vb_ctx *ctx) {
   if (!ctx) return VB_ERR_ARG;
   if (ctx->state < 1) return ctx->fail(VB_ERR_STATE, "vb_setup: call vb_assemble first");
+  if (!ctx->finalized) {
+    int rc = finalize_device(ctx);
+    if (rc) return rc;
+  }
+  if (ctx->it_exec) {  // the captured iteration refers to the previous setup's buffers
+    (void)hipGraphExecDestroy(ctx->it_exec);
+    (void)hipGraphDestroy(ctx->it_graph);
+    ctx->it_exec = nullptr;
+    ctx->it_graph = nullptr;
+  }
   if (ctx->state == 2) {  // a new setup replaces the previous one
     CHK(hipStreamSynchronize(ctx->stream));
     free_list(ctx->setup_keep);
@@ -1463,11 +1536,26 @@ static int setup_impl(vb_ctx *ctx) {
       if (rc) return rc;
     }
   }
-  // coarse numbering
+  // coarse numbering, one contiguous block per problem:
+  // [primal coordinates of its entities | p0 of its subdomains]
   std::vector<int32_t> cstart(nE + 1, 0);
   for (int e = 0; e < nE; ++e) cstart[e + 1] = cstart[e] + ctx->ents[e].rank;
   ctx->nC = cstart[nE];
   ctx->nCS = ctx->nC + nS;
+  ctx->ent_cbase.assign(nE, 0);
+  ctx->sub_cp0.assign(nS, 0);
+  ctx->max_ncs = 0;
+  {
+    int cb = 0;
+    for (auto &P : ctx->probs) {
+      P.cbase = cb;
+      P.nprim = cstart[P.e0 + P.ne] - cstart[P.e0];
+      for (int e = P.e0; e < P.e0 + P.ne; ++e) ctx->ent_cbase[e] = cb + cstart[e] - cstart[P.e0];
+      for (int s = P.s0; s < P.s0 + P.ns; ++s) ctx->sub_cp0[s] = cb + P.nprim + (s - P.s0);
+      cb += P.nprim + P.ns;
+      ctx->max_ncs = std::max(ctx->max_ncs, P.nprim + P.ns);
+    }
+  }
   for (int s = 0; s < nS; ++s) {
     SubH &S = ctx->subs[s];
     S.pl.clear();
@@ -1480,7 +1568,7 @@ static int setup_impl(vb_ctx *ctx) {
       for (int j = 0; j < H.n; ++j) {
         if (j < H.rank) {
           S.pl.push_back(S.ent_off[q] + j);
-          S.cidx.push_back(cstart[S.ents[q]] + j);
+          S.cidx.push_back(ctx->ent_cbase[S.ents[q]] + j);
         } else {
           S.dl.push_back(S.ent_off[q] + j);
         }
@@ -1664,58 +1752,92 @@ static int setup_impl(vb_ctx *ctx) {
     rc = run_gather(ctx, ej, mxr, mxc);
     if (rc) return rc;
   }
-  // ---- 7. coarse problem
+  // ---- 7. coarse problem: per problem, the inverse of the bordered coarse
+  // matrix from the partial LDL^T of [[K_c, I], [I, 0]]
   {
-    const int nCS = ctx->nCS;
-    ctx->Kld = round_up(2 * nCS, 32);
-    CHK(ctx->dalloc(&ctx->Kaug, ctx->Kld * 2 * nCS, true));
-    CHK(hipMemsetAsync(ctx->Kaug, 0, ctx->Kld * 2 * nCS * sizeof(double), st));
-    std::vector<CoarseSub> cs(nS);
-    for (int s = 0; s < nS; ++s) {
-      SubH &S = ctx->subs[s];
-      int32_t *dc = nullptr, *dp = nullptr;
-      CHK(ctx->upload(&dc, S.cidx, true));
-      CHK(ctx->upload(&dp, S.pl, true));
-      cs[s] = {S.Nmat + S.ndl + S.ndl * S.Nld, S.Nld, S.npi, dc, dp, ctx->b0 + S.b0_off};
+    const int nP = (int)ctx->probs.size();
+    std::vector<int64_t> koff(nP), goff(nP), ldk(nP);
+    int64_t ktot = 0, gtot = 0, itot = 0;
+    for (int pp = 0; pp < nP; ++pp) {
+      const int ncs = ctx->probs[pp].nprim + ctx->probs[pp].ns;
+      ldk[pp] = round_up(2 * ncs, 32);
+      koff[pp] = ktot;
+      ktot += ldk[pp] * 2 * ncs;
+      goff[pp] = gtot;
+      gtot += (int64_t)ncs * ncs;
+      itot += (int64_t)((ncs + NB - 1) / NB) * NB * NB;
     }
-    CoarseSub *dcs = nullptr;
-    CHK(ctx->upload(&dcs, cs, true));
-    double vn = 0.0;
-    for (auto &S : ctx->subs) vn += S.vol * S.vol;
-    vn = std::sqrt(vn);
-    std::vector<double> w(nS);
-    for (int s = 0; s < nS; ++s) w[s] = ctx->subs[s].vol / vn;
-    double *dw = nullptr;
-    CHK(ctx->upload(&dw, w, true));
-    CHK(coarse_assemble(dcs, nS, ctx->Kaug, ctx->Kld, ctx->nC, dw, st));
-    std::vector<DiagJob> dj{{ctx->Kaug, ctx->Kld, nCS, 0, nCS, 1.0}};
-    int rc = run_diag(ctx, dj, nCS);
-    if (rc) return rc;
+    ctx->Kld = nP == 1 ? ldk[0] : 0;
+    CHK(ctx->dalloc(&ctx->Kaug, std::max<int64_t>(ktot, 1), true));
+    CHK(hipMemsetAsync(ctx->Kaug, 0, ktot * sizeof(double), st));
+    CHK(ctx->dalloc(&ctx->Gc, std::max<int64_t>(gtot, 1)));
     double *invC = nullptr;
-    CHK(ctx->dalloc(&invC, (int64_t)((nCS + NB - 1) / NB) * NB * NB, true));
-    std::vector<LdlJob<double>> lj{{ctx->Kaug, ctx->Kld, 2 * nCS, nCS, ctx->nC, 0, invC,
-                                    ctx->info + nS}};
-    rc = run_ldl(ctx, lj, 2 * nCS, nCS);
+    CHK(ctx->dalloc(&invC, std::max<int64_t>(itot, 1), true));
+    std::vector<DiagJob> dj;
+    std::vector<LdlJob<double>> lj;
+    std::vector<void *> m;
+    std::vector<int64_t> ld;
+    std::vector<int32_t> n;
+    std::vector<GatherJob> gj;
+    int32_t *di = nullptr;
+    {
+      std::vector<int32_t> iota(std::max(ctx->max_ncs, 1));
+      std::iota(iota.begin(), iota.end(), 0);
+      CHK(ctx->upload(&di, iota, true));
+    }
+    int64_t io = 0;
+    for (int pp = 0; pp < nP; ++pp) {
+      const auto &P = ctx->probs[pp];
+      const int ncs = P.nprim + P.ns;
+      double *K = ctx->Kaug + koff[pp];
+      std::vector<CoarseSub> cs(P.ns);
+      for (int sl = 0; sl < P.ns; ++sl) {
+        SubH &S = ctx->subs[P.s0 + sl];
+        std::vector<int32_t> cl(S.cidx.size());
+        for (size_t a = 0; a < cl.size(); ++a) cl[a] = S.cidx[a] - P.cbase;
+        int32_t *dc = nullptr, *dp = nullptr;
+        CHK(ctx->upload(&dc, cl, true));
+        CHK(ctx->upload(&dp, S.pl, true));
+        cs[sl] = {S.Nmat + S.ndl + S.ndl * S.Nld, S.Nld, S.npi, dc, dp, ctx->b0 + S.b0_off};
+      }
+      CoarseSub *dcs = nullptr;
+      CHK(ctx->upload(&dcs, cs, true));
+      double vn = 0.0;
+      for (int sl = 0; sl < P.ns; ++sl) vn += ctx->subs[P.s0 + sl].vol * ctx->subs[P.s0 + sl].vol;
+      vn = std::sqrt(vn);
+      std::vector<double> w(P.ns);
+      for (int sl = 0; sl < P.ns; ++sl) w[sl] = ctx->subs[P.s0 + sl].vol / vn;
+      double *dw = nullptr;
+      CHK(ctx->upload(&dw, w, true));
+      CHK(coarse_assemble(dcs, P.ns, K, ldk[pp], P.nprim, dw, st));
+      dj.push_back({K, ldk[pp], ncs, 0, ncs, 1.0});
+      lj.push_back({K, ldk[pp], 2 * ncs, ncs, P.nprim, 0, invC + io, ctx->info + nS + pp});
+      io += (int64_t)((ncs + NB - 1) / NB) * NB * NB;
+      m.push_back(K + ncs + ncs * ldk[pp]);
+      ld.push_back(ldk[pp]);
+      n.push_back(ncs);
+      gj.push_back({K + ncs + ncs * ldk[pp], ldk[pp], ctx->Gc + goff[pp], ncs, di, di, ncs, ncs,
+                    -1.0, 0, 0, 0});
+    }
+    int rc = run_diag(ctx, dj, ctx->max_ncs);
+    if (rc) return rc;
+    rc = run_ldl(ctx, lj, 2 * ctx->max_ncs, ctx->max_ncs);
     if (rc) return rc;
     {
-      std::vector<int> h(1);
-      CHK(hipMemcpyAsync(h.data(), ctx->info + nS, sizeof(int), hipMemcpyDeviceToHost, st));
+      std::vector<int> h(nP);
+      CHK(hipMemcpyAsync(h.data(), ctx->info + nS, nP * sizeof(int), hipMemcpyDeviceToHost, st));
       CHK(hipStreamSynchronize(st));
-      if (h[0]) return ctx->fail(VB_ERR_SINGULAR_COARSE, "coarse factorisation: pivot breakdown at column " + std::to_string(h[0] - 1));
+      for (int pp = 0; pp < nP; ++pp)
+        if (h[pp])
+          return ctx->fail(VB_ERR_SINGULAR_COARSE, "coarse factorisation of problem " +
+                                                       std::to_string(pp) + ": pivot breakdown at column " +
+                                                       std::to_string(h[pp] - 1));
     }
-    std::vector<void *> m{ctx->Kaug + nCS + nCS * ctx->Kld};
-    std::vector<int64_t> ld{ctx->Kld};
-    std::vector<int32_t> n{nCS};
     rc = run_symm(ctx, m, ld, n);
     if (rc) return rc;
-    CHK(ctx->dalloc(&ctx->Gc, (int64_t)nCS * nCS));
-    std::vector<int32_t> iota(nCS);
-    std::iota(iota.begin(), iota.end(), 0);
-    int32_t *di = nullptr;
-    CHK(ctx->upload(&di, iota, true));
-    std::vector<GatherJob> gj{{m[0], ctx->Kld, ctx->Gc, nCS, di, di, nCS, nCS, -1.0, 0, 0, 0}};
-    rc = run_gather(ctx, gj, nCS, nCS);
+    rc = run_gather(ctx, gj, ctx->max_ncs, ctx->max_ncs);
     if (rc) return rc;
+    ctx->gc_off = goff;
   }
   // ---- 8. scaling: deluxe D_E^(s) = (sum_l Sbar^(l))^-1 Sbar^(s) on the duals
   {
@@ -1817,10 +1939,11 @@ static int setup_impl(vb_ctx *ctx) {
     CHK(ctx->dalloc(&ctx->p, nTot));
     CHK(ctx->dalloc(&ctx->q, nTot));
     CHK(ctx->dalloc(&ctx->tmp, nTot));
-    CHK(ctx->dalloc(&ctx->sc, SC_COUNT));
-    CHK(ctx->dalloc(&ctx->part, 2 * DOT_BLOCKS));
-    CHK(ctx->dalloc(&ctx->hist_a, ctx->opt.maxit + 2));
-    CHK(ctx->dalloc(&ctx->hist_b, ctx->opt.maxit + 2));
+    CHK(ctx->dalloc(&ctx->sc, SC_STRIDE * ctx->probs.size()));
+    CHK(ctx->dalloc(&ctx->part, std::max<int64_t>(2 * DOT_BLOCKS, (int64_t)ctx->seg_G * ctx->probs.size())));
+    const int64_t nP = (int64_t)ctx->probs.size();
+    CHK(ctx->dalloc(&ctx->hist_a, (ctx->opt.maxit + 2) * nP));
+    CHK(ctx->dalloc(&ctx->hist_b, (ctx->opt.maxit + 2) * nP));
     // S_hat: per-subdomain bordered GEMV (reads p) + owner sums (into q)
     std::vector<GemvJob> js(nS);
     int64_t yoff = 0;
@@ -1904,17 +2027,22 @@ static int setup_impl(vb_ctx *ctx) {
     CHK(ctx->upload(&ctx->j_schur, js));
     CHK(ctx->upload(&ctx->j_neu1, jn1));
     CHK(ctx->upload(&ctx->j_neu2, jn2));
-    std::vector<GemvJob> jc{{ctx->Gc, ctx->nCS, ctx->nCS, ctx->nCS, ctx->rc, nullptr, nullptr,
-                             ctx->uc, 1.0, 0}};
+    std::vector<GemvJob> jc;
+    for (size_t pp = 0; pp < ctx->probs.size(); ++pp) {
+      const auto &P = ctx->probs[pp];
+      const int ncs = P.nprim + P.ns;
+      jc.push_back({ctx->Gc + ctx->gc_off[pp], ncs, ncs, ncs, ctx->rc + P.cbase, nullptr, nullptr,
+                    ctx->uc + P.cbase, 1.0, 0});
+    }
     CHK(ctx->upload(&ctx->j_coarse, jc));
     // coarse rhs: base = r at the primal positions (or p0), owners = Phi^T g contributions
     std::vector<int64_t> base(ctx->nCS), dst(ctx->nCS);
     std::vector<std::vector<int64_t>> cown(ctx->nCS);
     for (int e = 0; e < nE; ++e) {
       EntH &H = ctx->ents[e];
-      for (int j = 0; j < H.rank; ++j) base[cstart[e] + j] = H.gids[j];
+      for (int j = 0; j < H.rank; ++j) base[ctx->ent_cbase[e] + j] = H.gids[j];
     }
-    for (int s = 0; s < nS; ++s) base[ctx->nC + s] = nG + s;
+    for (int s = 0; s < nS; ++s) base[ctx->sub_cp0[s]] = nG + s;
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       for (int a = 0; a < S.npi; ++a) cown[S.cidx[a]].push_back(sto[s] + S.ndl + a);
@@ -2034,7 +2162,7 @@ static int apply_M_internal(vb_ctx *ctx) {  // z <- M~^-1 r
   if (ctx->n_restrict) CHK(gemv_t(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm, st));
   CHK(gemv_t(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, st));
   CHK(owner_sum(ctx->nCS, ctx->c_ptr, ctx->c_idx, ctx->tv, ctx->c_base, ctx->r, ctx->rc, st));
-  CHK(gemv_t(ctx->j_coarse, 1, ctx->nCS, ctx->nCS, st));
+  CHK(gemv_t(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, ctx->max_ncs, st));
   if (ctx->max_ndl) CHK(gemv_n(ctx->j_neu2, ctx->nS, ctx->max_ndl, ctx->max_npi, st));
   if (ctx->n_ext) CHK(extend(ctx->j_ext, ctx->n_ext, ctx->max_ext_m, ctx->j_extpart, ctx->wv, ctx->z, st));
   CHK(scatter_copy(ctx->nCS, ctx->uc, nullptr, ctx->uc_dst, ctx->z, 1.0, st));
@@ -2125,20 +2253,42 @@ extern "C" {
 
 }  // extern "C"
 
-// PCG on S~ x~ = b~ in the transformed coordinates (Sec. 7), on ctx->x.
+// PCG on S~ x~ = b~ in the transformed coordinates (Sec. 7), on ctx->x, for
+// every problem of the context at once: the operators are block diagonal
+// over the problems, the recurrences keep one set of scalars per problem
+// (segmented reductions), and a problem that has converged keeps its
+// iterate (alpha = 0) while the others continue.
 // x_zero: start from x~ = 0 (r = b) instead of the current ctx->x.
-// record: keep the Lanczos coefficients (alpha_k, beta_k) in hist_a/hist_b.
+// tol[p]: relative tolerance of problem p.  The Lanczos coefficients of each
+// problem are kept in hist_a/hist_b (leading dimension maxit + 2).
 struct PcgResult {
-  int it = 0, status = VB_OK;
-  double rel = 0.0, bnorm = 0.0;
+  int it = 0, status = VB_OK;  // over all problems: largest count, worst status
+  double rel = 0.0;
+  std::vector<double> sc;      // per-problem scalars at exit (SC_STRIDE each)
 };
 
-static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, double tol, int maxit, bool record,
-                    PcgResult *res) {
+static int pcg_body(vb_ctx *ctx) {
   hipStream_t st = ctx->stream;
+  const int P = (int)ctx->probs.size(), G = ctx->seg_G, ld = ctx->opt.maxit + 2;
+  int rc = apply_S_internal(ctx);
+  if (rc) return rc;
+  CHK(sdot(ctx->d_segs, P, G, ctx->p, ctx->q, ctx->part, ctx->sc, 0, ctx->hist_a, nullptr, ld, st));
+  CHK(supdate_xr(ctx->d_segs, P, G, ctx->sc, ctx->x, ctx->r, ctx->p, ctx->q, ctx->part, st));
+  rc = apply_M_internal(ctx);
+  if (rc) return rc;
+  CHK(sdot(ctx->d_segs, P, G, ctx->r, ctx->z, ctx->part, ctx->sc, 2, nullptr, ctx->hist_b, ld, st));
+  CHK(supdate_p(ctx->d_segs, P, G, ctx->sc, ctx->p, ctx->z, st));
+  return VB_OK;
+}
+
+static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, const std::vector<double> &tol,
+                    int maxit, PcgResult *res) {
+  hipStream_t st = ctx->stream;
+  const int P = (int)ctx->probs.size(), G = ctx->seg_G, ld = ctx->opt.maxit + 2;
   const int64_t n = ctx->nG + ctx->nS;
-  double hs[SC_COUNT];
-  CHK(hipMemsetAsync(ctx->sc, 0, SC_COUNT * sizeof(double), st));
+  maxit = std::max(0, std::min(maxit, ctx->opt.maxit));
+  CHK(hipMemcpyAsync(ctx->d_tol, tol.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(sinit(P, ctx->d_tol, maxit, ctx->sc, st));
   if (x_zero) {
     CHK(hipMemsetAsync(ctx->x, 0, n * sizeof(double), st));
     CHK(hipMemcpyAsync(ctx->r, b, n * sizeof(double), hipMemcpyDeviceToDevice, st));
@@ -2148,56 +2298,89 @@ static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, double tol, int m
     if (rc) return rc;
     CHK(vsub(n, b, ctx->q, ctx->r, st));
   }
-  CHK(dot(n, b, b, ctx->part, ctx->sc, 4, 0, nullptr, nullptr, st));
-  CHK(dot(n, ctx->r, ctx->r, ctx->part, ctx->sc, 1, 0, nullptr, nullptr, st));
-  CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  CHK(sdot(ctx->d_segs, P, G, b, b, ctx->part, ctx->sc, 4, nullptr, nullptr, ld, st));
+  CHK(sdot(ctx->d_segs, P, G, ctx->r, ctx->r, ctx->part, ctx->sc, 6, nullptr, nullptr, ld, st));
+  int rc = apply_M_internal(ctx);
+  if (rc) return rc;
+  CHK(sdot(ctx->d_segs, P, G, ctx->r, ctx->z, ctx->part, ctx->sc, 3, nullptr, nullptr, ld, st));
+  CHK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+  // iterations: a replayed HIP graph of one iteration when a stream of our
+  // own is given and launches are not being timed one by one; the host reads
+  // the per-problem flags every `every` iterations (the flags freeze
+  // converged problems in between)
+  const bool graph_ok = ctx->stream != nullptr && !ctx->opt.profile;
+  const int every = (ctx->schur_bytes > 4e8) ? 1 : 4;
+  std::vector<double> hs((size_t)P * SC_STRIDE);
+  CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
-  const double bn = std::sqrt(hs[SC_GG]);
-  double rel = bn > 0 ? std::sqrt(hs[SC_RR]) / bn : 0.0;
-  int it = 0, status = VB_OK;
-  double *ha = record ? ctx->hist_a : nullptr, *hb = record ? ctx->hist_b : nullptr;
-  if (rel > tol) {
-    int rc = apply_M_internal(ctx);
-    if (rc) return rc;
-    CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 3, 0, nullptr, nullptr, st));
-    CHK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-    while (true) {
-      rc = apply_S_internal(ctx);
-      if (rc) return rc;
-      CHK(dot(n, ctx->p, ctx->q, ctx->part, ctx->sc, 0, it, ha, nullptr, st));
-      CHK(update_xr(n, ctx->sc, ctx->x, ctx->r, ctx->p, ctx->q, ctx->part, ctx->sc, st));
-      CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
-      CHK(hipStreamSynchronize(st));
-      ++it;
-      if (hs[SC_FLAG] != 0.0) {
-        status = VB_ERR_BREAKDOWN;
-        break;
+  auto all_done = [&]() {
+    for (int pp = 0; pp < P; ++pp)
+      if (hs[(size_t)pp * SC_STRIDE + SC_DONE] == 0.0) return false;
+    return true;
+  };
+  int launched = 0;
+  bool first = true;
+  while (!all_done() && launched < maxit + every) {
+    for (int k = 0; k < every; ++k) {
+      if (graph_ok && !first) {
+        if (!ctx->it_exec) {
+          CHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+          int rc2 = pcg_body(ctx);
+          hipError_t e = hipStreamEndCapture(st, &ctx->it_graph);
+          if (rc2) return rc2;
+          CHK(e);
+          CHK(hipGraphInstantiate(&ctx->it_exec, ctx->it_graph, nullptr, nullptr, 0));
+        }
+        CHK(hipGraphLaunch(ctx->it_exec, st));
+      } else {  // the first iteration also runs every one-time attribute call
+        rc = pcg_body(ctx);
+        if (rc) return rc;
+        first = false;
       }
-      rel = std::sqrt(hs[SC_RR]) / bn;
-      if (rel <= tol) break;
-      if (it >= maxit) {
-        status = VB_ERR_NOT_CONVERGED;
-        break;
-      }
-      rc = apply_M_internal(ctx);
-      if (rc) return rc;
-      CHK(dot(n, ctx->r, ctx->z, ctx->part, ctx->sc, 2, it - 1, nullptr, hb, st));
-      CHK(update_p(n, ctx->sc, ctx->p, ctx->z, st));
+      ++launched;
     }
+    CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
   }
-  res->it = it;
-  res->status = status;
-  res->rel = rel;
-  res->bnorm = bn;
+  res->it = 0;
+  res->rel = 0.0;
+  res->status = VB_OK;
+  for (int pp = 0; pp < P; ++pp) {
+    const double *q = hs.data() + (size_t)pp * SC_STRIDE;
+    res->it = std::max(res->it, (int)q[SC_IT]);
+    const double rel = q[SC_GG] > 0 ? std::sqrt(q[SC_RR] / q[SC_GG]) : 0.0;
+    res->rel = std::max(res->rel, rel);
+    if (q[SC_FLAG] == 1.0) res->status = VB_ERR_BREAKDOWN;
+    else if ((q[SC_FLAG] == 2.0 || q[SC_DONE] == 0.0) && res->status == VB_OK)
+      res->status = VB_ERR_NOT_CONVERGED;
+  }
+  res->sc = hs;
   return VB_OK;
 }
 
-static int fill_lanczos(vb_ctx *ctx, int it, vb_solve_info *info) {
+static int lanczos_problem(vb_ctx *ctx, int pp, int it, double *lmin, double *lmax) {
+  const int ld = ctx->opt.maxit + 2;
   std::vector<double> a(it), b(it > 0 ? it - 1 : 0);
-  if (it) CHK(hipMemcpy(a.data(), ctx->hist_a, it * sizeof(double), hipMemcpyDeviceToHost));
-  if (it > 1) CHK(hipMemcpy(b.data(), ctx->hist_b, (it - 1) * sizeof(double), hipMemcpyDeviceToHost));
-  lanczos_extremes(a, b, &info->lambda_min, &info->lambda_max);
+  if (it) CHK(hipMemcpy(a.data(), ctx->hist_a + (int64_t)pp * ld, it * sizeof(double), hipMemcpyDeviceToHost));
+  if (it > 1) CHK(hipMemcpy(b.data(), ctx->hist_b + (int64_t)pp * ld, (it - 1) * sizeof(double), hipMemcpyDeviceToHost));
+  lanczos_extremes(a, b, lmin, lmax);
   return VB_OK;
+}
+
+// Combined info over the problems (the single problem's own when there is one).
+static void combine_info(const std::vector<vb_solve_info> &pi, vb_solve_info *out) {
+  *out = pi[0];
+  for (size_t k = 1; k < pi.size(); ++k) {
+    const vb_solve_info &q = pi[k];
+    out->iterations = std::max(out->iterations, q.iterations);
+    out->refinement_steps = std::max(out->refinement_steps, q.refinement_steps);
+    out->rel_residual = std::max(out->rel_residual, q.rel_residual);
+    out->true_rel_residual = std::max(out->true_rel_residual, q.true_rel_residual);
+    out->lambda_min = std::min(out->lambda_min, q.lambda_min);
+    out->lambda_max = std::max(out->lambda_max, q.lambda_max);
+    out->latency_ms = std::max(out->latency_ms, q.latency_ms);
+    if (q.status != VB_OK && out->status == VB_OK) out->status = q.status;
+  }
 }
 
 // One pass of the FP64 residual condensation used by the refinement:
@@ -2239,72 +2422,113 @@ static int interior_correction(vb_ctx *ctx, const double *dx) {
 // solve.  Each outer step condenses the FP64 residual of the local systems,
 // solves the interface correction with PCG on the FP32 operators to a loose
 // relative tolerance, recovers the interior correction with the FP32
-// factor and updates (x, interior state).  Stops when the condensed
-// residual has dropped by opt.tol relative to the first one.
+// factor and updates (x, interior state).  A problem stops when its
+// condensed residual has dropped by opt.tol relative to its first one.
 static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
   hipStream_t st = ctx->stream;
   const int64_t n = ctx->nG + ctx->nS;
   const int nE = (int)ctx->ents.size();
+  const int P = (int)ctx->probs.size(), G = ctx->seg_G;
   const int max_outer = 30;
   const double inner_floor = 1e-4;
-  double hs[SC_COUNT];
   CHK(hipEventRecord(ctx->ev0, st));
   CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
-  double r_first = 0.0, rel = 0.0;
-  int outer = 0, inner = 0, status = VB_OK, first_it = 0;
+  std::vector<double> r_first(P, 0.0), rel(P, 0.0), t0(P, 0.0), tdone(P, 0.0);
+  std::vector<int> steps(P, 0), inner(P, 0), done(P, 0);
+  std::vector<vb_solve_info> pi(P);
+  int outer = 0, status = VB_OK, inner_max = 0;
+  std::vector<double> hs((size_t)P * SC_STRIDE), one(P, 1.0);
+  // a clock reference for the latencies: the scalars' T0 of an empty init
+  CHK(hipMemcpyAsync(ctx->d_tol, one.data(), P * sizeof(double), hipMemcpyHostToDevice, st));
+  CHK(sinit(P, ctx->d_tol, 0, ctx->sc, st));
+  CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  for (int pp = 0; pp < P; ++pp) t0[pp] = hs[(size_t)pp * SC_STRIDE + SC_T0];
   while (true) {
     int rc = condense_residual(ctx, x_dev);
     if (rc) return rc;
     CHK(owner_sum((int)ctx->nG, ctx->ir_ptr, ctx->ir_idx, ctx->y_ir, nullptr, nullptr, ctx->dgv,
                   st));
     CHK(scatter_copy(ctx->nS, ctx->r0, nullptr, nullptr, ctx->dgv + ctx->nG, 1.0, st));
-    CHK(dot(n, ctx->dgv, ctx->dgv, ctx->part, ctx->sc, 5, 0, nullptr, nullptr, st));
-    CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+    CHK(sdot(ctx->d_segs, P, G, ctx->dgv, ctx->dgv, ctx->part, ctx->sc, 5, nullptr, nullptr, 0, st));
+    CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
-    const double rn = std::sqrt(hs[SC_TMP]);
-    if (outer == 0) r_first = rn;
-    rel = r_first > 0 ? rn / r_first : 0.0;
-    if (!(rel > ctx->opt.tol)) break;
-    if (outer >= max_outer || inner >= ctx->opt.maxit) {
+    bool all = true;
+    std::vector<double> tin(P);
+    for (int pp = 0; pp < P; ++pp) {
+      const double rn = std::sqrt(hs[(size_t)pp * SC_STRIDE + SC_TMP]);
+      if (outer == 0) r_first[pp] = rn;
+      rel[pp] = r_first[pp] > 0 ? rn / r_first[pp] : 0.0;
+      if (!done[pp] && !(rel[pp] > ctx->opt.tol)) {
+        done[pp] = 1;
+        tdone[pp] = outer;  // marks the outer step; the clock is taken below
+      }
+      if (!done[pp]) all = false;
+      tin[pp] = done[pp] ? 1e300 : std::max(inner_floor, 0.5 * ctx->opt.tol / std::max(rel[pp], 1e-300));
+    }
+    if (all) break;
+    if (outer >= max_outer || inner_max >= ctx->opt.maxit) {
       status = VB_ERR_NOT_CONVERGED;
       break;
     }
-    // interface correction on the FP32 operators
+    // interface corrections on the FP32 operators
     CHK(transform_vec(ctx->d_entdev, nE, ctx->dgv, +1, st));
-    const double tin = std::max(inner_floor, 0.5 * ctx->opt.tol / std::max(rel, 1e-300));
     PcgResult pr;
-    rc = pcg_core(ctx, ctx->dgv, true, tin, ctx->opt.maxit - inner, outer == 0, &pr);
+    rc = pcg_core(ctx, ctx->dgv, true, tin, ctx->opt.maxit - inner_max, &pr);
     if (rc) return rc;
-    if (outer == 0) first_it = pr.it;
-    inner += pr.it;
-    if (pr.status == VB_ERR_BREAKDOWN) {
-      status = pr.status;
-      break;
+    int mx = 0;
+    for (int pp = 0; pp < P; ++pp) {
+      const double *q = pr.sc.data() + (size_t)pp * SC_STRIDE;
+      const int it = (int)q[SC_IT];
+      if (!done[pp]) {
+        inner[pp] += it;
+        steps[pp] += 1;
+      }
+      mx = std::max(mx, it);
+      if (outer == 0) {  // Lanczos estimates of the first inner solve
+        rc = lanczos_problem(ctx, pp, it, &pi[pp].lambda_min, &pi[pp].lambda_max);
+        if (rc) return rc;
+      }
+      if (q[SC_FLAG] == 1.0) status = VB_ERR_BREAKDOWN;
     }
+    inner_max += mx;
+    if (status == VB_ERR_BREAKDOWN) break;
     CHK(hipMemcpyAsync(ctx->dx, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
     CHK(transform_vec(ctx->d_entdev, nE, ctx->dx, -1, st));
     rc = interior_correction(ctx, ctx->dx);
     if (rc) return rc;
     CHK(axpy(n, 1.0, ctx->dx, x_dev, st));
     ++outer;
+    // device clock after this step: the latency of problems finishing here
+    CHK(sinit(P, ctx->d_tol, 0, ctx->sc, st));
+    CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int pp = 0; pp < P; ++pp)
+      if (!done[pp]) tdone[pp] = hs[(size_t)pp * SC_STRIDE + SC_T0];
   }
   CHK(hipEventRecord(ctx->ev1, st));
   CHK(hipEventSynchronize(ctx->ev1));
   float ms = 0.f;
   CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->last_outer = outer;
-  ctx->last_inner = inner;
+  ctx->last_inner = inner_max;
+  for (int pp = 0; pp < P; ++pp) {
+    vb_solve_info &q = pi[pp];
+    q.iterations = inner[pp];
+    q.refinement_steps = steps[pp];
+    q.rel_residual = rel[pp];
+    q.true_rel_residual = rel[pp];
+    q.n_coarse = ctx->probs[pp].nprim + ctx->probs[pp].ns;
+    q.setup_ms = ctx->setup_ms;
+    q.solve_ms = ms;
+    q.status = done[pp] ? VB_OK : status;
+    q.latency_ms = (ctx->clock_khz > 0 && tdone[pp] > t0[pp]) ? (tdone[pp] - t0[pp]) / ctx->clock_khz : 0.0;
+  }
+  ctx->pinfo = pi;
   if (info) {
-    info->iterations = inner;
-    info->refinement_steps = outer;
-    info->rel_residual = rel;
-    info->true_rel_residual = rel;
+    combine_info(pi, info);
     info->n_coarse = ctx->nCS;
-    info->setup_ms = ctx->setup_ms;
-    info->solve_ms = ms;
     info->status = status;
-    int rc = fill_lanczos(ctx, first_it, info);
-    if (rc) return rc;
   }
   if (status == VB_ERR_BREAKDOWN) return ctx->fail(status, "PCG breakdown: p^T S p <= 0 or NaN");
   if (status == VB_ERR_NOT_CONVERGED)
@@ -2321,38 +2545,52 @@ int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
   hipStream_t st = ctx->stream;
   const int64_t n = ctx->nG + ctx->nS;
   const int nE = (int)ctx->ents.size();
-  double hs[SC_COUNT];
+  const int P = (int)ctx->probs.size(), G = ctx->seg_G;
   CHK(hipEventRecord(ctx->ev0, st));
   // x~ = T^T x0 ; PCG on S~ x~ = g~
   CHK(hipMemcpyAsync(ctx->x, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   CHK(transform_vec(ctx->d_entdev, nE, ctx->x, +1, st));
   PcgResult pr;
-  int rc = pcg_core(ctx, ctx->g, false, ctx->opt.tol, ctx->opt.maxit, true, &pr);
+  std::vector<double> tol(P, ctx->opt.tol);
+  int rc = pcg_core(ctx, ctx->g, false, tol, ctx->opt.maxit, &pr);
   if (rc) return rc;
-  // true residual
+  // true residual per problem (into SC_TMP)
   CHK(hipMemcpyAsync(ctx->p, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   rc = apply_S_internal(ctx);
   if (rc) return rc;
   CHK(vsub(n, ctx->g, ctx->q, ctx->tmp, st));
-  CHK(dot(n, ctx->tmp, ctx->tmp, ctx->part, ctx->sc, 5, 0, nullptr, nullptr, st));
+  CHK(sdot(ctx->d_segs, P, G, ctx->tmp, ctx->tmp, ctx->part, ctx->sc, 5, nullptr, nullptr, 0, st));
   CHK(hipMemcpyAsync(x_dev, ctx->x, n * sizeof(double), hipMemcpyDeviceToDevice, st));
   CHK(transform_vec(ctx->d_entdev, nE, x_dev, -1, st));
   CHK(hipEventRecord(ctx->ev1, st));
-  CHK(hipMemcpyAsync(hs, ctx->sc, sizeof(hs), hipMemcpyDeviceToHost, st));
+  std::vector<double> hs((size_t)P * SC_STRIDE);
+  CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
   float ms = 0.f;
   CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
-  if (info) {
-    info->iterations = pr.it;
-    info->refinement_steps = 0;
-    info->rel_residual = pr.rel;
-    info->true_rel_residual = pr.bnorm > 0 ? std::sqrt(hs[SC_TMP]) / pr.bnorm : 0.0;
-    info->n_coarse = ctx->nCS;
-    info->setup_ms = ctx->setup_ms;
-    info->solve_ms = ms;
-    info->status = pr.status;
-    rc = fill_lanczos(ctx, pr.it, info);
+  std::vector<vb_solve_info> pi(P);
+  for (int pp = 0; pp < P; ++pp) {
+    const double *q = hs.data() + (size_t)pp * SC_STRIDE;
+    vb_solve_info &o = pi[pp];
+    o.iterations = (int)q[SC_IT];
+    o.refinement_steps = 0;
+    o.rel_residual = q[SC_GG] > 0 ? std::sqrt(q[SC_RR] / q[SC_GG]) : 0.0;
+    o.true_rel_residual = q[SC_GG] > 0 ? std::sqrt(q[SC_TMP] / q[SC_GG]) : 0.0;
+    o.n_coarse = ctx->probs[pp].nprim + ctx->probs[pp].ns;
+    o.setup_ms = ctx->setup_ms;
+    o.solve_ms = ms;
+    o.status = q[SC_FLAG] == 1.0 ? VB_ERR_BREAKDOWN
+               : (q[SC_FLAG] == 2.0 || q[SC_DONE] == 0.0) ? VB_ERR_NOT_CONVERGED : VB_OK;
+    o.latency_ms = (ctx->clock_khz > 0 && q[SC_TDONE] > q[SC_T0])
+                       ? (q[SC_TDONE] - q[SC_T0]) / ctx->clock_khz : 0.0;
+    rc = lanczos_problem(ctx, pp, o.iterations, &o.lambda_min, &o.lambda_max);
     if (rc) return rc;
+  }
+  ctx->pinfo = pi;
+  if (info) {
+    combine_info(pi, info);
+    if (P > 1) info->n_coarse = ctx->nCS;
+    info->status = pr.status;
   }
   if (pr.status == VB_ERR_BREAKDOWN) return ctx->fail(pr.status, "PCG breakdown: p^T S p <= 0 or NaN");
   if (pr.status == VB_ERR_NOT_CONVERGED) return ctx->fail(pr.status, "PCG reached maxit");
@@ -2441,6 +2679,26 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
 }  // extern "C"
 
 extern "C" {
+
+int vb_num_problems(const vb_ctx *ctx) { return ctx ? (int)ctx->probs.size() : VB_ERR_ARG; }
+
+int vb_problem_layout(const vb_ctx *ctx, int problem, vb_problem *out) {
+  if (!ctx || !out || problem < 0 || problem >= (int)ctx->probs.size()) return VB_ERR_ARG;
+  const auto &P = ctx->probs[problem];
+  out->iface_offset = P.g0;
+  out->n_iface = P.ng;
+  out->p0_offset = ctx->nG + P.s0;
+  out->sub_offset = P.s0;
+  out->n_sub = P.ns;
+  return VB_OK;
+}
+
+int vb_problem_solve_info(const vb_ctx *ctx, int problem, vb_solve_info *out) {
+  if (!ctx || !out || problem < 0 || problem >= (int)ctx->probs.size()) return VB_ERR_ARG;
+  if (problem >= (int)ctx->pinfo.size()) return VB_ERR_STATE;
+  *out = ctx->pinfo[problem];
+  return VB_OK;
+}
 
 int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_eigs, double *eigs) {
   if (!ctx || max_faces < 0 || max_eigs < 0) return VB_ERR_ARG;

@@ -1,0 +1,163 @@
+"""Several independent problems in one context (one launch per step covers
+every subdomain of every problem; PCG keeps scalars and convergence per
+problem) and the HIP-graph replay of the PCG iteration.
+
+Each problem of a batched context must reproduce its own single-problem
+solve: same iteration count (the recurrences are the same, only the
+grouping of the reductions' partial sums can differ) and the same solution
+to 1e-10 relative; the operators of the batched context are block diagonal.
+The graph-replayed iteration must give the eager iteration's result (same
+kernels and arguments), on every one of several solves in a row."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from inputs.workloads import make_workload
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+CASES = [("c1", 0), ("t8j", 0), ("t6f", 0)]
+
+
+@pytest.fixture(scope="module")
+def vb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09770_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def wls():
+    return [make_workload(name, seed=seed, workers=1)[0] for name, seed in CASES]
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def _single(vb, wl, **kw):
+    ctx = vb.vb_create(**kw)
+    vb.vb_assemble(ctx, wl)
+    vb.vb_setup(ctx)
+    n = vb.vb_interface_size(ctx)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    info = vb.vb_pcg_solve(ctx, x)
+    out = {"x": x.cpu().numpy(), "info": info, "n_iface": int(wl["n_iface"]),
+           "n_sub": len(wl["subs"])}
+    g = torch.zeros(n, dtype=torch.float64, device=DEV)
+    vb.vb_rhs(ctx, g)
+    out["g"] = g.cpu().numpy()
+    vb.vb_destroy(ctx)
+    return out
+
+
+def _split(vb, ctx, v, k):
+    L = vb.vb_problem_layout(ctx, k)
+    a = v[L["iface_offset"]: L["iface_offset"] + L["n_iface"]]
+    b = v[L["p0_offset"]: L["p0_offset"] + L["n_sub"]]
+    return np.concatenate([a, b])
+
+
+def test_batched_problems_match_single_solves(vb, wls):
+    ref = [_single(vb, wl) for wl in wls]
+    ctx = vb.vb_create()
+    try:
+        for wl in wls:
+            vb.vb_assemble(ctx, wl)
+        assert vb.vb_num_problems(ctx) == len(wls)
+        vb.vb_setup(ctx)
+        n = vb.vb_interface_size(ctx)
+        assert n == sum(len(r["x"]) for r in ref)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x)
+        g = torch.zeros(n, dtype=torch.float64, device=DEV)
+        vb.vb_rhs(ctx, g)
+        xg, gg = x.cpu().numpy(), g.cpu().numpy()
+        its = []
+        for k, r in enumerate(ref):
+            pi = vb.vb_problem_solve_info(ctx, k)
+            its.append(pi["iterations"])
+            assert pi["iterations"] == r["info"]["iterations"], (k, pi["iterations"], r["info"]["iterations"])
+            assert pi["true_rel_residual"] <= 1e-8 * 1.01
+            assert pi["latency_ms"] > 0.0
+            assert _rel(_split(vb, ctx, gg, k), r["g"]) < 1e-13
+            assert _rel(_split(vb, ctx, xg, k), r["x"]) < 1e-10
+        assert info["iterations"] == max(its)
+        # block-diagonal operators: S_hat and M^-1 of the batch act per problem
+        rng = np.random.default_rng(0)
+        v = rng.standard_normal(n)
+        y = torch.zeros(n, dtype=torch.float64, device=DEV)
+        vb.vb_schur_apply(ctx, torch.tensor(v, device=DEV), y)
+        yb = y.cpu().numpy()
+        zb = torch.zeros(n, dtype=torch.float64, device=DEV)
+        vb.vb_apply(ctx, torch.tensor(yb, device=DEV), zb)
+        zb = zb.cpu().numpy()
+    finally:
+        vb.vb_destroy(ctx)
+    for k, wl in enumerate(wls):
+        c1 = vb.vb_create()
+        vb.vb_assemble(c1, wl)
+        vb.vb_setup(c1)
+        nk = vb.vb_interface_size(c1)
+        vk = torch.tensor(_split_layout(v, ref, k), device=DEV)
+        yk = torch.zeros(nk, dtype=torch.float64, device=DEV)
+        vb.vb_schur_apply(c1, vk, yk)
+        zk = torch.zeros(nk, dtype=torch.float64, device=DEV)
+        vb.vb_apply(c1, yk, zk)
+        yk, zk = yk.cpu().numpy(), zk.cpu().numpy()
+        vb.vb_destroy(c1)
+        assert _rel(_split_layout(yb, ref, k), yk) < 1e-13
+        assert _rel(_split_layout(zb, ref, k), zk) < 1e-11
+
+
+def _split_layout(v, ref, k):
+    """Problem k's part of a batched vector, from the single-problem sizes
+    (interface sizes and subdomain counts in problem order)."""
+    ni = [r["n_iface"] for r in ref]
+    ns = [r["n_sub"] for r in ref]
+    g0 = sum(ni[:k])
+    p0 = sum(ni) + sum(ns[:k])
+    return np.concatenate([v[g0: g0 + ni[k]], v[p0: p0 + ns[k]]])
+
+
+def test_graph_replay_matches_eager(vb, wls):
+    wl = wls[1]
+    eager = _single(vb, wl)
+    stream = torch.cuda.Stream(device=DEV)
+    ctx = vb.vb_create(stream=stream.cuda_stream)
+    try:
+        vb.vb_assemble(ctx, wl)
+        with torch.cuda.stream(stream):
+            vb.vb_setup(ctx)
+            n = vb.vb_interface_size(ctx)
+            for rep in range(3):
+                x = torch.zeros(n, dtype=torch.float64, device=DEV)
+                torch.cuda.synchronize()
+                info = vb.vb_pcg_solve(ctx, x)
+                stream.synchronize()
+                assert info["iterations"] == eager["info"]["iterations"]
+                assert _rel(x.cpu().numpy(), eager["x"]) < 1e-13, rep
+    finally:
+        vb.vb_destroy(ctx)
+
+
+def test_mixed_batched_reaches_fp64(vb, wls):
+    ref = [_single(vb, wl, tol=1e-12) for wl in wls]
+    ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12)
+    try:
+        for wl in wls:
+            vb.vb_assemble(ctx, wl)
+        vb.vb_setup(ctx)
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x)
+        xg = x.cpu().numpy()
+        for k, r in enumerate(ref):
+            pi = vb.vb_problem_solve_info(ctx, k)
+            assert pi["refinement_steps"] >= 1
+            assert _rel(_split(vb, ctx, xg, k), r["x"]) < 1e-9
+    finally:
+        vb.vb_destroy(ctx)
