@@ -185,6 +185,11 @@ typedef struct vb_problem {
   int sub_offset, n_sub;          /* its subdomains [sub_offset, + n_sub) */
 } vb_problem;
 int vb_num_problems(const vb_ctx *ctx);
+/* Columns per workgroup that the autotuner chose (at the context's first
+ * vb_setup, by timing 8/16/32/64 on the operators themselves) for the
+ * per-iteration GEMVs: which = 0 S_hat p, 1 Neumann, 2 deluxe restriction,
+ * 3 coarse; 0 before the first setup. */
+int vb_tuned_tile(const vb_ctx *ctx, int which);
 int vb_problem_layout(const vb_ctx *ctx, int problem, vb_problem *out);
 /* Per-problem result of the last vb_pcg_solve (the info that call returns
  * combines them: largest iteration count, residual and latency, extreme

@@ -279,3 +279,24 @@ class Problem:
         u[free] = x[: len(free)]
         p = x[len(free): len(free) + self.Np]
         return u, p
+
+
+def with_viscosity(pb, nuK):
+    """The problem `pb` (built with nu = 1 and the default load) with the
+    element viscosities nuK: the velocity blocks of the element matrices and
+    the load (f is proportional to nu_K) scale by nu_K, the divergence rows do
+    not, and the Dirichlet lifting is recomputed.  Shares the mesh, the
+    numbering and the unit element matrices with `pb`."""
+    import copy
+    assert np.all(pb.nu == 1.0), "the base problem must have nu = 1"
+    q = copy.copy(pb)
+    nuK = np.asarray(nuK, float)
+    n = pb.nloc - 1
+    Ke = pb.Ke.copy()
+    Ke[:, :n, :n] *= nuK[:, None, None]
+    Fe = pb.Fe.copy()
+    Fe[:, :n] *= nuK[:, None]
+    q.Ke, q.Fe, q.nu = Ke, Fe, nuK
+    ud_e = pb.uD_red[pb.rmap] * pb.red_dir[pb.rmap]
+    q.ge = Fe - np.einsum("eij,ej->ei", Ke, ud_e)
+    return q

@@ -60,6 +60,8 @@ RECIPES = {
     "t12s": dict(n=12, jitter=0.0, k=2, parts=(3, 3, 3), cons=FULL, sinkers=True,
                  sinker_n=4, sinker_r=0.25),
     "t16s": dict(n=16, jitter=0.0, k=2, parts=(4, 4, 4), cons=FULL, sinkers=True),
+    # C5's shape at 12^3 per problem (a family on one jittered mesh, nu per problem)
+    "c5s": dict(n=12, jitter=0.15, k=3, parts=(3, 3, 3), cons=FULL, nu_per_sub=True),
 }
 
 
@@ -81,6 +83,25 @@ def make_workload(name, seed=0, workers=None, **over):
     pb = Problem(mesh, r["k"], nu, workers=workers)
     dec = Decomposition(pb, cuts, r["cons"])
     return dec.workload(), {"recipe": r, "problem": pb, "decomposition": dec, "name": name}
+
+
+def make_family(name, seeds, workers=None, mesh_seed=0, **over):
+    """Independent problems of recipe `name` sharing one mesh (jitter seed
+    `mesh_seed`): the unit-viscosity element matrices are computed once and
+    each problem's viscosity (per subdomain, drawn from its own seed) scales
+    them.  Returns a list of workloads."""
+    from .assemble import with_viscosity
+    r = dict(RECIPES[name])
+    r.update(over)
+    assert r.get("nu_per_sub"), "families vary the per-subdomain viscosity"
+    mesh = CubeMesh(r["n"], jitter=r["jitter"], seed=mesh_seed)
+    cuts = regular_cuts(r["n"], r["parts"])
+    base = Problem(mesh, r["k"], 1.0, workers=workers)
+    out = []
+    for sd in seeds:
+        pb = with_viscosity(base, subdomain_viscosity(mesh, cuts, sd))
+        out.append(Decomposition(pb, cuts, r["cons"]).workload())
+    return out
 
 
 def save_workload(path, wl):

@@ -100,6 +100,7 @@ def load():
         "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
                                        C.POINTER(C.c_double)]),
         "vb_num_problems": (C.c_int, [P]),
+        "vb_tuned_tile": (C.c_int, [P, C.c_int]),
         "vb_problem_layout": (C.c_int, [P, C.c_int, C.POINTER(vb_problem)]),
         "vb_problem_solve_info": (C.c_int, [P, C.c_int, C.POINTER(vb_solve_info)]),
         "vb_face_samples": (C.c_int64, [P, C.c_int64, C.POINTER(C.c_float), C.POINTER(C.c_float)]),
@@ -134,7 +135,7 @@ def exported_symbols():
             "vb_mlp_last_error", "vb_mlp_add_samples", "vb_mlp_num_samples", "vb_mlp_train",
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
-            "vb_problem_solve_info"]
+            "vb_problem_solve_info", "vb_tuned_tile"]
 
 
 class VBError(RuntimeError):
@@ -395,3 +396,7 @@ def vb_problem_solve_info(ctx, problem):
     out = vb_solve_info()
     _check(ctx, load().vb_problem_solve_info(ctx, int(problem), C.byref(out)))
     return out.as_dict()
+
+
+def vb_tuned_tile(ctx, which):
+    return int(load().vb_tuned_tile(ctx, int(which)))

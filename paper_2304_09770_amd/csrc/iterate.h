@@ -63,6 +63,8 @@ struct RecJob {
 };
 
 hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);
+hipError_t gemv_t_cpb(const GemvJob *d_jobs, int batch, int max_m, int max_n, int cpb,
+                      hipStream_t s);
 hipError_t gemv_n(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);
 hipError_t owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
                      const int64_t *bidx, const double *bsrc, double *y, hipStream_t s);

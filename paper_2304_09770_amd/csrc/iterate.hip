@@ -74,16 +74,19 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
 static hipError_t allow_big_lds() {
   static int done = 0;
   if (done) return hipSuccess;
-  hipError_t e = hipFuncSetAttribute((const void *)k_gemv_t<32>,
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-  if (e == hipSuccess)
-    e = hipFuncSetAttribute((const void *)k_gemv_n, hipFuncAttributeMaxDynamicSharedMemorySize,
-                            160 * 1024);
-  if (e == hipSuccess) done = 1;
-  return e;
+  const void *fs[] = {(const void *)k_gemv_t<8>, (const void *)k_gemv_t<16>,
+                      (const void *)k_gemv_t<32>, (const void *)k_gemv_t<64>, (const void *)k_gemv_n};
+  for (const void *f : fs) {
+    hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  done = 1;
+  return hipSuccess;
 }
 
-hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {
+// cpb: columns per workgroup (8, 16, 32 or 64), chosen by the autotuner.
+hipError_t gemv_t_cpb(const GemvJob *d_jobs, int batch, int max_m, int max_n, int cpb,
+                      hipStream_t s) {
   if (!batch || !max_n) return hipSuccess;
   size_t lds = (size_t)max_m * sizeof(double);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
@@ -91,8 +94,25 @@ hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStr
     hipError_t e = allow_big_lds();
     if (e != hipSuccess) return e;
   }
-  hipLaunchKernelGGL((k_gemv_t<32>), dim3((max_n + 31) / 32, batch), dim3(256), lds, s, d_jobs);
+  switch (cpb) {
+    case 8:
+      hipLaunchKernelGGL((k_gemv_t<8>), dim3((max_n + 7) / 8, batch), dim3(256), lds, s, d_jobs);
+      break;
+    case 16:
+      hipLaunchKernelGGL((k_gemv_t<16>), dim3((max_n + 15) / 16, batch), dim3(256), lds, s, d_jobs);
+      break;
+    case 64:
+      hipLaunchKernelGGL((k_gemv_t<64>), dim3((max_n + 63) / 64, batch), dim3(256), lds, s, d_jobs);
+      break;
+    default:
+      hipLaunchKernelGGL((k_gemv_t<32>), dim3((max_n + 31) / 32, batch), dim3(256), lds, s, d_jobs);
+      break;
+  }
   return hipGetLastError();
+}
+
+hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {
+  return gemv_t_cpb(d_jobs, batch, max_m, max_n, 32, s);
 }
 
 hipError_t gemv_n(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s) {

@@ -125,6 +125,9 @@ struct vb_ctx {
   hipGraph_t it_graph = nullptr;
   hipGraphExec_t it_exec = nullptr;
   std::vector<vb_solve_info> pinfo;  // per problem, last solve
+  // autotuned columns per workgroup of the per-iteration GEMVs:
+  // 0 S_hat p, 1 Neumann, 2 deluxe restriction, 3 coarse (0 = not tuned yet)
+  int cpb[4] = {0, 0, 0, 0};
   double clock_khz = 0.0;
   // adaptive coarse space of the last setup
   std::vector<vb_face_info> face_info;
@@ -1430,6 +1433,8 @@ static int adaptive_stage(vb_ctx *ctx) {
   return VB_OK;
 }
 
+static int autotune_gemvs(vb_ctx *ctx);
+
 extern "C" {
 
 static int setup_impl(vb_ctx *ctx);
@@ -2061,6 +2066,11 @@ static int setup_impl(vb_ctx *ctx) {
       ctx->max_nt = std::max(ctx->max_nt, S.ndl + S.npi);
     }
   }
+  // tile shapes of the per-iteration GEMVs, once per context
+  if (!ctx->cpb[0]) {
+    int rc = autotune_gemvs(ctx);
+    if (rc) return rc;
+  }
   // ---- 10. recovery structures
   {
     std::vector<int64_t> yoff(nS), invoff(nS);
@@ -2150,7 +2160,8 @@ static int setup_impl(vb_ctx *ctx) {
 static int apply_S_internal(vb_ctx *ctx) {  // q <- S~ p
   KTimer *t = ctx->opt.profile ? &ctx->t_gemv : nullptr;
   if (t) CHK(t->begin(ctx->stream, ctx->schur_bytes));
-  CHK(gemv_t(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m, ctx->stream));
+  CHK(gemv_t_cpb(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m, ctx->cpb[0] ? ctx->cpb[0] : 32,
+                 ctx->stream));
   if (t) CHK(t->end(ctx->stream));
   CHK(owner_sum((int)(ctx->nG + ctx->nS), ctx->own_ptr, ctx->own_idx, ctx->yloc, nullptr, nullptr,
                 ctx->q, ctx->stream));
@@ -2159,13 +2170,60 @@ static int apply_S_internal(vb_ctx *ctx) {  // q <- S~ p
 
 static int apply_M_internal(vb_ctx *ctx) {  // z <- M~^-1 r
   hipStream_t st = ctx->stream;
-  if (ctx->n_restrict) CHK(gemv_t(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm, st));
-  CHK(gemv_t(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, st));
+  auto cp = [&](int k) { return ctx->cpb[k] ? ctx->cpb[k] : 32; };
+  if (ctx->n_restrict)
+    CHK(gemv_t_cpb(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm, cp(2), st));
+  CHK(gemv_t_cpb(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, cp(1), st));
   CHK(owner_sum(ctx->nCS, ctx->c_ptr, ctx->c_idx, ctx->tv, ctx->c_base, ctx->r, ctx->rc, st));
-  CHK(gemv_t(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, ctx->max_ncs, st));
+  CHK(gemv_t_cpb(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, ctx->max_ncs, cp(3), st));
   if (ctx->max_ndl) CHK(gemv_n(ctx->j_neu2, ctx->nS, ctx->max_ndl, ctx->max_npi, st));
   if (ctx->n_ext) CHK(extend(ctx->j_ext, ctx->n_ext, ctx->max_ext_m, ctx->j_extpart, ctx->wv, ctx->z, st));
   CHK(scatter_copy(ctx->nCS, ctx->uc, nullptr, ctx->uc_dst, ctx->z, 1.0, st));
+  return VB_OK;
+}
+
+// Autotuner of the per-iteration GEMVs: each candidate tile shape (columns
+// per workgroup) is timed with HIP events on the operator's own jobs (one
+// warm-up and three timed launches; the outputs are scratch at this point)
+// and the fastest is kept for this context.
+static int autotune_gemvs(vb_ctx *ctx) {
+  hipStream_t st = ctx->stream;
+  struct Cand {
+    const GemvJob *jobs;
+    int batch, m, n;
+  } ops[4] = {{ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m},
+              {ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt},
+              {ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm},
+              {ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, ctx->max_ncs}};
+  static const int choices[] = {8, 16, 32, 64};
+  hipEvent_t e0, e1;
+  CHK(hipEventCreate(&e0));
+  CHK(hipEventCreate(&e1));
+  for (int k = 0; k < 4; ++k) {
+    const Cand &c = ops[k];
+    if (!c.jobs || c.batch <= 0 || c.n <= 0 || c.m <= 0) {
+      ctx->cpb[k] = 32;
+      continue;
+    }
+    float best = 1e30f;
+    int pick = 32;
+    for (int cpb : choices) {
+      CHK(gemv_t_cpb(c.jobs, c.batch, c.m, c.n, cpb, st));
+      CHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) CHK(gemv_t_cpb(c.jobs, c.batch, c.m, c.n, cpb, st));
+      CHK(hipEventRecord(e1, st));
+      CHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CHK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        pick = cpb;
+      }
+    }
+    ctx->cpb[k] = pick;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
   return VB_OK;
 }
 
@@ -2679,6 +2737,11 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
 }  // extern "C"
 
 extern "C" {
+
+int vb_tuned_tile(const vb_ctx *ctx, int which) {
+  if (!ctx || which < 0 || which > 3) return VB_ERR_ARG;
+  return ctx->cpb[which];
+}
 
 int vb_num_problems(const vb_ctx *ctx) { return ctx ? (int)ctx->probs.size() : VB_ERR_ARG; }
 

@@ -211,3 +211,16 @@ def test_random_cuts_seed0():
     c = random_cuts(48, 4, 12, 6, 0)
     assert [list(x) for x in c] == [[0, 7, 15, 24, 31, 36, 48], [0, 10, 21, 25, 34, 42, 48],
                                     [0, 10, 18, 24, 28, 36, 48]]
+
+
+def test_family_member_equals_direct_generation():
+    """A problem of a viscosity family (unit element matrices scaled per
+    element) equals the problem generated directly with that viscosity."""
+    from inputs.workloads import make_family, make_workload
+    wl, _ = make_workload("c5", seed=1, workers=1, n=4, k=2)
+    fam = make_family("c5s", [1], workers=1, mesh_seed=1, n=4, k=2)[0]
+    assert len(wl["subs"]) == len(fam["subs"]) and wl["n_iface"] == fam["n_iface"]
+    for a, b in zip(wl["subs"], fam["subs"]):
+        assert np.array_equal(a["indices"], b["indices"])
+        assert np.abs(a["data"] - b["data"]).max() <= 1e-13 * np.abs(a["data"]).max()
+        assert np.abs(a["rhs"] - b["rhs"]).max() <= 1e-12 * max(np.abs(a["rhs"]).max(), 1e-300)
