@@ -88,6 +88,8 @@ def main():
                     help="both: time the FP64 path and the mixed path; value = mixed")
     ap.add_argument("--prepare-only", action="store_true",
                     help="generate and store the workload (--cache) and exit")
+    ap.add_argument("--no-sequential", action="store_true",
+                    help="c5s: skip the one-context-per-problem comparison")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="copy a 1 GiB device buffer three times and exit (reference for the "
                          "HBM byte counters)")
@@ -290,10 +292,20 @@ def run_batched(args):
         u = torch.zeros(nloc, dtype=torch.float64, device=dev)
         info = None
         for _ in range(steps):
+            t0 = time.perf_counter()
             vb.vb_setup(ctx)
+            stream.synchronize()
+            t1 = time.perf_counter()
             x.zero_()
             info = vb.vb_pcg_solve(ctx, x)
+            stream.synchronize()
+            t2 = time.perf_counter()
             vb.vb_recover_all(ctx, x, u)
+            stream.synchronize()
+            t3 = time.perf_counter()
+            if len(ctx_wls[id(ctx)]) > 1:
+                log("batch step: setup %.3f s (device %.1f ms), solve %.3f s, recovery %.3f s"
+                    % (t1 - t0, info["setup_ms"], t2 - t1, t3 - t2))
         stream.synchronize()
         return info
 
@@ -316,7 +328,7 @@ def run_batched(args):
         dt_batch = (t1 - t0) / args.steps
         # one context per problem, one after the other
         seq = 0.0
-        for k, wl in enumerate(batch):
+        for k, wl in enumerate([] if args.no_sequential else batch):
             c = vb.vb_create(**opts)
             ctx_wls[id(c)] = [wl]
             vb.vb_assemble(c, wl)
@@ -350,8 +362,8 @@ def run_batched(args):
                    "precision": PRECISION_NAMES["mixed"]},
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
-        "sequential_solves_per_s": len(batch) / seq,
-        "batch_speedup": seq / dt_batch,
+        "sequential_solves_per_s": (len(batch) / seq) if seq else None,
+        "batch_speedup": (seq / dt_batch) if seq else None,
         "inner_iterations": {"min": int(its.min()), "max": int(its.max())},
         "refinement_steps_max": max(p["refinement_steps"] for p in per),
         "max_rel_residual": res,

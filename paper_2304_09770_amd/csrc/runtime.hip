@@ -180,10 +180,84 @@ struct vb_ctx {
     err = m;
     return code;
   }
+  // Setup scratch: small allocations come from 64 MB device chunks, each
+  // with a pinned host mirror at the same offsets.  An upload only writes
+  // the mirror and widens the chunk's dirty range; flush() copies every
+  // dirty range with one asynchronous copy on the context's stream and runs
+  // before each device operation of the setup (the CHK macro), so the
+  // thousands of small index and job arrays of a setup cost a few copies.
+  // Everything is released when the setup ends, after a synchronisation.
+  static constexpr size_t kChunk = 64ull << 20, kSmall = 4ull << 20;
+  struct Chunk {
+    char *dev = nullptr, *host = nullptr;
+    size_t used = 0, lo = 0, hi = 0;  // [lo, hi): bytes waiting for the copy
+  };
+  std::vector<Chunk> chunks;
+  bool dirty = false;
+
+  size_t cur_chunk = 0;  // chunks are kept for the context's lifetime and rewound per setup
+  hipError_t arena_alloc(void **p, size_t bytes, char **host = nullptr) {
+    bytes = (bytes + 255) & ~size_t(255);
+    while (cur_chunk < chunks.size() && chunks[cur_chunk].used + bytes > kChunk) ++cur_chunk;
+    if (cur_chunk == chunks.size()) {
+      Chunk c;
+      hipError_t e = hipMalloc((void **)&c.dev, kChunk);
+      if (e != hipSuccess) return e;
+      e = hipHostMalloc((void **)&c.host, kChunk, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        (void)hipFree(c.dev);
+        return e;
+      }
+      chunks.push_back(c);
+    }
+    Chunk &c = chunks[cur_chunk];
+    *p = c.dev + c.used;
+    if (host) {
+      *host = c.host + c.used;
+      if (c.lo == c.hi) c.lo = c.used;
+      c.hi = c.used + bytes;
+      dirty = true;
+    }
+    c.used += bytes;
+    return hipSuccess;
+  }
+  hipError_t flush() {
+    if (!dirty) return hipSuccess;
+    dirty = false;
+    for (Chunk &c : chunks)
+      if (c.hi > c.lo) {
+        hipError_t e = hipMemcpyAsync(c.dev + c.lo, c.host + c.lo, c.hi - c.lo,
+                                      hipMemcpyHostToDevice, stream);
+        c.lo = c.hi = 0;
+        if (e != hipSuccess) return e;
+      }
+    return hipSuccess;
+  }
+  // end of a setup: every copy has completed once the stream is idle
+  hipError_t release_setup_scratch() {
+    hipError_t e = flush();
+    hipError_t e2 = hipStreamSynchronize(stream);
+    if (e == hipSuccess) e = e2;
+    for (Chunk &c : chunks) c.used = c.lo = c.hi = 0;
+    cur_chunk = 0;
+    dirty = false;
+    for (void *q : setup_allocs) (void)hipFree(q);
+    setup_allocs.clear();
+    return e;
+  }
+  void free_chunks() {
+    for (Chunk &c : chunks) {
+      (void)hipFree(c.dev);
+      (void)hipHostFree(c.host);
+    }
+    chunks.clear();
+    cur_chunk = 0;
+  }
   template <class T>
   hipError_t dalloc(T **p, size_t count, bool setup_scope = false) {
     *p = nullptr;
     if (count == 0) count = 1;
+    if (setup_scope && count * sizeof(T) <= kSmall) return arena_alloc((void **)p, count * sizeof(T));
     hipError_t e = hipMalloc((void **)p, count * sizeof(T));
     if (e == hipSuccess)
       (setup_scope ? setup_allocs : (cur_scope == 2 ? setup_keep : allocs)).push_back(*p);
@@ -191,10 +265,19 @@ struct vb_ctx {
   }
   template <class T>
   hipError_t upload(T **p, const std::vector<T> &v, bool setup_scope = false) {
+    const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
+    if (setup_scope && bytes <= kSmall) {
+      char *h = nullptr;
+      hipError_t e = arena_alloc((void **)p, bytes, &h);
+      if (e == hipSuccess && !v.empty()) std::memcpy(h, v.data(), v.size() * sizeof(T));
+      return e;
+    }
     hipError_t e = dalloc(p, v.size(), setup_scope);
     if (e != hipSuccess) return e;
-    if (!v.empty()) e = hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
-    return e;
+    if (v.empty()) return hipSuccess;
+    e = flush();  // keep the order of the copies
+    if (e != hipSuccess) return e;
+    return hipMemcpy(*p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
   }
 };
 
@@ -215,10 +298,19 @@ struct vb_mlp {
   }
 };
 
-#define CHK(x)                                                                        \
-  do {                                                                                \
-    hipError_t e_ = (x);                                                              \
-    if (e_ != hipSuccess)                                                             \
+#define CHK(x)                                                                       \
+  do {                                                                               \
+    hipError_t f_ = ctx->flush();                                                    \
+    hipError_t e_ = (f_ != hipSuccess) ? f_ : (x);                                   \
+    if (e_ != hipSuccess)                                                            \
+      return ctx->fail(e_ == hipErrorOutOfMemory ? VB_ERR_OOM : VB_ERR_DEVICE,        \
+                       std::string(#x) + ": " + hipGetErrorString(e_));               \
+  } while (0)
+// allocations and uploads: no flush, so consecutive uploads share one copy
+#define UCHK(x)                                                                      \
+  do {                                                                               \
+    hipError_t e_ = (x);                                                             \
+    if (e_ != hipSuccess)                                                            \
       return ctx->fail(e_ == hipErrorOutOfMemory ? VB_ERR_OOM : VB_ERR_DEVICE,        \
                        std::string(#x) + ": " + hipGetErrorString(e_));               \
   } while (0)
@@ -274,7 +366,8 @@ void vb_destroy(vb_ctx *ctx) {
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->it_exec) (void)hipGraphExecDestroy(ctx->it_exec);
   if (ctx->it_graph) (void)hipGraphDestroy(ctx->it_graph);
-  free_list(ctx->setup_allocs);
+  (void)ctx->release_setup_scratch();
+  ctx->free_chunks();
   free_list(ctx->setup_keep);
   ctx->t_ldl.destroy();
   ctx->t_gemv.destroy();
@@ -437,30 +530,30 @@ static int finalize_device(vb_ctx *ctx) {
   }
   {
     char *w = nullptr, *iv = nullptr;
-    CHK(ctx->dalloc(&w, (size_t)wtot * ctx->wsz));
-    CHK(ctx->dalloc(&iv, (size_t)itot * ctx->wsz));
+    UCHK(ctx->dalloc(&w, (size_t)wtot * ctx->wsz));
+    UCHK(ctx->dalloc(&iv, (size_t)itot * ctx->wsz));
     ctx->W = w;
     ctx->invL = iv;
   }
-  CHK(ctx->dalloc(&ctx->b0, btot));
-  CHK(ctx->dalloc(&ctx->hv, htot));
-  CHK(ctx->dalloc(&ctx->info, 4 * (size_t)n_sub + 64 + 4 * (size_t)n_ent));
+  UCHK(ctx->dalloc(&ctx->b0, btot));
+  UCHK(ctx->dalloc(&ctx->hv, htot));
+  UCHK(ctx->dalloc(&ctx->info, 4 * (size_t)n_sub + 64 + 4 * (size_t)n_ent));
   ctx->subdev.resize(n_sub);
   for (int s = 0; s < n_sub; ++s) {
     SubH &S = ctx->subs[s];
-    CHK(ctx->upload(&S.d_indptr, S.indptr));
-    CHK(ctx->upload(&S.d_indices, S.indices));
-    CHK(ctx->upload(&S.d_vals, S.vals));
-    CHK(ctx->upload(&S.d_rhs, S.rhs));
-    CHK(ctx->upload(&S.d_pos, S.pos));
-    CHK(ctx->upload(&S.d_kind, S.kind));
-    CHK(ctx->upload(&S.d_gid, S.gid));
-    CHK(ctx->upload(&S.d_pw, S.pw));
+    UCHK(ctx->upload(&S.d_indptr, S.indptr));
+    UCHK(ctx->upload(&S.d_indices, S.indices));
+    UCHK(ctx->upload(&S.d_vals, S.vals));
+    UCHK(ctx->upload(&S.d_rhs, S.rhs));
+    UCHK(ctx->upload(&S.d_pos, S.pos));
+    UCHK(ctx->upload(&S.d_kind, S.kind));
+    UCHK(ctx->upload(&S.d_gid, S.gid));
+    UCHK(ctx->upload(&S.d_pw, S.pw));
     std::vector<int64_t> gext(S.gidl);
     gext.push_back(n_iface + s);
-    CHK(ctx->upload(&S.d_gidl, gext));
-    CHK(ctx->upload(&S.d_ents, S.ents));
-    CHK(ctx->upload(&S.d_entoff, S.ent_off));
+    UCHK(ctx->upload(&S.d_gidl, gext));
+    UCHK(ctx->upload(&S.d_ents, S.ents));
+    UCHK(ctx->upload(&S.d_entoff, S.ent_off));
     SubDev &D = ctx->subdev[s];
     D.W = (char *)ctx->W + S.W_off * ctx->wsz;
     D.ld = S.ld;
@@ -483,16 +576,16 @@ static int finalize_device(vb_ctx *ctx) {
     D.ent = S.d_ents;
     D.ent_off = S.d_entoff;
   }
-  CHK(ctx->upload(&ctx->d_subdev, ctx->subdev));
+  UCHK(ctx->upload(&ctx->d_subdev, ctx->subdev));
   ctx->entdev.resize(n_ent);
   for (int e = 0; e < n_ent; ++e) {
     EntH &H = ctx->ents[e];
-    CHK(ctx->upload(&H.d_gids, H.gids));
-    CHK(ctx->upload(&H.d_con, H.con));
+    UCHK(ctx->upload(&H.d_gids, H.gids));
+    UCHK(ctx->upload(&H.d_con, H.con));
     int rmax = std::max(1, std::min(H.ncon, H.n));
-    CHK(ctx->dalloc(&H.d_V, (size_t)H.n * rmax));
-    CHK(ctx->dalloc(&H.d_tau, (size_t)rmax));
-    CHK(ctx->dalloc(&H.d_work, (size_t)H.n * std::max(1, H.ncon)));
+    UCHK(ctx->dalloc(&H.d_V, (size_t)H.n * rmax));
+    UCHK(ctx->dalloc(&H.d_tau, (size_t)rmax));
+    UCHK(ctx->dalloc(&H.d_work, (size_t)H.n * std::max(1, H.ncon)));
     H.d_rank = ctx->info + 4 * n_sub + 64 + e;
     EntDev &D = ctx->entdev[e];
     D.n = H.n;
@@ -504,7 +597,7 @@ static int finalize_device(vb_ctx *ctx) {
     D.rank = H.d_rank;
     D.work = H.d_work;
   }
-  CHK(ctx->upload(&ctx->d_entdev, ctx->entdev));
+  UCHK(ctx->upload(&ctx->d_entdev, ctx->entdev));
   ctx->entdev0 = ctx->entdev;
   for (auto &H : ctx->ents) {
     H.ncon0 = H.ncon;
@@ -521,9 +614,9 @@ static int finalize_device(vb_ctx *ctx) {
     segs.push_back({P.g0, P.ng, ctx->nG + P.s0, P.ns});
     maxn = std::max<int64_t>(maxn, P.ng + P.ns);
   }
-  CHK(ctx->upload(&ctx->d_segs, segs));
+  UCHK(ctx->upload(&ctx->d_segs, segs));
   ctx->seg_G = (int)std::min<int64_t>(DOT_BLOCKS, std::max<int64_t>(1, (maxn + 255) / 256));
-  CHK(ctx->dalloc(&ctx->d_tol, ctx->probs.size()));
+  UCHK(ctx->dalloc(&ctx->d_tol, ctx->probs.size()));
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, 0) == hipSuccess)
     ctx->clock_khz = khz;
@@ -541,7 +634,7 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
                    bool timed = false) {
   if (jobs.empty()) return VB_OK;
   LdlJob<T> *dj = nullptr;
-  CHK(ctx->upload(&dj, jobs, true));
+  UCHK(ctx->upload(&dj, jobs, true));
   std::vector<int> hn(jobs.size()), he(jobs.size());
   for (size_t b = 0; b < jobs.size(); ++b) {
     hn[b] = jobs[b].n;
@@ -555,7 +648,7 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
 static int run_gather(vb_ctx *ctx, const std::vector<GatherJob> &jobs, int max_m, int max_n) {
   if (jobs.empty()) return VB_OK;
   GatherJob *dj = nullptr;
-  CHK(ctx->upload(&dj, jobs, true));
+  UCHK(ctx->upload(&dj, jobs, true));
   CHK(gather_blocks(dj, (int)jobs.size(), max_m, max_n, ctx->stream));
   return VB_OK;
 }
@@ -563,7 +656,7 @@ static int run_gather(vb_ctx *ctx, const std::vector<GatherJob> &jobs, int max_m
 static int run_diag(vb_ctx *ctx, const std::vector<DiagJob> &jobs, int max_cnt) {
   if (jobs.empty()) return VB_OK;
   DiagJob *dj = nullptr;
-  CHK(ctx->upload(&dj, jobs, true));
+  UCHK(ctx->upload(&dj, jobs, true));
   CHK(set_diag(dj, (int)jobs.size(), max_cnt, ctx->stream));
   return VB_OK;
 }
@@ -574,9 +667,9 @@ static int run_symm(vb_ctx *ctx, const std::vector<void *> &m, const std::vector
   void **dm = nullptr;
   int64_t *dld = nullptr;
   int32_t *dn = nullptr;
-  CHK(ctx->upload(&dm, m, true));
-  CHK(ctx->upload(&dld, ld, true));
-  CHK(ctx->upload(&dn, n, true));
+  UCHK(ctx->upload(&dm, m, true));
+  UCHK(ctx->upload(&dld, ld, true));
+  UCHK(ctx->upload(&dn, n, true));
   int mx = *std::max_element(n.begin(), n.end());
   if (transpose)
     CHK(transpose_sq(dm, dld, dn, (int)m.size(), mx, fp32, ctx->stream));
@@ -620,7 +713,7 @@ static int primal_qr(vb_ctx *ctx) {
 
 template <typename J>
 static int upload_jobs(vb_ctx *ctx, J **d, const std::vector<J> &h) {
-  CHK(ctx->upload(d, h, true));
+  UCHK(ctx->upload(d, h, true));
   return VB_OK;
 }
 
@@ -654,7 +747,7 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
   const int nf = (int)nf_;
   const int64_t ncoord = coff[nf];
   float *score = nullptr;
-  CHK(ctx->dalloc(&score, std::max<int64_t>(ncoord, 1), true));
+  UCHK(ctx->dalloc(&score, std::max<int64_t>(ncoord, 1), true));
   CHK(mlp_forward(pred->p, pred->mu, pred->sd, ctx->d_feat, ncoord, score, st));
   std::vector<float> hs(ncoord);
   std::vector<double> rho(nf);
@@ -706,10 +799,11 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
   }
   if (act.empty()) return VB_OK;
   const int na = (int)act.size();
-  double *w = nullptr;
+  double *w = nullptr, *lr = nullptr;  // lr: per face 64 Ritz values then 64 residuals
   int *cntH = nullptr;
-  CHK(ctx->dalloc(&w, tot, true));
-  CHK(ctx->dalloc(&cntH, na, true));
+  UCHK(ctx->dalloc(&w, tot, true));
+  UCHK(ctx->dalloc(&lr, (int64_t)na * 128, true));
+  UCHK(ctx->dalloc(&cntH, na, true));
   CHK(hipMemsetAsync(w, 0, tot * sizeof(double), st));
   {  // starting blocks (b x n, ld b): unit vectors of the chosen coordinates
     std::vector<std::vector<double>> v0(na);
@@ -783,10 +877,10 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
       gu.push_back({V, F.C, w + P.o_u, P.b, P.n, P.b, P.b, P.n, P.n, 0, 1.0, 0.0});
       gh.push_back({V, w + P.o_u, w + P.o_h, P.b, P.b, P.b, P.b, P.b, P.n, 0, 1.0, 0.0});
       sj.push_back({w + P.o_h, P.b, P.b});
+      double *lam = lr + (int64_t)live[k] * 128, *res = lam + 64;
       ej.push_back({w + P.o_h, P.b, P.b, P.b, w + P.o_d, w + P.o_e, w + P.o_tau, w + P.o_zh, P.b,
-                    w + P.o_lam, cntH + live[k], 2.0 * P.rho + 1.0});
-      rj.push_back({V, w + P.o_u, w + P.o_zh, P.b, w + P.o_lam, P.b, P.n, F.Z, P.n,
-                    w + P.o_v2, w + P.o_res});
+                    lam, cntH + live[k], 2.0 * P.rho + 1.0});
+      rj.push_back({V, w + P.o_u, w + P.o_zh, P.b, lam, P.b, P.n, F.Z, P.n, w + P.o_v2, res});
     }
     OrthJob *doj = nullptr;
     GemmJob<double> *dgu = nullptr, *dgh = nullptr;
@@ -809,13 +903,13 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
     CHK(tridiag_eig(dej, nl, max_b, max_b, st));
     CHK(back_transform(dej, nl, st));
     CHK(ritz(drj, nl, max_b, st));
+    std::vector<double> hlr((size_t)na * 128);
+    CHK(hipMemcpyAsync(hlr.data(), lr, hlr.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
     for (size_t k = 0; k < live.size(); ++k) {
       PF &P = act[live[k]];
       const int q = P.q;
-      std::vector<double> th(P.b), res(P.b);
-      CHK(hipMemcpyAsync(th.data(), w + P.o_lam, P.b * sizeof(double), hipMemcpyDeviceToHost, st));
-      CHK(hipMemcpyAsync(res.data(), w + P.o_res, P.b * sizeof(double), hipMemcpyDeviceToHost, st));
-      CHK(hipStreamSynchronize(st));
+      const double *th = hlr.data() + (size_t)live[k] * 128, *res = th + 64;
       int kr = 0;
       while (kr < P.b && th[kr] < sigma) ++kr;
       passes[q] = pass + 1;
@@ -832,7 +926,8 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
         hc[q] = kr;
         if (kr > 0) {
           const PredFace F = get(q);
-          CHK(hipMemcpyAsync(F.lam, w + P.o_lam, kr * sizeof(double), hipMemcpyDeviceToDevice, st));
+          CHK(hipMemcpyAsync(F.lam, lr + (int64_t)live[k] * 128, kr * sizeof(double),
+                             hipMemcpyDeviceToDevice, st));
         }
       } else {  // next pass from the Ritz vectors
         CHK(hipMemcpyAsync(w + P.o_y[0], w + P.o_v2, (size_t)P.b * P.n * sizeof(double),
@@ -935,10 +1030,10 @@ static int adaptive_stage(vb_ctx *ctx) {
     max_2nd = std::max(max_2nd, 2 * n);
   }
   double *ar = nullptr;
-  CHK(ctx->dalloc(&ar, tot, true));
+  UCHK(ctx->dalloc(&ar, tot, true));
   CHK(hipMemsetAsync(ar, 0, tot * sizeof(double), st));
   int *iinfo = nullptr;  // LDL pivot reports (2 per face for P, 4 for the pencil) + counts
-  CHK(ctx->dalloc(&iinfo, 7 * (int64_t)nf + 1, true));
+  UCHK(ctx->dalloc(&iinfo, 7 * (int64_t)nf + 1, true));
   CHK(hipMemsetAsync(iinfo, 0, (7 * (int64_t)nf + 1) * sizeof(int), st));
   int *cnt = iinfo + 6 * nf;
   // ---- 1. P_k per face and side, in chunks bounded in memory
@@ -950,7 +1045,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     int32_t *d_dualidx = nullptr;  // [0, max_nd) shifted per job through the out pointer
     std::vector<int32_t> iota(std::max(max_nd, 1));
     std::iota(iota.begin(), iota.end(), 0);
-    CHK(ctx->upload(&d_dualidx, iota, true));
+    UCHK(ctx->upload(&d_dualidx, iota, true));
     double *pbuf = nullptr;
     size_t pcap = 0;
     while (ci < faces.size()) {
@@ -968,7 +1063,7 @@ static int adaptive_stage(vb_ctx *ctx) {
       }
       if ((size_t)bytes > pcap) {
         if (pbuf) CHK(hipStreamSynchronize(st));
-        CHK(ctx->dalloc(&pbuf, (size_t)(bytes / 8.0) + 64, true));
+        UCHK(ctx->dalloc(&pbuf, (size_t)(bytes / 8.0) + 64, true));
         pcap = (size_t)bytes;
       }
       std::vector<GatherJob> gp, ga0, ga1, gt0, gt1;
@@ -993,7 +1088,7 @@ static int adaptive_stage(vb_ctx *ctx) {
             if (l < f.off[k] || l >= f.off[k] + f.nF) perm.push_back(l);
           for (int l = 0; l < f.nF; ++l) perm.push_back(f.off[k] + l);
           int32_t *d_perm = nullptr;
-          CHK(ctx->upload(&d_perm, perm, true));
+          UCHK(ctx->upload(&d_perm, perm, true));
           gp.push_back({x_block(ctx, S), S.ld, P, ldp, d_perm, d_perm, ng, ng, 1.0, 0, f32 ? 1 : 0, 0});
           ft.push_back({P, ldp, ng, ng - f.nF, ctx->d_entdev + f.e, +1});
           tm.push_back(P);
@@ -1024,7 +1119,7 @@ static int adaptive_stage(vb_ctx *ctx) {
         }
       }
       double *invs = nullptr;
-      CHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
+      UCHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
       int64_t io = 0;
       for (auto &J : lj) {
         J.invL = invs + io;
@@ -1066,8 +1161,8 @@ static int adaptive_stage(vb_ctx *ctx) {
   }
   // traces of A_i + A_j and A_j (features of the learned predictor)
   double *tr_pre = nullptr, *tr_post = nullptr;
-  CHK(ctx->dalloc(&tr_pre, 2 * (int64_t)nf, true));
-  CHK(ctx->dalloc(&tr_post, 2 * (int64_t)nf, true));
+  UCHK(ctx->dalloc(&tr_pre, 2 * (int64_t)nf, true));
+  UCHK(ctx->dalloc(&tr_post, 2 * (int64_t)nf, true));
   {
     std::vector<SymJob> tj;
     for (auto &f : faces) {
@@ -1093,7 +1188,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     {
       std::vector<int32_t> iota(std::max(max_2nd, 1));
       std::iota(iota.begin(), iota.end(), 0);
-      CHK(ctx->upload(&d_ii, iota, true));
+      UCHK(ctx->upload(&d_ii, iota, true));
     }
     int64_t invtot = 0;
     for (auto &f : faces) {
@@ -1105,9 +1200,9 @@ static int adaptive_stage(vb_ctx *ctx) {
     int rc = run_gather(ctx, cp, max_2nd, max_2nd);
     if (rc) return rc;
     double *invs = nullptr;
-    CHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
+    UCHK(ctx->dalloc(&invs, std::max<int64_t>(invtot, 1), true));
     double *invr = nullptr;  // scratch of the retries (one panel set per face)
-    CHK(ctx->dalloc(&invr, std::max<int64_t>(invtot / 3, 1), true));
+    UCHK(ctx->dalloc(&invr, std::max<int64_t>(invtot / 3, 1), true));
     int64_t io = 0;
     std::vector<int64_t> roff(nf);
     {
@@ -1200,7 +1295,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     int32_t *d_dualidx = nullptr;
     std::vector<int32_t> iota(std::max(max_nd, 1));
     std::iota(iota.begin(), iota.end(), 0);
-    CHK(ctx->upload(&d_dualidx, iota, true));
+    UCHK(ctx->upload(&d_dualidx, iota, true));
     for (int q = 0; q < nf; ++q) {
       const Face &f = faces[q];
       const int n = f.nd;
@@ -1220,8 +1315,8 @@ static int adaptive_stage(vb_ctx *ctx) {
         cj[a] = n + a;
       }
       int32_t *d_ri = nullptr, *d_cj = nullptr;
-      CHK(ctx->upload(&d_ri, ri, true));
-      CHK(ctx->upload(&d_cj, cj, true));
+      UCHK(ctx->upload(&d_ri, ri, true));
+      UCHK(ctx->upload(&d_cj, cj, true));
       gw.push_back({M, 1, ar + f.o_wt, n, d_ri, d_cj, n, n, 1.0, 0, 0, 0});
       const double *Ap = QA + n + (int64_t)n * f.ld2;
       g1.push_back({ar + f.o_wt, Ap, ar + f.o_t2, n, f.ld2, n, n, n, n, 0, 1.0, 0.0});
@@ -1275,12 +1370,12 @@ static int adaptive_stage(vb_ctx *ctx) {
   std::vector<int64_t> coff(nf + 1, 0);
   for (int q = 0; q < nf; ++q) coff[q + 1] = coff[q] + faces[q].nd;
   const int64_t ncoord = coff[nf];
-  CHK(ctx->dalloc(&ctx->d_feat, ncoord * MLP_F));
-  CHK(ctx->dalloc(&ctx->d_lab, ncoord));
+  UCHK(ctx->dalloc(&ctx->d_feat, ncoord * MLP_F));
+  UCHK(ctx->dalloc(&ctx->d_lab, ncoord));
   CHK(hipMemsetAsync(ctx->d_lab, 0xff, ncoord * sizeof(float), st));  // NaN: no label
   ctx->n_coord = ncoord;
   double *d_rho = nullptr;
-  CHK(ctx->dalloc(&d_rho, nf, true));
+  UCHK(ctx->dalloc(&d_rho, nf, true));
   {
     std::vector<FeatJob> fj0(nf);
     for (int q = 0; q < nf; ++q) {
@@ -1390,7 +1485,43 @@ static int adaptive_stage(vb_ctx *ctx) {
     CHK(face_transform(dfj, (int)fj.size(), max_cols, st));
     CHK(normalize_cols(drn, (int)rn.size(), max_cols, st));
   }
-  // ---- 5. append the rows; record the faces
+  // ---- 5. append the rows; record the faces: each face's rows (nF x cols)
+  // and eigenvalues are copied into one pinned host buffer, one sync
+  std::vector<int64_t> hoff(nf + 1, 0);
+  for (int q = 0; q < nf; ++q) {
+    const Face &f = faces[q];
+    const int m = hc[q];
+    const int cols = (m >= f.nd) ? f.nd : m;
+    const int neig = (m >= f.nd) ? 0 : m;
+    hoff[q + 1] = hoff[q] + (int64_t)f.nF * cols + neig;
+  }
+  double *hbuf = nullptr;
+  CHK(hipHostMalloc((void **)&hbuf, std::max<int64_t>(hoff[nf], 1) * sizeof(double),
+                    hipHostMallocDefault));
+  struct HostFree {
+    double *p;
+    ~HostFree() { (void)hipHostFree(p); }
+  } hb_guard{hbuf};
+  for (int q = 0; q < nf; ++q) {
+    const Face &f = faces[q];
+    const int m = hc[q];
+    const int cols = (m >= f.nd) ? f.nd : m;
+    const int neig = (m >= f.nd) ? 0 : m;
+    if (cols > 0)
+      CHK(hipMemcpyAsync(hbuf + hoff[q], ar + f.o_r, (size_t)f.nF * cols * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+    if (neig > 0)
+      CHK(hipMemcpyAsync(hbuf + hoff[q] + (int64_t)f.nF * cols, ar + f.o_lam, neig * sizeof(double),
+                         hipMemcpyDeviceToHost, st));
+  }
+  CHK(hipStreamSynchronize(st));
+  int64_t extra = 0;
+  for (int q = 0; q < nf; ++q) {
+    const Face &f = faces[q];
+    const int m = hc[q];
+    const int cols = (m >= f.nd) ? f.nd : m;
+    if (cols > 0) extra += (int64_t)(ctx->ents[f.e].ncon + cols) * f.nF;
+  }
   for (int q = 0; q < nf; ++q) {
     Face &f = faces[q];
     EntH &H = ctx->ents[f.e];
@@ -1399,33 +1530,59 @@ static int adaptive_stage(vb_ctx *ctx) {
     const int cols = full ? f.nd : m;
     vb_face_info fi{f.e, f.s[0], f.s[1], f.nd, m, kpred[q], path[q], passes[q], f.shift};
     ctx->face_info.push_back(fi);
-    if (!full && m > 0) {
-      std::vector<double> lam(m);
-      CHK(hipMemcpyAsync(lam.data(), ar + f.o_lam, m * sizeof(double), hipMemcpyDeviceToHost, st));
-      CHK(hipStreamSynchronize(st));
-      ctx->face_eigs.insert(ctx->face_eigs.end(), lam.begin(), lam.end());
-    }
+    const double *hr = hbuf + hoff[q];
+    if (!full && m > 0)
+      ctx->face_eigs.insert(ctx->face_eigs.end(), hr + (int64_t)f.nF * cols, hr + (int64_t)f.nF * cols + m);
     if (cols == 0) continue;
     if (H.ncon + cols > 1024)
       return ctx->fail(VB_ERR_ARG, "adaptive: more than 1024 constraint rows on face entity " +
                                        std::to_string(f.e));
-    std::vector<double> R((size_t)f.nF * cols);
-    CHK(hipMemcpyAsync(R.data(), ar + f.o_r, R.size() * sizeof(double), hipMemcpyDeviceToHost, st));
-    CHK(hipStreamSynchronize(st));
     // R is nF x cols column-major: column c is row c of the constraint block
-    H.con.insert(H.con.end(), R.begin(), R.end());
+    H.con.insert(H.con.end(), hr, hr + (int64_t)f.nF * cols);
     H.ncon += cols;
-    CHK(ctx->upload(&H.d_con, H.con));
-    const int rmax = std::max(1, std::min(H.ncon, H.n));
-    CHK(ctx->dalloc(&H.d_V, (size_t)H.n * rmax));
-    CHK(ctx->dalloc(&H.d_tau, (size_t)rmax));
-    CHK(ctx->dalloc(&H.d_work, (size_t)H.n * std::max(1, H.ncon)));
-    EntDev &D = ctx->entdev[f.e];
-    D.n_con = H.ncon;
-    D.con = H.d_con;
-    D.V = H.d_V;
-    D.tau = H.d_tau;
-    D.work = H.d_work;
+  }
+  // device copies of the grown constraint blocks and their QR workspace:
+  // one allocation each for all faces
+  {
+    int64_t ccon = 0, cv = 0, ct = 0, cw = 0;
+    for (int q = 0; q < nf; ++q) {
+      if (hc[q] == 0) continue;
+      const EntH &H = ctx->ents[faces[q].e];
+      const int rmax = std::max(1, std::min(H.ncon, H.n));
+      ccon += round_up((int64_t)H.ncon * H.n, 32);
+      cv += round_up((int64_t)H.n * rmax, 32);
+      ct += round_up(rmax, 32);
+      cw += round_up((int64_t)H.n * std::max(1, H.ncon), 32);
+    }
+    double *dcon = nullptr, *dv = nullptr, *dt = nullptr, *dw = nullptr;
+    UCHK(ctx->dalloc(&dcon, std::max<int64_t>(ccon, 1)));
+    UCHK(ctx->dalloc(&dv, std::max<int64_t>(cv, 1)));
+    UCHK(ctx->dalloc(&dt, std::max<int64_t>(ct, 1)));
+    UCHK(ctx->dalloc(&dw, std::max<int64_t>(cw, 1)));
+    std::vector<double> hcon(std::max<int64_t>(ccon, 1));
+    int64_t oc = 0, ov = 0, ot = 0, ow = 0;
+    for (int q = 0; q < nf; ++q) {
+      if (hc[q] == 0) continue;
+      EntH &H = ctx->ents[faces[q].e];
+      const int rmax = std::max(1, std::min(H.ncon, H.n));
+      std::copy(H.con.begin(), H.con.end(), hcon.begin() + oc);
+      H.d_con = dcon + oc;
+      H.d_V = dv + ov;
+      H.d_tau = dt + ot;
+      H.d_work = dw + ow;
+      oc += round_up((int64_t)H.ncon * H.n, 32);
+      ov += round_up((int64_t)H.n * rmax, 32);
+      ot += round_up(rmax, 32);
+      ow += round_up((int64_t)H.n * std::max(1, H.ncon), 32);
+      EntDev &D = ctx->entdev[faces[q].e];
+      D.n_con = H.ncon;
+      D.con = H.d_con;
+      D.V = H.d_V;
+      D.tau = H.d_tau;
+      D.work = H.d_work;
+    }
+    CHK(hipMemcpy(dcon, hcon.data(), hcon.size() * sizeof(double), hipMemcpyHostToDevice));
+    (void)extra;
   }
   CHK(hipMemcpyAsync(ctx->d_entdev, ctx->entdev.data(), ctx->entdev.size() * sizeof(EntDev),
                      hipMemcpyHostToDevice, st));
@@ -1467,7 +1624,9 @@ int vb_setup(vb_ctx *ctx) {
   ctx->cur_scope = 2;
   int rc = setup_impl(ctx);
   ctx->cur_scope = 0;
-  free_list(ctx->setup_allocs);
+  hipError_t e = ctx->release_setup_scratch();
+  if (!rc && e != hipSuccess)
+    rc = ctx->fail(VB_ERR_DEVICE, std::string("setup: ") + hipGetErrorString(e));
   return rc;
 }
 
@@ -1603,17 +1762,17 @@ static int setup_impl(vb_ctx *ctx) {
   }
   // ---- 5. transformed right-hand side g~ (owner sums over the rhs columns)
   const int64_t nTot = nG + nS;
-  CHK(ctx->dalloc(&ctx->g, nTot));
+  UCHK(ctx->dalloc(&ctx->g, nTot));
   {
     // condensed local right-hand sides (border column of X) -> flat FP64 buffer
     std::vector<int32_t> iota(ctx->max_ng + 1);
     std::iota(iota.begin(), iota.end(), 0);
     int32_t *d_iota = nullptr;
-    CHK(ctx->upload(&d_iota, iota, true));
+    UCHK(ctx->upload(&d_iota, iota, true));
     int64_t ftot = 0;
     for (auto &S : ctx->subs) ftot += S.ng;
     double *gl = nullptr;
-    CHK(ctx->dalloc(&gl, std::max<int64_t>(ftot, 1), true));
+    UCHK(ctx->dalloc(&gl, std::max<int64_t>(ftot, 1), true));
     std::vector<GatherJob> gj;
     std::vector<std::vector<int64_t>> own(nG);
     int64_t fo = 0;
@@ -1632,16 +1791,16 @@ static int setup_impl(vb_ctx *ctx) {
       ptr[g + 1] = ptr[g] + own[g].size();
       idx.insert(idx.end(), own[g].begin(), own[g].end());
     }
-    CHK(ctx->upload(&ctx->g_ptr, ptr, true));
-    CHK(ctx->upload(&ctx->g_idx, idx, true));
+    UCHK(ctx->upload(&ctx->g_ptr, ptr, true));
+    UCHK(ctx->upload(&ctx->g_idx, idx, true));
     CHK(owner_sum((int)nG, ctx->g_ptr, ctx->g_idx, gl, nullptr, nullptr, ctx->g, st));
     std::vector<int64_t> src(nS), dst(nS);
     for (int s = 0; s < nS; ++s) {
       src[s] = ctx->subs[s].b0_off + ctx->subs[s].ng;
       dst[s] = nG + s;
     }
-    CHK(ctx->upload(&ctx->p0_src, src, true));
-    CHK(ctx->upload(&ctx->p0_dst, dst, true));
+    UCHK(ctx->upload(&ctx->p0_src, src, true));
+    UCHK(ctx->upload(&ctx->p0_dst, dst, true));
     CHK(scatter_copy(nS, ctx->b0, ctx->p0_src, ctx->p0_dst, ctx->g, 1.0, st));
   }
   // border of X becomes the transformed flux row: X_s = [[S~, b0~], [b0~^T, 0]]
@@ -1651,7 +1810,7 @@ static int setup_impl(vb_ctx *ctx) {
     std::vector<int32_t> iota(ctx->max_ng + 1);
     std::iota(iota.begin(), iota.end(), 0);
     int32_t *d_iota = nullptr;
-    CHK(ctx->upload(&d_iota, iota, true));
+    UCHK(ctx->upload(&d_iota, iota, true));
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       char *X = (char *)Xptr(S);
@@ -1685,12 +1844,12 @@ static int setup_impl(vb_ctx *ctx) {
       ntot += S.Nld * std::max(S.Nn, 1);
     }
     double *Nall = nullptr;
-    CHK(ctx->dalloc(&Nall, ntot, true));
+    UCHK(ctx->dalloc(&Nall, ntot, true));
     CHK(hipMemsetAsync(Nall, 0, ntot * sizeof(double), st));
     int64_t off = 0, itot = 0;
     for (auto &S : ctx->subs) itot += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
     double *invN = nullptr;
-    CHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
+    UCHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
     int64_t ioff = 0;
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
@@ -1699,7 +1858,7 @@ static int setup_impl(vb_ctx *ctx) {
       std::vector<int32_t> idx(S.dl);
       idx.insert(idx.end(), S.pl.begin(), S.pl.end());
       int32_t *d_idx = nullptr;
-      CHK(ctx->upload(&d_idx, idx, true));
+      UCHK(ctx->upload(&d_idx, idx, true));
       int m = S.ndl + S.npi;
       gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
       mxg = std::max(mxg, m);
@@ -1734,7 +1893,7 @@ static int setup_impl(vb_ctx *ctx) {
     int64_t gtot = 0;
     for (auto &S : ctx->subs) gtot += (int64_t)S.ndl * (S.ndl + S.npi);
     double *G1all = nullptr;
-    CHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1)));
+    UCHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1)));
     std::vector<GatherJob> ej;
     int64_t goff = 0;
     int mxr = 0, mxc = 0;
@@ -1746,8 +1905,8 @@ static int setup_impl(vb_ctx *ctx) {
       for (int a = 0; a < S.ndl; ++a) rows[a] = cols[a] = S.npi + a;
       for (int a = 0; a < S.npi; ++a) pc[a] = a;
       int32_t *dr = nullptr, *dpc = nullptr;
-      CHK(ctx->upload(&dr, rows, true));
-      CHK(ctx->upload(&dpc, pc, true));
+      UCHK(ctx->upload(&dr, rows, true));
+      UCHK(ctx->upload(&dpc, pc, true));
       const double *T = S.Nmat + S.ndl + S.ndl * S.Nld;
       ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0});
       if (S.npi) ej.push_back({T, S.Nld, S.G1 + (int64_t)S.ndl * S.ndl, S.ndl, dr, dpc, S.ndl, S.npi, 1.0, 0});
@@ -1773,11 +1932,11 @@ static int setup_impl(vb_ctx *ctx) {
       itot += (int64_t)((ncs + NB - 1) / NB) * NB * NB;
     }
     ctx->Kld = nP == 1 ? ldk[0] : 0;
-    CHK(ctx->dalloc(&ctx->Kaug, std::max<int64_t>(ktot, 1), true));
+    UCHK(ctx->dalloc(&ctx->Kaug, std::max<int64_t>(ktot, 1), true));
     CHK(hipMemsetAsync(ctx->Kaug, 0, ktot * sizeof(double), st));
-    CHK(ctx->dalloc(&ctx->Gc, std::max<int64_t>(gtot, 1)));
+    UCHK(ctx->dalloc(&ctx->Gc, std::max<int64_t>(gtot, 1)));
     double *invC = nullptr;
-    CHK(ctx->dalloc(&invC, std::max<int64_t>(itot, 1), true));
+    UCHK(ctx->dalloc(&invC, std::max<int64_t>(itot, 1), true));
     std::vector<DiagJob> dj;
     std::vector<LdlJob<double>> lj;
     std::vector<void *> m;
@@ -1788,7 +1947,7 @@ static int setup_impl(vb_ctx *ctx) {
     {
       std::vector<int32_t> iota(std::max(ctx->max_ncs, 1));
       std::iota(iota.begin(), iota.end(), 0);
-      CHK(ctx->upload(&di, iota, true));
+      UCHK(ctx->upload(&di, iota, true));
     }
     int64_t io = 0;
     for (int pp = 0; pp < nP; ++pp) {
@@ -1801,19 +1960,19 @@ static int setup_impl(vb_ctx *ctx) {
         std::vector<int32_t> cl(S.cidx.size());
         for (size_t a = 0; a < cl.size(); ++a) cl[a] = S.cidx[a] - P.cbase;
         int32_t *dc = nullptr, *dp = nullptr;
-        CHK(ctx->upload(&dc, cl, true));
-        CHK(ctx->upload(&dp, S.pl, true));
+        UCHK(ctx->upload(&dc, cl, true));
+        UCHK(ctx->upload(&dp, S.pl, true));
         cs[sl] = {S.Nmat + S.ndl + S.ndl * S.Nld, S.Nld, S.npi, dc, dp, ctx->b0 + S.b0_off};
       }
       CoarseSub *dcs = nullptr;
-      CHK(ctx->upload(&dcs, cs, true));
+      UCHK(ctx->upload(&dcs, cs, true));
       double vn = 0.0;
       for (int sl = 0; sl < P.ns; ++sl) vn += ctx->subs[P.s0 + sl].vol * ctx->subs[P.s0 + sl].vol;
       vn = std::sqrt(vn);
       std::vector<double> w(P.ns);
       for (int sl = 0; sl < P.ns; ++sl) w[sl] = ctx->subs[P.s0 + sl].vol / vn;
       double *dw = nullptr;
-      CHK(ctx->upload(&dw, w, true));
+      UCHK(ctx->upload(&dw, w, true));
       CHK(coarse_assemble(dcs, P.ns, K, ldk[pp], P.nprim, dw, st));
       dj.push_back({K, ldk[pp], ncs, 0, ncs, 1.0});
       lj.push_back({K, ldk[pp], 2 * ncs, ncs, P.nprim, 0, invC + io, ctx->info + nS + pp});
@@ -1858,7 +2017,16 @@ static int setup_impl(vb_ctx *ctx) {
       if (m > 0) itot += (int64_t)((m + NB - 1) / NB) * NB * NB;
     }
     double *invD = nullptr;
-    CHK(ctx->dalloc(&invD, std::max<int64_t>(itot, 1), true));
+    UCHK(ctx->dalloc(&invD, std::max<int64_t>(itot, 1), true));
+    // every D_E^(s) in one allocation
+    int64_t dtot = 0;
+    for (auto &H : ctx->ents) {
+      const int m = H.n - H.rank;
+      if (m > 0) dtot += (int64_t)H.subs.size() * m * m;
+    }
+    double *dall = nullptr;
+    UCHK(ctx->dalloc(&dall, std::max<int64_t>(dtot, 1)));
+    int64_t doff = 0;
     int64_t ioff = 0;
     int cnt = 0;
     for (int e = 0; e < nE; ++e) {
@@ -1867,10 +2035,13 @@ static int setup_impl(vb_ctx *ctx) {
       H.D.assign(H.subs.size(), nullptr);
       H.Sbar.assign(H.subs.size(), nullptr);
       std::vector<int64_t> dg(H.gids.begin() + H.rank, H.gids.end());
-      CHK(ctx->upload(&H.d_dual_gids, dg));
+      UCHK(ctx->upload(&H.d_dual_gids, dg));
       if (m <= 0) continue;
       max_m = std::max(max_m, m);
-      for (size_t q = 0; q < H.subs.size(); ++q) CHK(ctx->dalloc(&H.D[q], (int64_t)m * m));
+      for (size_t q = 0; q < H.subs.size(); ++q) {
+        H.D[q] = dall + doff;
+        doff += (int64_t)m * m;
+      }
       if (ctx->opt.scaling == VB_SCALING_COUNTING) {
         for (size_t q = 0; q < H.subs.size(); ++q) {
           CHK(hipMemsetAsync(H.D[q], 0, (size_t)m * m * sizeof(double), st));
@@ -1879,7 +2050,7 @@ static int setup_impl(vb_ctx *ctx) {
         continue;
       }
       H.Dld = round_up(2 * m, 32);
-      CHK(ctx->dalloc(&H.Daug, H.Dld * 2 * m, true));
+      UCHK(ctx->dalloc(&H.Daug, H.Dld * 2 * m, true));
       CHK(hipMemsetAsync(H.Daug, 0, H.Dld * 2 * m * sizeof(double), st));
       for (size_t q = 0; q < H.subs.size(); ++q) {
         const int s = H.subs[q];
@@ -1888,11 +2059,11 @@ static int setup_impl(vb_ctx *ctx) {
         std::vector<int32_t> idx(m);
         for (int a = 0; a < m; ++a) idx[a] = S.ent_off[qq] + H.rank + a;
         int32_t *d_idx = nullptr;
-        CHK(ctx->upload(&d_idx, idx, true));
+        UCHK(ctx->upload(&d_idx, idx, true));
         const void *X = Xptr(S);
         if (rounds.size() <= q) rounds.resize(q + 1);
         rounds[q].push_back({X, S.ld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
-        CHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
+        UCHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
         sb.push_back({X, S.ld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
         mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, m, m, m, m, 0, -1.0, 0.0});
       }
@@ -1931,24 +2102,24 @@ static int setup_impl(vb_ctx *ctx) {
       rc = run_symm(ctx, m, ld, n);
       if (rc) return rc;
       GemmJob<double> *dmj = nullptr;
-      CHK(ctx->upload(&dmj, mj, true));
+      UCHK(ctx->upload(&dmj, mj, true));
       CHK(gemm_nt_batched<double>(dmj, (int)mj.size(), max_m, max_m, st));
     }
   }
   // ---- 9. iteration structures
   {
     // vectors
-    CHK(ctx->dalloc(&ctx->x, nTot));
-    CHK(ctx->dalloc(&ctx->r, nTot));
-    CHK(ctx->dalloc(&ctx->z, nTot));
-    CHK(ctx->dalloc(&ctx->p, nTot));
-    CHK(ctx->dalloc(&ctx->q, nTot));
-    CHK(ctx->dalloc(&ctx->tmp, nTot));
-    CHK(ctx->dalloc(&ctx->sc, SC_STRIDE * ctx->probs.size()));
-    CHK(ctx->dalloc(&ctx->part, std::max<int64_t>(2 * DOT_BLOCKS, (int64_t)ctx->seg_G * ctx->probs.size())));
+    UCHK(ctx->dalloc(&ctx->x, nTot));
+    UCHK(ctx->dalloc(&ctx->r, nTot));
+    UCHK(ctx->dalloc(&ctx->z, nTot));
+    UCHK(ctx->dalloc(&ctx->p, nTot));
+    UCHK(ctx->dalloc(&ctx->q, nTot));
+    UCHK(ctx->dalloc(&ctx->tmp, nTot));
+    UCHK(ctx->dalloc(&ctx->sc, SC_STRIDE * ctx->probs.size()));
+    UCHK(ctx->dalloc(&ctx->part, std::max<int64_t>(2 * DOT_BLOCKS, (int64_t)ctx->seg_G * ctx->probs.size())));
     const int64_t nP = (int64_t)ctx->probs.size();
-    CHK(ctx->dalloc(&ctx->hist_a, (ctx->opt.maxit + 2) * nP));
-    CHK(ctx->dalloc(&ctx->hist_b, (ctx->opt.maxit + 2) * nP));
+    UCHK(ctx->dalloc(&ctx->hist_a, (ctx->opt.maxit + 2) * nP));
+    UCHK(ctx->dalloc(&ctx->hist_b, (ctx->opt.maxit + 2) * nP));
     // S_hat: per-subdomain bordered GEMV (reads p) + owner sums (into q)
     std::vector<GemvJob> js(nS);
     int64_t yoff = 0;
@@ -1966,15 +2137,15 @@ static int setup_impl(vb_ctx *ctx) {
     ctx->schur_bytes = 0.0;
     for (auto &S : ctx->subs)  // the bordered matrix once + x gather + y write
       ctx->schur_bytes += 8.0 * ((double)(S.ng + 1) * (S.ng + 1) + 2.0 * (S.ng + 1));
-    CHK(ctx->dalloc(&ctx->yloc, yoff));
+    UCHK(ctx->dalloc(&ctx->yloc, yoff));
     for (int s = 0; s < nS; ++s) js[s].y = ctx->yloc + ctx->subs[s].y_off;
     std::vector<int64_t> ptr(nTot + 1, 0), idx;
     for (int64_t gg = 0; gg < nTot; ++gg) {
       ptr[gg + 1] = ptr[gg] + own[gg].size();
       idx.insert(idx.end(), own[gg].begin(), own[gg].end());
     }
-    CHK(ctx->upload(&ctx->own_ptr, ptr));
-    CHK(ctx->upload(&ctx->own_idx, idx));
+    UCHK(ctx->upload(&ctx->own_ptr, ptr));
+    UCHK(ctx->upload(&ctx->own_idx, idx));
     // dual vectors: gD (restricted), wv (Neumann output), tv (Neumann [t1; t2])
     int64_t goff = 0, toff = 0;
     std::vector<int64_t> sgo(nS), sto(nS);
@@ -1986,11 +2157,11 @@ static int setup_impl(vb_ctx *ctx) {
     }
     ctx->n_gD = goff;
     ctx->n_tv = toff;
-    CHK(ctx->dalloc(&ctx->gD, goff));
-    CHK(ctx->dalloc(&ctx->wv, goff));
-    CHK(ctx->dalloc(&ctx->tv, toff));
-    CHK(ctx->dalloc(&ctx->rc, ctx->nCS));
-    CHK(ctx->dalloc(&ctx->uc, ctx->nCS));
+    UCHK(ctx->dalloc(&ctx->gD, goff));
+    UCHK(ctx->dalloc(&ctx->wv, goff));
+    UCHK(ctx->dalloc(&ctx->tv, toff));
+    UCHK(ctx->dalloc(&ctx->rc, ctx->nCS));
+    UCHK(ctx->dalloc(&ctx->uc, ctx->nCS));
     // restriction jobs per (entity, subdomain) with duals
     std::vector<GemvJob> jr;
     std::vector<ExtJob> ej;
@@ -2014,24 +2185,24 @@ static int setup_impl(vb_ctx *ctx) {
     ctx->n_restrict = (int)jr.size();
     ctx->n_ext = (int)ej.size();
     ctx->max_ext_m = ctx->max_rm;
-    CHK(ctx->upload(&ctx->j_restrict, jr));
-    CHK(ctx->upload(&ctx->j_ext, ej));
-    CHK(ctx->upload(&ctx->j_extpart, ep));
+    UCHK(ctx->upload(&ctx->j_restrict, jr));
+    UCHK(ctx->upload(&ctx->j_ext, ej));
+    UCHK(ctx->upload(&ctx->j_extpart, ep));
     // Neumann jobs
     std::vector<GemvJob> jn1(nS), jn2(nS);
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       std::vector<int64_t> ci(S.cidx.begin(), S.cidx.end());
       int64_t *dci = nullptr;
-      CHK(ctx->upload(&dci, ci));
+      UCHK(ctx->upload(&dci, ci));
       jn1[s] = {S.G1, std::max(S.ndl, 1), S.ndl, S.ndl + S.npi, ctx->gD + sgo[s], nullptr, nullptr,
                 ctx->tv + sto[s], 1.0, 0};
       jn2[s] = {S.G1 + (int64_t)S.ndl * S.ndl, std::max(S.ndl, 1), S.ndl, S.npi, ctx->uc, dci,
                 ctx->tv + sto[s], ctx->wv + sgo[s], 1.0, 0};
     }
-    CHK(ctx->upload(&ctx->j_schur, js));
-    CHK(ctx->upload(&ctx->j_neu1, jn1));
-    CHK(ctx->upload(&ctx->j_neu2, jn2));
+    UCHK(ctx->upload(&ctx->j_schur, js));
+    UCHK(ctx->upload(&ctx->j_neu1, jn1));
+    UCHK(ctx->upload(&ctx->j_neu2, jn2));
     std::vector<GemvJob> jc;
     for (size_t pp = 0; pp < ctx->probs.size(); ++pp) {
       const auto &P = ctx->probs[pp];
@@ -2039,7 +2210,7 @@ static int setup_impl(vb_ctx *ctx) {
       jc.push_back({ctx->Gc + ctx->gc_off[pp], ncs, ncs, ncs, ctx->rc + P.cbase, nullptr, nullptr,
                     ctx->uc + P.cbase, 1.0, 0});
     }
-    CHK(ctx->upload(&ctx->j_coarse, jc));
+    UCHK(ctx->upload(&ctx->j_coarse, jc));
     // coarse rhs: base = r at the primal positions (or p0), owners = Phi^T g contributions
     std::vector<int64_t> base(ctx->nCS), dst(ctx->nCS);
     std::vector<std::vector<int64_t>> cown(ctx->nCS);
@@ -2057,10 +2228,10 @@ static int setup_impl(vb_ctx *ctx) {
       cptr[c + 1] = cptr[c] + cown[c].size();
       cidx.insert(cidx.end(), cown[c].begin(), cown[c].end());
     }
-    CHK(ctx->upload(&ctx->c_ptr, cptr));
-    CHK(ctx->upload(&ctx->c_idx, cidx));
-    CHK(ctx->upload(&ctx->c_base, base));
-    CHK(ctx->upload(&ctx->uc_dst, base));
+    UCHK(ctx->upload(&ctx->c_ptr, cptr));
+    UCHK(ctx->upload(&ctx->c_idx, cidx));
+    UCHK(ctx->upload(&ctx->c_base, base));
+    UCHK(ctx->upload(&ctx->uc_dst, base));
     for (auto &S : ctx->subs) {
       ctx->max_gt_m = std::max(ctx->max_gt_m, S.ng + 1);
       ctx->max_nt = std::max(ctx->max_nt, S.ndl + S.npi);
@@ -2083,18 +2254,18 @@ static int setup_impl(vb_ctx *ctx) {
       ctx->rec_off[s + 1] = ctx->rec_off[s] + ctx->subs[s].n;
     }
     otot = ctx->rec_off[nS];
-    CHK(ctx->dalloc(&ctx->yrec, tot));
-    CHK(ctx->dalloc(&ctx->zrec, tot));
-    CHK(ctx->dalloc(&ctx->rec_out, otot));
-    CHK(ctx->upload(&ctx->d_yoff, yoff));
-    CHK(ctx->upload(&ctx->d_invoff, invoff));
+    UCHK(ctx->dalloc(&ctx->yrec, tot));
+    UCHK(ctx->dalloc(&ctx->zrec, tot));
+    UCHK(ctx->dalloc(&ctx->rec_out, otot));
+    UCHK(ctx->upload(&ctx->d_yoff, yoff));
+    UCHK(ctx->upload(&ctx->d_invoff, invoff));
     std::vector<RecJob> rj(nS);
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       rj[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
                ctx->zrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
     }
-    CHK(ctx->upload(&ctx->j_rec, rj));
+    UCHK(ctx->upload(&ctx->j_rec, rj));
     if (ctx->fp32) {  // refinement buffers: dense per-subdomain vectors of length N
       std::vector<int64_t> yoff2(nS), uoff(nS);
       int64_t t2 = 0;
@@ -2104,18 +2275,18 @@ static int setup_impl(vb_ctx *ctx) {
         uoff[s] = ctx->rec_off[s];
       }
       ctx->n_ir = t2;
-      CHK(ctx->dalloc(&ctx->y_ir, t2));
-      CHK(ctx->dalloc(&ctx->z_ir, t2));
-      CHK(ctx->dalloc(&ctx->zst, t2));
+      UCHK(ctx->dalloc(&ctx->y_ir, t2));
+      UCHK(ctx->dalloc(&ctx->z_ir, t2));
+      UCHK(ctx->dalloc(&ctx->zst, t2));
       CHK(hipMemsetAsync(ctx->y_ir, 0, t2 * sizeof(double), st));
       CHK(hipMemsetAsync(ctx->z_ir, 0, t2 * sizeof(double), st));
-      CHK(ctx->dalloc(&ctx->u_loc, otot));
-      CHK(ctx->dalloc(&ctx->R_loc, otot));
-      CHK(ctx->dalloc(&ctx->r0, nS));
-      CHK(ctx->dalloc(&ctx->dgv, nG + nS));
-      CHK(ctx->dalloc(&ctx->dx, nG + nS));
-      CHK(ctx->upload(&ctx->d_yoff2, yoff2));
-      CHK(ctx->upload(&ctx->d_uoff, uoff));
+      UCHK(ctx->dalloc(&ctx->u_loc, otot));
+      UCHK(ctx->dalloc(&ctx->R_loc, otot));
+      UCHK(ctx->dalloc(&ctx->r0, nS));
+      UCHK(ctx->dalloc(&ctx->dgv, nG + nS));
+      UCHK(ctx->dalloc(&ctx->dx, nG + nS));
+      UCHK(ctx->upload(&ctx->d_yoff2, yoff2));
+      UCHK(ctx->upload(&ctx->d_uoff, uoff));
       std::vector<RecJob> rj2(nS);
       std::vector<std::vector<int64_t>> own(nG);
       for (int s = 0; s < nS; ++s) {
@@ -2124,14 +2295,14 @@ static int setup_impl(vb_ctx *ctx) {
                   ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]};
         for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff2[s] + S.e + 1 + l);
       }
-      CHK(ctx->upload(&ctx->j_rec_ir, rj2));
+      UCHK(ctx->upload(&ctx->j_rec_ir, rj2));
       std::vector<int64_t> ptr(nG + 1, 0), idx;
       for (int64_t g = 0; g < nG; ++g) {
         ptr[g + 1] = ptr[g] + own[g].size();
         idx.insert(idx.end(), own[g].begin(), own[g].end());
       }
-      CHK(ctx->upload(&ctx->ir_ptr, ptr));
-      CHK(ctx->upload(&ctx->ir_idx, idx));
+      UCHK(ctx->upload(&ctx->ir_ptr, ptr));
+      UCHK(ctx->upload(&ctx->ir_idx, idx));
     }
   }
   CHK(hipEventRecord(ctx->ev1, st));
@@ -2519,7 +2690,7 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
       rel[pp] = r_first[pp] > 0 ? rn / r_first[pp] : 0.0;
       if (!done[pp] && !(rel[pp] > ctx->opt.tol)) {
         done[pp] = 1;
-        tdone[pp] = outer;  // marks the outer step; the clock is taken below
+        if (outer == 0) tdone[pp] = t0[pp];  // converged before any step
       }
       if (!done[pp]) all = false;
       tin[pp] = done[pp] ? 1e300 : std::max(inner_floor, 0.5 * ctx->opt.tol / std::max(rel[pp], 1e-300));

@@ -548,22 +548,25 @@ hipError_t recover_backsolve(const SubDev *d_subs, const void *invL, const int64
 }
 
 // ------------------------------------------------- mixed-precision refinement
-// R = f - K u on every subdomain's local system (CSR order, FP64).
-__global__ void k_local_residual(const SubDev *subs, const double *u, const int64_t *uoff,
-                                 double *R) {
+// R = f - K u on every subdomain's local system (CSR order, FP64): one wave
+// per row, lanes over the row's nonzeros (coalesced), wave reduction.
+__global__ __launch_bounds__(256) void k_local_residual(const SubDev *subs, const double *u,
+                                                        const int64_t *uoff, double *R) {
   const SubDev S = subs[blockIdx.y];
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (row >= S.n_csr) return;
   const double *us = u + uoff[blockIdx.y];
-  double s = S.rhs[row];
-  for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) s -= S.vals[q] * us[S.indices[q]];
-  R[uoff[blockIdx.y] + row] = s;
+  double s = 0.0;
+  for (int64_t q = S.indptr[row] + l; q < S.indptr[row + 1]; q += 64)
+    s += S.vals[q] * us[S.indices[q]];
+  s = warp_sum(s);
+  if (l == 0) R[uoff[blockIdx.y] + row] = S.rhs[row] - s;
 }
 
 hipError_t local_residual(const SubDev *d_subs, const double *u, const int64_t *uoff, double *R,
                           int nsub, int max_rows, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  hipLaunchKernelGGL(k_local_residual, dim3((max_rows + 255) / 256, nsub), dim3(256), 0, s, d_subs,
+  hipLaunchKernelGGL(k_local_residual, dim3((max_rows + 3) / 4, nsub), dim3(256), 0, s, d_subs,
                      u, uoff, R);
   return hipGetLastError();
 }
