@@ -25,6 +25,8 @@ import numpy as np  # noqa: E402
 WORKLOADS = {
     "c2": "32^3 jittered cube (0.15h), VEM k=2, nu=1, 4x4x4 subdomains, vertex+edge+face, deluxe",
     "c1": "8^3 cube, VEM k=2, nu=1, 2x2x2 subdomains, vertex+edge+flux, deluxe",
+    "c3": "48^3 jittered cube (0.15h), VEM k=2, nu=1, 216 uneven subdomains (cuts at seeded "
+          "random positions, 4-12 elements per side), vertex+edge+face, deluxe",
     "c5s": "32 independent problems in one context, each 12^3 jittered cube (0.15h, one mesh), "
            "VEM k=3, 3x3x3 subdomains, nu per subdomain log-uniform in [1e-3, 1e3] (seed = "
            "problem), vertex+edge+face, deluxe, adaptive theta=10 through the learned predictor, "
@@ -40,6 +42,8 @@ PEAK_HBM_GBS = 8000.0
 # workload and path; to be cleared whenever the kernel changes.
 TRAFFIC_BYTES = {("c2", "mixed"): 4.0655e10}
 TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
+# workloads whose FP64 local factors exceed one GPU's memory: mixed path only
+FP64_DOES_NOT_FIT = {"c3": "FP64 bordered local matrices 355 GB > 288 GB HBM (FP32: 178 GB)"}
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
 
@@ -117,7 +121,10 @@ def main():
         wl = load_workload(args.cache)
         log("loaded workload %s (%.1f s)" % (args.cache, time.perf_counter() - t))
     else:
-        wl, _ = make_workload(args.config, workers=min(16, os.cpu_count() or 1))
+        t00 = time.perf_counter()
+        wl, _ = make_workload(args.config, workers=min(16, os.cpu_count() or 1),
+                              progress=lambda m: log("workload %s: %s (%.0f s)"
+                                                     % (args.config, m, time.perf_counter() - t00)))
         log("generated workload %s (%.1f s)" % (args.config, time.perf_counter() - t))
         if args.cache:
             save_workload(args.cache, wl)
@@ -139,6 +146,13 @@ def main():
     nloc = sum(len(sd["kind"]) for sd in wl["subs"])
     runs = {}
     order = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
+    skipped = {}
+    if args.config in FP64_DOES_NOT_FIT and "fp64" in order:
+        order.remove("fp64")
+        skipped["fp64"] = FP64_DOES_NOT_FIT[args.config]
+        log("fp64 path skipped: " + skipped["fp64"])
+        if not order:
+            sys.exit(2)
     for prec in order:
         code = vb.VB_PREC_FP64 if prec == "fp64" else vb.VB_PREC_MIXED
         ctx = vb.vb_create(precision=code, tol=1e-8, stream=stream.cuda_stream, profile=1)
@@ -247,6 +261,7 @@ def main():
         "roofline": roof(R, peak, "f64" if head == "fp64" else "f32", head),
         "iteration_kernel": gemv(R),
         "runs": {k: summary(v) for k, v in runs.items()},
+        "skipped": skipped or None,
         "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
         "mixed_accuracy": check or None,
         "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64", "fp64") if "fp64" in runs else None,

@@ -79,6 +79,12 @@ typedef struct vb_options {
                             vectors come from the network; faces where it does
                             not converge with a margin fall back to the dense
                             exact eigensolve */
+  double setup_mem_limit; /* bytes of device memory the setup may hold at once for
+                             the augmented local Neumann matrices (they are formed
+                             and factored in waves of consecutive subdomains that
+                             fit); 0 = 60% of the free device memory at that step.
+                             A single subdomain larger than the limit still forms
+                             a wave of its own. Results do not depend on it. */
 } vb_options;
 
 /* One face of the adaptive coarse space (Sec. 6), as selected by vb_setup. */

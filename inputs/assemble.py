@@ -88,7 +88,7 @@ class Problem:
     """
 
     def __init__(self, mesh, k, nu=1.0, force=None, uD=None, divD=None, keep_full=False,
-                 chunk=None, workers=None):
+                 chunk=None, workers=None, progress=None):
         self.mesh, self.k = mesh, k
         L = DofLayout(k)
         self.L = L
@@ -169,8 +169,13 @@ class Problem:
             import concurrent.futures as cf
             import os
             nw = workers or min(16, os.cpu_count() or 1)
+            results = []
+            every = max(1, len(chunks) // 8)
             with cf.ProcessPoolExecutor(nw) as ex:
-                results = list(ex.map(_chunk_matrices, [(m, k, el) for el in chunks]))
+                for r in ex.map(_chunk_matrices, [(m, k, el) for el in chunks]):
+                    results.append(r)
+                    if progress and len(results) % every == 0:
+                        progress("element matrices: %d of %d chunks" % (len(results), len(chunks)))
         for ci, s in enumerate(range(0, m.nK, chunk)):
             el = np.arange(s, min(m.nK, s + chunk))
             if uniform:

@@ -65,7 +65,8 @@ RECIPES = {
 }
 
 
-def make_workload(name, seed=0, workers=None, **over):
+def make_workload(name, seed=0, workers=None, progress=None, **over):
+    """progress: optional callable taking a status string (long generations)."""
     r = dict(RECIPES[name])
     r.update(over)
     mesh = CubeMesh(r["n"], jitter=r["jitter"], seed=seed)
@@ -80,9 +81,16 @@ def make_workload(name, seed=0, workers=None, **over):
                               seed=seed)
     if r.get("nu_per_sub"):
         nu = subdomain_viscosity(mesh, cuts, seed)
-    pb = Problem(mesh, r["k"], nu, workers=workers)
+    pb = Problem(mesh, r["k"], nu, workers=workers, progress=progress)
+    if progress:
+        progress("element matrices done")
     dec = Decomposition(pb, cuts, r["cons"])
-    return dec.workload(), {"recipe": r, "problem": pb, "decomposition": dec, "name": name}
+    if progress:
+        progress("decomposition done")
+    wl = dec.workload()
+    if progress:
+        progress("subdomain matrices done")
+    return wl, {"recipe": r, "problem": pb, "decomposition": dec, "name": name}
 
 
 def make_family(name, seeds, workers=None, mesh_seed=0, **over):

@@ -54,6 +54,7 @@ struct SubH {
   int64_t Nld = 0;
   int Nn = 0;
   double *G1 = nullptr;
+  double *Spi = nullptr;        // local coarse block S_Pi (npi x npi), setup scope
 };
 
 struct EntH {
@@ -263,6 +264,14 @@ struct vb_ctx {
       (setup_scope ? setup_allocs : (cur_scope == 2 ? setup_keep : allocs)).push_back(*p);
     return e;
   }
+  // a setup-scope allocation no longer needed before the setup ends
+  void free_setup_early(void *p) {
+    auto it = std::find(setup_allocs.begin(), setup_allocs.end(), p);
+    if (it == setup_allocs.end()) return;  // arena memory: reclaimed with the arena
+    (void)hipStreamSynchronize(stream);
+    (void)hipFree(p);
+    setup_allocs.erase(it);
+  }
   template <class T>
   hipError_t upload(T **p, const std::vector<T> &v, bool setup_scope = false) {
     const size_t bytes = std::max<size_t>(v.size(), 1) * sizeof(T);
@@ -340,7 +349,7 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
     delete ctx;
     return VB_ERR_ARG;
   }
-  if (d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) {
+  if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) || d.setup_mem_limit < 0.0) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -1831,89 +1840,117 @@ static int setup_impl(vb_ctx *ctx) {
   }
   // ---- 6. local constrained Neumann problems: eliminate the duals of
   //         [[S_DD, S_DP, I], [S_PD, S_PP, 0], [I, 0, 0]] -> [[S_Pi, .], [Phi, -S_DD^-1]]
+  //         The augmented matrices are formed and factored in waves of
+  //         consecutive subdomains sized to the free device memory; each wave
+  //         leaves G1 = [S_DD^-1 | Phi] and S_Pi behind.
   {
-    std::vector<GatherJob> gj;
-    std::vector<DiagJob> dj;
-    std::vector<LdlJob<double>> lj;
-    int max_m = 0, max_e = 0, mxg = 0;
-    int64_t ntot = 0;
-    for (int s = 0; s < nS; ++s) {
-      SubH &S = ctx->subs[s];
+    int64_t gtot = 0, stot = 0, itot = 0, ntot = 0, nmax = 1;
+    for (auto &S : ctx->subs) {
       S.Nn = 2 * S.ndl + S.npi;
       S.Nld = round_up(std::max(S.Nn, 1), 32);
+      gtot += (int64_t)S.ndl * (S.ndl + S.npi);
+      stot += (int64_t)S.npi * S.npi;
+      itot += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
       ntot += S.Nld * std::max(S.Nn, 1);
-    }
-    double *Nall = nullptr;
-    UCHK(ctx->dalloc(&Nall, ntot, true));
-    CHK(hipMemsetAsync(Nall, 0, ntot * sizeof(double), st));
-    int64_t off = 0, itot = 0;
-    for (auto &S : ctx->subs) itot += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
-    double *invN = nullptr;
-    UCHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
-    int64_t ioff = 0;
-    for (int s = 0; s < nS; ++s) {
-      SubH &S = ctx->subs[s];
-      S.Nmat = Nall + off;
-      off += S.Nld * std::max(S.Nn, 1);
-      std::vector<int32_t> idx(S.dl);
-      idx.insert(idx.end(), S.pl.begin(), S.pl.end());
-      int32_t *d_idx = nullptr;
-      UCHK(ctx->upload(&d_idx, idx, true));
-      int m = S.ndl + S.npi;
-      gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
-      mxg = std::max(mxg, m);
-      if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0});
-      lj.push_back({S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, invN + ioff, ctx->info + s});
-      ioff += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
-      max_m = std::max(max_m, S.Nn);
-      max_e = std::max(max_e, S.ndl);
+      nmax = std::max(nmax, S.Nld * std::max(S.Nn, 1));
       ctx->max_ndl = std::max(ctx->max_ndl, S.ndl);
       ctx->max_npi = std::max(ctx->max_npi, S.npi);
     }
-    int rc = run_gather(ctx, gj, mxg, mxg);
-    if (rc) return rc;
-    rc = run_diag(ctx, dj, ctx->max_ndl);
-    if (rc) return rc;
-    CHK(hipMemsetAsync(ctx->info, 0, nS * sizeof(int), st));
-    rc = run_ldl(ctx, lj, max_m, max_e);
-    if (rc) return rc;
-    rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Neumann factorisation (subdomain index)");
-    if (rc) return rc;
-    // symmetrize the trailing block, then G1 = [S_DD^-1 | Phi]
-    std::vector<void *> m;
-    std::vector<int64_t> ld;
-    std::vector<int32_t> n;
-    for (auto &S : ctx->subs) {
-      m.push_back(S.Nmat + S.ndl + S.ndl * S.Nld);
-      ld.push_back(S.Nld);
-      n.push_back(S.npi + S.ndl);
-    }
-    rc = run_symm(ctx, m, ld, n);
-    if (rc) return rc;
-    int64_t gtot = 0;
-    for (auto &S : ctx->subs) gtot += (int64_t)S.ndl * (S.ndl + S.npi);
-    double *G1all = nullptr;
+    double *G1all = nullptr, *Spall = nullptr, *invN = nullptr;
     UCHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1)));
-    std::vector<GatherJob> ej;
-    int64_t goff = 0;
-    int mxr = 0, mxc = 0;
-    for (auto &S : ctx->subs) {
-      S.G1 = G1all + goff;
-      goff += (int64_t)S.ndl * (S.ndl + S.npi);
-      if (!S.ndl) continue;
-      std::vector<int32_t> rows(S.ndl), cols(S.ndl), pc(S.npi);
-      for (int a = 0; a < S.ndl; ++a) rows[a] = cols[a] = S.npi + a;
-      for (int a = 0; a < S.npi; ++a) pc[a] = a;
-      int32_t *dr = nullptr, *dpc = nullptr;
-      UCHK(ctx->upload(&dr, rows, true));
-      UCHK(ctx->upload(&dpc, pc, true));
-      const double *T = S.Nmat + S.ndl + S.ndl * S.Nld;
-      ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0});
-      if (S.npi) ej.push_back({T, S.Nld, S.G1 + (int64_t)S.ndl * S.ndl, S.ndl, dr, dpc, S.ndl, S.npi, 1.0, 0});
-      mxr = std::max(mxr, S.ndl);
-      mxc = std::max(mxc, std::max(S.ndl, S.npi));
+    UCHK(ctx->dalloc(&Spall, std::max<int64_t>(stot, 1), true));
+    UCHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
+    {
+      int64_t go = 0, so = 0;
+      for (auto &S : ctx->subs) {
+        S.G1 = G1all + go;
+        S.Spi = Spall + so;
+        go += (int64_t)S.ndl * (S.ndl + S.npi);
+        so += (int64_t)S.npi * S.npi;
+      }
     }
-    rc = run_gather(ctx, ej, mxr, mxc);
+    size_t fre = 0, tot = 0;
+    CHK(hipMemGetInfo(&fre, &tot));
+    const double lim = ctx->opt.setup_mem_limit > 0.0 ? ctx->opt.setup_mem_limit : 0.6 * (double)fre;
+    const int64_t budget = std::max<int64_t>(nmax, (int64_t)(lim / 8));
+    const int64_t wmax = std::min(ntot, budget);
+    double *Nbuf = nullptr;
+    UCHK(ctx->dalloc(&Nbuf, wmax, true));
+    int rc = 0;
+    int64_t ioff = 0;
+    for (int s0 = 0; s0 < nS && !rc;) {
+      int s1 = s0;
+      int64_t off = 0;
+      while (s1 < nS && off + ctx->subs[s1].Nld * std::max(ctx->subs[s1].Nn, 1) <= wmax)
+        off += ctx->subs[s1].Nld * std::max(ctx->subs[s1].Nn, 1), ++s1;
+      CHK(hipMemsetAsync(Nbuf, 0, off * sizeof(double), st));
+      std::vector<GatherJob> gj, ej;
+      std::vector<DiagJob> dj;
+      std::vector<LdlJob<double>> lj;
+      std::vector<void *> m;
+      std::vector<int64_t> ld;
+      std::vector<int32_t> n;
+      int max_m = 0, max_e = 0, mxg = 0, mxr = 0, mxc = 0;
+      off = 0;
+      for (int s = s0; s < s1; ++s) {
+        SubH &S = ctx->subs[s];
+        S.Nmat = Nbuf + off;
+        off += S.Nld * std::max(S.Nn, 1);
+        std::vector<int32_t> idx(S.dl);
+        idx.insert(idx.end(), S.pl.begin(), S.pl.end());
+        int32_t *d_idx = nullptr;
+        UCHK(ctx->upload(&d_idx, idx, true));
+        const int mm = S.ndl + S.npi;
+        gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, mm, mm, 1.0, 0, f32 ? 1 : 0, 0});
+        mxg = std::max(mxg, mm);
+        if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0});
+        lj.push_back({S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, invN + ioff, ctx->info + s});
+        ioff += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
+        max_m = std::max(max_m, S.Nn);
+        max_e = std::max(max_e, S.ndl);
+        // trailing block after the elimination: [[S_Pi, .], [Phi, -S_DD^-1]]
+        const double *T = S.Nmat + S.ndl + S.ndl * S.Nld;
+        m.push_back((void *)T);
+        ld.push_back(S.Nld);
+        n.push_back(S.npi + S.ndl);
+        // its pieces: (rows, cols) index lists into T
+        std::vector<int32_t> rows(S.ndl), pc(S.npi);
+        for (int a = 0; a < S.ndl; ++a) rows[a] = S.npi + a;
+        for (int a = 0; a < S.npi; ++a) pc[a] = a;
+        int32_t *dr = nullptr, *dpc = nullptr;
+        UCHK(ctx->upload(&dr, rows, true));
+        UCHK(ctx->upload(&dpc, pc, true));
+        if (S.ndl) {
+          ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0});
+          if (S.npi)
+            ej.push_back({T, S.Nld, S.G1 + (int64_t)S.ndl * S.ndl, S.ndl, dr, dpc, S.ndl, S.npi, 1.0, 0});
+        }
+        if (S.npi) ej.push_back({T, S.Nld, S.Spi, S.npi, dpc, dpc, S.npi, S.npi, 1.0, 0});
+        mxr = std::max(mxr, std::max(S.ndl, S.npi));
+        mxc = std::max(mxc, std::max(S.ndl, S.npi));
+      }
+      rc = run_gather(ctx, gj, mxg, mxg);
+      if (!rc) rc = run_diag(ctx, dj, ctx->max_ndl);
+      if (!rc) {
+        CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
+        rc = run_ldl(ctx, lj, max_m, max_e);
+      }
+      if (!rc) {
+        std::vector<int> h(s1 - s0);
+        CHK(hipMemcpyAsync(h.data(), ctx->info + s0, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+        CHK(hipStreamSynchronize(st));
+        for (size_t q = 0; q < h.size() && !rc; ++q)
+          if (h[q])
+            rc = ctx->fail(VB_ERR_NOT_SPD, "Neumann factorisation (subdomain index): pivot breakdown in block " +
+                                               std::to_string(s0 + (int)q) + " at column " +
+                                               std::to_string(h[q] - 1));
+      }
+      if (!rc) rc = run_symm(ctx, m, ld, n);
+      if (!rc) rc = run_gather(ctx, ej, mxr, mxc);
+      s0 = s1;
+    }
+    ctx->free_setup_early(Nbuf);
+    for (auto &S : ctx->subs) S.Nmat = nullptr;
     if (rc) return rc;
   }
   // ---- 7. coarse problem: per problem, the inverse of the bordered coarse
@@ -1962,7 +1999,7 @@ static int setup_impl(vb_ctx *ctx) {
         int32_t *dc = nullptr, *dp = nullptr;
         UCHK(ctx->upload(&dc, cl, true));
         UCHK(ctx->upload(&dp, S.pl, true));
-        cs[sl] = {S.Nmat + S.ndl + S.ndl * S.Nld, S.Nld, S.npi, dc, dp, ctx->b0 + S.b0_off};
+        cs[sl] = {S.Spi, std::max(S.npi, 1), S.npi, dc, dp, ctx->b0 + S.b0_off};
       }
       CoarseSub *dcs = nullptr;
       UCHK(ctx->upload(&dcs, cs, true));

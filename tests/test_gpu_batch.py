@@ -7,7 +7,9 @@ solve: same iteration count (the recurrences are the same, only the
 grouping of the reductions' partial sums can differ) and the same solution
 to 1e-10 relative; the operators of the batched context are block diagonal.
 The graph-replayed iteration must give the eager iteration's result (same
-kernels and arguments), on every one of several solves in a row."""
+kernels and arguments), on every one of several solves in a row.  Forming
+the local Neumann matrices in waves of subdomains (a setup memory limit)
+runs the same per-subdomain arithmetic, so it must not change the result."""
 import numpy as np
 import pytest
 
@@ -161,3 +163,13 @@ def test_mixed_batched_reaches_fp64(vb, wls):
             assert _rel(_split(vb, ctx, xg, k), r["x"]) < 1e-9
     finally:
         vb.vb_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_neumann_waves_match_one_wave(vb, wls, precision):
+    wl = wls[2]
+    one = _single(vb, wl, precision=precision)
+    # a limit below any subdomain's augmented matrix: one subdomain per wave
+    waves = _single(vb, wl, precision=precision, setup_mem_limit=1.0)
+    assert waves["info"]["iterations"] == one["info"]["iterations"]
+    assert _rel(waves["x"], one["x"]) < 1e-14
