@@ -58,8 +58,10 @@ enum { VB_KIND_INTERIOR = 0, VB_KIND_INTERFACE = 1, VB_KIND_PRESSURE = 2 };
 enum { VB_ENT_VERTEX = 0, VB_ENT_EDGE = 1, VB_ENT_FACE = 2 };
 
 typedef struct vb_options {
-  int precision;     /* VB_PREC_FP64, or VB_PREC_MIXED: local factors and Schur
-                        operators stored in FP32 (FP64 accumulation), FP64
+  int precision;     /* VB_PREC_FP64, or VB_PREC_MIXED: local Dirichlet and
+                        Neumann factors and Schur operators stored in FP32 (FP64
+                        accumulation; coarse factorisation, deluxe scaling and
+                        PCG recurrences stay FP64), FP64
                         residuals of the local systems drive an iterative
                         refinement of the whole saddle system (see vb_pcg_solve) */
   int scaling;       /* VB_SCALING_DELUXE (Sec. 6) or VB_SCALING_COUNTING (eq. pseudoinv) */

@@ -50,10 +50,10 @@ struct SubH {
   double *d_vals = nullptr, *d_rhs = nullptr, *d_pw = nullptr;
   int64_t *d_gidl = nullptr, *d_gid = nullptr;
   int32_t *d_ents = nullptr, *d_entoff = nullptr;
-  double *Nmat = nullptr;
+  void *Nmat = nullptr;         // augmented Neumann matrix (FP32 in mixed precision)
   int64_t Nld = 0;
   int Nn = 0;
-  double *G1 = nullptr;
+  void *G1 = nullptr;           // [S_DD^-1 | Phi] (FP32 in mixed precision)
   double *Spi = nullptr;        // local coarse block S_Pi (npi x npi), setup scope
 };
 
@@ -1842,8 +1842,13 @@ static int setup_impl(vb_ctx *ctx) {
   //         [[S_DD, S_DP, I], [S_PD, S_PP, 0], [I, 0, 0]] -> [[S_Pi, .], [Phi, -S_DD^-1]]
   //         The augmented matrices are formed and factored in waves of
   //         consecutive subdomains sized to the free device memory; each wave
-  //         leaves G1 = [S_DD^-1 | Phi] and S_Pi behind.
+  //         leaves G1 = [S_DD^-1 | Phi] and S_Pi behind.  In mixed
+  //         precision they are FP32 (they only enter the preconditioner);
+  //         S_Pi is stored in FP64 for the FP64 coarse factorisation.
   {
+    const bool nf = f32;
+    const size_t nsz = nf ? sizeof(float) : sizeof(double);
+    auto at = [&](void *p, int64_t off) -> void * { return (char *)p + off * (int64_t)nsz; };
     int64_t gtot = 0, stot = 0, itot = 0, ntot = 0, nmax = 1;
     for (auto &S : ctx->subs) {
       S.Nn = 2 * S.ndl + S.npi;
@@ -1856,14 +1861,15 @@ static int setup_impl(vb_ctx *ctx) {
       ctx->max_ndl = std::max(ctx->max_ndl, S.ndl);
       ctx->max_npi = std::max(ctx->max_npi, S.npi);
     }
-    double *G1all = nullptr, *Spall = nullptr, *invN = nullptr;
-    UCHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1)));
+    char *G1all = nullptr, *invN = nullptr;
+    double *Spall = nullptr;
+    UCHK(ctx->dalloc(&G1all, std::max<int64_t>(gtot, 1) * nsz));
     UCHK(ctx->dalloc(&Spall, std::max<int64_t>(stot, 1), true));
-    UCHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1), true));
+    UCHK(ctx->dalloc(&invN, std::max<int64_t>(itot, 1) * nsz, true));
     {
       int64_t go = 0, so = 0;
       for (auto &S : ctx->subs) {
-        S.G1 = G1all + go;
+        S.G1 = at(G1all, go);
         S.Spi = Spall + so;
         go += (int64_t)S.ndl * (S.ndl + S.npi);
         so += (int64_t)S.npi * S.npi;
@@ -1872,10 +1878,10 @@ static int setup_impl(vb_ctx *ctx) {
     size_t fre = 0, tot = 0;
     CHK(hipMemGetInfo(&fre, &tot));
     const double lim = ctx->opt.setup_mem_limit > 0.0 ? ctx->opt.setup_mem_limit : 0.6 * (double)fre;
-    const int64_t budget = std::max<int64_t>(nmax, (int64_t)(lim / 8));
+    const int64_t budget = std::max<int64_t>(nmax, (int64_t)(lim / (double)nsz));
     const int64_t wmax = std::min(ntot, budget);
-    double *Nbuf = nullptr;
-    UCHK(ctx->dalloc(&Nbuf, wmax, true));
+    char *Nbuf = nullptr;
+    UCHK(ctx->dalloc(&Nbuf, wmax * nsz, true));
     int rc = 0;
     int64_t ioff = 0;
     for (int s0 = 0; s0 < nS && !rc;) {
@@ -1883,10 +1889,11 @@ static int setup_impl(vb_ctx *ctx) {
       int64_t off = 0;
       while (s1 < nS && off + ctx->subs[s1].Nld * std::max(ctx->subs[s1].Nn, 1) <= wmax)
         off += ctx->subs[s1].Nld * std::max(ctx->subs[s1].Nn, 1), ++s1;
-      CHK(hipMemsetAsync(Nbuf, 0, off * sizeof(double), st));
+      CHK(hipMemsetAsync(Nbuf, 0, off * nsz, st));
       std::vector<GatherJob> gj, ej;
       std::vector<DiagJob> dj;
       std::vector<LdlJob<double>> lj;
+      std::vector<LdlJob<float>> lj32;
       std::vector<void *> m;
       std::vector<int64_t> ld;
       std::vector<int32_t> n;
@@ -1894,23 +1901,29 @@ static int setup_impl(vb_ctx *ctx) {
       off = 0;
       for (int s = s0; s < s1; ++s) {
         SubH &S = ctx->subs[s];
-        S.Nmat = Nbuf + off;
+        S.Nmat = at(Nbuf, off);
         off += S.Nld * std::max(S.Nn, 1);
         std::vector<int32_t> idx(S.dl);
         idx.insert(idx.end(), S.pl.begin(), S.pl.end());
         int32_t *d_idx = nullptr;
         UCHK(ctx->upload(&d_idx, idx, true));
         const int mm = S.ndl + S.npi;
-        gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, mm, mm, 1.0, 0, f32 ? 1 : 0, 0});
+        gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, mm, mm, 1.0, 0, f32 ? 1 : 0,
+                      nf ? 1 : 0});
         mxg = std::max(mxg, mm);
-        if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0});
-        lj.push_back({S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, invN + ioff, ctx->info + s});
+        if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0, nf ? 1 : 0});
+        if (nf)
+          lj32.push_back({(float *)S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, (float *)at(invN, ioff),
+                          ctx->info + s});
+        else
+          lj.push_back({(double *)S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, (double *)at(invN, ioff),
+                        ctx->info + s});
         ioff += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
         max_m = std::max(max_m, S.Nn);
         max_e = std::max(max_e, S.ndl);
         // trailing block after the elimination: [[S_Pi, .], [Phi, -S_DD^-1]]
-        const double *T = S.Nmat + S.ndl + S.ndl * S.Nld;
-        m.push_back((void *)T);
+        void *T = at(S.Nmat, S.ndl + S.ndl * S.Nld);
+        m.push_back(T);
         ld.push_back(S.Nld);
         n.push_back(S.npi + S.ndl);
         // its pieces: (rows, cols) index lists into T
@@ -1920,12 +1933,14 @@ static int setup_impl(vb_ctx *ctx) {
         int32_t *dr = nullptr, *dpc = nullptr;
         UCHK(ctx->upload(&dr, rows, true));
         UCHK(ctx->upload(&dpc, pc, true));
+        const int o = nf ? 1 : 0;
         if (S.ndl) {
-          ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0});
+          ej.push_back({T, S.Nld, S.G1, S.ndl, dr, dr, S.ndl, S.ndl, -1.0, 0, o, o});
           if (S.npi)
-            ej.push_back({T, S.Nld, S.G1 + (int64_t)S.ndl * S.ndl, S.ndl, dr, dpc, S.ndl, S.npi, 1.0, 0});
+            ej.push_back({T, S.Nld, at(S.G1, (int64_t)S.ndl * S.ndl), S.ndl, dr, dpc, S.ndl, S.npi,
+                          1.0, 0, o, o});
         }
-        if (S.npi) ej.push_back({T, S.Nld, S.Spi, S.npi, dpc, dpc, S.npi, S.npi, 1.0, 0});
+        if (S.npi) ej.push_back({T, S.Nld, S.Spi, S.npi, dpc, dpc, S.npi, S.npi, 1.0, 0, o, 0});
         mxr = std::max(mxr, std::max(S.ndl, S.npi));
         mxc = std::max(mxc, std::max(S.ndl, S.npi));
       }
@@ -1933,7 +1948,7 @@ static int setup_impl(vb_ctx *ctx) {
       if (!rc) rc = run_diag(ctx, dj, ctx->max_ndl);
       if (!rc) {
         CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
-        rc = run_ldl(ctx, lj, max_m, max_e);
+        rc = nf ? run_ldl(ctx, lj32, max_m, max_e) : run_ldl(ctx, lj, max_m, max_e);
       }
       if (!rc) {
         std::vector<int> h(s1 - s0);
@@ -1945,7 +1960,7 @@ static int setup_impl(vb_ctx *ctx) {
                                                std::to_string(s0 + (int)q) + " at column " +
                                                std::to_string(h[q] - 1));
       }
-      if (!rc) rc = run_symm(ctx, m, ld, n);
+      if (!rc) rc = run_symm(ctx, m, ld, n, false, nf);
       if (!rc) rc = run_gather(ctx, ej, mxr, mxc);
       s0 = s1;
     }
@@ -2232,10 +2247,11 @@ static int setup_impl(vb_ctx *ctx) {
       std::vector<int64_t> ci(S.cidx.begin(), S.cidx.end());
       int64_t *dci = nullptr;
       UCHK(ctx->upload(&dci, ci));
+      const size_t gsz = ctx->fp32 ? sizeof(float) : sizeof(double);
       jn1[s] = {S.G1, std::max(S.ndl, 1), S.ndl, S.ndl + S.npi, ctx->gD + sgo[s], nullptr, nullptr,
-                ctx->tv + sto[s], 1.0, 0};
-      jn2[s] = {S.G1 + (int64_t)S.ndl * S.ndl, std::max(S.ndl, 1), S.ndl, S.npi, ctx->uc, dci,
-                ctx->tv + sto[s], ctx->wv + sgo[s], 1.0, 0};
+                ctx->tv + sto[s], 1.0, 0, ctx->fp32 ? 1 : 0};
+      jn2[s] = {(const char *)S.G1 + (int64_t)S.ndl * S.ndl * gsz, std::max(S.ndl, 1), S.ndl, S.npi,
+                ctx->uc, dci, ctx->tv + sto[s], ctx->wv + sgo[s], 1.0, 0, ctx->fp32 ? 1 : 0};
     }
     UCHK(ctx->upload(&ctx->j_schur, js));
     UCHK(ctx->upload(&ctx->j_neu1, jn1));

@@ -493,11 +493,25 @@ hipError_t recover_rhs(const SubDev *d_subs, const double *x_orig, double *y, co
   return hipGetLastError();
 }
 
+// Four consecutive entries of a column (16-byte aligned), widened to FP64.
+__device__ __forceinline__ void load4(const float *p, double v[4]) {
+  const float4 f = *reinterpret_cast<const float4 *>(p);
+  v[0] = f.x, v[1] = f.y, v[2] = f.z, v[3] = f.w;
+}
+__device__ __forceinline__ void load4(const double *p, double v[4]) {
+  const double2 *q = reinterpret_cast<const double2 *>(p);
+  const double2 a = q[0], b = q[1];
+  v[0] = a.x, v[1] = a.y, v[2] = b.x, v[3] = b.y;
+}
+
 // Right-looking block back substitution for L_II^T z = y, step for the block
 // i = [i0, i0+b): z_i = inv(L_ii)^T y_i (every workgroup recomputes it from
-// the cached inverse; workgroup 0 stores it), then y_k -= L[i-block, k]^T z_i
-// for all columns k < i0, one wave per column (the block rows are contiguous
-// in the column-major factor).
+// the cached inverse, staged in LDS; workgroup 0 stores it), then
+// y_k -= L[i-block, k]^T z_i for the columns k < i0 of this workgroup's range
+// of 256.  The block rows of a column are contiguous in the column-major
+// factor: 16 lanes cover them with 16-byte loads (4 rows each, z in
+// registers) and reduce with 4 shuffles, so a wave finishes 4 columns per
+// step.
 template <typename T>
 __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const T *invL,
                                                       const int64_t *invoff, double *y,
@@ -505,31 +519,47 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
                                                       int nb) {
   const SubDev S = subs[blockIdx.y];
   if (i0 >= S.e) return;
+  const int k0 = blockIdx.x * 256;
+  if (k0 > 0 && k0 >= i0) return;
   const int b = min(nb, S.e - i0);
   double *ys = y + yoff[blockIdx.y];
   double *zs = z + yoff[blockIdx.y];
+  __shared__ T inv_s[64 * 65];
   __shared__ double yi[64], zi[64];
   const T *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) inv_s[(t / nb) * 65 + t % nb] = inv[t];
   if (threadIdx.x < b) yi[threadIdx.x] = ys[i0 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x < b) {
     const int c = threadIdx.x;
     double s = 0.0;  // (inv^T y)_c = sum_{r >= c} inv[r][c] y_r
-    for (int r = c; r < b; ++r) s += (double)inv[r + c * nb] * yi[r];
+    for (int r = c; r < b; ++r) s += (double)inv_s[c * 65 + r] * yi[r];
     zi[c] = s;
     if (blockIdx.x == 0) zs[i0 + c] = s;
   }
   __syncthreads();
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const double zl = (l < b) ? zi[l] : 0.0;
-  const int k0 = blockIdx.x * 64;
-  for (int kk = w; kk < 64; kk += 4) {
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, g = l >> 4, q = l & 15;
+  double zq[4];
+  for (int t = 0; t < 4; ++t) zq[t] = (4 * q + t < b) ? zi[4 * q + t] : 0.0;
+  const bool full = 4 * q + 3 < b;
+  const T *W = Wp<T>(S) + i0 + 4 * q;
+  for (int kk = 4 * w + g; kk < 256; kk += 16) {
     const int k = k0 + kk;
-    if (k >= i0) break;
-    const auto col = gptr(Wp<T>(S) + (int64_t)k * S.ld + i0);
-    double s = (l < b) ? (double)col[l] * zl : 0.0;
-    s = warp_sum(s);
-    if (l == 0) ys[k] -= s;
+    if (k >= i0) break;  // uniform over the 16 lanes of a column
+    const T *col = W + (int64_t)k * S.ld;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (full) {
+      load4(col, v);
+    } else {
+      for (int t = 0; t < 4; ++t)
+        if (4 * q + t < b) v[t] = (double)col[t];
+    }
+    double s = v[0] * zq[0] + v[1] * zq[1] + v[2] * zq[2] + v[3] * zq[3];
+    s += __shfl_xor(s, 1, 16);
+    s += __shfl_xor(s, 2, 16);
+    s += __shfl_xor(s, 4, 16);
+    s += __shfl_xor(s, 8, 16);
+    if (q == 0) ys[k] -= s;
   }
 }
 
@@ -537,7 +567,8 @@ hipError_t recover_backsolve(const SubDev *d_subs, const void *invL, const int64
                              double *y, double *z, const int64_t *yoff, int nsub, int i0, int nb,
                              bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  const int gx = i0 > 0 ? (i0 + 63) / 64 : 1;
+  if (nb != 32 && nb != 64) return hipErrorInvalidValue;
+  const int gx = i0 > 0 ? (i0 + 255) / 256 : 1;
   if (fp32)
     hipLaunchKernelGGL(k_recover_step<float>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
                        (const float *)invL, invoff, y, z, yoff, i0, nb);
@@ -605,8 +636,11 @@ hipError_t residual_to_dense(const SubDev *d_subs, const double *R, const int64_
 }
 
 // Forward substitution step for block [i0, i0+b) of L (all rows below the
-// block, interface rows included): z_i = inv(L_ii) y_i;
-// y_r -= sum_c L[r, i0+c] z_c for r in [i0+b, N-1).  One thread per row.
+// block, interface rows included): z_i = inv(L_ii) y_i (inverse staged in
+// LDS, recomputed by every workgroup, stored by workgroup 0);
+// y_r -= sum_c L[r, i0+c] z_c for r in [i0+b, N-1).  Each thread owns 4
+// consecutive rows (16-byte loads along the contiguous columns), a
+// workgroup 1024 rows.
 template <typename T>
 __global__ __launch_bounds__(256) void k_forward_step(const SubDev *subs, const T *invL,
                                                       const int64_t *invoff, double *y, double *z,
@@ -614,34 +648,55 @@ __global__ __launch_bounds__(256) void k_forward_step(const SubDev *subs, const 
   const SubDev S = subs[blockIdx.y];
   if (i0 >= S.e) return;
   const int b = min(nb, S.e - i0);
+  const int rbeg = i0 + b, rend = S.N - 1;  // rows updated: [rbeg, rend)
+  const int r0 = (rbeg & ~3) + blockIdx.x * 1024;
+  if (r0 >= rend) return;  // never workgroup 0: rend > e >= rbeg
   double *ys = y + yoff[blockIdx.y];
   double *zs = z + yoff[blockIdx.y];
+  __shared__ T inv_s[64 * 64];
   __shared__ double yi[64], zi[64];
   const T *inv = invL + invoff[blockIdx.y] + (int64_t)(i0 / nb) * nb * nb;
+  for (int t = threadIdx.x; t < nb * nb; t += blockDim.x) inv_s[t] = inv[t];
   if (threadIdx.x < b) yi[threadIdx.x] = ys[i0 + threadIdx.x];
   __syncthreads();
   if (threadIdx.x < b) {
     const int r = threadIdx.x;
     double s = 0.0;  // (inv y)_r = sum_{c <= r} inv[r][c] y_c
-    for (int c = 0; c <= r; ++c) s += (double)inv[r + c * nb] * yi[c];
+    for (int c = 0; c <= r; ++c) s += (double)inv_s[r + c * nb] * yi[c];
     zi[r] = s;
     if (blockIdx.x == 0) zs[i0 + r] = s;
   }
   __syncthreads();
-  const int r = i0 + b + blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= S.N - 1) return;
-  const auto Wb = gptr(Wp<T>(S));
-  double s = 0.0;
-  for (int c = 0; c < b; ++c) s += (double)Wb[(int64_t)r + (int64_t)(i0 + c) * S.ld] * zi[c];
-  ys[r] -= s;
+  const int r = r0 + 4 * threadIdx.x;
+  if (r >= rend) return;
+  const T *base = Wp<T>(S) + (int64_t)i0 * S.ld + r;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (r >= rbeg && r + 4 <= rend) {
+#pragma unroll 8
+    for (int c = 0; c < b; ++c) {
+      double v[4];
+      load4(base + (int64_t)c * S.ld, v);
+      const double zc = zi[c];
+      acc[0] += v[0] * zc, acc[1] += v[1] * zc, acc[2] += v[2] * zc, acc[3] += v[3] * zc;
+    }
+    for (int t = 0; t < 4; ++t) ys[r + t] -= acc[t];
+  } else {
+    for (int t = 0; t < 4; ++t) {
+      if (r + t < rbeg || r + t >= rend) continue;
+      double a = 0.0;
+      for (int c = 0; c < b; ++c) a += (double)base[(int64_t)c * S.ld + t] * zi[c];
+      ys[r + t] -= a;
+    }
+  }
 }
 
 hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *invoff, double *y,
                         double *z, const int64_t *yoff, int nsub, int i0, int nb, int max_N,
                         bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  const int rows = max_N - i0;
-  const int gx = rows > 0 ? (rows + 255) / 256 : 1;
+  if (nb != 32 && nb != 64) return hipErrorInvalidValue;
+  const int rows = max_N - i0 + 4;
+  const int gx = rows > 0 ? (rows + 1023) / 1024 : 1;
   if (fp32)
     hipLaunchKernelGGL(k_forward_step<float>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
                        (const float *)invL, invoff, y, z, yoff, i0, nb);

@@ -241,8 +241,9 @@ def test_mixed_interior_recovery_parity(vb, mixed_case):
 
 
 def test_mixed_operators_are_fp32_roundings(vb, mixed_case):
-    """S_hat from the FP32 factorisation differs from the FP64 one by FP32
-    rounding amplified by the local conditioning, and is not identical."""
+    """S_hat and M^-1 from the FP32 factorisations differ from the FP64 ones
+    by FP32 rounding amplified by the local conditioning, and are not
+    identical."""
     name, wl, meta, o, ctx = mixed_case
     n = vb.vb_interface_size(ctx)
     x = np.random.default_rng(3).standard_normal(n)
@@ -251,3 +252,19 @@ def test_mixed_operators_are_fp32_roundings(vb, mixed_case):
     torch.cuda.synchronize()
     d = _rel(y.cpu().numpy(), o.apply_S(x))
     assert 1e-12 < d < 1e-3, d
+    # M^-1 is built from that S_hat (its local Neumann factors are FP32 too;
+    # coarse factorisation and deluxe scaling FP64): its relative change is
+    # the change of S_hat, or FP32 rounding, amplified by the conditioning of
+    # the local Neumann blocks S_DD that it inverts
+    # (compared like the FP64 preconditioner: on a residual in the range of
+    # S_hat, the p0 part up to the constant kernel)
+    r = o.apply_S(x)
+    z = torch.zeros(n, dtype=torch.float64, device=DEV)
+    vb.vb_apply(ctx, _dev(r), z)
+    torch.cuda.synchronize()
+    zg, zo, nG = z.cpu().numpy(), o.apply_M(r), o.nG
+    zg[nG:] -= zg[nG:].mean()
+    zo[nG:] -= zo[nG:].mean()
+    dm = _rel(zg, zo)
+    kappa = max(np.linalg.cond(L.St[np.ix_(L.Dl, L.Dl)]) for L in o.loc if len(L.Dl))
+    assert 1e-12 < dm < 10.0 * kappa * max(d, 2.0 ** -24), (dm, d, kappa)
