@@ -42,8 +42,6 @@ PEAK_HBM_GBS = 8000.0
 # workload and path; to be cleared whenever the kernel changes.
 TRAFFIC_BYTES = {("c2", "mixed"): 4.0655e10}
 TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
-# workloads whose FP64 local factors exceed one GPU's memory: mixed path only
-FP64_DOES_NOT_FIT = {"c3": "FP64 bordered local matrices 355 GB > 288 GB HBM (FP32: 178 GB)"}
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
 
@@ -145,14 +143,10 @@ def main():
     n = None
     nloc = sum(len(sd["kind"]) for sd in wl["subs"])
     runs = {}
-    order = ["fp64", "mixed"] if args.precision == "both" else [args.precision]
-    skipped = {}
-    if args.config in FP64_DOES_NOT_FIT and "fp64" in order:
-        order.remove("fp64")
-        skipped["fp64"] = FP64_DOES_NOT_FIT[args.config]
-        log("fp64 path skipped: " + skipped["fp64"])
-        if not order:
-            sys.exit(2)
+    # mixed first: each context is destroyed after its run except the FP64
+    # one, kept for the accuracy check of the mixed solution (both do not
+    # fit in memory at once at the largest workloads)
+    order = ["mixed", "fp64"] if args.precision == "both" else [args.precision]
     for prec in order:
         code = vb.VB_PREC_FP64 if prec == "fp64" else vb.VB_PREC_MIXED
         ctx = vb.vb_create(precision=code, tol=1e-8, stream=stream.cuda_stream, profile=1)
@@ -192,6 +186,11 @@ def main():
         log("%s: timed %d solves in %.3f s: %d iterations, residual %.2e"
             % (prec, args.steps, dt, last["iterations"], last["true_rel_residual"]))
         runs[prec] = dict(ctx=ctx, x=x, dt=dt, ldl=ldl, gmv=gmv, info=last)
+        if prec != "fp64":
+            vb.vb_destroy(ctx)
+            runs[prec]["ctx"] = None
+            del u
+            torch.cuda.empty_cache()
     # ---- accuracy of the mixed solution against the FP64 operator and solution
     check = {}
     if "mixed" in runs and "fp64" in runs:
@@ -208,7 +207,8 @@ def main():
         log("mixed vs fp64: %s" % check)
         assert check["fp64_interface_rel_residual"] <= 1e-8 * 1.01, check
     for r in runs.values():
-        vb.vb_destroy(r["ctx"])
+        if r["ctx"] is not None:
+            vb.vb_destroy(r["ctx"])
     head = "mixed" if "mixed" in runs else "fp64"
     R = runs[head]
     if head == "fp64":
@@ -261,7 +261,6 @@ def main():
         "roofline": roof(R, peak, "f64" if head == "fp64" else "f32", head),
         "iteration_kernel": gemv(R),
         "runs": {k: summary(v) for k, v in runs.items()},
-        "skipped": skipped or None,
         "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
         "mixed_accuracy": check or None,
         "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64", "fp64") if "fp64" in runs else None,

@@ -87,6 +87,16 @@ typedef struct vb_options {
                              fit); 0 = 60% of the free device memory at that step.
                              A single subdomain larger than the limit still forms
                              a wave of its own. Results do not depend on it. */
+  double local_mem_limit; /* bytes of device memory for the dense bordered local
+                             Dirichlet matrices (FP64 only). When all of them
+                             exceed it, they are formed, factored and condensed
+                             in waves of consecutive subdomains sharing one
+                             buffer of at most this size (a single larger
+                             subdomain forms a wave of its own): the condensed
+                             interface blocks are kept in a compact array and
+                             vb_recover_all / vb_get_local_solution factor each
+                             wave again. 0 = 45% of the free device memory at
+                             the first vb_setup. Results do not depend on it. */
 } vb_options;
 
 /* One face of the adaptive coarse space (Sec. 6), as selected by vb_setup. */

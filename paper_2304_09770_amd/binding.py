@@ -26,7 +26,7 @@ class vb_options(C.Structure):
                 ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
                 ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double),
                 ("predictor", C.c_void_p),
-                ("setup_mem_limit", C.c_double)]
+                ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double)]
 
 
 class vb_problem(C.Structure):
@@ -167,10 +167,10 @@ def _check(ctx, rc):
 # ------------------------------------------------------------- C-ABI names
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
               svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
-              predictor=None, setup_mem_limit=0.0):
+              predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
-                     adaptive_theta, predictor, setup_mem_limit)
+                     adaptive_theta, predictor, setup_mem_limit, local_mem_limit)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:

@@ -62,6 +62,8 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 struct SubDev {
   void *W;          // dense local matrix (double or float), column-major, ld
   int64_t ld;
+  void *X;          // condensed bordered interface block (ng+1)^2: inside W, or a
+  int64_t xld;      // compact copy when the local matrices are processed in waves
   int nv, nel, ng;  // interior velocity, element pressures, interface DoFs
   int N;            // nv + nel + ng + 1 (last row/col: right-hand side)
   int e;            // eliminated columns = nv + nel - 1

@@ -45,6 +45,8 @@ struct SubH {
   int npi = 0, ndl = 0;
   // device
   int64_t W_off = 0, inv_off = 0, b0_off = 0, hv_off = 0, y_off = 0;
+  void *X = nullptr;            // condensed block (ng+1)^2 of W, or its compact copy
+  int64_t xld = 0, X_off = 0;
   int64_t *d_indptr = nullptr;
   int32_t *d_indices = nullptr, *d_pos = nullptr, *d_kind = nullptr;
   double *d_vals = nullptr, *d_rhs = nullptr, *d_pw = nullptr;
@@ -102,6 +104,12 @@ struct vb_ctx {
   size_t wsz = 8;         // bytes per entry of W and invL
   void *W = nullptr;
   void *invL = nullptr;
+  // dense local matrices: one wave holding every subdomain, or (FP64 beyond
+  // the memory limit) waves of consecutive subdomains sharing W, with the
+  // condensed blocks copied to Xc and the factors recomputed for recovery
+  bool stream_w = false;
+  std::vector<std::pair<int, int>> waves;
+  void *Xc = nullptr;
   double *b0 = nullptr, *hv = nullptr;
   int *info = nullptr;
   SubDev *d_subdev = nullptr;
@@ -349,7 +357,8 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
     delete ctx;
     return VB_ERR_ARG;
   }
-  if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) || d.setup_mem_limit < 0.0) {
+  if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) || d.setup_mem_limit < 0.0 ||
+      d.local_mem_limit < 0.0) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -526,10 +535,10 @@ static int finalize_device(vb_ctx *ctx) {
   const int n_ent = (int)ctx->ents.size();
   const int64_t n_iface = ctx->nG;
   // ---- device copies of the caller's data and the dense workspace
-  int64_t wtot = 0, itot = 0, btot = 0, htot = 0;
+  int64_t wtot = 0, itot = 0, btot = 0, htot = 0, wmax1 = 1;
   for (auto &S : ctx->subs) {
-    S.W_off = wtot;
     wtot += S.ld * S.N;
+    wmax1 = std::max(wmax1, S.ld * S.N);
     S.inv_off = itot;
     itot += (int64_t)((S.e + NB - 1) / NB) * NB * NB;
     S.b0_off = btot;
@@ -538,11 +547,44 @@ static int finalize_device(vb_ctx *ctx) {
     htot += S.nel + 1;
   }
   {
+    size_t fre = 0, tot = 0;
+    UCHK(hipMemGetInfo(&fre, &tot));
+    const double lim = ctx->opt.local_mem_limit > 0.0 ? ctx->opt.local_mem_limit : 0.45 * (double)fre;
+    ctx->stream_w = !ctx->fp32 && (double)wtot * (double)ctx->wsz > lim;
+    ctx->waves.clear();
+    int64_t wcap = 0;
+    const int64_t cap = ctx->stream_w ? std::max<int64_t>(wmax1, (int64_t)(lim / ctx->wsz)) : wtot;
+    for (int s0 = 0; s0 < n_sub;) {
+      int s1 = s0;
+      int64_t off = 0;
+      while (s1 < n_sub && (s1 == s0 || off + ctx->subs[s1].ld * ctx->subs[s1].N <= cap)) {
+        ctx->subs[s1].W_off = off;
+        off += ctx->subs[s1].ld * ctx->subs[s1].N;
+        ++s1;
+      }
+      ctx->waves.push_back({s0, s1});
+      wcap = std::max(wcap, off);
+      s0 = s1;
+    }
     char *w = nullptr, *iv = nullptr;
-    UCHK(ctx->dalloc(&w, (size_t)wtot * ctx->wsz));
+    UCHK(ctx->dalloc(&w, (size_t)std::max<int64_t>(wcap, 1) * ctx->wsz));
     UCHK(ctx->dalloc(&iv, (size_t)itot * ctx->wsz));
     ctx->W = w;
     ctx->invL = iv;
+    int64_t xtot = 0;
+    for (auto &S : ctx->subs) {
+      if (ctx->stream_w) {
+        S.xld = round_up(S.ng + 1, 32);
+        S.X_off = xtot;
+        xtot += S.xld * (S.ng + 1);
+      } else {
+        S.xld = S.ld;
+        S.X_off = S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld;
+      }
+    }
+    if (ctx->stream_w) UCHK(ctx->dalloc(&w, (size_t)xtot * ctx->wsz));
+    ctx->Xc = ctx->stream_w ? w : ctx->W;
+    for (auto &S : ctx->subs) S.X = (char *)ctx->Xc + S.X_off * ctx->wsz;
   }
   UCHK(ctx->dalloc(&ctx->b0, btot));
   UCHK(ctx->dalloc(&ctx->hv, htot));
@@ -566,6 +608,8 @@ static int finalize_device(vb_ctx *ctx) {
     SubDev &D = ctx->subdev[s];
     D.W = (char *)ctx->W + S.W_off * ctx->wsz;
     D.ld = S.ld;
+    D.X = S.X;
+    D.xld = S.xld;
     D.nv = S.nv;
     D.nel = S.nel;
     D.ng = S.ng;
@@ -700,7 +744,8 @@ static int check_info(vb_ctx *ctx, int count, int code, const char *what) {
 
 
 static void *x_block(vb_ctx *ctx, const SubH &S) {
-  return (char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
+  (void)ctx;
+  return S.X;
 }
 
 // Householder QR with column pivoting of every entity's constraint rows.
@@ -1003,7 +1048,7 @@ static int adaptive_stage(vb_ctx *ctx) {
     std::vector<int32_t> n;
     for (auto &S : ctx->subs) {
       m.push_back(x_block(ctx, S));
-      ld.push_back(S.ld);
+      ld.push_back(S.xld);
       n.push_back(S.ng + 1);
     }
     int rc = run_symm(ctx, m, ld, n, false, f32);
@@ -1098,7 +1143,7 @@ static int adaptive_stage(vb_ctx *ctx) {
           for (int l = 0; l < f.nF; ++l) perm.push_back(f.off[k] + l);
           int32_t *d_perm = nullptr;
           UCHK(ctx->upload(&d_perm, perm, true));
-          gp.push_back({x_block(ctx, S), S.ld, P, ldp, d_perm, d_perm, ng, ng, 1.0, 0, f32 ? 1 : 0, 0});
+          gp.push_back({x_block(ctx, S), S.xld, P, ldp, d_perm, d_perm, ng, ng, 1.0, 0, f32 ? 1 : 0, 0});
           ft.push_back({P, ldp, ng, ng - f.nF, ctx->d_entdev + f.e, +1});
           tm.push_back(P);
           tld.push_back(ldp);
@@ -1601,6 +1646,55 @@ static int adaptive_stage(vb_ctx *ctx) {
 
 static int autotune_gemvs(vb_ctx *ctx);
 
+// Dense bordered local matrices of subdomains [s0, s1) (one wave sharing W):
+// densify the CSR, rotate the pressures, partial LDL^T of the interior
+// columns.  Deterministic: a wave factorised again reproduces its factors.
+static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
+  hipStream_t st = ctx->stream;
+  const bool f32 = ctx->fp32;
+  int64_t wend = 0;
+  int mxN = 0, mxe = 0;
+  for (int s = s0; s < s1; ++s) {
+    const SubH &S = ctx->subs[s];
+    wend = std::max(wend, S.W_off + S.ld * S.N);
+    mxN = std::max(mxN, S.N);
+    mxe = std::max(mxe, S.e);
+  }
+  const int64_t w0 = ctx->subs[s0].W_off;
+  CHK(hipMemsetAsync((char *)ctx->W + w0 * ctx->wsz, 0, (wend - w0) * ctx->wsz, st));
+  CHK(densify(ctx->d_subdev + s0, s1 - s0, ctx->max_n_csr, f32, st));
+  CHK(house_pressure(ctx->d_subdev + s0, s1 - s0, mxN, f32, st));
+  CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
+  int rc;
+  if (f32) {
+    std::vector<LdlJob<float>> jobs;
+    for (int s = s0; s < s1; ++s) {
+      SubH &S = ctx->subs[s];
+      jobs.push_back({(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
+                      (float *)ctx->invL + S.inv_off, ctx->info + s});
+    }
+    rc = run_ldl(ctx, jobs, mxN, mxe, timed);
+  } else {
+    std::vector<LdlJob<double>> jobs;
+    for (int s = s0; s < s1; ++s) {
+      SubH &S = ctx->subs[s];
+      jobs.push_back({(double *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
+                      (double *)ctx->invL + S.inv_off, ctx->info + s});
+    }
+    rc = run_ldl(ctx, jobs, mxN, mxe, timed);
+  }
+  if (rc) return rc;
+  std::vector<int> h(s1 - s0);
+  CHK(hipMemcpyAsync(h.data(), ctx->info + s0, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  for (size_t q = 0; q < h.size(); ++q)
+    if (h[q])
+      return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
+                                           std::to_string(s0 + (int)q) + " at column " +
+                                           std::to_string(h[q] - 1));
+  return VB_OK;
+}
+
 extern "C" {
 
 static int setup_impl(vb_ctx *ctx);
@@ -1660,41 +1754,23 @@ static int setup_impl(vb_ctx *ctx) {
   ctx->d_feat = ctx->d_lab = nullptr;  // freed with the previous setup
   ctx->n_coord = 0;
   CHK(hipEventRecord(ctx->ev0, st));
-  // ---- 1. local dense bordered matrices, flux rows, pressure split
-  int64_t wtot = 0;
-  for (auto &S : ctx->subs) wtot += S.ld * S.N;
-  CHK(hipMemsetAsync(ctx->W, 0, wtot * ctx->wsz, st));
+  // ---- 1.-2. per wave of subdomains: local dense bordered matrices, pressure
+  //      split, Dirichlet factorisation + Schur complement (eqs. uipi,
+  //      firstSchur); with several waves the condensed blocks are copied out
   const bool f32 = ctx->fp32;
-  auto Xptr = [&](const SubH &S) -> void * {
-    return (char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
-  };
+  auto Xptr = [&](const SubH &S) -> void * { return S.X; };
   CHK(hipMemsetAsync(ctx->info, 0, (4 * (size_t)nS + 64 + 4 * ctx->ents.size()) * sizeof(int), st));
-  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, f32, st));
   CHK(flux_rows(ctx->d_subdev, nS, ctx->max_n_csr, st));
-  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, f32, st));
-  // ---- 2. Dirichlet factorisation + Schur complement (eqs. uipi, firstSchur)
-  {
-    int rc;
-    if (f32) {
-      std::vector<LdlJob<float>> jobs(nS);
-      for (int s = 0; s < nS; ++s) {
-        SubH &S = ctx->subs[s];
-        jobs[s] = {(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
-                   (float *)ctx->invL + S.inv_off, ctx->info + s};
-      }
-      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, true);
-    } else {
-      std::vector<LdlJob<double>> jobs(nS);
-      for (int s = 0; s < nS; ++s) {
-        SubH &S = ctx->subs[s];
-        jobs[s] = {(double *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
-                   (double *)ctx->invL + S.inv_off, ctx->info + s};
-      }
-      rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, true);
+  for (const auto &wv : ctx->waves) {
+    int rc = factor_wave(ctx, wv.first, wv.second, true);
+    if (rc) return rc;
+    if (!ctx->stream_w) continue;
+    for (int s = wv.first; s < wv.second; ++s) {
+      const SubH &S = ctx->subs[s];
+      const char *src = (const char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
+      CHK(hipMemcpy2DAsync(S.X, S.xld * ctx->wsz, src, S.ld * ctx->wsz, (S.ng + 1) * ctx->wsz, S.ng + 1,
+                           hipMemcpyDeviceToDevice, st));
     }
-    if (rc) return rc;
-    rc = check_info(ctx, nS, VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index)");
-    if (rc) return rc;
   }
   // ---- 3. primal constraints: QR with column pivoting per entity
   const int nE = (int)ctx->ents.size();
@@ -1758,7 +1834,7 @@ static int setup_impl(vb_ctx *ctx) {
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       m[s] = Xptr(S);
-      ld[s] = S.ld;
+      ld[s] = S.xld;
       n[s] = S.ng + 1;
     }
     int rc = run_symm(ctx, m, ld, n, false, f32);
@@ -1787,7 +1863,7 @@ static int setup_impl(vb_ctx *ctx) {
     int64_t fo = 0;
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
-      GatherJob J{Xptr(S), S.ld, gl + fo, S.ng, d_iota, d_iota, S.ng, 1, 1.0, 0, f32 ? 1 : 0, 0};
+      GatherJob J{Xptr(S), S.xld, gl + fo, S.ng, d_iota, d_iota, S.ng, 1, 1.0, 0, f32 ? 1 : 0, 0};
       J.ci = d_iota + S.ng;  // column ng of X
       gj.push_back(J);
       for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(fo + l);
@@ -1826,12 +1902,12 @@ static int setup_impl(vb_ctx *ctx) {
       double *b0 = ctx->b0 + S.b0_off;
       const int o32 = f32 ? 1 : 0;
       // last column: X[l, ng] = b0[l]  (in: b0 as an ng x 1 matrix)
-      jobs.push_back({b0, 1, X + (int64_t)S.ng * S.ld * ctx->wsz, S.ld, d_iota, d_iota, S.ng, 1,
+      jobs.push_back({b0, 1, X + (int64_t)S.ng * S.xld * ctx->wsz, S.xld, d_iota, d_iota, S.ng, 1,
                       1.0, 0, 0, o32});
       // last row: X[ng, l] = b0[l]  (in: b0 as a 1 x ng matrix, ld 1)
-      jobs.push_back({b0, 1, X + (int64_t)S.ng * ctx->wsz, S.ld, d_iota, d_iota, 1, S.ng, 1.0, 0, 0,
+      jobs.push_back({b0, 1, X + (int64_t)S.ng * ctx->wsz, S.xld, d_iota, d_iota, 1, S.ng, 1.0, 0, 0,
                       o32});
-      dj.push_back({X, S.ld, S.ng, S.ng, 1, 0.0, o32});
+      dj.push_back({X, S.xld, S.ng, S.ng, 1, 0.0, o32});
     }
     int rc = run_gather(ctx, jobs, ctx->max_ng, ctx->max_ng);
     if (rc) return rc;
@@ -1908,7 +1984,7 @@ static int setup_impl(vb_ctx *ctx) {
         int32_t *d_idx = nullptr;
         UCHK(ctx->upload(&d_idx, idx, true));
         const int mm = S.ndl + S.npi;
-        gj.push_back({Xptr(S), S.ld, S.Nmat, S.Nld, d_idx, d_idx, mm, mm, 1.0, 0, f32 ? 1 : 0,
+        gj.push_back({Xptr(S), S.xld, S.Nmat, S.Nld, d_idx, d_idx, mm, mm, 1.0, 0, f32 ? 1 : 0,
                       nf ? 1 : 0});
         mxg = std::max(mxg, mm);
         if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0, nf ? 1 : 0});
@@ -2114,9 +2190,9 @@ static int setup_impl(vb_ctx *ctx) {
         UCHK(ctx->upload(&d_idx, idx, true));
         const void *X = Xptr(S);
         if (rounds.size() <= q) rounds.resize(q + 1);
-        rounds[q].push_back({X, S.ld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
+        rounds[q].push_back({X, S.xld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
         UCHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
-        sb.push_back({X, S.ld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
+        sb.push_back({X, S.xld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
         mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, m, m, m, m, 0, -1.0, 0.0});
       }
       dj.push_back({H.Daug, H.Dld, m, 0, m, 1.0});
@@ -2179,7 +2255,7 @@ static int setup_impl(vb_ctx *ctx) {
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       S.y_off = yoff;
-      js[s] = {Xptr(S), S.ld, S.ng + 1, S.ng + 1, ctx->p, S.d_gidl, nullptr, nullptr, 1.0, 0,
+      js[s] = {Xptr(S), S.xld, S.ng + 1, S.ng + 1, ctx->p, S.d_gidl, nullptr, nullptr, 1.0, 0,
                f32 ? 1 : 0};
       for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff + l);
       own[nG + s].push_back(yoff + S.ng);
@@ -2901,11 +2977,20 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
                          hipMemcpyDeviceToDevice, st));
     return VB_OK;
   }
-  CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, ctx->nS, ctx->max_e, ctx->fp32, st));
   const int nb = ctx->opt.panel;  // the panel width the factorisation used
-  for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
-    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->zrec,
-                          ctx->d_yoff, ctx->nS, j0, nb, ctx->fp32, st));
+  for (const auto &wv : ctx->waves) {
+    const int s0 = wv.first, n = wv.second - wv.first;
+    if (ctx->stream_w) {  // the factors of this wave again (W holds the last wave's)
+      int rc = factor_wave(ctx, s0, wv.second, false);
+      if (rc) return rc;
+    }
+    int mxe = 0;
+    for (int s = s0; s < wv.second; ++s) mxe = std::max(mxe, ctx->subs[s].e);
+    CHK(recover_rhs(ctx->d_subdev + s0, x_dev, ctx->yrec, ctx->d_yoff + s0, n, mxe, ctx->fp32, st));
+    for (int j0 = ((mxe - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+      CHK(recover_backsolve(ctx->d_subdev + s0, ctx->invL, ctx->d_invoff + s0, ctx->yrec, ctx->zrec,
+                            ctx->d_yoff + s0, n, j0, nb, ctx->fp32, st));
+  }
   CHK(recover_out(ctx->j_rec, ctx->nS, x_dev, ctx->nG, st));
   if (out_dev)
     CHK(hipMemcpyAsync(out_dev, ctx->rec_out, ctx->rec_off[ctx->nS] * sizeof(double),

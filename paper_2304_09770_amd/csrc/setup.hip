@@ -363,16 +363,16 @@ __global__ void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
   const EntDev E = ents[S.ent[blockIdx.y]];
   const int o = S.ent_off[blockIdx.y];
   const int rk = *E.rank;
-  T *X = Wp<T>(S) + (int64_t)(S.e + 1) + (int64_t)(S.e + 1) * S.ld;
-  T *row = X + i;
+  T *row = (T *)S.X + i;
+  const int64_t ld = S.xld;
   for (int k = 0; k < rk; ++k) {
     const double *v = E.V + (int64_t)k * E.n;
     const double tau = E.tau[k];
     double t = 0.0;
-    for (int c = k; c < E.n; ++c) t += (double)row[(int64_t)(o + c) * S.ld] * v[c];
+    for (int c = k; c < E.n; ++c) t += (double)row[(int64_t)(o + c) * ld] * v[c];
     t *= tau;
     for (int c = k; c < E.n; ++c)
-      row[(int64_t)(o + c) * S.ld] = (T)((double)row[(int64_t)(o + c) * S.ld] - t * v[c]);
+      row[(int64_t)(o + c) * ld] = (T)((double)row[(int64_t)(o + c) * ld] - t * v[c]);
   }
 }
 

@@ -9,7 +9,10 @@ to 1e-10 relative; the operators of the batched context are block diagonal.
 The graph-replayed iteration must give the eager iteration's result (same
 kernels and arguments), on every one of several solves in a row.  Forming
 the local Neumann matrices in waves of subdomains (a setup memory limit)
-runs the same per-subdomain arithmetic, so it must not change the result."""
+runs the same per-subdomain arithmetic, so it must not change the result;
+neither must forming, factoring and condensing the dense local Dirichlet
+matrices in waves (compact condensed blocks, factors recomputed for the
+interior recovery)."""
 import numpy as np
 import pytest
 
@@ -173,3 +176,27 @@ def test_neumann_waves_match_one_wave(vb, wls, precision):
     waves = _single(vb, wl, precision=precision, setup_mem_limit=1.0)
     assert waves["info"]["iterations"] == one["info"]["iterations"]
     assert _rel(waves["x"], one["x"]) < 1e-14
+
+
+def test_dirichlet_waves_match_resident(vb, wls):
+    wl = wls[2]
+    nloc = sum(len(sd["kind"]) for sd in wl["subs"])
+    out = []
+    for lim in (0.0, 1.0):  # resident; one subdomain per wave
+        ctx = vb.vb_create(local_mem_limit=lim)
+        try:
+            vb.vb_assemble(ctx, wl)
+            vb.vb_setup(ctx)
+            n = vb.vb_interface_size(ctx)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            info = vb.vb_pcg_solve(ctx, x)
+            u = torch.zeros(nloc, dtype=torch.float64, device=DEV)
+            vb.vb_recover_all(ctx, x, u)
+            torch.cuda.synchronize()
+            out.append((info, x.cpu().numpy(), u.cpu().numpy()))
+        finally:
+            vb.vb_destroy(ctx)
+    (i0, x0, u0), (i1, x1, u1) = out
+    assert i1["iterations"] == i0["iterations"]
+    assert _rel(x1, x0) < 1e-14
+    assert _rel(u1, u0) < 1e-14
