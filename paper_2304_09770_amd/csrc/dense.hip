@@ -399,7 +399,7 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     if (r != hipSuccess) return r;
     attr = true;
   }
-  const int SB = 4 * nb;  // super-panel width
+  const int SB = 8 * nb;  // super-panel width
   for (int J0 = 0; J0 < max_e; J0 += SB) {
     const int jend = std::min(J0 + SB, max_e);
     for (int j0 = J0; j0 < jend; j0 += nb) {
