@@ -208,8 +208,13 @@ constexpr int WT = 128;
 // keep the prefetch of the next chunk hidden behind the current one.
 template <typename T> struct WideKW { static constexpr int value = 16; };
 template <> struct WideKW<float> { static constexpr int value = 32; };
-template <typename T>
-__device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int J0, int SB) {
+// RECT: only the columns [ke, min(col_end, e)) of the trailing matrix (the
+// rest of an enclosing super-panel); the tiles are enumerated column block
+// by column block, nt_max row tiles per block.  Otherwise the whole lower
+// triangle beyond ke, tiles enumerated row by row.
+template <typename T, bool RECT>
+__device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int J0, int SB,
+                                                     int col_end, int nt_max) {
   typedef Mfma<T> M;
   constexpr int KW = WideKW<T>::value;
   const LdlJob<T> J = jobs[blockIdx.y];
@@ -219,10 +224,26 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
   if (m0 >= J.n) return;
   const int nt = (J.n - m0 + WT - 1) / WT;
   const int t = blockIdx.x;
-  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
-  while (ti * (ti + 1) / 2 > t) --ti;
-  const int tk = t - ti * (ti + 1) / 2;
+  int ti, tk, ce;
+  if (RECT) {
+    ce = min(col_end, J.e);
+    if (ce <= m0) return;
+    const int ntk = (ce - m0 + WT - 1) / WT;
+    int rem = t;
+    tk = 0;
+    while (tk < ntk && rem >= nt_max - tk) {
+      rem -= nt_max - tk;
+      ++tk;
+    }
+    if (tk >= ntk) return;
+    ti = tk + rem;
+  } else {
+    ce = J.n;
+    ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+    while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+    while (ti * (ti + 1) / 2 > t) --ti;
+    tk = t - ti * (ti + 1) / 2;
+  }
   if (ti >= nt) return;
   const int i0 = m0 + ti * WT, k0 = m0 + tk * WT;
   extern __shared__ unsigned char smem_raw[];
@@ -235,7 +256,7 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
   // staging map: row r (128), columns c = c0 + 2q (q < KW/2)
   const int r = tid & (WT - 1), c0 = tid >> 7;
   const int ri = min(i0 + r, J.n - 1), rk = min(k0 + r, J.n - 1);
-  const bool oki = (i0 + r < J.n), okk = (k0 + r < J.n);
+  const bool oki = (i0 + r < J.n), okk = (k0 + r < ce);
   constexpr int NQ = KW / 2;
   T bi_[NQ], bk_[NQ];
   // raw loads only: the masks and pivot signs are applied when the values are
@@ -291,7 +312,7 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int col = k0 + 64 * wk + 16 * bk + M::row(lk, q);
-        if (col < J.n) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
+        if (col < ce) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
       }
     }
 }
@@ -300,18 +321,29 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 // bytes per stage, four waves per SIMD.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
-  ldl_update_wide_body<double>(jobs, J0, SB);
+  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
-  ldl_update_wide_body<float>(jobs, J0, SB);
+  ldl_update_wide_body<float, false>(jobs, J0, SB, 0, 0);
+}
+// the update inside an enclosing super-panel (columns up to its end)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_rect_f64(const LdlJob<double> *jobs, int J0, int SB, int col_end, int nt_max) {
+  ldl_update_wide_body<double, true>(jobs, J0, SB, col_end, nt_max);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ldl_update_rect_f32(const LdlJob<float> *jobs, int J0, int SB, int col_end, int nt_max) {
+  ldl_update_wide_body<float, true>(jobs, J0, SB, col_end, nt_max);
 }
 template <typename T> struct WideKernel;
 template <> struct WideKernel<double> {
   static constexpr auto fn = k_ldl_update_wide_f64;
+  static constexpr auto rect = k_ldl_update_rect_f64;
 };
 template <> struct WideKernel<float> {
   static constexpr auto fn = k_ldl_update_wide_f32;
+  static constexpr auto rect = k_ldl_update_rect_f32;
 };
 
 // C = alpha A B^T + beta C (column-major), 64x64 tiles, K in chunks of 64.
@@ -396,25 +428,48 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f32,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void *)k_ldl_update_rect_f64,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void *)k_ldl_update_rect_f32,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r != hipSuccess) return r;
     attr = true;
   }
-  const int SB = 8 * nb;  // super-panel width
-  for (int J0 = 0; J0 < max_e; J0 += SB) {
-    const int jend = std::min(J0 + SB, max_e);
-    for (int j0 = J0; j0 < jend; j0 += nb) {
-      hipError_t r = (nb == 64) ? ldl_panel_step<T, 64>(d_jobs, batch, max_n, j0, J0 + SB, s)
-                                : ldl_panel_step<T, 32>(d_jobs, batch, max_n, j0, J0 + SB, s);
-      if (r != hipSuccess) return r;
+  // two levels of super-panels: the columns of an outer super-panel (SB1)
+  // are factored in inner super-panels (SB2) of nb-wide panels; the update
+  // of the rest of the outer super-panel follows each inner one, the update
+  // of the whole trailing matrix each outer one (rank SB1)
+  const int SB1 = 16 * nb, SB2 = 4 * nb;
+  for (int J0 = 0; J0 < max_e; J0 += SB1) {
+    const int j1end = std::min(J0 + SB1, max_e);
+    for (int J1 = J0; J1 < j1end; J1 += SB2) {
+      const int j2end = std::min(J1 + SB2, max_e);
+      for (int j0 = J1; j0 < j2end; j0 += nb) {
+        hipError_t r = (nb == 64) ? ldl_panel_step<T, 64>(d_jobs, batch, max_n, j0, J1 + SB2, s)
+                                  : ldl_panel_step<T, 32>(d_jobs, batch, max_n, j0, J1 + SB2, s);
+        if (r != hipSuccess) return r;
+      }
+      const int ncols = J0 + SB1 - (J1 + SB2);
+      if (ncols > 0 && max_n > J1) {
+        const int nt_max = (max_n - J1 + WT - 1) / WT;
+        const int ntk = std::min(nt_max, (ncols + WT - 1) / WT);
+        const int ntiles = ntk * nt_max - ntk * (ntk - 1) / 2;
+        hipLaunchKernelGGL(WideKernel<T>::rect, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J1,
+                           SB2, J0 + SB1, nt_max);
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+      }
     }
-    // algorithmic flops of the wide update: K * m * (m + 1) per matrix
+    // algorithmic flops of the trailing update: K * m * (m + 1) per matrix
     // (symmetric rank-K update of the m x m lower triangle)
     double flops = 0.0;
     if (timer && hn && he)
       for (size_t q = 0; q < hn->size(); ++q) {
         if (J0 >= (*he)[q]) continue;
-        const double K = std::min(J0 + SB, (*he)[q]) - J0;
-        const double m = (*hn)[q] - std::min(J0 + SB, (*he)[q]);
+        const double K = std::min(J0 + SB1, (*he)[q]) - J0;
+        const double m = (*hn)[q] - std::min(J0 + SB1, (*he)[q]);
         if (m > 0) flops += K * m * (m + 1.0);
       }
     // a job whose elimination ends inside this super-panel has n - e_job
@@ -425,7 +480,7 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
       const int ntiles = wt * (wt + 1) / 2;
       if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
       hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
-                         SB);
+                         SB1);
       if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
     }
     hipError_t e = hipGetLastError();

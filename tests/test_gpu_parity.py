@@ -40,7 +40,10 @@ def test_batched_ldl_schur_matches_definition(vb):
     """Partial signed LDL^T: trailing block = A22 - A21 A11^-1 A21^T, with
     A11 a saddle matrix [[SPD, B^T], [B, 0]] (velocity pivots +, pressure -)."""
     rng = np.random.default_rng(0)
-    cases = [(200, 150, 120), (97, 70, 64), (130, 129, 100), (64, 64, 64)]
+    # small cases, and cases whose elimination crosses the boundaries of the
+    # inner (256) and outer (1024) super-panels of the blocked factorisation
+    cases = [(200, 150, 120), (97, 70, 64), (130, 129, 100), (64, 64, 64),
+             (1300, 1024, 900), (1500, 1100, 1000), (2600, 2300, 2000)]
     mats, ptrs, ns, lds, es, ps, refs = [], [], [], [], [], [], []
     for n, e, p in cases:
         Q = rng.standard_normal((n, n))
