@@ -40,7 +40,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the readings of a 1 GiB device copy: x2.0, x1.0), per
 # workload and path; to be cleared whenever the kernel changes.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {("c2", "mixed"): 9.9103e10}
 TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
@@ -219,8 +219,8 @@ def main():
         ldl = r["ldl"]
         a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
         return {"bound": "mfma",
-                "kernel": "k_ldl_update_wide_%s (rank-256 trailing update of the local Dirichlet "
-                          "LDL^T)" % dtype,
+                "kernel": "k_ldl_update_wide_%s (rank-1024 trailing update of the local "
+                          "Dirichlet LDL^T)" % dtype,
                 "achieved": a, "peak": pk, "unit": "TFLOP/s", "frac": (a / pk) if a else None,
                 "traffic": TRAFFIC_BYTES.get((args.config, prec)),
                 "traffic_source": TRAFFIC_SOURCE if (args.config, prec) in TRAFFIC_BYTES else None,

@@ -319,12 +319,23 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 
 // FP64: 206 VGPRs, two waves per SIMD.  FP32: 124 VGPRs and half the LDS
 // bytes per stage, four waves per SIMD.
+// The local Dirichlet factorisations (the dominant work, timed per launch)
+// and the other factorisations (Neumann, deluxe, coarse, face problems) run
+// the same code under two kernel names, so that profiles separate them.
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
   ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
+  ldl_update_wide_body<float, false>(jobs, J0, SB, 0, 0);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide_aux_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ldl_update_wide_aux_f32(const LdlJob<float> *jobs, int J0, int SB) {
   ldl_update_wide_body<float, false>(jobs, J0, SB, 0, 0);
 }
 // the update inside an enclosing super-panel (columns up to its end)
@@ -339,10 +350,12 @@ void k_ldl_update_rect_f32(const LdlJob<float> *jobs, int J0, int SB, int col_en
 template <typename T> struct WideKernel;
 template <> struct WideKernel<double> {
   static constexpr auto fn = k_ldl_update_wide_f64;
+  static constexpr auto aux = k_ldl_update_wide_aux_f64;
   static constexpr auto rect = k_ldl_update_rect_f64;
 };
 template <> struct WideKernel<float> {
   static constexpr auto fn = k_ldl_update_wide_f32;
+  static constexpr auto aux = k_ldl_update_wide_aux_f32;
   static constexpr auto rect = k_ldl_update_rect_f32;
 };
 
@@ -418,7 +431,7 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer, const std::vector<int> *hn,
-                       const std::vector<int> *he) {
+                       const std::vector<int> *he, bool dirichlet) {
   if (batch == 0 || max_e == 0) return hipSuccess;
   static bool attr = false;
   const size_t lds = 2 * (size_t)WideKW<T>::value * WT * sizeof(T);
@@ -427,6 +440,12 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f32,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_aux_f64,
+                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (r == hipSuccess)
+      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_aux_f32,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void *)k_ldl_update_rect_f64,
@@ -479,8 +498,12 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
       const int wt = (rows + WT - 1) / WT;
       const int ntiles = wt * (wt + 1) / 2;
       if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
-      hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
-                         SB1);
+      if (dirichlet)
+        hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
+                           SB1);
+      else
+        hipLaunchKernelGGL(WideKernel<T>::aux, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
+                           SB1);
       if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
     }
     hipError_t e = hipGetLastError();
@@ -499,9 +522,11 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 }
 
 template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t,
-                                        KTimer *, const std::vector<int> *, const std::vector<int> *);
+                                        KTimer *, const std::vector<int> *, const std::vector<int> *,
+                                        bool);
 template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t,
-                                       KTimer *, const std::vector<int> *, const std::vector<int> *);
+                                       KTimer *, const std::vector<int> *, const std::vector<int> *,
+                                       bool);
 template hipError_t gemm_nt_batched<double>(const GemmJob<double> *, int, int, int, hipStream_t);
 template hipError_t gemm_nt_batched<float>(const GemmJob<float> *, int, int, int, hipStream_t);
 

@@ -694,7 +694,7 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
     he[b] = jobs[b].e;
   }
   CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
-                     (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he));
+                     (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he, timed));
   return VB_OK;
 }
 
