@@ -27,11 +27,16 @@ WORKLOADS = {
     "c1": "8^3 cube, VEM k=2, nu=1, 2x2x2 subdomains, vertex+edge+flux, deluxe",
     "c3": "48^3 jittered cube (0.15h), VEM k=2, nu=1, 216 uneven subdomains (cuts at seeded "
           "random positions, 4-12 elements per side), vertex+edge+face, deluxe",
+    "c4": "32^3 cube, VEM k=2, 8 spherical sinkers (radius 0.1, centres seed 0) with nu=1e4 "
+          "inside and 1 outside, 4x4x4 subdomains, vertex+edge+face, deluxe, adaptive face "
+          "constraints theta=10 through the learned predictor (trained on the exact eigensolves "
+          "of sinker seeds 1, 2), FP64",
     "c5s": "32 independent problems in one context, each 12^3 jittered cube (0.15h, one mesh), "
            "VEM k=3, 3x3x3 subdomains, nu per subdomain log-uniform in [1e-3, 1e3] (seed = "
            "problem), vertex+edge+face, deluxe, adaptive theta=10 through the learned predictor, "
            "mixed precision",
 }
+C4_TRAIN_SEEDS = (1, 2)
 C5S_PROBLEMS = 32
 C5S_TRAIN_SEEDS = (100, 101)
 PEAK_FP64_TFLOPS = 78.6
@@ -48,6 +53,18 @@ PRECISION_NAMES = {"fp64": "fp64",
 
 def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def ldl_roofline(ldl, peak, dtype, traffic=None, source=None):
+    """Achieved rate of the timed Dirichlet trailing-update launches
+    (vb_kernel_stats 0: algorithmic flops and HIP-event durations)."""
+    a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
+    return {"bound": "mfma",
+            "kernel": "k_ldl_update_wide_%s (rank-1024 trailing update of the local "
+                      "Dirichlet LDL^T)" % dtype,
+            "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": (a / peak) if a else None,
+            "traffic": traffic, "traffic_source": source,
+            "launches": ldl["launches"], "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
 
 
 def cpu_baseline(wl, nsample, budget_s=30.0):
@@ -112,6 +129,8 @@ def main():
         return
     if args.config == "c5s":
         return run_batched(args)
+    if args.config == "c4":
+        return run_adaptive(args)
     # ---- workload (before any GPU initialisation)
     from inputs.workloads import make_workload, save_workload, load_workload
     t = time.perf_counter()
@@ -216,16 +235,9 @@ def main():
     peak = PEAK_FP64_TFLOPS if head == "fp64" else PEAK_FP32_TFLOPS
 
     def roof(r, pk, dtype, prec):
-        ldl = r["ldl"]
-        a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
-        return {"bound": "mfma",
-                "kernel": "k_ldl_update_wide_%s (rank-1024 trailing update of the local "
-                          "Dirichlet LDL^T)" % dtype,
-                "achieved": a, "peak": pk, "unit": "TFLOP/s", "frac": (a / pk) if a else None,
-                "traffic": TRAFFIC_BYTES.get((args.config, prec)),
-                "traffic_source": TRAFFIC_SOURCE if (args.config, prec) in TRAFFIC_BYTES else None,
-                "launches": ldl["launches"],
-                "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
+        key = (args.config, prec)
+        return ldl_roofline(r["ldl"], pk, dtype, TRAFFIC_BYTES.get(key),
+                            TRAFFIC_SOURCE if key in TRAFFIC_BYTES else None)
 
     def gemv(r):
         g = r["gmv"]
@@ -269,6 +281,108 @@ def main():
     print(json.dumps(out), flush=True)
 
 
+def run_adaptive(args):
+    """C4: the adaptive coarse space through the learned predictor against the
+    exact adaptive space and the minimal primal space (the plain FP64 GPU
+    method), all FP64 (the contrast of 1e4 inside subdomains)."""
+    from inputs.workloads import make_workload, mlp_init_params
+    t = time.perf_counter()
+    nw = min(16, os.cpu_count() or 1)
+    wl, _ = make_workload("c4", seed=0, workers=nw)
+    train = [make_workload("c4", seed=sd, workers=nw)[0] for sd in C4_TRAIN_SEEDS]
+    log("generated c4 and %d training workloads (%.1f s)" % (len(train), time.perf_counter() - t))
+    import torch
+    from paper_2304_09770_amd import binding as vb
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    stream = torch.cuda.Stream(device=dev)
+    theta = 10.0
+    m = vb.vb_mlp_create(mlp_init_params(12, 32, 7), stream.cuda_stream)
+    with torch.cuda.stream(stream):
+        for w in train:
+            c = vb.vb_create(adaptive_theta=theta, stream=stream.cuda_stream)
+            vb.vb_assemble(c, w)
+            vb.vb_setup(c)
+            vb.vb_mlp_add_samples(m, c)
+            vb.vb_destroy(c)
+        hist = vb.vb_mlp_train(m, 1500, 3e-3)
+    log("predictor: %d samples, loss %.3e -> %.3e" % (vb.vb_mlp_num_samples(m), hist[0], hist[-1]))
+    nloc = sum(len(sd["kind"]) for sd in wl["subs"])
+    spaces = [("minimal", {}), ("exact", dict(adaptive_theta=theta)),
+              ("learned", dict(adaptive_theta=theta, predictor=m))]
+    runs, xs = {}, {}
+    with torch.cuda.stream(stream):
+        for name, kw in spaces:
+            ctx = vb.vb_create(tol=1e-8, stream=stream.cuda_stream, profile=1, **kw)
+            vb.vb_assemble(ctx, wl)
+            n = vb.vb_interface_size(ctx)
+            x = torch.zeros(n, dtype=torch.float64, device=dev)
+            u = torch.zeros(nloc, dtype=torch.float64, device=dev)
+
+            def solve():
+                vb.vb_setup(ctx)
+                x.zero_()
+                info = vb.vb_pcg_solve(ctx, x)
+                vb.vb_recover_all(ctx, x, u)
+                return info
+
+            for _ in range(args.warmup):
+                solve()
+            stream.synchronize()
+            vb.vb_kernel_stats(ctx, 0, reset=True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(args.steps):
+                info = solve()
+            stream.synchronize()
+            dt = (time.perf_counter() - t0) / args.steps
+            faces = vb.vb_adaptive_info(ctx) if kw else []
+            runs[name] = {"solves_per_s": 1.0 / dt, "ms_per_step": 1e3 * dt,
+                          "iterations": info["iterations"],
+                          "kappa": info["lambda_max"] / info["lambda_min"],
+                          "n_coarse": info["n_coarse"], "rel_residual": info["true_rel_residual"],
+                          "setup_ms": info["setup_ms"], "solve_ms": info["solve_ms"],
+                          "faces": len(faces),
+                          "predicted_path_faces": sum(f["path"] == 1 for f in faces),
+                          "fallback_faces": sum(f["path"] == 2 for f in faces),
+                          "selected_rows": sum(f["n_selected"] for f in faces)}
+            runs[name]["ldl"] = vb.vb_kernel_stats(ctx, 0)
+            xs[name] = x.cpu().numpy()
+            log("%s: %.3f solves/s, %d iterations, kappa %.1f, N_c %d"
+                % (name, 1.0 / dt, info["iterations"], runs[name]["kappa"], info["n_coarse"]))
+            assert info["true_rel_residual"] <= 1e-8 * 1.01, info
+            vb.vb_destroy(ctx)
+    vb.vb_mlp_destroy(m)
+    ldl = runs["learned"].pop("ldl")
+    for r in runs.values():
+        r.pop("ldl", None)
+    ref = xs["exact"]
+    out = {
+        "metric": "PCG+BDDC solves/s at 1e-8 rel. residual, mixed/batched vs FP64 GPU",
+        "value": runs["learned"]["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": runs["learned"]["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "c4: " + WORKLOADS["c4"], "subdomains": len(wl["subs"]),
+                   "precision": "fp64"},
+        "roofline": ldl_roofline(ldl, PEAK_FP64_TFLOPS, "f64"),
+        "runs": runs,
+        "speedup_vs_fp64": runs["learned"]["solves_per_s"] / runs["minimal"]["solves_per_s"],
+        "speedup_vs_exact_adaptive": runs["learned"]["solves_per_s"] / runs["exact"]["solves_per_s"],
+        "rel_diff_learned_vs_exact_solution": float(np.linalg.norm(xs["learned"] - ref) /
+                                                    np.linalg.norm(ref)),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def run_batched(args):
     """Several independent problems in one context against one context per
     problem: aggregate solves/s and per-problem latency (device clock from the
@@ -297,7 +411,7 @@ def run_batched(args):
         hist = vb.vb_mlp_train(m, 1500, 3e-3)
     log("predictor: %d samples, loss %.3e -> %.3e" % (vb.vb_mlp_num_samples(m), hist[0], hist[-1]))
     opts = dict(precision=vb.VB_PREC_MIXED, tol=1e-8, adaptive_theta=theta, predictor=m,
-                stream=stream.cuda_stream)
+                stream=stream.cuda_stream, profile=1)
 
     def run(ctx, steps):
         n = vb.vb_interface_size(ctx)
@@ -331,10 +445,12 @@ def run_batched(args):
         for wl in batch:
             vb.vb_assemble(ctx, wl)
         run(ctx, args.warmup)
+        vb.vb_kernel_stats(ctx, 0, reset=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         info = run(ctx, args.steps)
         t1 = time.perf_counter()
+        ldl = vb.vb_kernel_stats(ctx, 0)
         per = [vb.vb_problem_solve_info(ctx, k) for k in range(len(batch))]
         faces = vb.vb_adaptive_info(ctx)
         tiles = [vb.vb_tuned_tile(ctx, k) for k in range(4)]
@@ -385,7 +501,7 @@ def run_batched(args):
         "predicted_path_faces": sum(f["path"] == 1 for f in faces),
         "fallback_faces": sum(f["path"] == 2 for f in faces),
         "gemv_tiles": tiles,
-        "roofline": None,
+        "roofline": ldl_roofline(ldl, PEAK_FP32_TFLOPS, "f32"),
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

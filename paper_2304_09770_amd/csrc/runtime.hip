@@ -786,12 +786,17 @@ struct PredFace {
 // predicted count allows it.  The network's scores summed over a face give
 // k; the block has b = max(k + 4, 1.3 k + 2) vectors (at most 64 and n/2),
 // starting from the unit vectors of the b best-scored coordinates.  A pass
-// applies a degree-20 Chebyshev filter damping [2 sigma, rho] (rho: the
-// Gershgorin bound of C), orthonormalises, and takes Rayleigh-Ritz pairs
-// (eigensolve of the b x b projection with the dense kernels).  Accepted
+// applies a degree-20 Chebyshev filter damping [a, rho] (rho: the
+// Gershgorin bound of C; a = 2 sigma in the first pass, then the largest
+// Ritz value of the block, so that everything beyond the block is damped),
+// orthonormalises, and takes Rayleigh-Ritz pairs (eigensolve of the b x b
+// projection with the dense kernels).  Accepted
 // when fewer than b - 2 Ritz values lie below sigma (a margin that the
-// count is complete) and every selected pair has residual <= 1e-9 rho;
-// otherwise up to 4 passes, then the face falls back to the exact solve.
+// count is complete), every selected pair has residual <= 1e-6 rho, and the
+// count is certain: a symmetric matrix has an eigenvalue within the residual
+// norm of every Ritz value, so theta_t + r_t < sigma for the selected pairs
+// and theta - r > sigma for the next one.  Otherwise up to 6 passes, then
+// the face falls back to the exact solve.
 template <class GetFace>
 static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
                           const std::vector<int64_t> &coff, const double *d_rho, double sigma,
@@ -883,7 +888,7 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
     }
     CHK(hipStreamSynchronize(st));
   }
-  const int deg = 20, max_pass = 4;
+  const int deg = 20, max_pass = 6;
   std::vector<char> done(na, 0);
   for (int pass = 0; pass < max_pass; ++pass) {
     std::vector<int> live;
@@ -973,8 +978,13 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
         continue;
       }
       double rmax = 0.0;
-      for (int t = 0; t < kr; ++t) rmax = std::max(rmax, res[t]);
-      if (rmax <= 1e-9 * P.rho) {
+      bool certain = true;
+      for (int t = 0; t < kr; ++t) {
+        rmax = std::max(rmax, res[t]);
+        certain = certain && th[t] + res[t] < sigma;
+      }
+      certain = certain && th[kr] - res[kr] > sigma;
+      if (rmax <= 1e-6 * P.rho && certain) {
         done[live[k]] = 1;
         path[q] = 1;
         hc[q] = kr;
@@ -983,7 +993,12 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
           CHK(hipMemcpyAsync(F.lam, lr + (int64_t)live[k] * 128, kr * sizeof(double),
                              hipMemcpyDeviceToDevice, st));
         }
-      } else {  // next pass from the Ritz vectors
+      } else {  // next pass from the Ritz vectors, damping beyond the block
+        const double an = th[P.b - 1];
+        if (an > 1.02 * sigma && an < P.rho) {
+          P.e = 0.5 * (P.rho - an);
+          P.c0 = 0.5 * (P.rho + an);
+        }
         CHK(hipMemcpyAsync(w + P.o_y[0], w + P.o_v2, (size_t)P.b * P.n * sizeof(double),
                            hipMemcpyDeviceToDevice, st));
       }
