@@ -320,10 +320,18 @@ def run_adaptive(args):
             u = torch.zeros(nloc, dtype=torch.float64, device=dev)
 
             def solve():
+                t0 = time.perf_counter()
                 vb.vb_setup(ctx)
+                stream.synchronize()
+                t1 = time.perf_counter()
                 x.zero_()
                 info = vb.vb_pcg_solve(ctx, x)
+                stream.synchronize()
+                t2 = time.perf_counter()
                 vb.vb_recover_all(ctx, x, u)
+                stream.synchronize()
+                log("%s step: setup %.3f s (device %.1f ms), solve %.3f s, recovery %.3f s"
+                    % (name, t1 - t0, info["setup_ms"], t2 - t1, time.perf_counter() - t2))
                 return info
 
             for _ in range(args.warmup):

@@ -124,7 +124,7 @@ hipError_t symmetrize(void *const *mats, const int64_t *lds, const int32_t *ns, 
 hipError_t transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
                         int max_n, bool fp32, hipStream_t s);
 hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
-                        int max_ent, bool fp32, hipStream_t s);
+                        int max_ent, int max_en, bool fp32, hipStream_t s);
 hipError_t transform_b0(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ent,
                         hipStream_t s);
 // global vector <-> transformed coordinates (dir = +1: x~ = T^T x, -1: x = T x~)

@@ -88,7 +88,7 @@ struct vb_ctx {
   std::string err;
   int state = 0;  // 0 created, 1 assembled, 2 set up
   std::vector<void *> allocs;        // assemble scope (until destroy)
-  std::vector<void *> setup_allocs;  // setup scratch (freed when setup ends)
+  std::vector<void *> setup_allocs;  // setup scratch (back to the pool when setup ends)
   std::vector<void *> setup_keep;    // setup results (freed by the next setup)
   int cur_scope = 0;                 // 0: allocs, 2: setup_keep
   KTimer t_ldl, t_gemv;              // per-launch device timing of the dominant kernels
@@ -250,9 +250,68 @@ struct vb_ctx {
     for (Chunk &c : chunks) c.used = c.lo = c.hi = 0;
     cur_chunk = 0;
     dirty = false;
-    for (void *q : setup_allocs) (void)hipFree(q);
+    for (void *q : setup_allocs) pool_put(q);
     setup_allocs.clear();
     return e;
+  }
+  // Device blocks of the setup (scratch and results) are kept between
+  // setups and handed out again by best fit: a new setup of the same
+  // problem finds every large buffer it needs without hipMalloc/hipFree
+  // (which synchronise and, for buffers of tens of GB, can stall for
+  // seconds).  Unused blocks are released when an allocation fails and when
+  // the context is destroyed.
+  struct PBlock {
+    void *p;
+    size_t bytes;
+    bool used;
+  };
+  std::vector<PBlock> pool;
+  hipError_t pool_get(void **out, size_t bytes) {
+    bytes = (bytes + 255) & ~size_t(255);
+    int best = -1;
+    for (size_t i = 0; i < pool.size(); ++i) {
+      const PBlock &b = pool[i];
+      if (b.used || b.bytes < bytes || b.bytes > bytes + bytes / 2 + (size_t(64) << 20)) continue;
+      if (best < 0 || b.bytes < pool[best].bytes) best = (int)i;
+    }
+    if (best >= 0) {
+      pool[best].used = true;
+      *out = pool[best].p;
+      return hipSuccess;
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      pool_trim();
+      e = hipMalloc(out, bytes);
+    }
+    if (e == hipSuccess) pool.push_back({*out, bytes, true});
+    return e;
+  }
+  void pool_put(void *p) {
+    for (PBlock &b : pool)
+      if (b.p == p) {
+        b.used = false;
+        return;
+      }
+    (void)hipFree(p);  // not a pool block
+  }
+  void pool_trim() {
+    (void)hipStreamSynchronize(stream);
+    std::vector<PBlock> keep;
+    for (PBlock &b : pool) {
+      if (b.used)
+        keep.push_back(b);
+      else
+        (void)hipFree(b.p);
+    }
+    pool.swap(keep);
+  }
+  size_t pool_unused_bytes() const {
+    size_t t = 0;
+    for (const PBlock &b : pool)
+      if (!b.used) t += b.bytes;
+    return t;
   }
   void free_chunks() {
     for (Chunk &c : chunks) {
@@ -267,7 +326,17 @@ struct vb_ctx {
     *p = nullptr;
     if (count == 0) count = 1;
     if (setup_scope && count * sizeof(T) <= kSmall) return arena_alloc((void **)p, count * sizeof(T));
-    hipError_t e = hipMalloc((void **)p, count * sizeof(T));
+    hipError_t e;
+    if (setup_scope || cur_scope == 2) {
+      e = pool_get((void **)p, count * sizeof(T));
+    } else {
+      e = hipMalloc((void **)p, count * sizeof(T));
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        pool_trim();
+        e = hipMalloc((void **)p, count * sizeof(T));
+      }
+    }
     if (e == hipSuccess)
       (setup_scope ? setup_allocs : (cur_scope == 2 ? setup_keep : allocs)).push_back(*p);
     return e;
@@ -277,7 +346,7 @@ struct vb_ctx {
     auto it = std::find(setup_allocs.begin(), setup_allocs.end(), p);
     if (it == setup_allocs.end()) return;  // arena memory: reclaimed with the arena
     (void)hipStreamSynchronize(stream);
-    (void)hipFree(p);
+    pool_put(p);
     setup_allocs.erase(it);
   }
   template <class T>
@@ -386,7 +455,9 @@ void vb_destroy(vb_ctx *ctx) {
   if (ctx->it_graph) (void)hipGraphDestroy(ctx->it_graph);
   (void)ctx->release_setup_scratch();
   ctx->free_chunks();
-  free_list(ctx->setup_keep);
+  for (void *q : ctx->setup_keep) ctx->pool_put(q);
+  ctx->setup_keep.clear();
+  ctx->pool_trim();
   ctx->t_ldl.destroy();
   ctx->t_gemv.destroy();
   free_list(ctx->allocs);
@@ -1109,6 +1180,7 @@ static int adaptive_stage(vb_ctx *ctx) {
   {
     size_t fr = 0, totm = 0;
     CHK(hipMemGetInfo(&fr, &totm));
+    fr += ctx->pool_unused_bytes();
     const double budget = std::min(32.0e9, 0.5 * (double)fr);
     size_t ci = 0;
     int32_t *d_dualidx = nullptr;  // [0, max_nd) shifted per job through the out pointer
@@ -1729,7 +1801,8 @@ int vb_setup(vb_ctx *ctx) {
   }
   if (ctx->state == 2) {  // a new setup replaces the previous one
     CHK(hipStreamSynchronize(ctx->stream));
-    free_list(ctx->setup_keep);
+    for (void *q : ctx->setup_keep) ctx->pool_put(q);
+    ctx->setup_keep.clear();
     for (auto &H : ctx->ents) {
       H.D.clear();
       H.d_dual_gids = nullptr;
@@ -1852,12 +1925,14 @@ static int setup_impl(vb_ctx *ctx) {
       ld[s] = S.xld;
       n[s] = S.ng + 1;
     }
+    int max_en = 1;
+    for (const auto &H : ctx->ents) max_en = std::max(max_en, H.n);
     int rc = run_symm(ctx, m, ld, n, false, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, f32, st));
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
     rc = run_symm(ctx, m, ld, n, true, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, f32, st));
+    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
     CHK(transform_b0(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ent, st));
   }
   // ---- 5. transformed right-hand side g~ (owner sums over the rhs columns)
@@ -1968,6 +2043,7 @@ static int setup_impl(vb_ctx *ctx) {
     }
     size_t fre = 0, tot = 0;
     CHK(hipMemGetInfo(&fre, &tot));
+    fre += ctx->pool_unused_bytes();
     const double lim = ctx->opt.setup_mem_limit > 0.0 ? ctx->opt.setup_mem_limit : 0.6 * (double)fre;
     const int64_t budget = std::max<int64_t>(nmax, (int64_t)(lim / (double)nsz));
     const int64_t wmax = std::min(ntot, budget);

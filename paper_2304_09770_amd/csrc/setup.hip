@@ -2,6 +2,8 @@
 // primal change of basis, block gathers, interior recovery and the
 // refinement steps of the mixed-precision path.  The dense local matrices
 // are stored in T = double (FP64 path) or float (mixed path).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -350,41 +352,78 @@ hipError_t transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns
   return hipGetLastError();
 }
 
-// X <- X T for the bordered interface block X = W[e+1.., e+1..] (size ng+1):
-// for every local entity, apply its reflectors H_0, H_1, ... to the entity's
-// columns.  One thread per row.
-template <typename T>
-__global__ void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
+// X <- X T for the condensed bordered interface block X (size ng+1): for
+// every local entity, apply its reflectors H_0, H_1, ... to the entity's
+// columns.  A workgroup takes R rows of one entity block into LDS, applies
+// all the entity's reflectors there (256/R lanes per row; a lane always owns
+// the same columns, so the rows need no barrier between reflectors: the dot
+// products meet in shuffles), and writes the block back once.
+template <typename T, int R>
+__global__ __launch_bounds__(256) void k_apply_T_cols(const SubDev *subs, const EntDev *ents) {
+  constexpr int L = 256 / R;
   const SubDev S = subs[blockIdx.z];
   if ((int)blockIdx.y >= S.n_ent) return;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int nx = S.ng + 1;
-  if (i >= nx) return;
+  const int i0 = blockIdx.x * R;
+  if (i0 >= nx) return;
   const EntDev E = ents[S.ent[blockIdx.y]];
-  const int o = S.ent_off[blockIdx.y];
-  const int rk = *E.rank;
-  T *row = (T *)S.X + i;
-  const int64_t ld = S.xld;
+  const int rk = *E.rank, n = E.n;
+  if (rk <= 0) return;
+  extern __shared__ __align__(16) unsigned char smem_t[];
+  T *Xs = reinterpret_cast<T *>(smem_t);  // R x n, column-major
+  T *X = (T *)S.X + (int64_t)S.ent_off[blockIdx.y] * S.xld;
+  const int rows = min(R, nx - i0);
+  for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+    const int r = idx % R, c = idx / R;
+    Xs[idx] = (r < rows) ? X[(int64_t)(i0 + r) + (int64_t)c * S.xld] : T(0);
+  }
+  __syncthreads();
+  const int r = threadIdx.x / L, l = threadIdx.x % L;
   for (int k = 0; k < rk; ++k) {
-    const double *v = E.V + (int64_t)k * E.n;
-    const double tau = E.tau[k];
+    const double *v = E.V + (int64_t)k * n;
     double t = 0.0;
-    for (int c = k; c < E.n; ++c) t += (double)row[(int64_t)(o + c) * ld] * v[c];
-    t *= tau;
-    for (int c = k; c < E.n; ++c)
-      row[(int64_t)(o + c) * ld] = (T)((double)row[(int64_t)(o + c) * ld] - t * v[c]);
+    for (int c = l; c < n; c += L)
+      if (c >= k) t += (double)Xs[c * R + r] * v[c];
+    for (int m = L / 2; m > 0; m >>= 1) t += __shfl_xor(t, m, L);
+    t *= E.tau[k];
+    for (int c = l; c < n; c += L)
+      if (c >= k) Xs[c * R + r] = (T)((double)Xs[c * R + r] - t * v[c]);
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < R * n; idx += blockDim.x) {
+    const int rr = idx % R, c = idx / R;
+    if (rr < rows) X[(int64_t)(i0 + rr) + (int64_t)c * S.xld] = Xs[idx];
   }
 }
 
-hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
-                        int max_ent, bool fp32, hipStream_t s) {
-  if (!nsub || !max_ent) return hipSuccess;
-  dim3 g((max_ng + 1 + 127) / 128, max_ent, nsub);
-  if (fp32)
-    hipLaunchKernelGGL(k_apply_T_cols<float>, g, dim3(128), 0, s, d_subs, d_ents);
-  else
-    hipLaunchKernelGGL(k_apply_T_cols<double>, g, dim3(128), 0, s, d_subs, d_ents);
+template <typename T, int R>
+static hipError_t launch_apply_T(const SubDev *d_subs, const EntDev *d_ents, int nsub, int nx,
+                                 int max_ent, size_t lds, hipStream_t s) {
+  if (lds > 64 * 1024) {
+    hipError_t e = hipFuncSetAttribute((const void *)k_apply_T_cols<T, R>,
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL((k_apply_T_cols<T, R>), dim3((nx + R - 1) / R, max_ent, nsub), dim3(256), lds,
+                     s, d_subs, d_ents);
   return hipGetLastError();
+}
+
+template <typename T>
+static hipError_t apply_T_typed(const SubDev *d_subs, const EntDev *d_ents, int nsub, int nx,
+                                int max_ent, int max_en, hipStream_t s) {
+  const size_t row = (size_t)std::max(max_en, 1) * sizeof(T);
+  if (16 * row <= 48 * 1024) return launch_apply_T<T, 16>(d_subs, d_ents, nsub, nx, max_ent, 16 * row, s);
+  if (8 * row <= 48 * 1024) return launch_apply_T<T, 8>(d_subs, d_ents, nsub, nx, max_ent, 8 * row, s);
+  if (4 * row <= 150 * 1024) return launch_apply_T<T, 4>(d_subs, d_ents, nsub, nx, max_ent, 4 * row, s);
+  return hipErrorInvalidValue;  // an entity larger than 4 rows of LDS can hold
+}
+
+hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
+                        int max_ent, int max_en, bool fp32, hipStream_t s) {
+  if (!nsub || !max_ent) return hipSuccess;
+  return fp32 ? apply_T_typed<float>(d_subs, d_ents, nsub, max_ng + 1, max_ent, max_en, s)
+              : apply_T_typed<double>(d_subs, d_ents, nsub, max_ng + 1, max_ent, max_en, s);
 }
 
 // b0~ = T^T b0 (per local entity, reflectors in order H_0, H_1, ...).
