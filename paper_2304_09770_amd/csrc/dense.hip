@@ -125,6 +125,59 @@ __global__ __launch_bounds__(256) void k_ldl_panel(const LdlJob<T> *jobs, int j0
   }
 }
 
+// The same panel on the matrix cores (NB = 64): a workgroup takes 64 rows,
+// C[c][r] = sum_t inv(L_jj)[c][t] A[r][t] (t <= c; the inverse block is
+// lower triangular, zero above), then L[r][c] = d_c C[c][r].  Both operands
+// are staged in LDS; each wave computes a 32 x 32 block.
+template <typename T>
+__global__ __launch_bounds__(256) void k_ldl_panel_mfma(const LdlJob<T> *jobs, int j0) {
+  typedef Mfma<T> M;
+  constexpr int NB = 64, PR = 64;
+  const LdlJob<T> J = jobs[blockIdx.y];
+  if (j0 >= J.e) return;
+  const int b = min(NB, J.e - j0);
+  const int r0 = j0 + b + blockIdx.x * PR;
+  if (r0 >= J.n) return;
+  __shared__ T Pc[NB][NB + 1];  // Pc[t][c] = inv(L_jj)[c][t]
+  __shared__ T Pr[NB][PR + 1];  // Pr[t][r] = A[r0 + r][j0 + t]
+  const int tid = threadIdx.x;
+  const T *inv = J.invL + (int64_t)(j0 / NB) * NB * NB;
+  for (int idx = tid; idx < NB * NB; idx += blockDim.x) Pc[idx / NB][idx % NB] = inv[idx];
+  for (int idx = tid; idx < PR * NB; idx += blockDim.x) {
+    const int r = idx % PR, t = idx / PR;
+    T v = 0;
+    if (r0 + r < J.n && t < b) v = J.A[(int64_t)(r0 + r) + (int64_t)(j0 + t) * J.ld];
+    Pr[t][r] = v;
+  }
+  __syncthreads();
+  const int w = tid >> 6, l = tid & 63;
+  const int wr = w >> 1, wc = w & 1, lr = l & 15, lk = l >> 4;
+  typename M::acc_t acc[2][2];
+  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < 2; ++c) acc[a][c] = M::zero();
+  for (int t0 = 0; t0 < NB; t0 += 4) {
+    T av[2], bv[2];
+    for (int q = 0; q < 2; ++q) {
+      av[q] = Pc[t0 + lk][32 * wc + 16 * q + lr];
+      bv[q] = Pr[t0 + lk][32 * wr + 16 * q + lr];
+    }
+    for (int br = 0; br < 2; ++br)
+      for (int bc = 0; bc < 2; ++bc) acc[br][bc] = M::mma(av[bc], bv[br], acc[br][bc]);
+  }
+  for (int br = 0; br < 2; ++br)
+    for (int bc = 0; bc < 2; ++bc) {
+      const int row = r0 + 32 * wr + 16 * br + lr;
+      if (row >= J.n) continue;
+      for (int q = 0; q < 4; ++q) {
+        const int c = 32 * wc + 16 * bc + M::row(lk, q);
+        if (c < b) {
+          const T d = (j0 + c < J.p) ? T(1) : T(-1);
+          J.A[(int64_t)row + (int64_t)(j0 + c) * J.ld] = d * acc[br][bc][q];
+        }
+      }
+    }
+}
+
 // A_ik -= L_ij D_j L_kj^T on 64x64 tiles of the trailing matrix, restricted
 // to columns < col_end (the rest of the current super-panel): tile (ti, tk)
 // with ti >= tk from a rectangular grid of nt x ntk tiles.
@@ -420,7 +473,11 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
   const int ntk = (col_end - j0 + TILE - 1) / TILE;
   hipLaunchKernelGGL((k_ldl_diag<T, NB>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
   if (rows > 0) {
-    hipLaunchKernelGGL((k_ldl_panel<T, NB>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
+    if (NB == 64)
+      hipLaunchKernelGGL((k_ldl_panel_mfma<T>), dim3((rows + 63) / 64, batch), dim3(256), 0, s,
+                         d_jobs, j0);
+    else
+      hipLaunchKernelGGL((k_ldl_panel<T, NB>), dim3(pt, batch), dim3(256), 0, s, d_jobs, j0);
     if (ntk > 0)
       hipLaunchKernelGGL((k_ldl_update<T, NB>), dim3(rt * ntk, batch), dim3(256), 0, s, d_jobs,
                          j0, col_end, ntk);
