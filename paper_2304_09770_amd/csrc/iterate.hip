@@ -6,40 +6,60 @@
 namespace vb {
 
 // y_b[j] = alpha * sum_i A_b[i + j*lda] x_b[i] (+ y_b[j] if accumulate), one
-// wave per column, x_b staged in LDS (gathered through xidx if given).
-// Columns are contiguous in HBM: every wave streams one column.
+// wave per column, CPB columns per workgroup.  Columns are contiguous in HBM:
+// every wave streams its columns.  x_b (gathered through xidx if given) is
+// staged through LDS in chunks of GT_CHUNK rows, so a workgroup holds 16 KB
+// of LDS whatever the size of its operator and many workgroups share a CU
+// (the largest operators of an uneven decomposition would otherwise run at
+// two workgroups per CU).
+constexpr int GT_CHUNK = 2048;
 template <int CPB>
 __global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
+  constexpr int NQ = CPB / 4;
   const GemvJob J = jobs[blockIdx.y];
   const int j0 = blockIdx.x * CPB;
   if (j0 >= J.n) return;
-  extern __shared__ double xs[];
-  for (int i = threadIdx.x; i < J.m; i += blockDim.x)
-    xs[i] = J.xidx ? J.x[J.xidx[i]] : J.x[i];
-  __syncthreads();
+  __shared__ double xs[GT_CHUNK];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  for (int jj = w; jj < CPB; jj += 4) {
-    const int j = j0 + jj;
-    if (j >= J.n) break;
-    double s0 = 0.0, s1 = 0.0;
-    if (J.a_f32) {
-      const auto col = gptr((const float *)J.A + (int64_t)j * J.lda);
-      int i = l;
-      for (; i + 64 < J.m; i += 128) {
-        s0 += (double)col[i] * xs[i];
-        s1 += (double)col[i + 64] * xs[i + 64];
+  double acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
+  for (int c0 = 0; c0 < J.m; c0 += GT_CHUNK) {
+    const int cm = min(GT_CHUNK, J.m - c0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cm; i += blockDim.x)
+      xs[i] = J.xidx ? J.x[J.xidx[c0 + i]] : J.x[c0 + i];
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int j = j0 + w + 4 * q;
+      if (j >= J.n) break;
+      double s0 = 0.0, s1 = 0.0;
+      if (J.a_f32) {
+        const auto col = gptr((const float *)J.A + (int64_t)j * J.lda + c0);
+        int i = l;
+        for (; i + 64 < cm; i += 128) {
+          s0 += (double)col[i] * xs[i];
+          s1 += (double)col[i + 64] * xs[i + 64];
+        }
+        if (i < cm) s0 += (double)col[i] * xs[i];
+      } else {
+        const auto col = gptr((const double *)J.A + (int64_t)j * J.lda + c0);
+        int i = l;
+        for (; i + 64 < cm; i += 128) {
+          s0 += col[i] * xs[i];
+          s1 += col[i + 64] * xs[i + 64];
+        }
+        if (i < cm) s0 += col[i] * xs[i];
       }
-      if (i < J.m) s0 += (double)col[i] * xs[i];
-    } else {
-      const auto col = gptr((const double *)J.A + (int64_t)j * J.lda);
-      int i = l;
-      for (; i + 64 < J.m; i += 128) {
-        s0 += col[i] * xs[i];
-        s1 += col[i + 64] * xs[i + 64];
-      }
-      if (i < J.m) s0 += col[i] * xs[i];
+      acc[q] += s0 + s1;
     }
-    double s = warp_sum(s0 + s1);
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int j = j0 + w + 4 * q;
+    if (j >= J.n) break;
+    const double s = warp_sum(acc[q]);
     if (l == 0) {
       double v = J.alpha * s;
       if (J.acc) v += J.y[j];
@@ -74,8 +94,7 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
 static hipError_t allow_big_lds() {
   static int done = 0;
   if (done) return hipSuccess;
-  const void *fs[] = {(const void *)k_gemv_t<8>, (const void *)k_gemv_t<16>,
-                      (const void *)k_gemv_t<32>, (const void *)k_gemv_t<64>, (const void *)k_gemv_n};
+  const void *fs[] = {(const void *)k_gemv_n};
   for (const void *f : fs) {
     hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
@@ -88,12 +107,8 @@ static hipError_t allow_big_lds() {
 hipError_t gemv_t_cpb(const GemvJob *d_jobs, int batch, int max_m, int max_n, int cpb,
                       hipStream_t s) {
   if (!batch || !max_n) return hipSuccess;
-  size_t lds = (size_t)max_m * sizeof(double);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
-    hipError_t e = allow_big_lds();
-    if (e != hipSuccess) return e;
-  }
+  (void)max_m;
+  const size_t lds = 0;
   switch (cpb) {
     case 8:
       hipLaunchKernelGGL((k_gemv_t<8>), dim3((max_n + 7) / 8, batch), dim3(256), lds, s, d_jobs);

@@ -2354,8 +2354,8 @@ static int setup_impl(vb_ctx *ctx) {
     }
     ctx->n_yloc = yoff;
     ctx->schur_bytes = 0.0;
-    for (auto &S : ctx->subs)  // the bordered matrix once + x gather + y write
-      ctx->schur_bytes += 8.0 * ((double)(S.ng + 1) * (S.ng + 1) + 2.0 * (S.ng + 1));
+    for (auto &S : ctx->subs)  // the bordered matrix once (its storage type) + x gather + y write
+      ctx->schur_bytes += (double)ctx->wsz * (double)(S.ng + 1) * (S.ng + 1) + 16.0 * (S.ng + 1);
     UCHK(ctx->dalloc(&ctx->yloc, yoff));
     for (int s = 0; s < nS; ++s) js[s].y = ctx->yloc + ctx->subs[s].y_off;
     std::vector<int64_t> ptr(nTot + 1, 0), idx;
@@ -2758,7 +2758,7 @@ static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, const std::vector
   // the per-problem flags every `every` iterations (the flags freeze
   // converged problems in between)
   const bool graph_ok = ctx->stream != nullptr && !ctx->opt.profile;
-  const int every = (ctx->schur_bytes > 4e8) ? 1 : 4;
+  const int every = (ctx->schur_bytes * (8.0 / ctx->wsz) > 4e8) ? 1 : 4;
   std::vector<double> hs((size_t)P * SC_STRIDE);
   CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
