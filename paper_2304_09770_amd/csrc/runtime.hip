@@ -109,6 +109,7 @@ struct vb_ctx {
   // condensed blocks copied to Xc and the factors recomputed for recovery
   bool stream_w = false;
   std::vector<std::pair<int, int>> waves;
+  int w_wave = -1;  // the wave whose factors W holds (several waves), or -1
   void *Xc = nullptr;
   double *b0 = nullptr, *hv = nullptr;
   int *info = nullptr;
@@ -1849,10 +1850,12 @@ static int setup_impl(vb_ctx *ctx) {
   auto Xptr = [&](const SubH &S) -> void * { return S.X; };
   CHK(hipMemsetAsync(ctx->info, 0, (4 * (size_t)nS + 64 + 4 * ctx->ents.size()) * sizeof(int), st));
   CHK(flux_rows(ctx->d_subdev, nS, ctx->max_n_csr, st));
+  ctx->w_wave = -1;
   for (const auto &wv : ctx->waves) {
     int rc = factor_wave(ctx, wv.first, wv.second, true);
     if (rc) return rc;
     if (!ctx->stream_w) continue;
+    ctx->w_wave = (int)(&wv - ctx->waves.data());
     for (int s = wv.first; s < wv.second; ++s) {
       const SubH &S = ctx->subs[s];
       const char *src = (const char *)ctx->W + (S.W_off + (S.e + 1) + (int64_t)(S.e + 1) * S.ld) * ctx->wsz;
@@ -3069,11 +3072,18 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
     return VB_OK;
   }
   const int nb = ctx->opt.panel;  // the panel width the factorisation used
-  for (const auto &wv : ctx->waves) {
+  // with several waves: first the wave whose factors W still holds, then the
+  // others, each factored again
+  const int nw = (int)ctx->waves.size(), first = std::max(ctx->w_wave, 0);
+  for (int k = 0; k < nw; ++k) {
+    const int wi = (first + k) % nw;
+    const auto &wv = ctx->waves[wi];
     const int s0 = wv.first, n = wv.second - wv.first;
-    if (ctx->stream_w) {  // the factors of this wave again (W holds the last wave's)
+    if (ctx->stream_w && wi != ctx->w_wave) {
+      ctx->w_wave = -1;
       int rc = factor_wave(ctx, s0, wv.second, false);
       if (rc) return rc;
+      ctx->w_wave = wi;
     }
     int mxe = 0;
     for (int s = s0; s < wv.second; ++s) mxe = std::max(mxe, ctx->subs[s].e);

@@ -1,0 +1,139 @@
+"""The entry points' contract on the GPU, through the C-ABI.
+
+* call order: vb_setup before vb_assemble, and vb_pcg_solve / vb_apply
+  before vb_setup, return VB_ERR_STATE;
+* option checks: an unsupported panel width, precision or a negative memory
+  limit make vb_create return VB_ERR_ARG;
+* the iteration cap: with maxit = 3 vb_pcg_solve returns
+  VB_ERR_NOT_CONVERGED and still writes its iterate, which is the third PCG
+  iterate of the oracle (same recurrences, Sec. 7);
+* repeated setups of one context give the same solution bit for bit (the
+  setup reuses its device buffers from one setup to the next, so nothing of
+  the previous setup may leak into the next);
+* counting scaling (the pseudo-inverse weights of the paper's
+  multiplicity-based averaging) against the oracle with the same scaling.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from inputs.workloads import make_workload
+from oracle.bddc import OracleBDDC
+from oracle.pcg import pcg
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+VB_ERR_ARG, VB_ERR_STATE, VB_ERR_NOT_CONVERGED = -1, -2, -8
+
+
+@pytest.fixture(scope="module")
+def vb():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2304_09770_amd import binding
+    binding.load()
+    return binding
+
+
+@pytest.fixture(scope="module")
+def c1():
+    wl, _ = make_workload("c1", workers=1)
+    return wl
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+def test_call_order(vb, c1):
+    ctx = vb.vb_create()
+    try:
+        with pytest.raises(vb.VBError) as e:
+            vb.vb_setup(ctx)
+        assert e.value.code == VB_ERR_STATE
+        vb.vb_assemble(ctx, c1)
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        with pytest.raises(vb.VBError) as e:
+            vb.vb_pcg_solve(ctx, x)
+        assert e.value.code == VB_ERR_STATE
+        with pytest.raises(vb.VBError) as e:
+            vb.vb_apply(ctx, x, torch.zeros_like(x))
+        assert e.value.code == VB_ERR_STATE
+        vb.vb_setup(ctx)  # the right order still works afterwards
+        info = vb.vb_pcg_solve(ctx, x)
+        assert info["true_rel_residual"] <= 1e-8 * 1.01
+    finally:
+        vb.vb_destroy(ctx)
+
+
+@pytest.mark.parametrize("kw", [dict(panel=48), dict(precision=7), dict(setup_mem_limit=-1.0),
+                                dict(local_mem_limit=-1.0)])
+def test_bad_options(vb, kw):
+    with pytest.raises(vb.VBError) as e:
+        vb.vb_create(**kw)
+    assert e.value.code == VB_ERR_ARG
+
+
+def test_iteration_cap_writes_the_iterate(vb, c1):
+    o = OracleBDDC(c1)
+    ctx = vb.vb_create(maxit=3)
+    try:
+        vb.vb_assemble(ctx, c1)
+        vb.vb_setup(ctx)
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x, raise_on_error=False)
+        torch.cuda.synchronize()
+    finally:
+        vb.vb_destroy(ctx)
+    assert info["status"] == VB_ERR_NOT_CONVERGED
+    assert info["iterations"] == 3
+    assert 1e-8 < info["true_rel_residual"] < 1.0
+    xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=3)
+    assert _rel(x.cpu().numpy(), xo) < 1e-10
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_repeated_setup_is_reproducible(vb, c1, precision):
+    ctx = vb.vb_create(precision=precision)
+    try:
+        vb.vb_assemble(ctx, c1)
+        n = vb.vb_interface_size(ctx)
+        out = []
+        for _ in range(3):
+            vb.vb_setup(ctx)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            info = vb.vb_pcg_solve(ctx, x)
+            torch.cuda.synchronize()
+            out.append((info["iterations"], x.cpu().numpy()))
+    finally:
+        vb.vb_destroy(ctx)
+    for it, x in out[1:]:
+        assert it == out[0][0]
+        assert np.array_equal(x, out[0][1])
+
+
+def test_counting_scaling_parity(vb, c1):
+    o = OracleBDDC(c1, scaling="counting")
+    ctx = vb.vb_create(scaling=vb.VB_SCALING_COUNTING, tol=1e-12)
+    try:
+        vb.vb_assemble(ctx, c1)
+        vb.vb_setup(ctx)
+        n = vb.vb_interface_size(ctx)
+        r = o.apply_S(np.random.default_rng(5).standard_normal(n))
+        z = torch.zeros(n, dtype=torch.float64, device=DEV)
+        vb.vb_apply(ctx, torch.tensor(r, device=DEV), z)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x)
+        torch.cuda.synchronize()
+    finally:
+        vb.vb_destroy(ctx)
+    zg, zo, nG = z.cpu().numpy(), o.apply_M(r), o.nG
+    assert _rel(zg[:nG], zo[:nG]) < 1e-10
+    dp = (zg[nG:] - zg[nG:].mean()) - (zo[nG:] - zo[nG:].mean())
+    assert np.linalg.norm(dp) < 1e-10 * np.linalg.norm(zo)
+    xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
+    assert _rel(x.cpu().numpy(), xo) < 1e-10
+    assert info["lambda_min"] > 1 - 1e-6
