@@ -182,6 +182,10 @@ struct vb_ctx {
   std::vector<int64_t> uoff;
   int last_outer = 0, last_inner = 0;
   int recover_steps = 4;  // interior refinement passes of vb_recover_all (mixed)
+  // the interface solution of the last mixed solve, whose interior state zst
+  // was refined with it: recovery at that x starts from zst
+  double *x_last = nullptr;
+  bool zst_valid = false;
 
   double setup_ms = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -1810,6 +1814,7 @@ int vb_setup(vb_ctx *ctx) {
     }
     ctx->state = 1;
   }
+  ctx->zst_valid = false;
   ctx->n_restrict = ctx->n_ext = 0;
   ctx->max_rm = ctx->max_ext_m = ctx->max_gt_m = ctx->max_gt_n = 0;
   ctx->max_ndl = ctx->max_npi = ctx->max_nt = 0;
@@ -2501,6 +2506,7 @@ static int setup_impl(vb_ctx *ctx) {
       UCHK(ctx->dalloc(&ctx->y_ir, t2));
       UCHK(ctx->dalloc(&ctx->z_ir, t2));
       UCHK(ctx->dalloc(&ctx->zst, t2));
+      UCHK(ctx->dalloc(&ctx->x_last, nG + nS));
       CHK(hipMemsetAsync(ctx->y_ir, 0, t2 * sizeof(double), st));
       CHK(hipMemsetAsync(ctx->z_ir, 0, t2 * sizeof(double), st));
       UCHK(ctx->dalloc(&ctx->u_loc, otot));
@@ -2977,6 +2983,10 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
     q.latency_ms = (ctx->clock_khz > 0 && tdone[pp] > t0[pp]) ? (tdone[pp] - t0[pp]) / ctx->clock_khz : 0.0;
   }
   ctx->pinfo = pi;
+  if (status != VB_ERR_BREAKDOWN) {  // (x, zst) is a consistent iterate
+    CHK(hipMemcpyAsync(ctx->x_last, x_dev, n * sizeof(double), hipMemcpyDeviceToDevice, st));
+    ctx->zst_valid = true;
+  }
   if (info) {
     combine_info(pi, info);
     info->n_coarse = ctx->nCS;
@@ -3054,10 +3064,30 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
   if (ctx->state != 2) return ctx->fail(VB_ERR_STATE, "vb_recover_all: call vb_setup first");
   hipStream_t st = ctx->stream;
   if (ctx->fp32) {
-    // FP32 factor: start from zero interior state and refine the interior
-    // equations in FP64 with the interface data fixed at x
-    CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
-    for (int k = 0; k < ctx->recover_steps; ++k) {
+    // FP32 factor: refine the interior equations in FP64 with the interface
+    // data fixed at x, from the interior state of the last solve when x is
+    // that solve's result (two passes), else from zero (recover_steps passes)
+    int passes = ctx->recover_steps;
+    bool from_solve = false;
+    if (ctx->zst_valid) {
+      const int64_t n = ctx->nG + ctx->nS;
+      const int P = (int)ctx->probs.size();
+      CHK(vsub(n, x_dev, ctx->x_last, ctx->tmp, st));
+      CHK(sdot(ctx->d_segs, P, ctx->seg_G, ctx->tmp, ctx->tmp, ctx->part, ctx->sc, 5, nullptr,
+               nullptr, 0, st));
+      std::vector<double> hs((size_t)P * SC_STRIDE);
+      CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+      CHK(hipStreamSynchronize(st));
+      from_solve = true;
+      for (int pp = 0; pp < P; ++pp) from_solve = from_solve && hs[(size_t)pp * SC_STRIDE + SC_TMP] == 0.0;
+    }
+    if (from_solve) {
+      passes = std::min(passes, 2);
+    } else {
+      CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
+      ctx->zst_valid = false;
+    }
+    for (int k = 0; k < passes; ++k) {
       int rc = condense_residual(ctx, x_dev);
       if (rc) return rc;
       rc = interior_correction(ctx, nullptr);

@@ -243,6 +243,30 @@ def test_mixed_interior_recovery_parity(vb, mixed_case):
         assert _rel(u[kind == 1], xo[sd["gid"][kind == 1]]) < 1e-15
 
 
+def test_mixed_recovery_from_the_solve_state(vb, mixed_case):
+    """Recovery at the interface solution of the last mixed solve starts from
+    the interior state refined with it (fewer passes); it must give the
+    oracle's recovery from that same interface solution."""
+    name, wl, meta, o, ctx = mixed_case
+    n = vb.vb_interface_size(ctx)
+    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+    vb.vb_pcg_solve(ctx, x)
+    nloc = sum(len(sd["kind"]) for sd in wl["subs"])
+    u = torch.zeros(nloc, dtype=torch.float64, device=DEV)
+    vb.vb_recover_all(ctx, x, u)
+    torch.cuda.synchronize()
+    xg, ug = x.cpu().numpy(), u.cpu().numpy()
+    rec = o.recover(xg)
+    off = 0
+    for s, sd in enumerate(wl["subs"]):
+        kind = sd["kind"]
+        us = ug[off: off + len(kind)]
+        off += len(kind)
+        uI, c = rec[s]
+        assert _rel(np.concatenate([us[kind == 0], us[kind == 2]]), np.concatenate([uI, c])) < 1e-10
+        assert _rel(us[kind == 1], xg[sd["gid"][kind == 1]]) < 1e-15
+
+
 def test_mixed_operators_are_fp32_roundings(vb, mixed_case):
     """S_hat and M^-1 from the FP32 factorisations differ from the FP64 ones
     by FP32 rounding amplified by the local conditioning, and are not
