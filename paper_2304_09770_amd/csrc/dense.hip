@@ -372,16 +372,110 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 
 // FP64: 206 VGPRs, two waves per SIMD.  FP32: 124 VGPRs and half the LDS
 // bytes per stage, four waves per SIMD.
-// The local Dirichlet factorisations (the dominant work, timed per launch)
-// and the other factorisations (Neumann, deluxe, coarse, face problems) run
-// the same code under two kernel names, so that profiles separate them.
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
-  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
+// FP32 variant of the triangular update for matrices whose leading dimension
+// is a multiple of 4 and whose columns start on 16-byte boundaries: the panel
+// strips go from HBM straight into LDS (global_load_lds_dwordx4, no
+// registers, no LDS stores), double-buffered in chunks of 16 columns, so
+// each chunk costs one barrier and the next chunk's loads overlap the
+// current chunk's matrix-core work.  Every load is 16-byte aligned: the tile
+// grid starts at ke rounded down to a multiple of 4, rows below ke (panel
+// rows) and beyond n enter the products but are never written; columns at
+// or beyond ke are loaded as (finite) copies of column ke-1 and weighted 0.
+constexpr int DKW = 16;
+__device__ __forceinline__ void dma16(const float *g, float *lds_wave_base) {
+  __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
+                                   (void __attribute__((address_space(3))) *)lds_wave_base, 16, 0, 0);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
-  ldl_update_wide_body<float, false>(jobs, J0, SB, 0, 0);
+  typedef Mfma<float> M;
+  const LdlJob<float> J = jobs[blockIdx.y];
+  const int kb = J0, ke = min(J0 + SB, J.e);
+  if (kb >= ke) return;
+  const int m0 = ke;
+  if (m0 >= J.n) return;
+  const int m0a = m0 & ~3;
+  const int nt = (J.n - m0a + WT - 1) / WT;
+  const int t = blockIdx.x;
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tk = t - ti * (ti + 1) / 2;
+  if (ti >= nt) return;
+  const int i0 = m0a + ti * WT, k0 = m0a + tk * WT;
+  __shared__ __align__(16) float PiA[DKW * WT], PkA[DKW * WT], PiB[DKW * WT], PkB[DKW * WT];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int wi = w >> 1, wk = w & 1, lr = l & 15, lk = l >> 4;
+  // load map: wave w, pair p = w + 4 j (j = 0, 1) -> columns 2p, 2p + 1 of the
+  // chunk; lane l -> column 2p + (l >> 5), rows 4 (l & 31) .. + 3 of the strip
+  const int nclamp = max((J.n - 4) & ~3, 0);
+  const int ri = min(i0 + 4 * (l & 31), nclamp), rk = min(k0 + 4 * (l & 31), nclamp);
+  auto issue = [&](int cc, float *Pi, float *Pk) {
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int pr = w + 4 * j;
+      const int cl = min(cc + 2 * pr + (l >> 5), ke - 1);
+      const float *col = J.A + (int64_t)cl * J.ld;
+      dma16(col + ri, Pi + 2 * pr * WT);
+      dma16(col + rk, Pk + 2 * pr * WT);
+    }
+  };
+  typename M::acc_t acc[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) acc[a][c] = M::zero();
+  auto compute = [&](int cc, const float *Pi, const float *Pk) {
+#pragma unroll
+    for (int s0 = 0; s0 < DKW; s0 += 4) {
+      const int c = cc + s0 + lk;
+      const float d = (c < ke) ? ((c < J.p) ? 1.f : -1.f) : 0.f;
+      float av[4], bv[4];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        av[q] = Pk[(s0 + lk) * WT + 64 * wk + 16 * q + lr] * d;
+        bv[q] = Pi[(s0 + lk) * WT + 64 * wi + 16 * q + lr];
+      }
+#pragma unroll
+      for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+        for (int bk = 0; bk < 4; ++bk) acc[bi][bk] = M::mma(av[bk], bv[bi], acc[bi][bk]);
+    }
+  };
+  issue(kb, PiA, PkA);
+  for (int cc = kb; cc < ke; cc += 2 * DKW) {
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's loads of chunk cc
+    __syncthreads();
+    if (cc + DKW < ke) issue(cc + DKW, PiB, PkB);
+    compute(cc, PiA, PkA);
+    if (cc + DKW >= ke) break;
+    __builtin_amdgcn_s_waitcnt(0x0F70);
+    __syncthreads();
+    if (cc + 2 * DKW < ke) issue(cc + 2 * DKW, PiA, PkA);
+    compute(cc + DKW, PiB, PkB);
+  }
+#pragma unroll
+  for (int bi = 0; bi < 4; ++bi)
+#pragma unroll
+    for (int bk = 0; bk < 4; ++bk) {
+      const int row = i0 + 64 * wi + 16 * bi + lr;
+      if (row < m0 || row >= J.n) continue;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int col = k0 + 64 * wk + 16 * bk + M::row(lk, q);
+        if (col >= m0 && col < J.n) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
+      }
+    }
+}
+
+// The local Dirichlet factorisations (the dominant work, timed per launch)
+// and the other factorisations (Neumann, deluxe, coarse, face problems) run
+// under two kernel names, so that profiles separate them: FP64 the same code,
+// FP32 the direct-to-LDS kernel above for the Dirichlet factorisations (the
+// staged kernel for the others and for unaligned matrices).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void k_ldl_update_wide_aux_f64(const LdlJob<double> *jobs, int J0, int SB) {
@@ -407,7 +501,7 @@ template <> struct WideKernel<double> {
   static constexpr auto rect = k_ldl_update_rect_f64;
 };
 template <> struct WideKernel<float> {
-  static constexpr auto fn = k_ldl_update_wide_f32;
+  static constexpr auto fn = k_ldl_update_wide_aux_f32;  // unaligned Dirichlet matrices
   static constexpr auto aux = k_ldl_update_wide_aux_f32;
   static constexpr auto rect = k_ldl_update_rect_f32;
 };
@@ -488,16 +582,13 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer, const std::vector<int> *hn,
-                       const std::vector<int> *he, bool dirichlet) {
+                       const std::vector<int> *he, bool dirichlet, bool aligned16) {
   if (batch == 0 || max_e == 0) return hipSuccess;
   static bool attr = false;
   const size_t lds = 2 * (size_t)WideKW<T>::value * WT * sizeof(T);
   if (!attr) {
     hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f64,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (r == hipSuccess)
-      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f32,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void *)k_ldl_update_wide_aux_f64,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
@@ -552,10 +643,14 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     // trailing rows: size the grid by the upper bound max_n - J0
     const int rows = max_n - J0;
     if (rows > 0) {
-      const int wt = (rows + WT - 1) / WT;
+      const bool dma = dirichlet && aligned16 && sizeof(T) == sizeof(float);
+      const int wt = (rows + (dma ? 4 : 0) + WT - 1) / WT;  // the DMA grid starts up to 3 rows lower
       const int ntiles = wt * (wt + 1) / 2;
       if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
-      if (dirichlet)
+      if (dma)
+        hipLaunchKernelGGL(k_ldl_update_wide_f32, dim3(ntiles, batch), dim3(256), 0, s,
+                           (const LdlJob<float> *)d_jobs, J0, SB1);
+      else if (dirichlet)
         hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
                            SB1);
       else
@@ -580,10 +675,10 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 
 template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t,
                                         KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                        bool);
+                                        bool, bool);
 template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t,
                                        KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                       bool);
+                                       bool, bool);
 template hipError_t gemm_nt_batched<double>(const GemmJob<double> *, int, int, int, hipStream_t);
 template hipError_t gemm_nt_batched<float>(const GemmJob<float> *, int, int, int, hipStream_t);
 

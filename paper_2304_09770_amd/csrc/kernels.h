@@ -53,7 +53,7 @@ template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer = nullptr,
                        const std::vector<int> *hn = nullptr, const std::vector<int> *he = nullptr,
-                       bool dirichlet = false);
+                       bool dirichlet = false, bool aligned16 = false);
 template <typename T>
 hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int max_n,
                            hipStream_t s);

@@ -765,12 +765,16 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
   LdlJob<T> *dj = nullptr;
   UCHK(ctx->upload(&dj, jobs, true));
   std::vector<int> hn(jobs.size()), he(jobs.size());
+  bool aligned16 = true;  // 16-byte aligned columns (leading dimension a multiple of 16 bytes)
   for (size_t b = 0; b < jobs.size(); ++b) {
     hn[b] = jobs[b].n;
     he[b] = jobs[b].e;
+    aligned16 = aligned16 && (jobs[b].ld * sizeof(T)) % 16 == 0 &&
+                reinterpret_cast<uintptr_t>(jobs[b].A) % 16 == 0;
   }
   CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
-                     (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he, timed));
+                     (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he, timed,
+                     aligned16));
   return VB_OK;
 }
 
