@@ -372,29 +372,40 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 
 // FP64: 206 VGPRs, two waves per SIMD.  FP32: 124 VGPRs and half the LDS
 // bytes per stage, four waves per SIMD.
-// FP32 variant of the triangular update for matrices whose leading dimension
-// is a multiple of 4 and whose columns start on 16-byte boundaries: the panel
-// strips go from HBM straight into LDS (global_load_lds_dwordx4, no
-// registers, no LDS stores), double-buffered in chunks of 16 columns, so
+// The triangular update for matrices whose columns start on 16-byte
+// boundaries (leading dimension a multiple of 16 bytes): the panel strips go
+// from HBM straight into LDS (global_load_lds_dwordx4, no registers, no LDS
+// stores), double-buffered in chunks of 16 (FP32) or 8 (FP64) columns, so
 // each chunk costs one barrier and the next chunk's loads overlap the
 // current chunk's matrix-core work.  Every load is 16-byte aligned: the tile
-// grid starts at ke rounded down to a multiple of 4, rows below ke (panel
-// rows) and beyond n enter the products but are never written; columns at
-// or beyond ke are loaded as (finite) copies of column ke-1 and weighted 0.
-constexpr int DKW = 16;
-__device__ __forceinline__ void dma16(const float *g, float *lds_wave_base) {
+// grid starts at ke rounded down to a multiple of VW = 16 / sizeof(T) rows;
+// a group of VW rows that starts below ld is read as it is (ld is a multiple
+// of VW, so it ends inside the column), a group starting at or beyond ld is
+// read from the column's last VW rows instead; rows below ke (panel rows)
+// and at or beyond n enter the products only for outputs that are never
+// written; columns at or beyond ke are loaded as (finite) copies of column
+// ke-1 and weighted 0.
+template <typename T> struct Dma {
+  static constexpr int VW = 16 / sizeof(T);   // entries per 16-byte load
+  static constexpr int KW = 64 / sizeof(T);   // columns per chunk (16 KB per buffer pair)
+  static constexpr int CPI = 64 * VW / WT;    // strip columns per wave-wide load
+};
+template <typename T>
+__device__ __forceinline__ void dma16(const T *g, T *lds_wave_base) {
   __builtin_amdgcn_global_load_lds((const void __attribute__((address_space(1))) *)g,
                                    (void __attribute__((address_space(3))) *)lds_wave_base, 16, 0, 0);
 }
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
-void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
-  typedef Mfma<float> M;
-  const LdlJob<float> J = jobs[blockIdx.y];
+template <typename T>
+__device__ __forceinline__ void ldl_update_dma_body(const LdlJob<T> *jobs, int J0, int SB) {
+  typedef Mfma<T> M;
+  constexpr int VW = Dma<T>::VW, DKW = Dma<T>::KW, CPI = Dma<T>::CPI;
+  constexpr int NI = DKW / CPI / 4;  // wave-wide loads per strip, wave and chunk
+  const LdlJob<T> J = jobs[blockIdx.y];
   const int kb = J0, ke = min(J0 + SB, J.e);
   if (kb >= ke) return;
   const int m0 = ke;
   if (m0 >= J.n) return;
-  const int m0a = m0 & ~3;
+  const int m0a = m0 & ~(VW - 1);
   const int nt = (J.n - m0a + WT - 1) / WT;
   const int t = blockIdx.x;
   int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -403,21 +414,22 @@ void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
   const int tk = t - ti * (ti + 1) / 2;
   if (ti >= nt) return;
   const int i0 = m0a + ti * WT, k0 = m0a + tk * WT;
-  __shared__ __align__(16) float PiA[DKW * WT], PkA[DKW * WT], PiB[DKW * WT], PkB[DKW * WT];
+  __shared__ __align__(16) T PiA[DKW * WT], PkA[DKW * WT], PiB[DKW * WT], PkB[DKW * WT];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int wi = w >> 1, wk = w & 1, lr = l & 15, lk = l >> 4;
-  // load map: wave w, pair p = w + 4 j (j = 0, 1) -> columns 2p, 2p + 1 of the
-  // chunk; lane l -> column 2p + (l >> 5), rows 4 (l & 31) .. + 3 of the strip
-  const int nclamp = max((J.n - 4) & ~3, 0);
-  const int ri = min(i0 + 4 * (l & 31), nclamp), rk = min(k0 + 4 * (l & 31), nclamp);
-  auto issue = [&](int cc, float *Pi, float *Pk) {
+  // load map: wave w, load j -> strip columns CPI (w + 4 j) .. + CPI - 1;
+  // lane l -> column + l / (WT / VW), rows VW (l % (WT / VW)) .. + VW - 1
+  const int lc = l / (WT / VW), lrow = VW * (l % (WT / VW));
+  const int64_t last = J.ld - VW;  // the last group of a column
+  const int64_t ri = min((int64_t)(i0 + lrow), last), rk = min((int64_t)(k0 + lrow), last);
+  auto issue = [&](int cc, T *Pi, T *Pk) {
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      const int pr = w + 4 * j;
-      const int cl = min(cc + 2 * pr + (l >> 5), ke - 1);
-      const float *col = J.A + (int64_t)cl * J.ld;
-      dma16(col + ri, Pi + 2 * pr * WT);
-      dma16(col + rk, Pk + 2 * pr * WT);
+    for (int j = 0; j < NI; ++j) {
+      const int c0 = CPI * (w + 4 * j);
+      const int cl = min(cc + c0 + lc, ke - 1);
+      const T *col = J.A + (int64_t)cl * J.ld;
+      dma16(col + ri, Pi + c0 * WT);
+      dma16(col + rk, Pk + c0 * WT);
     }
   };
   typename M::acc_t acc[4][4];
@@ -425,12 +437,12 @@ void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
   for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int c = 0; c < 4; ++c) acc[a][c] = M::zero();
-  auto compute = [&](int cc, const float *Pi, const float *Pk) {
+  auto compute = [&](int cc, const T *Pi, const T *Pk) {
 #pragma unroll
     for (int s0 = 0; s0 < DKW; s0 += 4) {
       const int c = cc + s0 + lk;
-      const float d = (c < ke) ? ((c < J.p) ? 1.f : -1.f) : 0.f;
-      float av[4], bv[4];
+      const T d = (c < ke) ? ((c < J.p) ? T(1) : T(-1)) : T(0);
+      T av[4], bv[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         av[q] = Pk[(s0 + lk) * WT + 64 * wk + 16 * q + lr] * d;
@@ -468,21 +480,34 @@ void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
     }
 }
 
-// The local Dirichlet factorisations (the dominant work, timed per launch)
-// and the other factorisations (Neumann, deluxe, coarse, face problems) run
-// under two kernel names, so that profiles separate them: FP64 the same code,
-// FP32 the direct-to-LDS kernel above for the Dirichlet factorisations (the
-// staged kernel for the others and for unaligned matrices).
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
-  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
+// The local Dirichlet factorisations (timed per launch), the other
+// factorisations (Neumann, deluxe, coarse, face problems) and matrices that
+// are not 16-byte aligned (staged kernel) run under separate kernel names so
+// that profiles separate them.
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ldl_update_wide_f32(const LdlJob<float> *jobs, int J0, int SB) {
+  ldl_update_dma_body<float>(jobs, J0, SB);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
-void k_ldl_update_wide_aux_f64(const LdlJob<double> *jobs, int J0, int SB) {
-  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
+void k_ldl_update_wide_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_dma_body<double>(jobs, J0, SB);
 }
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
 void k_ldl_update_wide_aux_f32(const LdlJob<float> *jobs, int J0, int SB) {
+  ldl_update_dma_body<float>(jobs, J0, SB);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide_aux_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_dma_body<double>(jobs, J0, SB);
+}
+
+// the staged kernel for matrices that are not 16-byte aligned
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2)))
+void k_ldl_update_wide_u_f64(const LdlJob<double> *jobs, int J0, int SB) {
+  ldl_update_wide_body<double, false>(jobs, J0, SB, 0, 0);
+}
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4, 4)))
+void k_ldl_update_wide_u_f32(const LdlJob<float> *jobs, int J0, int SB) {
   ldl_update_wide_body<float, false>(jobs, J0, SB, 0, 0);
 }
 // the update inside an enclosing super-panel (columns up to its end)
@@ -496,13 +521,15 @@ void k_ldl_update_rect_f32(const LdlJob<float> *jobs, int J0, int SB, int col_en
 }
 template <typename T> struct WideKernel;
 template <> struct WideKernel<double> {
-  static constexpr auto fn = k_ldl_update_wide_f64;
-  static constexpr auto aux = k_ldl_update_wide_aux_f64;
+  static constexpr auto fn = k_ldl_update_wide_f64;       // 16-byte aligned, Dirichlet
+  static constexpr auto aux = k_ldl_update_wide_aux_f64;  // 16-byte aligned, others
+  static constexpr auto u = k_ldl_update_wide_u_f64;      // not aligned
   static constexpr auto rect = k_ldl_update_rect_f64;
 };
 template <> struct WideKernel<float> {
-  static constexpr auto fn = k_ldl_update_wide_aux_f32;  // unaligned Dirichlet matrices
+  static constexpr auto fn = k_ldl_update_wide_f32;
   static constexpr auto aux = k_ldl_update_wide_aux_f32;
+  static constexpr auto u = k_ldl_update_wide_u_f32;
   static constexpr auto rect = k_ldl_update_rect_f32;
 };
 
@@ -587,13 +614,10 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
   static bool attr = false;
   const size_t lds = 2 * (size_t)WideKW<T>::value * WT * sizeof(T);
   if (!attr) {
-    hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide_f64,
+    hipError_t r = hipFuncSetAttribute((const void *)k_ldl_update_wide_u_f64,
                                        hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
-      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_aux_f64,
-                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-    if (r == hipSuccess)
-      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_aux_f32,
+      r = hipFuncSetAttribute((const void *)k_ldl_update_wide_u_f32,
                               hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (r == hipSuccess)
       r = hipFuncSetAttribute((const void *)k_ldl_update_rect_f64,
@@ -643,18 +667,17 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     // trailing rows: size the grid by the upper bound max_n - J0
     const int rows = max_n - J0;
     if (rows > 0) {
-      const bool dma = dirichlet && aligned16 && sizeof(T) == sizeof(float);
-      const int wt = (rows + (dma ? 4 : 0) + WT - 1) / WT;  // the DMA grid starts up to 3 rows lower
+      // the aligned kernels start their tile grid up to VW - 1 rows lower
+      const int wt = (rows + (aligned16 ? Dma<T>::VW : 0) + WT - 1) / WT;
       const int ntiles = wt * (wt + 1) / 2;
       if (timer) { hipError_t r = timer->begin(s, flops); if (r != hipSuccess) return r; }
-      if (dma)
-        hipLaunchKernelGGL(k_ldl_update_wide_f32, dim3(ntiles, batch), dim3(256), 0, s,
-                           (const LdlJob<float> *)d_jobs, J0, SB1);
-      else if (dirichlet)
-        hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
+      if (!aligned16)
+        hipLaunchKernelGGL(WideKernel<T>::u, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
                            SB1);
+      else if (dirichlet)
+        hipLaunchKernelGGL(WideKernel<T>::fn, dim3(ntiles, batch), dim3(256), 0, s, d_jobs, J0, SB1);
       else
-        hipLaunchKernelGGL(WideKernel<T>::aux, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J0,
+        hipLaunchKernelGGL(WideKernel<T>::aux, dim3(ntiles, batch), dim3(256), 0, s, d_jobs, J0,
                            SB1);
       if (timer) { hipError_t r = timer->end(s); if (r != hipSuccess) return r; }
     }
