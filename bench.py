@@ -50,7 +50,7 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the readings of a 1 GiB device copy: x2.0, x1.0), per
 # workload and path; to be cleared whenever the kernel changes.
-TRAFFIC_BYTES = {}
+TRAFFIC_BYTES = {("c2", "mixed"): 1.0557e11}
 TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
