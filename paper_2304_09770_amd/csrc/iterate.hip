@@ -464,6 +464,12 @@ __global__ void k_sfinal(int P, int G, const double *part, double *sc, int mode,
     case 5: q[SC_TMP] = s0; break;
     default: {
       q[SC_RR] = s0;
+      if (!isfinite(s0) || !isfinite(q[SC_GG])) {  // NaN/Inf data: a breakdown, not convergence
+        q[SC_FLAG] = 1.0;
+        q[SC_DONE] = 1.0;
+        q[SC_TDONE] = (double)wall_clock64();
+        break;
+      }
       if (!(sqrt(s0) > q[SC_TOL] * sqrt(q[SC_GG]))) {
         q[SC_DONE] = 1.0;
         q[SC_TDONE] = (double)wall_clock64();

@@ -2915,10 +2915,11 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
     CHK(sdot(ctx->d_segs, P, G, ctx->dgv, ctx->dgv, ctx->part, ctx->sc, 5, nullptr, nullptr, 0, st));
     CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
-    bool all = true;
+    bool all = true, nonfinite = false;
     std::vector<double> tin(P);
     for (int pp = 0; pp < P; ++pp) {
       const double rn = std::sqrt(hs[(size_t)pp * SC_STRIDE + SC_TMP]);
+      if (!std::isfinite(rn) || (outer == 0 && !std::isfinite(r_first[pp]))) nonfinite = true;
       if (outer == 0) r_first[pp] = rn;
       rel[pp] = r_first[pp] > 0 ? rn / r_first[pp] : 0.0;
       if (!done[pp] && !(rel[pp] > ctx->opt.tol)) {
@@ -2927,6 +2928,11 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
       }
       if (!done[pp]) all = false;
       tin[pp] = done[pp] ? 1e300 : std::max(inner_floor, 0.5 * ctx->opt.tol / std::max(rel[pp], 1e-300));
+    }
+    if (nonfinite) {  // NaN/Inf in the data: a breakdown, not convergence
+      status = VB_ERR_BREAKDOWN;
+      for (int pp = 0; pp < P; ++pp) done[pp] = 0;
+      break;
     }
     if (all) break;
     if (outer >= max_outer || inner_max >= ctx->opt.maxit) {

@@ -11,7 +11,11 @@
   setup reuses its device buffers from one setup to the next, so nothing of
   the previous setup may leak into the next);
 * counting scaling (the pseudo-inverse weights of the paper's
-  multiplicity-based averaging) against the oracle with the same scaling.
+  multiplicity-based averaging) against the oracle with the same scaling;
+* bad input data map to error codes (every kernel still runs to its end):
+  a local velocity block that is not positive definite makes vb_setup return
+  VB_ERR_NOT_SPD naming the subdomain, and a NaN in a right-hand side makes
+  vb_pcg_solve return VB_ERR_BREAKDOWN.
 """
 import numpy as np
 import pytest
@@ -24,7 +28,7 @@ from oracle.pcg import pcg
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-VB_ERR_ARG, VB_ERR_STATE, VB_ERR_NOT_CONVERGED = -1, -2, -8
+VB_ERR_ARG, VB_ERR_STATE, VB_ERR_NOT_SPD, VB_ERR_BREAKDOWN, VB_ERR_NOT_CONVERGED = -1, -2, -5, -7, -8
 
 
 @pytest.fixture(scope="module")
@@ -137,3 +141,41 @@ def test_counting_scaling_parity(vb, c1):
     xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
     assert _rel(x.cpu().numpy(), xo) < 1e-10
     assert info["lambda_min"] > 1 - 1e-6
+
+
+def _copy(wl):
+    return {"n_iface": wl["n_iface"], "ents": wl["ents"],
+            "subs": [{k: np.array(v, copy=True) for k, v in sd.items()} for sd in wl["subs"]]}
+
+
+def test_non_spd_local_block_is_reported(vb, c1):
+    bad = _copy(c1)
+    sd = bad["subs"][3]
+    vel = sd["kind"] != 2  # velocity DoFs (interior and interface)
+    rows = np.repeat(np.arange(len(sd["kind"])), np.diff(sd["indptr"]))
+    vv = vel[rows] & vel[sd["indices"]]
+    sd["data"][vv] *= -1.0  # the velocity block negative definite
+    ctx = vb.vb_create()
+    try:
+        vb.vb_assemble(ctx, bad)
+        with pytest.raises(vb.VBError) as e:
+            vb.vb_setup(ctx)
+        assert e.value.code == VB_ERR_NOT_SPD
+        assert "block 3 " in str(e.value)
+    finally:
+        vb.vb_destroy(ctx)
+
+
+def test_nan_rhs_is_reported(vb, c1):
+    bad = _copy(c1)
+    bad["subs"][0]["rhs"][0] = np.nan
+    ctx = vb.vb_create()
+    try:
+        vb.vb_assemble(ctx, bad)
+        vb.vb_setup(ctx)
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x, raise_on_error=False)
+    finally:
+        vb.vb_destroy(ctx)
+    assert info["status"] == VB_ERR_BREAKDOWN
