@@ -481,6 +481,20 @@ def run_batched(args):
         tiles = [vb.vb_tuned_tile(ctx, k) for k in range(4)]
         vb.vb_destroy(ctx)
         dt_batch = (t1 - t0) / args.steps
+        # the same batch with the exact adaptive eigensolves (no predictor)
+        ex_opts = dict(opts)
+        ex_opts["predictor"] = None
+        ctx = vb.vb_create(**ex_opts)
+        ctx_wls[id(ctx)] = batch
+        for wl in batch:
+            vb.vb_assemble(ctx, wl)
+        run(ctx, args.warmup)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run(ctx, args.steps)
+        dt_exact = (time.perf_counter() - t0) / args.steps
+        vb.vb_destroy(ctx)
+        log("exact adaptive batch: %.3f s per step (learned %.3f s)" % (dt_exact, dt_batch))
         # one context per problem, one after the other
         seq = 0.0
         for k, wl in enumerate([] if args.no_sequential else batch):
@@ -518,6 +532,8 @@ def run_batched(args):
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max())},
         "sequential_solves_per_s": (len(batch) / seq) if seq else None,
+        "exact_adaptive_solves_per_s": len(batch) / dt_exact,
+        "learned_speedup_vs_exact_adaptive": dt_exact / dt_batch,
         "batch_speedup": (seq / dt_batch) if seq else None,
         "inner_iterations": {"min": int(its.min()), "max": int(its.max())},
         "refinement_steps_max": max(p["refinement_steps"] for p in per),
