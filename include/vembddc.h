@@ -181,7 +181,14 @@ const char *vb_last_error(const vb_ctx *ctx);
  * setup and iteration launch covers the subdomains of all problems; PCG keeps
  * separate scalars and convergence per problem).  Problem p's interface ids
  * are offset by the interface sizes of the problems before it, its
- * subdomains by their subdomain counts (see vb_problem_layout). */
+ * subdomains by their subdomain counts (see vb_problem_layout).  The host
+ * arrays are copied.  Returns VB_ERR_ARG (reason in vb_last_error) for
+ * inconsistent data: sizes, a CSR whose row pointers do not rise from 0 to
+ * nnz or whose column indices leave 0..n-1, unknown DoF kinds, interface ids
+ * outside 0..n_iface-1 or not covered by exactly one entity, a subdomain
+ * holding part of an entity, fewer than two pressures, or a pressure weight
+ * (element volume) that is not positive; a failed call leaves the context
+ * as it was.  VB_ERR_STATE after vb_setup. */
 int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
                 int n_ent, const vb_entity *ents);
 

@@ -475,9 +475,27 @@ const char *vb_last_error(const vb_ctx *ctx) { return ctx ? ctx->err.c_str() : "
 
 int64_t vb_interface_size(const vb_ctx *ctx) { return ctx ? ctx->nG + ctx->nS : 0; }
 
+static int assemble_impl(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
+                         int n_ent, const vb_entity *ents);
+
+// A failed call leaves the context as it was (the problems added before).
 int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs, int n_ent,
                 const vb_entity *ents) {
   if (!ctx) return VB_ERR_ARG;
+  const size_t e0 = ctx->ents.size(), s0 = ctx->subs.size();
+  const int mx[5] = {ctx->max_n_csr, ctx->max_N, ctx->max_e, ctx->max_ng, ctx->max_ent};
+  const int rc = assemble_impl(ctx, n_iface, n_sub, subs, n_ent, ents);
+  if (rc != VB_OK && ctx->state <= 1 && !ctx->finalized) {
+    ctx->ents.resize(e0);
+    ctx->subs.resize(s0);
+    ctx->max_n_csr = mx[0], ctx->max_N = mx[1], ctx->max_e = mx[2], ctx->max_ng = mx[3],
+    ctx->max_ent = mx[4];
+  }
+  return rc;
+}
+
+static int assemble_impl(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
+                         int n_ent, const vb_entity *ents) {
   if (ctx->state > 1 || ctx->finalized)
     return ctx->fail(VB_ERR_STATE, "vb_assemble: problems can only be added before vb_setup");
   if (n_iface < 0 || n_sub <= 0 || !subs || n_ent < 0 || (n_ent > 0 && !ents))
@@ -521,11 +539,14 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     const int s = s0 + sl;
     const vb_subdomain &D = subs[sl];
     SubH &S = ctx->subs[s];
-    if (D.n <= 0 || !D.indptr || !D.indices || !D.data || !D.kind || !D.gid || !D.pweight || !D.rhs)
+    if (D.n <= 0 || D.nnz < 0 || !D.indptr || !D.indices || !D.data || !D.kind || !D.gid ||
+        !D.pweight || !D.rhs)
       return ctx->fail(VB_ERR_ARG, "vb_assemble: bad subdomain " + std::to_string(sl));
     S.n = D.n;
     S.indptr.assign(D.indptr, D.indptr + D.n + 1);
-    if (S.indptr[0] != 0 || S.indptr[D.n] != D.nnz)
+    bool mono = S.indptr[0] == 0 && S.indptr[D.n] == D.nnz;
+    for (int i = 0; i < D.n && mono; ++i) mono = S.indptr[i] <= S.indptr[i + 1];
+    if (!mono)
       return ctx->fail(VB_ERR_ARG, "vb_assemble: bad indptr in subdomain " + std::to_string(sl));
     S.indices.resize(D.nnz);
     for (int64_t q = 0; q < D.nnz; ++q) {
@@ -563,6 +584,9 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
     for (int i = 0; i < D.n; ++i) {
       if (S.kind[i] == VB_KIND_INTERIOR) S.pos[i] = cv++;
       else if (S.kind[i] == VB_KIND_PRESSURE) {
+        if (!(D.pweight[i] > 0.0) || !std::isfinite(D.pweight[i]))
+          return ctx->fail(VB_ERR_ARG, "vb_assemble: pressure weights (element volumes) must be "
+                                       "positive, subdomain " + std::to_string(sl));
         S.pos[i] = S.nv + cp++;
         S.pw.push_back(D.pweight[i]);
         S.vol += D.pweight[i];

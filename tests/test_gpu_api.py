@@ -15,7 +15,9 @@
 * bad input data map to error codes (every kernel still runs to its end):
   a local velocity block that is not positive definite makes vb_setup return
   VB_ERR_NOT_SPD naming the subdomain, and a NaN in a right-hand side makes
-  vb_pcg_solve return VB_ERR_BREAKDOWN.
+  vb_pcg_solve return VB_ERR_BREAKDOWN; inconsistent CSR row pointers or a
+  zero element volume make vb_assemble return VB_ERR_ARG and leave the
+  context as it was.
 """
 import numpy as np
 import pytest
@@ -179,3 +181,26 @@ def test_nan_rhs_is_reported(vb, c1):
     finally:
         vb.vb_destroy(ctx)
     assert info["status"] == VB_ERR_BREAKDOWN
+
+
+def test_bad_assembly_data_is_rejected_and_rolled_back(vb, c1):
+    bad_ptr = _copy(c1)
+    ip = bad_ptr["subs"][1]["indptr"]
+    ip[5], ip[6] = ip[6], ip[5]  # row pointers no longer rise
+    bad_w = _copy(c1)
+    sd = bad_w["subs"][2]
+    sd["pweight"][np.nonzero(sd["kind"] == 2)[0][0]] = 0.0
+    ctx = vb.vb_create()
+    try:
+        for bad in (bad_ptr, bad_w):
+            with pytest.raises(vb.VBError) as e:
+                vb.vb_assemble(ctx, bad)
+            assert e.value.code == VB_ERR_ARG
+        assert vb.vb_num_problems(ctx) == 0
+        vb.vb_assemble(ctx, c1)  # the context is still empty and usable
+        vb.vb_setup(ctx)
+        x = torch.zeros(vb.vb_interface_size(ctx), dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x)
+        assert info["true_rel_residual"] <= 1e-8 * 1.01
+    finally:
+        vb.vb_destroy(ctx)
