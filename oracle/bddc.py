@@ -34,9 +34,13 @@ KIND_INTERIOR, KIND_INTERFACE, KIND_PRESSURE = 0, 1, 2
 
 
 class LocalSchur:
-    """Static condensation of one subdomain (eqs. uipi, firstSchur)."""
+    """Static condensation of one subdomain (eqs. uipi, firstSchur).
 
-    def __init__(self, sd):
+    condense=False keeps only the factorisation of the Dirichlet problem
+    (enough for recover), without forming S_Gamma^(i) and g.
+    """
+
+    def __init__(self, sd, condense=True):
         n = len(sd["kind"])
         K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(n, n))
         kind = sd["kind"]
@@ -60,14 +64,15 @@ class LocalSchur:
         self.nv, self.npr = nv, npr
         C = sp.vstack([A_IG, Bp_G, sp.csr_matrix((1, len(self.ig)))]).toarray()
         self.C = C
-        X = self.lu.solve(C)
-        self.S = self.A_GG - C.T @ X
         rhs = sd["rhs"]
         self.f_I = rhs[self.iv]
         self.f_G = rhs[self.ig]
         self.h_p = rhs[self.ip]
-        xb = self.lu.solve(np.concatenate([self.f_I, self.h_p, [0.0]]))
-        self.g = self.f_G - C.T @ xb
+        if condense:
+            X = self.lu.solve(C)
+            self.S = self.A_GG - C.T @ X
+            xb = self.lu.solve(np.concatenate([self.f_I, self.h_p, [0.0]]))
+            self.g = self.f_G - C.T @ xb
         # p0 row: B0_Gamma = sum of the element flux rows on the interface
         self.B0 = np.asarray(Bp_G.sum(axis=0)).ravel()
         self.g0 = float(self.h_p.sum())
