@@ -245,15 +245,22 @@ int vb_apply(vb_ctx *ctx, const double *r_dev, double *z_dev);
 int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info);
 
 /* Interior recovery (eq. uipi) for subdomain `sub` from the interface
- * solution x_dev: writes the local DoF vector (the subdomain's own CSR DoF
- * order: velocities, then element pressures = Q_I part + p0) to u_host. */
+ * solution x_dev: writes the subdomain's local DoF vector (n entries of its
+ * vb_subdomain, in that CSR DoF order; interface entries copied from x_dev,
+ * element pressures = Q_I part + p0) to u_host.  Runs vb_recover_all for
+ * every subdomain and copies one out: to read several, call vb_recover_all
+ * once instead. */
 int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_host);
 
 /* Interior recovery for every subdomain at once: out_dev (device, may be
  * NULL to only refresh the internal copy) receives the concatenation over
  * subdomains of their local DoF vectors, each in its own CSR DoF order.
- * VB_PREC_MIXED: the FP32-factor recovery is followed by FP64 refinement of
- * the interior equations with the interface data fixed at x_dev. */
+ * VB_PREC_MIXED: FP64 refinement of the interior equations with the FP32
+ * factor, the interface data fixed at x_dev: two passes from the interior
+ * iterate of the last vb_pcg_solve when x_dev holds that solve's solution
+ * bit for bit, else four passes from zero.  FP64 with local matrices in
+ * waves (vb_options.local_mem_limit): every wave but the resident one is
+ * factored again. */
 int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev);
 
 /* Adaptive coarse space of the last vb_setup (Sec. 6): fills up to
