@@ -178,29 +178,52 @@ hipError_t scatter_copy(int n, const double *src, const int64_t *sidx, const int
 }
 
 // Deluxe extension: z[gid[m]] = sum_q (D_q w_q)[m] over the subdomains of
-// the entity (D_q = null: counting weights 1/card).  One thread per row.
-__global__ void k_extend(const ExtJob *jobs, const ExtPart *parts, const double *w, double *z) {
+// the entity (D_q = null: counting weights 1/card).  A workgroup takes 64
+// rows (lanes over the rows: coalesced reads down the columns of the
+// column-major D_q); its four waves split the columns, four independent
+// sums per lane, and the partial sums are added through LDS in a fixed
+// order.
+__global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPart *parts,
+                                                const double *w, double *z) {
   const ExtJob J = jobs[blockIdx.y];
-  const int m = blockIdx.x * blockDim.x + threadIdx.x;
-  if (m >= J.m) return;
+  const int r0 = blockIdx.x * 64;
+  if (r0 >= J.m) return;  // uniform over the workgroup
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int m = r0 + lane;
+  const bool row = m < J.m;
+  const int c0 = (int)((int64_t)J.m * wv / 4), c1 = (int)((int64_t)J.m * (wv + 1) / 4);
   double s = 0.0;
   for (int q = 0; q < J.nparts; ++q) {
     const ExtPart P = parts[J.part0 + q];
     const double *wq = w + P.woff;
     if (P.D) {
-      const auto a = gptr(P.D + m);
-      for (int l = 0; l < J.m; ++l) s += a[(int64_t)l * P.ld] * wq[l];
-    } else {
+      if (row) {
+        const auto a = gptr(P.D + m);
+        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+        int l = c0;
+        for (; l + 4 <= c1; l += 4) {
+          s0 += a[(int64_t)l * P.ld] * wq[l];
+          s1 += a[(int64_t)(l + 1) * P.ld] * wq[l + 1];
+          s2 += a[(int64_t)(l + 2) * P.ld] * wq[l + 2];
+          s3 += a[(int64_t)(l + 3) * P.ld] * wq[l + 3];
+        }
+        for (; l < c1; ++l) s0 += a[(int64_t)l * P.ld] * wq[l];
+        s += (s0 + s1) + (s2 + s3);
+      }
+    } else if (wv == 0 && row) {
       s += wq[m] * P.scale;
     }
   }
-  z[J.gids[m]] = s;
+  __shared__ double part[4][64];
+  part[wv][lane] = s;
+  __syncthreads();
+  if (wv == 0 && row) z[J.gids[m]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
 }
 
 hipError_t extend(const ExtJob *d_jobs, int njobs, int max_m, const ExtPart *d_parts,
                   const double *w, double *z, hipStream_t s) {
   if (!njobs || !max_m) return hipSuccess;
-  hipLaunchKernelGGL(k_extend, dim3((max_m + 127) / 128, njobs), dim3(128), 0, s, d_jobs, d_parts,
+  hipLaunchKernelGGL(k_extend, dim3((max_m + 63) / 64, njobs), dim3(256), 0, s, d_jobs, d_parts,
                      w, z);
   return hipGetLastError();
 }
