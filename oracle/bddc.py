@@ -1,5 +1,8 @@
 """FP64 reference BDDC for the interface saddle-point problem (Sec. 4).
 
+Test infrastructure only (the CPU oracle): the tests, the smoke check and
+the CPU-baseline leg of the benchmark use it; the library never does.
+
 Input: the plain-data workload (per-subdomain reduced local saddle matrices
 in CSR, DoF kinds, global interface ids, element volumes of the pressure
 DoFs, local right-hand sides; per-entity constraint functionals).

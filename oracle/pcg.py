@@ -1,5 +1,7 @@
 """Preconditioned conjugate gradients with a Lanczos condition estimate.
 
+Test infrastructure only (the CPU oracle).
+
 The interface system S_hat u = g_hat (eq. globInt) is solved by CG
 preconditioned with M^-1 (eq. BDDCprec), from x0 = 0, stopping when the
 recursive residual satisfies ||r||_2 <= tol ||g_hat||_2 (Sec. 7: a 1e-8
