@@ -37,3 +37,45 @@ def test_binding_refuses_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(binding, "_lib", None)
     with pytest.raises(RuntimeError):
         binding.load()
+
+
+def test_binding_structs_match_the_header(tmp_path):
+    """Every struct of the header has the same size and field offsets in the
+    ctypes binding as in C (a gcc probe of include/vembddc.h)."""
+    import ctypes
+    import shutil
+    import subprocess
+
+    from paper_2304_09770_amd import binding
+    if shutil.which("gcc") is None:
+        pytest.skip("no host C compiler")
+    structs = [getattr(binding, n) for n in ("vb_options", "vb_problem", "vb_face_info",
+                                             "vb_kernel_stat", "vb_subdomain", "vb_entity",
+                                             "vb_solve_info")]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "vembddc.h"', "int main(void) {"]
+    for S in structs:
+        n = S.__name__
+        lines.append('printf("%s sizeof %%zu\\n", sizeof(%s));' % (n, n))
+        for f, _ in S._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (n, f, n, f))
+    lines.append("return 0; }")
+    src = tmp_path / "probe.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "probe"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                    str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out.splitlines()}
+    for S in structs:
+        n = S.__name__
+        assert got[(n, "sizeof")] == ctypes.sizeof(S), n
+        for f, _ in S._fields_:
+            assert got[(n, f)] == getattr(S, f).offset, (n, f)
+    # and no field of the header is missing from the binding
+    txt = open(os.path.join(ROOT, "include", "vembddc.h")).read()
+    for S in structs:
+        body = re.search(r"typedef struct %s \{(.*?)\} %s;" % (S.__name__, S.__name__), txt, re.S)
+        assert body, S.__name__
+        decl = re.sub(r"/\*.*?\*/", "", body.group(1), flags=re.S)
+        names = re.findall(r"(\w+)\s*(?:,|;)", decl)
+        assert sorted(names) == sorted(f for f, _ in S._fields_), S.__name__
