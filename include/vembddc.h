@@ -169,7 +169,10 @@ typedef struct vb_solve_info {
 
 typedef struct vb_ctx vb_ctx;
 
-/* Create a context; opt may be NULL for defaults. */
+/* Create a context; opt may be NULL for defaults (fields left 0 take their
+ * defaults too).  VB_ERR_ARG for an unknown precision or scaling, a panel
+ * width other than 32 or 64, a negative or NaN memory limit or adaptive
+ * threshold, or a non-finite tolerance. */
 int vb_create(vb_ctx **ctx, const vb_options *opt);
 void vb_destroy(vb_ctx *ctx);
 const char *vb_last_error(const vb_ctx *ctx);

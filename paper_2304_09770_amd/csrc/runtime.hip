@@ -431,8 +431,12 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
     delete ctx;
     return VB_ERR_ARG;
   }
-  if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) || d.setup_mem_limit < 0.0 ||
-      d.local_mem_limit < 0.0) {
+  // NaN fails every comparison: the limits and tolerances are checked as
+  // "x >= 0" so that NaN is rejected rather than taken as a value
+  if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) ||
+      (d.scaling != VB_SCALING_DELUXE && d.scaling != VB_SCALING_COUNTING) ||
+      !(d.setup_mem_limit >= 0.0) || !(d.local_mem_limit >= 0.0) || !std::isfinite(d.tol) ||
+      !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta)) {
     delete ctx;
     return VB_ERR_ARG;
   }

@@ -2,8 +2,9 @@
 
 * call order: vb_setup before vb_assemble, and vb_pcg_solve / vb_apply
   before vb_setup, return VB_ERR_STATE;
-* option checks: an unsupported panel width, precision or a negative memory
-  limit make vb_create return VB_ERR_ARG;
+* option checks: an unsupported panel width, precision or scaling, a
+  negative or NaN memory limit, a NaN tolerance or a negative adaptive
+  threshold make vb_create return VB_ERR_ARG;
 * the iteration cap: with maxit = 3 vb_pcg_solve returns
   VB_ERR_NOT_CONVERGED and still writes its iterate, which is the third PCG
   iterate of the oracle (same recurrences, Sec. 7);
@@ -74,8 +75,9 @@ def test_call_order(vb, c1):
         vb.vb_destroy(ctx)
 
 
-@pytest.mark.parametrize("kw", [dict(panel=48), dict(precision=7), dict(setup_mem_limit=-1.0),
-                                dict(local_mem_limit=-1.0)])
+@pytest.mark.parametrize("kw", [dict(panel=48), dict(precision=7), dict(scaling=3),
+                                dict(setup_mem_limit=-1.0), dict(local_mem_limit=float("nan")),
+                                dict(tol=float("nan")), dict(adaptive_theta=-1.0)])
 def test_bad_options(vb, kw):
     with pytest.raises(vb.VBError) as e:
         vb.vb_create(**kw)

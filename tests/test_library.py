@@ -79,3 +79,20 @@ def test_binding_structs_match_the_header(tmp_path):
         decl = re.sub(r"/\*.*?\*/", "", body.group(1), flags=re.S)
         names = re.findall(r"(\w+)\s*(?:,|;)", decl)
         assert sorted(names) == sorted(f for f, _ in S._fields_), S.__name__
+
+
+@pytest.mark.parametrize("kw", [dict(panel=48), dict(precision=7), dict(scaling=3),
+                                dict(setup_mem_limit=-1.0), dict(local_mem_limit=float("nan")),
+                                dict(tol=float("nan")), dict(tol=float("inf")),
+                                dict(svd_tol=float("nan")), dict(adaptive_theta=-1.0),
+                                dict(adaptive_theta=float("nan"))])
+def test_bad_options_are_rejected_on_the_host(kw):
+    """vb_create checks its options before any HIP call, so this runs without
+    a GPU."""
+    from paper_2304_09770_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2304_09770_amd.build import build
+        build()
+    with pytest.raises(binding.VBError) as e:
+        binding.vb_create(**kw)
+    assert e.value.code == -1
