@@ -123,6 +123,45 @@ def test_deluxe_partition_of_unity(tiny_jit):
             assert np.abs(sum(mats) - np.eye(mats[0].shape[0])).max() < 1e-12
 
 
+def _deluxe_energy_checks(o, rng):
+    """For every entity shared by several subdomains: w_q random local values
+    on its dual coordinates, v = sum_q D_q w_q (the extension), and
+    E(x) = sum_q (w_q - x)^T Sbar_q (w_q - x).  Returns the largest
+    |E(v+d) - E(v-d)| / (E(v+d) + E(v-d)) and whether E(v +- d) > E(v)
+    held for every trial."""
+    worst, above = 0.0, True
+    for e in range(len(o.ents)):
+        items = [(i, pos, D) for (ee, i), (pos, D) in o.D.items() if ee == e]
+        if len(items) < 2:
+            continue
+        Sb = [o.loc[i].St[np.ix_(pos, pos)] for i, pos, _ in items]
+        w = [rng.standard_normal(D.shape[0]) for _, _, D in items]
+        v = sum(D @ wq for (_, _, D), wq in zip(items, w))
+
+        def E(x):
+            return sum((wq - x) @ S @ (wq - x) for wq, S in zip(w, Sb))
+
+        for _ in range(3):
+            d = rng.standard_normal(len(v)) * np.linalg.norm(v) / np.sqrt(len(v))
+            ep, em, e0 = E(v + d), E(v - d), E(v)
+            worst = max(worst, abs(ep - em) / (ep + em))
+            above = above and ep > e0 and em > e0
+    return worst, above
+
+
+def test_deluxe_average_minimises_the_weighted_energy(tiny_jit):
+    """Deluxe averaging (Sec. 6): the extension sum_q D_q w_q of local values
+    on an entity's dual coordinates minimises sum_q ||w_q - v||^2 in the
+    Sbar_q norms (Sbar_q: subdomain q's block of the transformed S_Gamma on
+    those coordinates).  A quadratic takes equal values at v* + d and v* - d
+    exactly at its minimiser, so the test perturbs symmetrically.  Unlike
+    sum_q D_q = I, this fails for transposed blocks D_q^T or a product taken
+    in the wrong order."""
+    pb, dec, o = tiny_jit
+    worst, above = _deluxe_energy_checks(o, np.random.default_rng(3))
+    assert worst < 1e-10 and above
+
+
 def test_preconditioner_symmetric(tiny_jit):
     pb, dec, o = tiny_jit
     rng = np.random.default_rng(0)
