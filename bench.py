@@ -72,6 +72,58 @@ def ldl_roofline(ldl, peak, dtype, traffic=None, source=None):
             "launches": ldl["launches"], "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
 
 
+def dense_condensation_flops(wl):
+    """Flops a dense right-looking LDL^T executes to condense every
+    subdomain's interior unknowns (interior velocities and the n_el - 1
+    mean-free pressures, e in all) onto its n_Gamma interface unknowns
+    (eqs. uipi, firstSchur), m = e + n_Gamma: per eliminated column with t
+    rows left (pivot included), t - 1 to scale the column by the pivot and
+    t (t - 1) for the rank-1 update of the trailing lower triangle, t^2 - 1
+    in all, for t from m - e + 1 to m."""
+    tot = 0
+    for sd in wl["subs"]:
+        kind = np.asarray(sd["kind"])
+        e = int(np.sum(kind == 0)) + int(np.sum(kind == 2)) - 1
+        m = e + int(np.sum(kind == 1))
+        s2 = lambda n: n * (n + 1) * (2 * n + 1) // 6
+        tot += (s2(m) - s2(m - e)) - e
+    return float(tot)
+
+
+def sparse_lu_flops(lu):
+    """Flops of a sparse LU factorisation from its factors' structure:
+    sum over pivots of 2 (c_j - 1)(r_j - 1) + (c_j - 1), c_j and r_j the
+    entries of column j of L and row j of U (diagonal included)."""
+    c = np.diff(lu.L.tocsc().indptr).astype(np.float64)
+    r = np.bincount(lu.U.tocsc().indices, minlength=lu.shape[0]).astype(np.float64)
+    return float(np.sum(2.0 * (c - 1.0) * (r - 1.0) + (c - 1.0)))
+
+
+def setup_flops(wl, sparse_sample, setup_ms):
+    """The local condensation's work counted two ways: what the dense
+    factorisation executes, and the LU flops of the oracle's sparse
+    factorisation of the interior matrices (fill-reducing COLAMD ordering;
+    sampled subdomains scaled to all, halved for the symmetric factorisation
+    it stands for; the dense Schur complement itself not included), each
+    per second of the measured setup."""
+    try:
+        dense = dense_condensation_flops(wl)
+        out = {"dense_executed": dense,
+               "dense_tflops_per_setup_s": dense / (setup_ms * 1e-3) / 1e12 if setup_ms else None,
+               "sparse_factor_est": None, "sparse_tflops_per_setup_s": None, "sparse_sample": None}
+        if sparse_sample:
+            nsub = len(wl["subs"])
+            sp_f = 0.5 * float(np.mean(sparse_sample)) * nsub
+            out.update(sparse_factor_est=sp_f,
+                       sparse_tflops_per_setup_s=sp_f / (setup_ms * 1e-3) / 1e12 if setup_ms else None,
+                       sparse_sample="SuperLU (COLAMD) factors of %d of %d subdomains' interior "
+                                     "matrices, mean scaled x%d, halved" % (len(sparse_sample), nsub, nsub))
+        return out
+    except Exception as ex:  # a report field only: never fail the bench line
+        log("setup flop model skipped: %r" % (ex,))
+        return None
+
+
 def cpu_baseline(wl, nsample, budget_s=30.0):
     """The oracle's local Schur complement (sparse LU + one solve per
     interface column) on `nsample` subdomains, scaled to all subdomains:
@@ -84,15 +136,21 @@ def cpu_baseline(wl, nsample, budget_s=30.0):
     except Exception:
         threads = os.cpu_count() or 1
     t0 = time.perf_counter()
-    done = 0
+    done, lus = 0, []
     for s in range(nsample):
-        LocalSchur(wl["subs"][s])
+        lus.append(LocalSchur(wl["subs"][s]).lu)
         done += 1
         if time.perf_counter() - t0 > budget_s:
             break
     dt = (time.perf_counter() - t0) / done
     nsub = len(wl["subs"])
+    try:
+        sparse = [sparse_lu_flops(lu) for lu in lus]
+    except Exception as ex:
+        log("sparse flop count skipped: %r" % (ex,))
+        sparse = None
     return {"value": 1.0 / (dt * nsub), "unit": "solves/s", "cores": int(threads),
+            "_sparse_flops": sparse,
             "kind": "oracle",
             "sample": "local Schur complements (sparse LU, one solve per interface column) of "
                       "%d of %d subdomains, %.2f s each, scaled x%d; oracle coarse/deluxe/PCG "
@@ -154,9 +212,10 @@ def main():
         return
     nsub = len(wl["subs"])
     # ---- CPU baseline (oracle, bounded sample)
-    cpu = None
+    cpu, sparse_flops = None, None
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_sample)
+        sparse_flops = cpu.pop("_sparse_flops")
         log("cpu baseline: %s" % cpu["sample"])
     # ---- GPU
     import torch
@@ -293,6 +352,7 @@ def main():
         "speedup_vs_fp64": (runs["fp64"]["dt"] / runs["mixed"]["dt"]) if len(runs) == 2 else None,
         "mixed_accuracy": check or None,
         "roofline_fp64": roof(runs["fp64"], PEAK_FP64_TFLOPS, "f64", "fp64") if "fp64" in runs else None,
+        "setup_flops": setup_flops(wl, sparse_flops, R["info"]["setup_ms"]),
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)

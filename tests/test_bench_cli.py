@@ -1,5 +1,6 @@
-"""bench.py's command line on the CPU: more than one GPU is refused with a
-message (this build has no multi-GPU path), before any GPU work."""
+"""bench.py on the CPU: more than one GPU is refused with a message (this
+build has no multi-GPU path), before any GPU work; the setup flop counts it
+reports match brute force and the textbook dense LU count."""
 import os
 import subprocess
 import sys
@@ -13,3 +14,49 @@ def test_more_than_one_gpu_is_refused():
     assert r.returncode == 2
     assert "exactly one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def _bench():
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_dense_condensation_flops_match_brute_force():
+    import numpy as np
+    b = _bench()
+    subs = []
+    for nv, npr, ng in [(7, 3, 5), (20, 4, 0), (1, 2, 9)]:
+        subs.append({"kind": np.array([0] * nv + [2] * npr + [1] * ng)})
+    want = 0
+    for nv, npr, ng in [(7, 3, 5), (20, 4, 0), (1, 2, 9)]:
+        e, m = nv + npr - 1, nv + npr - 1 + ng
+        for j in range(e):  # rank-1 update of the trailing lower triangle
+            want += sum(2 for r in range(j + 1, m) for c in range(j + 1, r + 1))  # multiply-add
+            want += m - j - 1  # the column below the pivot scaled by it
+    assert b.dense_condensation_flops({"subs": subs}) == float(want)
+
+
+def test_sparse_lu_flops_of_a_dense_matrix_is_the_textbook_count():
+    import numpy as np
+    import scipy.sparse as sp
+    from scipy.sparse.linalg import splu
+    b = _bench()
+    n = 40
+    A = np.random.default_rng(0).standard_normal((n, n)) + n * np.eye(n)
+    lu = splu(sp.csc_matrix(A), permc_spec="NATURAL")
+    want = sum(2 * k * k + k for k in range(n))  # 2n^3/3 + O(n^2)
+    assert b.sparse_lu_flops(lu) == float(want)
+
+
+def test_setup_flops_report_on_a_small_workload():
+    from inputs.workloads import make_workload
+    from oracle.bddc import LocalSchur
+    b = _bench()
+    wl, _ = make_workload("c1", workers=1)
+    lu = LocalSchur(wl["subs"][0], condense=False).lu
+    rep = b.setup_flops(wl, [b.sparse_lu_flops(lu)], 10.0)
+    assert 0 < rep["sparse_factor_est"] < rep["dense_executed"]
+    assert rep["dense_tflops_per_setup_s"] == rep["dense_executed"] / 1e-2 / 1e12
