@@ -13,7 +13,8 @@ warm solves/s (the setup reused: PCG or refinement and recovery only).
 Prints one JSON line: the metric, value (mixed solves/s), the per-path runs,
 the speedup over the FP64 path, the accuracy of the mixed solution, the
 roofline of the dominant kernel (the FP32 rank-1024 trailing update of the
-local Dirichlet factorisations, HIP-event timed) and of the Schur GEMV, and
+local Dirichlet factorisations, HIP-event timed) and of the Schur GEMV, the
+local condensation's flops (dense as executed, and a sparse LU estimate) and
 the oracle's CPU baseline.  `--config c3|c4|c5s` select the other workloads.
 """
 import argparse
