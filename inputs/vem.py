@@ -9,7 +9,10 @@ Local degrees of freedom of an element K (Sec. 3, D1-D5), in this order:
   (1/|f|) int_f (v.n_f) m, (1/|f|) int_f (v.t1_f) m, (1/|f|) int_f (v.t2_f) m,
   with the face frame (t1_f, t2_f, n_f) fixed globally per face (n_f points
   toward +axis), so the tangential moments recover v_tau;
-* D4: (1/|K|) int_K v.(xh ^ p) for p in [P_{k-3}]^3 (k = 3: the 3 constants);
+* D4: (1/|K|) int_K v.(xh ^ (e_c m_g)) for the scaled monomials m_g of
+  degree <= k-3 (k = 3: the 3 constants), leaving out the pairs (c = z, m_g
+  = z q): xh ^ (e_x x q) + xh ^ (e_y y q) + xh ^ (e_z z q) = xh ^ (xh q) = 0,
+  so x ^ [P_{k-3}]^3 has dimension 3 dim P_{k-3} - dim P_{k-4} (k = 4: 11);
 * D5: (h_K/|K|) int_K div(v) m for the non-constant scaled monomials of
   degree <= k-1.
 
@@ -33,7 +36,7 @@ The divergence rows are exact (computed from D1-D3 and D5).
 import numpy as np
 from .quadrature import (gauss_legendre01, gauss_lobatto_interior01, triangle_rule,
                          tet_rule)
-from .poly import (mono3, mono2, dim3, dim2, eval3, eval2, grad2_eval, grad3_coef,
+from .poly import (mono3, mono2, dim3, dim2, index3, eval3, eval2, grad2_eval, grad3_coef,
                    lap3_coef, lap2_coef, wedge_coef, helmholtz_tables)
 from .mesh import LOCAL_VERTS, LOCAL_EDGES, LOCAL_FACES
 
@@ -46,10 +49,14 @@ class DofLayout:
     """Element-local DoF numbering for degree k."""
 
     def __init__(self, k):
-        assert k in (2, 3), "degrees 2 and 3 are supported"
+        assert k in (2, 3, 4), "degrees 2, 3 and 4 are supported"
         self.k = k
         self.nf2 = dim2(k - 2)  # face moment monomials per kind
-        self.nD4 = 3 if k == 3 else 0
+        ex = mono3(k - 3) if k >= 3 else ()
+        self.d4_pairs = [(c, g) for c in range(3) for g, e in enumerate(ex)
+                         if not (c == 2 and e[2] >= 1)]
+        self._d4_pos = {pr: i for i, pr in enumerate(self.d4_pairs)}
+        self.nD4 = len(self.d4_pairs)
         self.nD5 = dim3(k - 1) - 1
         self.nP = dim3(k - 1)  # pressure monomials per element
         self.off2 = 24
@@ -73,6 +80,18 @@ class DofLayout:
 
     def d5(self, a):  # a = 0 .. nD5-1  (monomial index a+1)
         return self.off5 + a
+
+    def d4_terms(self, c, g):
+        """(coefficient, DoF) pairs giving (1/|K|) int_K v.(xh ^ (e_c m_g)) for
+        any m_g of degree <= k-3: the DoF itself, or for a left-out pair
+        (c = z, m_g = z q) minus the x q and y q moments."""
+        if (c, g) in self._d4_pos:
+            return [(1.0, self.d4(self._d4_pos[(c, g)]))]
+        e = mono3(self.k - 3)[g]
+        idx = index3(self.k - 3)
+        gx = idx[(e[0] + 1, e[1], e[2] - 1)]
+        gy = idx[(e[0], e[1] + 1, e[2] - 1)]
+        return [(-1.0, self.d4(self._d4_pos[(0, gx)])), (-1.0, self.d4(self._d4_pos[(1, gy)]))]
 
 
 def _edge_nodes(k):
@@ -255,11 +274,13 @@ def element_matrices(mesh, k, elems, nu, force=None, keep=False):
             q = Qt[j][c, g]  # over dim3(j+1)
             val = hK[:, None] * ein("a,ean->en", q, GRADQ[:, : len(q)])
             if j >= 1:
-                r = Rt[j][c, g]  # (3, dim3(j-1))
-                # r of degree j-1 <= k-3 -> D4 (only k=3, j=1, r constant)
+                r = Rt[j][c, g]  # (3, dim3(j-1)), homogeneous of degree j-1 <= k-3
+                # int_K v.(xh ^ r) from the D4 moments
                 for kk in range(3):
-                    if abs(r[kk, 0]) > 0:
-                        val[:, L.d4(kk)] += r[kk, 0] * vK
+                    for gg in range(r.shape[1]):
+                        if r[kk, gg] != 0.0:
+                            for coef, dof in L.d4_terms(kk, gg):
+                                val[:, dof] += coef * r[kk, gg] * vK
             VM[:, c, g] = val
     # Pi^nabla_k
     G3 = grad3_coef(k + 1)
@@ -333,11 +354,11 @@ def element_matrices(mesh, k, elems, nu, force=None, keep=False):
             for kind, vec in enumerate((nf, t1, t2)):
                 DOFM[:, L.d3(lf, b, kind)] = vec[:, :, None] * FX[:, b][:, None, :]
     if L.nD4:
-        W0 = wedge_coef(0)  # xh ^ e_k : (3, 1, 3, dim3(1))
-        for kk in range(3):
-            wr = W0[kk, 0]  # (3, dim3(1))
+        Wd = wedge_coef(k - 3)  # xh ^ (e_kk m_g) : (3, dim3(k-3), 3, dim3(k-2))
+        for i, (kk, gg) in enumerate(L.d4_pairs):
+            wr = Wd[kk, gg]  # (3, dim3(k-2))
             for c in range(3):
-                DOFM[:, L.d4(kk), c] = ein("p,ebp->eb", wr[c], Mass[:, :nk, :dim3(1)]) / vK[:, None]
+                DOFM[:, L.d4(i), c] = ein("p,ebp->eb", wr[c], Mass[:, :nk, :dim3(k - 2)]) / vK[:, None]
     # D5 of e_c m_b: (hK/|K|) int (1/hK) d_c m_b m_a = (1/|K|) sum G3[c][b,g] Mass[g,a]
     for a in range(1, nkm1):
         for c in range(3):
@@ -401,11 +422,12 @@ def interpolate(mesh, k, elems, u, divu=None):
     Xh = (Pv - xK[:, None]) / hK[:, None, None]
     if L.nD4:
         uq = u(Pv)
-        for kk in range(3):
+        M4 = eval3(Xh, k - 3)
+        for i, (kk, gg) in enumerate(L.d4_pairs):
             ek = np.zeros(3)
             ek[kk] = 1.0
-            wq = np.cross(Xh, ek)
-            out[:, L.d4(kk)] = ein("eq,eqc,eqc->e", Wv, uq, wq) / vK
+            wq = np.cross(Xh, ek) * M4[:, :, gg, None]
+            out[:, L.d4(i)] = ein("eq,eqc,eqc->e", Wv, uq, wq) / vK
     if divu is not None:
         M = eval3(Xh, k - 1)
         dq = divu(Pv)
