@@ -91,7 +91,8 @@ class LocalSchur:
 
 
 class OracleBDDC:
-    def __init__(self, wl, scaling="deluxe", adaptive_theta=0.0, svd_tol=1e-10):
+    def __init__(self, wl, scaling="deluxe", adaptive_theta=0.0, svd_tol=1e-10,
+                 adaptive_edges=False):
         self.wl = wl
         self.nG = wl["n_iface"]
         self.loc = [LocalSchur(sd) for sd in wl["subs"]]
@@ -113,7 +114,7 @@ class OracleBDDC:
         self._setup_basis()
         if adaptive_theta > 0:
             from .adaptive import adaptive_rows
-            self.eig_info = adaptive_rows(self, adaptive_theta)
+            self.eig_info = adaptive_rows(self, adaptive_theta, edges=adaptive_edges)
             self._setup_basis()
         self._setup_scaling()
         self._setup_coarse()

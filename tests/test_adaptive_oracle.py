@@ -3,7 +3,10 @@ mathematics fixes: the closed form of the parallel sum, the Schur complement
 as the inverse of a block of the inverse, the Loewner bound lambda in [0, 1],
 the rigid-mode cluster of faces next to a floating subdomain
 (ker X:Y = ker X + ker Y), Sylvester's inertia for the selected count, the
-all-selected limit, and the effect on the condition number."""
+all-selected limit, and the effect on the condition number; for the
+optional edge eigenproblems (parallel sums over all subdomains sharing an
+edge) the closed form of a several-term parallel sum, lambda in [0, 1], the
+all-selected limit and a lower kappa_2 than faces alone."""
 import numpy as np
 import pytest
 import scipy.linalg as sla
@@ -116,3 +119,54 @@ def test_adaptive_bounds_condition_and_keeps_solution():
     assert k2[10.0] <= 20.0, k2
     assert k2[0.0] > 10 * k2[10.0], k2
     assert k2[2.0] <= k2[10.0] * 1.001, k2
+
+
+# ------------------------------------------------- edges (beyond the paper's text)
+def _edges(o):
+    return [e for e, E in enumerate(o.ents)
+            if E["kind"] == 1 and len(o.ent_subs[e]) >= 2 and len(o.de_idx[e])]
+
+
+def test_parallel_sum_of_several_is_the_inverse_of_summed_inverses():
+    rng = np.random.default_rng(2)
+    X, Y, Z, W = (_spd(rng, 7) for _ in range(4))
+    ref = np.linalg.inv(sum(np.linalg.inv(M) for M in (X, Y, Z, W)))
+    fold = parallel_sum(parallel_sum(parallel_sum(X, Y), Z), W)
+    assert np.abs(fold - ref).max() < 1e-12 * np.abs(ref).max()
+
+
+def test_edge_eigenvalues_in_unit_interval(floating):
+    """At^(k) <= A^(k) in the Loewner order for every sharing subdomain, and
+    the parallel sum is monotone, so the edge pencil's eigenvalues lie in
+    [0, 1] like the faces'."""
+    pb, dec, o = floating
+    edges = _edges(o)
+    assert any(len(o.ent_subs[e]) == 4 for e in edges)
+    for e in edges:
+        Atp, Ap, subs = face_pencil(o, e)
+        lam = sla.eigh(Atp, Ap, eigvals_only=True)
+        assert lam.min() > -1e-9 and lam.max() < 1 + 1e-9, (e, subs)
+
+
+def test_all_selected_makes_edges_primal(floating):
+    pb, dec, o = floating
+    oa = OracleBDDC(dec.workload(), adaptive_theta=0.5, adaptive_edges=True)
+    for e in _edges(o):
+        assert oa.npi[e] == len(o.ents[e]["gids"])
+
+
+def test_edge_enrichment_lowers_the_condition_number(floating):
+    """At theta = 2 the edges' eigenproblems take kappa_2 below the
+    faces-only value; lambda_min stays 1 and PCG reaches the direct solve."""
+    pb, dec, o = floating
+    wl = dec.workload()
+    ref = np.concatenate(dec.interface_solution(pb.solve_reduced_direct()))
+    k2 = {}
+    for edges in (False, True):
+        oe = OracleBDDC(wl, adaptive_theta=2.0, adaptive_edges=edges)
+        x, info = pcg(oe.apply_S, oe.apply_M, oe.rhs(), tol=1e-10)
+        lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+        assert lmin > 1 - 1e-8
+        assert np.linalg.norm(x - ref) <= 1e-6 * np.linalg.norm(ref)
+        k2[edges] = lmax / lmin
+    assert k2[True] < k2[False], k2
