@@ -145,13 +145,30 @@ class VBError(RuntimeError):
         self.code = code
 
 
-def _ptr(t):
-    """Device address of a torch tensor or an int."""
+def _ptr(t, dtype=None, n=None):
+    """Device address of a torch tensor, or an int taken as a raw device
+    address.  A tensor must be on the GPU and contiguous; its element type
+    (`dtype`, e.g. "float64") and minimum length `n` are checked when given,
+    so that a host tensor, a wrong element type or a short vector is refused
+    here instead of reaching the kernels."""
     if t is None:
         return None
     if isinstance(t, int):
         return t
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("expected a GPU tensor, got %s" % getattr(t, "device", type(t).__name__))
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    if dtype is not None and str(t.dtype) != "torch." + dtype:
+        raise TypeError("expected a %s tensor, got %s" % (dtype, t.dtype))
+    if n is not None and t.numel() < n:
+        raise ValueError("expected at least %d elements, got %d" % (n, t.numel()))
     return t.data_ptr()
+
+
+def _vec(ctx, t):
+    """An interface vector of the context: float64, vb_interface_size long."""
+    return _ptr(t, "float64", vb_interface_size(ctx))
 
 
 def _np(a, dt):
@@ -218,20 +235,20 @@ def vb_interface_size(ctx):
 
 
 def vb_rhs(ctx, g):
-    _check(ctx, load().vb_rhs(ctx, _ptr(g)))
+    _check(ctx, load().vb_rhs(ctx, _vec(ctx, g)))
 
 
 def vb_schur_apply(ctx, x, y):
-    _check(ctx, load().vb_schur_apply(ctx, _ptr(x), _ptr(y)))
+    _check(ctx, load().vb_schur_apply(ctx, _vec(ctx, x), _vec(ctx, y)))
 
 
 def vb_apply(ctx, r, z):
-    _check(ctx, load().vb_apply(ctx, _ptr(r), _ptr(z)))
+    _check(ctx, load().vb_apply(ctx, _vec(ctx, r), _vec(ctx, z)))
 
 
 def vb_pcg_solve(ctx, x, raise_on_error=True):
     info = vb_solve_info()
-    rc = load().vb_pcg_solve(ctx, _ptr(x), C.byref(info))
+    rc = load().vb_pcg_solve(ctx, _vec(ctx, x), C.byref(info))
     if raise_on_error:
         _check(ctx, rc)
     return info.as_dict()
@@ -239,19 +256,21 @@ def vb_pcg_solve(ctx, x, raise_on_error=True):
 
 def vb_get_local_solution(ctx, x, sub, n):
     out = np.zeros(n)
-    rc = load().vb_get_local_solution(ctx, _ptr(x), int(sub),
+    rc = load().vb_get_local_solution(ctx, _vec(ctx, x), int(sub),
                                       out.ctypes.data_as(C.POINTER(C.c_double)))
     _check(ctx, rc)
     return out
 
 
 def vb_recover_all(ctx, x, out):
-    _check(ctx, load().vb_recover_all(ctx, _ptr(x), _ptr(out)))
+    _check(ctx, load().vb_recover_all(ctx, _vec(ctx, x), _ptr(out, "float64")))
 
 
 def vb_batched_ldl(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
-    rc = load().vb_batched_ldl(ctx, len(n), _ptr(ptrs), _ptr(n), _ptr(ld), _ptr(e), _ptr(p),
-                               _ptr(info), int(max_n), int(max_e))
+    b = len(n)
+    rc = load().vb_batched_ldl(ctx, b, _ptr(ptrs, "int64", b), _ptr(n, "int32", b),
+                               _ptr(ld, "int32", b), _ptr(e, "int32", b), _ptr(p, "int32", b),
+                               _ptr(info, "int32", b), int(max_n), int(max_e))
     _check(ctx, rc)
 
 
@@ -353,13 +372,17 @@ def vb_mlp_train(m, epochs, lr):
 
 
 def vb_mlp_forward(m, X, s):
-    _mcheck(m, load().vb_mlp_forward(m, _ptr(X), int(X.shape[0]), _ptr(s)))
+    N = int(X.shape[0])
+    _mcheck(m, load().vb_mlp_forward(m, _ptr(X, "float32", N * VB_MLP_FEATURES), N,
+                                     _ptr(s, "float32", N)))
 
 
 def vb_mlp_loss_grad(m, X, y, g):
     loss = C.c_double()
-    _mcheck(m, load().vb_mlp_loss_grad(m, _ptr(X), _ptr(y), int(X.shape[0]), _ptr(g),
-                                       C.byref(loss)))
+    N = int(X.shape[0])
+    _mcheck(m, load().vb_mlp_loss_grad(m, _ptr(X, "float32", N * VB_MLP_FEATURES),
+                                       _ptr(y, "float32", N), N,
+                                       _ptr(g, "float32", VB_MLP_NPARAMS), C.byref(loss)))
     return loss.value
 
 

@@ -96,3 +96,41 @@ def test_bad_options_are_rejected_on_the_host(kw):
     with pytest.raises(binding.VBError) as e:
         binding.vb_create(**kw)
     assert e.value.code == -1
+
+
+def test_binding_refuses_host_mistyped_or_short_tensors():
+    """Device arguments are checked before the library is called: a host
+    tensor, a wrong element type or a short vector raises instead of
+    handing the kernels a bad address.  A stand-in object plays the GPU
+    tensor, so no device is needed."""
+    torch = pytest.importorskip("torch")
+    from paper_2304_09770_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        from paper_2304_09770_amd.build import build
+        build()
+
+    class OnGpu:
+        is_cuda = True
+
+        def __init__(self, dtype, n, contiguous=True):
+            self.dtype, self.n, self.c = dtype, n, contiguous
+
+        def is_contiguous(self):
+            return self.c
+
+        def numel(self):
+            return self.n
+
+        def data_ptr(self):
+            return 4096
+
+    with pytest.raises(ValueError):
+        binding.vb_rhs(None, torch.zeros(4, dtype=torch.float64))  # host memory
+    with pytest.raises(TypeError):
+        binding._ptr(OnGpu(torch.float32, 10), "float64")
+    with pytest.raises(ValueError):
+        binding._ptr(OnGpu(torch.float64, 3), "float64", 10)
+    with pytest.raises(ValueError):
+        binding._ptr(OnGpu(torch.float64, 10, contiguous=False), "float64")
+    assert binding._ptr(OnGpu(torch.float64, 10), "float64", 10) == 4096
+    assert binding._ptr(12288) == 12288 and binding._ptr(None) is None
