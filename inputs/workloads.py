@@ -18,6 +18,9 @@ Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3);
 adaptive cases: t6f (6^3 jittered, 3x3x3: a floating centre subdomain),
 t8f (8^3 jittered, 4x4x4: faces between two floating subdomains),
 t12s (12^3, 3x3x3, 4 sinkers of radius 0.25 with nu=1e4).
+The paper's optimality tables (32 subdomains as 4x4x2 boxes, minimal
+constraints): deg2, deg3, deg4 (8^3, k = 2, 3, 4: the degree test) and
+mesh16, mesh20, mesh24, mesh28, mesh32 (n^3, k = 2: the mesh test).
 """
 import numpy as np
 
@@ -63,6 +66,10 @@ RECIPES = {
     # C5's shape at 12^3 per problem (a family on one jittered mesh, nu per problem)
     "c5s": dict(n=12, jitter=0.15, k=3, parts=(3, 3, 3), cons=FULL, nu_per_sub=True),
 }
+for _k in (2, 3, 4):
+    RECIPES["deg%d" % _k] = dict(n=8, jitter=0.0, k=_k, parts=(4, 4, 2), cons=MIN)
+for _n in (16, 20, 24, 28, 32):
+    RECIPES["mesh%d" % _n] = dict(n=_n, jitter=0.0, k=2, parts=(4, 4, 2), cons=MIN)
 
 
 def make_workload(name, seed=0, workers=None, progress=None, **over):

@@ -239,3 +239,18 @@ def test_family_member_equals_direct_generation():
         assert np.array_equal(a["indices"], b["indices"])
         assert np.abs(a["data"] - b["data"]).max() <= 1e-13 * np.abs(a["data"]).max()
         assert np.abs(a["rhs"] - b["rhs"]).max() <= 1e-12 * max(np.abs(a["rhs"]).max(), 1e-300)
+
+
+def test_paper_table_recipes():
+    """The deg* and mesh* recipes are the paper's optimality-test rows (the
+    (n, k) of each appears in the printed tables) with 32 subdomains."""
+    from inputs.workloads import RECIPES, make_workload
+    printed = {(n, k) for n, k, _ in _rows()}
+    names = ["deg2", "deg3", "deg4"] + ["mesh%d" % n for n in (16, 20, 24, 28, 32)]
+    for name in names:
+        r = RECIPES[name]
+        assert (r["n"], r["k"]) in printed, name
+        assert np.prod(r["parts"]) == 32
+    wl, meta = make_workload("deg2", workers=1)
+    assert len(wl["subs"]) == 32
+    assert meta["problem"].Nv + meta["problem"].Np == 16787
