@@ -1,6 +1,8 @@
-"""The paper's degree test (Table optDeg1: CUBE 8^3, 32 subdomains, k = 2, 3,
-4) on the CPU oracle: the minimal coarse space, the adaptive one at
-theta = 2 (faces, then faces and edges), and every face coordinate primal.
+"""The paper's optimality tests on the CPU oracle (opt-in, minutes each).
+
+The degree test (Table optDeg1: CUBE 8^3, 32 subdomains, k = 2, 3, 4): the
+minimal coarse space, the adaptive one at theta = 2 (faces, then faces and
+edges), and every face coordinate primal.
 It takes about 12 minutes on 8 cores (the k = 4 adaptive cases dominate), so
 it runs only when VB_DEGREE_STUDY is set:
 
@@ -12,6 +14,9 @@ the DoF counts equal the paper's; kappa_2 of the minimal space grows with k
 (the eigenproblems the paper defines) even fully primal faces leave kappa_2
 above 2, the floor set by the edges, while with the edges' eigenproblems
 too kappa_2 stays flat in k like the paper's (1.81, 1.44, 1.49).
+
+The first row of the mesh test (Table optMesh1: CUBE 16^3, k = 2) runs
+with VB_MESH_STUDY=1.
 """
 import os
 
@@ -24,8 +29,8 @@ from inputs.mesh import CubeMesh
 from oracle.bddc import OracleBDDC
 from oracle.pcg import lanczos_extremes, pcg
 
-pytestmark = pytest.mark.skipif(not os.environ.get("VB_DEGREE_STUDY"),
-                                reason="about 12 minutes of CPU: set VB_DEGREE_STUDY=1")
+_DEGREE = pytest.mark.skipif(not os.environ.get("VB_DEGREE_STUDY"),
+                             reason="about 12 minutes of CPU: set VB_DEGREE_STUDY=1")
 PAPER_NDOFS = {2: 16787, 3: 40667, 4: 76387}
 
 
@@ -38,6 +43,7 @@ def _run(k, theta, edges=False):
     return pb.Nv + pb.Np, o.nc, info["iters"], lmax / lmin
 
 
+@_DEGREE
 def test_degree_study():
     rows = {}
     for k in (2, 3, 4):
@@ -58,3 +64,27 @@ def test_degree_study():
     assert k2min[0] < k2min[1] < k2min[2]
     assert np.all([rows[k][3][3] > 2.0 for k in (2, 4)])
     assert np.all([rows[k][2][3] < 2.5 for k in (2, 3, 4)])
+
+
+@pytest.mark.skipif(not os.environ.get("VB_MESH_STUDY"),
+                    reason="about 17 minutes of CPU: set VB_MESH_STUDY=1")
+def test_mesh_study_first_row():
+    """The first row of the paper's mesh test (Table optMesh1: CUBE 16^3,
+    k = 2, 32 subdomains; the paper: nu_tol = inf 125, 44, 44.67 and
+    nu_tol = 2 2861, 9, 1.59 for N_Pi, it, kappa_2) on the oracle:
+
+        VB_MESH_STUDY=1 python -m pytest tests/test_degree_study.py -s -k mesh
+    """
+    from inputs.workloads import make_workload
+    wl, meta = make_workload("mesh16", workers=min(8, os.cpu_count() or 1))
+    assert meta["problem"].Nv + meta["problem"].Np == 124195
+    out = {}
+    for key, theta, edges in (("minimal", 0.0, False), ("faces", 2.0, False),
+                              ("faces+edges", 2.0, True)):
+        o = OracleBDDC(wl, adaptive_theta=theta, adaptive_edges=edges)
+        _, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-8)
+        lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+        out[key] = (o.nc, info["iters"], lmax / lmin)
+        print("\n%-12s Nc %5d  it %3d  k2 %6.2f" % ((key,) + out[key]), flush=True)
+    assert out["faces+edges"][2] < out["faces"][2] < out["minimal"][2] / 3
+    assert out["faces+edges"][2] < 2.5
