@@ -254,3 +254,37 @@ def test_paper_table_recipes():
     wl, meta = make_workload("deg2", workers=1)
     assert len(wl["subs"]) == 32
     assert meta["problem"].Nv + meta["problem"].Np == 16787
+
+
+@pytest.mark.parametrize("name", ["c1", "t8j", "deg4"])
+def test_workloads_meet_the_assemble_contract(name):
+    """What vb_assemble requires of its input (row pointers rising from 0 to
+    nnz, column indices in range, known DoF kinds, interface ids covered by
+    exactly one entity and held whole by each subdomain, at least two
+    pressures, positive element volumes), checked on the generator's output,
+    k = 4 included."""
+    from inputs.workloads import make_workload
+    wl, _ = make_workload(name, workers=1)
+    n_iface = wl["n_iface"]
+    owner = -np.ones(n_iface, np.int64)
+    for e, E in enumerate(wl["ents"]):
+        g = np.asarray(E["gids"])
+        assert len(g) > 0 and np.all(owner[g] < 0)
+        owner[g] = e
+        con = np.asarray(E["con"])  # n_con x n rows over the entity's DoFs
+        assert con.size == 0 or con.shape[-1] == len(g)
+    assert np.all(owner >= 0)
+    for sd in wl["subs"]:
+        n = len(sd["kind"])
+        ip = np.asarray(sd["indptr"])
+        assert ip[0] == 0 and ip[-1] == len(sd["indices"]) and np.all(np.diff(ip) >= 0)
+        ix = np.asarray(sd["indices"])
+        assert ix.min() >= 0 and ix.max() < n
+        kind = np.asarray(sd["kind"])
+        assert set(np.unique(kind)) <= {0, 1, 2} and np.sum(kind == 2) >= 2
+        pw = np.asarray(sd["pweight"])[kind == 2]
+        assert np.all(np.isfinite(pw)) and np.all(pw > 0)
+        gid = np.asarray(sd["gid"])[kind == 1]
+        assert gid.min() >= 0 and gid.max() < n_iface
+        for e in np.unique(owner[gid]):  # every entity it touches, whole
+            assert np.sum(owner[gid] == e) == len(wl["ents"][e]["gids"])
