@@ -181,6 +181,17 @@ def test_pcg_matches_direct_solve(tiny_jit):
     assert np.linalg.norm(x - ref) < 1e-10 * np.linalg.norm(ref)
 
 
+def test_pcg_matches_direct_solve_degree_4():
+    """The whole oracle pipeline at k = 4 (decomposition, condensation,
+    BDDC, PCG) against the direct solve of the assembled global system."""
+    pb, dec, o = _setup(4, (2, 2, 2), FULL, jitter=0.15, seed=4, k=4)
+    x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-12)
+    u = pb.solve_reduced_direct()
+    uG, p0 = dec.interface_solution(u)
+    ref = np.concatenate([uG, p0])
+    assert np.linalg.norm(x - ref) < 1e-9 * np.linalg.norm(ref)
+
+
 def test_all_primal_converges_in_one_iteration():
     pb = Problem(CubeMesh(4), 2, 1.0, workers=1)
     dec = Decomposition(pb, regular_cuts(4, (2, 2, 2)), MIN)
