@@ -204,15 +204,20 @@ def test_all_primal_converges_in_one_iteration():
 
 
 def _benign_spectrum(o):
-    """Nonzero eigenvalues of M^-1 S_hat (dense, tiny problems)."""
+    """Nonzero eigenvalues of M^-1 S_hat on the benign space (dense, tiny
+    problems).  With r's p0 part zero, M^-1 r has zero net flux out of every
+    subdomain (the coarse problem imposes it), so CG stays in
+    V_B = {(u, p0): B0^(i) u = 0 for all i}; M^-1 S_hat maps V_B into itself
+    and is self-adjoint in the S_hat form there.  The eigenvalues come from
+    the restriction V^T M^-1 S_hat V, V an orthonormal basis of V_B, with the
+    constant-p0 kernel (eigenvalue 0) dropped."""
     n = o.n
     M = np.array([o.apply_M(e) for e in np.eye(n)]).T
     S = o.dense_S()
-    # nonzero spectrum of M S = spectrum of the symmetric S^1/2 M S^1/2
-    es, V = np.linalg.eigh(S)
-    Sh = (V * np.sqrt(np.maximum(es, 0.0))) @ V.T
-    Ms = 0.5 * (M + M.T)
-    ev = np.linalg.eigvalsh(Sh @ Ms @ Sh)
+    V = sla.null_space(S[o.nG:, :])
+    ev = sla.eigvals(V.T @ M @ S @ V)
+    assert np.abs(ev.imag).max() < 1e-9 * np.abs(ev).max()
+    ev = np.sort(ev.real)
     return ev[np.abs(ev) > 1e-8]
 
 
@@ -227,8 +232,8 @@ def test_min_eigenvalue_is_one_dense(tiny):
 def test_min_eigenvalue_bound_degree_4():
     """Theorem teoEst at VEM degree 4 (jittered mesh, 2^3 elements per
     subdomain, vertex + edge + face constraints): every nonzero eigenvalue
-    of M^-1 S_hat is >= 1, and the smallest lies just above 1 (1 + 1.0e-7
-    here; the rounding of the dense product is about 1e-10)."""
+    of M^-1 S_hat on the benign space is >= 1, and the smallest is 1 (the
+    rounding of the dense restriction is about 1e-13)."""
     nz = _benign_spectrum(_setup(4, (2, 2, 2), FULL, jitter=0.15, seed=4, k=4)[2])
     assert 1 - 1e-10 < nz.min() < 1 + 1e-6
 
@@ -254,3 +259,64 @@ def test_counting_scaling_converges_to_same_solution():
     xc, ic = pcg(oc.apply_S, oc.apply_M, g, tol=1e-8)
     assert ic["iters"] < 200
     assert np.linalg.norm(xd - xc) < 1e-6 * np.linalg.norm(xd)
+
+
+@pytest.mark.parametrize("k", [2, 4])
+def test_recover_matches_direct_solve(k):
+    """Interior recovery (eq. uipi, Sec. 4.2): given the interface velocity
+    and p0 of the direct solve of the assembled reduced system, every
+    subdomain's recovered interior velocity and element pressures equal the
+    direct solve's.  A wrong sign on the C u_Gamma term or a dropped p0
+    fails it."""
+    pb, dec, o = _setup(4, (2, 2, 2), FULL, jitter=0.15, seed=5, k=k)
+    u = pb.solve_reduced_direct()
+    uG, p0 = dec.interface_solution(u)
+    rec = o.recover(np.concatenate([uG, p0]))
+    for sd, (uI, c) in zip(dec.subs, rec):
+        ref_u = u[sd.dofs[sd.kind == 0]]
+        ref_p = u[sd.dofs[sd.kind == 2]]
+        assert np.linalg.norm(uI - ref_u) <= 1e-10 * np.linalg.norm(ref_u)
+        # the pressures are O(h^k) here (the manufactured p is 0), so they are
+        # compared on the scale of the local solution
+        assert np.linalg.norm(c - ref_p) <= 1e-9 * np.linalg.norm(ref_u)
+
+
+def test_lanczos_extremes_closed_form():
+    """Lanczos from the CG coefficients (Sec. 5, the estimate behind Theorem
+    teoEst's condition numbers): for A = diag(d) and M^-1 = diag(m) with
+    distinct products d*m and a right-hand side that excites every
+    eigenvector, CG terminates after n steps and the tridiagonal matrix
+    built from its alphas and betas is similar to M^-1 A, so its extreme
+    eigenvalues are min(d*m) and max(d*m).  A wrong diagonal or off-diagonal
+    entry of T moves them."""
+    rng = np.random.default_rng(2)
+    for n in (2, 3, 6, 9):
+        d = rng.uniform(0.5, 20.0, n)
+        m = rng.uniform(0.2, 3.0, n)
+        b = rng.uniform(0.5, 1.5, n)
+        x, info = pcg(lambda v: d * v, lambda v: m * v, b, fixed_iters=n)
+        lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+        dm = d * m
+        assert abs(lmin - dm.min()) < 1e-10 * dm.max()
+        assert abs(lmax - dm.max()) < 1e-10 * dm.max()
+
+
+def test_lanczos_extremes_match_dense_spectrum(tiny_jit):
+    """On the BDDC-preconditioned interface operator: CG from a random
+    right-hand side with zero p0 part (so it stays in the benign space) to a
+    1e-12 residual.  The largest eigenvalue of its Lanczos matrix equals the
+    largest of the dense benign spectrum to 1e-8 (an isolated extreme
+    eigenvalue converges first), and the smallest lies in that spectrum's
+    range: above lambda_min = 1 (Theorem teoEst) and within 1% of it (the
+    eigenvalue-1 cluster of the coarse space is not resolved one by one
+    before the residual converges)."""
+    o = tiny_jit[2]
+    nz = _benign_spectrum(o)
+    rng = np.random.default_rng(11)
+    b = rng.standard_normal(o.n)
+    b[o.nG:] = 0.0
+    x, info = pcg(o.apply_S, o.apply_M, b, tol=1e-12, maxit=400)
+    lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+    assert abs(lmax - nz.max()) < 1e-8 * nz.max()
+    assert nz.min() - 1e-10 <= lmin <= 1.01 * nz.min()
+    assert abs(nz.min() - 1.0) < 1e-10
