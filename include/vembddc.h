@@ -255,6 +255,12 @@ int vb_pcg_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info);
  * once instead. */
 int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_host);
 
+/* Number of local DoFs of subdomain `sub` (the n of its vb_subdomain: the
+ * length vb_get_local_solution writes), or with sub = -1 their sum over all
+ * subdomains of all problems (the length vb_recover_all writes to out_dev).
+ * VB_ERR_ARG before vb_assemble or for sub outside -1..n_sub-1. */
+int64_t vb_local_size(const vb_ctx *ctx, int sub);
+
 /* Interior recovery for every subdomain at once: out_dev (device, may be
  * NULL to only refresh the internal copy) receives the concatenation over
  * subdomains of their local DoF vectors, each in its own CSR DoF order.
@@ -287,7 +293,12 @@ int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_ei
 #define VB_MLP_FEATURES 12
 #define VB_MLP_NPARAMS 1505
 typedef struct vb_mlp vb_mlp;
-/* init: VB_MLP_NPARAMS host floats (copied); stream: hipStream_t or NULL. */
+/* init: VB_MLP_NPARAMS host floats (copied).  stream: the hipStream_t every
+ * call of the model runs on, in order after the caller's earlier work on it;
+ * NULL = the default stream (training then drains the default stream and
+ * runs its captured epochs on a stream of the model's own, since the default
+ * stream cannot be captured).  Inside vb_setup the predictor runs on the
+ * context's stream: the model must not be trained concurrently. */
 int vb_mlp_create(vb_mlp **m, const float *init, void *stream);
 void vb_mlp_destroy(vb_mlp *m);
 const char *vb_mlp_last_error(const vb_mlp *m);
@@ -330,6 +341,12 @@ int vb_mlp_add_data(vb_mlp *m, const float *X_host, const float *y_host, int64_t
  * which = 1 the bordered local Schur GEMV of S_hat p (the iteration's
  * dominant kernel, work in bytes read/written).  reset != 0 clears them. */
 int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out);
+
+/* Switch the per-launch timing of vb_options.profile on (nonzero) or off for
+ * the calls that follow.  While it is on, the PCG iteration runs launch by
+ * launch instead of as a replayed HIP graph, and every timed launch is
+ * bracketed by two events. */
+int vb_set_profile(vb_ctx *ctx, int on);
 
 /* Batched dense partial signed LDL^T (the kernel under the Dirichlet and
  * Neumann solves).  For each of `batch` column-major matrices A_b (size n_b,

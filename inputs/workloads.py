@@ -14,7 +14,9 @@ data the hot path consumes plus the generator objects (for tests).
       (centres uniform, seed 0), 4x4x4 subdomains
   c5  one of 32 problems: 24^3, plane jitter 0.15h, k=3, 3x3x3 subdomains,
       nu constant per subdomain, log-uniform in [1e-3, 1e3] (seed p)
-Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3);
+Small parity cases: t8j (8^3 jittered, full constraints), t12 (12^3, 3x3x3),
+t12u (12^3, uneven cuts of 2..6 elements), t12b (12^3, 2x2x2: about 3,000
+eliminated columns per subdomain), t8k3 (8^3, k=3), t6k4 (6^3, k=4);
 adaptive cases: t6f (6^3 jittered, 3x3x3: a floating centre subdomain),
 t8f (8^3 jittered, 4x4x4: faces between two floating subdomains),
 t12s (12^3, 3x3x3, 4 sinkers of radius 0.25 with nu=1e4).
@@ -58,6 +60,14 @@ RECIPES = {
     "t8j": dict(n=8, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
     "t12": dict(n=12, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),
     "t16": dict(n=16, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
+    # parity cases for the shapes of the larger configurations: uneven cuts
+    # (2..6 elements per side), subdomains of 6^3 elements (about 3,000
+    # eliminated columns each: several super-panels of the factorisation),
+    # degrees 3 and 4
+    "t12u": dict(n=12, jitter=0.15, k=2, random_cuts=(2, 6, 3), cons=FULL),
+    "t12b": dict(n=12, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
+    "t8k3": dict(n=8, jitter=0.15, k=3, parts=(2, 2, 2), cons=FULL),
+    "t6k4": dict(n=6, jitter=0.15, k=4, parts=(2, 2, 2), cons=FULL),
     "t6f": dict(n=6, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),
     "t8f": dict(n=8, jitter=0.15, k=2, parts=(4, 4, 4), cons=FULL),
     "t12s": dict(n=12, jitter=0.0, k=2, parts=(3, 3, 3), cons=FULL, sinkers=True,

@@ -96,6 +96,8 @@ def load():
         "vb_pcg_solve": (C.c_int, [P, P, C.POINTER(vb_solve_info)]),
         "vb_get_local_solution": (C.c_int, [P, P, C.c_int, C.POINTER(C.c_double)]),
         "vb_recover_all": (C.c_int, [P, P, P]),
+        "vb_local_size": (C.c_int64, [P, C.c_int]),
+        "vb_set_profile": (C.c_int, [P, C.c_int]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
         "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
@@ -136,7 +138,7 @@ def exported_symbols():
             "vb_mlp_last_error", "vb_mlp_add_samples", "vb_mlp_num_samples", "vb_mlp_train",
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
-            "vb_problem_solve_info", "vb_tuned_tile"]
+            "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile"]
 
 
 class VBError(RuntimeError):
@@ -254,8 +256,20 @@ def vb_pcg_solve(ctx, x, raise_on_error=True):
     return info.as_dict()
 
 
-def vb_get_local_solution(ctx, x, sub, n):
-    out = np.zeros(n)
+def vb_local_size(ctx, sub=-1):
+    """Local DoFs of subdomain `sub`, or (sub = -1) of all subdomains."""
+    n = int(load().vb_local_size(ctx, int(sub)))
+    _check(ctx, n if n < 0 else 0)
+    return n
+
+
+def vb_get_local_solution(ctx, x, sub, n=None):
+    """Subdomain `sub`'s local DoF vector (host).  The buffer is sized by the
+    library (vb_local_size); `n`, if given, must equal that size."""
+    m = vb_local_size(ctx, sub)
+    if n is not None and int(n) != m:
+        raise ValueError("subdomain %d has %d local DoFs, not %d" % (sub, m, n))
+    out = np.zeros(m)
     rc = load().vb_get_local_solution(ctx, _vec(ctx, x), int(sub),
                                       out.ctypes.data_as(C.POINTER(C.c_double)))
     _check(ctx, rc)
@@ -263,7 +277,10 @@ def vb_get_local_solution(ctx, x, sub, n):
 
 
 def vb_recover_all(ctx, x, out):
-    _check(ctx, load().vb_recover_all(ctx, _vec(ctx, x), _ptr(out, "float64")))
+    """out: None, or a float64 device tensor of at least vb_local_size(ctx)
+    elements."""
+    n = vb_local_size(ctx) if out is not None else None
+    _check(ctx, load().vb_recover_all(ctx, _vec(ctx, x), _ptr(out, "float64", n)))
 
 
 def vb_batched_ldl(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
@@ -278,6 +295,10 @@ def vb_kernel_stats(ctx, which, reset=False):
     st = vb_kernel_stat()
     _check(ctx, load().vb_kernel_stats(ctx, int(which), int(bool(reset)), C.byref(st)))
     return {"launches": st.launches, "total_ms": st.total_ms, "work": st.work}
+
+
+def vb_set_profile(ctx, on):
+    _check(ctx, load().vb_set_profile(ctx, int(bool(on))))
 
 
 def vb_adaptive_info(ctx):

@@ -373,8 +373,9 @@ struct vb_ctx {
 };
 
 struct vb_mlp {
-  hipStream_t stream = nullptr;
-  bool own_stream = false;
+  hipStream_t stream = nullptr;     // the caller's stream (NULL: the default stream)
+  hipStream_t cap_stream = nullptr; // training's own stream when `stream` is NULL
+  bool own_stream = false;          // cap_stream was created here
   std::string err;
   float *p = nullptr, *m = nullptr, *v = nullptr, *g = nullptr, *mu = nullptr, *sd = nullptr;
   int *t = nullptr;
@@ -2242,6 +2243,26 @@ static int setup_impl(vb_ctx *ctx) {
       gj.push_back({K + ncs + ncs * ldk[pp], ldk[pp], ctx->Gc + goff[pp], ncs, di, di, ncs, ncs,
                     -1.0, 0, 0, 0});
     }
+    // the diagonal of every coarse matrix before and after its factorisation
+    // (one strided copy each): a pivot that cancels to 1e-10 of its column's
+    // own diagonal entry means a singular coarse problem (for instance a
+    // primal space that does not see the face fluxes, Assumption 1), which
+    // rounding may leave with either sign
+    std::vector<int64_t> doff(nP + 1, 0);
+    for (int pp = 0; pp < nP; ++pp) doff[pp + 1] = doff[pp] + ctx->probs[pp].nprim + ctx->probs[pp].ns;
+    std::vector<double> dg0(doff[nP]), dg1(doff[nP]);
+    auto diag_copy = [&](std::vector<double> &out) -> hipError_t {
+      for (int pp = 0; pp < nP; ++pp) {
+        const int64_t ncs = doff[pp + 1] - doff[pp];
+        if (!ncs) continue;
+        hipError_t e = hipMemcpy2DAsync(out.data() + doff[pp], sizeof(double), ctx->Kaug + koff[pp],
+                                        (ldk[pp] + 1) * sizeof(double), sizeof(double), ncs,
+                                        hipMemcpyDeviceToHost, st);
+        if (e != hipSuccess) return e;
+      }
+      return hipSuccess;
+    };
+    CHK(diag_copy(dg0));
     int rc = run_diag(ctx, dj, ctx->max_ncs);
     if (rc) return rc;
     rc = run_ldl(ctx, lj, 2 * ctx->max_ncs, ctx->max_ncs);
@@ -2249,12 +2270,17 @@ static int setup_impl(vb_ctx *ctx) {
     {
       std::vector<int> h(nP);
       CHK(hipMemcpyAsync(h.data(), ctx->info + nS, nP * sizeof(int), hipMemcpyDeviceToHost, st));
+      CHK(diag_copy(dg1));
       CHK(hipStreamSynchronize(st));
-      for (int pp = 0; pp < nP; ++pp)
-        if (h[pp])
+      for (int pp = 0; pp < nP; ++pp) {
+        int bad = h[pp] ? h[pp] - 1 : -1;
+        for (int64_t j = doff[pp]; bad < 0 && j < doff[pp + 1]; ++j)
+          if (!(dg1[j] * dg1[j] > 1e-10 * std::fabs(dg0[j]))) bad = (int)(j - doff[pp]);
+        if (bad >= 0)
           return ctx->fail(VB_ERR_SINGULAR_COARSE, "coarse factorisation of problem " +
                                                        std::to_string(pp) + ": pivot breakdown at column " +
-                                                       std::to_string(h[pp] - 1));
+                                                       std::to_string(bad));
+      }
     }
     rc = run_symm(ctx, m, ld, n);
     if (rc) return rc;
@@ -3167,6 +3193,14 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
   return VB_OK;
 }
 
+int64_t vb_local_size(const vb_ctx *ctx, int sub) {
+  if (!ctx || ctx->state < 1 || sub < -1 || sub >= ctx->nS) return VB_ERR_ARG;
+  if (sub >= 0) return ctx->subs[sub].n;
+  int64_t tot = 0;
+  for (const auto &S : ctx->subs) tot += S.n;
+  return tot;
+}
+
 int vb_get_local_solution(vb_ctx *ctx, const double *x_dev, int sub, double *u_host) {
   if (!ctx || !x_dev || !u_host || sub < 0 || sub >= ctx->nS) return VB_ERR_ARG;
   int rc = vb_recover_all(ctx, x_dev, nullptr);
@@ -3198,13 +3232,22 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
   double *scratch = nullptr;
   CHK(hipMalloc(&scratch, std::max<int64_t>(per * batch, 1) * sizeof(double)));
   std::vector<LdlJob<double>> jobs(batch);
-  for (int b = 0; b < batch; ++b)
+  // 16-byte aligned columns everywhere: the trailing updates load their
+  // panel strips straight into LDS (the kernels the library's own
+  // factorisations use); otherwise the staged kernels
+  bool aligned16 = true;
+  for (int b = 0; b < batch; ++b) {
     jobs[b] = {hA[b], hld[b], hn[b], he[b], hp[b], 0, scratch + per * b, info + b};
+    aligned16 = aligned16 && hld[b] >= 2 && (hld[b] * sizeof(double)) % 16 == 0 &&
+                reinterpret_cast<uintptr_t>(hA[b]) % 16 == 0;
+  }
   LdlJob<double> *dj = nullptr;
   hipError_t err = hipMalloc(&dj, batch * sizeof(LdlJob<double>));
   if (err == hipSuccess) err = hipMemcpy(dj, jobs.data(), batch * sizeof(LdlJob<double>), hipMemcpyHostToDevice);
   if (err == hipSuccess) err = hipMemsetAsync(info, 0, batch * sizeof(int32_t), st);
-  if (err == hipSuccess) err = ldl_batched<double>(dj, batch, max_n, max_e, ctx->opt.panel, st);
+  if (err == hipSuccess)
+    err = ldl_batched<double>(dj, batch, max_n, max_e, ctx->opt.panel, st, nullptr, &hn, &he, false,
+                              aligned16);
   if (err == hipSuccess) err = hipStreamSynchronize(st);
   (void)hipFree(dj);
   (void)hipFree(scratch);
@@ -3252,6 +3295,12 @@ int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_ei
   return nf;
 }
 
+int vb_set_profile(vb_ctx *ctx, int on) {
+  if (!ctx) return VB_ERR_ARG;
+  ctx->opt.profile = on ? 1 : 0;
+  return VB_OK;
+}
+
 int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out) {
   if (!ctx || !out || which < 0 || which > 1) return VB_ERR_ARG;
   KTimer &t = which == 0 ? ctx->t_ldl : ctx->t_gemv;
@@ -3287,12 +3336,9 @@ int vb_mlp_create(vb_mlp **out, const float *init, void *stream) {
   if (!out || !init) return VB_ERR_ARG;
   vb_mlp *m = new vb_mlp();
   *out = m;
-  if (stream) {
-    m->stream = (hipStream_t)stream;
-  } else {
-    MCHK(hipStreamCreateWithFlags(&m->stream, hipStreamNonBlocking));
-    m->own_stream = true;
-  }
+  // NULL = the default stream, as for vb_options.stream: every launch of the
+  // model is then ordered after the caller's work on that stream
+  m->stream = (hipStream_t)stream;
   const size_t P = MLP_NPARAMS * sizeof(float);
   MCHK(hipMalloc(&m->p, P));
   MCHK(hipMalloc(&m->m, P));
@@ -3311,11 +3357,12 @@ int vb_mlp_create(vb_mlp **out, const float *init, void *stream) {
 
 void vb_mlp_destroy(vb_mlp *m) {
   if (!m) return;
-  if (m->stream) (void)hipStreamSynchronize(m->stream);
+  (void)hipStreamSynchronize(m->stream);
+  if (m->cap_stream) (void)hipStreamSynchronize(m->cap_stream);
   for (void *q : {(void *)m->p, (void *)m->m, (void *)m->v, (void *)m->g, (void *)m->mu,
                   (void *)m->sd, (void *)m->t, (void *)m->loss, (void *)m->X, (void *)m->y})
     if (q) (void)hipFree(q);
-  if (m->own_stream) (void)hipStreamDestroy(m->stream);
+  if (m->own_stream) (void)hipStreamDestroy(m->cap_stream);
   delete m;
 }
 
@@ -3389,7 +3436,18 @@ int vb_mlp_add_samples(vb_mlp *m, vb_ctx *ctx) {
 int vb_mlp_train(vb_mlp *m, int epochs, float lr, double *loss_history) {
   if (!m || epochs < 0 || !(lr > 0.0f)) return VB_ERR_ARG;
   if (m->n <= 0) return m->fail(VB_ERR_STATE, "vb_mlp_train: no samples");
+  // the epoch is captured as a HIP graph, which the default stream cannot
+  // hold: with it, training runs on a stream of its own after the default
+  // stream has drained
   hipStream_t st = m->stream;
+  if (!st) {
+    MCHK(hipStreamSynchronize(nullptr));
+    if (!m->own_stream) {
+      MCHK(hipStreamCreateWithFlags(&m->cap_stream, hipStreamNonBlocking));
+      m->own_stream = true;
+    }
+    st = m->cap_stream;
+  }
   const int nblk = (int)((m->n + 63) / 64);
   float *partial = nullptr;
   double *lpart = nullptr, *hist = nullptr;

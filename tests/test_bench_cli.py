@@ -60,3 +60,15 @@ def test_setup_flops_report_on_a_small_workload():
     rep = b.setup_flops(wl, [b.sparse_lu_flops(lu)], 10.0)
     assert 0 < rep["sparse_factor_est"] < rep["dense_executed"]
     assert rep["dense_tflops_per_setup_s"] == rep["dense_executed"] / 1e-2 / 1e12
+
+
+def test_cpu_baseline_sample_and_full_oracle_on_c1():
+    from inputs.workloads import make_workload
+    b = _bench()
+    wl, _ = make_workload("c1", workers=1)
+    rep = b.cpu_baseline(wl, budget_s=0.0)  # the bound still takes one subdomain
+    assert rep["kind"] == "oracle" and rep["value"] > 0 and rep["cores"] >= 1
+    assert "1 of 8 subdomains" in rep["sample"]
+    full = b.oracle_full_c1()
+    assert full["iterations"] > 0 and full["solves_per_s"] > 0
+    assert full["setup_s"] > 0 and full["pcg_s"] > 0 and full["recovery_s"] > 0

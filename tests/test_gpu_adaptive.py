@@ -8,7 +8,16 @@ evaluations inside the oracle itself (pseudo-inverses vs exact solves)
 already differ by 1.7e-9.  The new
 primal space is compared through what depends on it only: M^-1 r and the
 PCG iterates (the bases differ: Householder QR on the GPU, SVD in the
-oracle)."""
+oracle).
+
+At that contrast the eigenvectors of the rigid-mode cluster (eigenvalues
+that are 0 up to FP64 noise) are fixed only up to rotations within the
+cluster, so the GPU's own adaptive rows and the oracle's may span slightly
+different spaces.  There the preconditioner and the iterates are compared
+on a tie-free context instead: a non-adaptive GPU context whose entity
+constraints are the given rows plus the oracle's adaptive rows (the same
+primal space by construction), against the oracle's adaptive M^-1 r and
+PCG iterates to 1e-10."""
 import numpy as np
 import pytest
 
@@ -89,10 +98,37 @@ def test_face_selection_parity(vb, acase):
     assert total > 0
 
 
-def test_adaptive_preconditioner_parity(vb, acase):
+def _with_oracle_rows(wl, o):
+    """The workload with the oracle's adaptive rows (original coordinates of
+    each entity's DoFs) appended to its entities' constraint blocks."""
+    ents = []
+    for e, E in enumerate(wl["ents"]):
+        con = np.asarray(E["con"], dtype=np.float64).reshape(-1, len(E["gids"]))
+        if o.extra_rows[e] is not None:
+            con = np.vstack([con, o.extra_rows[e]])
+        ents.append(dict(E, con=con))
+    return dict(wl, ents=ents)
+
+
+@pytest.fixture(scope="module")
+def operator_ctx(vb, acase):
+    """The context whose M^-1 is compared with the oracle's: the adaptive
+    context itself on the strict cases, the tie-free one on t12s."""
     name, wl, meta, o, ctx = acase
-    if name not in STRICT:
-        pytest.skip("cluster span fixed only to noise/gap at this contrast; see module doc")
+    if name in STRICT:
+        yield ctx
+        return
+    c = vb.vb_create(tol=1e-8)
+    vb.vb_assemble(c, _with_oracle_rows(wl, o))
+    vb.vb_setup(c)
+    yield c
+    vb.vb_destroy(c)
+
+
+def test_adaptive_preconditioner_parity(vb, acase, operator_ctx):
+    name, wl, meta, o, _ = acase
+    ctx = operator_ctx
+    tol = 1e-9 if name in STRICT else 1e-10
     n = vb.vb_interface_size(ctx)
     rng = np.random.default_rng(5)
     r = o.apply_S(rng.standard_normal(n))
@@ -102,24 +138,27 @@ def test_adaptive_preconditioner_parity(vb, acase):
     zo = o.apply_M(r)
     zg = z.cpu().numpy()
     nG = o.nG
-    assert _rel(zg[:nG], zo[:nG]) < 1e-9
+    assert _rel(zg[:nG], zo[:nG]) < tol, _rel(zg[:nG], zo[:nG])
     dp = (zg[nG:] - zg[nG:].mean()) - (zo[nG:] - zo[nG:].mean())
-    assert np.linalg.norm(dp) < 1e-9 * np.linalg.norm(zo)
+    assert np.linalg.norm(dp) < tol * np.linalg.norm(zo)
 
 
-def test_adaptive_pcg_parity(vb, acase):
-    name, wl, meta, o, ctx = acase
-    if name not in STRICT:
-        pytest.skip("cluster span fixed only to noise/gap at this contrast; see module doc")
+def test_adaptive_pcg_parity(vb, acase, operator_ctx):
+    name, wl, meta, o, _ = acase
+    ctx = operator_ctx
+    tol = 1e-9 if name in STRICT else 1e-10
     n = vb.vb_interface_size(ctx)
     x = torch.zeros(n, dtype=torch.float64, device=DEV)
     info = vb.vb_pcg_solve(ctx, x)
     torch.cuda.synchronize()
     K = info["iterations"]
     xo, oi = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=K)
-    assert _rel(x.cpu().numpy(), xo) < 1e-9
+    assert _rel(x.cpu().numpy(), xo) < tol, (K, _rel(x.cpu().numpy(), xo))
     assert info["lambda_min"] > 1 - 1e-6
-    assert info["lambda_max"] / info["lambda_min"] < 2 * THETA
+    lmin, lmax = lanczos_extremes(oi["alphas"], oi["betas"])
+    assert abs(info["lambda_max"] / info["lambda_min"] - lmax / lmin) <= 1e-6 * lmax / lmin
+    if name in STRICT:
+        assert info["lambda_max"] / info["lambda_min"] < 2 * THETA
 
 
 def test_adaptive_contrast_solution(vb, acase):

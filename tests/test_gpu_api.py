@@ -15,8 +15,10 @@
   multiplicity-based averaging) against the oracle with the same scaling;
 * bad input data map to error codes (every kernel still runs to its end):
   a local velocity block that is not positive definite makes vb_setup return
-  VB_ERR_NOT_SPD naming the subdomain, and a NaN in a right-hand side makes
-  vb_pcg_solve return VB_ERR_BREAKDOWN; inconsistent CSR row pointers or a
+  VB_ERR_NOT_SPD naming the subdomain, a primal space without the face
+  fluxes makes it return VB_ERR_SINGULAR_COARSE, and a NaN in a right-hand
+  side makes vb_pcg_solve return VB_ERR_BREAKDOWN; inconsistent CSR row
+  pointers or a
   zero element volume make vb_assemble return VB_ERR_ARG and leave the
   context as it was.
 """
@@ -32,6 +34,7 @@ from oracle.pcg import pcg
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
 VB_ERR_ARG, VB_ERR_STATE, VB_ERR_NOT_SPD, VB_ERR_BREAKDOWN, VB_ERR_NOT_CONVERGED = -1, -2, -5, -7, -8
+VB_ERR_SINGULAR_COARSE = -6
 
 
 @pytest.fixture(scope="module")
@@ -166,6 +169,29 @@ def test_non_spd_local_block_is_reported(vb, c1):
             vb.vb_setup(ctx)
         assert e.value.code == VB_ERR_NOT_SPD
         assert "block 3 " in str(e.value)
+    finally:
+        vb.vb_destroy(ctx)
+
+
+def test_primal_space_without_fluxes_gives_singular_coarse(vb, c1):
+    """Without the face flux constraints (Assumption 1: the flux of every
+    face must be a primal functional) the coarse problem has no flux rows,
+    the p0 block of the bordered coarse matrix keeps rank one, and its
+    factorisation must stop with VB_ERR_SINGULAR_COARSE."""
+    bad = _copy(c1)
+    ents = []
+    for E in bad["ents"]:
+        if E["kind"] == 2:  # faces: c1's only face row is the flux
+            E = dict(E, con=np.zeros((0, len(E["gids"]))))
+        ents.append(E)
+    bad["ents"] = ents
+    ctx = vb.vb_create()
+    try:
+        vb.vb_assemble(ctx, bad)
+        with pytest.raises(vb.VBError) as e:
+            vb.vb_setup(ctx)
+        assert e.value.code == VB_ERR_SINGULAR_COARSE, str(e.value)
+        assert "coarse factorisation of problem 0" in str(e.value)
     finally:
         vb.vb_destroy(ctx)
 

@@ -168,6 +168,45 @@ def test_mixed_batched_reaches_fp64(vb, wls):
         vb.vb_destroy(ctx)
 
 
+@pytest.fixture(scope="module")
+def oracles(wls):
+    from oracle.bddc import OracleBDDC
+    return [OracleBDDC(wl) for wl in wls]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_batched_graph_path_matches_oracle(vb, wls, oracles, precision):
+    """Every problem of a batched context, solved on a stream of its own
+    (the PCG iteration replayed as a HIP graph), against the oracle:
+    FP64: the iterate after the problem's own iteration count equals the
+    oracle's iterate after as many iterations (1e-10); mixed: the refined
+    solution equals the oracle's solution to 1e-13 (1e-10)."""
+    from oracle.pcg import pcg
+    stream = torch.cuda.Stream(device=DEV)
+    tol = 1e-8 if precision == 0 else 1e-12
+    ctx = vb.vb_create(precision=precision, tol=tol, stream=stream.cuda_stream)
+    try:
+        for wl in wls:
+            vb.vb_assemble(ctx, wl)
+        with torch.cuda.stream(stream):
+            vb.vb_setup(ctx)
+            n = vb.vb_interface_size(ctx)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_pcg_solve(ctx, x)
+            stream.synchronize()
+        xg = x.cpu().numpy()
+        for k, o in enumerate(oracles):
+            pi = vb.vb_problem_solve_info(ctx, k)
+            xk = _split(vb, ctx, xg, k)
+            if precision == 0:
+                xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=pi["iterations"])
+            else:
+                xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
+            assert _rel(xk, xo) < 1e-10, (k, precision, _rel(xk, xo))
+    finally:
+        vb.vb_destroy(ctx)
+
+
 @pytest.mark.parametrize("precision", [0, 1])
 def test_neumann_waves_match_one_wave(vb, wls, precision):
     wl = wls[2]

@@ -36,9 +36,14 @@ def _dev(a):
     return torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=DEV)
 
 
-def test_batched_ldl_schur_matches_definition(vb):
+@pytest.mark.parametrize("aligned", [False, True])
+def test_batched_ldl_schur_matches_definition(vb, aligned):
     """Partial signed LDL^T: trailing block = A22 - A21 A11^-1 A21^T, with
-    A11 a saddle matrix [[SPD, B^T], [B, 0]] (velocity pivots +, pressure -)."""
+    A11 a saddle matrix [[SPD, B^T], [B, 0]] (velocity pivots +, pressure -).
+    aligned: leading dimensions rounded up to 32 (16-byte aligned columns,
+    as the library lays out its own matrices), so the trailing updates load
+    their panel strips straight into LDS; otherwise n + 3 (the staged
+    kernels)."""
     rng = np.random.default_rng(0)
     # small cases, and cases whose elimination crosses the boundaries of the
     # inner (256) and outer (1024) super-panels of the blocked factorisation
@@ -49,7 +54,7 @@ def test_batched_ldl_schur_matches_definition(vb):
         Q = rng.standard_normal((n, n))
         A = Q @ Q.T / n + np.eye(n)
         A[p:e, p:e] = 0.0  # saddle: zero pressure block, B rows full rank
-        ld = n + 3
+        ld = (n + 31) // 32 * 32 if aligned else n + 3
         M = np.zeros((ld, n))
         M[:n, :n] = A
         t = _dev(M.T.copy())  # column-major storage: row-major transpose
@@ -107,8 +112,18 @@ def _problem(name):
     return _PROBLEMS[name]
 
 
-@pytest.fixture(scope="module", params=["c1", "t8j", "t12"])
+# c1, t8j, t12: tiles and ragged panels, 2/4/8-way sharing; t12u: uneven
+# cuts (2..6 elements per side, the shape of the 216-subdomain workload);
+# t12b: about 3,560 eliminated columns per subdomain (several outer
+# super-panels of the factorisation on 16-byte aligned matrices); t8k3,
+# t6k4: degrees 3 and 4
+FP64_CASES = ["c1", "t8j", "t12", "t12u", "t12b", "t8k3", "t6k4"]
+MIXED_CASES = ["c1", "t8j", "t12", "t12u", "t8k3", "t6k4"]
+
+
+@pytest.fixture(scope="module", params=FP64_CASES)
 def case(request, vb):
+    print("fp64 case", request.param, flush=True)
     wl, meta, o = _problem(request.param)
     ctx = vb.vb_create(tol=1e-8)
     vb.vb_assemble(ctx, wl)
@@ -201,8 +216,9 @@ def test_interior_recovery_parity(vb, case):
 # sparse local systems, so the tolerance is the FP64 path's (1e-10 relative
 # against the oracle solved to 1e-13), not an FP32 one.
 
-@pytest.fixture(scope="module", params=["c1", "t8j", "t12"])
+@pytest.fixture(scope="module", params=MIXED_CASES)
 def mixed_case(request, vb):
+    print("mixed case", request.param, flush=True)
     wl, meta, o = _problem(request.param)
     ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12)
     vb.vb_assemble(ctx, wl)
