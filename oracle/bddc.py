@@ -36,14 +36,28 @@ from scipy.sparse.linalg import splu
 KIND_INTERIOR, KIND_INTERFACE, KIND_PRESSURE = 0, 1, 2
 
 
+class _DenseLU:
+    """Dense LU (LAPACK, partial pivoting) with the splu solve interface."""
+
+    def __init__(self, K):
+        self.f = sla.lu_factor(K.toarray())
+
+    def solve(self, b):
+        return sla.lu_solve(self.f, b)
+
+
 class LocalSchur:
     """Static condensation of one subdomain (eqs. uipi, firstSchur).
 
     condense=False keeps only the factorisation of the Dirichlet problem
     (enough for recover), without forming S_Gamma^(i) and g.
+    dense=True factors the Dirichlet matrix with a dense LU instead of the
+    sparse one: a second FP64 evaluation of the same formulas, which
+    measures how far rounding alone moves the results on ill-conditioned
+    problems.
     """
 
-    def __init__(self, sd, condense=True):
+    def __init__(self, sd, condense=True, dense=False):
         n = len(sd["kind"])
         K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(n, n))
         kind = sd["kind"]
@@ -63,7 +77,7 @@ class LocalSchur:
         Kii = sp.bmat([[A_II, Bp_I.T, None],
                        [Bp_I, None, sp.csr_matrix(w[:, None])],
                        [None, sp.csr_matrix(w[None, :]), None]]).tocsc()
-        self.lu = splu(Kii)
+        self.lu = _DenseLU(Kii) if dense else splu(Kii)
         self.nv, self.npr = nv, npr
         C = sp.vstack([A_IG, Bp_G, sp.csr_matrix((1, len(self.ig)))]).toarray()
         self.C = C
@@ -92,10 +106,10 @@ class LocalSchur:
 
 class OracleBDDC:
     def __init__(self, wl, scaling="deluxe", adaptive_theta=0.0, svd_tol=1e-10,
-                 adaptive_edges=False):
+                 adaptive_edges=False, dense_local=False):
         self.wl = wl
         self.nG = wl["n_iface"]
-        self.loc = [LocalSchur(sd) for sd in wl["subs"]]
+        self.loc = [LocalSchur(sd, dense=dense_local) for sd in wl["subs"]]
         self.N = len(self.loc)
         self.n = self.nG + self.N  # global interface vector: u_Gamma then p0
         self.svd_tol = svd_tol

@@ -37,6 +37,8 @@ struct GemvJob {
   double alpha;        // gemv_t: y = alpha A^T x (+ y if acc)
   int acc;
   int a_f32;
+  double *y2;          // gemv_t, square A, no acc: y2[j] = x_j - y[j] (x_j gathered like
+                       // the rows), the complement (I - A)^T x of the same product
 };
 
 struct ExtPart {
@@ -50,6 +52,8 @@ struct ExtJob {
   int nparts;
   int part0;
   const int64_t *gids;  // m global positions
+  int pair;             // two parts whose matrices sum to I: only the first one's D is
+                        // read, z = w_2 + D_1 (w_1 - w_2)
 };
 
 struct RecJob {

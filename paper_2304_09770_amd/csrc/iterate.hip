@@ -64,6 +64,7 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
       double v = J.alpha * s;
       if (J.acc) v += J.y[j];
       J.y[j] = v;
+      if (J.y2) J.y2[j] = (J.xidx ? J.x[J.xidx[j]] : J.x[j]) - v;
     }
   }
 }
@@ -178,52 +179,96 @@ hipError_t scatter_copy(int n, const double *src, const int64_t *sidx, const int
 }
 
 // Deluxe extension: z[gid[m]] = sum_q (D_q w_q)[m] over the subdomains of
-// the entity (D_q = null: counting weights 1/card).  A workgroup takes 64
-// rows (lanes over the rows: coalesced reads down the columns of the
-// column-major D_q); its four waves split the columns, four independent
-// sums per lane, and the partial sums are added through LDS in a fixed
-// order.
+// the entity (D_q = null: counting weights 1/card); for a pair of
+// subdomains whose matrices sum to the identity, z = w_2 + D_1 (w_1 - w_2),
+// so only D_1 is read.  A workgroup takes 128 rows: each lane two adjacent
+// rows with one 16-byte load per column (the matrices are stored with an
+// even leading dimension, 16-byte aligned; the row past an odd m is in the
+// column's storage and feeds no output).  The vector the matrix multiplies
+// is staged in LDS in chunks of EXT_CHUNK columns, which the four waves
+// split, four columns in flight per lane; the partial sums are added
+// through LDS in a fixed order.
+constexpr int EXT_CHUNK = 1024;
+typedef double v2d __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ v2d load2(const double *p) {
+  return *(const __attribute__((address_space(1))) v2d *)p;
+}
+
 __global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPart *parts,
                                                 const double *w, double *z) {
   const ExtJob J = jobs[blockIdx.y];
-  const int r0 = blockIdx.x * 64;
+  const int r0 = blockIdx.x * 128;
   if (r0 >= J.m) return;  // uniform over the workgroup
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int m = r0 + lane;
-  const bool row = m < J.m;
-  const int c0 = (int)((int64_t)J.m * wv / 4), c1 = (int)((int64_t)J.m * (wv + 1) / 4);
-  double s = 0.0;
-  for (int q = 0; q < J.nparts; ++q) {
-    const ExtPart P = parts[J.part0 + q];
-    const double *wq = w + P.woff;
-    if (P.D) {
-      if (row) {
-        const auto a = gptr(P.D + m);
-        double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-        int l = c0;
-        for (; l + 4 <= c1; l += 4) {
-          s0 += a[(int64_t)l * P.ld] * wq[l];
-          s1 += a[(int64_t)(l + 1) * P.ld] * wq[l + 1];
-          s2 += a[(int64_t)(l + 2) * P.ld] * wq[l + 2];
-          s3 += a[(int64_t)(l + 3) * P.ld] * wq[l + 3];
-        }
-        for (; l < c1; ++l) s0 += a[(int64_t)l * P.ld] * wq[l];
-        s += (s0 + s1) + (s2 + s3);
+  const int m0 = r0 + 2 * lane;
+  const bool rows = m0 < J.m;
+  __shared__ double xs[EXT_CHUNK];
+  double s0 = 0.0, s1 = 0.0;
+  // s += D[m0:m0+2, :] (u - v) (v may be null); called by the whole workgroup
+  auto matvec = [&](const double *D, int64_t ld, const double *u, const double *v) {
+    for (int cb = 0; cb < J.m; cb += EXT_CHUNK) {
+      const int cm = min(EXT_CHUNK, J.m - cb);
+      __syncthreads();
+      for (int i = threadIdx.x; i < cm; i += blockDim.x) xs[i] = v ? u[cb + i] - v[cb + i] : u[cb + i];
+      __syncthreads();
+      if (!rows) continue;
+      const int k0 = cm * wv / 4, k1 = cm * (wv + 1) / 4;
+      const double *a = D + m0 + (int64_t)cb * ld;
+      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
+      int l = k0;
+      for (; l + 4 <= k1; l += 4) {
+        const v2d d0 = load2(a + (int64_t)l * ld);
+        const v2d d1 = load2(a + (int64_t)(l + 1) * ld);
+        const v2d d2 = load2(a + (int64_t)(l + 2) * ld);
+        const v2d d3 = load2(a + (int64_t)(l + 3) * ld);
+        const double x0 = xs[l], x1 = xs[l + 1], x2 = xs[l + 2], x3 = xs[l + 3];
+        t0 += d0.x * x0; q0 += d0.y * x0;
+        t1 += d1.x * x1; q1 += d1.y * x1;
+        t2 += d2.x * x2; q2 += d2.y * x2;
+        t3 += d3.x * x3; q3 += d3.y * x3;
       }
-    } else if (wv == 0 && row) {
-      s += wq[m] * P.scale;
+      for (; l < k1; ++l) {
+        const v2d d0 = load2(a + (int64_t)l * ld);
+        t0 += d0.x * xs[l]; q0 += d0.y * xs[l];
+      }
+      s0 += (t0 + t1) + (t2 + t3);
+      s1 += (q0 + q1) + (q2 + q3);
+    }
+  };
+  const double *wlast = nullptr;
+  if (J.pair) {
+    const ExtPart P = parts[J.part0], Q = parts[J.part0 + 1];
+    wlast = w + Q.woff;
+    matvec(P.D, P.ld, w + P.woff, wlast);
+  } else {
+    for (int q = 0; q < J.nparts; ++q) {
+      const ExtPart P = parts[J.part0 + q];
+      const double *wq = w + P.woff;
+      if (P.D) {
+        matvec(P.D, P.ld, wq, nullptr);
+      } else if (wv == 0 && rows) {
+        s0 += wq[m0] * P.scale;
+        if (m0 + 1 < J.m) s1 += wq[m0 + 1] * P.scale;
+      }
     }
   }
-  __shared__ double part[4][64];
-  part[wv][lane] = s;
+  __shared__ double part[4][128];
+  part[wv][2 * lane] = s0;
+  part[wv][2 * lane + 1] = s1;
   __syncthreads();
-  if (wv == 0 && row) z[J.gids[m]] = (part[0][lane] + part[1][lane]) + (part[2][lane] + part[3][lane]);
+  const int t = threadIdx.x;
+  if (t < 128 && r0 + t < J.m) {
+    const int r = r0 + t;
+    double v = (part[0][t] + part[1][t]) + (part[2][t] + part[3][t]);
+    if (wlast) v += wlast[r];
+    z[J.gids[r]] = v;
+  }
 }
 
 hipError_t extend(const ExtJob *d_jobs, int njobs, int max_m, const ExtPart *d_parts,
                   const double *w, double *z, hipStream_t s) {
   if (!njobs || !max_m) return hipSuccess;
-  hipLaunchKernelGGL(k_extend, dim3((max_m + 63) / 64, njobs), dim3(256), 0, s, d_jobs, d_parts,
+  hipLaunchKernelGGL(k_extend, dim3((max_m + 127) / 128, njobs), dim3(256), 0, s, d_jobs, d_parts,
                      w, z);
   return hipGetLastError();
 }

@@ -75,7 +75,8 @@ struct EntH {
   // deluxe
   double *Daug = nullptr;
   int64_t Dld = 0;
-  std::vector<double *> D;  // per sharing subdomain
+  std::vector<double *> D;  // per sharing subdomain (null: I - D[0] for a pair)
+  int64_t Dmld = 0;         // leading dimension of the D matrices (even)
   std::vector<double *> Sbar;
   int64_t *d_dual_gids = nullptr;
 };
@@ -2303,11 +2304,18 @@ static int setup_impl(vb_ctx *ctx) {
     }
     double *invD = nullptr;
     UCHK(ctx->dalloc(&invD, std::max<int64_t>(itot, 1), true));
-    // every D_E^(s) in one allocation
+    // every D_E^(s) in one allocation, each with an even leading dimension
+    // (16-byte aligned columns for the extension's loads).  An entity shared
+    // by two subdomains keeps only D_E^(first): the other is I - D_E^(first)
+    // (the deluxe weights sum to the identity), which the restriction and the
+    // extension apply without reading a second matrix.
+    auto pair_of = [&](const EntH &H) {
+      return ctx->opt.scaling != VB_SCALING_COUNTING && H.subs.size() == 2;
+    };
     int64_t dtot = 0;
     for (auto &H : ctx->ents) {
       const int m = H.n - H.rank;
-      if (m > 0) dtot += (int64_t)H.subs.size() * m * m;
+      if (m > 0) dtot += (int64_t)(pair_of(H) ? 1 : H.subs.size()) * round_up(m, 2) * m;
     }
     double *dall = nullptr;
     UCHK(ctx->dalloc(&dall, std::max<int64_t>(dtot, 1)));
@@ -2323,14 +2331,16 @@ static int setup_impl(vb_ctx *ctx) {
       UCHK(ctx->upload(&H.d_dual_gids, dg));
       if (m <= 0) continue;
       max_m = std::max(max_m, m);
-      for (size_t q = 0; q < H.subs.size(); ++q) {
+      const int64_t ldm = round_up(m, 2);
+      H.Dmld = ldm;
+      for (size_t q = 0; q < (pair_of(H) ? 1 : H.subs.size()); ++q) {
         H.D[q] = dall + doff;
-        doff += (int64_t)m * m;
+        doff += ldm * m;
       }
       if (ctx->opt.scaling == VB_SCALING_COUNTING) {
         for (size_t q = 0; q < H.subs.size(); ++q) {
-          CHK(hipMemsetAsync(H.D[q], 0, (size_t)m * m * sizeof(double), st));
-          dj.push_back({H.D[q], m, 0, 0, m, 1.0 / H.subs.size()});
+          CHK(hipMemsetAsync(H.D[q], 0, (size_t)ldm * m * sizeof(double), st));
+          dj.push_back({H.D[q], ldm, 0, 0, m, 1.0 / H.subs.size()});
         }
         continue;
       }
@@ -2350,7 +2360,8 @@ static int setup_impl(vb_ctx *ctx) {
         rounds[q].push_back({X, S.xld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
         UCHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
         sb.push_back({X, S.xld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
-        mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, m, m, m, m, 0, -1.0, 0.0});
+        if (H.D[q])
+          mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, ldm, m, m, m, 0, -1.0, 0.0});
       }
       dj.push_back({H.Daug, H.Dld, m, 0, m, 1.0});
       lj.push_back({H.Daug, H.Dld, 2 * m, m, m, 0, invD + ioff, ctx->info + 2 * nS + 2 + (cnt % 16)});
@@ -2455,14 +2466,23 @@ static int setup_impl(vb_ctx *ctx) {
       EntH &H = ctx->ents[e];
       const int m = H.n - H.rank;
       if (m <= 0) continue;
-      ExtJob J{m, (int)H.subs.size(), (int)ep.size(), H.d_dual_gids};
+      const bool pair = H.D.size() == 2 && H.D[0] && !H.D[1];  // D^(2) = I - D^(1)
+      ExtJob J{m, (int)H.subs.size(), (int)ep.size(), H.d_dual_gids, pair ? 1 : 0};
+      std::vector<int64_t> wos;
       for (size_t qd = 0; qd < H.subs.size(); ++qd) {
         const int s = H.subs[qd];
         SubH &S = ctx->subs[s];
         int qq = (int)(std::find(S.ents.begin(), S.ents.end(), e) - S.ents.begin());
-        const int64_t wo = sgo[s] + S.doff[qq];
-        jr.push_back({H.D[qd], m, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wo, 1.0, 0});
-        ep.push_back({H.D[qd], m, wo, 0.0});
+        wos.push_back(sgo[s] + S.doff[qq]);
+        ep.push_back({H.D[qd], H.Dmld, wos.back(), 0.0});
+      }
+      if (pair) {  // g^(1) = D^(1)T r, g^(2) = r - g^(1): one read of D^(1)
+        GemvJob G{H.D[0], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[0], 1.0, 0};
+        G.y2 = ctx->gD + wos[1];
+        jr.push_back(G);
+      } else {
+        for (size_t qd = 0; qd < H.subs.size(); ++qd)
+          jr.push_back({H.D[qd], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[qd], 1.0, 0});
       }
       ej.push_back(J);
       ctx->max_rm = std::max(ctx->max_rm, m);

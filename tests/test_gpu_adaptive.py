@@ -17,7 +17,12 @@ different spaces.  There the preconditioner and the iterates are compared
 on a tie-free context instead: a non-adaptive GPU context whose entity
 constraints are the given rows plus the oracle's adaptive rows (the same
 primal space by construction), against the oracle's adaptive M^-1 r and
-PCG iterates to 1e-10."""
+PCG iterates.  The bar is set by the oracle itself: two FP64 evaluations of
+the same oracle on that primal space, one with sparse and one with dense LU
+factors of the local Dirichlet matrices, differ by about 2e-8 in M^-1 r and
+1e-9 in the 20th iterate (the local Neumann blocks S_DD have condition
+numbers up to 1.8e6 at this contrast), so the GPU must lie within 10 times
+that spread of the oracle (and within 1e-10 where the spread is smaller)."""
 import numpy as np
 import pytest
 
@@ -112,23 +117,24 @@ def _with_oracle_rows(wl, o):
 
 @pytest.fixture(scope="module")
 def operator_ctx(vb, acase):
-    """The context whose M^-1 is compared with the oracle's: the adaptive
-    context itself on the strict cases, the tie-free one on t12s."""
+    """(context, second oracle evaluation): the adaptive context itself on
+    the strict cases; on t12s the tie-free context and the oracle on the
+    same primal space with dense local LU factors."""
     name, wl, meta, o, ctx = acase
     if name in STRICT:
-        yield ctx
+        yield ctx, None
         return
+    wl2 = _with_oracle_rows(wl, o)
     c = vb.vb_create(tol=1e-8)
-    vb.vb_assemble(c, _with_oracle_rows(wl, o))
+    vb.vb_assemble(c, wl2)
     vb.vb_setup(c)
-    yield c
+    yield c, OracleBDDC(wl2, dense_local=True)
     vb.vb_destroy(c)
 
 
 def test_adaptive_preconditioner_parity(vb, acase, operator_ctx):
     name, wl, meta, o, _ = acase
-    ctx = operator_ctx
-    tol = 1e-9 if name in STRICT else 1e-10
+    ctx, o2 = operator_ctx
     n = vb.vb_interface_size(ctx)
     rng = np.random.default_rng(5)
     r = o.apply_S(rng.standard_normal(n))
@@ -138,22 +144,32 @@ def test_adaptive_preconditioner_parity(vb, acase, operator_ctx):
     zo = o.apply_M(r)
     zg = z.cpu().numpy()
     nG = o.nG
-    assert _rel(zg[:nG], zo[:nG]) < tol, _rel(zg[:nG], zo[:nG])
+    tol = 1e-9
+    if o2 is not None:
+        spread = _rel(o2.apply_M(r)[:nG], zo[:nG])
+        print("oracle spread of M^-1 r: %.2e" % spread, flush=True)
+        tol = max(1e-10, 10.0 * spread)
+    assert _rel(zg[:nG], zo[:nG]) < tol, (_rel(zg[:nG], zo[:nG]), tol)
     dp = (zg[nG:] - zg[nG:].mean()) - (zo[nG:] - zo[nG:].mean())
     assert np.linalg.norm(dp) < tol * np.linalg.norm(zo)
 
 
 def test_adaptive_pcg_parity(vb, acase, operator_ctx):
     name, wl, meta, o, _ = acase
-    ctx = operator_ctx
-    tol = 1e-9 if name in STRICT else 1e-10
+    ctx, o2 = operator_ctx
     n = vb.vb_interface_size(ctx)
     x = torch.zeros(n, dtype=torch.float64, device=DEV)
     info = vb.vb_pcg_solve(ctx, x)
     torch.cuda.synchronize()
     K = info["iterations"]
     xo, oi = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=K)
-    assert _rel(x.cpu().numpy(), xo) < tol, (K, _rel(x.cpu().numpy(), xo))
+    tol = 1e-9
+    if o2 is not None:
+        x2, _ = pcg(o2.apply_S, o2.apply_M, o2.rhs(), fixed_iters=K)
+        spread = _rel(x2, xo)
+        print("oracle spread of iterate %d: %.2e" % (K, spread), flush=True)
+        tol = max(1e-10, 10.0 * spread)
+    assert _rel(x.cpu().numpy(), xo) < tol, (K, _rel(x.cpu().numpy(), xo), tol)
     assert info["lambda_min"] > 1 - 1e-6
     lmin, lmax = lanczos_extremes(oi["alphas"], oi["betas"])
     assert abs(info["lambda_max"] / info["lambda_min"] - lmax / lmin) <= 1e-6 * lmax / lmin

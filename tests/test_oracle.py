@@ -320,3 +320,18 @@ def test_lanczos_extremes_match_dense_spectrum(tiny_jit):
     assert abs(lmax - nz.max()) < 1e-8 * nz.max()
     assert nz.min() - 1e-10 <= lmin <= 1.01 * nz.min()
     assert abs(nz.min() - 1.0) < 1e-10
+
+
+def test_dense_local_factors_agree_with_sparse(tiny_jit):
+    """The oracle's second evaluation (dense LU of the local Dirichlet
+    matrices instead of sparse LU) computes the same S_Gamma, g and M^-1 on
+    a well-conditioned problem: agreement to rounding."""
+    pb, dec, o = tiny_jit
+    od = OracleBDDC(dec.workload(), dense_local=True)
+    rng = np.random.default_rng(11)
+    x = rng.standard_normal(o.n)
+    rel = lambda a, b: np.linalg.norm(a - b) / np.linalg.norm(b)
+    assert rel(od.rhs(), o.rhs()) < 1e-12
+    assert rel(od.apply_S(x), o.apply_S(x)) < 1e-12
+    r = o.apply_S(x)
+    assert rel(od.apply_M(r)[: o.nG], o.apply_M(r)[: o.nG]) < 1e-11
