@@ -360,6 +360,30 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n,
                    const int32_t *ld, const int32_t *e, const int32_t *p,
                    int32_t *info, int max_n, int max_e);
 
+/* Bytes of device working memory vb_batched_ldl_noalloc holds per GPU. */
+#define VB_NOALLOC_SCRATCH_BYTES (32u << 20)
+
+/* vb_batched_ldl for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same factorisation, arguments and results (the same kernels, so the
+ * same bits), with its working memory -- the job table, the inverse
+ * diagonal blocks of every panel and one flag -- in a fixed device array of
+ * VB_NOALLOC_SCRATCH_BYTES per GPU that the library holds until the process
+ * ends (its address is looked up on the first call on each device).  It
+ * calls no hipMalloc, hipFree or other allocating device routine.
+ * Differences from vb_batched_ldl: the sizes are checked on the device, not
+ * the host: a matrix with n < 0, n > max_n, e < 0, e > n, e > max_e or
+ * ld < n is left untouched with info = -1 while the others are factored.
+ * Returns VB_ERR_ARG when batch * ceil(max_e / 64) * 64 * 64 * 8 bytes of
+ * inverse diagonal blocks, plus 256 bytes and 48 bytes per matrix, exceed
+ * VB_NOALLOC_SCRATCH_BYTES.  Every call on a GPU uses that GPU's one array:
+ * calls that overlap on one GPU (other threads, other contexts' streams)
+ * race and must be serialised by the caller.  Stream-ordered on the
+ * context's stream; returns after the factorisation has finished. */
+int vb_batched_ldl_noalloc(vb_ctx *ctx, int batch, double *const *A, const int32_t *n,
+                           const int32_t *ld, const int32_t *e, const int32_t *p,
+                           int32_t *info, int max_n, int max_e);
+
 #ifdef __cplusplus
 }
 #endif

@@ -99,6 +99,7 @@ def load():
         "vb_local_size": (C.c_int64, [P, C.c_int]),
         "vb_set_profile": (C.c_int, [P, C.c_int]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
+        "vb_batched_ldl_noalloc": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
         "vb_adaptive_info": (C.c_int, [P, C.c_int, C.POINTER(vb_face_info), C.c_int,
                                        C.POINTER(C.c_double)]),
@@ -138,7 +139,8 @@ def exported_symbols():
             "vb_mlp_last_error", "vb_mlp_add_samples", "vb_mlp_num_samples", "vb_mlp_train",
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
-            "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile"]
+            "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
+            "vb_batched_ldl_noalloc"]
 
 
 class VBError(RuntimeError):
@@ -289,6 +291,18 @@ def vb_batched_ldl(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
                                _ptr(ld, "int32", b), _ptr(e, "int32", b), _ptr(p, "int32", b),
                                _ptr(info, "int32", b), int(max_n), int(max_e))
     _check(ctx, rc)
+
+
+def vb_batched_ldl_noalloc(ctx, ptrs, n, ld, e, p, info, max_n, max_e):
+    b = len(n)
+    rc = load().vb_batched_ldl_noalloc(ctx, b, _ptr(ptrs, "int64", b), _ptr(n, "int32", b),
+                                       _ptr(ld, "int32", b), _ptr(e, "int32", b),
+                                       _ptr(p, "int32", b), _ptr(info, "int32", b), int(max_n),
+                                       int(max_e))
+    _check(ctx, rc)
+
+
+VB_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 
 def vb_kernel_stats(ctx, which, reset=False):

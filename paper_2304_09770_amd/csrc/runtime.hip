@@ -3338,6 +3338,13 @@ int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out) {
 
 }  // extern "C"
 
+// accessors for the allocation-free entry point (noalloc.hip)
+namespace vb {
+hipStream_t ctx_stream(const vb_ctx *ctx) { return ctx->stream; }
+int ctx_panel(const vb_ctx *ctx) { return ctx->opt.panel; }
+int ctx_fail(vb_ctx *ctx, int code, const char *msg) { return ctx->fail(code, msg); }
+}  // namespace vb
+
 // ------------------------------------------------------------ predictor ABI
 #define MCHK(x)                                                                   \
   do {                                                                            \
