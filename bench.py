@@ -95,6 +95,41 @@ def dense_condensation_flops(wl):
     return float(tot)
 
 
+def _tri_count(m, e):
+    """sum of t^2 - 1 for t = m - e + 1 .. m (see dense_condensation_flops)."""
+    s2 = lambda n: n * (n + 1) * (2 * n + 1) // 6
+    return (s2(m) - s2(m - e)) - e
+
+
+def nested_condensation_flops(wl):
+    """Flops the two-level factorisation executes, counted like
+    dense_condensation_flops: per sub-box front (its e interior velocities
+    and pressures but one eliminated, m = e + 1 + |B| rows: the kept
+    pressure and the separator and interface DoFs it couples to), then per
+    subdomain the second level (separator velocities and sub-box constants
+    but one eliminated, onto the interface DoFs).  None without sub-box
+    labels."""
+    import scipy.sparse as sp
+    tot = 0
+    for sd in wl["subs"]:
+        if sd.get("part") is None:
+            return None
+        kind, part = np.asarray(sd["kind"]), np.asarray(sd["part"])
+        n = len(kind)
+        K = sp.csr_matrix((np.ones(len(sd["indices"])), sd["indices"], sd["indptr"]), shape=(n, n))
+        elim = (kind != 1) & (part >= 0)
+        nbox = int(part.max()) + 1
+        for b in range(nbox):
+            rows = np.nonzero(elim & (part == b))[0]
+            cols = np.unique(K[rows].indices)
+            nB = int(np.sum(~elim[cols]))
+            e = len(rows) - 1
+            tot += _tri_count(e + 1 + nB, e)
+        e2 = int(np.sum((kind == 0) & (part < 0))) + nbox - 1
+        tot += _tri_count(e2 + int(np.sum(kind == 1)), e2)
+    return float(tot)
+
+
 def sparse_lu_flops(lu):
     """Flops of a sparse LU factorisation from its factors' structure:
     sum over pivots of 2 (c_j - 1)(r_j - 1) + (c_j - 1), c_j and r_j the
@@ -105,16 +140,19 @@ def sparse_lu_flops(lu):
 
 
 def setup_flops(wl, sparse_sample, setup_ms):
-    """The local condensation's work counted two ways: what the dense
-    factorisation executes, and the LU flops of the oracle's sparse
-    factorisation of the interior matrices (fill-reducing COLAMD ordering;
-    sampled subdomains scaled to all, halved for the symmetric factorisation
-    it stands for; the dense Schur complement itself not included), each
-    per second of the measured setup."""
+    """The local condensation's work counted three ways: what the two-level
+    factorisation executes (when the workload carries sub-box labels), what
+    one dense factorisation per subdomain would execute, and the LU flops of
+    the oracle's sparse factorisation of the interior matrices (fill-reducing
+    COLAMD ordering; sampled subdomains scaled to all, halved for the
+    symmetric factorisation it stands for; the dense Schur complement itself
+    not included), each per second of the measured setup."""
     try:
         dense = dense_condensation_flops(wl)
-        out = {"dense_executed": dense,
-               "dense_tflops_per_setup_s": dense / (setup_ms * 1e-3) / 1e12 if setup_ms else None,
+        nested = nested_condensation_flops(wl)
+        per_s = lambda f: f / (setup_ms * 1e-3) / 1e12 if (setup_ms and f) else None
+        out = {"nested_executed": nested, "nested_tflops_per_setup_s": per_s(nested),
+               "dense_single_level": dense, "dense_tflops_per_setup_s": per_s(dense),
                "sparse_factor_est": None, "sparse_tflops_per_setup_s": None, "sparse_sample": None}
         if sparse_sample:
             nsub = len(wl["subs"])
@@ -122,7 +160,8 @@ def setup_flops(wl, sparse_sample, setup_ms):
             out.update(sparse_factor_est=sp_f,
                        sparse_tflops_per_setup_s=sp_f / (setup_ms * 1e-3) / 1e12 if setup_ms else None,
                        sparse_sample="SuperLU (COLAMD) factors of %d of %d subdomains' interior "
-                                     "matrices, mean scaled x%d, halved" % (len(sparse_sample), nsub, nsub))
+                                     "matrices (each scaled to a subdomain of mean n_I^2), mean "
+                                     "scaled x%d, halved" % (len(sparse_sample), nsub, nsub))
         return out
     except Exception as ex:  # a report field only: never fail the bench line
         log("setup flop model skipped: %r" % (ex,))
@@ -137,39 +176,48 @@ def _blas_threads():
         return os.cpu_count() or 1
 
 
-def cpu_baseline(wl, budget_s=20.0, seed=0):
+def cpu_baseline(wl, budget_s=20.0):
     """The oracle on a time-bounded sample of the benchmark's own workload:
     its local Schur complements (sparse LU of the Dirichlet problem and one
-    solve per interface column: the dominant part of its setup) on
-    subdomains taken in a seeded random order until `budget_s` seconds have
-    passed (at least one), the mean time scaled to all subdomains.  The
-    oracle's coarse, scaling, PCG and recovery work is left out, so the
-    solves/s it implies is an upper bound for the oracle."""
+    solve per interface column: the dominant part of its setup) on the
+    subdomains of smallest cost proxy p = n_I^(4/3) n_Gamma (n_I interior
+    unknowns: sparse-factor solves of fill ~ n_I^(4/3), one per interface
+    column) until `budget_s` seconds have passed (at least one), scaled to
+    all subdomains by the ratio sum_all p / sum_sampled p.  The oracle's
+    coarse, scaling, PCG and recovery work is left out, so the solves/s it
+    implies is an upper bound for the oracle."""
     from oracle.bddc import LocalSchur
     nsub = len(wl["subs"])
-    order = np.random.default_rng(seed).permutation(nsub)
+    proxy = []
+    for sd in wl["subs"]:
+        kind = np.asarray(sd["kind"])
+        n_i = float(np.sum(kind != 1))
+        proxy.append(n_i ** (4.0 / 3.0) * float(np.sum(kind == 1)))
+    proxy = np.array(proxy)
+    order = np.argsort(proxy, kind="stable")
     t0 = time.perf_counter()
-    times, lus = [], []
+    times, lus, done = [], [], []
     for s in order:
         t1 = time.perf_counter()
         lus.append(LocalSchur(wl["subs"][int(s)]).lu)
         times.append(time.perf_counter() - t1)
+        done.append(int(s))
         if time.perf_counter() - t0 > budget_s:
             break
-    dt = float(np.mean(times))
+    est = sum(times) / proxy[done].sum() * proxy.sum()
     try:
         sparse = [sparse_lu_flops(lu) for lu in lus]
     except Exception as ex:
         log("sparse flop count skipped: %r" % (ex,))
         sparse = None
-    return {"value": 1.0 / (dt * nsub), "unit": "solves/s", "cores": int(_blas_threads()),
-            "_sparse_flops": sparse,
+    return {"value": 1.0 / est, "unit": "solves/s", "cores": int(_blas_threads()),
+            "_sparse_flops": sparse, "_sampled": done,
             "kind": "oracle",
             "sample": "local Schur complements (sparse LU, one solve per interface column) of "
-                      "%d of %d subdomains in seeded random order (%.1f s of CPU work, %.2f s "
-                      "each), mean scaled x%d; the oracle's coarse, scaling, PCG and recovery "
-                      "work is not included (its full solve is timed at c1 in "
-                      "oracle_full_c1)" % (len(times), nsub, sum(times), dt, nsub)}
+                      "the %d of %d subdomains of smallest cost proxy n_I^(4/3) n_Gamma "
+                      "(%.1f s of CPU work), scaled to all by the proxy (%.0f s estimated); the "
+                      "oracle's coarse, scaling, PCG and recovery work is not included (its full "
+                      "solve is timed at c1 in oracle_full_c1)" % (len(times), nsub, sum(times), est)}
 
 
 def oracle_full_c1():
@@ -323,6 +371,10 @@ def main():
     if not args.no_cpu:
         cpu = cpu_baseline(wl, args.cpu_budget)
         sparse_flops = cpu.pop("_sparse_flops")
+        sampled = cpu.pop("_sampled")
+        if sparse_flops:  # per sampled subdomain, scaled to a subdomain of mean n_I^2
+            n_i2 = np.array([float(np.sum(np.asarray(sd["kind"]) != 1)) ** 2 for sd in wl["subs"]])
+            sparse_flops = [f * n_i2.mean() / n_i2[k] for f, k in zip(sparse_flops, sampled)]
         log("cpu baseline: %s" % cpu["sample"])
         full_c1 = oracle_full_c1()
         log("oracle in full at c1: %s" % full_c1)

@@ -291,8 +291,39 @@ class Decomposition:
             pw[d >= pb.Nvr] = pb.mesh.elem_vol[d[d >= pb.Nvr] - pb.Nvr]
             sd = Subdomain()
             sd.dofs, sd.kind, sd.gid, sd.pweight, sd.K, sd.rhs, sd.elems = d, kind, g.astype(np.int64), pw, K, rhs, el
+            sd.part = self._sub_boxes(s, el, lr, kind)
             self.subs.append(sd)
         self.sub_vol = np.array([pb.mesh.elem_vol[sd.elems].sum() for sd in self.subs])
+
+    def _sub_boxes(self, s, el, lr, kind):
+        """Geometric one-level nested dissection of subdomain s: its box of
+        elements is halved along every axis with at least two elements,
+        giving up to eight sub-boxes.  Per local DoF: the sub-box whose
+        elements alone carry it (its interior velocities and element
+        pressures), or -1 for the separator DoFs shared by elements of
+        several sub-boxes and for the interface DoFs."""
+        m = self.pb.mesh
+        px, py, pz = self.parts
+        seg = (s % px, (s // px) % py, s // (px * py))
+        nb, sub = [], np.zeros(len(el), np.int64)
+        mult = 1
+        for a in range(3):
+            c0, c1 = self.cuts[a][seg[a]], self.cuts[a][seg[a] + 1]
+            side = c1 - c0
+            pieces = 2 if side >= 2 else 1
+            half = (m.eidx[el, a] - c0) >= side // 2 if pieces == 2 else np.zeros(len(el), bool)
+            sub += mult * half.astype(np.int64)
+            mult *= pieces
+        ok = lr >= 0
+        b = np.broadcast_to(sub[:, None], lr.shape)[ok]
+        idx = lr[ok]
+        lo = np.full(len(kind), np.iinfo(np.int64).max)
+        hi = np.full(len(kind), -1)
+        np.minimum.at(lo, idx, b)
+        np.maximum.at(hi, idx, b)
+        part = np.where(lo == hi, lo, -1).astype(np.int32)
+        part[kind == KIND_INTERFACE] = -1
+        return part
 
     # ---------------------------------------------------------------------
     def interface_solution(self, xred):
@@ -314,7 +345,7 @@ class Decomposition:
             subs.append({"indptr": sd.K.indptr.astype(np.int64), "indices": sd.K.indices.astype(np.int64),
                          "data": sd.K.data.astype(np.float64), "kind": sd.kind.astype(np.int32),
                          "gid": sd.gid.astype(np.int64), "pweight": sd.pweight.astype(np.float64),
-                         "rhs": sd.rhs.astype(np.float64)})
+                         "rhs": sd.rhs.astype(np.float64), "part": sd.part.astype(np.int32)})
         ents = []
         for e in range(len(self.ent_dofs)):
             ents.append({"kind": int(self.ent_kind[e]), "gids": self.ent_dofs[e].astype(np.int64),

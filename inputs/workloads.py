@@ -148,7 +148,8 @@ def load_workload(path):
     subs = []
     for i in range(int(z["nsub"][0])):
         subs.append({k: z["s%d_%s" % (i, k)] for k in
-                     ("indptr", "indices", "data", "kind", "gid", "pweight", "rhs")})
+                     ("indptr", "indices", "data", "kind", "gid", "pweight", "rhs", "part")
+                     if "s%d_%s" % (i, k) in z})
     ents = []
     for e in range(int(z["nent"][0])):
         ents.append({"kind": int(z["e%d_kind" % e][0]), "gids": z["e%d_gids" % e],

@@ -51,7 +51,8 @@ class vb_subdomain(C.Structure):
     _fields_ = [("n", C.c_int32), ("nnz", C.c_int64), ("indptr", C.POINTER(C.c_int64)),
                 ("indices", C.POINTER(C.c_int64)), ("data", C.POINTER(C.c_double)),
                 ("kind", C.POINTER(C.c_int32)), ("gid", C.POINTER(C.c_int64)),
-                ("pweight", C.POINTER(C.c_double)), ("rhs", C.POINTER(C.c_double))]
+                ("pweight", C.POINTER(C.c_double)), ("rhs", C.POINTER(C.c_double)),
+                ("part", C.POINTER(C.c_int32))]
 
 
 class vb_entity(C.Structure):
@@ -203,9 +204,12 @@ def vb_destroy(ctx):
     load().vb_destroy(ctx)
 
 
-def vb_assemble(ctx, workload):
+def vb_assemble(ctx, workload, nested=True):
     """workload: dict(n_iface, subs=[dict(indptr, indices, data, kind, gid,
-    pweight, rhs)], ents=[dict(kind, gids, con)]) (numpy arrays)."""
+    pweight, rhs[, part])], ents=[dict(kind, gids, con)]) (numpy arrays).
+    nested: pass the sub-box labels `part` when the workload has them (the
+    two-level local factorisation); False: one dense factorisation per
+    subdomain."""
     keep = []
     subs = (vb_subdomain * len(workload["subs"]))()
     for i, sd in enumerate(workload["subs"]):
@@ -217,7 +221,11 @@ def vb_assemble(ctx, workload):
         pw, pwp = _np(sd["pweight"], np.float64)
         rh, rhp = _np(sd["rhs"], np.float64)
         keep += [ip, ix, dv, kd, gd, pw, rh]
-        subs[i] = vb_subdomain(len(kd), len(ix), ipp, ixp, dvp, kdp, gdp, pwp, rhp)
+        ptp = None
+        if nested and sd.get("part") is not None:
+            pt, ptp = _np(sd["part"], np.int32)
+            keep.append(pt)
+        subs[i] = vb_subdomain(len(kd), len(ix), ipp, ixp, dvp, kdp, gdp, pwp, rhp, ptp)
     ents = (vb_entity * max(1, len(workload["ents"])))()
     for e, E in enumerate(workload["ents"]):
         g, gp = _np(E["gids"], np.int64)

@@ -64,6 +64,9 @@ struct RecJob {
   const double *hv;
   const double *z;   // interior solution in dense order
   double *out;
+  const int32_t *oidx;  // null, or per CSR DoF its index in out (-1: not written)
+  double *sep_out;      // null, or receives z at the dense positions of the kind-0 DoFs
+  double *c_out;        // null, or receives the nel pressure values (rows need not be CSR DoFs)
 };
 
 hipError_t gemv_t(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStream_t s);

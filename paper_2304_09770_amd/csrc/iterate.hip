@@ -430,6 +430,7 @@ __global__ void k_recover_out(const RecJob *jobs, const double *x_orig, int64_t 
     double v;
     if (k == 0) {
       v = J.z[p];
+      if (J.sep_out) J.sep_out[p] = v;
     } else if (k == 1) {
       v = x_orig[J.gid[i]];
     } else {
@@ -437,8 +438,14 @@ __global__ void k_recover_out(const RecJob *jobs, const double *x_orig, int64_t 
       const double pi = (q < J.nel - 1) ? J.z[p] : 0.0;
       v = pi - tau * J.hv[q] * t + p0;
     }
-    J.out[i] = v;
+    const int o = J.oidx ? J.oidx[i] : i;
+    if (o >= 0) J.out[o] = v;
   }
+  if (J.c_out)
+    for (int q = threadIdx.x; q < J.nel; q += blockDim.x) {
+      const double pi = (q < J.nel - 1) ? J.z[J.nv + q] : 0.0;
+      J.c_out[q] = pi - tau * J.hv[q] * t + p0;
+    }
 }
 
 hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,

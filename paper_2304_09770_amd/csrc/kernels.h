@@ -81,7 +81,29 @@ struct SubDev {
   int n_ent;              // entities touching the subdomain
   const int32_t *ent;     // [n_ent] entity ids
   const int32_t *ent_off; // [n_ent] local offset of each entity block
+  const int32_t *oidx;    // null, or per CSR row its row in the subdomain's full CSR
+                          // (-1: none); the local residual is read through it
 };
+
+// One front of the two-level factorisation: its trailing block [kept | B |
+// rhs] (m rows from row e of the front matrix) and where those rows sit in
+// its subdomain's second-level matrix and vectors.
+struct FrontJob {
+  const void *Wf;       // front matrix (double, or float in mixed precision)
+  int64_t ldf;
+  int e, m;
+  void *W2;             // second-level matrix of the subdomain
+  int64_t ld2;
+  const int32_t *map;   // m second-level dense positions
+  double gamma;         // kept coordinate -> sub-box constant pressure
+  const double *yf;     // front residual (dense order), for front_rhs
+  double *y2;           // second-level residual (dense order)
+};
+hipError_t front_scatter(const FrontJob *d_jobs, int njobs, int max_m, bool fp32, hipStream_t s);
+hipError_t front_rhs(const FrontJob *d_jobs, int njobs, hipStream_t s);
+hipError_t l2_residual(const SubDev *d_subs, const double *R, const int64_t *roff, double *y,
+                       const int64_t *yoff, int nsub, hipStream_t s);
+hipError_t segment_sum(int n, const int32_t *first, const double *in, double *out, hipStream_t s);
 
 struct EntDev {
   int n;          // DoFs

@@ -57,6 +57,39 @@ struct SubH {
   int Nn = 0;
   void *G1 = nullptr;           // [S_DD^-1 | Phi] (FP32 in mixed precision)
   double *Spi = nullptr;        // local coarse block S_Pi (npi x npi), setup scope
+  // two-level nested dissection (sub-box labels given): the fields above
+  // describe the second level (CSR over the separator and interface DoFs,
+  // "pressures" = the sub-box constants); n stays the full local size
+  std::vector<int32_t> part;    // sub-box labels as given (empty: none)
+  int n2 = 0;                   // CSR rows of the fields above (= n without the split)
+  int nsep = 0, nbox = 0;
+  int first_front = 0;          // fronts [first_front, first_front + nbox)
+  std::vector<int32_t> oidx;    // second-level CSR row -> full CSR row
+  int32_t *d_oidx = nullptr;
+  // the full local CSR (flux rows and local residuals) and its single-level
+  // dense positions
+  int f_nv = 0, f_nel = 0;
+  std::vector<int64_t> f_indptr;
+  std::vector<int32_t> f_indices, f_pos;
+  std::vector<double> f_vals, f_rhs;
+  int64_t *d_f_indptr = nullptr;
+  int32_t *d_f_indices = nullptr, *d_f_pos = nullptr;
+  double *d_f_vals = nullptr, *d_f_rhs = nullptr;
+  int64_t sep_off = 0;          // its separator values in the second-level vector
+};
+
+// A front of the two-level factorisation: one sub-box of a subdomain, with
+// the SubH fields describing its dense matrix [interior velocity | element
+// pressures | B (separator and interface DoFs it couples to) | rhs].
+struct FrontH {
+  SubH S;
+  int sub = 0, box = 0;
+  std::vector<int32_t> oidx;    // front CSR row -> full CSR row of its subdomain (-1: B rows)
+  std::vector<int32_t> map;     // second-level dense positions of [kept | B | rhs]
+  std::vector<int32_t> bsep;    // per B DoF: separator index, or -1 (interface DoF)
+  std::vector<int64_t> bgid;    // per B DoF: global interface id (interface DoFs)
+  double gamma = 1.0;           // kept coordinate -> sub-box constant pressure
+  int32_t *d_oidx = nullptr, *d_map = nullptr;
 };
 
 struct EntH {
@@ -99,6 +132,28 @@ struct vb_ctx {
   std::vector<SubH> subs;
   std::vector<EntH> ents;
   int max_n_csr = 0, max_N = 0, max_e = 0, max_ng = 0, max_ent = 0;
+  int max_n_full = 0;  // largest full local CSR
+  // two-level nested dissection of every subdomain (sub-box labels given)
+  bool nd = false, nd_any = false, nd_none = true;
+  std::vector<FrontH> fronts;
+  int max_nf_csr = 0, max_Nf = 0, max_ef = 0, max_nbox = 0, max_fm = 0;
+  void *FW = nullptr, *invLf = nullptr;  // front matrices and inverse diagonal blocks
+  SubDev *d_frdev = nullptr, *d_fulldev = nullptr;
+  std::vector<SubDev> frdev, fulldev;
+  int *info_f = nullptr;
+  double *hvf = nullptr;
+  double *G2 = nullptr, *G2d = nullptr;  // [interface vector | separator values | sub-box constants]
+  int64_t n_sep_tot = 0, g2_c0 = 0, n_g2 = 0;
+  int32_t *d_fr_first = nullptr;         // per subdomain: first front (nS + 1)
+  std::vector<std::vector<FrontJob>> fj_scatter;  // per box index: that box's front of every subdomain
+  std::vector<FrontJob *> d_fj_scatter;
+  int64_t *d_yofff = nullptr, *d_invofff = nullptr, *d_yoff2f = nullptr, *d_roff_f = nullptr;
+  RecJob *j_recf = nullptr, *j_rec_irf = nullptr;
+  double *r0f = nullptr;
+  int64_t n_ir2 = 0;                     // second-level part of y_ir / z_ir / zst
+  int64_t *sep_src = nullptr, *sep_dst = nullptr;  // separator corrections -> G2d
+  std::vector<std::vector<FrontJob>> fj_rhs;
+  std::vector<FrontJob *> d_fj_rhs;
 
   // device buffers
   bool fp32 = false;      // mixed precision: FP32 local Dirichlet factors
@@ -548,7 +603,7 @@ static int assemble_impl(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdo
     if (D.n <= 0 || D.nnz < 0 || !D.indptr || !D.indices || !D.data || !D.kind || !D.gid ||
         !D.pweight || !D.rhs)
       return ctx->fail(VB_ERR_ARG, "vb_assemble: bad subdomain " + std::to_string(sl));
-    S.n = D.n;
+    S.n = S.n2 = D.n;
     S.indptr.assign(D.indptr, D.indptr + D.n + 1);
     bool mono = S.indptr[0] == 0 && S.indptr[D.n] == D.nnz;
     for (int i = 0; i < D.n && mono; ++i) mono = S.indptr[i] <= S.indptr[i + 1];
@@ -619,7 +674,43 @@ static int assemble_impl(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdo
                                          " holds only part of entity " + std::to_string(e - e0));
       ctx->ents[e].subs.push_back(s);
     }
+    // sub-box labels of a one-level nested dissection: checked here, used
+    // when every subdomain of the context has them
+    S.part.clear();
+    if (D.part) {
+      S.part.assign(D.part, D.part + D.n);
+      int nbox = 0;
+      for (int i = 0; i < D.n; ++i) {
+        if (S.kind[i] == VB_KIND_INTERFACE) {
+          S.part[i] = -1;
+          continue;
+        }
+        if (S.part[i] < -1 || (S.kind[i] == VB_KIND_PRESSURE && S.part[i] < 0))
+          return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(sl) +
+                                           ": sub-box labels must be >= -1, and >= 0 for pressures");
+        nbox = std::max(nbox, S.part[i] + 1);
+      }
+      std::vector<int> npress(nbox, 0);
+      for (int i = 0; i < D.n; ++i)
+        if (S.kind[i] == VB_KIND_PRESSURE) npress[S.part[i]]++;
+      for (int b = 0; b < nbox; ++b)
+        if (!npress[b])
+          return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(sl) +
+                                           ": sub-box " + std::to_string(b) + " holds no pressure");
+      for (int i = 0; i < D.n; ++i) {
+        const int a = S.part[i];
+        if (a < 0) continue;
+        for (int64_t q = S.indptr[i]; q < S.indptr[i + 1]; ++q) {
+          const int b = S.part[S.indices[q]];
+          if (b >= 0 && b != a)
+            return ctx->fail(VB_ERR_ARG, "vb_assemble: subdomain " + std::to_string(sl) +
+                                             ": DoFs of sub-boxes " + std::to_string(a) + " and " +
+                                             std::to_string(b) + " are coupled");
+        }
+      }
+    }
     ctx->max_n_csr = std::max(ctx->max_n_csr, S.n);
+    ctx->max_n_full = std::max(ctx->max_n_full, S.n);
     ctx->max_N = std::max(ctx->max_N, S.N);
     ctx->max_e = std::max(ctx->max_e, S.e);
     ctx->max_ng = std::max(ctx->max_ng, S.ng);
@@ -634,12 +725,316 @@ static int assemble_impl(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdo
 
 }  // extern "C"
 
+// Two-level nested dissection, when every subdomain carries sub-box labels:
+// one front per sub-box (its interior velocities and element pressures,
+// bordered by the separator and interface DoFs B it couples to), and each
+// subdomain's SubH rewritten as the second level (separator velocities,
+// one "pressure" per sub-box = its constant pressure, the interface DoFs).
+static int build_nd(vb_ctx *ctx) {
+  ctx->fronts.clear();
+  ctx->max_n_csr = ctx->max_N = ctx->max_e = 0;
+  ctx->max_n_full = ctx->max_nf_csr = ctx->max_Nf = ctx->max_ef = ctx->max_nbox = ctx->max_fm = 0;
+  int64_t sep_off = 0;
+  for (int s = 0; s < ctx->nS; ++s) {
+    SubH &S = ctx->subs[s];
+    const int n = S.n;
+    S.f_indptr = S.indptr;
+    S.f_indices = S.indices;
+    S.f_vals = S.vals;
+    S.f_rhs = S.rhs;
+    S.f_pos = S.pos;
+    S.f_nv = S.nv;
+    S.f_nel = S.nel;
+    int nbox = 0;
+    for (int i = 0; i < n; ++i) nbox = std::max(nbox, S.part[i] + 1);
+    // second-level dense positions of the separator and interface DoFs
+    std::vector<int32_t> l2(n, -1);
+    int nsep = 0;
+    for (int i = 0; i < n; ++i)
+      if (S.kind[i] == VB_KIND_INTERIOR && S.part[i] < 0) l2[i] = nsep++;
+    for (int i = 0; i < n; ++i)
+      if (S.kind[i] == VB_KIND_INTERFACE) l2[i] = nsep + nbox + (S.pos[i] - S.nv - S.nel);
+    const int N2 = nsep + nbox + S.ng + 1;
+    std::vector<double> boxvol(nbox, 0.0);
+    S.first_front = (int)ctx->fronts.size();
+    std::vector<int32_t> floc(n, -1);
+    for (int b = 0; b < nbox; ++b) {
+      ctx->fronts.emplace_back();
+      FrontH &F = ctx->fronts.back();
+      F.sub = s;
+      F.box = b;
+      SubH &T = F.S;
+      std::vector<int> rows;
+      for (int i = 0; i < n; ++i)
+        if (S.kind[i] == VB_KIND_INTERIOR && S.part[i] == b) rows.push_back(i);
+      T.nv = (int)rows.size();
+      for (int i = 0; i < n; ++i)
+        if (S.kind[i] == VB_KIND_PRESSURE && S.part[i] == b) rows.push_back(i);
+      T.nel = (int)rows.size() - T.nv;
+      std::vector<int> B;
+      for (int i : rows)
+        for (int64_t q = S.indptr[i]; q < S.indptr[i + 1]; ++q) {
+          const int j = S.indices[q];
+          if (l2[j] >= 0 && floc[j] != -2) {
+            floc[j] = -2;
+            B.push_back(j);
+          }
+        }
+      std::sort(B.begin(), B.end(), [&](int a, int c) { return l2[a] < l2[c]; });
+      T.ng = (int)B.size();
+      const int nr = (int)rows.size();
+      for (int k = 0; k < nr; ++k) floc[rows[k]] = k;
+      for (int k = 0; k < T.ng; ++k) floc[B[k]] = nr + k;
+      T.n = T.n2 = nr + T.ng;
+      T.indptr.assign(1, 0);
+      T.indices.clear();
+      T.vals.clear();
+      T.rhs.clear();
+      for (int i : rows) {
+        for (int64_t q = S.indptr[i]; q < S.indptr[i + 1]; ++q) {
+          T.indices.push_back(floc[S.indices[q]]);
+          T.vals.push_back(S.vals[q]);
+        }
+        T.indptr.push_back((int64_t)T.indices.size());
+        T.rhs.push_back(S.rhs[i]);
+      }
+      for (int j : B) {
+        for (int64_t q = S.indptr[j]; q < S.indptr[j + 1]; ++q) {
+          const int c = floc[S.indices[q]];
+          if (c >= 0 && c < nr && S.part[S.indices[q]] == b) {
+            T.indices.push_back(c);
+            T.vals.push_back(S.vals[q]);
+          }
+        }
+        T.indptr.push_back((int64_t)T.indices.size());
+        T.rhs.push_back(0.0);
+      }
+      T.kind.assign(T.n, VB_KIND_INTERIOR);
+      for (int k = T.nv; k < nr; ++k) T.kind[k] = VB_KIND_PRESSURE;
+      for (int k = nr; k < T.n; ++k) T.kind[k] = VB_KIND_INTERFACE;
+      T.pos.resize(T.n);
+      std::iota(T.pos.begin(), T.pos.end(), 0);
+      T.pw.clear();
+      double ss = 0.0;
+      for (int k = T.nv; k < nr; ++k) {
+        const double w = S.pw[S.pos[rows[k]] - S.nv];
+        T.pw.push_back(w);
+        boxvol[b] += w;
+        ss += w * w;
+      }
+      T.vol = boxvol[b];
+      // the kept coordinate (last after the reflector that maps the volumes
+      // w onto it, alpha = -sign(w_last) |w|) is gamma times the constant
+      // pressure of the sub-box, gamma = sum(w) / alpha
+      const double alpha = (T.pw.back() >= 0.0) ? -std::sqrt(ss) : std::sqrt(ss);
+      F.gamma = boxvol[b] / alpha;
+      T.N = T.nv + T.nel + T.ng + 1;
+      T.e = T.nv + T.nel - 1;
+      T.ld = round_up(T.N, 32);
+      F.oidx.assign(T.n, -1);
+      for (int k = 0; k < nr; ++k) F.oidx[k] = rows[k];
+      F.map.clear();
+      F.map.push_back(nsep + b);
+      F.bsep.clear();
+      F.bgid.clear();
+      for (int j : B) {
+        F.map.push_back(l2[j]);
+        F.bsep.push_back(S.kind[j] == VB_KIND_INTERIOR ? l2[j] : -1);
+        F.bgid.push_back(S.kind[j] == VB_KIND_INTERFACE ? S.gid[j] : -1);
+      }
+      F.map.push_back(N2 - 1);
+      for (int i : rows) floc[i] = -1;
+      for (int j : B) floc[j] = -1;
+      ctx->max_nf_csr = std::max(ctx->max_nf_csr, T.n);
+      ctx->max_Nf = std::max(ctx->max_Nf, T.N);
+      ctx->max_ef = std::max(ctx->max_ef, T.e);
+      ctx->max_fm = std::max(ctx->max_fm, T.ng + 2);
+    }
+    // the second level: CSR over the separator and interface DoFs
+    std::vector<int32_t> rows2;
+    for (int i = 0; i < n; ++i)
+      if (l2[i] >= 0) rows2.push_back(i);
+    std::vector<int64_t> ip(1, 0);
+    std::vector<int32_t> ix, kd, ps;
+    std::vector<int64_t> gd;
+    std::vector<double> vl, rh;
+    std::vector<int32_t> loc2(n, -1);
+    for (size_t k = 0; k < rows2.size(); ++k) loc2[rows2[k]] = (int32_t)k;
+    for (int i : rows2) {
+      for (int64_t q = S.indptr[i]; q < S.indptr[i + 1]; ++q) {
+        const int c = loc2[S.indices[q]];
+        if (c < 0) continue;
+        ix.push_back(c);
+        vl.push_back(S.vals[q]);
+      }
+      ip.push_back((int64_t)ix.size());
+      rh.push_back(S.rhs[i]);
+      kd.push_back(S.kind[i]);
+      gd.push_back(S.gid[i]);
+      ps.push_back(l2[i]);
+    }
+    S.indptr.swap(ip);
+    S.indices.swap(ix);
+    S.vals.swap(vl);
+    S.rhs.swap(rh);
+    S.kind.swap(kd);
+    S.gid.swap(gd);
+    S.pos.swap(ps);
+    S.oidx = rows2;
+    S.n2 = (int)rows2.size();
+    S.nv = nsep;
+    S.nel = nbox;
+    S.pw = boxvol;
+    S.nsep = nsep;
+    S.nbox = nbox;
+    S.N = N2;
+    S.e = nsep + nbox - 1;
+    S.ld = round_up(S.N, 32);
+    S.sep_off = sep_off;
+    sep_off += nsep;
+    ctx->max_n_csr = std::max(ctx->max_n_csr, S.n2);
+    ctx->max_N = std::max(ctx->max_N, S.N);
+    ctx->max_e = std::max(ctx->max_e, S.e);
+    ctx->max_n_full = std::max(ctx->max_n_full, S.n);
+    ctx->max_nbox = std::max(ctx->max_nbox, nbox);
+  }
+  ctx->n_sep_tot = sep_off;
+  ctx->nd = true;
+  return VB_OK;
+}
+
+// Device data of the two-level factorisation: front matrices and their
+// descriptors, the full local CSR views, the second-level vector layout
+// G2 = [global interface vector | separator values | sub-box constants] and
+// the scatter jobs (one list per sub-box index: no two jobs of a list add
+// into the same second-level matrix).
+static int finalize_nd(vb_ctx *ctx) {
+  const int nS = ctx->nS, nF = (int)ctx->fronts.size();
+  int64_t ftot = 0, fitot = 0, fhtot = 0;
+  for (auto &F : ctx->fronts) {
+    SubH &T = F.S;
+    T.W_off = ftot;
+    ftot += T.ld * T.N;
+    T.inv_off = fitot;
+    fitot += (int64_t)((T.e + NB - 1) / NB) * NB * NB;
+    T.hv_off = fhtot;
+    fhtot += T.nel + 1;
+  }
+  char *fw = nullptr, *fi = nullptr;
+  UCHK(ctx->dalloc(&fw, (size_t)std::max<int64_t>(ftot, 1) * ctx->wsz));
+  UCHK(ctx->dalloc(&fi, (size_t)std::max<int64_t>(fitot, 1) * ctx->wsz));
+  ctx->FW = fw;
+  ctx->invLf = fi;
+  UCHK(ctx->dalloc(&ctx->hvf, std::max<int64_t>(fhtot, 1)));
+  UCHK(ctx->dalloc(&ctx->info_f, std::max(nF, 1)));
+  ctx->g2_c0 = ctx->nG + nS + ctx->n_sep_tot;
+  ctx->n_g2 = ctx->g2_c0 + nF;
+  UCHK(ctx->dalloc(&ctx->G2, ctx->n_g2));
+  UCHK(ctx->dalloc(&ctx->G2d, ctx->n_g2));
+  ctx->frdev.assign(nF, SubDev{});
+  for (int f = 0; f < nF; ++f) {
+    FrontH &F = ctx->fronts[f];
+    SubH &T = F.S;
+    const SubH &P = ctx->subs[F.sub];
+    // B DoFs: separator values or interface ids in G2
+    T.gidl.resize(T.ng);
+    T.gid.assign(T.n, -1);
+    const int nr = T.nv + T.nel;
+    for (int k = 0; k < T.ng; ++k) {
+      T.gidl[k] = F.bsep[k] >= 0 ? ctx->nG + nS + P.sep_off + F.bsep[k] : F.bgid[k];
+      T.gid[nr + k] = T.gidl[k];
+    }
+    UCHK(ctx->upload(&T.d_indptr, T.indptr));
+    UCHK(ctx->upload(&T.d_indices, T.indices));
+    UCHK(ctx->upload(&T.d_vals, T.vals));
+    UCHK(ctx->upload(&T.d_rhs, T.rhs));
+    UCHK(ctx->upload(&T.d_pos, T.pos));
+    UCHK(ctx->upload(&T.d_kind, T.kind));
+    UCHK(ctx->upload(&T.d_gid, T.gid));
+    UCHK(ctx->upload(&T.d_pw, T.pw));
+    UCHK(ctx->upload(&T.d_gidl, T.gidl));
+    UCHK(ctx->upload(&F.d_oidx, F.oidx));
+    UCHK(ctx->upload(&F.d_map, F.map));
+    SubDev &D = ctx->frdev[f];
+    D.W = (char *)ctx->FW + T.W_off * ctx->wsz;
+    D.ld = T.ld;
+    D.nv = T.nv;
+    D.nel = T.nel;
+    D.ng = T.ng;
+    D.N = T.N;
+    D.e = T.e;
+    D.n_csr = T.n;
+    D.indptr = T.d_indptr;
+    D.indices = T.d_indices;
+    D.vals = T.d_vals;
+    D.rhs = T.d_rhs;
+    D.pos = T.d_pos;
+    D.pweight = T.d_pw;
+    D.hv = ctx->hvf + T.hv_off;
+    D.gidl = T.d_gidl;
+    D.oidx = F.d_oidx;
+  }
+  UCHK(ctx->upload(&ctx->d_frdev, ctx->frdev));
+  ctx->fulldev.assign(nS, SubDev{});
+  std::vector<int32_t> first(nS + 1, 0);
+  for (int s = 0; s < nS; ++s) {
+    SubH &S = ctx->subs[s];
+    UCHK(ctx->upload(&S.d_f_indptr, S.f_indptr));
+    UCHK(ctx->upload(&S.d_f_indices, S.f_indices));
+    UCHK(ctx->upload(&S.d_f_vals, S.f_vals));
+    UCHK(ctx->upload(&S.d_f_rhs, S.f_rhs));
+    UCHK(ctx->upload(&S.d_f_pos, S.f_pos));
+    SubDev &D = ctx->fulldev[s];
+    D.nv = S.f_nv;
+    D.nel = S.f_nel;
+    D.ng = S.ng;
+    D.n_csr = S.n;
+    D.indptr = S.d_f_indptr;
+    D.indices = S.d_f_indices;
+    D.vals = S.d_f_vals;
+    D.rhs = S.d_f_rhs;
+    D.pos = S.d_f_pos;
+    D.b0 = ctx->b0 + S.b0_off;
+    first[s + 1] = S.first_front + S.nbox;
+  }
+  UCHK(ctx->upload(&ctx->d_fulldev, ctx->fulldev));
+  UCHK(ctx->upload(&ctx->d_fr_first, first));
+  ctx->fj_scatter.assign(ctx->max_nbox, {});
+  for (int s = 0; s < nS; ++s) {
+    const SubH &S = ctx->subs[s];
+    for (int b = 0; b < S.nbox; ++b) {
+      const FrontH &F = ctx->fronts[S.first_front + b];
+      FrontJob J{};
+      J.Wf = (char *)ctx->FW + F.S.W_off * ctx->wsz;
+      J.ldf = F.S.ld;
+      J.e = F.S.e;
+      J.m = F.S.ng + 2;
+      J.W2 = (char *)ctx->W + S.W_off * ctx->wsz;
+      J.ld2 = S.ld;
+      J.map = F.d_map;
+      J.gamma = F.gamma;
+      ctx->fj_scatter[b].push_back(J);
+    }
+  }
+  ctx->d_fj_scatter.assign(ctx->max_nbox, nullptr);
+  for (int b = 0; b < ctx->max_nbox; ++b) UCHK(ctx->upload(&ctx->d_fj_scatter[b], ctx->fj_scatter[b]));
+  return VB_OK;
+}
+
 // Device copies of every assembled problem and the dense workspace (run by
 // the first vb_setup, once all problems are known).
 static int finalize_device(vb_ctx *ctx) {
   const int n_sub = ctx->nS;
   const int n_ent = (int)ctx->ents.size();
   const int64_t n_iface = ctx->nG;
+  {
+    bool all = n_sub > 0;
+    for (const auto &S : ctx->subs) all = all && !S.part.empty();
+    if (all) {
+      int rc = build_nd(ctx);
+      if (rc) return rc;
+    }
+  }
   // ---- device copies of the caller's data and the dense workspace
   int64_t wtot = 0, itot = 0, btot = 0, htot = 0, wmax1 = 1;
   for (auto &S : ctx->subs) {
@@ -656,7 +1051,7 @@ static int finalize_device(vb_ctx *ctx) {
     size_t fre = 0, tot = 0;
     UCHK(hipMemGetInfo(&fre, &tot));
     const double lim = ctx->opt.local_mem_limit > 0.0 ? ctx->opt.local_mem_limit : 0.45 * (double)fre;
-    ctx->stream_w = !ctx->fp32 && (double)wtot * (double)ctx->wsz > lim;
+    ctx->stream_w = !ctx->fp32 && !ctx->nd && (double)wtot * (double)ctx->wsz > lim;
     ctx->waves.clear();
     int64_t wcap = 0;
     const int64_t cap = ctx->stream_w ? std::max<int64_t>(wmax1, (int64_t)(lim / ctx->wsz)) : wtot;
@@ -721,7 +1116,7 @@ static int finalize_device(vb_ctx *ctx) {
     D.ng = S.ng;
     D.N = S.N;
     D.e = S.e;
-    D.n_csr = S.n;
+    D.n_csr = S.n2;
     D.indptr = S.d_indptr;
     D.indices = S.d_indices;
     D.vals = S.d_vals;
@@ -734,8 +1129,16 @@ static int finalize_device(vb_ctx *ctx) {
     D.n_ent = (int)S.ents.size();
     D.ent = S.d_ents;
     D.ent_off = S.d_entoff;
+    if (ctx->nd) {
+      UCHK(ctx->upload(&S.d_oidx, S.oidx));
+      D.oidx = S.d_oidx;
+    }
   }
   UCHK(ctx->upload(&ctx->d_subdev, ctx->subdev));
+  if (ctx->nd) {
+    int rc = finalize_nd(ctx);
+    if (rc) return rc;
+  }
   ctx->entdev.resize(n_ent);
   for (int e = 0; e < n_ent; ++e) {
     EntH &H = ctx->ents[e];
@@ -1821,6 +2224,74 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
   return VB_OK;
 }
 
+// The two-level factorisation: every front (sub-box) densified, its
+// pressures split and factored up to its kept coordinate; then every
+// subdomain's second-level matrix (separator and interface rows of the local
+// CSR) receives the fronts' trailing blocks, in sub-box order, and is split
+// and factored like a single-level local matrix.
+template <typename T>
+static int factor_nd_t(vb_ctx *ctx, bool timed) {
+  hipStream_t st = ctx->stream;
+  const bool f32 = ctx->fp32;
+  const int nS = ctx->nS, nF = (int)ctx->fronts.size();
+  const FrontH &FL = ctx->fronts.back();
+  CHK(hipMemsetAsync(ctx->FW, 0, (FL.S.W_off + FL.S.ld * FL.S.N) * ctx->wsz, st));
+  CHK(densify(ctx->d_frdev, nF, ctx->max_nf_csr, f32, st));
+  CHK(house_pressure(ctx->d_frdev, nF, ctx->max_Nf, f32, st));
+  CHK(hipMemsetAsync(ctx->info_f, 0, nF * sizeof(int), st));
+  {
+    std::vector<LdlJob<T>> jobs;
+    for (int f = 0; f < nF; ++f) {
+      const SubH &F = ctx->fronts[f].S;
+      jobs.push_back({(T *)ctx->FW + F.W_off, F.ld, F.N, F.e, F.nv, 0, (T *)ctx->invLf + F.inv_off,
+                      ctx->info_f + f});
+    }
+    int rc = run_ldl(ctx, jobs, ctx->max_Nf, ctx->max_ef, timed);
+    if (rc) return rc;
+  }
+  {
+    std::vector<int> h(nF);
+    CHK(hipMemcpyAsync(h.data(), ctx->info_f, nF * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int f = 0; f < nF; ++f)
+      if (h[f])
+        return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
+                                             std::to_string(ctx->fronts[f].sub) + " at column " +
+                                             std::to_string(h[f] - 1) + " of its sub-box " +
+                                             std::to_string(ctx->fronts[f].box));
+  }
+  const SubH &SL = ctx->subs.back();
+  CHK(hipMemsetAsync(ctx->W, 0, (SL.W_off + SL.ld * SL.N) * ctx->wsz, st));
+  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, f32, st));
+  for (int b = 0; b < ctx->max_nbox; ++b)
+    CHK(front_scatter(ctx->d_fj_scatter[b], (int)ctx->fj_scatter[b].size(), ctx->max_fm, f32, st));
+  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, f32, st));
+  CHK(hipMemsetAsync(ctx->info, 0, nS * sizeof(int), st));
+  {
+    std::vector<LdlJob<T>> jobs;
+    for (int s = 0; s < nS; ++s) {
+      const SubH &S = ctx->subs[s];
+      jobs.push_back({(T *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0, (T *)ctx->invL + S.inv_off,
+                      ctx->info + s});
+    }
+    int rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, timed);
+    if (rc) return rc;
+  }
+  std::vector<int> h(nS);
+  CHK(hipMemcpyAsync(h.data(), ctx->info, nS * sizeof(int), hipMemcpyDeviceToHost, st));
+  CHK(hipStreamSynchronize(st));
+  for (int s = 0; s < nS; ++s)
+    if (h[s])
+      return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
+                                           std::to_string(s) + " at column " + std::to_string(h[s] - 1) +
+                                           " of its separator level");
+  return VB_OK;
+}
+
+static int factor_nd(vb_ctx *ctx, bool timed) {
+  return ctx->fp32 ? factor_nd_t<float>(ctx, timed) : factor_nd_t<double>(ctx, timed);
+}
+
 extern "C" {
 
 static int setup_impl(vb_ctx *ctx);
@@ -1888,10 +2359,13 @@ static int setup_impl(vb_ctx *ctx) {
   const bool f32 = ctx->fp32;
   auto Xptr = [&](const SubH &S) -> void * { return S.X; };
   CHK(hipMemsetAsync(ctx->info, 0, (4 * (size_t)nS + 64 + 4 * ctx->ents.size()) * sizeof(int), st));
-  CHK(flux_rows(ctx->d_subdev, nS, ctx->max_n_csr, st));
+  if (ctx->nd)
+    CHK(flux_rows(ctx->d_fulldev, nS, ctx->max_n_full, st));
+  else
+    CHK(flux_rows(ctx->d_subdev, nS, ctx->max_n_csr, st));
   ctx->w_wave = -1;
   for (const auto &wv : ctx->waves) {
-    int rc = factor_wave(ctx, wv.first, wv.second, true);
+    int rc = ctx->nd ? factor_nd(ctx, true) : factor_wave(ctx, wv.first, wv.second, true);
     if (rc) return rc;
     if (!ctx->stream_w) continue;
     ctx->w_wave = (int)(&wv - ctx->waves.data());
@@ -2548,9 +3022,10 @@ static int setup_impl(vb_ctx *ctx) {
     int rc = autotune_gemvs(ctx);
     if (rc) return rc;
   }
-  // ---- 10. recovery structures
+  // ---- 10. recovery structures (second level first, then the fronts)
   {
-    std::vector<int64_t> yoff(nS), invoff(nS);
+    const int nF = (int)ctx->fronts.size();
+    std::vector<int64_t> yoff(nS), invoff(nS), yofff(nF), invofff(nF);
     int64_t tot = 0, otot = 0;
     ctx->rec_off.assign(nS + 1, 0);
     for (int s = 0; s < nS; ++s) {
@@ -2559,26 +3034,60 @@ static int setup_impl(vb_ctx *ctx) {
       invoff[s] = ctx->subs[s].inv_off;
       ctx->rec_off[s + 1] = ctx->rec_off[s] + ctx->subs[s].n;
     }
+    for (int f = 0; f < nF; ++f) {
+      yofff[f] = tot;
+      tot += ctx->fronts[f].S.e + 1;
+      invofff[f] = ctx->fronts[f].S.inv_off;
+    }
     otot = ctx->rec_off[nS];
     UCHK(ctx->dalloc(&ctx->yrec, tot));
     UCHK(ctx->dalloc(&ctx->zrec, tot));
     UCHK(ctx->dalloc(&ctx->rec_out, otot));
     UCHK(ctx->upload(&ctx->d_yoff, yoff));
     UCHK(ctx->upload(&ctx->d_invoff, invoff));
-    std::vector<RecJob> rj(nS);
-    for (int s = 0; s < nS; ++s) {
+    // second-level jobs: separator and interface outputs; in the two-level
+    // case also the separator values and the sub-box constants into G2
+    auto l2job = [&](int s, const double *z, double *out) {
       SubH &S = ctx->subs[s];
-      rj[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
-               ctx->zrec + yoff[s], ctx->rec_out + ctx->rec_off[s]};
-    }
+      RecJob J{s, S.n2, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off, z, out};
+      if (ctx->nd) {
+        J.oidx = S.d_oidx;
+        J.sep_out = ctx->G2 + ctx->nG + nS + S.sep_off;
+        J.c_out = ctx->G2 + ctx->g2_c0 + S.first_front;
+      }
+      return J;
+    };
+    // front jobs: interior velocity and pressure outputs (constant = G2 entry)
+    auto frjob = [&](int f, const double *z, double *out) {
+      FrontH &F = ctx->fronts[f];
+      SubH &T = F.S;
+      RecJob J{f, T.n, T.nv, T.nel, T.d_kind, T.d_pos, T.d_gid, ctx->hvf + T.hv_off, z, out};
+      J.oidx = F.d_oidx;
+      return J;
+    };
+    std::vector<RecJob> rj(nS), rjf(nF);
+    for (int s = 0; s < nS; ++s) rj[s] = l2job(s, ctx->zrec + yoff[s], ctx->rec_out + ctx->rec_off[s]);
+    for (int f = 0; f < nF; ++f)
+      rjf[f] = frjob(f, ctx->zrec + yofff[f], ctx->rec_out + ctx->rec_off[ctx->fronts[f].sub]);
     UCHK(ctx->upload(&ctx->j_rec, rj));
-    if (ctx->fp32) {  // refinement buffers: dense per-subdomain vectors of length N
-      std::vector<int64_t> yoff2(nS), uoff(nS);
+    if (nF) {
+      UCHK(ctx->upload(&ctx->d_yofff, yofff));
+      UCHK(ctx->upload(&ctx->d_invofff, invofff));
+      UCHK(ctx->upload(&ctx->j_recf, rjf));
+    }
+    if (ctx->fp32) {  // refinement buffers: dense per-subdomain / per-front vectors of length N
+      std::vector<int64_t> yoff2(nS), uoff(nS), yoff2f(nF), roff(nF);
       int64_t t2 = 0;
       for (int s = 0; s < nS; ++s) {
         yoff2[s] = t2;
         t2 += ctx->subs[s].N;
         uoff[s] = ctx->rec_off[s];
+      }
+      ctx->n_ir2 = t2;
+      for (int f = 0; f < nF; ++f) {
+        yoff2f[f] = t2;
+        t2 += ctx->fronts[f].S.N;
+        roff[f] = ctx->rec_off[ctx->fronts[f].sub];
       }
       ctx->n_ir = t2;
       UCHK(ctx->dalloc(&ctx->y_ir, t2));
@@ -2594,12 +3103,11 @@ static int setup_impl(vb_ctx *ctx) {
       UCHK(ctx->dalloc(&ctx->dx, nG + nS));
       UCHK(ctx->upload(&ctx->d_yoff2, yoff2));
       UCHK(ctx->upload(&ctx->d_uoff, uoff));
-      std::vector<RecJob> rj2(nS);
+      std::vector<RecJob> rj2(nS), rj2f(nF);
       std::vector<std::vector<int64_t>> own(nG);
       for (int s = 0; s < nS; ++s) {
         SubH &S = ctx->subs[s];
-        rj2[s] = {s, S.n, S.nv, S.nel, S.d_kind, S.d_pos, S.d_gid, ctx->hv + S.hv_off,
-                  ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]};
+        rj2[s] = l2job(s, ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]);
         for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff2[s] + S.e + 1 + l);
       }
       UCHK(ctx->upload(&ctx->j_rec_ir, rj2));
@@ -2610,6 +3118,44 @@ static int setup_impl(vb_ctx *ctx) {
       }
       UCHK(ctx->upload(&ctx->ir_ptr, ptr));
       UCHK(ctx->upload(&ctx->ir_idx, idx));
+      if (nF) {
+        for (int f = 0; f < nF; ++f)
+          rj2f[f] = frjob(f, ctx->zst + yoff2f[f], ctx->u_loc + ctx->rec_off[ctx->fronts[f].sub]);
+        UCHK(ctx->upload(&ctx->j_rec_irf, rj2f));
+        UCHK(ctx->upload(&ctx->d_yoff2f, yoff2f));
+        UCHK(ctx->upload(&ctx->d_roff_f, roff));
+        UCHK(ctx->dalloc(&ctx->r0f, nF));
+        // front residual rows -> second-level residual, one list per sub-box index
+        ctx->fj_rhs.assign(ctx->max_nbox, {});
+        for (int s = 0; s < nS; ++s) {
+          const SubH &S = ctx->subs[s];
+          for (int b = 0; b < S.nbox; ++b) {
+            const int f = S.first_front + b;
+            const FrontH &F = ctx->fronts[f];
+            FrontJob J{};
+            J.e = F.S.e;
+            J.m = F.S.ng + 2;
+            J.map = F.d_map;
+            J.gamma = F.gamma;
+            J.yf = ctx->y_ir + yoff2f[f];
+            J.y2 = ctx->y_ir + yoff2[s];
+            ctx->fj_rhs[b].push_back(J);
+          }
+        }
+        ctx->d_fj_rhs.assign(ctx->max_nbox, nullptr);
+        for (int b = 0; b < ctx->max_nbox; ++b) UCHK(ctx->upload(&ctx->d_fj_rhs[b], ctx->fj_rhs[b]));
+        // separator corrections of the second level -> G2d
+        std::vector<int64_t> src, dst;
+        for (int s = 0; s < nS; ++s) {
+          const SubH &S = ctx->subs[s];
+          for (int k = 0; k < S.nsep; ++k) {
+            src.push_back(yoff2[s] + k);
+            dst.push_back(ctx->nG + nS + S.sep_off + k);
+          }
+        }
+        UCHK(ctx->upload(&ctx->sep_src, src));
+        UCHK(ctx->upload(&ctx->sep_dst, dst));
+      }
     }
   }
   CHK(hipEventRecord(ctx->ev1, st));
@@ -2925,7 +3471,47 @@ static void combine_info(const std::vector<vb_solve_info> &pi, vb_solve_info *ou
 // factor over the eliminated columns (eq. uipi); on return the rows e+1.. of
 // y hold the condensed interface residual of every subdomain and r0 the
 // residual of its constant-pressure equation.
+// u_loc <- the local solution vectors from the interior state zst and the
+// interface vector x (two-level: second level first, writing the separator
+// values and sub-box constants into G2, then the fronts).
+static int state_to_local(vb_ctx *ctx, const double *x_orig) {
+  hipStream_t st = ctx->stream;
+  CHK(recover_out(ctx->j_rec_ir, ctx->nS, x_orig, ctx->nG, st));
+  if (ctx->nd)
+    CHK(recover_out(ctx->j_rec_irf, (int)ctx->fronts.size(), ctx->G2, ctx->g2_c0, st));
+  return VB_OK;
+}
+
+// Two-level version of condense_residual: the local residual in every front,
+// forward-substituted through the front's factor; its trailing rows added
+// into the second-level residual (in sub-box order) with the separator and
+// interface rows of the local residual; then the second-level forward
+// substitution.
+static int condense_residual_nd(vb_ctx *ctx, const double *x_orig) {
+  hipStream_t st = ctx->stream;
+  const int nS = ctx->nS, nF = (int)ctx->fronts.size(), nb = ctx->opt.panel;
+  CHK(hipMemcpyAsync(ctx->G2, x_orig, (ctx->nG + nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
+  int rc = state_to_local(ctx, x_orig);
+  if (rc) return rc;
+  CHK(local_residual(ctx->d_fulldev, ctx->u_loc, ctx->d_uoff, ctx->R_loc, nS, ctx->max_n_full, st));
+  CHK(residual_to_dense(ctx->d_frdev, ctx->R_loc, ctx->d_roff_f, ctx->y_ir, ctx->d_yoff2f, ctx->r0f, nF,
+                        ctx->max_nf_csr, st));
+  for (int i0 = 0; i0 < ctx->max_ef; i0 += nb)
+    CHK(forward_step(ctx->d_frdev, ctx->invLf, ctx->d_invofff, ctx->y_ir, ctx->z_ir, ctx->d_yoff2f, nF,
+                     i0, nb, ctx->max_Nf, ctx->fp32, st));
+  CHK(hipMemsetAsync(ctx->y_ir, 0, ctx->n_ir2 * sizeof(double), st));
+  for (int b = 0; b < ctx->max_nbox; ++b)
+    CHK(front_rhs(ctx->d_fj_rhs[b], (int)ctx->fj_rhs[b].size(), st));
+  CHK(l2_residual(ctx->d_subdev, ctx->R_loc, ctx->d_uoff, ctx->y_ir, ctx->d_yoff2, nS, st));
+  CHK(segment_sum(nS, ctx->d_fr_first, ctx->r0f, ctx->r0, st));
+  for (int i0 = 0; i0 < ctx->max_e; i0 += nb)
+    CHK(forward_step(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir, ctx->d_yoff2, nS, i0,
+                     nb, ctx->max_N, ctx->fp32, st));
+  return VB_OK;
+}
+
 static int condense_residual(vb_ctx *ctx, const double *x_orig) {
+  if (ctx->nd) return condense_residual_nd(ctx, x_orig);
   hipStream_t st = ctx->stream;
   CHK(recover_out(ctx->j_rec_ir, ctx->nS, x_orig, ctx->nG, st));
   CHK(local_residual(ctx->d_subdev, ctx->u_loc, ctx->d_uoff, ctx->R_loc, ctx->nS, ctx->max_n_csr,
@@ -2943,12 +3529,31 @@ static int condense_residual(vb_ctx *ctx, const double *x_orig) {
 // K_II dz = y_I - C dx through L^T, then zst += dz.
 static int interior_correction(vb_ctx *ctx, const double *dx) {
   hipStream_t st = ctx->stream;
-  CHK(back_rhs(ctx->d_subdev, ctx->z_ir, dx, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e,
-               ctx->fp32, st));
   const int nb = ctx->opt.panel;
-  for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
-    CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir,
-                          ctx->d_yoff2, ctx->nS, j0, nb, ctx->fp32, st));
+  if (ctx->max_e > 0) {
+    CHK(back_rhs(ctx->d_subdev, ctx->z_ir, dx, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e,
+                 ctx->fp32, st));
+    for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+      CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir,
+                            ctx->d_yoff2, ctx->nS, j0, nb, ctx->fp32, st));
+  }
+  if (ctx->nd) {
+    // the fronts see the interface correction and the separator corrections
+    // of the second level through G2d
+    const int nS = ctx->nS, nF = (int)ctx->fronts.size();
+    if (dx)
+      CHK(hipMemcpyAsync(ctx->G2d, dx, (ctx->nG + nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    else
+      CHK(hipMemsetAsync(ctx->G2d, 0, (ctx->nG + nS) * sizeof(double), st));
+    CHK(scatter_copy((int)ctx->n_sep_tot, ctx->z_ir, ctx->sep_src, ctx->sep_dst, ctx->G2d, 1.0, st));
+    if (ctx->max_ef > 0) {
+      CHK(back_rhs(ctx->d_frdev, ctx->z_ir, ctx->G2d, ctx->y_ir, ctx->d_yoff2f, nF, ctx->max_ef,
+                   ctx->fp32, st));
+      for (int j0 = ((ctx->max_ef - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+        CHK(recover_backsolve(ctx->d_frdev, ctx->invLf, ctx->d_invofff, ctx->y_ir, ctx->z_ir,
+                              ctx->d_yoff2f, nF, j0, nb, ctx->fp32, st));
+    }
+  }
   CHK(axpy(ctx->n_ir, 1.0, ctx->z_ir, ctx->zst, st));
   return VB_OK;
 }
@@ -3177,7 +3782,12 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
       rc = interior_correction(ctx, nullptr);
       if (rc) return rc;
     }
-    CHK(recover_out(ctx->j_rec_ir, ctx->nS, x_dev, ctx->nG, st));
+    if (ctx->nd)
+      CHK(hipMemcpyAsync(ctx->G2, x_dev, (ctx->nG + ctx->nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    {
+      int rc = state_to_local(ctx, x_dev);
+      if (rc) return rc;
+    }
     CHK(hipMemcpyAsync(ctx->rec_out, ctx->u_loc, ctx->rec_off[ctx->nS] * sizeof(double),
                        hipMemcpyDeviceToDevice, st));
     if (out_dev)
@@ -3186,6 +3796,30 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
     return VB_OK;
   }
   const int nb = ctx->opt.panel;  // the panel width the factorisation used
+  if (ctx->nd) {
+    // second level: separator velocities and sub-box constants; then every
+    // front from its separator and interface values and its constant
+    const int nS = ctx->nS, nF = (int)ctx->fronts.size();
+    if (ctx->max_e > 0) {
+      CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, nS, ctx->max_e, ctx->fp32, st));
+      for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+        CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->zrec, ctx->d_yoff,
+                              nS, j0, nb, ctx->fp32, st));
+    }
+    CHK(hipMemcpyAsync(ctx->G2, x_dev, (ctx->nG + nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
+    CHK(recover_out(ctx->j_rec, nS, x_dev, ctx->nG, st));
+    if (ctx->max_ef > 0) {
+      CHK(recover_rhs(ctx->d_frdev, ctx->G2, ctx->yrec, ctx->d_yofff, nF, ctx->max_ef, ctx->fp32, st));
+      for (int j0 = ((ctx->max_ef - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+        CHK(recover_backsolve(ctx->d_frdev, ctx->invLf, ctx->d_invofff, ctx->yrec, ctx->zrec,
+                              ctx->d_yofff, nF, j0, nb, ctx->fp32, st));
+    }
+    CHK(recover_out(ctx->j_recf, nF, ctx->G2, ctx->g2_c0, st));
+    if (out_dev)
+      CHK(hipMemcpyAsync(out_dev, ctx->rec_out, ctx->rec_off[nS] * sizeof(double),
+                         hipMemcpyDeviceToDevice, st));
+    return VB_OK;
+  }
   // with several waves: first the wave whose factors W still holds, then the
   // others, each factored again
   const int nw = (int)ctx->waves.size(), first = std::max(ctx->w_wave, 0);

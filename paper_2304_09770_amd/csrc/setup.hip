@@ -641,8 +641,9 @@ hipError_t local_residual(const SubDev *d_subs, const double *u, const int64_t *
   return hipGetLastError();
 }
 
-// y[pos[i]] = R[i] (dense order), pressures rotated by the reflector H;
-// r0 = sum of the (unrotated) pressure residuals.  One block per subdomain.
+// y[pos[i]] = R[i] (dense order; R[oidx[i]] through the row map when given,
+// 0 where it is -1), pressures rotated by the reflector H; r0 = sum of the
+// (unrotated) pressure residuals.  One block per subdomain.
 __global__ void k_residual_to_dense(const SubDev *subs, const double *R, const int64_t *roff,
                                     double *y, const int64_t *yoff, double *r0) {
   const SubDev S = subs[blockIdx.x];
@@ -652,10 +653,12 @@ __global__ void k_residual_to_dense(const SubDev *subs, const double *R, const i
   double vr = 0.0, sr = 0.0;
   for (int i = threadIdx.x; i < S.n_csr; i += blockDim.x) {
     const int p = S.pos[i];
-    ys[p] = Rs[i];
+    const int o = S.oidx ? S.oidx[i] : i;
+    const double v = o >= 0 ? Rs[o] : 0.0;
+    ys[p] = v;
     if (p >= S.nv && p < S.nv + S.nel) {
-      vr += S.hv[p - S.nv] * Rs[i];
-      sr += Rs[i];
+      vr += S.hv[p - S.nv] * v;
+      sr += v;
     }
   }
   vr = block_sum(vr, red);

@@ -58,8 +58,37 @@ def test_setup_flops_report_on_a_small_workload():
     wl, _ = make_workload("c1", workers=1)
     lu = LocalSchur(wl["subs"][0], condense=False).lu
     rep = b.setup_flops(wl, [b.sparse_lu_flops(lu)], 10.0)
-    assert 0 < rep["sparse_factor_est"] < rep["dense_executed"]
-    assert rep["dense_tflops_per_setup_s"] == rep["dense_executed"] / 1e-2 / 1e12
+    assert 0 < rep["sparse_factor_est"] < rep["dense_single_level"]
+    assert rep["dense_tflops_per_setup_s"] == rep["dense_single_level"] / 1e-2 / 1e12
+    # the two-level factorisation: fronts of the 2x2x2 sub-boxes, then the
+    # separators, fewer operations than one dense factorisation
+    assert 0 < rep["nested_executed"] < rep["dense_single_level"]
+    assert rep["nested_tflops_per_setup_s"] == rep["nested_executed"] / 1e-2 / 1e12
+
+
+def test_nested_flops_match_brute_force():
+    """One subdomain of 8 DoFs: sub-box 0 = {0, 1 (pressure)}, sub-box 1 =
+    {2, 3 (pressure)}, separator {4}, interface {5, 6}; row couplings give
+    B_0 = {4, 5}, B_1 = {4, 6}."""
+    import numpy as np
+    import scipy.sparse as sp
+    b = _bench()
+    kind = np.array([0, 2, 0, 2, 0, 1, 1, 2])
+    part = np.array([0, 0, 1, 1, -1, -1, -1, 0])
+    edges = [(0, 1), (0, 4), (1, 5), (2, 3), (2, 4), (3, 6), (0, 7), (4, 5), (5, 6)]
+    A = sp.lil_matrix((8, 8))
+    for i, j in edges:
+        A[i, j] = A[j, i] = 1.0
+    for i in range(8):
+        A[i, i] = 1.0
+    A = A.tocsr()
+    wl = {"subs": [{"kind": kind, "part": part, "indptr": A.indptr, "indices": A.indices}]}
+    brute = lambda m, e: sum(t * t - 1 for t in range(m - e + 1, m + 1))
+    # sub-box 0: rows {0, 1, 7}, e = 2, B = {4, 5}; sub-box 1: rows {2, 3},
+    # e = 1, B = {4, 6}; second level: separator {4} + 2 sub-box constants,
+    # e = 2, onto 2 interface DoFs
+    want = brute(2 + 1 + 2, 2) + brute(1 + 1 + 2, 1) + brute(2 + 2, 2)
+    assert b.nested_condensation_flops(wl) == float(want)
 
 
 def test_cpu_baseline_sample_and_full_oracle_on_c1():

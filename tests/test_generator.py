@@ -288,3 +288,32 @@ def test_workloads_meet_the_assemble_contract(name):
         assert gid.min() >= 0 and gid.max() < n_iface
         for e in np.unique(owner[gid]):  # every entity it touches, whole
             assert np.sum(owner[gid] == e) == len(wl["ents"][e]["gids"])
+
+
+@pytest.mark.parametrize("name", ["c1", "t12u"])
+def test_sub_box_labels_split_each_subdomain(name):
+    """The sub-box labels of every subdomain: a geometric halving of its box
+    of elements; the eliminated DoFs of two sub-boxes never share a matrix
+    entry, every pressure lies in a sub-box, interface DoFs carry -1, and
+    the separator (interior velocities labelled -1) is exactly the set of
+    interior velocities coupled to two or more sub-boxes."""
+    import scipy.sparse as sp
+    from inputs.workloads import make_workload
+    wl, _ = make_workload(name, workers=2)
+    for sd in wl["subs"]:
+        kind, part = sd["kind"], sd["part"]
+        n = len(kind)
+        K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(n, n)).tocoo()
+        a, b = part[K.row], part[K.col]
+        assert not np.any((a >= 0) & (b >= 0) & (a != b))
+        assert np.all(part[kind == 2] >= 0) and np.all(part[kind == 1] == -1)
+        nb = part.max() + 1
+        assert 1 <= nb <= 8 and set(np.unique(part[part >= 0])) == set(range(nb))
+        # interior velocity DoFs reached from several sub-boxes' eliminated DoFs
+        elim = part >= 0
+        touch = sp.csr_matrix((np.ones(K.nnz)[elim[K.col]], (K.row[elim[K.col]], part[K.col][elim[K.col]])),
+                              shape=(n, nb))
+        multi = np.asarray((touch > 0).sum(axis=1)).ravel() >= 2
+        sep = (kind == 0) & (part < 0)
+        assert np.all(sep <= multi | (np.asarray((touch > 0).sum(axis=1)).ravel() == 0))
+        assert not np.any(multi & (kind == 0) & (part >= 0))

@@ -173,6 +173,26 @@ def test_non_spd_local_block_is_reported(vb, c1):
         vb.vb_destroy(ctx)
 
 
+def test_bad_sub_box_labels_are_rejected(vb, c1):
+    """Sub-box labels whose eliminated DoFs couple across sub-boxes, or a
+    pressure on the separator, make vb_assemble return VB_ERR_ARG."""
+    coupled = _copy(c1)
+    sd = coupled["subs"][0]
+    inner = np.nonzero(sd["part"] >= 0)[0]
+    sd["part"][inner[0]] = (sd["part"][inner[0]] + 1) % (sd["part"].max() + 1)
+    sep_p = _copy(c1)
+    sd = sep_p["subs"][1]
+    sd["part"][np.nonzero(sd["kind"] == 2)[0][0]] = -1
+    for bad, what in ((coupled, "coupled"), (sep_p, ">= 0 for pressures")):
+        ctx = vb.vb_create()
+        try:
+            with pytest.raises(vb.VBError) as e:
+                vb.vb_assemble(ctx, bad)
+            assert e.value.code == VB_ERR_ARG and what in str(e.value), str(e.value)
+        finally:
+            vb.vb_destroy(ctx)
+
+
 def test_primal_space_without_fluxes_gives_singular_coarse(vb, c1):
     """Without the face flux constraints (Assumption 1: the flux of every
     face must be a primal functional) the coarse problem has no flux rows,

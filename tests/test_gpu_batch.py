@@ -218,13 +218,15 @@ def test_neumann_waves_match_one_wave(vb, wls, precision):
 
 
 def test_dirichlet_waves_match_resident(vb, wls):
+    # waves of dense local matrices: the single-level factorisation (the
+    # two-level one keeps its smaller matrices resident)
     wl = wls[2]
     nloc = sum(len(sd["kind"]) for sd in wl["subs"])
     out = []
     for lim in (0.0, 1.0):  # resident; one subdomain per wave
         ctx = vb.vb_create(local_mem_limit=lim)
         try:
-            vb.vb_assemble(ctx, wl)
+            vb.vb_assemble(ctx, wl, nested=False)
             vb.vb_setup(ctx)
             n = vb.vb_interface_size(ctx)
             x = torch.zeros(n, dtype=torch.float64, device=DEV)

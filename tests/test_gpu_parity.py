@@ -114,21 +114,30 @@ def _problem(name):
 
 # c1, t8j, t12: tiles and ragged panels, 2/4/8-way sharing; t12u: uneven
 # cuts (2..6 elements per side, the shape of the 216-subdomain workload);
-# t12b: about 3,560 eliminated columns per subdomain (several outer
-# super-panels of the factorisation on 16-byte aligned matrices); t8k3,
-# t6k4: degrees 3 and 4
-FP64_CASES = ["c1", "t8j", "t12", "t12u", "t12b", "t8k3", "t6k4"]
-MIXED_CASES = ["c1", "t8j", "t12", "t12u", "t8k3", "t6k4"]
+# t12b: 6^3-element subdomains (3,560 eliminated columns each in one dense
+# factorisation: several outer super-panels on 16-byte aligned matrices);
+# t8k3, t6k4: degrees 3 and 4.  nested: the two-level factorisation (each
+# subdomain's sub-boxes first, then its separators), else one dense
+# factorisation per subdomain.
+FP64_CASES = [("c1", True), ("t8j", True), ("t12", True), ("t12u", True), ("t12b", True),
+              ("t8k3", True), ("t6k4", True), ("c1", False), ("t12u", False), ("t12b", False)]
+MIXED_CASES = [("c1", True), ("t8j", True), ("t12", True), ("t12u", True), ("t8k3", True),
+               ("t6k4", True), ("t8j", False), ("t12u", False)]
 
 
-@pytest.fixture(scope="module", params=FP64_CASES)
+def _ids(cases):
+    return ["%s-%s" % (n, "nested" if nd else "dense") for n, nd in cases]
+
+
+@pytest.fixture(scope="module", params=FP64_CASES, ids=_ids(FP64_CASES))
 def case(request, vb):
-    print("fp64 case", request.param, flush=True)
-    wl, meta, o = _problem(request.param)
+    name, nested = request.param
+    print("fp64 case", name, "nested" if nested else "dense", flush=True)
+    wl, meta, o = _problem(name)
     ctx = vb.vb_create(tol=1e-8)
-    vb.vb_assemble(ctx, wl)
+    vb.vb_assemble(ctx, wl, nested=nested)
     vb.vb_setup(ctx)
-    yield request.param, wl, meta, o, ctx
+    yield name, wl, meta, o, ctx
     vb.vb_destroy(ctx)
 
 
@@ -216,15 +225,52 @@ def test_interior_recovery_parity(vb, case):
 # sparse local systems, so the tolerance is the FP64 path's (1e-10 relative
 # against the oracle solved to 1e-13), not an FP32 one.
 
-@pytest.fixture(scope="module", params=MIXED_CASES)
+@pytest.fixture(scope="module", params=MIXED_CASES, ids=_ids(MIXED_CASES))
 def mixed_case(request, vb):
-    print("mixed case", request.param, flush=True)
-    wl, meta, o = _problem(request.param)
+    name, nested = request.param
+    print("mixed case", name, "nested" if nested else "dense", flush=True)
+    wl, meta, o = _problem(name)
     ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12)
-    vb.vb_assemble(ctx, wl)
+    vb.vb_assemble(ctx, wl, nested=nested)
     vb.vb_setup(ctx)
-    yield request.param, wl, meta, o, ctx
+    yield name, wl, meta, o, ctx
     vb.vb_destroy(ctx)
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_two_level_factorisation_equals_single_level(vb, precision):
+    """The two-level (sub-boxes, then separators) factorisation is an exact
+    reordering of the single-level one: same S_hat, g_hat, solution and
+    local solutions to rounding (FP64); in mixed precision both reach the
+    FP64 solution."""
+    wl, meta, o = _problem("t12u")
+    out = []
+    for nested in (True, False):
+        ctx = vb.vb_create(precision=precision, tol=1e-8 if precision == 0 else 1e-12)
+        try:
+            vb.vb_assemble(ctx, wl, nested=nested)
+            vb.vb_setup(ctx)
+            n = vb.vb_interface_size(ctx)
+            g = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_rhs(ctx, g)
+            xr = torch.tensor(np.random.default_rng(4).standard_normal(n), device=DEV)
+            y = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_schur_apply(ctx, xr, y)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            info = vb.vb_pcg_solve(ctx, x)
+            u = torch.zeros(vb.vb_local_size(ctx), dtype=torch.float64, device=DEV)
+            vb.vb_recover_all(ctx, x, u)
+            torch.cuda.synchronize()
+            out.append((g.cpu().numpy(), y.cpu().numpy(), x.cpu().numpy(), u.cpu().numpy(), info))
+        finally:
+            vb.vb_destroy(ctx)
+    (g1, y1, x1, u1, i1), (g0, y0, x0, u0, i0) = out
+    if precision == 0:
+        assert _rel(g1, g0) < 1e-12 and _rel(y1, y0) < 1e-12
+        assert i1["iterations"] == i0["iterations"]
+        assert _rel(x1, x0) < 1e-11 and _rel(u1, u0) < 1e-10
+    else:
+        assert _rel(x1, x0) < 1e-10 and _rel(u1, u0) < 1e-9
 
 
 def test_mixed_solution_parity(vb, mixed_case):
