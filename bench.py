@@ -46,6 +46,9 @@ WORKLOADS = {
            "problem), vertex+edge+face, deluxe, adaptive theta=10 through the learned predictor, "
            "mixed precision",
 }
+for _k in (2, 3, 4):
+    WORKLOADS["deg%d" % _k] = ("8^3 cube, VEM k=%d, nu=1, 4x4x2 subdomains, vertex+edge+flux, deluxe "
+                               "(the paper's degree test, Table optDeg1 setting)" % _k)
 C4_TRAIN_SEEDS = (1, 2)
 C5S_PROBLEMS = 32
 C5S_TRAIN_SEEDS = (100, 101)
@@ -55,8 +58,8 @@ PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the readings of a 1 GiB device copy: x2.0, x1.0), per
 # workload and path; to be cleared whenever the kernel changes.
-TRAFFIC_BYTES = {("c2", "mixed"): 1.0557e11}
-TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c2_hbm_counters.md"
+TRAFFIC_BYTES = {("c3", "mixed"): 5.0158e10}
+TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c3_hbm_counters.md"
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
 
@@ -673,7 +676,7 @@ def run_batched(args):
         ldl = vb.vb_kernel_stats(ctx, 0)
         vb.vb_set_profile(ctx, 0)
         faces = vb.vb_adaptive_info(ctx)
-        tiles = [vb.vb_tuned_tile(ctx, k) for k in range(4)]
+        tiles = [vb.vb_tuned_tile(ctx, k) for k in range(5)]
         vb.vb_destroy(ctx)
         dt_batch = (t1 - t0) / args.steps
         # the same batch with the exact adaptive eigensolves (no predictor)

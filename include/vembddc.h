@@ -97,7 +97,25 @@ typedef struct vb_options {
                              vb_recover_all / vb_get_local_solution factor each
                              wave again. 0 = 45% of the free device memory at
                              the first vb_setup. Results do not depend on it. */
+  int pcg_launch;         /* how the PCG iterations are launched: VB_PCG_AUTO (0),
+                             VB_PCG_GRAPH (1: the launches of one iteration
+                             captured as a HIP graph and replayed, the host
+                             reading the convergence flags between replays) or
+                             VB_PCG_PERSISTENT (2: one cooperative launch runs
+                             every iteration of every problem, phases separated
+                             by grid barriers, convergence decided on the
+                             device; falls back to the graph where cooperative
+                             launches are unavailable).  Same arithmetic in the
+                             same order: the results are identical.  AUTO picks
+                             the persistent launch when one S_hat application
+                             reads less than 1 GB, else the graph. */
+  int schur_kernel;       /* S_hat p: 0 = chosen by the autotuner, 1 = full-matrix
+                             GEMV of each bordered local operator, 2 = the tiled
+                             symmetric kernel reading its lower triangle only
+                             (half the bytes; the operators are symmetric). */
 } vb_options;
+
+enum { VB_PCG_AUTO = 0, VB_PCG_GRAPH = 1, VB_PCG_PERSISTENT = 2 };
 
 /* One face of the adaptive coarse space (Sec. 6), as selected by vb_setup. */
 typedef struct vb_face_info {
@@ -229,7 +247,9 @@ int vb_num_problems(const vb_ctx *ctx);
 /* Columns per workgroup that the autotuner chose (at the context's first
  * vb_setup, by timing 8/16/32/64 on the operators themselves) for the
  * per-iteration GEMVs: which = 0 S_hat p, 1 Neumann, 2 deluxe restriction,
- * 3 coarse; 0 before the first setup. */
+ * 3 coarse; 0 before the first setup.  which = 4: 1 if S_hat p reads only
+ * the lower triangle of each symmetric local operator (the tiled symmetric
+ * kernel, timed against the best full-matrix tile), else 0. */
 int vb_tuned_tile(const vb_ctx *ctx, int which);
 int vb_problem_layout(const vb_ctx *ctx, int problem, vb_problem *out);
 /* Per-problem result of the last vb_pcg_solve (the info that call returns
@@ -360,6 +380,11 @@ int vb_kernel_stats(vb_ctx *ctx, int which, int reset, vb_kernel_stat *out);
  * launch instead of as a replayed HIP graph, and every timed launch is
  * bracketed by two events. */
 int vb_set_profile(vb_ctx *ctx, int on);
+
+/* How the last PCG iterations of this context were launched: VB_PCG_GRAPH or
+ * VB_PCG_PERSISTENT (see vb_options.pcg_launch; the mixed-precision solve
+ * reports its last inner PCG), 0 before any solve. */
+int vb_pcg_launch_used(const vb_ctx *ctx);
 
 /* Batched dense partial signed LDL^T (the kernel under the Dirichlet and
  * Neumann solves).  For each of `batch` column-major matrices A_b (size n_b,

@@ -19,6 +19,7 @@ ERRORS = {-1: "VB_ERR_ARG", -2: "VB_ERR_STATE", -3: "VB_ERR_OOM", -4: "VB_ERR_DE
           -8: "VB_ERR_NOT_CONVERGED"}
 VB_PREC_FP64, VB_PREC_MIXED = 0, 1
 VB_SCALING_DELUXE, VB_SCALING_COUNTING = 0, 1
+VB_PCG_AUTO, VB_PCG_GRAPH, VB_PCG_PERSISTENT = 0, 1, 2
 
 
 class vb_options(C.Structure):
@@ -26,7 +27,8 @@ class vb_options(C.Structure):
                 ("maxit", C.c_int), ("svd_tol", C.c_double), ("panel", C.c_int),
                 ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double),
                 ("predictor", C.c_void_p),
-                ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double)]
+                ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double),
+                ("pcg_launch", C.c_int), ("schur_kernel", C.c_int)]
 
 
 class vb_problem(C.Structure):
@@ -99,6 +101,7 @@ def load():
         "vb_recover_all": (C.c_int, [P, P, P]),
         "vb_local_size": (C.c_int64, [P, C.c_int]),
         "vb_set_profile": (C.c_int, [P, C.c_int]),
+        "vb_pcg_launch_used": (C.c_int, [P]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_batched_ldl_noalloc": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
@@ -141,7 +144,7 @@ def exported_symbols():
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
             "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
-            "vb_batched_ldl_noalloc"]
+            "vb_batched_ldl_noalloc", "vb_pcg_launch_used"]
 
 
 class VBError(RuntimeError):
@@ -189,10 +192,12 @@ def _check(ctx, rc):
 # ------------------------------------------------------------- C-ABI names
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
               svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
-              predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0):
+              predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0, pcg_launch=0,
+              schur_kernel=0):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
-                     adaptive_theta, predictor, setup_mem_limit, local_mem_limit)
+                     adaptive_theta, predictor, setup_mem_limit, local_mem_limit, pcg_launch,
+                     schur_kernel)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -317,6 +322,10 @@ def vb_kernel_stats(ctx, which, reset=False):
     st = vb_kernel_stat()
     _check(ctx, load().vb_kernel_stats(ctx, int(which), int(bool(reset)), C.byref(st)))
     return {"launches": st.launches, "total_ms": st.total_ms, "work": st.work}
+
+
+def vb_pcg_launch_used(ctx):
+    return int(load().vb_pcg_launch_used(ctx))
 
 
 def vb_set_profile(ctx, on):

@@ -41,6 +41,29 @@ struct GemvJob {
                        // the rows), the complement (I - A)^T x of the same product
 };
 
+// y = alpha A x (+ y if acc) for a symmetric A (n x n, column-major) read
+// through its lower triangle only, in SYMV_T x SYMV_T tiles: each tile adds
+// its rows' and (off the diagonal) its columns' contributions to `part`
+// (SYMV_T row sums, then SYMV_T column sums, per tile), which a second pass
+// reduces in a fixed order.
+constexpr int SYMV_T = 256;
+struct SymvJob {
+  const void *A;       // double, or float if a_f32
+  int64_t lda;
+  int n, a_f32;
+  const double *x;
+  const int64_t *xidx;
+  double *y;
+  double alpha;
+  int acc;
+  double *part;        // symv_tiles(n) * 2 * SYMV_T doubles
+};
+__host__ __device__ inline int symv_tiles(int n) {
+  const int T = (n + SYMV_T - 1) / SYMV_T;
+  return T * (T + 1) / 2;
+}
+hipError_t symv(const SymvJob *d_jobs, int batch, int max_n, hipStream_t s);
+
 struct ExtPart {
   const double *D;  // m x m column-major (null: counting weight `scale`)
   int64_t ld;
@@ -101,5 +124,45 @@ hipError_t supdate_p(const Seg *segs, int P, int G, const double *sc, double *p,
 hipError_t sinit(int P, const double *tol, int maxit, double *sc, hipStream_t s);
 hipError_t recover_out(const RecJob *d_jobs, int nsub, const double *x_orig, int64_t nG,
                        hipStream_t s);
+
+// ---- the whole PCG iteration loop in one persistent cooperative launch
+// One GEMV launch of the iteration: its jobs, batch, grid width and columns
+// per workgroup (the autotuned tile).
+struct GemvPhase {
+  const GemvJob *jobs;
+  int batch, gx, cpb;
+};
+// Everything one iteration (S~ p, M~^-1 r, recurrences, as launched one by
+// one in the graph-replayed iteration) reads and writes.
+struct PcgPlan {
+  GemvPhase schur, restrict_, neu1, coarse, neu2;  // neu2: gemv_n (batch 0: none)
+  const SymvJob *ssym;  // non-null: S~ p by the symmetric kernel (schur unused)
+  int ssym_batch, ssym_tiles, ssym_rows;
+  const ExtJob *ext;
+  const ExtPart *extpart;
+  int n_ext, ext_gx;
+  const double *wv;
+  int n_own;
+  const int64_t *own_ptr, *own_idx;
+  const double *yloc;
+  int n_cs;
+  const int64_t *c_ptr, *c_idx, *c_base;
+  const double *tv;
+  double *rc;
+  const double *uc;
+  const int64_t *uc_dst;
+  const Seg *segs;
+  int P, G;
+  double *part, *sc, *hist_a, *hist_b;
+  int hist_ld;
+  double *x, *r, *p, *q, *z;
+  unsigned *bar;     // 2 words: arrivals, generation (zero before the launch)
+  int *err;          // set to 1 if a grid barrier timed out
+  int max_iter;      // iterations at most (every problem stops at its maxit before)
+};
+// Blocks of the persistent launch (co-resident: occupancy x CUs, at most
+// `per_cu` per CU); 0 if cooperative launches are not available.
+int pcg_persistent_blocks(int per_cu);
+hipError_t pcg_persistent(const PcgPlan *d_plan, int nblocks, hipStream_t s);
 
 }  // namespace vb

@@ -1,5 +1,7 @@
 // Per-iteration kernels of PCG + BDDC (HBM-bound dense GEMVs, gathers,
 // deterministic interface assembly and the CG recurrences).
+#include <algorithm>
+
 #include "common.h"
 #include "iterate.h"
 
@@ -13,13 +15,14 @@ namespace vb {
 // (the largest operators of an uneven decomposition would otherwise run at
 // two workgroups per CU).
 constexpr int GT_CHUNK = 2048;
+// The body of one workgroup (bx, by) of the launch: shared by the standalone
+// kernel and the persistent PCG kernel (xs: GT_CHUNK doubles of LDS).
 template <int CPB>
-__global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
+__device__ __forceinline__ void gemv_t_block(const GemvJob *jobs, int bx, int by, double *xs) {
   constexpr int NQ = CPB / 4;
-  const GemvJob J = jobs[blockIdx.y];
-  const int j0 = blockIdx.x * CPB;
+  const GemvJob J = jobs[by];
+  const int j0 = bx * CPB;
   if (j0 >= J.n) return;
-  __shared__ double xs[GT_CHUNK];
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
   double acc[NQ];
 #pragma unroll
@@ -69,15 +72,21 @@ __global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
   }
 }
 
+template <int CPB>
+__global__ __launch_bounds__(256) void k_gemv_t(const GemvJob *jobs) {
+  __shared__ double xs[GT_CHUNK];
+  gemv_t_block<CPB>(jobs, blockIdx.x, blockIdx.y, xs);
+}
+
 // y_b[i] = base_b[i] + sum_j A_b[i + j*lda] x_b[j], one thread per row,
 // x_b (length n, gathered through xidx) staged in LDS.
-__global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
-  const GemvJob J = jobs[blockIdx.y];
-  extern __shared__ double xs[];
+__device__ __forceinline__ void gemv_n_block(const GemvJob *jobs, int bx, int by, double *xs) {
+  const GemvJob J = jobs[by];
+  __syncthreads();  // xs may still be read by the previous block of a persistent loop
   for (int j = threadIdx.x; j < J.n; j += blockDim.x)
     xs[j] = J.xidx ? J.x[J.xidx[j]] : J.x[j];
   __syncthreads();
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int i = bx * blockDim.x + threadIdx.x;
   if (i >= J.m) return;
   double s = J.base ? J.base[i] : 0.0;
   if (J.a_f32) {
@@ -88,6 +97,11 @@ __global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
     for (int j = 0; j < J.n; ++j) s += a[(int64_t)j * J.lda] * xs[j];
   }
   J.y[i] = s;
+}
+
+__global__ __launch_bounds__(256) void k_gemv_n(const GemvJob *jobs) {
+  extern __shared__ double xs[];
+  gemv_n_block(jobs, blockIdx.x, blockIdx.y, xs);
 }
 
 // The staged vectors can exceed the default 64 KB of dynamic LDS; CDNA4 has
@@ -145,13 +159,18 @@ hipError_t gemv_n(const GemvJob *d_jobs, int batch, int max_m, int max_n, hipStr
 
 // y[g] = (bidx ? bsrc[bidx[g]] : 0) + sum_{t in [ptr[g], ptr[g+1])} src[idx[t]]
 // (deterministic assembly of subdomain contributions, fixed order).
-__global__ void k_owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
-                            const int64_t *bidx, const double *bsrc, double *y) {
-  const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ void owner_sum_at(int64_t g, int n, const int64_t *ptr, const int64_t *idx,
+                                             const double *src, const int64_t *bidx,
+                                             const double *bsrc, double *y) {
   if (g >= n) return;
   double s = bidx ? bsrc[bidx[g]] : 0.0;
   for (int64_t t = ptr[g]; t < ptr[g + 1]; ++t) s += src[idx[t]];
   y[g] = s;
+}
+
+__global__ void k_owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
+                            const int64_t *bidx, const double *bsrc, double *y) {
+  owner_sum_at((int64_t)blockIdx.x * blockDim.x + threadIdx.x, n, ptr, idx, src, bidx, bsrc, y);
 }
 
 hipError_t owner_sum(int n, const int64_t *ptr, const int64_t *idx, const double *src,
@@ -194,15 +213,16 @@ __device__ __forceinline__ v2d load2(const double *p) {
   return *(const __attribute__((address_space(1))) v2d *)p;
 }
 
-__global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPart *parts,
-                                                const double *w, double *z) {
-  const ExtJob J = jobs[blockIdx.y];
-  const int r0 = blockIdx.x * 128;
+// xs: EXT_CHUNK doubles of LDS, part: 4 x 128 doubles of LDS
+__device__ __forceinline__ void extend_block(const ExtJob *jobs, const ExtPart *parts,
+                                             const double *w, double *z, int bx, int by,
+                                             double *xs, double (*part)[128]) {
+  const ExtJob J = jobs[by];
+  const int r0 = bx * 128;
   if (r0 >= J.m) return;  // uniform over the workgroup
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int m0 = r0 + 2 * lane;
   const bool rows = m0 < J.m;
-  __shared__ double xs[EXT_CHUNK];
   double s0 = 0.0, s1 = 0.0;
   // s += D[m0:m0+2, :] (u - v) (v may be null); called by the whole workgroup
   auto matvec = [&](const double *D, int64_t ld, const double *u, const double *v) {
@@ -252,7 +272,7 @@ __global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPar
       }
     }
   }
-  __shared__ double part[4][128];
+  __syncthreads();
   part[wv][2 * lane] = s0;
   part[wv][2 * lane + 1] = s1;
   __syncthreads();
@@ -263,6 +283,13 @@ __global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPar
     if (wlast) v += wlast[r];
     z[J.gids[r]] = v;
   }
+}
+
+__global__ __launch_bounds__(256) void k_extend(const ExtJob *jobs, const ExtPart *parts,
+                                                const double *w, double *z) {
+  __shared__ double xs[EXT_CHUNK];
+  __shared__ double part[4][128];
+  extend_block(jobs, parts, w, z, blockIdx.x, blockIdx.y, xs, part);
 }
 
 hipError_t extend(const ExtJob *d_jobs, int njobs, int max_m, const ExtPart *d_parts,
@@ -462,27 +489,29 @@ __device__ __forceinline__ int64_t seg_index(const Seg &S, int64_t k) {
 }
 
 // part[p * G + c] = sum over problem p's entries handled by block c of a.b
-__global__ __launch_bounds__(256) void k_sdot(const Seg *segs, const double *a, const double *b,
-                                              double *part) {
-  const Seg S = segs[blockIdx.y];
-  const int G = gridDim.x;
-  __shared__ double red[16];
+__device__ __forceinline__ void sdot_block(const Seg *segs, const double *a, const double *b,
+                                           double *part, int bx, int by, int G, double *red) {
+  const Seg S = segs[by];
   const int64_t n = S.n0 + S.n1;
   double s = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)G * blockDim.x) {
+  for (int64_t k = (int64_t)bx * blockDim.x + threadIdx.x; k < n; k += (int64_t)G * blockDim.x) {
     const int64_t i = seg_index(S, k);
     s += a[i] * b[i];
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * G + blockIdx.x] = s;
+  if (threadIdx.x == 0) part[(int64_t)by * G + bx] = s;
 }
 
-// One thread per problem: fixed-order sum of its G partials, then the
-// scalar bookkeeping of the mode.
-__global__ void k_sfinal(int P, int G, const double *part, double *sc, int mode, double *hist_a,
-                         double *hist_b, int hist_ld) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+__global__ __launch_bounds__(256) void k_sdot(const Seg *segs, const double *a, const double *b,
+                                              double *part) {
+  __shared__ double red[16];
+  sdot_block(segs, a, b, part, blockIdx.x, blockIdx.y, gridDim.x, red);
+}
+
+// Problem p: fixed-order sum of its G partials, then the scalar bookkeeping
+// of the mode.
+__device__ __forceinline__ void sfinal_at(int p, int P, int G, const double *part, double *sc,
+                                          int mode, double *hist_a, double *hist_b, int hist_ld) {
   if (p >= P) return;
   double s0 = 0.0;
   for (int c = 0; c < G; ++c) s0 += part[(int64_t)p * G + c];
@@ -554,6 +583,11 @@ __global__ void k_sfinal(int P, int G, const double *part, double *sc, int mode,
   }
 }
 
+__global__ void k_sfinal(int P, int G, const double *part, double *sc, int mode, double *hist_a,
+                         double *hist_b, int hist_ld) {
+  sfinal_at(blockIdx.x * blockDim.x + threadIdx.x, P, G, part, sc, mode, hist_a, hist_b, hist_ld);
+}
+
 hipError_t sdot(const Seg *segs, int P, int G, const double *a, const double *b, double *part,
                 double *sc, int mode, double *hist_a, double *hist_b, int hist_ld, hipStream_t s) {
   if (P <= 0) return hipSuccess;
@@ -564,17 +598,14 @@ hipError_t sdot(const Seg *segs, int P, int G, const double *a, const double *b,
 }
 
 // x += alpha_p p ; r -= alpha_p q ; partial r.r per (problem, block)
-__global__ __launch_bounds__(256) void k_supdate_xr(const Seg *segs, const double *sc, double *x,
-                                                    double *r, const double *p, const double *q,
-                                                    double *part) {
-  const Seg S = segs[blockIdx.y];
-  const int G = gridDim.x;
-  __shared__ double red[16];
-  const double a = sc[(int64_t)blockIdx.y * SC_STRIDE + SC_ALPHA];
+__device__ __forceinline__ void supdate_xr_block(const Seg *segs, const double *sc, double *x,
+                                                 double *r, const double *p, const double *q,
+                                                 double *part, int bx, int by, int G, double *red) {
+  const Seg S = segs[by];
+  const double a = sc[(int64_t)by * SC_STRIDE + SC_ALPHA];
   const int64_t n = S.n0 + S.n1;
   double s = 0.0;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)G * blockDim.x) {
+  for (int64_t k = (int64_t)bx * blockDim.x + threadIdx.x; k < n; k += (int64_t)G * blockDim.x) {
     const int64_t i = seg_index(S, k);
     x[i] += a * p[i];
     const double ri = r[i] - a * q[i];
@@ -582,7 +613,14 @@ __global__ __launch_bounds__(256) void k_supdate_xr(const Seg *segs, const doubl
     s += ri * ri;
   }
   s = block_sum(s, red);
-  if (threadIdx.x == 0) part[(int64_t)blockIdx.y * G + blockIdx.x] = s;
+  if (threadIdx.x == 0) part[(int64_t)by * G + bx] = s;
+}
+
+__global__ __launch_bounds__(256) void k_supdate_xr(const Seg *segs, const double *sc, double *x,
+                                                    double *r, const double *p, const double *q,
+                                                    double *part) {
+  __shared__ double red[16];
+  supdate_xr_block(segs, sc, x, r, p, q, part, blockIdx.x, blockIdx.y, gridDim.x, red);
 }
 
 hipError_t supdate_xr(const Seg *segs, int P, int G, double *sc, double *x, double *r,
@@ -594,15 +632,19 @@ hipError_t supdate_xr(const Seg *segs, int P, int G, double *sc, double *x, doub
   return hipGetLastError();
 }
 
-__global__ void k_supdate_p(const Seg *segs, const double *sc, double *p, const double *z) {
-  const Seg S = segs[blockIdx.y];
-  const double b = sc[(int64_t)blockIdx.y * SC_STRIDE + SC_BETA];
+__device__ __forceinline__ void supdate_p_block(const Seg *segs, const double *sc, double *p,
+                                                const double *z, int bx, int by, int G) {
+  const Seg S = segs[by];
+  const double b = sc[(int64_t)by * SC_STRIDE + SC_BETA];
   const int64_t n = S.n0 + S.n1;
-  for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n;
-       k += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t k = (int64_t)bx * blockDim.x + threadIdx.x; k < n; k += (int64_t)G * blockDim.x) {
     const int64_t i = seg_index(S, k);
     p[i] = z[i] + b * p[i];
   }
+}
+
+__global__ void k_supdate_p(const Seg *segs, const double *sc, double *p, const double *z) {
+  supdate_p_block(segs, sc, p, z, blockIdx.x, blockIdx.y, gridDim.x);
 }
 
 hipError_t supdate_p(const Seg *segs, int P, int G, const double *sc, double *p, const double *z,
@@ -627,4 +669,271 @@ hipError_t sinit(int P, const double *tol, int maxit, double *sc, hipStream_t s)
   hipLaunchKernelGGL(k_sinit, dim3((P + 63) / 64), dim3(64), 0, s, P, tol, maxit, sc);
   return hipGetLastError();
 }
+// ------------------------------------------------ symmetric matrix-vector
+// Tile (ti, tj), tj <= ti, of job `by` (tile index t = ti (ti + 1) / 2 + tj):
+// lane l of every wave holds rows R0 + l + 64 k (k < 4) of the tile, so each
+// column read is four coalesced 64-entry loads (no alignment needed); the
+// four waves split the tile's columns.  Row sums use x of the columns
+// (staged in LDS), column sums x of the rows (in registers) reduced across
+// the wave, lane l keeping its wave's column l.  On a diagonal tile the row
+// sums take the entries on and below the diagonal, the column sums those
+// strictly below, so that every entry of the full matrix is used once.
+template <typename T>
+__device__ __forceinline__ void symv_tile(const SymvJob &J, int t, double *xs, double (*red)[SYMV_T]) {
+  int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
+  while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
+  while (ti * (ti + 1) / 2 > t) --ti;
+  const int tj = t - ti * (ti + 1) / 2;
+  const int R0 = ti * SYMV_T, C0 = tj * SYMV_T;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  __syncthreads();
+  for (int c = threadIdx.x; c < SYMV_T; c += blockDim.x) {
+    const int j = C0 + c;
+    xs[c] = j < J.n ? (J.xidx ? J.x[J.xidx[j]] : J.x[j]) : 0.0;
+  }
+  double xr[4], racc[4];
+  bool rin[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = R0 + lane + 64 * k;
+    rin[k] = r < J.n;
+    xr[k] = rin[k] ? (J.xidx ? J.x[J.xidx[r]] : J.x[r]) : 0.0;
+    racc[k] = 0.0;
+  }
+  __syncthreads();
+  const bool diag = ti == tj;
+  const T *A = (const T *)J.A;
+  double csum = 0.0;
+  const int c0 = 64 * w, c1 = min(c0 + 64, J.n - C0);
+  for (int c = c0; c < c1; ++c) {
+    const int j = C0 + c;
+    const auto col = gptr(A + (int64_t)j * J.lda + R0 + lane);
+    double v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) v[k] = rin[k] ? (double)col[64 * k] : 0.0;
+    const double xj = xs[c];
+    double cp = 0.0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int r = R0 + lane + 64 * k;
+      const double vr = (!diag || r >= j) ? v[k] : 0.0;
+      const double vc = (!diag || r > j) ? v[k] : 0.0;
+      racc[k] += vr * xj;
+      cp += vc * xr[k];
+    }
+    cp = warp_sum(cp);
+    if (lane == c - c0) csum = cp;
+  }
+  double *P = J.part + (int64_t)t * 2 * SYMV_T;
+  P[SYMV_T + 64 * w + lane] = csum;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) red[w][lane + 64 * k] = racc[k];
+  __syncthreads();
+  for (int r = threadIdx.x; r < SYMV_T; r += blockDim.x)
+    P[r] = (red[0][r] + red[1][r]) + (red[2][r] + red[3][r]);
+}
+
+// y[i] = alpha (sum of the row sums of the tiles in i's tile row + the
+// column sums of the tiles on and below the diagonal in i's tile column)
+// (+ y[i]).
+__device__ __forceinline__ void symv_reduce_at(const SymvJob &J, int i) {
+  if (i >= J.n) return;
+  const int ti = i / SYMV_T, il = i % SYMV_T, T = (J.n + SYMV_T - 1) / SYMV_T;
+  double s = 0.0;
+  for (int tj = 0; tj <= ti; ++tj) s += J.part[(int64_t)(ti * (ti + 1) / 2 + tj) * 2 * SYMV_T + il];
+  for (int t2 = ti; t2 < T; ++t2)
+    s += J.part[(int64_t)(t2 * (t2 + 1) / 2 + ti) * 2 * SYMV_T + SYMV_T + il];
+  double v = J.alpha * s;
+  if (J.acc) v += J.y[i];
+  J.y[i] = v;
+}
+
+__global__ __launch_bounds__(256) void k_symv_tiles(const SymvJob *jobs) {
+  const SymvJob J = jobs[blockIdx.y];
+  if ((int)blockIdx.x >= symv_tiles(J.n)) return;
+  __shared__ double xs[SYMV_T];
+  __shared__ double red[4][SYMV_T];
+  if (J.a_f32)
+    symv_tile<float>(J, blockIdx.x, xs, red);
+  else
+    symv_tile<double>(J, blockIdx.x, xs, red);
+}
+
+__global__ __launch_bounds__(256) void k_symv_reduce(const SymvJob *jobs) {
+  const SymvJob J = jobs[blockIdx.y];
+  symv_reduce_at(J, blockIdx.x * blockDim.x + threadIdx.x);
+}
+
+hipError_t symv(const SymvJob *d_jobs, int batch, int max_n, hipStream_t s) {
+  if (!batch || !max_n) return hipSuccess;
+  hipLaunchKernelGGL(k_symv_tiles, dim3(symv_tiles(max_n), batch), dim3(256), 0, s, d_jobs);
+  hipLaunchKernelGGL(k_symv_reduce, dim3((max_n + 255) / 256, batch), dim3(256), 0, s, d_jobs);
+  return hipGetLastError();
+}
+
+// ------------------------------------------- persistent PCG iteration loop
+// Grid-wide barrier of a cooperative launch (every block co-resident): one
+// arrival counter and a generation word; thread 0 of each block arrives
+// (release), the last arrival resets the counter and advances the
+// generation, the others wait for it (acquire).  A wait longer than about
+// 20 s of the constant device clock (100 MHz) returns false, so every
+// block leaves instead of hanging.
+__device__ __forceinline__ bool grid_barrier(unsigned *bar, unsigned nblocks) {
+  constexpr unsigned long long limit = 2000000000ull;
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ok = 1;
+    const unsigned g = __hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned a = __hip_atomic_fetch_add(&bar[0], 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    if (a == nblocks - 1) {
+      __hip_atomic_store(&bar[0], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&bar[1], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    } else {
+      const unsigned long long t0 = wall_clock64();
+      while (__hip_atomic_load(&bar[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (wall_clock64() - t0 > limit) {
+          ok = 0;
+          break;
+        }
+      }
+    }
+    __threadfence();
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <int CPB>
+__device__ __forceinline__ void gemv_phase_t(const GemvPhase &ph, double *xs) {
+  const int nv = ph.gx * ph.batch;
+  for (int v = blockIdx.x; v < nv; v += gridDim.x) gemv_t_block<CPB>(ph.jobs, v % ph.gx, v / ph.gx, xs);
+}
+
+__device__ __forceinline__ void gemv_phase(const GemvPhase &ph, double *xs) {
+  switch (ph.cpb) {
+    case 8: gemv_phase_t<8>(ph, xs); break;
+    case 16: gemv_phase_t<16>(ph, xs); break;
+    case 64: gemv_phase_t<64>(ph, xs); break;
+    default: gemv_phase_t<32>(ph, xs); break;
+  }
+}
+
+// The PCG iterations of every problem until all have stopped (converged,
+// broken down or at maxit; the per-problem scalars decide, as in the
+// launch-by-launch iteration), each phase of an iteration spread over the
+// resident blocks and followed by a grid barrier.  The arithmetic and its
+// order are those of the launch-by-launch iteration.
+__global__ __launch_bounds__(256) void k_pcg_persistent(const PcgPlan *plan) {
+  const PcgPlan L = *plan;
+  __shared__ double xs[GT_CHUNK];
+  __shared__ double part4[4][SYMV_T];  // extend's 4 x 128 partial sums, or symv's 4 x 256
+  __shared__ double red[16];
+  const unsigned nb = gridDim.x;
+  const int tid = threadIdx.x, bsz = blockDim.x;
+  const int nv_dot = L.G * L.P;
+  auto sync = [&]() -> bool {
+    if (grid_barrier(L.bar, nb)) return true;
+    if (tid == 0) atomicExch(L.err, 1);
+    return false;
+  };
+  for (int it = 0; it < L.max_iter; ++it) {
+    bool all = true;
+    for (int pp = 0; pp < L.P; ++pp)
+      all = all && ((volatile const double *)L.sc)[(int64_t)pp * SC_STRIDE + SC_DONE] != 0.0;
+    if (all) break;
+    // q = S~ p
+    if (L.ssym) {
+      const int nv = L.ssym_tiles * L.ssym_batch;
+      for (int v = blockIdx.x; v < nv; v += nb) {
+        const SymvJob J = L.ssym[v / L.ssym_tiles];
+        const int t = v % L.ssym_tiles;
+        if (t >= symv_tiles(J.n)) continue;
+        if (J.a_f32)
+          symv_tile<float>(J, t, xs, (double(*)[SYMV_T])&part4[0][0]);
+        else
+          symv_tile<double>(J, t, xs, (double(*)[SYMV_T])&part4[0][0]);
+      }
+      if (!sync()) return;
+      const int nr = L.ssym_rows * L.ssym_batch;
+      for (int v = blockIdx.x * bsz + tid; v < nr; v += nb * bsz)
+        symv_reduce_at(L.ssym[v / L.ssym_rows], v % L.ssym_rows);
+    } else {
+      gemv_phase(L.schur, xs);
+    }
+    if (!sync()) return;
+    for (int64_t g = (int64_t)blockIdx.x * bsz + tid; g < L.n_own; g += (int64_t)nb * bsz)
+      owner_sum_at(g, L.n_own, L.own_ptr, L.own_idx, L.yloc, nullptr, nullptr, L.q);
+    if (!sync()) return;
+    // alpha = rz / p.q ; x += alpha p ; r -= alpha q ; convergence
+    for (int v = blockIdx.x; v < nv_dot; v += nb)
+      sdot_block(L.segs, L.p, L.q, L.part, v % L.G, v / L.G, L.G, red);
+    if (!sync()) return;
+    for (int pp = blockIdx.x * bsz + tid; pp < L.P; pp += nb * bsz)
+      sfinal_at(pp, L.P, L.G, L.part, L.sc, 0, L.hist_a, nullptr, L.hist_ld);
+    if (!sync()) return;
+    for (int v = blockIdx.x; v < nv_dot; v += nb)
+      supdate_xr_block(L.segs, L.sc, L.x, L.r, L.p, L.q, L.part, v % L.G, v / L.G, L.G, red);
+    if (!sync()) return;
+    for (int pp = blockIdx.x * bsz + tid; pp < L.P; pp += nb * bsz)
+      sfinal_at(pp, L.P, L.G, L.part, L.sc, 1, nullptr, nullptr, 0);
+    if (!sync()) return;
+    // z = M~^-1 r
+    if (L.restrict_.batch) {
+      gemv_phase(L.restrict_, xs);
+      if (!sync()) return;
+    }
+    gemv_phase(L.neu1, xs);
+    if (!sync()) return;
+    for (int64_t g = (int64_t)blockIdx.x * bsz + tid; g < L.n_cs; g += (int64_t)nb * bsz)
+      owner_sum_at(g, L.n_cs, L.c_ptr, L.c_idx, L.tv, L.c_base, L.r, L.rc);
+    if (!sync()) return;
+    gemv_phase(L.coarse, xs);
+    if (!sync()) return;
+    if (L.neu2.batch) {
+      const int nv = L.neu2.gx * L.neu2.batch;
+      for (int v = blockIdx.x; v < nv; v += nb) gemv_n_block(L.neu2.jobs, v % L.neu2.gx, v / L.neu2.gx, xs);
+      if (!sync()) return;
+    }
+    if (L.n_ext) {
+      const int nv = L.ext_gx * L.n_ext;
+      for (int v = blockIdx.x; v < nv; v += nb)
+        extend_block(L.ext, L.extpart, L.wv, L.z, v % L.ext_gx, v / L.ext_gx, xs,
+                     (double(*)[128])&part4[0][0]);
+    }
+    for (int64_t i = (int64_t)blockIdx.x * bsz + tid; i < L.n_cs; i += (int64_t)nb * bsz)
+      L.z[L.uc_dst[i]] = L.uc[i];
+    if (!sync()) return;
+    // beta = r.z / rz ; p = z + beta p
+    for (int v = blockIdx.x; v < nv_dot; v += nb)
+      sdot_block(L.segs, L.r, L.z, L.part, v % L.G, v / L.G, L.G, red);
+    if (!sync()) return;
+    for (int pp = blockIdx.x * bsz + tid; pp < L.P; pp += nb * bsz)
+      sfinal_at(pp, L.P, L.G, L.part, L.sc, 2, nullptr, L.hist_b, L.hist_ld);
+    if (!sync()) return;
+    for (int v = blockIdx.x; v < nv_dot; v += nb)
+      supdate_p_block(L.segs, L.sc, L.p, L.z, v % L.G, v / L.G, L.G);
+    if (!sync()) return;
+  }
+}
+
+int pcg_persistent_blocks(int per_cu) {
+  int dev = 0, coop = 0, cus = 0, occ = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&coop, hipDeviceAttributeCooperativeLaunch, dev) != hipSuccess || !coop)
+    return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, k_pcg_persistent, 256, 0) != hipSuccess)
+    return 0;
+  return std::max(0, std::min(occ, per_cu)) * cus;
+}
+
+hipError_t pcg_persistent(const PcgPlan *d_plan, int nblocks, hipStream_t s) {
+  void *args[] = {(void *)&d_plan};
+  return hipLaunchCooperativeKernel((const void *)k_pcg_persistent, dim3(nblocks), dim3(256), args, 0,
+                                    s);
+}
+
 }  // namespace vb

@@ -190,6 +190,14 @@ struct vb_ctx {
   std::vector<int64_t> gc_off;  // per problem: offset of its coarse inverse in Gc
   hipGraph_t it_graph = nullptr;
   hipGraphExec_t it_exec = nullptr;
+  // the persistent launch of the PCG iterations: its plan (rebuilt after each
+  // setup), barrier words and error flag, and the resident block count
+  PcgPlan plan_h{};
+  PcgPlan *d_plan = nullptr;
+  unsigned *d_pbar = nullptr;  // [arrivals, generation, error flag, spare]
+  bool plan_valid = false;
+  int pnb = -1;                // blocks of the persistent launch (0: unavailable)
+  int last_launch = 0;         // VB_PCG_GRAPH or VB_PCG_PERSISTENT, last pcg_core
   std::vector<vb_solve_info> pinfo;  // per problem, last solve
   // autotuned columns per workgroup of the per-iteration GEMVs:
   // 0 S_hat p, 1 Neumann, 2 deluxe restriction, 3 coarse (0 = not tuned yet)
@@ -223,6 +231,10 @@ struct vb_ctx {
   int max_gt_m = 0, max_gt_n = 0, max_ndl = 0, max_npi = 0, max_nt = 0;
   int64_t n_yloc = 0, n_gD = 0, n_tv = 0;
   double schur_bytes = 0.0;  // algorithmic bytes of one S~ GEMV launch
+  // S~ p through the lower triangle only (chosen by the autotuner when faster)
+  SymvJob *j_ssym = nullptr;
+  bool ssym_on = false;
+  double schur_bytes_full = 0.0, schur_bytes_sym = 0.0;
   // recovery
   double *yrec = nullptr, *zrec = nullptr, *rec_out = nullptr;
   int64_t *d_yoff = nullptr, *d_invoff = nullptr;
@@ -493,7 +505,9 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
   if ((d.precision != VB_PREC_FP64 && d.precision != VB_PREC_MIXED) ||
       (d.scaling != VB_SCALING_DELUXE && d.scaling != VB_SCALING_COUNTING) ||
       !(d.setup_mem_limit >= 0.0) || !(d.local_mem_limit >= 0.0) || !std::isfinite(d.tol) ||
-      !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta)) {
+      !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta) ||
+      d.pcg_launch < VB_PCG_AUTO || d.pcg_launch > VB_PCG_PERSISTENT || d.schur_kernel < 0 ||
+      d.schur_kernel > 2) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -1304,12 +1318,18 @@ struct PredFace {
 // Ritz value of the block, so that everything beyond the block is damped),
 // orthonormalises, and takes Rayleigh-Ritz pairs (eigensolve of the b x b
 // projection with the dense kernels).  Accepted
-// when fewer than b - 2 Ritz values lie below sigma (a margin that the
-// count is complete), every selected pair has residual <= 1e-6 rho, and the
-// count is certain: a symmetric matrix has an eigenvalue within the residual
-// norm of every Ritz value, so theta_t + r_t < sigma for the selected pairs
-// and theta - r > sigma for the next one.  Otherwise up to 6 passes, then
-// the face falls back to the exact solve.
+// when fewer than b - 2 Ritz values lie below sigma, every selected pair
+// has residual <= 1e-6 rho, theta_t + r_t < sigma for the selected pairs
+// and theta - r > sigma for the next one.  The residual bounds prove that
+// an eigenvalue lies below sigma near each selected Ritz value (a symmetric
+// matrix has an eigenvalue within the residual norm of every Ritz value);
+// they do not prove that no other eigenvalue lies below sigma, since an
+// eigenvector nearly orthogonal to the block is damped but not seen.  The
+// count is therefore a heuristic: complete when the filter has reached
+// every such eigenvector, which the two spare Ritz values above sigma and
+// the filter's damping of everything beyond the block make likely, not
+// certain.  Otherwise up to 6 passes, then the face falls back to the
+// exact solve.
 template <class GetFace>
 static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
                           const std::vector<int64_t> &coff, const double *d_rho, double sigma,
@@ -1491,13 +1511,13 @@ static int predicted_eigs(vb_ctx *ctx, vb_mlp *pred, size_t nf_, GetFace get,
         continue;
       }
       double rmax = 0.0;
-      bool certain = true;
+      bool separated = true;  // the selected Ritz values and the next one bracket sigma
       for (int t = 0; t < kr; ++t) {
         rmax = std::max(rmax, res[t]);
-        certain = certain && th[t] + res[t] < sigma;
+        separated = separated && th[t] + res[t] < sigma;
       }
-      certain = certain && th[kr] - res[kr] > sigma;
-      if (rmax <= 1e-6 * P.rho && certain) {
+      separated = separated && th[kr] - res[kr] > sigma;
+      if (rmax <= 1e-6 * P.rho && separated) {
         done[live[k]] = 1;
         path[q] = 1;
         hc[q] = kr;
@@ -2346,6 +2366,7 @@ static int setup_impl(vb_ctx *ctx) {
     H.d_work = H.d_work0;
   }
   ctx->entdev = ctx->entdev0;
+  ctx->plan_valid = false;
   CHK(hipMemcpyAsync(ctx->d_entdev, ctx->entdev.data(), ctx->entdev.size() * sizeof(EntDev),
                      hipMemcpyHostToDevice, st));
   ctx->face_info.clear();
@@ -2904,11 +2925,29 @@ static int setup_impl(vb_ctx *ctx) {
       yoff += S.ng + 1;
     }
     ctx->n_yloc = yoff;
-    ctx->schur_bytes = 0.0;
-    for (auto &S : ctx->subs)  // the bordered matrix once (its storage type) + x gather + y write
-      ctx->schur_bytes += (double)ctx->wsz * (double)(S.ng + 1) * (S.ng + 1) + 16.0 * (S.ng + 1);
+    ctx->schur_bytes_full = ctx->schur_bytes_sym = 0.0;
+    for (auto &S : ctx->subs) {  // the bordered matrix once (its storage type) + x gather + y write
+      const double n1 = S.ng + 1;
+      ctx->schur_bytes_full += (double)ctx->wsz * n1 * n1 + 16.0 * n1;
+      ctx->schur_bytes_sym += (double)ctx->wsz * n1 * (n1 + 1) * 0.5 + 16.0 * n1;
+    }
+    ctx->schur_bytes = ctx->ssym_on ? ctx->schur_bytes_sym : ctx->schur_bytes_full;
     UCHK(ctx->dalloc(&ctx->yloc, yoff));
     for (int s = 0; s < nS; ++s) js[s].y = ctx->yloc + ctx->subs[s].y_off;
+    {  // the same operator through its lower triangle (tile partial sums in `part`)
+      int64_t ptot = 0;
+      for (auto &S : ctx->subs) ptot += (int64_t)symv_tiles(S.ng + 1) * 2 * SYMV_T;
+      double *pbuf = nullptr;
+      UCHK(ctx->dalloc(&pbuf, std::max<int64_t>(ptot, 1)));
+      std::vector<SymvJob> sj(nS);
+      int64_t po = 0;
+      for (int s = 0; s < nS; ++s) {
+        const SubH &S = ctx->subs[s];
+        sj[s] = {Xptr(S), S.xld, S.ng + 1, f32 ? 1 : 0, ctx->p, S.d_gidl, js[s].y, 1.0, 0, pbuf + po};
+        po += (int64_t)symv_tiles(S.ng + 1) * 2 * SYMV_T;
+      }
+      UCHK(ctx->upload(&ctx->j_ssym, sj));
+    }
     std::vector<int64_t> ptr(nTot + 1, 0), idx;
     for (int64_t gg = 0; gg < nTot; ++gg) {
       ptr[gg + 1] = ptr[gg] + own[gg].size();
@@ -3184,8 +3223,11 @@ static int setup_impl(vb_ctx *ctx) {
 static int apply_S_internal(vb_ctx *ctx) {  // q <- S~ p
   KTimer *t = ctx->opt.profile ? &ctx->t_gemv : nullptr;
   if (t) CHK(t->begin(ctx->stream, ctx->schur_bytes));
-  CHK(gemv_t_cpb(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m, ctx->cpb[0] ? ctx->cpb[0] : 32,
-                 ctx->stream));
+  if (ctx->ssym_on)
+    CHK(symv(ctx->j_ssym, ctx->nS, ctx->max_gt_m, ctx->stream));
+  else
+    CHK(gemv_t_cpb(ctx->j_schur, ctx->nS, ctx->max_gt_m, ctx->max_gt_m,
+                   ctx->cpb[0] ? ctx->cpb[0] : 32, ctx->stream));
   if (t) CHK(t->end(ctx->stream));
   CHK(owner_sum((int)(ctx->nG + ctx->nS), ctx->own_ptr, ctx->own_idx, ctx->yloc, nullptr, nullptr,
                 ctx->q, ctx->stream));
@@ -3245,6 +3287,17 @@ static int autotune_gemvs(vb_ctx *ctx) {
       }
     }
     ctx->cpb[k] = pick;
+    if (k == 0) {  // S~ p: the lower-triangle kernel against the best full-matrix tile
+      CHK(symv(ctx->j_ssym, ctx->nS, ctx->max_gt_m, st));
+      CHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) CHK(symv(ctx->j_ssym, ctx->nS, ctx->max_gt_m, st));
+      CHK(hipEventRecord(e1, st));
+      CHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CHK(hipEventElapsedTime(&ms, e0, e1));
+      ctx->ssym_on = ctx->opt.schur_kernel == 2 || (ctx->opt.schur_kernel == 0 && ms < best);
+      ctx->schur_bytes = ctx->ssym_on ? ctx->schur_bytes_sym : ctx->schur_bytes_full;
+    }
   }
   (void)hipEventDestroy(e0);
   (void)hipEventDestroy(e1);
@@ -3363,6 +3416,75 @@ static int pcg_body(vb_ctx *ctx) {
   return VB_OK;
 }
 
+// The phases of pcg_body as one plan for the persistent launch (the same
+// jobs, grids and autotuned tiles).  False when the iteration does not fit
+// it (the Neumann primal vectors staged in LDS exceed its buffer).
+static bool persistent_plan(vb_ctx *ctx) {
+  if (ctx->max_npi > 2048) return false;
+  auto cp = [&](int k) { return ctx->cpb[k] ? ctx->cpb[k] : 32; };
+  auto ph = [&](const GemvJob *j, int batch, int max_n, int cpb) {
+    GemvPhase g{j, (j && max_n > 0) ? batch : 0, (max_n + cpb - 1) / cpb, cpb};
+    return g;
+  };
+  PcgPlan &L = ctx->plan_h;
+  L = PcgPlan{};
+  L.schur = ph(ctx->j_schur, ctx->nS, ctx->max_gt_m, cp(0));
+  if (ctx->ssym_on) {
+    L.ssym = ctx->j_ssym;
+    L.ssym_batch = ctx->nS;
+    L.ssym_tiles = symv_tiles(ctx->max_gt_m);
+    L.ssym_rows = ctx->max_gt_m;
+  }
+  L.restrict_ = ph(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, cp(2));
+  L.neu1 = ph(ctx->j_neu1, ctx->nS, ctx->max_nt, cp(1));
+  L.coarse = ph(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, cp(3));
+  L.neu2 = GemvPhase{ctx->j_neu2, ctx->max_ndl ? ctx->nS : 0, (ctx->max_ndl + 255) / 256, 0};
+  L.ext = ctx->j_ext;
+  L.extpart = ctx->j_extpart;
+  L.n_ext = ctx->n_ext;
+  L.ext_gx = (ctx->max_ext_m + 127) / 128;
+  L.wv = ctx->wv;
+  L.n_own = (int)(ctx->nG + ctx->nS);
+  L.own_ptr = ctx->own_ptr;
+  L.own_idx = ctx->own_idx;
+  L.yloc = ctx->yloc;
+  L.n_cs = ctx->nCS;
+  L.c_ptr = ctx->c_ptr;
+  L.c_idx = ctx->c_idx;
+  L.c_base = ctx->c_base;
+  L.tv = ctx->tv;
+  L.rc = ctx->rc;
+  L.uc = ctx->uc;
+  L.uc_dst = ctx->uc_dst;
+  L.segs = ctx->d_segs;
+  L.P = (int)ctx->probs.size();
+  L.G = ctx->seg_G;
+  L.part = ctx->part;
+  L.sc = ctx->sc;
+  L.hist_a = ctx->hist_a;
+  L.hist_b = ctx->hist_b;
+  L.hist_ld = ctx->opt.maxit + 2;
+  L.x = ctx->x;
+  L.r = ctx->r;
+  L.p = ctx->p;
+  L.q = ctx->q;
+  L.z = ctx->z;
+  L.bar = ctx->d_pbar;
+  L.err = (int *)(ctx->d_pbar + 2);
+  L.max_iter = ctx->opt.maxit + 1;
+  return true;
+}
+
+static int pcg_loop(vb_ctx *ctx, int maxit, std::vector<double> &hs);
+
+// Whether pcg_core runs its iterations as one persistent launch.
+static bool use_persistent(vb_ctx *ctx) {
+  if (ctx->opt.profile || ctx->opt.pcg_launch == VB_PCG_GRAPH) return false;
+  if (ctx->opt.pcg_launch == VB_PCG_AUTO && ctx->schur_bytes >= 1e9) return false;
+  if (ctx->pnb < 0) ctx->pnb = pcg_persistent_blocks(2);
+  return ctx->pnb > 0;
+}
+
 static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, const std::vector<double> &tol,
                     int maxit, PcgResult *res) {
   hipStream_t st = ctx->stream;
@@ -3386,13 +3508,72 @@ static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, const std::vector
   if (rc) return rc;
   CHK(sdot(ctx->d_segs, P, G, ctx->r, ctx->z, ctx->part, ctx->sc, 3, nullptr, nullptr, ld, st));
   CHK(hipMemcpyAsync(ctx->p, ctx->z, n * sizeof(double), hipMemcpyDeviceToDevice, st));
-  // iterations: a replayed HIP graph of one iteration when a stream of our
-  // own is given and launches are not being timed one by one; the host reads
-  // the per-problem flags every `every` iterations (the flags freeze
-  // converged problems in between)
+  std::vector<double> hs((size_t)P * SC_STRIDE);
+  bool persisted = false;
+  if (use_persistent(ctx)) {
+    if (!ctx->d_plan) {
+      UCHK(ctx->dalloc((char **)&ctx->d_plan, sizeof(PcgPlan)));
+      UCHK(ctx->dalloc(&ctx->d_pbar, 4));
+    }
+    if (!ctx->plan_valid) {
+      if (!persistent_plan(ctx)) {
+        ctx->pnb = 0;
+      } else {
+        CHK(hipMemcpyAsync(ctx->d_plan, &ctx->plan_h, sizeof(PcgPlan), hipMemcpyHostToDevice, st));
+        ctx->plan_valid = true;
+      }
+    }
+    if (ctx->pnb > 0) {
+      // every problem's sc[MAXIT] is this call's maxit (sinit above)
+      CHK(hipMemsetAsync(ctx->d_pbar, 0, 4 * sizeof(unsigned), st));
+      hipError_t e = pcg_persistent(ctx->d_plan, ctx->pnb, st);
+      if (e == hipSuccess) {
+        unsigned flag[4] = {0, 0, 0, 0};
+        CHK(hipMemcpyAsync(flag, ctx->d_pbar, sizeof(flag), hipMemcpyDeviceToHost, st));
+        CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+        CHK(hipStreamSynchronize(st));
+        if (flag[2])
+          return ctx->fail(VB_ERR_DEVICE, "persistent PCG launch: a grid barrier timed out");
+        persisted = true;
+        ctx->last_launch = VB_PCG_PERSISTENT;
+      } else {  // cooperative launch refused: the graph-replayed iteration from now on
+        (void)hipGetLastError();
+        ctx->pnb = 0;
+      }
+    }
+  }
+  if (!persisted) {
+    rc = pcg_loop(ctx, maxit, hs);
+    if (rc) return rc;
+    ctx->last_launch = VB_PCG_GRAPH;
+  }
+  res->it = 0;
+  res->rel = 0.0;
+  res->status = VB_OK;
+  for (int pp = 0; pp < P; ++pp) {
+    const double *q = hs.data() + (size_t)pp * SC_STRIDE;
+    res->it = std::max(res->it, (int)q[SC_IT]);
+    const double rel = q[SC_GG] > 0 ? std::sqrt(q[SC_RR] / q[SC_GG]) : 0.0;
+    res->rel = std::max(res->rel, rel);
+    if (q[SC_FLAG] == 1.0) res->status = VB_ERR_BREAKDOWN;
+    else if ((q[SC_FLAG] == 2.0 || q[SC_DONE] == 0.0) && res->status == VB_OK)
+      res->status = VB_ERR_NOT_CONVERGED;
+  }
+  res->sc = hs;
+  return VB_OK;
+}
+
+// The iterations launch by launch: the first eagerly (it also runs every
+// one-time attribute call), the rest as a replayed HIP graph of one
+// iteration when a stream of our own is given and launches are not being
+// timed one by one; the host reads the per-problem flags every `every`
+// iterations (the flags freeze converged problems in between).
+static int pcg_loop(vb_ctx *ctx, int maxit, std::vector<double> &hs) {
+  hipStream_t st = ctx->stream;
+  const int P = (int)ctx->probs.size();
+  int rc = VB_OK;
   const bool graph_ok = ctx->stream != nullptr && !ctx->opt.profile;
   const int every = (ctx->schur_bytes * (8.0 / ctx->wsz) > 4e8) ? 1 : 4;
-  std::vector<double> hs((size_t)P * SC_STRIDE);
   CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
   auto all_done = [&]() {
@@ -3424,19 +3605,6 @@ static int pcg_core(vb_ctx *ctx, const double *b, bool x_zero, const std::vector
     CHK(hipMemcpyAsync(hs.data(), ctx->sc, hs.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
   }
-  res->it = 0;
-  res->rel = 0.0;
-  res->status = VB_OK;
-  for (int pp = 0; pp < P; ++pp) {
-    const double *q = hs.data() + (size_t)pp * SC_STRIDE;
-    res->it = std::max(res->it, (int)q[SC_IT]);
-    const double rel = q[SC_GG] > 0 ? std::sqrt(q[SC_RR] / q[SC_GG]) : 0.0;
-    res->rel = std::max(res->rel, rel);
-    if (q[SC_FLAG] == 1.0) res->status = VB_ERR_BREAKDOWN;
-    else if ((q[SC_FLAG] == 2.0 || q[SC_DONE] == 0.0) && res->status == VB_OK)
-      res->status = VB_ERR_NOT_CONVERGED;
-  }
-  res->sc = hs;
   return VB_OK;
 }
 
@@ -3914,7 +4082,8 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
 extern "C" {
 
 int vb_tuned_tile(const vb_ctx *ctx, int which) {
-  if (!ctx || which < 0 || which > 3) return VB_ERR_ARG;
+  if (!ctx || which < 0 || which > 4) return VB_ERR_ARG;
+  if (which == 4) return ctx->ssym_on ? 1 : 0;
   return ctx->cpb[which];
 }
 
@@ -3948,6 +4117,8 @@ int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_ei
     for (int i = 0; i < std::min((int)ctx->face_eigs.size(), max_eigs); ++i) eigs[i] = ctx->face_eigs[i];
   return nf;
 }
+
+int vb_pcg_launch_used(const vb_ctx *ctx) { return ctx ? ctx->last_launch : VB_ERR_ARG; }
 
 int vb_set_profile(vb_ctx *ctx, int on) {
   if (!ctx) return VB_ERR_ARG;

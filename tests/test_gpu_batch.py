@@ -241,3 +241,83 @@ def test_dirichlet_waves_match_resident(vb, wls):
     assert i1["iterations"] == i0["iterations"]
     assert _rel(x1, x0) < 1e-14
     assert _rel(u1, u0) < 1e-14
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_persistent_launch_matches_graph_and_oracle(vb, wls, oracles, precision):
+    """The PCG iterations as one persistent cooperative launch (phases
+    separated by grid barriers, convergence decided on the device) against
+    the graph-replayed iteration: the same arithmetic in the same order, so
+    the same iteration counts and solutions to rounding, for every problem of
+    a batched context; and against the oracle (FP64: the iterate after the
+    problem's own iteration count; mixed: the oracle's solution to 1e-13)."""
+    from oracle.pcg import pcg
+    tol = 1e-8 if precision == 0 else 1e-12
+    out = {}
+    for launch in (vb.VB_PCG_GRAPH, vb.VB_PCG_PERSISTENT):
+        stream = torch.cuda.Stream(device=DEV)
+        ctx = vb.vb_create(precision=precision, tol=tol, stream=stream.cuda_stream,
+                           pcg_launch=launch)
+        try:
+            for wl in wls:
+                vb.vb_assemble(ctx, wl)
+            with torch.cuda.stream(stream):
+                vb.vb_setup(ctx)
+                n = vb.vb_interface_size(ctx)
+                res = []
+                for rep in range(2):  # a second solve reuses the launch plan
+                    x = torch.zeros(n, dtype=torch.float64, device=DEV)
+                    vb.vb_pcg_solve(ctx, x)
+                    stream.synchronize()
+                    res.append(x.cpu().numpy())
+            assert vb.vb_pcg_launch_used(ctx) == launch
+            its = [vb.vb_problem_solve_info(ctx, k)["iterations"] for k in range(len(wls))]
+            out[launch] = (res, its, [_split(vb, ctx, res[0], k) for k in range(len(wls))])
+        finally:
+            vb.vb_destroy(ctx)
+    (rg, ig, xg), (rp, ip, xp) = out[vb.VB_PCG_GRAPH], out[vb.VB_PCG_PERSISTENT]
+    assert ip == ig
+    assert _rel(rp[0], rg[0]) < 1e-14 and _rel(rp[1], rp[0]) < 1e-14
+    for k, o in enumerate(oracles):
+        if precision == 0:
+            xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=ip[k])
+        else:
+            xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
+        assert _rel(xp[k], xo) < 1e-10, (k, _rel(xp[k], xo))
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_symmetric_schur_kernel_matches_full_and_oracle(vb, wls, oracles, precision):
+    """S_hat p through the lower triangle of each bordered local operator
+    (tiled symmetric kernel) against the full-matrix GEMV: the operators are
+    symmetric to rounding, so S_hat x agrees to 1e-13 and the solutions to
+    the PCG tolerance; against the oracle as every other path."""
+    from oracle.pcg import pcg
+    tol = 1e-8 if precision == 0 else 1e-12
+    out = {}
+    for kern in (1, 2):
+        ctx = vb.vb_create(precision=precision, tol=tol, schur_kernel=kern)
+        try:
+            for wl in wls:
+                vb.vb_assemble(ctx, wl)
+            vb.vb_setup(ctx)
+            assert vb.vb_tuned_tile(ctx, 4) == (1 if kern == 2 else 0)
+            n = vb.vb_interface_size(ctx)
+            v = torch.tensor(np.random.default_rng(9).standard_normal(n), device=DEV)
+            y = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_schur_apply(ctx, v, y)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_pcg_solve(ctx, x)
+            its = [vb.vb_problem_solve_info(ctx, k)["iterations"] for k in range(len(wls))]
+            xs = [_split(vb, ctx, x.cpu().numpy(), k) for k in range(len(wls))]
+            out[kern] = (y.cpu().numpy(), xs, its)
+        finally:
+            vb.vb_destroy(ctx)
+    (y1, x1, i1), (y2, x2, i2) = out[1], out[2]
+    assert _rel(y2, y1) < 1e-13 if precision == 0 else _rel(y2, y1) < 1e-6
+    for k, o in enumerate(oracles):
+        if precision == 0:
+            xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=i2[k])
+        else:
+            xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
+        assert _rel(x2[k], xo) < 1e-10, (k, _rel(x2[k], xo))
