@@ -280,6 +280,9 @@ def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
         last = infos[-1]
         log("%s: timed %d solves in %.3f s: %d iterations, residual %.2e"
             % (prec, steps, dt, last["iterations"], last["true_rel_residual"]))
+        launch = {vb.VB_PCG_GRAPH: "graph", vb.VB_PCG_PERSISTENT: "persistent"}.get(
+            vb.vb_pcg_launch_used(ctx), "eager")
+        sym = vb.vb_tuned_tile(ctx, 4) == 1
         # warm solves: the setup reused, PCG (or refinement) + recovery only
         torch.cuda.synchronize()
         t2 = time.perf_counter()
@@ -304,7 +307,7 @@ def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
         stream.synchronize()
     del u
     return dict(ctx=ctx, x=x, dt=dt, steps=steps, warmup=warmup, ldl=ldl, gmv=gmv, info=last,
-                dtw=dtw, warm_steps=warm_steps)
+                dtw=dtw, warm_steps=warm_steps, launch=launch, sym=sym)
 
 
 def main():
@@ -435,7 +438,10 @@ def main():
     def gemv(r):
         g = r["gmv"]
         b = g["work"] / (g["total_ms"] * 1e-3) / 1e9 if g["total_ms"] > 0 else None
-        return {"kernel": "k_gemv_t (S_hat p, bordered local Schur GEMV)", "bound": "hbm",
+        name = ("k_symv_tiles + k_symv_reduce (S_hat p through the lower triangle of each "
+                "bordered local Schur operator)") if r["sym"] else \
+            "k_gemv_t (S_hat p, bordered local Schur GEMV)"
+        return {"kernel": name, "bound": "hbm",
                 "achieved": b, "peak": PEAK_HBM_GBS, "unit": "GB/s",
                 "frac": (b / PEAK_HBM_GBS) if b else None, "launches": g["launches"],
                 "avg_launch_ms": g["total_ms"] / max(g["launches"], 1)}
@@ -445,7 +451,7 @@ def main():
         return {"solves_per_s": r["steps"] / r["dt"], "ms_per_step": 1e3 * r["dt"] / r["steps"],
                 "steps": r["steps"], "warmup": r["warmup"],
                 "warm_solves_per_s": (r["warm_steps"] / r["dtw"]) if r["warm_steps"] else None,
-                "warm_steps": r["warm_steps"],
+                "warm_steps": r["warm_steps"], "pcg_launch": r["launch"],
                 "iterations": i["iterations"], "refinement_steps": i["refinement_steps"],
                 "rel_residual": i["true_rel_residual"], "lambda_min": i["lambda_min"],
                 "lambda_max": i["lambda_max"],
@@ -468,8 +474,10 @@ def main():
         "config": {"workload": args.config + ": " + WORKLOADS[args.config],
                    "precision": PRECISION_NAMES[head], "subdomains": nsub,
                    "interface_unknowns": n,
-                   "timed_mode": "per-launch timing off (PCG iteration replayed as a HIP graph); "
-                                 "kernel figures from one extra profiled solve"},
+                   "timed_mode": "per-launch timing off, PCG iterations launched as: %s "
+                                 "(persistent: one cooperative launch per inner solve; graph: one "
+                                 "captured iteration replayed); kernel figures from one extra "
+                                 "profiled solve (launch by launch)" % R["launch"]},
         "roofline": roof(R, peak, "f64" if head == "fp64" else "f32", head),
         "iteration_kernel": gemv(R),
         "runs": {k: summary(v) for k, v in runs.items()},

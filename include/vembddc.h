@@ -113,6 +113,14 @@ typedef struct vb_options {
                              GEMV of each bordered local operator, 2 = the tiled
                              symmetric kernel reading its lower triangle only
                              (half the bytes; the operators are symmetric). */
+  double fp32_pivot_min;  /* VB_PREC_MIXED: an FP32 pivot of a local Dirichlet
+                             factorisation (its sign times the diagonal entry,
+                             before the square root) at or below this value
+                             counts as a breakdown of that subdomain's block, as
+                             a wrong-signed or zero pivot does; such blocks are
+                             factored again in FP64 (see vb_setup).  0 (default):
+                             only wrong-signed or zero pivots.  In the units of
+                             the local matrices; must be finite and >= 0. */
 } vb_options;
 
 enum { VB_PCG_AUTO = 0, VB_PCG_GRAPH = 1, VB_PCG_PERSISTENT = 2 };
@@ -230,8 +238,23 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
  * factorisations and Schur complements S_Gamma^(i) with the condensed
  * right-hand side, change of basis, deluxe (or counting) scaling, local
  * constrained Neumann operators and the coarse problem.  Returns
- * VB_ERR_NOT_SPD (subdomain index in vb_last_error) on a pivot breakdown. */
+ * VB_ERR_NOT_SPD (subdomain index in vb_last_error) on a pivot breakdown.
+ * In VB_PREC_MIXED a subdomain whose FP32 Dirichlet factorisation breaks
+ * down (eq. uipi: either level of the two-level scheme) is densified and
+ * factored again in FP64, and its FP64 factors, inverse diagonal blocks and
+ * Schur complement are rounded into its FP32 storage (the outer FP64
+ * refinement corrects the rounding); vb_fp64_retries lists those
+ * subdomains.  VB_ERR_NOT_SPD only when the FP64 factorisation breaks down
+ * too.  A breakdown of an FP32 local Neumann factorisation is reported, not
+ * retried. */
 int vb_setup(vb_ctx *ctx);
+
+/* Subdomains (vb_assemble order, ascending) whose local Dirichlet
+ * factorisation the last vb_setup redid in FP64 after an FP32 breakdown.
+ * Returns their number (0 in VB_PREC_FP64 or before a setup) and writes the
+ * first min(number, max) of them to subs (host memory; may be NULL when
+ * max = 0); a negative max is VB_ERR_ARG. */
+int vb_fp64_retries(const vb_ctx *ctx, int max, int32_t *subs);
 
 /* Length of the global interface vector: the interface ids of all problems
  * (problem order), then one p0 entry per subdomain (subdomain order). */
@@ -413,7 +436,7 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n,
  * the host: a matrix with n < 0, n > max_n, e < 0, e > n, e > max_e or
  * ld < n is left untouched with info = -1 while the others are factored.
  * Returns VB_ERR_ARG when batch * ceil(max_e / 64) * 64 * 64 * 8 bytes of
- * inverse diagonal blocks, plus 256 bytes and 48 bytes per matrix, exceed
+ * inverse diagonal blocks, plus 256 bytes and 56 bytes per matrix, exceed
  * VB_NOALLOC_SCRATCH_BYTES.  Every call on a GPU uses that GPU's one array:
  * calls that overlap on one GPU (other threads, other contexts' streams)
  * race and must be serialised by the caller.  Stream-ordered on the

@@ -28,7 +28,8 @@ class vb_options(C.Structure):
                 ("stream", C.c_void_p), ("profile", C.c_int), ("adaptive_theta", C.c_double),
                 ("predictor", C.c_void_p),
                 ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double),
-                ("pcg_launch", C.c_int), ("schur_kernel", C.c_int)]
+                ("pcg_launch", C.c_int), ("schur_kernel", C.c_int),
+                ("fp32_pivot_min", C.c_double)]
 
 
 class vb_problem(C.Structure):
@@ -102,6 +103,7 @@ def load():
         "vb_local_size": (C.c_int64, [P, C.c_int]),
         "vb_set_profile": (C.c_int, [P, C.c_int]),
         "vb_pcg_launch_used": (C.c_int, [P]),
+        "vb_fp64_retries": (C.c_int, [P, C.c_int, C.POINTER(C.c_int32)]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_batched_ldl_noalloc": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
@@ -144,7 +146,7 @@ def exported_symbols():
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
             "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
-            "vb_batched_ldl_noalloc", "vb_pcg_launch_used"]
+            "vb_batched_ldl_noalloc", "vb_pcg_launch_used", "vb_fp64_retries"]
 
 
 class VBError(RuntimeError):
@@ -193,11 +195,11 @@ def _check(ctx, rc):
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
               svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
               predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0, pcg_launch=0,
-              schur_kernel=0):
+              schur_kernel=0, fp32_pivot_min=0.0):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
                      adaptive_theta, predictor, setup_mem_limit, local_mem_limit, pcg_launch,
-                     schur_kernel)
+                     schur_kernel, fp32_pivot_min)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -326,6 +328,17 @@ def vb_kernel_stats(ctx, which, reset=False):
 
 def vb_pcg_launch_used(ctx):
     return int(load().vb_pcg_launch_used(ctx))
+
+
+def vb_fp64_retries(ctx):
+    """Subdomains whose Dirichlet factorisation the last vb_setup redid in FP64."""
+    lib = load()
+    n = lib.vb_fp64_retries(ctx, 0, None)
+    if n < 0:
+        raise VBError(n, "vb_fp64_retries")
+    buf = (C.c_int32 * max(n, 1))()
+    n = lib.vb_fp64_retries(ctx, n, buf)
+    return [int(buf[i]) for i in range(n)]
 
 
 def vb_set_profile(ctx, on):

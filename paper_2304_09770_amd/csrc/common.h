@@ -43,7 +43,9 @@ template <typename T> struct LdlJob {
   int64_t ld;
   int n, e, p, pad;
   T *invL;     // per panel: NB*NB block (column-major) of inv(L_jj); panels stored consecutively
-  int *info;   // 0 or 1 + column of the first wrong-signed pivot
+  int *info;   // 0 or 1 + column of the first pivot at or below pmin (after its sign)
+  double pmin; // a signed pivot (d_j times the diagonal entry, before its square root)
+               // must exceed this value; 0: only wrong-signed or zero pivots fail
 };
 
 // Batched C = alpha * A * B^T + beta * C, all column-major.

@@ -45,7 +45,7 @@ __global__ __launch_bounds__(256) void k_ldl_diag(const LdlJob<T> *jobs, int j0)
     if (tid == 0) {
       T d = (j0 + c < J.p) ? T(1) : T(-1);
       T v = d * S[c][c];
-      if (!(v > T(0))) {  // wrong-signed or zero pivot: report, keep going finitely
+      if (!(v > T(J.pmin))) {  // wrong-signed, zero or too small pivot: report, keep going finitely
         if (!bad) { bad = 1; atomicCAS(J.info, 0, j0 + c + 1); }
         v = T(1);
       }

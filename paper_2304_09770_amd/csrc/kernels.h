@@ -138,6 +138,8 @@ hipError_t coarse_assemble(const CoarseSub *d_cs, int nsub, double *K, int64_t l
 
 // fp32: the dense local matrices W are float (mixed precision), else double
 hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, bool fp32, hipStream_t s);
+// dst[i] = src[i] rounded to FP32, i < n
+hipError_t cast_to_f32(const double *src, float *dst, int64_t n, hipStream_t s);
 hipError_t flux_rows(const SubDev *d_subs, int nsub, int max_rows, hipStream_t s);
 hipError_t house_pressure(const SubDev *d_subs, int nsub, int max_N, bool fp32, hipStream_t s);
 hipError_t entity_qr(const EntDev *d_ents, int nent, int rmax, double tol, hipStream_t s);

@@ -234,6 +234,7 @@ struct vb_ctx {
   // S~ p through the lower triangle only (chosen by the autotuner when faster)
   SymvJob *j_ssym = nullptr;
   bool ssym_on = false;
+  std::vector<int> fp64_retried;  // subdomains whose Dirichlet factorisation was redone in FP64
   double schur_bytes_full = 0.0, schur_bytes_sym = 0.0;
   // recovery
   double *yrec = nullptr, *zrec = nullptr, *rec_out = nullptr;
@@ -507,7 +508,7 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
       !(d.setup_mem_limit >= 0.0) || !(d.local_mem_limit >= 0.0) || !std::isfinite(d.tol) ||
       !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta) ||
       d.pcg_launch < VB_PCG_AUTO || d.pcg_launch > VB_PCG_PERSISTENT || d.schur_kernel < 0 ||
-      d.schur_kernel > 2) {
+      d.schur_kernel > 2 || !(d.fp32_pivot_min >= 0.0) || !std::isfinite(d.fp32_pivot_min)) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -2195,6 +2196,155 @@ static int adaptive_stage(vb_ctx *ctx) {
 
 static int autotune_gemvs(vb_ctx *ctx);
 
+static int64_t inv_size(const SubH &S) { return (int64_t)((S.e + NB - 1) / NB) * NB * NB; }
+
+// Mixed precision: the subdomains in `bad` (ascending), whose FP32 Dirichlet
+// factorisation broke down, factored again in FP64 in temporary buffers:
+// densified and their pressures split as before -- in the two-level scheme
+// every front of theirs first, its trailing block scattered into the second
+// level -- with only wrong-signed or zero pivots failing.  The FP64 factors,
+// inverse diagonal blocks and Schur complements are then rounded into the
+// FP32 storage that every later step reads.
+static int retry_fp64(vb_ctx *ctx, const std::vector<int> &bad) {
+  hipStream_t st = ctx->stream;
+  const int nb = (int)bad.size();
+  std::vector<int> frs;  // fronts of the bad subdomains, subdomain by subdomain
+  if (ctx->nd)
+    for (int s : bad)
+      for (int b = 0; b < ctx->subs[s].nbox; ++b) frs.push_back(ctx->subs[s].first_front + b);
+  const int nfr = (int)frs.size();
+  int *d_info = nullptr;
+  UCHK(ctx->dalloc(&d_info, (size_t)(nb + nfr), true));
+  CHK(hipMemsetAsync(d_info, 0, (nb + nfr) * sizeof(int), st));
+  auto check = [&](int off, int cnt, const std::vector<int> &ids, const char *where) -> int {
+    std::vector<int> h(cnt);
+    CHK(hipMemcpyAsync(h.data(), d_info + off, cnt * sizeof(int), hipMemcpyDeviceToHost, st));
+    CHK(hipStreamSynchronize(st));
+    for (int q = 0; q < cnt; ++q)
+      if (h[q])
+        return ctx->fail(VB_ERR_NOT_SPD,
+                         "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
+                             std::to_string(ids[q]) + " at column " + std::to_string(h[q] - 1) + where +
+                             " in FP32 and again in its FP64 retry");
+    return VB_OK;
+  };
+  std::vector<void *> temps;
+  // ---- first level: the fronts
+  std::vector<int64_t> foff(nfr + 1, 0), fioff(nfr + 1, 0);
+  double *fw = nullptr, *fi = nullptr;
+  if (nfr) {
+    std::vector<SubDev> dv(nfr);
+    std::vector<LdlJob<double>> jobs;
+    std::vector<int> ids;
+    int mxN = 0, mxe = 0;
+    for (int q = 0; q < nfr; ++q) {
+      const SubH &F = ctx->fronts[frs[q]].S;
+      foff[q + 1] = foff[q] + F.ld * F.N;
+      fioff[q + 1] = fioff[q] + inv_size(F);
+    }
+    UCHK(ctx->dalloc(&fw, (size_t)foff[nfr], true));
+    UCHK(ctx->dalloc(&fi, (size_t)fioff[nfr], true));
+    temps.push_back(fw);
+    temps.push_back(fi);
+    for (int q = 0; q < nfr; ++q) {
+      const SubH &F = ctx->fronts[frs[q]].S;
+      dv[q] = ctx->frdev[frs[q]];
+      dv[q].W = fw + foff[q];
+      jobs.push_back({fw + foff[q], F.ld, F.N, F.e, F.nv, 0, fi + fioff[q], d_info + nb + q});
+      ids.push_back(ctx->fronts[frs[q]].sub);
+      mxN = std::max(mxN, F.N);
+      mxe = std::max(mxe, F.e);
+    }
+    SubDev *d_dv = nullptr;
+    UCHK(ctx->upload(&d_dv, dv, true));
+    CHK(hipMemsetAsync(fw, 0, foff[nfr] * sizeof(double), st));
+    CHK(densify(d_dv, nfr, ctx->max_nf_csr, false, st));
+    CHK(house_pressure(d_dv, nfr, mxN, false, st));
+    int rc = run_ldl(ctx, jobs, mxN, mxe);
+    if (!rc) rc = check(nb, nfr, ids, " of a sub-box");
+    if (rc) return rc;
+  }
+  // ---- the local matrices (two-level: the second level)
+  std::vector<int64_t> woff(nb + 1, 0), ioff(nb + 1, 0);
+  for (int q = 0; q < nb; ++q) {
+    const SubH &S = ctx->subs[bad[q]];
+    woff[q + 1] = woff[q] + S.ld * S.N;
+    ioff[q + 1] = ioff[q] + inv_size(S);
+  }
+  double *w = nullptr, *wi = nullptr;
+  UCHK(ctx->dalloc(&w, (size_t)woff[nb], true));
+  UCHK(ctx->dalloc(&wi, (size_t)ioff[nb], true));
+  temps.push_back(w);
+  temps.push_back(wi);
+  {
+    std::vector<SubDev> dv(nb);
+    std::vector<LdlJob<double>> jobs;
+    int mxN = 0, mxe = 0;
+    for (int q = 0; q < nb; ++q) {
+      const SubH &S = ctx->subs[bad[q]];
+      dv[q] = ctx->subdev[bad[q]];
+      dv[q].W = w + woff[q];
+      jobs.push_back({w + woff[q], S.ld, S.N, S.e, S.nv, 0, wi + ioff[q], d_info + q});
+      mxN = std::max(mxN, S.N);
+      mxe = std::max(mxe, S.e);
+    }
+    SubDev *d_dv = nullptr;
+    UCHK(ctx->upload(&d_dv, dv, true));
+    CHK(hipMemsetAsync(w, 0, woff[nb] * sizeof(double), st));
+    CHK(densify(d_dv, nb, ctx->max_n_csr, false, st));
+    if (ctx->nd) {  // the fronts' trailing blocks, in sub-box order as in the FP32 pass
+      std::vector<int> first(nb);
+      for (int q = 0, c = 0; q < nb; ++q) {
+        first[q] = c;
+        c += ctx->subs[bad[q]].nbox;
+      }
+      for (int b = 0; b < ctx->max_nbox; ++b) {
+        std::vector<FrontJob> fj;
+        for (int q = 0; q < nb; ++q) {
+          const SubH &S = ctx->subs[bad[q]];
+          if (b >= S.nbox) continue;
+          const FrontH &F = ctx->fronts[S.first_front + b];
+          const int fq = first[q] + b;
+          FrontJob J{};
+          J.Wf = fw + foff[fq];
+          J.ldf = F.S.ld;
+          J.e = F.S.e;
+          J.m = F.S.ng + 2;
+          J.W2 = w + woff[q];
+          J.ld2 = S.ld;
+          J.map = F.d_map;
+          J.gamma = F.gamma;
+          fj.push_back(J);
+        }
+        if (fj.empty()) continue;
+        FrontJob *d_fj = nullptr;
+        UCHK(ctx->upload(&d_fj, fj, true));
+        CHK(front_scatter(d_fj, (int)fj.size(), ctx->max_fm, false, st));
+      }
+    }
+    CHK(house_pressure(d_dv, nb, mxN, false, st));
+    int rc = run_ldl(ctx, jobs, mxN, mxe);
+    if (!rc) rc = check(0, nb, bad, ctx->nd ? " of its separator level" : "");
+    if (rc) return rc;
+  }
+  // ---- rounded into the FP32 storage; the FP32 pass's flags cleared
+  for (int q = 0; q < nfr; ++q) {
+    const SubH &F = ctx->fronts[frs[q]].S;
+    CHK(cast_to_f32(fw + foff[q], (float *)ctx->FW + F.W_off, F.ld * F.N, st));
+    CHK(cast_to_f32(fi + fioff[q], (float *)ctx->invLf + F.inv_off, inv_size(F), st));
+    CHK(hipMemsetAsync(ctx->info_f + frs[q], 0, sizeof(int), st));
+  }
+  for (int q = 0; q < nb; ++q) {
+    const SubH &S = ctx->subs[bad[q]];
+    CHK(cast_to_f32(w + woff[q], (float *)ctx->W + S.W_off, S.ld * S.N, st));
+    CHK(cast_to_f32(wi + ioff[q], (float *)ctx->invL + S.inv_off, inv_size(S), st));
+    CHK(hipMemsetAsync(ctx->info + bad[q], 0, sizeof(int), st));
+  }
+  for (void *t : temps) ctx->free_setup_early(t);
+  ctx->fp64_retried.insert(ctx->fp64_retried.end(), bad.begin(), bad.end());
+  return VB_OK;
+}
+
 // Dense bordered local matrices of subdomains [s0, s1) (one wave sharing W):
 // densify the CSR, rotate the pressures, partial LDL^T of the interior
 // columns.  Deterministic: a wave factorised again reproduces its factors.
@@ -2220,7 +2370,7 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
     for (int s = s0; s < s1; ++s) {
       SubH &S = ctx->subs[s];
       jobs.push_back({(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
-                      (float *)ctx->invL + S.inv_off, ctx->info + s});
+                      (float *)ctx->invL + S.inv_off, ctx->info + s, ctx->opt.fp32_pivot_min});
     }
     rc = run_ldl(ctx, jobs, mxN, mxe, timed);
   } else {
@@ -2233,15 +2383,18 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
     rc = run_ldl(ctx, jobs, mxN, mxe, timed);
   }
   if (rc) return rc;
-  std::vector<int> h(s1 - s0);
+  std::vector<int> h(s1 - s0), bad;
   CHK(hipMemcpyAsync(h.data(), ctx->info + s0, h.size() * sizeof(int), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
-  for (size_t q = 0; q < h.size(); ++q)
-    if (h[q])
+  for (size_t q = 0; q < h.size(); ++q) {
+    if (!h[q]) continue;
+    if (!f32)
       return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
                                            std::to_string(s0 + (int)q) + " at column " +
                                            std::to_string(h[q] - 1));
-  return VB_OK;
+    bad.push_back(s0 + (int)q);
+  }
+  return bad.empty() ? VB_OK : retry_fp64(ctx, bad);
 }
 
 // The two-level factorisation: every front (sub-box) densified, its
@@ -2264,21 +2417,25 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
     for (int f = 0; f < nF; ++f) {
       const SubH &F = ctx->fronts[f].S;
       jobs.push_back({(T *)ctx->FW + F.W_off, F.ld, F.N, F.e, F.nv, 0, (T *)ctx->invLf + F.inv_off,
-                      ctx->info_f + f});
+                      ctx->info_f + f, f32 ? ctx->opt.fp32_pivot_min : 0.0});
     }
     int rc = run_ldl(ctx, jobs, ctx->max_Nf, ctx->max_ef, timed);
     if (rc) return rc;
   }
+  std::vector<char> broke(nS, 0);  // mixed precision: subdomains to factor again in FP64
   {
     std::vector<int> h(nF);
     CHK(hipMemcpyAsync(h.data(), ctx->info_f, nF * sizeof(int), hipMemcpyDeviceToHost, st));
     CHK(hipStreamSynchronize(st));
-    for (int f = 0; f < nF; ++f)
-      if (h[f])
+    for (int f = 0; f < nF; ++f) {
+      if (!h[f]) continue;
+      if (!f32)
         return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
                                              std::to_string(ctx->fronts[f].sub) + " at column " +
                                              std::to_string(h[f] - 1) + " of its sub-box " +
                                              std::to_string(ctx->fronts[f].box));
+      broke[ctx->fronts[f].sub] = 1;
+    }
   }
   const SubH &SL = ctx->subs.back();
   CHK(hipMemsetAsync(ctx->W, 0, (SL.W_off + SL.ld * SL.N) * ctx->wsz, st));
@@ -2292,7 +2449,7 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
     for (int s = 0; s < nS; ++s) {
       const SubH &S = ctx->subs[s];
       jobs.push_back({(T *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0, (T *)ctx->invL + S.inv_off,
-                      ctx->info + s});
+                      ctx->info + s, f32 ? ctx->opt.fp32_pivot_min : 0.0});
     }
     int rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, timed);
     if (rc) return rc;
@@ -2300,12 +2457,15 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
   std::vector<int> h(nS);
   CHK(hipMemcpyAsync(h.data(), ctx->info, nS * sizeof(int), hipMemcpyDeviceToHost, st));
   CHK(hipStreamSynchronize(st));
-  for (int s = 0; s < nS; ++s)
-    if (h[s])
+  std::vector<int> bad;
+  for (int s = 0; s < nS; ++s) {
+    if (h[s] && !f32)
       return ctx->fail(VB_ERR_NOT_SPD, "Dirichlet factorisation (subdomain index): pivot breakdown in block " +
                                            std::to_string(s) + " at column " + std::to_string(h[s] - 1) +
                                            " of its separator level");
-  return VB_OK;
+    if (h[s] || broke[s]) bad.push_back(s);
+  }
+  return bad.empty() ? VB_OK : retry_fp64(ctx, bad);
 }
 
 static int factor_nd(vb_ctx *ctx, bool timed) {
@@ -2356,6 +2516,7 @@ static int setup_impl(vb_ctx *ctx) {
   hipStream_t st = ctx->stream;
   const int nS = ctx->nS;
   const int64_t nG = ctx->nG;
+  ctx->fp64_retried.clear();
   // start from the given constraints
   for (auto &H : ctx->ents) {
     H.ncon = H.ncon0;
@@ -4116,6 +4277,13 @@ int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_ei
   if (eigs)
     for (int i = 0; i < std::min((int)ctx->face_eigs.size(), max_eigs); ++i) eigs[i] = ctx->face_eigs[i];
   return nf;
+}
+
+int vb_fp64_retries(const vb_ctx *ctx, int max, int32_t *subs) {
+  if (!ctx || max < 0 || (max > 0 && !subs)) return VB_ERR_ARG;
+  const int n = (int)ctx->fp64_retried.size();
+  for (int i = 0; i < std::min(n, max); ++i) subs[i] = ctx->fp64_retried[i];
+  return n;
 }
 
 int vb_pcg_launch_used(const vb_ctx *ctx) { return ctx ? ctx->last_launch : VB_ERR_ARG; }

@@ -40,6 +40,19 @@ hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, bool fp32, hipS
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(256) void k_cast_f32(const double *src, float *dst, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = (float)src[i];
+}
+
+hipError_t cast_to_f32(const double *src, float *dst, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(k_cast_f32, dim3((unsigned)blocks), dim3(256), 0, s, src, dst, n);
+  return hipGetLastError();
+}
+
 // B0_Gamma^(i): the equation tested with the constant pressure on the
 // subdomain (eq. discMat) is the sum of the element flux rows; by symmetry of
 // the local matrix, entry l is the sum over pressure columns of interface row

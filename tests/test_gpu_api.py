@@ -13,9 +13,13 @@
   the previous setup may leak into the next);
 * counting scaling (the pseudo-inverse weights of the paper's
   multiplicity-based averaging) against the oracle with the same scaling;
+* mixed precision retries a subdomain whose FP32 Dirichlet factorisation
+  breaks down in FP64 (a pivot floor set from the host forces the
+  breakdown) and still reaches the oracle's solution;
 * bad input data map to error codes (every kernel still runs to its end):
   a local velocity block that is not positive definite makes vb_setup return
-  VB_ERR_NOT_SPD naming the subdomain, a primal space without the face
+  VB_ERR_NOT_SPD naming the subdomain (in mixed precision after its FP64
+  retry breaks down too), a primal space without the face
   fluxes makes it return VB_ERR_SINGULAR_COARSE, and a NaN in a right-hand
   side makes vb_pcg_solve return VB_ERR_BREAKDOWN; inconsistent CSR row
   pointers or a
@@ -155,22 +159,72 @@ def _copy(wl):
             "subs": [{k: np.array(v, copy=True) for k, v in sd.items()} for sd in wl["subs"]]}
 
 
-def test_non_spd_local_block_is_reported(vb, c1):
+@pytest.mark.parametrize("precision", [0, 1])
+def test_non_spd_local_block_is_reported(vb, c1, precision):
+    """Also in mixed precision, where the block is first retried in FP64."""
     bad = _copy(c1)
     sd = bad["subs"][3]
     vel = sd["kind"] != 2  # velocity DoFs (interior and interface)
     rows = np.repeat(np.arange(len(sd["kind"])), np.diff(sd["indptr"]))
     vv = vel[rows] & vel[sd["indices"]]
     sd["data"][vv] *= -1.0  # the velocity block negative definite
-    ctx = vb.vb_create()
+    ctx = vb.vb_create(precision=precision)
     try:
         vb.vb_assemble(ctx, bad)
         with pytest.raises(vb.VBError) as e:
             vb.vb_setup(ctx)
         assert e.value.code == VB_ERR_NOT_SPD
         assert "block 3 " in str(e.value)
+        if precision == 1:
+            assert "FP64 retry" in str(e.value)
     finally:
         vb.vb_destroy(ctx)
+
+
+def _scaled(wl, s, c):
+    """The workload with subdomain s's local matrix and right-hand side
+    multiplied by c: the same saddle structure (a coefficient jump), every
+    pivot of its factorisation multiplied by c."""
+    w = _copy(wl)
+    w["subs"][s]["data"] = w["subs"][s]["data"] * c
+    w["subs"][s]["rhs"] = w["subs"][s]["rhs"] * c
+    return w
+
+
+@pytest.mark.parametrize("nested", [False, True])
+def test_fp64_retry_of_fp32_breakdown(vb, c1, nested):
+    """Mixed precision, VB_ERR_NOT_SPD's retry clause.  On c1 every pivot of
+    a local Dirichlet factorisation lies far above 1e-7: velocity pivots are
+    at least lambda_min of the interior velocity block (2.3e-2; eliminating
+    pressures first only raises them), pressure pivots lie in the spectrum of
+    a pressure Schur complement (smallest nonzero eigenvalue 3e-4).  With
+    subdomain 3's local system multiplied by 1e-10 its pivots are at most
+    1e-10 times the largest diagonal entry (4.3), so a pivot floor of 1e-7
+    makes exactly that block break down in FP32.  vb_setup factors it again
+    in FP64, reports it, and the refined solution matches the oracle's on the
+    scaled workload as every mixed case does.  A floor above every pivot
+    retries every subdomain, with the same solution; no floor, none."""
+    cases = [(_scaled(c1, 3, 1e-10), 1e-7, [3]), (c1, 1e300, list(range(8))), (c1, 0.0, [])]
+    for wl, floor, expect in cases:
+        print("fp64 retry case: floor", floor, "nested", nested, flush=True)
+        o = OracleBDDC(wl)
+        ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12, fp32_pivot_min=floor)
+        try:
+            vb.vb_assemble(ctx, wl, nested=nested)
+            vb.vb_setup(ctx)
+            assert vb.vb_fp64_retries(ctx) == expect
+            n = vb.vb_interface_size(ctx)
+            x = torch.zeros(n, dtype=torch.float64, device=DEV)
+            info = vb.vb_pcg_solve(ctx, x)
+            torch.cuda.synchronize()
+            assert info["true_rel_residual"] <= 1e-12
+            xg = x.cpu().numpy()
+            g = o.rhs()
+            assert np.linalg.norm(g - o.apply_S(xg)) <= 1e-10 * np.linalg.norm(g)
+            xo, _ = pcg(o.apply_S, o.apply_M, g, tol=1e-13)
+            assert _rel(xg, xo) < 1e-10, _rel(xg, xo)
+        finally:
+            vb.vb_destroy(ctx)
 
 
 def test_bad_sub_box_labels_are_rejected(vb, c1):

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared():
     txt = open(os.path.join(ROOT, "include", "vembddc.h")).read()
-    return sorted(set(re.findall(r"\b(vb_[a-z_]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(vb_[a-z0-9_]+)\s*\(", txt)))
 
 
 def test_header_declares_the_boundary():
@@ -85,7 +85,9 @@ def test_binding_structs_match_the_header(tmp_path):
                                 dict(setup_mem_limit=-1.0), dict(local_mem_limit=float("nan")),
                                 dict(tol=float("nan")), dict(tol=float("inf")),
                                 dict(svd_tol=float("nan")), dict(adaptive_theta=-1.0),
-                                dict(adaptive_theta=float("nan"))])
+                                dict(adaptive_theta=float("nan")), dict(fp32_pivot_min=-1.0),
+                                dict(fp32_pivot_min=float("nan")),
+                                dict(fp32_pivot_min=float("inf"))])
 def test_bad_options_are_rejected_on_the_host(kw):
     """vb_create checks its options before any HIP call, so this runs without
     a GPU."""
