@@ -19,7 +19,7 @@ local condensation's flops (dense as executed, and a sparse LU estimate) and
 the oracle's CPU baseline.  The timed solves run as in production (per-launch
 timing off, the PCG iteration replayed as a HIP graph); the kernel figures
 come from one more solve with per-launch HIP-event timing, outside the timed
-region.  `--config c1|c2|c4|c5s` select the other workloads.
+region.  `--config c1|c2|c4|c4l|c5s|deg2|deg3|deg4` select the other workloads.
 """
 import argparse
 import json
@@ -41,6 +41,10 @@ WORKLOADS = {
           "inside and 1 outside, 4x4x4 subdomains, vertex+edge+face, deluxe, adaptive face "
           "constraints theta=10 through the learned predictor (trained on the exact eigensolves "
           "of sinker seeds 1, 2), FP64",
+    "c4l": "36^3 cube, VEM k=2, 8 spherical sinkers (radius 0.1, centres seed 0) with nu=1e4 "
+           "inside and 1 outside, 3x3x3 subdomains of 12^3 elements (faces of about 1,500 dual "
+           "coordinates), vertex+edge+face, deluxe, adaptive face constraints theta=10 through "
+           "the learned predictor (trained on the exact eigensolves of sinker seeds 1, 2), FP64",
     "c5s": "32 independent problems in one context, each 12^3 jittered cube (0.15h, one mesh), "
            "VEM k=3, 3x3x3 subdomains, nu per subdomain log-uniform in [1e-3, 1e3] (seed = "
            "problem), vertex+edge+face, deluxe, adaptive theta=10 through the learned predictor, "
@@ -351,7 +355,7 @@ def main():
         return
     if args.config == "c5s":
         return run_batched(args)
-    if args.config == "c4":
+    if args.config in ("c4", "c4l"):
         return run_adaptive(args)
     # ---- workload (before any GPU initialisation)
     from inputs.workloads import make_workload, save_workload, load_workload
@@ -497,15 +501,17 @@ def main():
 
 
 def run_adaptive(args):
-    """C4: the adaptive coarse space through the learned predictor against the
-    exact adaptive space and the minimal primal space (the plain FP64 GPU
-    method), all FP64 (the contrast of 1e4 inside subdomains)."""
+    """C4 (and c4l: the same sinkers with 12^3-element subdomains): the
+    adaptive coarse space through the learned predictor against the exact
+    adaptive space and the minimal primal space (the plain FP64 GPU method),
+    all FP64 (the contrast of 1e4 inside subdomains)."""
     from inputs.workloads import make_workload, mlp_init_params
     t = time.perf_counter()
     nw = min(16, os.cpu_count() or 1)
-    wl, _ = make_workload("c4", seed=0, workers=nw)
-    train = [make_workload("c4", seed=sd, workers=nw)[0] for sd in C4_TRAIN_SEEDS]
-    log("generated c4 and %d training workloads (%.1f s)" % (len(train), time.perf_counter() - t))
+    name = args.config
+    wl, _ = make_workload(name, seed=0, workers=nw)
+    train = [make_workload(name, seed=sd, workers=nw)[0] for sd in C4_TRAIN_SEEDS]
+    log("generated %s and %d training workloads (%.1f s)" % (name, len(train), time.perf_counter() - t))
     import torch
     from paper_2304_09770_amd import binding as vb
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -597,7 +603,7 @@ def run_adaptive(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "c4: " + WORKLOADS["c4"], "subdomains": len(wl["subs"]),
+        "config": {"workload": name + ": " + WORKLOADS[name], "subdomains": len(wl["subs"]),
                    "precision": "fp64"},
         "roofline": ldl_roofline(ldl, PEAK_FP64_TFLOPS, "f64"),
         "runs": runs,

@@ -109,10 +109,11 @@ typedef struct vb_options {
                              same order: the results are identical.  AUTO picks
                              the persistent launch when one S_hat application
                              reads less than 1 GB, else the graph. */
-  int schur_kernel;       /* S_hat p: 0 = chosen by the autotuner, 1 = full-matrix
-                             GEMV of each bordered local operator, 2 = the tiled
-                             symmetric kernel reading its lower triangle only
-                             (half the bytes; the operators are symmetric). */
+  int schur_kernel;       /* the symmetric per-iteration operators (S_hat p, and
+                             S_DeltaDelta^-1 of the local Neumann solves): 0 =
+                             each chosen by the autotuner, 1 = full-matrix GEMVs,
+                             2 = the tiled symmetric kernel reading the lower
+                             triangle only (half the bytes). */
   double fp32_pivot_min;  /* VB_PREC_MIXED: an FP32 pivot of a local Dirichlet
                              factorisation (its sign times the diagonal entry,
                              before the square root) at or below this value
@@ -121,6 +122,17 @@ typedef struct vb_options {
                              factored again in FP64 (see vb_setup).  0 (default):
                              only wrong-signed or zero pivots.  In the units of
                              the local matrices; must be finite and >= 0. */
+  int tune_factor;        /* the dense factorisations' panel width (32 or 64)
+                             and outer super-panel (the rank of each trailing
+                             update: 8, 16 or 32 panels), chosen per class
+                             (local Dirichlet or its fronts, the second level
+                             of the two-level scheme, local Neumann) by timing
+                             the context's first factorisation of that class
+                             with each candidate: 0 = when that factorisation
+                             is large (more than 2e11 e n^2 summed over its
+                             matrices), 1 = always, 2 = never (panel and
+                             16-panel super-panels).  Results differ only by
+                             rounding.  See vb_tuned_tile. */
 } vb_options;
 
 enum { VB_PCG_AUTO = 0, VB_PCG_GRAPH = 1, VB_PCG_PERSISTENT = 2 };
@@ -272,7 +284,14 @@ int vb_num_problems(const vb_ctx *ctx);
  * per-iteration GEMVs: which = 0 S_hat p, 1 Neumann, 2 deluxe restriction,
  * 3 coarse; 0 before the first setup.  which = 4: 1 if S_hat p reads only
  * the lower triangle of each symmetric local operator (the tiled symmetric
- * kernel, timed against the best full-matrix tile), else 0. */
+ * kernel, timed against the best full-matrix tile), else 0.  which = 5: 1 if
+ * the local Neumann solves read only the lower triangle of the symmetric
+ * S_DeltaDelta^-1 block of [S_DeltaDelta^-1 | Phi] (the same kernel, plus a
+ * GEMV of the Phi block), else 0.  which = 6, 7, 8: the panel width of the
+ * local Dirichlet factorisation (single level, or the fronts of the
+ * two-level scheme), of its second level, of the local Neumann
+ * factorisation; which = 9, 10, 11: their outer super-panel columns (see
+ * vb_options.tune_factor); 0 before that factorisation has run. */
 int vb_tuned_tile(const vb_ctx *ctx, int which);
 int vb_problem_layout(const vb_ctx *ctx, int problem, vb_problem *out);
 /* Per-problem result of the last vb_pcg_solve (the info that call returns

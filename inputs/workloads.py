@@ -56,6 +56,10 @@ RECIPES = {
     "c2": dict(n=32, jitter=0.15, k=2, parts=(4, 4, 4), cons=FULL),
     "c3": dict(n=48, jitter=0.15, k=2, random_cuts=(4, 12, 6), cons=FULL),
     "c4": dict(n=32, jitter=0.0, k=2, parts=(4, 4, 4), cons=FULL, sinkers=True),
+    # C4's sinkers with 12^3-element subdomains: faces of 12 x 12 elements
+    # (about 1,500 dual coordinates each), where the dense face eigensolve
+    # grows as the cube of the face size
+    "c4l": dict(n=36, jitter=0.0, k=2, parts=(3, 3, 3), cons=FULL, sinkers=True),
     "c5": dict(n=24, jitter=0.15, k=3, parts=(3, 3, 3), cons=FULL, nu_per_sub=True),
     "t8j": dict(n=8, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL),
     "t12": dict(n=12, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL),

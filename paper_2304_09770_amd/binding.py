@@ -29,7 +29,7 @@ class vb_options(C.Structure):
                 ("predictor", C.c_void_p),
                 ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double),
                 ("pcg_launch", C.c_int), ("schur_kernel", C.c_int),
-                ("fp32_pivot_min", C.c_double)]
+                ("fp32_pivot_min", C.c_double), ("tune_factor", C.c_int)]
 
 
 class vb_problem(C.Structure):
@@ -195,11 +195,11 @@ def _check(ctx, rc):
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
               svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
               predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0, pcg_launch=0,
-              schur_kernel=0, fp32_pivot_min=0.0):
+              schur_kernel=0, fp32_pivot_min=0.0, tune_factor=0):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
                      adaptive_theta, predictor, setup_mem_limit, local_mem_limit, pcg_launch,
-                     schur_kernel, fp32_pivot_min)
+                     schur_kernel, fp32_pivot_min, tune_factor)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:

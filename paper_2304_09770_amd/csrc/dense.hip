@@ -609,8 +609,11 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer, const std::vector<int> *hn,
-                       const std::vector<int> *he, bool dirichlet, bool aligned16) {
+                       const std::vector<int> *he, bool dirichlet, bool aligned16, int sb1) {
   if (batch == 0 || max_e == 0) return hipSuccess;
+  if (nb != 32 && nb != 64) return hipErrorInvalidValue;
+  if (sb1 == 0) sb1 = 16 * nb;
+  if (sb1 <= 0 || sb1 % (4 * nb)) return hipErrorInvalidValue;
   static bool attr = false;
   const size_t lds = 2 * (size_t)WideKW<T>::value * WT * sizeof(T);
   if (!attr) {
@@ -632,7 +635,7 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
   // are factored in inner super-panels (SB2) of nb-wide panels; the update
   // of the rest of the outer super-panel follows each inner one, the update
   // of the whole trailing matrix each outer one (rank SB1)
-  const int SB1 = 16 * nb, SB2 = 4 * nb;
+  const int SB1 = sb1, SB2 = 4 * nb;
   for (int J0 = 0; J0 < max_e; J0 += SB1) {
     const int j1end = std::min(J0 + SB1, max_e);
     for (int J1 = J0; J1 < j1end; J1 += SB2) {
@@ -698,10 +701,10 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 
 template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t,
                                         KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                        bool, bool);
+                                        bool, bool, int);
 template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t,
                                        KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                       bool, bool);
+                                       bool, bool, int);
 template hipError_t gemm_nt_batched<double>(const GemmJob<double> *, int, int, int, hipStream_t);
 template hipError_t gemm_nt_batched<float>(const GemmJob<float> *, int, int, int, hipStream_t);
 

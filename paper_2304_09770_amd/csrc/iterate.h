@@ -138,6 +138,9 @@ struct PcgPlan {
   GemvPhase schur, restrict_, neu1, coarse, neu2;  // neu2: gemv_n (batch 0: none)
   const SymvJob *ssym;  // non-null: S~ p by the symmetric kernel (schur unused)
   int ssym_batch, ssym_tiles, ssym_rows;
+  const SymvJob *nsym;  // non-null: the S_DD^-1 block of neu1 by the symmetric kernel and
+  int nsym_batch, nsym_tiles, nsym_rows;  // its Phi block by nphi (neu1 unused)
+  GemvPhase nphi;
   const ExtJob *ext;
   const ExtPart *extpart;
   int n_ext, ext_gx;

@@ -37,25 +37,29 @@ __device__ __forceinline__ void gemv_t_block(const GemvJob *jobs, int bx, int by
     for (int q = 0; q < NQ; ++q) {
       const int j = j0 + w + 4 * q;
       if (j >= J.n) break;
-      double s0 = 0.0, s1 = 0.0;
-      if (J.a_f32) {
-        const auto col = gptr((const float *)J.A + (int64_t)j * J.lda + c0);
+      // eight loads per lane in flight, then pairs, then the last row
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      auto dot = [&](auto col) {
         int i = l;
+        for (; i + 448 < cm; i += 512) {
+          const double a0 = col[i], a1 = col[i + 64], a2 = col[i + 128], a3 = col[i + 192];
+          const double a4 = col[i + 256], a5 = col[i + 320], a6 = col[i + 384], a7 = col[i + 448];
+          s0 += a0 * xs[i] + a4 * xs[i + 256];
+          s1 += a1 * xs[i + 64] + a5 * xs[i + 320];
+          s2 += a2 * xs[i + 128] + a6 * xs[i + 384];
+          s3 += a3 * xs[i + 192] + a7 * xs[i + 448];
+        }
         for (; i + 64 < cm; i += 128) {
           s0 += (double)col[i] * xs[i];
           s1 += (double)col[i + 64] * xs[i + 64];
         }
         if (i < cm) s0 += (double)col[i] * xs[i];
-      } else {
-        const auto col = gptr((const double *)J.A + (int64_t)j * J.lda + c0);
-        int i = l;
-        for (; i + 64 < cm; i += 128) {
-          s0 += col[i] * xs[i];
-          s1 += col[i + 64] * xs[i + 64];
-        }
-        if (i < cm) s0 += col[i] * xs[i];
-      }
-      acc[q] += s0 + s1;
+      };
+      if (J.a_f32)
+        dot(gptr((const float *)J.A + (int64_t)j * J.lda + c0));
+      else
+        dot(gptr((const double *)J.A + (int64_t)j * J.lda + c0));
+      acc[q] += (s0 + s1) + (s2 + s3);
     }
   }
 #pragma unroll
@@ -673,11 +677,16 @@ hipError_t sinit(int P, const double *tol, int maxit, double *sc, hipStream_t s)
 // Tile (ti, tj), tj <= ti, of job `by` (tile index t = ti (ti + 1) / 2 + tj):
 // lane l of every wave holds rows R0 + l + 64 k (k < 4) of the tile, so each
 // column read is four coalesced 64-entry loads (no alignment needed); the
-// four waves split the tile's columns.  Row sums use x of the columns
-// (staged in LDS), column sums x of the rows (in registers) reduced across
-// the wave, lane l keeping its wave's column l.  On a diagonal tile the row
-// sums take the entries on and below the diagonal, the column sums those
-// strictly below, so that every entry of the full matrix is used once.
+// four waves split the tile's columns and take them SYMV_U at a time, so
+// that 4 SYMV_U loads per lane are in flight.  Row sums use x of the columns
+// (staged in LDS), column sums x of the rows (in registers): the SYMV_U
+// column sums of a step are reduced across the wave together by a butterfly
+// (each exchange halves the values a lane carries), after which lanes
+// 8u .. 8u + 7 hold column u's sum.  On a diagonal tile the row sums take
+// the entries on and below the diagonal, the column sums those strictly
+// below, so that every entry of the full matrix is used once.
+constexpr int SYMV_U = 8;
+
 template <typename T>
 __device__ __forceinline__ void symv_tile(const SymvJob &J, int t, double *xs, double (*red)[SYMV_T]) {
   int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
@@ -693,39 +702,69 @@ __device__ __forceinline__ void symv_tile(const SymvJob &J, int t, double *xs, d
   }
   double xr[4], racc[4];
   bool rin[4];
+  int rr[4];  // the rows read: rows at or beyond n read row n - 1 and are weighted 0
 #pragma unroll
   for (int k = 0; k < 4; ++k) {
     const int r = R0 + lane + 64 * k;
     rin[k] = r < J.n;
+    rr[k] = min(r, J.n - 1);
     xr[k] = rin[k] ? (J.xidx ? J.x[J.xidx[r]] : J.x[r]) : 0.0;
     racc[k] = 0.0;
   }
   __syncthreads();
   const bool diag = ti == tj;
   const T *A = (const T *)J.A;
-  double csum = 0.0;
-  const int c0 = 64 * w, c1 = min(c0 + 64, J.n - C0);
-  for (int c = c0; c < c1; ++c) {
-    const int j = C0 + c;
-    const auto col = gptr(A + (int64_t)j * J.lda + R0 + lane);
-    double v[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) v[k] = rin[k] ? (double)col[64 * k] : 0.0;
-    const double xj = xs[c];
-    double cp = 0.0;
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      const int r = R0 + lane + 64 * k;
-      const double vr = (!diag || r >= j) ? v[k] : 0.0;
-      const double vc = (!diag || r > j) ? v[k] : 0.0;
-      racc[k] += vr * xj;
-      cp += vc * xr[k];
-    }
-    cp = warp_sum(cp);
-    if (lane == c - c0) csum = cp;
-  }
   double *P = J.part + (int64_t)t * 2 * SYMV_T;
-  P[SYMV_T + 64 * w + lane] = csum;
+  const bool b5 = lane & 32, b4 = lane & 16, b3 = lane & 8;
+  const int c0 = 64 * w, c1 = min(c0 + 64, J.n - C0);
+  for (int c = c0; c < c1; c += SYMV_U) {  // c + SYMV_U - 1 <= c0 + 63
+    // every load in bounds and unconditional (columns past c1 read column
+    // c1 - 1), so that all 4 SYMV_U of them are issued before the first use
+    double v[SYMV_U][4];
+#pragma unroll
+    for (int u = 0; u < SYMV_U; ++u) {
+      const bool cin = c + u < c1;
+      const auto col = gptr(A + (int64_t)(C0 + min(c + u, c1 - 1)) * J.lda);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)  // weighted, not selected: the load stays unconditional
+        v[u][k] = (double)col[rr[k]] * ((cin && rin[k]) ? 1.0 : 0.0);
+    }
+    double cp[SYMV_U];
+#pragma unroll
+    for (int u = 0; u < SYMV_U; ++u) {
+      const int j = C0 + c + u;
+      const double xj = xs[c + u];
+      double sc = 0.0;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int r = R0 + lane + 64 * k;
+        const double vr = (!diag || r >= j) ? v[u][k] : 0.0;
+        const double vc = (!diag || r > j) ? v[u][k] : 0.0;
+        racc[k] += vr * xj;
+        sc += vc * xr[k];
+      }
+      cp[u] = sc;
+    }
+    // butterfly over lane bits 5, 4, 3: the lane keeps the half of its
+    // values selected by its bit and adds the partner's copy of that half
+    double a4[4], a2[2];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const double keep = b5 ? cp[i + 4] : cp[i], send = b5 ? cp[i] : cp[i + 4];
+      a4[i] = keep + __shfl_xor(send, 32);
+    }
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const double keep = b4 ? a4[i + 2] : a4[i], send = b4 ? a4[i] : a4[i + 2];
+      a2[i] = keep + __shfl_xor(send, 16);
+    }
+    double a1 = (b3 ? a2[1] : a2[0]) + __shfl_xor(b3 ? a2[0] : a2[1], 8);
+    a1 += __shfl_xor(a1, 4);
+    a1 += __shfl_xor(a1, 2);
+    a1 += __shfl_xor(a1, 1);
+    const int u = lane >> 3;  // the column this lane now holds
+    if ((lane & 7) == 0 && c + u < c1) P[SYMV_T + c + u] = a1;
+  }
 #pragma unroll
   for (int k = 0; k < 4; ++k) red[w][lane + 64 * k] = racc[k];
   __syncthreads();
@@ -885,7 +924,25 @@ __global__ __launch_bounds__(256) void k_pcg_persistent(const PcgPlan *plan) {
       gemv_phase(L.restrict_, xs);
       if (!sync()) return;
     }
-    gemv_phase(L.neu1, xs);
+    if (L.nsym) {  // [S_DD^-1 | Phi]^T g: the symmetric block's tiles and the Phi block
+      const int nv = L.nsym_tiles * L.nsym_batch;
+      for (int v = blockIdx.x; v < nv; v += nb) {
+        const SymvJob J = L.nsym[v / L.nsym_tiles];
+        const int t = v % L.nsym_tiles;
+        if (t >= symv_tiles(J.n)) continue;
+        if (J.a_f32)
+          symv_tile<float>(J, t, xs, (double(*)[SYMV_T])&part4[0][0]);
+        else
+          symv_tile<double>(J, t, xs, (double(*)[SYMV_T])&part4[0][0]);
+      }
+      gemv_phase(L.nphi, xs);
+      if (!sync()) return;
+      const int nr = L.nsym_rows * L.nsym_batch;
+      for (int v = blockIdx.x * bsz + tid; v < nr; v += nb * bsz)
+        symv_reduce_at(L.nsym[v / L.nsym_rows], v % L.nsym_rows);
+    } else {
+      gemv_phase(L.neu1, xs);
+    }
     if (!sync()) return;
     for (int64_t g = (int64_t)blockIdx.x * bsz + tid; g < L.n_cs; g += (int64_t)nb * bsz)
       owner_sum_at(g, L.n_cs, L.c_ptr, L.c_idx, L.tv, L.c_base, L.r, L.rc);

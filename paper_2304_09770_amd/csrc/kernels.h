@@ -49,11 +49,13 @@ struct KTimer {
 };
 
 // ---------------------------------------------------------------- dense
+// nb: panel width (32 or 64); sb1: columns of an outer super-panel, whose
+// trailing update is one rank-sb1 product (a multiple of 4 nb; 0 = 16 nb)
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer = nullptr,
                        const std::vector<int> *hn = nullptr, const std::vector<int> *he = nullptr,
-                       bool dirichlet = false, bool aligned16 = false);
+                       bool dirichlet = false, bool aligned16 = false, int sb1 = 0);
 template <typename T>
 hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int max_n,
                            hipStream_t s);

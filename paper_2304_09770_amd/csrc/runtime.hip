@@ -8,6 +8,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -202,6 +203,10 @@ struct vb_ctx {
   // autotuned columns per workgroup of the per-iteration GEMVs:
   // 0 S_hat p, 1 Neumann, 2 deluxe restriction, 3 coarse (0 = not tuned yet)
   int cpb[4] = {0, 0, 0, 0};
+  // factorisation classes (0: local Dirichlet or its fronts, 1: second
+  // level, 2: local Neumann): panel width and outer super-panel, 0 = not yet
+  // chosen
+  int fac_nb[3] = {0, 0, 0}, fac_sb[3] = {0, 0, 0};
   double clock_khz = 0.0;
   // adaptive coarse space of the last setup
   std::vector<vb_face_info> face_info;
@@ -234,6 +239,9 @@ struct vb_ctx {
   // S~ p through the lower triangle only (chosen by the autotuner when faster)
   SymvJob *j_ssym = nullptr;
   bool ssym_on = false;
+  SymvJob *j_nsym = nullptr;  // the S_DD^-1 blocks of the Neumann operators, lower triangle
+  GemvJob *j_nphi = nullptr;  // their Phi blocks
+  bool nsym_on = false;
   std::vector<int> fp64_retried;  // subdomains whose Dirichlet factorisation was redone in FP64
   double schur_bytes_full = 0.0, schur_bytes_sym = 0.0;
   // recovery
@@ -508,7 +516,8 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
       !(d.setup_mem_limit >= 0.0) || !(d.local_mem_limit >= 0.0) || !std::isfinite(d.tol) ||
       !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta) ||
       d.pcg_launch < VB_PCG_AUTO || d.pcg_launch > VB_PCG_PERSISTENT || d.schur_kernel < 0 ||
-      d.schur_kernel > 2 || !(d.fp32_pivot_min >= 0.0) || !std::isfinite(d.fp32_pivot_min)) {
+      d.schur_kernel > 2 || !(d.fp32_pivot_min >= 0.0) || !std::isfinite(d.fp32_pivot_min) ||
+      d.tune_factor < 0 || d.tune_factor > 2) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -1208,7 +1217,7 @@ extern "C" {
 // ------------------------------------------------------------------ setup
 template <typename T>
 static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max_e,
-                   bool timed = false) {
+                   bool timed = false, int nb = 0, int sb1 = 0) {
   if (jobs.empty()) return VB_OK;
   LdlJob<T> *dj = nullptr;
   UCHK(ctx->upload(&dj, jobs, true));
@@ -1220,10 +1229,70 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
     aligned16 = aligned16 && (jobs[b].ld * sizeof(T)) % 16 == 0 &&
                 reinterpret_cast<uintptr_t>(jobs[b].A) % 16 == 0;
   }
-  CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, ctx->opt.panel, ctx->stream,
+  CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, nb ? nb : ctx->opt.panel, ctx->stream,
                      (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he, timed,
-                     aligned16));
+                     aligned16, sb1));
   return VB_OK;
+}
+
+// Panel width of the local Dirichlet factors of a level (0: single level or
+// fronts, 1: second level): the step of the triangular sweeps over them.
+static int dir_nb(const vb_ctx *ctx, int level) {
+  return ctx->fac_nb[level] ? ctx->fac_nb[level] : ctx->opt.panel;
+}
+
+// The factorisation of class `cls` (see vb_ctx::fac_nb) with its chosen
+// panel width and super-panel.  The first time a class runs, if the
+// options ask for it, every candidate is timed on these very matrices
+// (prepare() forms them again before each further run) and the fastest is
+// kept for the context; the last candidate's factors stand when it is the
+// fastest, otherwise the matrices are formed and factored once more.
+template <typename T>
+static int tuned_ldl(vb_ctx *ctx, int cls, std::vector<LdlJob<T>> &jobs, int max_n, int max_e,
+                     bool timed, const std::function<int()> &prepare) {
+  if (ctx->fac_nb[cls] == 0) {
+    double work = 0.0;
+    for (const auto &J : jobs) work += (double)J.e * J.n * J.n;
+    const bool tune = !jobs.empty() && (ctx->opt.tune_factor == 1 ||
+                                        (ctx->opt.tune_factor == 0 && work > 2e11));
+    if (!tune) {
+      ctx->fac_nb[cls] = ctx->opt.panel;
+      ctx->fac_sb[cls] = 16 * ctx->opt.panel;
+    } else {
+      static const int cand[][2] = {{64, 1024}, {64, 512}, {64, 2048}, {32, 512}, {32, 1024}, {32, 256}};
+      const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+      hipEvent_t e0, e1;
+      CHK(hipEventCreate(&e0));
+      CHK(hipEventCreate(&e1));
+      float best = 1e30f;
+      int pick = 0;
+      int rc = VB_OK;
+      for (int c = 0; c < nc && !rc; ++c) {
+        if (c > 0) rc = prepare();
+        if (rc) break;
+        if (hipEventRecord(e0, ctx->stream) != hipSuccess) rc = VB_ERR_DEVICE;
+        if (!rc) rc = run_ldl(ctx, jobs, max_n, max_e, false, cand[c][0], cand[c][1]);
+        if (!rc && (hipEventRecord(e1, ctx->stream) != hipSuccess ||
+                    hipEventSynchronize(e1) != hipSuccess))
+          rc = VB_ERR_DEVICE;
+        float ms = 0.f;
+        if (!rc && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) rc = VB_ERR_DEVICE;
+        if (!rc && ms < best) {
+          best = ms;
+          pick = c;
+        }
+      }
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      if (rc) return rc == VB_ERR_DEVICE ? ctx->fail(rc, "factorisation autotuner: HIP event error") : rc;
+      ctx->fac_nb[cls] = cand[pick][0];
+      ctx->fac_sb[cls] = cand[pick][1];
+      if (pick == nc - 1 && !(timed && ctx->opt.profile)) return VB_OK;
+      int rp = prepare();
+      if (rp) return rp;
+    }
+  }
+  return run_ldl(ctx, jobs, max_n, max_e, timed, ctx->fac_nb[cls], ctx->fac_sb[cls]);
 }
 
 static int run_gather(vb_ctx *ctx, const std::vector<GatherJob> &jobs, int max_m, int max_n) {
@@ -2260,7 +2329,7 @@ static int retry_fp64(vb_ctx *ctx, const std::vector<int> &bad) {
     CHK(hipMemsetAsync(fw, 0, foff[nfr] * sizeof(double), st));
     CHK(densify(d_dv, nfr, ctx->max_nf_csr, false, st));
     CHK(house_pressure(d_dv, nfr, mxN, false, st));
-    int rc = run_ldl(ctx, jobs, mxN, mxe);
+    int rc = run_ldl(ctx, jobs, mxN, mxe, false, ctx->fac_nb[0], ctx->fac_sb[0]);
     if (!rc) rc = check(nb, nfr, ids, " of a sub-box");
     if (rc) return rc;
   }
@@ -2323,7 +2392,8 @@ static int retry_fp64(vb_ctx *ctx, const std::vector<int> &bad) {
       }
     }
     CHK(house_pressure(d_dv, nb, mxN, false, st));
-    int rc = run_ldl(ctx, jobs, mxN, mxe);
+    const int lv = ctx->nd ? 1 : 0;  // the inverse blocks must match the sweeps' panel width
+    int rc = run_ldl(ctx, jobs, mxN, mxe, false, ctx->fac_nb[lv], ctx->fac_sb[lv]);
     if (!rc) rc = check(0, nb, bad, ctx->nd ? " of its separator level" : "");
     if (rc) return rc;
   }
@@ -2360,11 +2430,15 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
     mxe = std::max(mxe, S.e);
   }
   const int64_t w0 = ctx->subs[s0].W_off;
-  CHK(hipMemsetAsync((char *)ctx->W + w0 * ctx->wsz, 0, (wend - w0) * ctx->wsz, st));
-  CHK(densify(ctx->d_subdev + s0, s1 - s0, ctx->max_n_csr, f32, st));
-  CHK(house_pressure(ctx->d_subdev + s0, s1 - s0, mxN, f32, st));
-  CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
-  int rc;
+  auto prepare = [&]() -> int {
+    CHK(hipMemsetAsync((char *)ctx->W + w0 * ctx->wsz, 0, (wend - w0) * ctx->wsz, st));
+    CHK(densify(ctx->d_subdev + s0, s1 - s0, ctx->max_n_csr, f32, st));
+    CHK(house_pressure(ctx->d_subdev + s0, s1 - s0, mxN, f32, st));
+    CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
+    return VB_OK;
+  };
+  int rc = prepare();
+  if (rc) return rc;
   if (f32) {
     std::vector<LdlJob<float>> jobs;
     for (int s = s0; s < s1; ++s) {
@@ -2372,7 +2446,7 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
       jobs.push_back({(float *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
                       (float *)ctx->invL + S.inv_off, ctx->info + s, ctx->opt.fp32_pivot_min});
     }
-    rc = run_ldl(ctx, jobs, mxN, mxe, timed);
+    rc = tuned_ldl(ctx, 0, jobs, mxN, mxe, timed, prepare);
   } else {
     std::vector<LdlJob<double>> jobs;
     for (int s = s0; s < s1; ++s) {
@@ -2380,7 +2454,7 @@ static int factor_wave(vb_ctx *ctx, int s0, int s1, bool timed) {
       jobs.push_back({(double *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0,
                       (double *)ctx->invL + S.inv_off, ctx->info + s});
     }
-    rc = run_ldl(ctx, jobs, mxN, mxe, timed);
+    rc = tuned_ldl(ctx, 0, jobs, mxN, mxe, timed, prepare);
   }
   if (rc) return rc;
   std::vector<int> h(s1 - s0), bad;
@@ -2408,10 +2482,17 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
   const bool f32 = ctx->fp32;
   const int nS = ctx->nS, nF = (int)ctx->fronts.size();
   const FrontH &FL = ctx->fronts.back();
-  CHK(hipMemsetAsync(ctx->FW, 0, (FL.S.W_off + FL.S.ld * FL.S.N) * ctx->wsz, st));
-  CHK(densify(ctx->d_frdev, nF, ctx->max_nf_csr, f32, st));
-  CHK(house_pressure(ctx->d_frdev, nF, ctx->max_Nf, f32, st));
-  CHK(hipMemsetAsync(ctx->info_f, 0, nF * sizeof(int), st));
+  auto prepare_f = [&]() -> int {
+    CHK(hipMemsetAsync(ctx->FW, 0, (FL.S.W_off + FL.S.ld * FL.S.N) * ctx->wsz, st));
+    CHK(densify(ctx->d_frdev, nF, ctx->max_nf_csr, f32, st));
+    CHK(house_pressure(ctx->d_frdev, nF, ctx->max_Nf, f32, st));
+    CHK(hipMemsetAsync(ctx->info_f, 0, nF * sizeof(int), st));
+    return VB_OK;
+  };
+  {
+    int rc = prepare_f();
+    if (rc) return rc;
+  }
   {
     std::vector<LdlJob<T>> jobs;
     for (int f = 0; f < nF; ++f) {
@@ -2419,7 +2500,7 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
       jobs.push_back({(T *)ctx->FW + F.W_off, F.ld, F.N, F.e, F.nv, 0, (T *)ctx->invLf + F.inv_off,
                       ctx->info_f + f, f32 ? ctx->opt.fp32_pivot_min : 0.0});
     }
-    int rc = run_ldl(ctx, jobs, ctx->max_Nf, ctx->max_ef, timed);
+    int rc = tuned_ldl(ctx, 0, jobs, ctx->max_Nf, ctx->max_ef, timed, prepare_f);
     if (rc) return rc;
   }
   std::vector<char> broke(nS, 0);  // mixed precision: subdomains to factor again in FP64
@@ -2438,12 +2519,19 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
     }
   }
   const SubH &SL = ctx->subs.back();
-  CHK(hipMemsetAsync(ctx->W, 0, (SL.W_off + SL.ld * SL.N) * ctx->wsz, st));
-  CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, f32, st));
-  for (int b = 0; b < ctx->max_nbox; ++b)
-    CHK(front_scatter(ctx->d_fj_scatter[b], (int)ctx->fj_scatter[b].size(), ctx->max_fm, f32, st));
-  CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, f32, st));
-  CHK(hipMemsetAsync(ctx->info, 0, nS * sizeof(int), st));
+  auto prepare_2 = [&]() -> int {
+    CHK(hipMemsetAsync(ctx->W, 0, (SL.W_off + SL.ld * SL.N) * ctx->wsz, st));
+    CHK(densify(ctx->d_subdev, nS, ctx->max_n_csr, f32, st));
+    for (int b = 0; b < ctx->max_nbox; ++b)
+      CHK(front_scatter(ctx->d_fj_scatter[b], (int)ctx->fj_scatter[b].size(), ctx->max_fm, f32, st));
+    CHK(house_pressure(ctx->d_subdev, nS, ctx->max_N, f32, st));
+    CHK(hipMemsetAsync(ctx->info, 0, nS * sizeof(int), st));
+    return VB_OK;
+  };
+  {
+    int rc = prepare_2();
+    if (rc) return rc;
+  }
   {
     std::vector<LdlJob<T>> jobs;
     for (int s = 0; s < nS; ++s) {
@@ -2451,7 +2539,7 @@ static int factor_nd_t(vb_ctx *ctx, bool timed) {
       jobs.push_back({(T *)ctx->W + S.W_off, S.ld, S.N, S.e, S.nv, 0, (T *)ctx->invL + S.inv_off,
                       ctx->info + s, f32 ? ctx->opt.fp32_pivot_min : 0.0});
     }
-    int rc = run_ldl(ctx, jobs, ctx->max_N, ctx->max_e, timed);
+    int rc = tuned_ldl(ctx, 1, jobs, ctx->max_N, ctx->max_e, timed, prepare_2);
     if (rc) return rc;
   }
   std::vector<int> h(nS);
@@ -2809,11 +2897,20 @@ static int setup_impl(vb_ctx *ctx) {
         mxr = std::max(mxr, std::max(S.ndl, S.npi));
         mxc = std::max(mxc, std::max(S.ndl, S.npi));
       }
+      const int64_t woff = off;
+      auto prepare = [&]() -> int {  // the wave's augmented matrices formed again
+        CHK(hipMemsetAsync(Nbuf, 0, woff * nsz, st));
+        int r = run_gather(ctx, gj, mxg, mxg);
+        if (!r) r = run_diag(ctx, dj, ctx->max_ndl);
+        if (!r) CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
+        return r;
+      };
       rc = run_gather(ctx, gj, mxg, mxg);
       if (!rc) rc = run_diag(ctx, dj, ctx->max_ndl);
       if (!rc) {
         CHK(hipMemsetAsync(ctx->info + s0, 0, (s1 - s0) * sizeof(int), st));
-        rc = nf ? run_ldl(ctx, lj32, max_m, max_e) : run_ldl(ctx, lj, max_m, max_e);
+        rc = nf ? tuned_ldl(ctx, 2, lj32, max_m, max_e, false, prepare)
+                : tuned_ldl(ctx, 2, lj, max_m, max_e, false, prepare);
       }
       if (!rc) {
         std::vector<int> h(s1 - s0);
@@ -3180,6 +3277,27 @@ static int setup_impl(vb_ctx *ctx) {
       jn2[s] = {(const char *)S.G1 + (int64_t)S.ndl * S.ndl * gsz, std::max(S.ndl, 1), S.ndl, S.npi,
                 ctx->uc, dci, ctx->tv + sto[s], ctx->wv + sgo[s], 1.0, 0, ctx->fp32 ? 1 : 0};
     }
+    {  // the same [S_DD^-1 | Phi]^T g as a symmetric product and a Phi^T g GEMV
+      int64_t ptot = 0;
+      for (auto &S : ctx->subs) ptot += (int64_t)symv_tiles(S.ndl) * 2 * SYMV_T;
+      double *pbuf = nullptr;
+      UCHK(ctx->dalloc(&pbuf, std::max<int64_t>(ptot, 1)));
+      std::vector<SymvJob> nj(nS);
+      std::vector<GemvJob> pj(nS);
+      int64_t po = 0;
+      const size_t gsz = ctx->fp32 ? sizeof(float) : sizeof(double);
+      for (int s = 0; s < nS; ++s) {
+        const SubH &S = ctx->subs[s];
+        nj[s] = {S.G1, std::max(S.ndl, 1), S.ndl, ctx->fp32 ? 1 : 0, ctx->gD + sgo[s], nullptr,
+                 ctx->tv + sto[s], 1.0, 0, pbuf + po};
+        po += (int64_t)symv_tiles(S.ndl) * 2 * SYMV_T;
+        pj[s] = {(const char *)S.G1 + (int64_t)S.ndl * S.ndl * gsz, std::max(S.ndl, 1), S.ndl, S.npi,
+                 ctx->gD + sgo[s], nullptr, nullptr, ctx->tv + sto[s] + S.ndl, 1.0, 0,
+                 ctx->fp32 ? 1 : 0};
+      }
+      UCHK(ctx->upload(&ctx->j_nsym, nj));
+      UCHK(ctx->upload(&ctx->j_nphi, pj));
+    }
     UCHK(ctx->upload(&ctx->j_schur, js));
     UCHK(ctx->upload(&ctx->j_neu1, jn1));
     UCHK(ctx->upload(&ctx->j_neu2, jn2));
@@ -3400,7 +3518,12 @@ static int apply_M_internal(vb_ctx *ctx) {  // z <- M~^-1 r
   auto cp = [&](int k) { return ctx->cpb[k] ? ctx->cpb[k] : 32; };
   if (ctx->n_restrict)
     CHK(gemv_t_cpb(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, ctx->max_rm, cp(2), st));
-  CHK(gemv_t_cpb(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, cp(1), st));
+  if (ctx->nsym_on) {
+    CHK(symv(ctx->j_nsym, ctx->nS, ctx->max_ndl, st));
+    CHK(gemv_t_cpb(ctx->j_nphi, ctx->nS, ctx->max_ndl, ctx->max_npi, cp(1), st));
+  } else {
+    CHK(gemv_t_cpb(ctx->j_neu1, ctx->nS, ctx->max_ndl, ctx->max_nt, cp(1), st));
+  }
   CHK(owner_sum(ctx->nCS, ctx->c_ptr, ctx->c_idx, ctx->tv, ctx->c_base, ctx->r, ctx->rc, st));
   CHK(gemv_t_cpb(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, ctx->max_ncs, cp(3), st));
   if (ctx->max_ndl) CHK(gemv_n(ctx->j_neu2, ctx->nS, ctx->max_ndl, ctx->max_npi, st));
@@ -3458,6 +3581,22 @@ static int autotune_gemvs(vb_ctx *ctx) {
       CHK(hipEventElapsedTime(&ms, e0, e1));
       ctx->ssym_on = ctx->opt.schur_kernel == 2 || (ctx->opt.schur_kernel == 0 && ms < best);
       ctx->schur_bytes = ctx->ssym_on ? ctx->schur_bytes_sym : ctx->schur_bytes_full;
+    }
+    if (k == 1) {  // [S_DD^-1 | Phi]^T g: symmetric block + Phi block against the full GEMV
+      auto both = [&]() -> hipError_t {
+        hipError_t e = symv(ctx->j_nsym, ctx->nS, ctx->max_ndl, st);
+        if (e == hipSuccess && ctx->max_npi > 0)
+          e = gemv_t_cpb(ctx->j_nphi, ctx->nS, ctx->max_ndl, ctx->max_npi, pick, st);
+        return e;
+      };
+      CHK(both());
+      CHK(hipEventRecord(e0, st));
+      for (int r = 0; r < 3; ++r) CHK(both());
+      CHK(hipEventRecord(e1, st));
+      CHK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      CHK(hipEventElapsedTime(&ms, e0, e1));
+      ctx->nsym_on = ctx->opt.schur_kernel == 2 || (ctx->opt.schur_kernel == 0 && ms < best);
     }
   }
   (void)hipEventDestroy(e0);
@@ -3598,6 +3737,13 @@ static bool persistent_plan(vb_ctx *ctx) {
   }
   L.restrict_ = ph(ctx->j_restrict, ctx->n_restrict, ctx->max_rm, cp(2));
   L.neu1 = ph(ctx->j_neu1, ctx->nS, ctx->max_nt, cp(1));
+  if (ctx->nsym_on) {
+    L.nsym = ctx->j_nsym;
+    L.nsym_batch = ctx->nS;
+    L.nsym_tiles = symv_tiles(ctx->max_ndl);
+    L.nsym_rows = ctx->max_ndl;
+    L.nphi = ph(ctx->j_nphi, ctx->nS, ctx->max_npi, cp(1));
+  }
   L.coarse = ph(ctx->j_coarse, (int)ctx->probs.size(), ctx->max_ncs, cp(3));
   L.neu2 = GemvPhase{ctx->j_neu2, ctx->max_ndl ? ctx->nS : 0, (ctx->max_ndl + 255) / 256, 0};
   L.ext = ctx->j_ext;
@@ -3818,7 +3964,7 @@ static int state_to_local(vb_ctx *ctx, const double *x_orig) {
 // substitution.
 static int condense_residual_nd(vb_ctx *ctx, const double *x_orig) {
   hipStream_t st = ctx->stream;
-  const int nS = ctx->nS, nF = (int)ctx->fronts.size(), nb = ctx->opt.panel;
+  const int nS = ctx->nS, nF = (int)ctx->fronts.size(), nb = dir_nb(ctx, 0), nb2 = dir_nb(ctx, 1);
   CHK(hipMemcpyAsync(ctx->G2, x_orig, (ctx->nG + nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
   int rc = state_to_local(ctx, x_orig);
   if (rc) return rc;
@@ -3833,9 +3979,9 @@ static int condense_residual_nd(vb_ctx *ctx, const double *x_orig) {
     CHK(front_rhs(ctx->d_fj_rhs[b], (int)ctx->fj_rhs[b].size(), st));
   CHK(l2_residual(ctx->d_subdev, ctx->R_loc, ctx->d_uoff, ctx->y_ir, ctx->d_yoff2, nS, st));
   CHK(segment_sum(nS, ctx->d_fr_first, ctx->r0f, ctx->r0, st));
-  for (int i0 = 0; i0 < ctx->max_e; i0 += nb)
+  for (int i0 = 0; i0 < ctx->max_e; i0 += nb2)
     CHK(forward_step(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir, ctx->d_yoff2, nS, i0,
-                     nb, ctx->max_N, ctx->fp32, st));
+                     nb2, ctx->max_N, ctx->fp32, st));
   return VB_OK;
 }
 
@@ -3847,7 +3993,7 @@ static int condense_residual(vb_ctx *ctx, const double *x_orig) {
                      st));
   CHK(residual_to_dense(ctx->d_subdev, ctx->R_loc, ctx->d_uoff, ctx->y_ir, ctx->d_yoff2, ctx->r0,
                         ctx->nS, ctx->max_n_csr, st));
-  const int nb = ctx->opt.panel;
+  const int nb = dir_nb(ctx, 0);
   for (int i0 = 0; i0 < ctx->max_e; i0 += nb)
     CHK(forward_step(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir, ctx->d_yoff2,
                      ctx->nS, i0, nb, ctx->max_N, ctx->fp32, st));
@@ -3858,13 +4004,13 @@ static int condense_residual(vb_ctx *ctx, const double *x_orig) {
 // K_II dz = y_I - C dx through L^T, then zst += dz.
 static int interior_correction(vb_ctx *ctx, const double *dx) {
   hipStream_t st = ctx->stream;
-  const int nb = ctx->opt.panel;
+  const int nb = dir_nb(ctx, 0), nb2 = dir_nb(ctx, ctx->nd ? 1 : 0);
   if (ctx->max_e > 0) {
     CHK(back_rhs(ctx->d_subdev, ctx->z_ir, dx, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e,
                  ctx->fp32, st));
-    for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+    for (int j0 = ((ctx->max_e - 1) / nb2) * nb2; j0 >= 0; j0 -= nb2)
       CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir,
-                            ctx->d_yoff2, ctx->nS, j0, nb, ctx->fp32, st));
+                            ctx->d_yoff2, ctx->nS, j0, nb2, ctx->fp32, st));
   }
   if (ctx->nd) {
     // the fronts see the interface correction and the separator corrections
@@ -4124,16 +4270,16 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
                          hipMemcpyDeviceToDevice, st));
     return VB_OK;
   }
-  const int nb = ctx->opt.panel;  // the panel width the factorisation used
+  const int nb = dir_nb(ctx, 0);  // the panel widths the factorisations used
   if (ctx->nd) {
     // second level: separator velocities and sub-box constants; then every
     // front from its separator and interface values and its constant
-    const int nS = ctx->nS, nF = (int)ctx->fronts.size();
+    const int nS = ctx->nS, nF = (int)ctx->fronts.size(), nb2 = dir_nb(ctx, 1);
     if (ctx->max_e > 0) {
       CHK(recover_rhs(ctx->d_subdev, x_dev, ctx->yrec, ctx->d_yoff, nS, ctx->max_e, ctx->fp32, st));
-      for (int j0 = ((ctx->max_e - 1) / nb) * nb; j0 >= 0; j0 -= nb)
+      for (int j0 = ((ctx->max_e - 1) / nb2) * nb2; j0 >= 0; j0 -= nb2)
         CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->yrec, ctx->zrec, ctx->d_yoff,
-                              nS, j0, nb, ctx->fp32, st));
+                              nS, j0, nb2, ctx->fp32, st));
     }
     CHK(hipMemcpyAsync(ctx->G2, x_dev, (ctx->nG + nS) * sizeof(double), hipMemcpyDeviceToDevice, st));
     CHK(recover_out(ctx->j_rec, nS, x_dev, ctx->nG, st));
@@ -4243,8 +4389,11 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n, c
 extern "C" {
 
 int vb_tuned_tile(const vb_ctx *ctx, int which) {
-  if (!ctx || which < 0 || which > 4) return VB_ERR_ARG;
+  if (!ctx || which < 0 || which > 11) return VB_ERR_ARG;
+  if (which >= 6 && which <= 8) return ctx->fac_nb[which - 6];
+  if (which >= 9) return ctx->fac_sb[which - 9];
   if (which == 4) return ctx->ssym_on ? 1 : 0;
+  if (which == 5) return ctx->nsym_on ? 1 : 0;
   return ctx->cpb[which];
 }
 

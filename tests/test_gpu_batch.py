@@ -288,10 +288,11 @@ def test_persistent_launch_matches_graph_and_oracle(vb, wls, oracles, precision)
 
 @pytest.mark.parametrize("precision", [0, 1])
 def test_symmetric_schur_kernel_matches_full_and_oracle(vb, wls, oracles, precision):
-    """S_hat p through the lower triangle of each bordered local operator
-    (tiled symmetric kernel) against the full-matrix GEMV: the operators are
-    symmetric to rounding, so S_hat x agrees to 1e-13 and the solutions to
-    the PCG tolerance; against the oracle as every other path."""
+    """S_hat p and the local Neumann solves' S_DeltaDelta^-1 through the lower
+    triangle of each symmetric local operator (tiled symmetric kernel)
+    against the full-matrix GEMVs: the operators are symmetric to rounding,
+    so S_hat x agrees to 1e-13, M^-1 r to 1e-12 and the solutions to the PCG
+    tolerance; against the oracle as every other path."""
     from oracle.pcg import pcg
     tol = 1e-8 if precision == 0 else 1e-12
     out = {}
@@ -302,19 +303,25 @@ def test_symmetric_schur_kernel_matches_full_and_oracle(vb, wls, oracles, precis
                 vb.vb_assemble(ctx, wl)
             vb.vb_setup(ctx)
             assert vb.vb_tuned_tile(ctx, 4) == (1 if kern == 2 else 0)
+            assert vb.vb_tuned_tile(ctx, 5) == (1 if kern == 2 else 0)
             n = vb.vb_interface_size(ctx)
             v = torch.tensor(np.random.default_rng(9).standard_normal(n), device=DEV)
             y = torch.zeros(n, dtype=torch.float64, device=DEV)
             vb.vb_schur_apply(ctx, v, y)
+            z = torch.zeros(n, dtype=torch.float64, device=DEV)
+            vb.vb_apply(ctx, y, z)
             x = torch.zeros(n, dtype=torch.float64, device=DEV)
             vb.vb_pcg_solve(ctx, x)
             its = [vb.vb_problem_solve_info(ctx, k)["iterations"] for k in range(len(wls))]
             xs = [_split(vb, ctx, x.cpu().numpy(), k) for k in range(len(wls))]
-            out[kern] = (y.cpu().numpy(), xs, its)
+            out[kern] = (y.cpu().numpy(), z.cpu().numpy(), xs, its)
         finally:
             vb.vb_destroy(ctx)
-    (y1, x1, i1), (y2, x2, i2) = out[1], out[2]
+    (y1, z1, x1, i1), (y2, z2, x2, i2) = out[1], out[2]
     assert _rel(y2, y1) < 1e-13 if precision == 0 else _rel(y2, y1) < 1e-6
+    # M^-1 r on the interface entries (the p0 entries are fixed up to constants)
+    nG = len(y1) - sum(len(w["subs"]) for w in wls)
+    assert _rel(z2[:nG], z1[:nG]) < (1e-12 if precision == 0 else 1e-5), _rel(z2[:nG], z1[:nG])
     for k, o in enumerate(oracles):
         if precision == 0:
             xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), fixed_iters=i2[k])
