@@ -247,6 +247,45 @@ def oracle_full_c1():
             "solves_per_s": 1.0 / (t3 - t0), "cores": int(_blas_threads())}
 
 
+def vem_assembly(vb, config, stream, dev):
+    """The workload's element matrices (A^K, B^K, F^K of every element of its
+    mesh) by vb_vem_element_matrices, timed on the GPU (second of two calls),
+    beside the host generator's element computation on a 256-element sample
+    (one process), scaled to all elements."""
+    import torch
+    from inputs.workloads import RECIPES
+    from inputs.mesh import CubeMesh
+    from inputs.vem import element_matrices
+    r = RECIPES[config]
+    mesh = CubeMesh(r["n"], jitter=r["jitter"], seed=0)
+    k, E = r["k"], mesh.nK
+    N, nP = vb.vb_vem_dofs(k)
+    X8 = torch.tensor(np.ascontiguousarray(mesh.verts[mesh.elem_verts].reshape(E, 24)), device=dev)
+    A = torch.empty((E, N, N), dtype=torch.float64, device=dev)
+    B = torch.empty((E, nP, N), dtype=torch.float64, device=dev)
+    F = torch.empty((E, N), dtype=torch.float64, device=dev)
+    ctx = vb.vb_create(stream=stream.cuda_stream)
+    try:
+        times = []
+        for _ in range(2):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            vb.vb_vem_element_matrices(ctx, k, X8, None, A, B, F)
+            times.append(time.perf_counter() - t0)
+    finally:
+        vb.vb_destroy(ctx)
+    del A, B, F, X8
+    torch.cuda.empty_cache()
+    el = np.arange(min(E, 256))
+    t0 = time.perf_counter()
+    element_matrices(mesh, k, el, 1.0)
+    th = (time.perf_counter() - t0) / len(el)
+    return {"elements": int(E), "k": int(k), "dofs_per_element": int(N), "gpu_s": times[-1],
+            "host_s_per_element": th, "host_estimate_s": th * E,
+            "note": "A^K, B^K and F^K of every element on the GPU; the host figure is the "
+                    "generator's element computation (one process) on 256 elements, scaled"}
+
+
 def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
     """Create a context for one precision, then time `steps` solves (after
     `warmup` untimed ones) with per-launch timing off, so that the PCG
@@ -322,6 +361,8 @@ def main():
     ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--cache", default=None, help="workload .npz (generated if missing)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-vem", action="store_true",
+                    help="skip the GPU element-matrix timing (outside the timed region)")
     ap.add_argument("--cpu-budget", type=float, default=20.0,
                     help="seconds of oracle work in the CPU baseline's sample")
     ap.add_argument("--precision", default="both", choices=["both", "fp64", "mixed"],
@@ -428,6 +469,12 @@ def main():
     for r in runs.values():
         if r["ctx"] is not None:
             vb.vb_destroy(r["ctx"])
+    torch.cuda.empty_cache()
+    vem = None
+    if not args.no_vem:
+        vem = vem_assembly(vb, args.config, stream, dev)
+        log("element matrices of %d elements on the GPU: %.3f s (host generator: %.1f s estimated)"
+            % (vem["elements"], vem["gpu_s"], vem["host_estimate_s"]))
     head = "mixed" if "mixed" in runs else "fp64"
     R = runs[head]
     if head == "fp64":
@@ -493,7 +540,8 @@ def main():
         "outside_timed_region": {"workload_generation_s": t_ass,
                                  "note": "mesh, VEM assembly and decomposition on the host "
                                          "(the paper's T_ass analogue) and vb_assemble's "
-                                         "host copies are not in the timed solves"},
+                                         "host copies are not in the timed solves",
+                                 "vem_element_matrices": vem},
         "cpu_baseline": cpu,
         "oracle_full_c1": full_c1,
     }
@@ -508,10 +556,10 @@ def run_adaptive(args):
     from inputs.workloads import make_workload, mlp_init_params
     t = time.perf_counter()
     nw = min(16, os.cpu_count() or 1)
-    name = args.config
-    wl, _ = make_workload(name, seed=0, workers=nw)
-    train = [make_workload(name, seed=sd, workers=nw)[0] for sd in C4_TRAIN_SEEDS]
-    log("generated %s and %d training workloads (%.1f s)" % (name, len(train), time.perf_counter() - t))
+    cfg = args.config
+    wl, _ = make_workload(cfg, seed=0, workers=nw)
+    train = [make_workload(cfg, seed=sd, workers=nw)[0] for sd in C4_TRAIN_SEEDS]
+    log("generated %s and %d training workloads (%.1f s)" % (cfg, len(train), time.perf_counter() - t))
     import torch
     from paper_2304_09770_amd import binding as vb
     assert torch.cuda.is_available(), "bench.py needs a GPU"
@@ -603,7 +651,7 @@ def run_adaptive(args):
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": name + ": " + WORKLOADS[name], "subdomains": len(wl["subs"]),
+        "config": {"workload": cfg + ": " + WORKLOADS[cfg], "subdomains": len(wl["subs"]),
                    "precision": "fp64"},
         "roofline": ldl_roofline(ldl, PEAK_FP64_TFLOPS, "f64"),
         "runs": runs,

@@ -428,6 +428,34 @@ int vb_set_profile(vb_ctx *ctx, int on);
  * reports its last inner PCG), 0 before any solve. */
 int vb_pcg_launch_used(const vb_ctx *ctx);
 
+/* Virtual element matrices (Sec. 3).  For n_elem hexahedra with planar
+ * faces, vertex coordinates X8 (device, n_elem x 8 x 3 doubles, local
+ * vertex v = ix + 2 iy + 4 iz of the element's unit-cube corners) and
+ * viscosities nu (device, n_elem; NULL = 1), the degree-k (2 <= k <= 4)
+ * divergence-free element of Sec. 3 with degrees of freedom D1-D5 (vertex
+ * values; values at the k-1 interior Gauss-Lobatto points of each edge;
+ * face moments of v.n, v.t1, v.t2 against the face monomials of degree
+ * <= k-2; the x-wedge volume moments of degree <= k-3; the divergence
+ * moments against the non-constant monomials of degree <= k-1), numbered
+ * vertex by vertex (3 components), edge by edge, face by face, then D4 and
+ * D5 (see vb_vem_dofs for the sizes):
+ *   A (device, n_elem x N x N, row-major): nu_K times the local form of
+ *     eq. discreteA, consistency int Pi^0_{k-1} eps(u) : Pi^0_{k-1} eps(v)
+ *     plus the dof-dof stabilisation sum_i sigma_i dof_i((I - Pi^nabla_k) u)
+ *     dof_i((I - Pi^nabla_k) v), sigma_i = max(h_K, consistency_ii);
+ *   B (device, n_elem x nP x N): int_K div(phi_j) m_a for the scaled
+ *     monomials m_a of degree <= k-1 (row 0: the constant);
+ *   F (device, n_elem x N; with_load != 0): eq. discreteF, int_K f .
+ *     Pi^0_k phi_j for the manufactured load f = (3 pi^2 / 2) nu curl(psi),
+ *     psi = sin(pi x) sin(pi y) sin(pi z) (1, 1, 1), by the rule exact to
+ *     degree 2k+1 on the element's 12 cone tetrahedra.
+ * Runs on the context's stream; returns when done.  VB_ERR_ARG for an
+ * unsupported degree or a missing pointer. */
+int vb_vem_element_matrices(vb_ctx *ctx, int k, int64_t n_elem, const double *X8, const double *nu,
+                            int with_load, double *A, double *B, double *F);
+/* Degrees of freedom N and pressure monomials nP of the degree-k element. */
+int vb_vem_dofs(int k, int *n_dof, int *n_pressure);
+
 /* Batched dense partial signed LDL^T (the kernel under the Dirichlet and
  * Neumann solves).  For each of `batch` column-major matrices A_b (size n_b,
  * leading dimension ld_b, lower triangle referenced) eliminate the first

@@ -104,6 +104,8 @@ def load():
         "vb_set_profile": (C.c_int, [P, C.c_int]),
         "vb_pcg_launch_used": (C.c_int, [P]),
         "vb_fp64_retries": (C.c_int, [P, C.c_int, C.POINTER(C.c_int32)]),
+        "vb_vem_element_matrices": (C.c_int, [P, C.c_int, C.c_int64, P, P, C.c_int, P, P, P]),
+        "vb_vem_dofs": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_batched_ldl_noalloc": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
@@ -146,7 +148,8 @@ def exported_symbols():
             "vb_mlp_forward", "vb_mlp_loss_grad", "vb_mlp_get_params", "vb_mlp_set_params",
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
             "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
-            "vb_batched_ldl_noalloc", "vb_pcg_launch_used", "vb_fp64_retries"]
+            "vb_batched_ldl_noalloc", "vb_pcg_launch_used", "vb_fp64_retries",
+            "vb_vem_element_matrices", "vb_vem_dofs"]
 
 
 class VBError(RuntimeError):
@@ -328,6 +331,31 @@ def vb_kernel_stats(ctx, which, reset=False):
 
 def vb_pcg_launch_used(ctx):
     return int(load().vb_pcg_launch_used(ctx))
+
+
+def vb_vem_dofs(k):
+    n, p = C.c_int(), C.c_int()
+    rc = load().vb_vem_dofs(int(k), C.byref(n), C.byref(p))
+    if rc != VB_OK:
+        raise VBError(rc, "vb_vem_dofs")
+    return n.value, p.value
+
+
+def vb_vem_element_matrices(ctx, k, X8, nu, A, B, F=None):
+    """X8: (E, 8, 3) or (E, 24) float64 device tensor; nu: (E,) or None;
+    A: (E, N, N), B: (E, nP, N), F: (E, N) or None, float64 device tensors."""
+    N, nP = vb_vem_dofs(k)
+    E = X8.shape[0]
+    if X8.numel() != 24 * E or A.numel() < E * N * N or B.numel() < E * nP * N:
+        raise ValueError("vb_vem_element_matrices: array sizes")
+    if nu is not None and nu.numel() < E:
+        raise ValueError("vb_vem_element_matrices: nu")
+    if F is not None and F.numel() < E * N:
+        raise ValueError("vb_vem_element_matrices: F")
+    _check(ctx, load().vb_vem_element_matrices(
+        ctx, int(k), int(E), _ptr(X8, "float64"), _ptr(nu, "float64") if nu is not None else None,
+        1 if F is not None else 0, _ptr(A, "float64"), _ptr(B, "float64"),
+        _ptr(F, "float64") if F is not None else None))
 
 
 def vb_fp64_retries(ctx):

@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 SOURCES = ["dense.hip", "setup.hip", "iterate.hip", "eigen.hip", "mlp.hip", "runtime.hip",
-           "nested.hip", "noalloc.hip"]
+           "nested.hip", "noalloc.hip", "vem.hip"]
 LIB = os.path.join(HERE, "libvembddc.so")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-fPIC", "-std=c++17",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

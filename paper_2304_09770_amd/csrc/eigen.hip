@@ -97,10 +97,10 @@ __global__ __launch_bounds__(1024) void k_tridiag(const EigJob *jobs) {
 hipError_t tridiag(const EigJob *d_jobs, int njobs, int max_n, hipStream_t s) {
   if (!njobs) return hipSuccess;
   const size_t lds = 2 * (size_t)max_n * sizeof(double);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
+  if (lds > 159 * 1024) return hipErrorInvalidValue;  // the static LDS comes on top
+  if (lds > 60 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)k_tridiag,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_tridiag, dim3(njobs), dim3(1024), lds, s, d_jobs);
@@ -268,10 +268,10 @@ __global__ __launch_bounds__(256) void k_tridiag_eig(const EigJob *jobs, int mca
 hipError_t tridiag_eig(const EigJob *d_jobs, int njobs, int max_n, int mcap, hipStream_t s) {
   if (!njobs) return hipSuccess;
   const size_t lds = 8 * (size_t)max_n * sizeof(double) + (size_t)max_n + 16;
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
+  if (lds > 159 * 1024) return hipErrorInvalidValue;  // the static LDS comes on top
+  if (lds > 60 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)k_tridiag_eig,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_tridiag_eig, dim3(njobs), dim3(256), lds, s, d_jobs, mcap);
@@ -327,10 +327,10 @@ __global__ __launch_bounds__(256) void k_lower_times(const RowJob *jobs) {
 hipError_t lower_times(const RowJob *d_jobs, int njobs, int max_n, int max_cols, hipStream_t s) {
   if (!njobs || !max_cols) return hipSuccess;
   const size_t lds = (size_t)max_n * sizeof(double);
-  if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (lds > 64 * 1024) {
+  if (lds > 159 * 1024) return hipErrorInvalidValue;  // the static LDS comes on top
+  if (lds > 60 * 1024) {
     hipError_t e = hipFuncSetAttribute((const void *)k_lower_times,
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
   }
   hipLaunchKernelGGL(k_lower_times, dim3(max_cols, njobs), dim3(256), lds, s, d_jobs);
