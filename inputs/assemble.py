@@ -88,12 +88,13 @@ class Problem:
     """
 
     def __init__(self, mesh, k, nu=1.0, force=None, uD=None, divD=None, keep_full=False,
-                 chunk=None, workers=None, progress=None):
+                 chunk=None, workers=None, progress=None, element_data=None):
         self.mesh, self.k = mesh, k
         L = DofLayout(k)
         self.L = L
         nuK = np.asarray(nu, float) if np.ndim(nu) else np.full(mesh.nK, float(nu))
         self.nu = nuK
+        default_load = force is None
         if force is None:
             force = lambda P, el: 1.5 * np.pi ** 2 * nuK[el][:, None, None] * u_curl(P)
         if uD is None:
@@ -161,8 +162,14 @@ class Problem:
         if keep_full:
             self.full = {"A": np.zeros((m.nK, L.N, L.N)), "B": np.zeros((m.nK, L.nP, L.N)),
                          "F": np.zeros((m.nK, L.N))}
-        uniform = (m.jitter == 0.0)
-        if uniform:
+        # element_data: (A, B, F) of every element for nu = 1 and the default
+        # load, computed elsewhere (A and F scale with nu_K)
+        if element_data is not None:
+            assert default_load, "element_data holds the default load"
+        uniform = (m.jitter == 0.0) and element_data is None
+        if element_data is not None:
+            pass
+        elif uniform:
             ref = element_matrices(m, k, np.array([0]), 1.0)
         elif workers is None or workers > 1:
             chunks = [np.arange(s, min(m.nK, s + chunk)) for s in range(0, m.nK, chunk)]
@@ -182,13 +189,18 @@ class Problem:
                 A = np.broadcast_to(ref["A"], (len(el),) + ref["A"].shape[1:]) * nuK[el][:, None, None]
                 B = np.broadcast_to(ref["B"], (len(el),) + ref["B"].shape[1:])
                 P0 = np.broadcast_to(ref["P0"], (len(el),) + ref["P0"].shape[1:])
-            else:
+            elif element_data is None:
                 if workers is None or workers > 1:
                     A, B, P0 = results[ci]
                 else:
                     A, B, P0 = _chunk_matrices((m, k, el))
                 A = A * nuK[el][:, None, None]
-            F = load_vector(m, k, el, P0, force)
+            if element_data is not None:
+                A = element_data[0][el] * nuK[el][:, None, None]
+                B = element_data[1][el]
+                F = element_data[2][el] * nuK[el][:, None]
+            else:
+                F = load_vector(m, k, el, P0, force)
             Ke[el, :nloc, :nloc] = A[:, keep_local][:, :, keep_local]
             Ke[el, nloc, :nloc] = B[:, 0, keep_local]
             Ke[el, :nloc, nloc] = B[:, 0, keep_local]

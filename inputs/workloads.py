@@ -133,6 +133,45 @@ def make_family(name, seeds, workers=None, mesh_seed=0, **over):
     return out
 
 
+def scaled_family(name, seeds, element_data=None, workers=None, mesh_seed=0, base=None, **over):
+    """The workloads of make_family(name, seeds) from one decomposition: the
+    unit-viscosity problem is decomposed once and each problem's subdomain
+    viscosity scales its subdomain's velocity-velocity entries and velocity
+    right-hand side (the divergence rows and the pressure right-hand side
+    do not depend on nu; the subdomain matrices are sums over the
+    subdomain's elements, whose viscosity is the subdomain's).  The same
+    workloads as make_family up to rounding.  element_data: optional unit
+    element matrices (see Problem).  base: an already decomposed
+    (Decomposition, unit workload) pair to reuse.  Yields the workloads one
+    by one."""
+    r = dict(RECIPES[name])
+    r.update(over)
+    assert r.get("nu_per_sub"), "families vary the per-subdomain viscosity"
+    mesh = CubeMesh(r["n"], jitter=r["jitter"], seed=mesh_seed)
+    cuts = regular_cuts(r["n"], r["parts"])
+    if base is None:
+        pb = Problem(mesh, r["k"], 1.0, workers=workers, element_data=element_data)
+        dec = Decomposition(pb, cuts, r["cons"])
+        base = (dec, dec.workload())
+    dec, wl0 = base
+    for sd in seeds:
+        nu_el = subdomain_viscosity(mesh, cuts, sd)
+        nu_sub = np.zeros(len(wl0["subs"]))
+        nu_sub[dec.elem_sub] = nu_el
+        subs = []
+        for s, sd0 in enumerate(wl0["subs"]):
+            kind = np.asarray(sd0["kind"])
+            vel = kind != 2
+            rows = np.repeat(np.arange(len(kind)), np.diff(sd0["indptr"]))
+            vv = vel[rows] & vel[sd0["indices"]]
+            data = np.array(sd0["data"], copy=True)
+            data[vv] *= nu_sub[s]
+            rhs = np.array(sd0["rhs"], copy=True)
+            rhs[vel] *= nu_sub[s]
+            subs.append(dict(sd0, data=data, rhs=rhs))
+        yield {"n_iface": wl0["n_iface"], "subs": subs, "ents": wl0["ents"]}
+
+
 def save_workload(path, wl):
     """Store a workload as one .npz of plain arrays (no pickles)."""
     arrs = {"n_iface": np.array([wl["n_iface"]]), "nsub": np.array([len(wl["subs"])]),

@@ -425,13 +425,14 @@ static hipError_t launch_apply_T(const SubDev *d_subs, const EntDev *d_ents, int
 template <typename T>
 static hipError_t apply_T_typed(const SubDev *d_subs, const EntDev *d_ents, int nsub, int nx,
                                 int max_ent, int max_en, hipStream_t s) {
-  // as many rows per workgroup as LDS holds (up to 32): the rows of a
-  // column are read and written as one contiguous segment of R entries
-  const size_t row = (size_t)std::max(max_en, 1) * sizeof(T), cap = 150 * 1024;
-  if (32 * row <= 64 * 1024) return launch_apply_T<T, 32>(d_subs, d_ents, nsub, nx, max_ent, 32 * row, s);
-  if (16 * row <= cap) return launch_apply_T<T, 16>(d_subs, d_ents, nsub, nx, max_ent, 16 * row, s);
-  if (8 * row <= cap) return launch_apply_T<T, 8>(d_subs, d_ents, nsub, nx, max_ent, 8 * row, s);
-  if (4 * row <= cap) return launch_apply_T<T, 4>(d_subs, d_ents, nsub, nx, max_ent, 4 * row, s);
+  // rows per workgroup: more rows read longer contiguous segments of each
+  // column, but past 48 KB of LDS fewer workgroups share a CU (at the
+  // 216-subdomain workload the setup took about 90 ms longer with 16 rows
+  // in 101 KB than with 4 rows in 25 KB)
+  const size_t row = (size_t)std::max(max_en, 1) * sizeof(T);
+  if (16 * row <= 48 * 1024) return launch_apply_T<T, 16>(d_subs, d_ents, nsub, nx, max_ent, 16 * row, s);
+  if (8 * row <= 48 * 1024) return launch_apply_T<T, 8>(d_subs, d_ents, nsub, nx, max_ent, 8 * row, s);
+  if (4 * row <= 150 * 1024) return launch_apply_T<T, 4>(d_subs, d_ents, nsub, nx, max_ent, 4 * row, s);
   return hipErrorInvalidValue;  // an entity larger than 4 rows of LDS can hold
 }
 

@@ -317,3 +317,22 @@ def test_sub_box_labels_split_each_subdomain(name):
         sep = (kind == 0) & (part < 0)
         assert np.all(sep <= multi | (np.asarray((touch > 0).sum(axis=1)).ravel() == 0))
         assert not np.any(multi & (kind == 0) & (part >= 0))
+
+
+def test_scaled_family_equals_per_problem_decomposition():
+    """One decomposition scaled by each problem's subdomain viscosity gives
+    the per-problem decomposition's workloads (make_family) to rounding:
+    velocity-velocity entries and velocity right-hand sides scale with the
+    subdomain's nu, divergence rows and pressure right-hand sides do not."""
+    from inputs.workloads import make_family, scaled_family
+    seeds = [3, 4]
+    ref = make_family("c5s", seeds, workers=1, n=6, parts=(2, 2, 2))
+    got = list(scaled_family("c5s", seeds, workers=1, n=6, parts=(2, 2, 2)))
+    for a, b in zip(got, ref):
+        assert a["n_iface"] == b["n_iface"]
+        for sa, sb in zip(a["subs"], b["subs"]):
+            for key in ("indptr", "indices", "kind", "gid"):
+                assert np.array_equal(sa[key], sb[key]), key
+            scale = np.abs(sb["data"]).max()
+            assert np.abs(sa["data"] - sb["data"]).max() <= 1e-13 * scale
+            assert np.abs(sa["rhs"] - sb["rhs"]).max() <= 1e-13 * np.abs(sb["rhs"]).max()
