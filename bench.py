@@ -330,6 +330,7 @@ def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
         launch = {vb.VB_PCG_GRAPH: "graph", vb.VB_PCG_PERSISTENT: "persistent"}.get(
             vb.vb_pcg_launch_used(ctx), "eager")
         sym = vb.vb_tuned_tile(ctx, 4) == 1
+        phases = vb.vb_setup_phases(ctx)
         tuned = {"gemv_columns_per_workgroup": [vb.vb_tuned_tile(ctx, w) for w in range(4)],
                  "symmetric_kernels": [vb.vb_tuned_tile(ctx, w) for w in (4, 5)],
                  "factor_panel": [vb.vb_tuned_tile(ctx, w) for w in (6, 7, 8)],
@@ -358,7 +359,7 @@ def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
         stream.synchronize()
     del u
     return dict(ctx=ctx, x=x, dt=dt, steps=steps, warmup=warmup, ldl=ldl, gmv=gmv, info=last,
-                dtw=dtw, warm_steps=warm_steps, launch=launch, sym=sym, tuned=tuned)
+                dtw=dtw, warm_steps=warm_steps, launch=launch, sym=sym, tuned=tuned, phases=phases)
 
 
 def main():
@@ -515,6 +516,7 @@ def main():
                 "steps": r["steps"], "warmup": r["warmup"],
                 "warm_solves_per_s": (r["warm_steps"] / r["dtw"]) if r["warm_steps"] else None,
                 "warm_steps": r["warm_steps"], "pcg_launch": r["launch"], "autotuned": r["tuned"],
+                "setup_phases_ms": r["phases"],
                 "iterations": i["iterations"], "refinement_steps": i["refinement_steps"],
                 "rel_residual": i["true_rel_residual"], "lambda_min": i["lambda_min"],
                 "lambda_max": i["lambda_max"],

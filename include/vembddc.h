@@ -122,9 +122,10 @@ typedef struct vb_options {
                              factored again in FP64 (see vb_setup).  0 (default):
                              only wrong-signed or zero pivots.  In the units of
                              the local matrices; must be finite and >= 0. */
-  int tune_factor;        /* the dense factorisations' panel width (32 or 64)
-                             and outer super-panel (the rank of each trailing
-                             update: 8, 16 or 32 panels), chosen per class
+  int tune_factor;        /* the dense factorisations' panel width and outer
+                             super-panel (the rank of each trailing update),
+                             one of (64, 1024), (64, 512), (64, 2048),
+                             (32, 512) columns, chosen per class
                              (local Dirichlet or its fronts, the second level
                              of the two-level scheme, local Neumann) by timing
                              the context's first factorisation of that class
@@ -260,6 +261,16 @@ int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *sub
  * too.  A breakdown of an FP32 local Neumann factorisation is reported, not
  * retried. */
 int vb_setup(vb_ctx *ctx);
+
+/* Device time of the phases of the last vb_setup, in milliseconds (HIP
+ * events on the context's stream, host work in between included): 0 local
+ * Dirichlet factorisations and Schur complements, 1 primal constraints
+ * (with the adaptive face eigenproblems), 2 change of basis, 3 condensed
+ * right-hand side, 4 local Neumann problems, 5 coarse problem, 6 scaling,
+ * 7 iteration structures (with the autotuner), 8 recovery structures.
+ * Writes min(9, max) values to ms (host); returns 9 (VB_ERR_ARG for a
+ * negative max or a NULL ms with max > 0); -1 for a phase not timed. */
+int vb_setup_phases(const vb_ctx *ctx, int max, double *ms);
 
 /* Subdomains (vb_assemble order, ascending) whose local Dirichlet
  * factorisation the last vb_setup redid in FP64 after an FP32 breakdown.

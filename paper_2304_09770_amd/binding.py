@@ -106,6 +106,7 @@ def load():
         "vb_fp64_retries": (C.c_int, [P, C.c_int, C.POINTER(C.c_int32)]),
         "vb_vem_element_matrices": (C.c_int, [P, C.c_int, C.c_int64, P, P, C.c_int, P, P, P]),
         "vb_vem_dofs": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
+        "vb_setup_phases": (C.c_int, [P, C.c_int, C.POINTER(C.c_double)]),
         "vb_batched_ldl": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_batched_ldl_noalloc": (C.c_int, [P, C.c_int, P, P, P, P, P, P, C.c_int, C.c_int]),
         "vb_kernel_stats": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(vb_kernel_stat)]),
@@ -149,7 +150,7 @@ def exported_symbols():
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
             "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
             "vb_batched_ldl_noalloc", "vb_pcg_launch_used", "vb_fp64_retries",
-            "vb_vem_element_matrices", "vb_vem_dofs"]
+            "vb_vem_element_matrices", "vb_vem_dofs", "vb_setup_phases"]
 
 
 class VBError(RuntimeError):
@@ -331,6 +332,19 @@ def vb_kernel_stats(ctx, which, reset=False):
 
 def vb_pcg_launch_used(ctx):
     return int(load().vb_pcg_launch_used(ctx))
+
+
+SETUP_PHASES = ("local Dirichlet", "primal constraints", "change of basis", "right-hand side",
+                "local Neumann", "coarse", "scaling", "iteration structures", "recovery structures")
+
+
+def vb_setup_phases(ctx):
+    """{phase name: ms} of the last vb_setup."""
+    buf = (C.c_double * len(SETUP_PHASES))()
+    n = load().vb_setup_phases(ctx, len(SETUP_PHASES), buf)
+    if n < 0:
+        raise VBError(n, "vb_setup_phases")
+    return {SETUP_PHASES[i]: float(buf[i]) for i in range(min(n, len(SETUP_PHASES)))}
 
 
 def vb_vem_dofs(k):

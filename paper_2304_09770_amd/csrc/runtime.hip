@@ -266,6 +266,11 @@ struct vb_ctx {
 
   double setup_ms = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
+  // setup phases: events at the start of phases 2..9 (phase 1 starts at
+  // ev0, the last ends at ev1) and the last setup's phase times
+  static constexpr int kPhases = 9;
+  hipEvent_t ph_ev[kPhases] = {};
+  double phase_ms[kPhases] = {};
 
   int fail(int code, const std::string &m) {
     err = m;
@@ -552,6 +557,8 @@ void vb_destroy(vb_ctx *ctx) {
   ctx->t_gemv.destroy();
   free_list(ctx->allocs);
   if (ctx->ev0) (void)hipEventDestroy(ctx->ev0);
+  for (hipEvent_t e : ctx->ph_ev)
+    if (e) (void)hipEventDestroy(e);
   if (ctx->ev1) (void)hipEventDestroy(ctx->ev1);
   delete ctx;
 }
@@ -1259,7 +1266,9 @@ static int tuned_ldl(vb_ctx *ctx, int cls, std::vector<LdlJob<T>> &jobs, int max
       ctx->fac_nb[cls] = ctx->opt.panel;
       ctx->fac_sb[cls] = 16 * ctx->opt.panel;
     } else {
-      static const int cand[][2] = {{64, 1024}, {64, 512}, {64, 2048}, {32, 512}, {32, 1024}, {32, 256}};
+      // (32-wide panels with 1024- or 256-column super-panels never won at
+      // the 64- and 216-subdomain workloads and are not tried)
+      static const int cand[][2] = {{64, 1024}, {64, 512}, {64, 2048}, {32, 512}};
       const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
       hipEvent_t e0, e1;
       CHK(hipEventCreate(&e0));
@@ -2623,6 +2632,13 @@ static int setup_impl(vb_ctx *ctx) {
   ctx->d_feat = ctx->d_lab = nullptr;  // freed with the previous setup
   ctx->n_coord = 0;
   CHK(hipEventRecord(ctx->ev0, st));
+  auto mark = [&](int ph) -> hipError_t {  // start of setup phase ph (1-based, >= 2)
+    if (!ctx->ph_ev[ph - 1]) {
+      hipError_t e = hipEventCreate(&ctx->ph_ev[ph - 1]);
+      if (e != hipSuccess) return e;
+    }
+    return hipEventRecord(ctx->ph_ev[ph - 1], st);
+  };
   // ---- 1.-2. per wave of subdomains: local dense bordered matrices, pressure
   //      split, Dirichlet factorisation + Schur complement (eqs. uipi,
   //      firstSchur); with several waves the condensed blocks are copied out
@@ -2646,6 +2662,7 @@ static int setup_impl(vb_ctx *ctx) {
                            hipMemcpyDeviceToDevice, st));
     }
   }
+  CHK(mark(2));
   // ---- 3. primal constraints: QR with column pivoting per entity
   const int nE = (int)ctx->ents.size();
   {
@@ -2700,6 +2717,7 @@ static int setup_impl(vb_ctx *ctx) {
     S.npi = (int)S.pl.size();
     S.ndl = (int)S.dl.size();
   }
+  CHK(mark(3));
   // ---- 4. change of basis on the bordered interface block: X <- T^T X T
   {
     std::vector<void *> m(nS);
@@ -2721,6 +2739,7 @@ static int setup_impl(vb_ctx *ctx) {
     CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
     CHK(transform_b0(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ent, st));
   }
+  CHK(mark(4));
   // ---- 5. transformed right-hand side g~ (owner sums over the rhs columns)
   const int64_t nTot = nG + nS;
   UCHK(ctx->dalloc(&ctx->g, nTot));
@@ -2790,6 +2809,7 @@ static int setup_impl(vb_ctx *ctx) {
     rc = run_diag(ctx, dj, 1);
     if (rc) return rc;
   }
+  CHK(mark(5));
   // ---- 6. local constrained Neumann problems: eliminate the duals of
   //         [[S_DD, S_DP, I], [S_PD, S_PP, 0], [I, 0, 0]] -> [[S_Pi, .], [Phi, -S_DD^-1]]
   //         The augmented matrices are formed and factored in waves of
@@ -2930,6 +2950,7 @@ static int setup_impl(vb_ctx *ctx) {
     for (auto &S : ctx->subs) S.Nmat = nullptr;
     if (rc) return rc;
   }
+  CHK(mark(6));
   // ---- 7. coarse problem: per problem, the inverse of the bordered coarse
   // matrix from the partial LDL^T of [[K_c, I], [I, 0]]
   {
@@ -3042,6 +3063,7 @@ static int setup_impl(vb_ctx *ctx) {
     if (rc) return rc;
     ctx->gc_off = goff;
   }
+  CHK(mark(7));
   // ---- 8. scaling: deluxe D_E^(s) = (sum_l Sbar^(l))^-1 Sbar^(s) on the duals
   {
     std::vector<LdlJob<double>> lj;
@@ -3155,6 +3177,7 @@ static int setup_impl(vb_ctx *ctx) {
       CHK(gemm_nt_batched<double>(dmj, (int)mj.size(), max_m, max_m, st));
     }
   }
+  CHK(mark(8));
   // ---- 9. iteration structures
   {
     // vectors
@@ -3340,6 +3363,7 @@ static int setup_impl(vb_ctx *ctx) {
     int rc = autotune_gemvs(ctx);
     if (rc) return rc;
   }
+  CHK(mark(9));
   // ---- 10. recovery structures (second level first, then the fronts)
   {
     const int nF = (int)ctx->fronts.size();
@@ -3481,6 +3505,12 @@ static int setup_impl(vb_ctx *ctx) {
   float ms = 0.f;
   CHK(hipEventElapsedTime(&ms, ctx->ev0, ctx->ev1));
   ctx->setup_ms = ms;
+  for (int ph = 1; ph <= vb_ctx::kPhases; ++ph) {
+    hipEvent_t a = ph == 1 ? ctx->ev0 : ctx->ph_ev[ph - 1];
+    hipEvent_t b = ph == vb_ctx::kPhases ? ctx->ev1 : ctx->ph_ev[ph];
+    float t = 0.f;
+    ctx->phase_ms[ph - 1] = (a && b && hipEventElapsedTime(&t, a, b) == hipSuccess) ? t : -1.0;
+  }
   // setup-only workspace (Neumann/deluxe augmented matrices, job arrays) is
   // released by the caller of setup_impl
   for (auto &H : ctx->ents) {
@@ -4426,6 +4456,12 @@ int vb_adaptive_info(vb_ctx *ctx, int max_faces, vb_face_info *faces, int max_ei
   if (eigs)
     for (int i = 0; i < std::min((int)ctx->face_eigs.size(), max_eigs); ++i) eigs[i] = ctx->face_eigs[i];
   return nf;
+}
+
+int vb_setup_phases(const vb_ctx *ctx, int max, double *ms) {
+  if (!ctx || max < 0 || (max > 0 && !ms)) return VB_ERR_ARG;
+  for (int i = 0; i < std::min(max, vb_ctx::kPhases); ++i) ms[i] = ctx->phase_ms[i];
+  return vb_ctx::kPhases;
 }
 
 int vb_fp64_retries(const vb_ctx *ctx, int max, int32_t *subs) {

@@ -22,7 +22,7 @@ from oracle.pcg import pcg
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-CANDIDATES = {(64, 1024), (64, 512), (64, 2048), (32, 512), (32, 1024), (32, 256)}
+CANDIDATES = {(64, 1024), (64, 512), (64, 2048), (32, 512)}
 
 
 @pytest.fixture(scope="module")
