@@ -737,7 +737,7 @@ def run_c5(args):
                 stream=stream.cuda_stream, profile=0, tune_factor=2)
     seeds = list(range(32))
     P = max(1, args.c5_wave)
-    waves, per, lat, faces_pred, faces_fb = [], [], [], 0, 0
+    waves, per, lat, faces_pred, faces_fb, mem_used = [], [], [], 0, 0, None
     for w0 in range(0, len(seeds), P):
         wls = list(scaled_family("c5", seeds[w0:w0 + P], base=base))
         with torch.cuda.stream(stream):
@@ -758,6 +758,11 @@ def run_c5(args):
                 stream.synchronize()
                 dt = time.perf_counter() - t1
             waves.append(dt)
+            if w0 == 0:
+                free, total = torch.cuda.mem_get_info()
+                log("c5: device memory in use with a wave's context: %.1f of %.1f GB"
+                    % ((total - free) / 1e9, total / 1e9))
+                mem_used = (total - free) / 1e9
             for q in range(len(wls)):
                 pi = vb.vb_problem_solve_info(ctx, q)
                 per.append(pi)
@@ -789,7 +794,8 @@ def run_c5(args):
         "dtype": "f32+f64",
         "data": "synthetic",
         "config": {"workload": "c5: " + WORKLOADS["c5"], "problems": len(seeds),
-                   "problems_per_context": P, "precision": PRECISION_NAMES["mixed"]},
+                   "problems_per_context": P, "precision": PRECISION_NAMES["mixed"],
+                   "device_memory_gb_per_wave": mem_used},
         "waves_s": waves,
         "latency_ms": {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
                        "max": float(lat.max()), "note": "from the start of the wave's solve"},

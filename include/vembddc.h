@@ -494,7 +494,7 @@ int vb_batched_ldl(vb_ctx *ctx, int batch, double *const *A, const int32_t *n,
  * the host: a matrix with n < 0, n > max_n, e < 0, e > n, e > max_e or
  * ld < n is left untouched with info = -1 while the others are factored.
  * Returns VB_ERR_ARG when batch * ceil(max_e / 64) * 64 * 64 * 8 bytes of
- * inverse diagonal blocks, plus 256 bytes and 56 bytes per matrix, exceed
+ * inverse diagonal blocks, plus 256 bytes and 64 bytes per matrix, exceed
  * VB_NOALLOC_SCRATCH_BYTES.  Every call on a GPU uses that GPU's one array:
  * calls that overlap on one GPU (other threads, other contexts' streams)
  * race and must be serialised by the caller.  Stream-ordered on the

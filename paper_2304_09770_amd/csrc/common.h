@@ -46,6 +46,11 @@ template <typename T> struct LdlJob {
   int *info;   // 0 or 1 + column of the first pivot at or below pmin (after its sign)
   double pmin; // a signed pivot (d_j times the diagonal entry, before its square root)
                // must exceed this value; 0: only wrong-signed or zero pivots fail
+  int zrow;    // 0, or the first row of an identity block I (rows zrow + t, columns t < e)
+               // below the eliminated columns: row zrow + t of L is zero left of column t,
+               // so every update from columns below c leaves rows >= zrow + c untouched
+               // and is skipped there
+  int zpad;
 };
 
 // Batched C = alpha * A * B^T + beta * C, all column-major.

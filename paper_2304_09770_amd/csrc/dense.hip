@@ -22,6 +22,13 @@ namespace vb {
 
 constexpr int TILE = 64;
 
+// Rows of J that an update from the columns below `end` can change: all of
+// them, or, for an identity-bordered matrix, those above zrow + end (the
+// identity rows further down are still zero in those columns).
+template <typename T> __host__ __device__ __forceinline__ int row_limit(const LdlJob<T> &J, int end) {
+  return J.zrow > 0 ? min(J.n, J.zrow + end) : J.n;
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(256) void k_ldl_diag(const LdlJob<T> *jobs, int j0) {
   const LdlJob<T> J = jobs[blockIdx.x];
@@ -100,8 +107,9 @@ __global__ __launch_bounds__(256) void k_ldl_panel(const LdlJob<T> *jobs, int j0
   const LdlJob<T> J = jobs[blockIdx.y];
   if (j0 >= J.e) return;
   const int b = min(NB, J.e - j0);
+  const int nl = row_limit(J, j0 + b);
   const int r0 = j0 + b + blockIdx.x * PROWS;
-  if (r0 >= J.n) return;
+  if (r0 >= nl) return;
   __shared__ T Li[NB][NB];
   __shared__ T At[NB][PROWS];
   const int tid = threadIdx.x;
@@ -110,13 +118,13 @@ __global__ __launch_bounds__(256) void k_ldl_panel(const LdlJob<T> *jobs, int j0
   for (int idx = tid; idx < PROWS * NB; idx += blockDim.x) {
     int r = idx % PROWS, t = idx / PROWS;
     T v = 0;
-    if (r0 + r < J.n && t < b) v = J.A[(int64_t)(r0 + r) + (int64_t)(j0 + t) * J.ld];
+    if (r0 + r < nl && t < b) v = J.A[(int64_t)(r0 + r) + (int64_t)(j0 + t) * J.ld];
     At[t][r] = v;
   }
   __syncthreads();
   const int r = tid % PROWS;
   const int cg = tid / PROWS;  // 0..7
-  if (r0 + r >= J.n) return;
+  if (r0 + r >= nl) return;
   for (int c = cg; c < b; c += 8) {
     T s = 0;
     for (int t = 0; t <= c; ++t) s += At[t][r] * Li[c][t];
@@ -136,8 +144,9 @@ __global__ __launch_bounds__(256) void k_ldl_panel_mfma(const LdlJob<T> *jobs, i
   const LdlJob<T> J = jobs[blockIdx.y];
   if (j0 >= J.e) return;
   const int b = min(NB, J.e - j0);
+  const int nl = row_limit(J, j0 + b);
   const int r0 = j0 + b + blockIdx.x * PR;
-  if (r0 >= J.n) return;
+  if (r0 >= nl) return;
   __shared__ T Pc[NB][NB + 1];  // Pc[t][c] = inv(L_jj)[c][t]
   __shared__ T Pr[NB][PR + 1];  // Pr[t][r] = A[r0 + r][j0 + t]
   const int tid = threadIdx.x;
@@ -146,7 +155,7 @@ __global__ __launch_bounds__(256) void k_ldl_panel_mfma(const LdlJob<T> *jobs, i
   for (int idx = tid; idx < PR * NB; idx += blockDim.x) {
     const int r = idx % PR, t = idx / PR;
     T v = 0;
-    if (r0 + r < J.n && t < b) v = J.A[(int64_t)(r0 + r) + (int64_t)(j0 + t) * J.ld];
+    if (r0 + r < nl && t < b) v = J.A[(int64_t)(r0 + r) + (int64_t)(j0 + t) * J.ld];
     Pr[t][r] = v;
   }
   __syncthreads();
@@ -167,7 +176,7 @@ __global__ __launch_bounds__(256) void k_ldl_panel_mfma(const LdlJob<T> *jobs, i
   for (int br = 0; br < 2; ++br)
     for (int bc = 0; bc < 2; ++bc) {
       const int row = r0 + 32 * wr + 16 * br + lr;
-      if (row >= J.n) continue;
+      if (row >= nl) continue;
       for (int q = 0; q < 4; ++q) {
         const int c = 32 * wc + 16 * bc + M::row(lk, q);
         if (c < b) {
@@ -190,8 +199,9 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
   const int b = min(NB, J.e - j0);
   const int m0 = j0 + b;
   const int ce = min(col_end, J.e);
-  if (m0 >= J.n || m0 >= ce) return;
-  const int nt = (J.n - m0 + TILE - 1) / TILE;
+  const int nl = row_limit(J, j0 + b);
+  if (m0 >= nl || m0 >= ce) return;
+  const int nt = (nl - m0 + TILE - 1) / TILE;
   const int ti = blockIdx.x / ntk_max, tk = blockIdx.x % ntk_max;
   if (ti >= nt || tk > ti) return;
   const int i0 = m0 + ti * TILE, k0 = m0 + tk * TILE;
@@ -208,7 +218,7 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
   const int lr = l & 15, lk = l >> 4;
   const int r = tid & (TILE - 1), c4 = tid >> 6;  // staging: row r, columns c4 + 4q
   const int ri = min(i0 + r, J.n - 1), rk = min(k0 + r, J.n - 1);
-  const bool oki = (i0 + r < J.n), okk = (k0 + r < ce);
+  const bool oki = (i0 + r < nl), okk = (k0 + r < ce);
   for (int cc = 0; cc < NB; cc += KC) {
     T vi[KC / 4], vk[KC / 4];
 #pragma unroll
@@ -242,7 +252,7 @@ __global__ __launch_bounds__(256) void k_ldl_update(const LdlJob<T> *jobs, int j
   for (int bi = 0; bi < 2; ++bi)
     for (int bk = 0; bk < 2; ++bk) {
       const int row = i0 + 32 * wi + 16 * bi + lr;
-      if (row >= J.n) continue;
+      if (row >= nl) continue;
       for (int q = 0; q < 4; ++q) {
         const int col = k0 + 32 * wk + 16 * bk + M::row(lk, q);
         if (col < ce) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
@@ -274,8 +284,9 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
   const int kb = J0, ke = min(J0 + SB, J.e);
   if (kb >= ke) return;
   const int m0 = ke;
-  if (m0 >= J.n) return;
-  const int nt = (J.n - m0 + WT - 1) / WT;
+  const int nl = row_limit(J, ke);
+  if (m0 >= nl) return;
+  const int nt = (nl - m0 + WT - 1) / WT;
   const int t = blockIdx.x;
   int ti, tk, ce;
   if (RECT) {
@@ -291,7 +302,7 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
     if (tk >= ntk) return;
     ti = tk + rem;
   } else {
-    ce = J.n;
+    ce = nl;
     ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
     while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
     while (ti * (ti + 1) / 2 > t) --ti;
@@ -309,7 +320,7 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
   // staging map: row r (128), columns c = c0 + 2q (q < KW/2)
   const int r = tid & (WT - 1), c0 = tid >> 7;
   const int ri = min(i0 + r, J.n - 1), rk = min(k0 + r, J.n - 1);
-  const bool oki = (i0 + r < J.n), okk = (k0 + r < ce);
+  const bool oki = (i0 + r < nl), okk = (k0 + r < ce);
   constexpr int NQ = KW / 2;
   T bi_[NQ], bk_[NQ];
   // raw loads only: the masks and pivot signs are applied when the values are
@@ -361,7 +372,7 @@ __device__ __forceinline__ void ldl_update_wide_body(const LdlJob<T> *jobs, int 
 #pragma unroll
     for (int bk = 0; bk < 4; ++bk) {
       const int row = i0 + 64 * wi + 16 * bi + lr;
-      if (row >= J.n) continue;
+      if (row >= nl) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int col = k0 + 64 * wk + 16 * bk + M::row(lk, q);
@@ -404,9 +415,10 @@ __device__ __forceinline__ void ldl_update_dma_body(const LdlJob<T> *jobs, int J
   const int kb = J0, ke = min(J0 + SB, J.e);
   if (kb >= ke) return;
   const int m0 = ke;
-  if (m0 >= J.n) return;
+  const int nl = row_limit(J, ke);
+  if (m0 >= nl) return;
   const int m0a = m0 & ~(VW - 1);
-  const int nt = (J.n - m0a + WT - 1) / WT;
+  const int nt = (nl - m0a + WT - 1) / WT;
   const int t = blockIdx.x;
   int ti = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
   while ((ti + 1) * (ti + 2) / 2 <= t) ++ti;
@@ -471,11 +483,11 @@ __device__ __forceinline__ void ldl_update_dma_body(const LdlJob<T> *jobs, int J
 #pragma unroll
     for (int bk = 0; bk < 4; ++bk) {
       const int row = i0 + 64 * wi + 16 * bi + lr;
-      if (row < m0 || row >= J.n) continue;
+      if (row < m0 || row >= nl) continue;
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int col = k0 + 64 * wk + 16 * bk + M::row(lk, q);
-        if (col >= m0 && col < J.n) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
+        if (col >= m0 && col < nl) J.A[(int64_t)row + (int64_t)col * J.ld] -= acc[bi][bk][q];
       }
     }
 }
@@ -609,8 +621,17 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer, const std::vector<int> *hn,
-                       const std::vector<int> *he, bool dirichlet, bool aligned16, int sb1) {
+                       const std::vector<int> *he, bool dirichlet, bool aligned16, int sb1,
+                       const std::vector<int> *hz) {
   if (batch == 0 || max_e == 0) return hipSuccess;
+  // the largest row bound over the jobs for an update from the columns below end
+  auto rows_to = [&](int end) {
+    if (!hz || !hn) return max_n;
+    int r = 0;
+    for (size_t q = 0; q < hn->size(); ++q)
+      r = std::max(r, (*hz)[q] > 0 ? std::min((*hn)[q], (*hz)[q] + end) : (*hn)[q]);
+    return std::min(r, max_n);
+  };
   if (nb != 32 && nb != 64) return hipErrorInvalidValue;
   if (sb1 == 0) sb1 = 16 * nb;
   if (sb1 <= 0 || sb1 % (4 * nb)) return hipErrorInvalidValue;
@@ -641,13 +662,15 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     for (int J1 = J0; J1 < j1end; J1 += SB2) {
       const int j2end = std::min(J1 + SB2, max_e);
       for (int j0 = J1; j0 < j2end; j0 += nb) {
-        hipError_t r = (nb == 64) ? ldl_panel_step<T, 64>(d_jobs, batch, max_n, j0, J1 + SB2, s)
-                                  : ldl_panel_step<T, 32>(d_jobs, batch, max_n, j0, J1 + SB2, s);
+        const int mr = rows_to(j0 + nb);
+        hipError_t r = (nb == 64) ? ldl_panel_step<T, 64>(d_jobs, batch, mr, j0, J1 + SB2, s)
+                                  : ldl_panel_step<T, 32>(d_jobs, batch, mr, j0, J1 + SB2, s);
         if (r != hipSuccess) return r;
       }
       const int ncols = J0 + SB1 - (J1 + SB2);
-      if (ncols > 0 && max_n > J1) {
-        const int nt_max = (max_n - J1 + WT - 1) / WT;
+      const int mr = rows_to(J1 + SB2);
+      if (ncols > 0 && mr > J1) {
+        const int nt_max = (mr - J1 + WT - 1) / WT;
         const int ntk = std::min(nt_max, (ncols + WT - 1) / WT);
         const int ntiles = ntk * nt_max - ntk * (ntk - 1) / 2;
         hipLaunchKernelGGL(WideKernel<T>::rect, dim3(ntiles, batch), dim3(256), lds, s, d_jobs, J1,
@@ -662,13 +685,16 @@ hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e,
     if (timer && hn && he)
       for (size_t q = 0; q < hn->size(); ++q) {
         if (J0 >= (*he)[q]) continue;
-        const double K = std::min(J0 + SB1, (*he)[q]) - J0;
-        const double m = (*hn)[q] - std::min(J0 + SB1, (*he)[q]);
+        const int ke = std::min(J0 + SB1, (*he)[q]);
+        const int nl = (hz && (*hz)[q] > 0) ? std::min((*hn)[q], (*hz)[q] + ke) : (*hn)[q];
+        const double K = ke - J0;
+        const double m = nl - ke;
         if (m > 0) flops += K * m * (m + 1.0);
       }
     // a job whose elimination ends inside this super-panel has n - e_job
-    // trailing rows: size the grid by the upper bound max_n - J0
-    const int rows = max_n - J0;
+    // trailing rows: size the grid by the upper bound max_n - J0 (or the
+    // identity-bordered jobs' row bound)
+    const int rows = rows_to(J0 + SB1) - J0;
     if (rows > 0) {
       // the aligned kernels start their tile grid up to VW - 1 rows lower
       const int wt = (rows + (aligned16 ? Dma<T>::VW : 0) + WT - 1) / WT;
@@ -701,10 +727,10 @@ hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int m
 
 template hipError_t ldl_batched<double>(const LdlJob<double> *, int, int, int, int, hipStream_t,
                                         KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                        bool, bool, int);
+                                        bool, bool, int, const std::vector<int> *);
 template hipError_t ldl_batched<float>(const LdlJob<float> *, int, int, int, int, hipStream_t,
                                        KTimer *, const std::vector<int> *, const std::vector<int> *,
-                                       bool, bool, int);
+                                       bool, bool, int, const std::vector<int> *);
 template hipError_t gemm_nt_batched<double>(const GemmJob<double> *, int, int, int, hipStream_t);
 template hipError_t gemm_nt_batched<float>(const GemmJob<float> *, int, int, int, hipStream_t);
 

@@ -50,12 +50,15 @@ struct KTimer {
 
 // ---------------------------------------------------------------- dense
 // nb: panel width (32 or 64); sb1: columns of an outer super-panel, whose
-// trailing update is one rank-sb1 product (a multiple of 4 nb; 0 = 16 nb)
+// trailing update is one rank-sb1 product (a multiple of 4 nb; 0 = 16 nb);
+// hz: the jobs' zrow (with hn, it sizes the grids of identity-bordered jobs
+// to the rows each step can change; without it, grids span max_n)
 template <typename T>
 hipError_t ldl_batched(const LdlJob<T> *d_jobs, int batch, int max_n, int max_e, int nb,
                        hipStream_t s, KTimer *timer = nullptr,
                        const std::vector<int> *hn = nullptr, const std::vector<int> *he = nullptr,
-                       bool dirichlet = false, bool aligned16 = false, int sb1 = 0);
+                       bool dirichlet = false, bool aligned16 = false, int sb1 = 0,
+                       const std::vector<int> *hz = nullptr);
 template <typename T>
 hipError_t gemm_nt_batched(const GemmJob<T> *d_jobs, int batch, int max_m, int max_n,
                            hipStream_t s);

@@ -81,6 +81,8 @@ __global__ __launch_bounds__(256) void k_noalloc_jobs(double *const *A, const in
     J.invL = inv + per * b;
     J.info = info + b;
     J.pmin = 0.0;
+    J.zrow = 0;
+    J.zpad = 0;
     jobs[b] = J;
     info[b] = ok ? 0 : -1;
     if (ok && !(lb >= 2 && (lb % 2) == 0 && (reinterpret_cast<uintptr_t>(Ab) % 16) == 0)) mine = 1;

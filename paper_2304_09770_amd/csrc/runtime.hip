@@ -1228,17 +1228,18 @@ static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max
   if (jobs.empty()) return VB_OK;
   LdlJob<T> *dj = nullptr;
   UCHK(ctx->upload(&dj, jobs, true));
-  std::vector<int> hn(jobs.size()), he(jobs.size());
+  std::vector<int> hn(jobs.size()), he(jobs.size()), hz(jobs.size());
   bool aligned16 = true;  // 16-byte aligned columns (leading dimension a multiple of 16 bytes)
   for (size_t b = 0; b < jobs.size(); ++b) {
     hn[b] = jobs[b].n;
     he[b] = jobs[b].e;
+    hz[b] = jobs[b].zrow;
     aligned16 = aligned16 && (jobs[b].ld * sizeof(T)) % 16 == 0 &&
                 reinterpret_cast<uintptr_t>(jobs[b].A) % 16 == 0;
   }
   CHK(ldl_batched<T>(dj, (int)jobs.size(), max_n, max_e, nb ? nb : ctx->opt.panel, ctx->stream,
                      (timed && ctx->opt.profile) ? &ctx->t_ldl : nullptr, &hn, &he, timed,
-                     aligned16, sb1));
+                     aligned16, sb1, &hz));
   return VB_OK;
 }
 
@@ -1985,7 +1986,7 @@ static int adaptive_stage(vb_ctx *ctx) {
       gm.push_back({QB + n + (int64_t)n * f.ld2, f.ld2, M, f.ld2, d_dualidx, d_dualidx, n, n, 1.0,
                     0, 0, 0});
       dm.push_back({M, f.ld2, n, 0, n, 1.0, 0});
-      lm.push_back({M, f.ld2, 2 * n, n, n, 0, invs + io, iinfo + 4 * nf + q});
+      lm.push_back({M, f.ld2, 2 * n, n, n, 0, invs + io, iinfo + 4 * nf + q, 0.0, n});
       io += (int64_t)((n + NB - 1) / NB) * NB * NB;
       sm.push_back(QA + n + (int64_t)n * f.ld2);
       sld.push_back(f.ld2);
@@ -2885,12 +2886,13 @@ static int setup_impl(vb_ctx *ctx) {
                       nf ? 1 : 0});
         mxg = std::max(mxg, mm);
         if (S.ndl) dj.push_back({S.Nmat, S.Nld, S.ndl + S.npi, 0, S.ndl, 1.0, nf ? 1 : 0});
+        // identity block at rows ndl + npi (eliminated columns 0 .. ndl - 1)
         if (nf)
           lj32.push_back({(float *)S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, (float *)at(invN, ioff),
-                          ctx->info + s});
+                          ctx->info + s, 0.0, S.ndl + S.npi});
         else
           lj.push_back({(double *)S.Nmat, S.Nld, S.Nn, S.ndl, S.ndl, 0, (double *)at(invN, ioff),
-                        ctx->info + s});
+                        ctx->info + s, 0.0, S.ndl + S.npi});
         ioff += (int64_t)((S.ndl + NB - 1) / NB) * NB * NB;
         max_m = std::max(max_m, S.Nn);
         max_e = std::max(max_e, S.ndl);
@@ -3010,7 +3012,7 @@ static int setup_impl(vb_ctx *ctx) {
       UCHK(ctx->upload(&dw, w, true));
       CHK(coarse_assemble(dcs, P.ns, K, ldk[pp], P.nprim, dw, st));
       dj.push_back({K, ldk[pp], ncs, 0, ncs, 1.0});
-      lj.push_back({K, ldk[pp], 2 * ncs, ncs, P.nprim, 0, invC + io, ctx->info + nS + pp});
+      lj.push_back({K, ldk[pp], 2 * ncs, ncs, P.nprim, 0, invC + io, ctx->info + nS + pp, 0.0, ncs});
       io += (int64_t)((ncs + NB - 1) / NB) * NB * NB;
       m.push_back(K + ncs + ncs * ldk[pp]);
       ld.push_back(ldk[pp]);
@@ -3139,7 +3141,8 @@ static int setup_impl(vb_ctx *ctx) {
           mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, ldm, m, m, m, 0, -1.0, 0.0});
       }
       dj.push_back({H.Daug, H.Dld, m, 0, m, 1.0});
-      lj.push_back({H.Daug, H.Dld, 2 * m, m, m, 0, invD + ioff, ctx->info + 2 * nS + 2 + (cnt % 16)});
+      lj.push_back({H.Daug, H.Dld, 2 * m, m, m, 0, invD + ioff, ctx->info + 2 * nS + 2 + (cnt % 16), 0.0,
+                    m});
       ioff += (int64_t)((m + NB - 1) / NB) * NB * NB;
       ++cnt;
     }
