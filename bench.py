@@ -357,9 +357,11 @@ def time_path(vb, wl, prec, steps, warmup, warm_steps, stream, dev, nloc):
         x.zero_()
         solve()  # leave x as the solution of a production-mode solve
         stream.synchronize()
+        history = vb.vb_refinement_history(ctx) if prec != "fp64" else None
     del u
     return dict(ctx=ctx, x=x, dt=dt, steps=steps, warmup=warmup, ldl=ldl, gmv=gmv, info=last,
-                dtw=dtw, warm_steps=warm_steps, launch=launch, sym=sym, tuned=tuned, phases=phases)
+                dtw=dtw, warm_steps=warm_steps, launch=launch, sym=sym, tuned=tuned, phases=phases,
+                history=history)
 
 
 def main():
@@ -521,7 +523,10 @@ def main():
                 "rel_residual": i["true_rel_residual"], "lambda_min": i["lambda_min"],
                 "lambda_max": i["lambda_max"],
                 "k2": (i["lambda_max"] / i["lambda_min"]) if i["lambda_min"] > 0 else None,
-                "n_coarse": i["n_coarse"], "setup_ms": i["setup_ms"], "solve_ms": i["solve_ms"]}
+                "n_coarse": i["n_coarse"], "setup_ms": i["setup_ms"], "solve_ms": i["solve_ms"],
+                "refinement_history": ({"rel_residual_before_step": r["history"][0],
+                                        "inner_iterations": r["history"][1]}
+                                       if r["history"] else None)}
 
     out = {
         "metric": "PCG+BDDC solves/s at 1e-8 rel. residual, mixed/batched vs FP64 GPU",

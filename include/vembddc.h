@@ -134,6 +134,14 @@ typedef struct vb_options {
                              matrices), 1 = always, 2 = never (panel and
                              16-panel super-panels).  Results differ only by
                              rounding.  See vb_tuned_tile. */
+  double inner_tol;       /* VB_PREC_MIXED: the relative residual reduction each
+                             inner PCG solve of the refinement aims at (on the
+                             FP32 operators; the last step aims only at what the
+                             outer tolerance still needs).  0 = default 1e-3
+                             (each step then reduces the FP64 residual by about
+                             that much; looser values take more steps, tighter
+                             ones more iterations per step).  Otherwise in
+                             (0, 1).  See vb_refinement_history. */
 } vb_options;
 
 enum { VB_PCG_AUTO = 0, VB_PCG_GRAPH = 1, VB_PCG_PERSISTENT = 2 };
@@ -278,6 +286,16 @@ int vb_setup_phases(const vb_ctx *ctx, int max, double *ms);
  * first min(number, max) of them to subs (host memory; may be NULL when
  * max = 0); a negative max is VB_ERR_ARG. */
 int vb_fp64_retries(const vb_ctx *ctx, int max, int32_t *subs);
+
+/* The refinement steps of the last VB_PREC_MIXED vb_pcg_solve for one
+ * problem (vb_assemble_batch order): rel[k] is the relative condensed FP64
+ * residual before step k (rel[0] = 1; the value after the last step is
+ * rel[steps]) and inner[k] the inner PCG iterations of step k.  Writes
+ * min(steps + 1, max) values to rel and min(steps, max) to inner (host
+ * memory; either may be NULL when max = 0) and returns steps (0 before a
+ * mixed solve or in VB_PREC_FP64); VB_ERR_ARG for a problem out of range or
+ * a negative max. */
+int vb_refinement_history(const vb_ctx *ctx, int problem, int max, double *rel, int32_t *inner);
 
 /* Length of the global interface vector: the interface ids of all problems
  * (problem order), then one p0 entry per subdomain (subdomain order). */

@@ -29,7 +29,8 @@ class vb_options(C.Structure):
                 ("predictor", C.c_void_p),
                 ("setup_mem_limit", C.c_double), ("local_mem_limit", C.c_double),
                 ("pcg_launch", C.c_int), ("schur_kernel", C.c_int),
-                ("fp32_pivot_min", C.c_double), ("tune_factor", C.c_int)]
+                ("fp32_pivot_min", C.c_double), ("tune_factor", C.c_int),
+                ("inner_tol", C.c_double)]
 
 
 class vb_problem(C.Structure):
@@ -104,6 +105,8 @@ def load():
         "vb_set_profile": (C.c_int, [P, C.c_int]),
         "vb_pcg_launch_used": (C.c_int, [P]),
         "vb_fp64_retries": (C.c_int, [P, C.c_int, C.POINTER(C.c_int32)]),
+        "vb_refinement_history": (C.c_int, [P, C.c_int, C.c_int, C.POINTER(C.c_double),
+                                            C.POINTER(C.c_int32)]),
         "vb_vem_element_matrices": (C.c_int, [P, C.c_int, C.c_int64, P, P, C.c_int, P, P, P]),
         "vb_vem_dofs": (C.c_int, [C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "vb_setup_phases": (C.c_int, [P, C.c_int, C.POINTER(C.c_double)]),
@@ -150,7 +153,7 @@ def exported_symbols():
             "vb_mlp_set_warm_start", "vb_mlp_add_data", "vb_num_problems", "vb_problem_layout",
             "vb_problem_solve_info", "vb_tuned_tile", "vb_local_size", "vb_set_profile",
             "vb_batched_ldl_noalloc", "vb_pcg_launch_used", "vb_fp64_retries",
-            "vb_vem_element_matrices", "vb_vem_dofs", "vb_setup_phases"]
+            "vb_vem_element_matrices", "vb_vem_dofs", "vb_setup_phases", "vb_refinement_history"]
 
 
 class VBError(RuntimeError):
@@ -199,11 +202,11 @@ def _check(ctx, rc):
 def vb_create(precision=VB_PREC_FP64, scaling=VB_SCALING_DELUXE, tol=1e-8, maxit=1000,
               svd_tol=1e-10, panel=0, stream=None, profile=0, adaptive_theta=0.0,
               predictor=None, setup_mem_limit=0.0, local_mem_limit=0.0, pcg_launch=0,
-              schur_kernel=0, fp32_pivot_min=0.0, tune_factor=0):
+              schur_kernel=0, fp32_pivot_min=0.0, tune_factor=0, inner_tol=0.0):
     lib = load()
     opt = vb_options(precision, scaling, tol, maxit, svd_tol, panel, stream, profile,
                      adaptive_theta, predictor, setup_mem_limit, local_mem_limit, pcg_launch,
-                     schur_kernel, fp32_pivot_min, tune_factor)
+                     schur_kernel, fp32_pivot_min, tune_factor, inner_tol)
     ctx = C.c_void_p()
     rc = lib.vb_create(C.byref(ctx), C.byref(opt))
     if rc != VB_OK:
@@ -381,6 +384,22 @@ def vb_fp64_retries(ctx):
     buf = (C.c_int32 * max(n, 1))()
     n = lib.vb_fp64_retries(ctx, n, buf)
     return [int(buf[i]) for i in range(n)]
+
+
+def vb_refinement_history(ctx, problem=0):
+    """(rel, inner) of the last mixed-precision solve of one problem: the
+    relative condensed residual before each refinement step and after the
+    last, and the inner PCG iterations of each step."""
+    lib = load()
+    n = lib.vb_refinement_history(ctx, problem, 0, None, None)
+    if n < 0:
+        raise VBError(n, "vb_refinement_history")
+    if n == 0:
+        return [], []
+    rel = (C.c_double * (n + 1))()
+    inner = (C.c_int32 * max(n, 1))()
+    n = lib.vb_refinement_history(ctx, problem, n + 1, rel, inner)
+    return [float(rel[i]) for i in range(n + 1)], [int(inner[i]) for i in range(n)]
 
 
 def vb_set_profile(ctx, on):

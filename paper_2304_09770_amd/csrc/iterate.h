@@ -65,10 +65,11 @@ __host__ __device__ inline int symv_tiles(int n) {
 hipError_t symv(const SymvJob *d_jobs, int batch, int max_n, hipStream_t s);
 
 struct ExtPart {
-  const double *D;  // m x m column-major (null: counting weight `scale`)
+  const void *D;    // m x m column-major, double or float if f32 (null: counting weight `scale`)
   int64_t ld;
   int64_t woff;     // offset of this subdomain's entity block in w
   double scale;
+  int f32;
 };
 struct ExtJob {
   int m;

@@ -205,16 +205,70 @@ hipError_t scatter_copy(int n, const double *src, const int64_t *sidx, const int
 // the entity (D_q = null: counting weights 1/card); for a pair of
 // subdomains whose matrices sum to the identity, z = w_2 + D_1 (w_1 - w_2),
 // so only D_1 is read.  A workgroup takes 128 rows: each lane two adjacent
-// rows with one 16-byte load per column (the matrices are stored with an
-// even leading dimension, 16-byte aligned; the row past an odd m is in the
-// column's storage and feeds no output).  The vector the matrix multiplies
-// is staged in LDS in chunks of EXT_CHUNK columns, which the four waves
-// split, four columns in flight per lane; the partial sums are added
-// through LDS in a fixed order.
+// rows with one 16-byte (FP64) or 8-byte (FP32 storage) load per column (the
+// matrices are stored with an even leading dimension, so the pair is
+// aligned; the row past an odd m is in the column's storage and feeds no
+// output).  The vector the matrix multiplies is staged in LDS in chunks of
+// EXT_CHUNK columns, which the four waves split, four (FP64) or eight (FP32)
+// columns in flight per lane; the partial sums are added through LDS in a
+// fixed order.
 constexpr int EXT_CHUNK = 1024;
 typedef double v2d __attribute__((ext_vector_type(2)));
+typedef float v2f __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ v2d load2(const double *p) {
   return *(const __attribute__((address_space(1))) v2d *)p;
+}
+__device__ __forceinline__ v2d load2(const float *p) {
+  const v2f f = *(const __attribute__((address_space(1))) v2f *)p;
+  return v2d{(double)f.x, (double)f.y};
+}
+template <typename T> struct ExtUnroll { static constexpr int value = 4; };
+template <> struct ExtUnroll<float> { static constexpr int value = 8; };
+
+// s += D[m0:m0+2, :] (u - v) (v may be null); called by the whole workgroup
+template <typename T>
+__device__ __forceinline__ void ext_matvec(const T *D, int64_t ld, const double *u, const double *v,
+                                           int m, int m0, bool rows, int wv, double *xs, double &s0,
+                                           double &s1) {
+  constexpr int U = ExtUnroll<T>::value;
+  for (int cb = 0; cb < m; cb += EXT_CHUNK) {
+    const int cm = min(EXT_CHUNK, m - cb);
+    __syncthreads();
+    for (int i = threadIdx.x; i < cm; i += blockDim.x) xs[i] = v ? u[cb + i] - v[cb + i] : u[cb + i];
+    __syncthreads();
+    if (!rows) continue;
+    const int k0 = cm * wv / 4, k1 = cm * (wv + 1) / 4;
+    const T *a = D + m0 + (int64_t)cb * ld;
+    double t[U], q[U];
+#pragma unroll
+    for (int j = 0; j < U; ++j) t[j] = q[j] = 0.0;
+    int l = k0;
+    for (; l + U <= k1; l += U) {
+      v2d d[U];
+#pragma unroll
+      for (int j = 0; j < U; ++j) d[j] = load2(a + (int64_t)(l + j) * ld);
+#pragma unroll
+      for (int j = 0; j < U; ++j) {
+        const double x = xs[l + j];
+        t[j] += d[j].x * x;
+        q[j] += d[j].y * x;
+      }
+    }
+    for (; l < k1; ++l) {
+      const v2d d0 = load2(a + (int64_t)l * ld);
+      t[0] += d0.x * xs[l];
+      q[0] += d0.y * xs[l];
+    }
+#pragma unroll
+    for (int w = U / 2; w >= 1; w /= 2)
+#pragma unroll
+      for (int j = 0; j < w; ++j) {
+        t[j] += t[j + w];
+        q[j] += q[j + w];
+      }
+    s0 += t[0];
+    s1 += q[0];
+  }
 }
 
 // xs: EXT_CHUNK doubles of LDS, part: 4 x 128 doubles of LDS
@@ -228,48 +282,23 @@ __device__ __forceinline__ void extend_block(const ExtJob *jobs, const ExtPart *
   const int m0 = r0 + 2 * lane;
   const bool rows = m0 < J.m;
   double s0 = 0.0, s1 = 0.0;
-  // s += D[m0:m0+2, :] (u - v) (v may be null); called by the whole workgroup
-  auto matvec = [&](const double *D, int64_t ld, const double *u, const double *v) {
-    for (int cb = 0; cb < J.m; cb += EXT_CHUNK) {
-      const int cm = min(EXT_CHUNK, J.m - cb);
-      __syncthreads();
-      for (int i = threadIdx.x; i < cm; i += blockDim.x) xs[i] = v ? u[cb + i] - v[cb + i] : u[cb + i];
-      __syncthreads();
-      if (!rows) continue;
-      const int k0 = cm * wv / 4, k1 = cm * (wv + 1) / 4;
-      const double *a = D + m0 + (int64_t)cb * ld;
-      double t0 = 0.0, t1 = 0.0, t2 = 0.0, t3 = 0.0, q0 = 0.0, q1 = 0.0, q2 = 0.0, q3 = 0.0;
-      int l = k0;
-      for (; l + 4 <= k1; l += 4) {
-        const v2d d0 = load2(a + (int64_t)l * ld);
-        const v2d d1 = load2(a + (int64_t)(l + 1) * ld);
-        const v2d d2 = load2(a + (int64_t)(l + 2) * ld);
-        const v2d d3 = load2(a + (int64_t)(l + 3) * ld);
-        const double x0 = xs[l], x1 = xs[l + 1], x2 = xs[l + 2], x3 = xs[l + 3];
-        t0 += d0.x * x0; q0 += d0.y * x0;
-        t1 += d1.x * x1; q1 += d1.y * x1;
-        t2 += d2.x * x2; q2 += d2.y * x2;
-        t3 += d3.x * x3; q3 += d3.y * x3;
-      }
-      for (; l < k1; ++l) {
-        const v2d d0 = load2(a + (int64_t)l * ld);
-        t0 += d0.x * xs[l]; q0 += d0.y * xs[l];
-      }
-      s0 += (t0 + t1) + (t2 + t3);
-      s1 += (q0 + q1) + (q2 + q3);
-    }
+  auto matvec = [&](const ExtPart &P, const double *u, const double *v) {
+    if (P.f32)
+      ext_matvec((const float *)P.D, P.ld, u, v, J.m, m0, rows, wv, xs, s0, s1);
+    else
+      ext_matvec((const double *)P.D, P.ld, u, v, J.m, m0, rows, wv, xs, s0, s1);
   };
   const double *wlast = nullptr;
   if (J.pair) {
     const ExtPart P = parts[J.part0], Q = parts[J.part0 + 1];
     wlast = w + Q.woff;
-    matvec(P.D, P.ld, w + P.woff, wlast);
+    matvec(P, w + P.woff, wlast);
   } else {
     for (int q = 0; q < J.nparts; ++q) {
       const ExtPart P = parts[J.part0 + q];
       const double *wq = w + P.woff;
       if (P.D) {
-        matvec(P.D, P.ld, wq, nullptr);
+        matvec(P, wq, nullptr);
       } else if (wv == 0 && rows) {
         s0 += wq[m0] * P.scale;
         if (m0 + 1 < J.m) s1 += wq[m0 + 1] * P.scale;

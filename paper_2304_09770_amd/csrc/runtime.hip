@@ -110,6 +110,7 @@ struct EntH {
   double *Daug = nullptr;
   int64_t Dld = 0;
   std::vector<double *> D;  // per sharing subdomain (null: I - D[0] for a pair)
+  std::vector<const void *> Dit;  // the copies the iteration reads (FP32 in mixed precision)
   int64_t Dmld = 0;         // leading dimension of the D matrices (even)
   std::vector<double *> Sbar;
   int64_t *d_dual_gids = nullptr;
@@ -258,11 +259,18 @@ struct vb_ctx {
   int64_t n_ir = 0;                              // length of y_ir / z_ir / zst
   std::vector<int64_t> uoff;
   int last_outer = 0, last_inner = 0;
+  // per problem: the relative condensed residual before each refinement step
+  // (and after the last) and the inner iterations of each step
+  std::vector<std::vector<double>> ref_rel;
+  std::vector<std::vector<int>> ref_inner;
   int recover_steps = 4;  // interior refinement passes of vb_recover_all (mixed)
   // the interface solution of the last mixed solve, whose interior state zst
   // was refined with it: recovery at that x starts from zst
   double *x_last = nullptr;
   bool zst_valid = false;
+  // y_ir, z_ir and r0 still hold the condensed residual at (x_last, zst): the
+  // check that ended the last mixed solve, which recovery can take as it is
+  bool cond_fresh = false;
 
   double setup_ms = 0.0;
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
@@ -522,7 +530,7 @@ int vb_create(vb_ctx **out, const vb_options *opt) {
       !std::isfinite(d.svd_tol) || !(d.adaptive_theta >= 0.0) || !std::isfinite(d.adaptive_theta) ||
       d.pcg_launch < VB_PCG_AUTO || d.pcg_launch > VB_PCG_PERSISTENT || d.schur_kernel < 0 ||
       d.schur_kernel > 2 || !(d.fp32_pivot_min >= 0.0) || !std::isfinite(d.fp32_pivot_min) ||
-      d.tune_factor < 0 || d.tune_factor > 2) {
+      d.tune_factor < 0 || d.tune_factor > 2 || !(d.inner_tol >= 0.0 && d.inner_tol < 1.0)) {
     delete ctx;
     return VB_ERR_ARG;
   }
@@ -2593,11 +2601,13 @@ int vb_setup(vb_ctx *ctx) {
     ctx->setup_keep.clear();
     for (auto &H : ctx->ents) {
       H.D.clear();
+      H.Dit.clear();
       H.d_dual_gids = nullptr;
     }
     ctx->state = 1;
   }
   ctx->zst_valid = false;
+  ctx->cond_fresh = false;
   ctx->n_restrict = ctx->n_ext = 0;
   ctx->max_rm = ctx->max_ext_m = ctx->max_gt_m = ctx->max_gt_n = 0;
   ctx->max_ndl = ctx->max_npi = ctx->max_nt = 0;
@@ -3094,8 +3104,9 @@ static int setup_impl(vb_ctx *ctx) {
       const int m = H.n - H.rank;
       if (m > 0) dtot += (int64_t)(pair_of(H) ? 1 : H.subs.size()) * round_up(m, 2) * m;
     }
+    // (mixed precision: the iteration reads an FP32 copy, made at the end)
     double *dall = nullptr;
-    UCHK(ctx->dalloc(&dall, std::max<int64_t>(dtot, 1)));
+    UCHK(ctx->dalloc(&dall, std::max<int64_t>(dtot, 1), f32));
     int64_t doff = 0;
     int64_t ioff = 0;
     int cnt = 0;
@@ -3178,6 +3189,20 @@ static int setup_impl(vb_ctx *ctx) {
       GemmJob<double> *dmj = nullptr;
       UCHK(ctx->upload(&dmj, mj, true));
       CHK(gemm_nt_batched<double>(dmj, (int)mj.size(), max_m, max_m, st));
+    }
+    // the matrices the iteration reads: in mixed precision an FP32 copy (the
+    // restriction and the extension read the same rounded D, so the
+    // preconditioner stays symmetric; a pair's second matrix is still
+    // I - D^(1) of that copy)
+    float *dall32 = nullptr;
+    if (f32 && dtot > 0) {
+      UCHK(ctx->dalloc(&dall32, dtot));
+      CHK(cast_to_f32(dall, dall32, dtot, st));
+    }
+    for (auto &H : ctx->ents) {
+      H.Dit.assign(H.D.size(), nullptr);
+      for (size_t q = 0; q < H.D.size(); ++q)
+        if (H.D[q]) H.Dit[q] = dall32 ? (const void *)(dall32 + (H.D[q] - dall)) : (const void *)H.D[q];
     }
   }
   CHK(mark(8));
@@ -3271,15 +3296,17 @@ static int setup_impl(vb_ctx *ctx) {
         SubH &S = ctx->subs[s];
         int qq = (int)(std::find(S.ents.begin(), S.ents.end(), e) - S.ents.begin());
         wos.push_back(sgo[s] + S.doff[qq]);
-        ep.push_back({H.D[qd], H.Dmld, wos.back(), 0.0});
+        ep.push_back({H.Dit[qd], H.Dmld, wos.back(), 0.0, f32 ? 1 : 0});
       }
       if (pair) {  // g^(1) = D^(1)T r, g^(2) = r - g^(1): one read of D^(1)
-        GemvJob G{H.D[0], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[0], 1.0, 0};
+        GemvJob G{H.Dit[0], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[0], 1.0, 0,
+                  f32 ? 1 : 0};
         G.y2 = ctx->gD + wos[1];
         jr.push_back(G);
       } else {
         for (size_t qd = 0; qd < H.subs.size(); ++qd)
-          jr.push_back({H.D[qd], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[qd], 1.0, 0});
+          jr.push_back({H.Dit[qd], H.Dmld, m, m, ctx->r, H.d_dual_gids, nullptr, ctx->gD + wos[qd], 1.0, 0,
+                        f32 ? 1 : 0});
       }
       ej.push_back(J);
       ctx->max_rm = std::max(ctx->max_rm, m);
@@ -4079,9 +4106,12 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
   const int nE = (int)ctx->ents.size();
   const int P = (int)ctx->probs.size(), G = ctx->seg_G;
   const int max_outer = 30;
-  const double inner_floor = 1e-4;
+  const double inner_floor = ctx->opt.inner_tol > 0.0 ? ctx->opt.inner_tol : 1e-3;
+  ctx->ref_rel.assign(ctx->probs.size(), {});
+  ctx->ref_inner.assign(ctx->probs.size(), {});
   CHK(hipEventRecord(ctx->ev0, st));
   CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
+  ctx->cond_fresh = false;
   std::vector<double> r_first(P, 0.0), rel(P, 0.0), t0(P, 0.0), tdone(P, 0.0);
   std::vector<int> steps(P, 0), inner(P, 0), done(P, 0);
   std::vector<vb_solve_info> pi(P);
@@ -4109,6 +4139,7 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
       if (!std::isfinite(rn) || (outer == 0 && !std::isfinite(r_first[pp]))) nonfinite = true;
       if (outer == 0) r_first[pp] = rn;
       rel[pp] = r_first[pp] > 0 ? rn / r_first[pp] : 0.0;
+      if (!done[pp]) ctx->ref_rel[pp].push_back(rel[pp]);
       if (!done[pp] && !(rel[pp] > ctx->opt.tol)) {
         done[pp] = 1;
         if (outer == 0) tdone[pp] = t0[pp];  // converged before any step
@@ -4121,7 +4152,10 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
       for (int pp = 0; pp < P; ++pp) done[pp] = 0;
       break;
     }
-    if (all) break;
+    if (all) {
+      ctx->cond_fresh = true;
+      break;
+    }
     if (outer >= max_outer || inner_max >= ctx->opt.maxit) {
       status = VB_ERR_NOT_CONVERGED;
       break;
@@ -4138,6 +4172,7 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
       if (!done[pp]) {
         inner[pp] += it;
         steps[pp] += 1;
+        ctx->ref_inner[pp].push_back(it);
       }
       mx = std::max(mx, it);
       if (outer == 0) {  // Lanczos estimates of the first inner solve
@@ -4263,9 +4298,12 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
   if (ctx->fp32) {
     // FP32 factor: refine the interior equations in FP64 with the interface
     // data fixed at x, from the interior state of the last solve when x is
-    // that solve's result (two passes), else from zero (recover_steps passes)
+    // that solve's result (one pass, on the condensed residual the solve's
+    // final check left), else from zero (recover_steps passes)
     int passes = ctx->recover_steps;
     bool from_solve = false;
+    const bool fresh = ctx->cond_fresh;
+    ctx->cond_fresh = false;
     if (ctx->zst_valid) {
       const int64_t n = ctx->nG + ctx->nS;
       const int P = (int)ctx->probs.size();
@@ -4279,13 +4317,13 @@ int vb_recover_all(vb_ctx *ctx, const double *x_dev, double *out_dev) {
       for (int pp = 0; pp < P; ++pp) from_solve = from_solve && hs[(size_t)pp * SC_STRIDE + SC_TMP] == 0.0;
     }
     if (from_solve) {
-      passes = std::min(passes, 2);
+      passes = std::min(passes, fresh ? 1 : 2);
     } else {
       CHK(hipMemsetAsync(ctx->zst, 0, ctx->n_ir * sizeof(double), st));
       ctx->zst_valid = false;
     }
     for (int k = 0; k < passes; ++k) {
-      int rc = condense_residual(ctx, x_dev);
+      int rc = (k == 0 && from_solve && fresh) ? VB_OK : condense_residual(ctx, x_dev);
       if (rc) return rc;
       rc = interior_correction(ctx, nullptr);
       if (rc) return rc;
@@ -4472,6 +4510,17 @@ int vb_fp64_retries(const vb_ctx *ctx, int max, int32_t *subs) {
   const int n = (int)ctx->fp64_retried.size();
   for (int i = 0; i < std::min(n, max); ++i) subs[i] = ctx->fp64_retried[i];
   return n;
+}
+
+int vb_refinement_history(const vb_ctx *ctx, int problem, int max, double *rel, int32_t *inner) {
+  if (!ctx || max < 0 || (max > 0 && (!rel || !inner))) return VB_ERR_ARG;
+  if (problem < 0 || problem >= (int)std::max<size_t>(ctx->probs.size(), 1)) return VB_ERR_ARG;
+  if (problem >= (int)ctx->ref_inner.size()) return 0;
+  const std::vector<double> &r = ctx->ref_rel[problem];
+  const std::vector<int> &it = ctx->ref_inner[problem];
+  for (int k = 0; k < std::min((int)r.size(), max); ++k) rel[k] = r[k];
+  for (int k = 0; k < std::min((int)it.size(), max); ++k) inner[k] = it[k];
+  return (int)it.size();
 }
 
 int vb_pcg_launch_used(const vb_ctx *ctx) { return ctx ? ctx->last_launch : VB_ERR_ARG; }

@@ -307,26 +307,59 @@ def test_mixed_interior_recovery_parity(vb, mixed_case):
 
 def test_mixed_recovery_from_the_solve_state(vb, mixed_case):
     """Recovery at the interface solution of the last mixed solve starts from
-    the interior state refined with it (fewer passes); it must give the
-    oracle's recovery from that same interface solution."""
+    the interior state refined with it, on the condensed residual of the
+    solve's final check (one pass); a second recovery at the same x starts
+    from the state the first one left.  Both must give the oracle's recovery
+    from that same interface solution."""
     name, wl, meta, o, ctx = mixed_case
     n = vb.vb_interface_size(ctx)
     x = torch.zeros(n, dtype=torch.float64, device=DEV)
     vb.vb_pcg_solve(ctx, x)
     nloc = sum(len(sd["kind"]) for sd in wl["subs"])
     u = torch.zeros(nloc, dtype=torch.float64, device=DEV)
+    u2 = torch.zeros(nloc, dtype=torch.float64, device=DEV)
     vb.vb_recover_all(ctx, x, u)
+    vb.vb_recover_all(ctx, x, u2)
     torch.cuda.synchronize()
-    xg, ug = x.cpu().numpy(), u.cpu().numpy()
+    xg = x.cpu().numpy()
     rec = o.recover(xg)
-    off = 0
-    for s, sd in enumerate(wl["subs"]):
-        kind = sd["kind"]
-        us = ug[off: off + len(kind)]
-        off += len(kind)
-        uI, c = rec[s]
-        assert _rel(np.concatenate([us[kind == 0], us[kind == 2]]), np.concatenate([uI, c])) < 1e-10
-        assert _rel(us[kind == 1], xg[sd["gid"][kind == 1]]) < 1e-15
+    for ug in (u.cpu().numpy(), u2.cpu().numpy()):
+        off = 0
+        for s, sd in enumerate(wl["subs"]):
+            kind = sd["kind"]
+            us = ug[off: off + len(kind)]
+            off += len(kind)
+            uI, c = rec[s]
+            assert _rel(np.concatenate([us[kind == 0], us[kind == 2]]), np.concatenate([uI, c])) < 1e-10
+            assert _rel(us[kind == 1], xg[sd["gid"][kind == 1]]) < 1e-15
+
+
+@pytest.mark.parametrize("inner_tol", [0.0, 1e-2])
+def test_mixed_refinement_history_and_inner_tolerance(vb, inner_tol):
+    """vb_refinement_history reports the condensed residual before every
+    refinement step (1 first) and after the last (at or below the
+    tolerance), decreasing, and the inner iterations, which add up to the
+    solve's; a looser inner tolerance (vb_options.inner_tol) reaches the
+    oracle's solution all the same."""
+    wl, meta, o = _problem("t12u")
+    ctx = vb.vb_create(precision=vb.VB_PREC_MIXED, tol=1e-12, inner_tol=inner_tol)
+    try:
+        vb.vb_assemble(ctx, wl, nested=True)
+        vb.vb_setup(ctx)
+        assert vb.vb_refinement_history(ctx) == ([], [])
+        n = vb.vb_interface_size(ctx)
+        x = torch.zeros(n, dtype=torch.float64, device=DEV)
+        info = vb.vb_pcg_solve(ctx, x)
+        rel, inner = vb.vb_refinement_history(ctx)
+        torch.cuda.synchronize()
+    finally:
+        vb.vb_destroy(ctx)
+    print("inner_tol", inner_tol, "history", rel, inner, flush=True)
+    assert len(inner) == info["refinement_steps"] and len(rel) == len(inner) + 1
+    assert rel[0] == 1.0 and rel[-1] <= 1e-12 and all(b < a for a, b in zip(rel, rel[1:]))
+    assert sum(inner) == info["iterations"] and min(inner) >= 1
+    xo, _ = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-13)
+    assert _rel(x.cpu().numpy(), xo) < 1e-10
 
 
 def test_mixed_operators_are_fp32_roundings(vb, mixed_case):

@@ -88,7 +88,8 @@ def test_binding_structs_match_the_header(tmp_path):
                                 dict(adaptive_theta=float("nan")), dict(fp32_pivot_min=-1.0),
                                 dict(fp32_pivot_min=float("nan")),
                                 dict(fp32_pivot_min=float("inf")), dict(tune_factor=3),
-                                dict(tune_factor=-1)])
+                                dict(tune_factor=-1), dict(inner_tol=1.0), dict(inner_tol=-1e-3),
+                                dict(inner_tol=float("nan"))])
 def test_bad_options_are_rejected_on_the_host(kw):
     """vb_create checks its options before any HIP call, so this runs without
     a GPU."""
