@@ -14,6 +14,7 @@
 //   update: A_ik -= L_ij D_j L_kj^T on the lower triangle of the trailing
 //           matrix, 64x64 tiles on the 16x16x4 matrix cores.
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 #include "kernels.h"
@@ -29,75 +30,85 @@ template <typename T> __host__ __device__ __forceinline__ int row_limit(const Ld
   return J.zrow > 0 ? min(J.n, J.zrow + end) : J.n;
 }
 
+// Broadcast of lane `l` (a compile-time constant after unrolling) to the wave.
+__device__ __forceinline__ float lane_bcast(float x, int l) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), l));
+}
+__device__ __forceinline__ double lane_bcast(double x, int l) {
+  const long long v = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)v, l), hi = __builtin_amdgcn_readlane((int)(v >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// f(integral_constant<I>) for I = B .. E - 1, unrolled at compile time (the
+// register arrays below are indexed only by these constants).
+template <int B, int E, class F>
+__device__ __forceinline__ void static_for(const F &f) {
+  if constexpr (B < E) {
+    f(std::integral_constant<int, B>{});
+    static_for<B + 1, E>(f);
+  }
+}
+
+// The NB x NB diagonal block of a panel, one wave per matrix, lane r holding
+// row r in registers: column by column the pivot d_c a_cc (lane c) and the
+// column entries l_kc (lane k) are broadcast, each lane scales its entry of
+// the column and updates its row (a right-looking unblocked LDL^T).  Then
+// inv(L_jj) in place, row by row (forward substitution of L X = I: row t of
+// X is final once lane t has divided by l_tt; the lanes below subtract
+// l_rt times it).  Rows and columns at or beyond b hold zeros.
 template <typename T, int NB>
-__global__ __launch_bounds__(256) void k_ldl_diag(const LdlJob<T> *jobs, int j0) {
+__global__ __launch_bounds__(64) void k_ldl_diag(const LdlJob<T> *jobs, int j0) {
   const LdlJob<T> J = jobs[blockIdx.x];
   if (j0 >= J.e) return;
   const int b = min(NB, J.e - j0);
-  // lower triangle: L_jj; strict upper triangle S[c][r] (r > c): inv(L_jj)[r][c]
-  __shared__ T S[NB][NB + 1];
-  __shared__ T Xd[NB];
-  __shared__ T piv;
-  __shared__ int bad;
-  const int tid = threadIdx.x;
-  if (tid == 0) bad = 0;
-  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-    int r = idx % NB, c = idx / NB;
-    T v = 0;
-    if (r < b && c < b && r >= c) v = J.A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * J.ld];
-    S[r][c] = v;
-  }
-  __syncthreads();
-  for (int c = 0; c < b; ++c) {
-    if (tid == 0) {
-      T d = (j0 + c < J.p) ? T(1) : T(-1);
-      T v = d * S[c][c];
+  const int r = threadIdx.x;
+  const bool row = r < b;
+  T a[NB];
+  static_for<0, NB>([&](auto k) {
+    a[k] = (row && k <= r && k < b) ? J.A[(int64_t)(j0 + r) + (int64_t)(j0 + k) * J.ld] : T(0);
+  });
+  bool bad = false;
+  static_for<0, NB>([&](auto cc) {
+    constexpr int c = decltype(cc)::value;
+    if (c < b) {  // uniform
+      const T d = (j0 + c < J.p) ? T(1) : T(-1);
+      T v = d * lane_bcast(a[c], c);
       if (!(v > T(J.pmin))) {  // wrong-signed, zero or too small pivot: report, keep going finitely
-        if (!bad) { bad = 1; atomicCAS(J.info, 0, j0 + c + 1); }
+        if (!bad && r == 0) atomicCAS(J.info, 0, j0 + c + 1);
+        bad = true;
         v = T(1);
       }
-      T l = sqrt(v);
-      S[c][c] = l;
-      piv = d * l;
+      const T l = sqrt(v);
+      if (r == c) a[c] = l;
+      if (r > c) a[c] /= d * l;
+      const T f = (r > c) ? a[c] * d : T(0);  // l_rc d_c on the rows below
+      static_for<c + 1, NB>([&](auto k) { a[k] -= f * lane_bcast(a[c], k); });
     }
-    __syncthreads();
-    const T pv = piv;
-    for (int r = c + 1 + tid; r < b; r += blockDim.x) S[r][c] /= pv;
-    __syncthreads();
-    // trailing update inside the block: S[r][k] -= l_rc d_c l_kc, r >= k > c
-    const int m = b - c - 1;
-    const T d = (j0 + c < J.p) ? T(1) : T(-1);
-    for (int idx = tid; idx < m * m; idx += blockDim.x) {
-      int r = c + 1 + idx % m, k = c + 1 + idx / m;
-      if (r >= k) S[r][k] -= S[r][c] * d * S[k][c];
+  });
+  if (row)
+    static_for<0, NB>([&](auto k) {
+      if (k <= r) J.A[(int64_t)(j0 + r) + (int64_t)(j0 + k) * J.ld] = a[k];
+    });
+  // X = inv(L_jj) over the same registers: after step t, lanes r <= t hold
+  // row r of X, lanes r > t the partial rows of the remaining system
+  static_for<0, NB>([&](auto tt) {
+    constexpr int t = decltype(tt)::value;
+    if (t < b) {  // uniform
+      const T rd = T(1) / lane_bcast(a[t], t);
+      if (r == t) {
+        static_for<0, t>([&](auto k) { a[k] *= rd; });
+        a[t] = rd;
+      }
+      const T lrt = a[t];  // l_rt on the rows below t
+      static_for<0, t + 1>([&](auto k) {
+        const T x = lane_bcast(a[k], t);  // X[t][k]
+        if (r > t) a[k] = (k < t) ? a[k] - lrt * x : -lrt * x;
+      });
     }
-    __syncthreads();
-  }
-  // write L_jj
-  for (int idx = tid; idx < b * b; idx += blockDim.x) {
-    int r = idx % b, c = idx / b;
-    if (r >= c) J.A[(int64_t)(j0 + r) + (int64_t)(j0 + c) * J.ld] = S[r][c];
-  }
-  // inv(L_jj) by forward substitution, one column per thread; column `col`
-  // of the inverse goes to the strict upper part of row `col` of S.
-  if (tid < b) {
-    const int col = tid;
-    const T dcol = T(1) / S[col][col];
-    Xd[col] = dcol;
-    for (int r = col + 1; r < b; ++r) {
-      T s = -S[r][col] * dcol;
-      for (int t = col + 1; t < r; ++t) s -= S[r][t] * S[col][t];
-      S[col][r] = s / S[r][r];
-    }
-  }
-  __syncthreads();
+  });
   T *inv = J.invL + (int64_t)(j0 / NB) * NB * NB;
-  for (int idx = tid; idx < NB * NB; idx += blockDim.x) {
-    int r = idx % NB, c = idx / NB;
-    T v = 0;
-    if (r < b && c < b) v = (r == c) ? Xd[c] : ((r > c) ? S[c][r] : T(0));
-    inv[idx] = v;
-  }
+  if (r < NB) static_for<0, NB>([&](auto k) { inv[r + k * NB] = (row && k <= r) ? a[k] : T(0); });
 }
 
 // L_ij = A_ij inv(L_jj)^T D_j for rows [j0+b, n) in tiles of PROWS rows.
@@ -604,7 +615,7 @@ static hipError_t ldl_panel_step(const LdlJob<T> *d_jobs, int batch, int max_n, 
   const int pt = (rows + PROWS - 1) / PROWS;
   const int rt = (rows + TILE - 1) / TILE;
   const int ntk = (col_end - j0 + TILE - 1) / TILE;
-  hipLaunchKernelGGL((k_ldl_diag<T, NB>), dim3(batch), dim3(256), 0, s, d_jobs, j0);
+  hipLaunchKernelGGL((k_ldl_diag<T, NB>), dim3(batch), dim3(64), 0, s, d_jobs, j0);
   if (rows > 0) {
     if (NB == 64)
       hipLaunchKernelGGL((k_ldl_panel_mfma<T>), dim3((rows + 63) / 64, batch), dim3(256), 0, s,

@@ -129,6 +129,7 @@ struct DiagJob {
   int f32;
 };
 hipError_t set_diag(const DiagJob *d_jobs, int batch, int max_cnt, hipStream_t s);
+hipError_t diag_gather(const double *A, int64_t ld, int n, double *out, hipStream_t s);
 
 struct CoarseSub {
   const double *SPi;   // npi x npi (full), leading dimension ld
@@ -198,6 +199,8 @@ hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *i
                         double *z, const int64_t *yoff, int nsub, int i0, int nb, int max_N,
                         bool fp32, hipStream_t s);
 // back-substitution right-hand side: y2_j = d_j z_j - sum_l L[e+1+l, j] dx[gid_l]
+hipError_t back_init(const SubDev *d_subs, const double *z, double *y2, const int64_t *yoff, int nsub,
+                     int max_e, hipStream_t s);
 hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
                     const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s);
 

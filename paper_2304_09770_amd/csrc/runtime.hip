@@ -154,6 +154,10 @@ struct vb_ctx {
   double *r0f = nullptr;
   int64_t n_ir2 = 0;                     // second-level part of y_ir / z_ir / zst
   int64_t *sep_src = nullptr, *sep_dst = nullptr;  // separator corrections -> G2d
+  // the interior correction's interface term -L_GammaI^T dx as GEMVs over the
+  // FP32 factors' interface rows (second level from dx, fronts from G2d)
+  GemvJob *j_brhs = nullptr, *j_brhsf = nullptr;
+  int brhs_m = 0, brhs_mf = 0;
   std::vector<std::vector<FrontJob>> fj_rhs;
   std::vector<FrontJob *> d_fj_rhs;
 
@@ -401,6 +405,20 @@ struct vb_ctx {
         (void)hipFree(b.p);
     }
     pool.swap(keep);
+  }
+  // whether pool_get would hand out an existing block for this request
+  bool pool_has(size_t bytes) const {
+    bytes = (bytes + 255) & ~size_t(255);
+    for (const PBlock &b : pool)
+      if (!b.used && b.bytes >= bytes && b.bytes <= bytes + bytes / 2 + (size_t(64) << 20)) return true;
+    return false;
+  }
+  // the largest unused pool block of at least lo and at most hi bytes (0: none)
+  size_t pool_fit(size_t lo, size_t hi) const {
+    size_t best = 0;
+    for (const PBlock &b : pool)
+      if (!b.used && b.bytes >= lo && b.bytes <= hi && b.bytes > best) best = b.bytes;
+    return best;
   }
   size_t pool_unused_bytes() const {
     size_t t = 0;
@@ -1230,6 +1248,21 @@ extern "C" {
 }  // extern "C"
 
 // ------------------------------------------------------------------ setup
+// Lists of values per key as CSR (ptr, idx): visit(emit) calls emit(key,
+// value) for every entry in a fixed order and is run twice (count, then
+// fill), so each key's values keep that order (the owner sums add them in
+// it).
+template <class Visit>
+static void build_csr(int64_t nkeys, const Visit &visit, std::vector<int64_t> &ptr,
+                      std::vector<int64_t> &idx) {
+  ptr.assign(nkeys + 1, 0);
+  visit([&](int64_t k, int64_t) { ++ptr[k + 1]; });
+  for (int64_t k = 0; k < nkeys; ++k) ptr[k + 1] += ptr[k];
+  idx.resize(ptr[nkeys]);
+  std::vector<int64_t> cur(ptr.begin(), ptr.end() - 1);
+  visit([&](int64_t k, int64_t v) { idx[cur[k]++] = v; });
+}
+
 template <typename T>
 static int run_ldl(vb_ctx *ctx, std::vector<LdlJob<T>> &jobs, int max_n, int max_e,
                    bool timed = false, int nb = 0, int sb1 = 0) {
@@ -2765,23 +2798,25 @@ static int setup_impl(vb_ctx *ctx) {
     double *gl = nullptr;
     UCHK(ctx->dalloc(&gl, std::max<int64_t>(ftot, 1), true));
     std::vector<GatherJob> gj;
-    std::vector<std::vector<int64_t>> own(nG);
     int64_t fo = 0;
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       GatherJob J{Xptr(S), S.xld, gl + fo, S.ng, d_iota, d_iota, S.ng, 1, 1.0, 0, f32 ? 1 : 0, 0};
       J.ci = d_iota + S.ng;  // column ng of X
       gj.push_back(J);
-      for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(fo + l);
       fo += S.ng;
     }
     int rc0 = run_gather(ctx, gj, ctx->max_ng, 1);
     if (rc0) return rc0;
-    std::vector<int64_t> ptr(nG + 1, 0), idx;
-    for (int64_t g = 0; g < nG; ++g) {
-      ptr[g + 1] = ptr[g] + own[g].size();
-      idx.insert(idx.end(), own[g].begin(), own[g].end());
-    }
+    std::vector<int64_t> ptr, idx;
+    build_csr(nG, [&](auto emit) {
+      int64_t o = 0;
+      for (int s = 0; s < nS; ++s) {
+        const SubH &S = ctx->subs[s];
+        for (int l = 0; l < S.ng; ++l) emit(S.gidl[l], o + l);
+        o += S.ng;
+      }
+    }, ptr, idx);
     UCHK(ctx->upload(&ctx->g_ptr, ptr, true));
     UCHK(ctx->upload(&ctx->g_idx, idx, true));
     CHK(owner_sum((int)nG, ctx->g_ptr, ctx->g_idx, gl, nullptr, nullptr, ctx->g, st));
@@ -2863,7 +2898,16 @@ static int setup_impl(vb_ctx *ctx) {
     fre += ctx->pool_unused_bytes();
     const double lim = ctx->opt.setup_mem_limit > 0.0 ? ctx->opt.setup_mem_limit : 0.6 * (double)fre;
     const int64_t budget = std::max<int64_t>(nmax, (int64_t)(lim / (double)nsz));
-    const int64_t wmax = std::min(ntot, budget);
+    int64_t wmax = std::min(ntot, budget);
+    // the budget follows the free memory, so an earlier setup's buffer (left in
+    // the pool) can be a little smaller than this request, which would then
+    // need a new allocation beside it: such a buffer (at least 3/4 of the
+    // request and the largest matrix) is taken whole instead
+    if (!ctx->pool_has((size_t)wmax * nsz)) {
+      const size_t want = (size_t)wmax * nsz;
+      const size_t fit = ctx->pool_fit(std::max((size_t)nmax * nsz, want / 4 * 3), want);
+      if (fit) wmax = (int64_t)(fit / nsz);
+    }
     char *Nbuf = nullptr;
     UCHK(ctx->dalloc(&Nbuf, wmax * nsz, true));
     int rc = 0;
@@ -3031,25 +3075,24 @@ static int setup_impl(vb_ctx *ctx) {
                     -1.0, 0, 0, 0});
     }
     // the diagonal of every coarse matrix before and after its factorisation
-    // (one strided copy each): a pivot that cancels to 1e-10 of its column's
-    // own diagonal entry means a singular coarse problem (for instance a
-    // primal space that does not see the face fluxes, Assumption 1), which
-    // rounding may leave with either sign
+    // (gathered on the device, one copy to the host): a pivot that cancels to
+    // 1e-10 of its column's own diagonal entry means a singular coarse
+    // problem (for instance a primal space that does not see the face fluxes,
+    // Assumption 1), which rounding may leave with either sign
     std::vector<int64_t> doff(nP + 1, 0);
     for (int pp = 0; pp < nP; ++pp) doff[pp + 1] = doff[pp] + ctx->probs[pp].nprim + ctx->probs[pp].ns;
-    std::vector<double> dg0(doff[nP]), dg1(doff[nP]);
-    auto diag_copy = [&](std::vector<double> &out) -> hipError_t {
+    std::vector<double> dg(2 * doff[nP]);
+    double *ddg = nullptr;
+    UCHK(ctx->dalloc(&ddg, std::max<int64_t>(2 * doff[nP], 1), true));
+    auto diag_copy = [&](int64_t half) -> hipError_t {
       for (int pp = 0; pp < nP; ++pp) {
-        const int64_t ncs = doff[pp + 1] - doff[pp];
-        if (!ncs) continue;
-        hipError_t e = hipMemcpy2DAsync(out.data() + doff[pp], sizeof(double), ctx->Kaug + koff[pp],
-                                        (ldk[pp] + 1) * sizeof(double), sizeof(double), ncs,
-                                        hipMemcpyDeviceToHost, st);
+        hipError_t e = diag_gather(ctx->Kaug + koff[pp], ldk[pp], (int)(doff[pp + 1] - doff[pp]),
+                                   ddg + half + doff[pp], st);
         if (e != hipSuccess) return e;
       }
       return hipSuccess;
     };
-    CHK(diag_copy(dg0));
+    CHK(diag_copy(0));
     int rc = run_diag(ctx, dj, ctx->max_ncs);
     if (rc) return rc;
     rc = run_ldl(ctx, lj, 2 * ctx->max_ncs, ctx->max_ncs);
@@ -3057,8 +3100,11 @@ static int setup_impl(vb_ctx *ctx) {
     {
       std::vector<int> h(nP);
       CHK(hipMemcpyAsync(h.data(), ctx->info + nS, nP * sizeof(int), hipMemcpyDeviceToHost, st));
-      CHK(diag_copy(dg1));
+      CHK(diag_copy(doff[nP]));
+      if (doff[nP] > 0)
+        CHK(hipMemcpyAsync(dg.data(), ddg, dg.size() * sizeof(double), hipMemcpyDeviceToHost, st));
       CHK(hipStreamSynchronize(st));
+      const double *dg0 = dg.data(), *dg1 = dg.data() + doff[nP];
       for (int pp = 0; pp < nP; ++pp) {
         int bad = h[pp] ? h[pp] - 1 : -1;
         for (int64_t j = doff[pp]; bad < 0 && j < doff[pp + 1]; ++j)
@@ -3107,7 +3153,23 @@ static int setup_impl(vb_ctx *ctx) {
     // (mixed precision: the iteration reads an FP32 copy, made at the end)
     double *dall = nullptr;
     UCHK(ctx->dalloc(&dall, std::max<int64_t>(dtot, 1), f32));
-    int64_t doff = 0;
+    // the augmented matrices [[sum Sbar, I], [I, 0]] (zeroed) and the Sbar
+    // blocks of every entity, each set in one allocation
+    int64_t atot = 0, stot = 0;
+    if (ctx->opt.scaling != VB_SCALING_COUNTING)
+      for (auto &H : ctx->ents) {
+        const int m = H.n - H.rank;
+        if (m <= 0) continue;
+        atot += round_up(2 * m, 32) * 2 * m;
+        stot += (int64_t)H.subs.size() * m * m;
+      }
+    double *aall = nullptr, *sall = nullptr;
+    UCHK(ctx->dalloc(&aall, std::max<int64_t>(atot, 1), true));
+    UCHK(ctx->dalloc(&sall, std::max<int64_t>(stot, 1), true));
+    if (atot) CHK(hipMemsetAsync(aall, 0, atot * sizeof(double), st));
+    if (ctx->opt.scaling == VB_SCALING_COUNTING && dtot)
+      CHK(hipMemsetAsync(dall, 0, dtot * sizeof(double), st));
+    int64_t doff = 0, aoff = 0, soff = 0;
     int64_t ioff = 0;
     int cnt = 0;
     for (int e = 0; e < nE; ++e) {
@@ -3126,15 +3188,12 @@ static int setup_impl(vb_ctx *ctx) {
         doff += ldm * m;
       }
       if (ctx->opt.scaling == VB_SCALING_COUNTING) {
-        for (size_t q = 0; q < H.subs.size(); ++q) {
-          CHK(hipMemsetAsync(H.D[q], 0, (size_t)ldm * m * sizeof(double), st));
-          dj.push_back({H.D[q], ldm, 0, 0, m, 1.0 / H.subs.size()});
-        }
+        for (size_t q = 0; q < H.subs.size(); ++q) dj.push_back({H.D[q], ldm, 0, 0, m, 1.0 / H.subs.size()});
         continue;
       }
       H.Dld = round_up(2 * m, 32);
-      UCHK(ctx->dalloc(&H.Daug, H.Dld * 2 * m, true));
-      CHK(hipMemsetAsync(H.Daug, 0, H.Dld * 2 * m * sizeof(double), st));
+      H.Daug = aall + aoff;
+      aoff += H.Dld * 2 * m;
       for (size_t q = 0; q < H.subs.size(); ++q) {
         const int s = H.subs[q];
         SubH &S = ctx->subs[s];
@@ -3146,7 +3205,8 @@ static int setup_impl(vb_ctx *ctx) {
         const void *X = Xptr(S);
         if (rounds.size() <= q) rounds.resize(q + 1);
         rounds[q].push_back({X, S.xld, H.Daug, H.Dld, d_idx, d_idx, m, m, 1.0, 1, f32 ? 1 : 0, 0});
-        UCHK(ctx->dalloc(&H.Sbar[q], (int64_t)m * m, true));
+        H.Sbar[q] = sall + soff;
+        soff += (int64_t)m * m;
         sb.push_back({X, S.xld, H.Sbar[q], m, d_idx, d_idx, m, m, 1.0, 0, f32 ? 1 : 0, 0});
         if (H.D[q])
           mj.push_back({H.Daug + m + m * H.Dld, H.Sbar[q], H.D[q], H.Dld, m, ldm, m, m, m, 0, -1.0, 0.0});
@@ -3223,14 +3283,11 @@ static int setup_impl(vb_ctx *ctx) {
     // S_hat: per-subdomain bordered GEMV (reads p) + owner sums (into q)
     std::vector<GemvJob> js(nS);
     int64_t yoff = 0;
-    std::vector<std::vector<int64_t>> own(nTot);
     for (int s = 0; s < nS; ++s) {
       SubH &S = ctx->subs[s];
       S.y_off = yoff;
       js[s] = {Xptr(S), S.xld, S.ng + 1, S.ng + 1, ctx->p, S.d_gidl, nullptr, nullptr, 1.0, 0,
                f32 ? 1 : 0};
-      for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff + l);
-      own[nG + s].push_back(yoff + S.ng);
       yoff += S.ng + 1;
     }
     ctx->n_yloc = yoff;
@@ -3257,11 +3314,14 @@ static int setup_impl(vb_ctx *ctx) {
       }
       UCHK(ctx->upload(&ctx->j_ssym, sj));
     }
-    std::vector<int64_t> ptr(nTot + 1, 0), idx;
-    for (int64_t gg = 0; gg < nTot; ++gg) {
-      ptr[gg + 1] = ptr[gg] + own[gg].size();
-      idx.insert(idx.end(), own[gg].begin(), own[gg].end());
-    }
+    std::vector<int64_t> ptr, idx;
+    build_csr(nTot, [&](auto emit) {
+      for (int s = 0; s < nS; ++s) {
+        const SubH &S = ctx->subs[s];
+        for (int l = 0; l < S.ng; ++l) emit(S.gidl[l], S.y_off + l);
+        emit(nG + s, S.y_off + S.ng);
+      }
+    }, ptr, idx);
     UCHK(ctx->upload(&ctx->own_ptr, ptr));
     UCHK(ctx->upload(&ctx->own_idx, idx));
     // dual vectors: gD (restricted), wv (Neumann output), tv (Neumann [t1; t2])
@@ -3364,21 +3424,18 @@ static int setup_impl(vb_ctx *ctx) {
     UCHK(ctx->upload(&ctx->j_coarse, jc));
     // coarse rhs: base = r at the primal positions (or p0), owners = Phi^T g contributions
     std::vector<int64_t> base(ctx->nCS), dst(ctx->nCS);
-    std::vector<std::vector<int64_t>> cown(ctx->nCS);
     for (int e = 0; e < nE; ++e) {
       EntH &H = ctx->ents[e];
       for (int j = 0; j < H.rank; ++j) base[ctx->ent_cbase[e] + j] = H.gids[j];
     }
     for (int s = 0; s < nS; ++s) base[ctx->sub_cp0[s]] = nG + s;
-    for (int s = 0; s < nS; ++s) {
-      SubH &S = ctx->subs[s];
-      for (int a = 0; a < S.npi; ++a) cown[S.cidx[a]].push_back(sto[s] + S.ndl + a);
-    }
-    std::vector<int64_t> cptr(ctx->nCS + 1, 0), cidx;
-    for (int c = 0; c < ctx->nCS; ++c) {
-      cptr[c + 1] = cptr[c] + cown[c].size();
-      cidx.insert(cidx.end(), cown[c].begin(), cown[c].end());
-    }
+    std::vector<int64_t> cptr, cidx;
+    build_csr(ctx->nCS, [&](auto emit) {
+      for (int s = 0; s < nS; ++s) {
+        const SubH &S = ctx->subs[s];
+        for (int a = 0; a < S.npi; ++a) emit(S.cidx[a], sto[s] + S.ndl + a);
+      }
+    }, cptr, cidx);
     UCHK(ctx->upload(&ctx->c_ptr, cptr));
     UCHK(ctx->upload(&ctx->c_idx, cidx));
     UCHK(ctx->upload(&ctx->c_base, base));
@@ -3475,19 +3532,34 @@ static int setup_impl(vb_ctx *ctx) {
       UCHK(ctx->dalloc(&ctx->dx, nG + nS));
       UCHK(ctx->upload(&ctx->d_yoff2, yoff2));
       UCHK(ctx->upload(&ctx->d_uoff, uoff));
+      {
+        std::vector<GemvJob> jb(nS), jbf(nF);
+        ctx->brhs_m = ctx->brhs_mf = 0;
+        auto job = [&](const SubDev &D, const double *x, double *y) {
+          return GemvJob{(const char *)D.W + (int64_t)(D.e + 1) * (int64_t)ctx->wsz, D.ld, D.ng, D.e, x, D.gidl,
+                         nullptr, y, -1.0, 1, 1};
+        };
+        for (int s = 0; s < nS; ++s) {
+          jb[s] = job(ctx->subdev[s], ctx->dx, ctx->y_ir + yoff2[s]);
+          ctx->brhs_m = std::max(ctx->brhs_m, ctx->subdev[s].ng);
+        }
+        for (int f = 0; f < nF; ++f) {
+          jbf[f] = job(ctx->frdev[f], ctx->G2d, ctx->y_ir + yoff2f[f]);
+          ctx->brhs_mf = std::max(ctx->brhs_mf, ctx->frdev[f].ng);
+        }
+        UCHK(ctx->upload(&ctx->j_brhs, jb));
+        if (nF) UCHK(ctx->upload(&ctx->j_brhsf, jbf));
+      }
       std::vector<RecJob> rj2(nS), rj2f(nF);
-      std::vector<std::vector<int64_t>> own(nG);
-      for (int s = 0; s < nS; ++s) {
-        SubH &S = ctx->subs[s];
-        rj2[s] = l2job(s, ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]);
-        for (int l = 0; l < S.ng; ++l) own[S.gidl[l]].push_back(yoff2[s] + S.e + 1 + l);
-      }
+      for (int s = 0; s < nS; ++s) rj2[s] = l2job(s, ctx->zst + yoff2[s], ctx->u_loc + ctx->rec_off[s]);
       UCHK(ctx->upload(&ctx->j_rec_ir, rj2));
-      std::vector<int64_t> ptr(nG + 1, 0), idx;
-      for (int64_t g = 0; g < nG; ++g) {
-        ptr[g + 1] = ptr[g] + own[g].size();
-        idx.insert(idx.end(), own[g].begin(), own[g].end());
-      }
+      std::vector<int64_t> ptr, idx;
+      build_csr(nG, [&](auto emit) {
+        for (int s = 0; s < nS; ++s) {
+          const SubH &S = ctx->subs[s];
+          for (int l = 0; l < S.ng; ++l) emit(S.gidl[l], yoff2[s] + S.e + 1 + l);
+        }
+      }, ptr, idx);
       UCHK(ctx->upload(&ctx->ir_ptr, ptr));
       UCHK(ctx->upload(&ctx->ir_idx, idx));
       if (nF) {
@@ -4066,8 +4138,11 @@ static int interior_correction(vb_ctx *ctx, const double *dx) {
   hipStream_t st = ctx->stream;
   const int nb = dir_nb(ctx, 0), nb2 = dir_nb(ctx, ctx->nd ? 1 : 0);
   if (ctx->max_e > 0) {
-    CHK(back_rhs(ctx->d_subdev, ctx->z_ir, dx, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e,
-                 ctx->fp32, st));
+    CHK(back_init(ctx->d_subdev, ctx->z_ir, ctx->y_ir, ctx->d_yoff2, ctx->nS, ctx->max_e, st));
+    if (dx) {
+      if (dx != ctx->dx) return ctx->fail(VB_ERR_STATE, "interior correction: unexpected vector");
+      CHK(gemv_t_cpb(ctx->j_brhs, ctx->nS, ctx->brhs_m, ctx->max_e, 8, st));
+    }
     for (int j0 = ((ctx->max_e - 1) / nb2) * nb2; j0 >= 0; j0 -= nb2)
       CHK(recover_backsolve(ctx->d_subdev, ctx->invL, ctx->d_invoff, ctx->y_ir, ctx->z_ir,
                             ctx->d_yoff2, ctx->nS, j0, nb2, ctx->fp32, st));
@@ -4082,8 +4157,8 @@ static int interior_correction(vb_ctx *ctx, const double *dx) {
       CHK(hipMemsetAsync(ctx->G2d, 0, (ctx->nG + nS) * sizeof(double), st));
     CHK(scatter_copy((int)ctx->n_sep_tot, ctx->z_ir, ctx->sep_src, ctx->sep_dst, ctx->G2d, 1.0, st));
     if (ctx->max_ef > 0) {
-      CHK(back_rhs(ctx->d_frdev, ctx->z_ir, ctx->G2d, ctx->y_ir, ctx->d_yoff2f, nF, ctx->max_ef,
-                   ctx->fp32, st));
+      CHK(back_init(ctx->d_frdev, ctx->z_ir, ctx->y_ir, ctx->d_yoff2f, nF, ctx->max_ef, st));
+      CHK(gemv_t_cpb(ctx->j_brhsf, nF, ctx->brhs_mf, ctx->max_ef, 8, st));
       for (int j0 = ((ctx->max_ef - 1) / nb) * nb; j0 >= 0; j0 -= nb)
         CHK(recover_backsolve(ctx->d_frdev, ctx->invLf, ctx->d_invofff, ctx->y_ir, ctx->z_ir,
                               ctx->d_yoff2f, nF, j0, nb, ctx->fp32, st));

@@ -262,6 +262,19 @@ hipError_t set_diag(const DiagJob *d_jobs, int batch, int max_cnt, hipStream_t s
   return hipGetLastError();
 }
 
+// out[i] = A[i + i * ld] for i < n (the diagonal of a column-major matrix,
+// made contiguous for one small copy to the host).
+__global__ void k_diag_gather(const double *A, int64_t ld, int n, double *out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = A[(int64_t)i * (ld + 1)];
+}
+
+hipError_t diag_gather(const double *A, int64_t ld, int n, double *out, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_diag_gather, dim3((n + 255) / 256), dim3(256), 0, s, A, ld, n, out);
+  return hipGetLastError();
+}
+
 // Coarse matrix of the partially assembled problem (eq. BDDCprec):
 // [[sum_i R_Pi^T S_Pi^(i) R_Pi, B0_Pi^T], [B0_Pi, -w w^T]] with w the
 // normalised subdomain volumes (removes the constant-p0 kernel of the
@@ -783,6 +796,23 @@ __global__ void k_back_rhs(const SubDev *subs, const double *z, const double *dx
     const double d = (j < S.nv) ? 1.0 : -1.0;
     y2[yoff[blockIdx.y] + j] = d * z[yoff[blockIdx.y] + j] - s;
   }
+}
+
+// y2_j = d_j z_j over the eliminated columns (the interior correction's
+// right-hand side before the interface term, which a GEMV adds).
+__global__ void k_back_init(const SubDev *subs, const double *z, double *y2, const int64_t *yoff) {
+  const SubDev S = subs[blockIdx.y];
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= S.e) return;
+  const int64_t o = yoff[blockIdx.y] + j;
+  y2[o] = (j < S.nv) ? z[o] : -z[o];
+}
+
+hipError_t back_init(const SubDev *d_subs, const double *z, double *y2, const int64_t *yoff, int nsub,
+                     int max_e, hipStream_t s) {
+  if (!nsub || max_e <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_back_init, dim3((max_e + 255) / 256, nsub), dim3(256), 0, s, d_subs, z, y2, yoff);
+  return hipGetLastError();
 }
 
 hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
