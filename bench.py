@@ -65,8 +65,10 @@ PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
 # HBM bytes per launch of the dominant kernel, from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE (scaled by the readings of a 1 GiB device copy: x2.0, x1.0), per
-# workload and path; to be cleared whenever the kernel changes.
-TRAFFIC_BYTES = {("c3", "mixed"): 5.0158e10}
+# workload, path and the outer super-panel the autotuner chose for the local
+# Dirichlet factorisations (the rank of each launch); to be cleared whenever
+# the kernel changes.
+TRAFFIC_BYTES = {("c3", "mixed", 1024): 5.0144e10}
 TRAFFIC_SOURCE = "profiles/ldl_update_wide_f32_c3_hbm_counters.md"
 PRECISION_NAMES = {"fp64": "fp64",
                    "mixed": "mixed: fp32 local factors and Schur operators, fp64 refinement"}
@@ -76,13 +78,13 @@ def log(msg):
     print("[bench] " + msg, file=sys.stderr, flush=True)
 
 
-def ldl_roofline(ldl, peak, dtype, traffic=None, source=None):
+def ldl_roofline(ldl, peak, dtype, rank, traffic=None, source=None):
     """Achieved rate of the timed Dirichlet trailing-update launches
     (vb_kernel_stats 0: algorithmic flops and HIP-event durations)."""
     a = ldl["work"] / (ldl["total_ms"] * 1e-3) / 1e12 if ldl["total_ms"] > 0 else None
     return {"bound": "mfma",
-            "kernel": "k_ldl_update_wide_%s (rank-1024 trailing update of the local "
-                      "Dirichlet LDL^T)" % dtype,
+            "kernel": "k_ldl_update_wide_%s (rank-%d trailing update of the local "
+                      "Dirichlet LDL^T)" % (dtype, rank),
             "achieved": a, "peak": peak, "unit": "TFLOP/s", "frac": (a / peak) if a else None,
             "traffic": traffic, "traffic_source": source,
             "launches": ldl["launches"], "avg_launch_ms": ldl["total_ms"] / max(ldl["launches"], 1)}
@@ -497,8 +499,9 @@ def main():
     peak = PEAK_FP64_TFLOPS if head == "fp64" else PEAK_FP32_TFLOPS
 
     def roof(r, pk, dtype, prec):
-        key = (args.config, prec)
-        return ldl_roofline(r["ldl"], pk, dtype, TRAFFIC_BYTES.get(key),
+        rank = r["tuned"]["factor_superpanel"][0]
+        key = (args.config, prec, rank)
+        return ldl_roofline(r["ldl"], pk, dtype, rank, TRAFFIC_BYTES.get(key),
                             TRAFFIC_SOURCE if key in TRAFFIC_BYTES else None)
 
     def gemv(r):
@@ -647,6 +650,7 @@ def run_adaptive(args):
                           "fallback_faces": sum(f["path"] == 2 for f in faces),
                           "selected_rows": sum(f["n_selected"] for f in faces)}
             runs[name]["ldl"] = vb.vb_kernel_stats(ctx, 0)
+            runs[name]["ldl_rank"] = vb.vb_tuned_tile(ctx, 9)
             xs[name] = x.cpu().numpy()
             log("%s: %.3f solves/s, %d iterations, kappa %.1f, N_c %d"
                 % (name, 1.0 / dt, info["iterations"], runs[name]["kappa"], info["n_coarse"]))
@@ -654,8 +658,10 @@ def run_adaptive(args):
             vb.vb_destroy(ctx)
     vb.vb_mlp_destroy(m)
     ldl = runs["learned"].pop("ldl")
+    ldl_rank = runs["learned"].pop("ldl_rank")
     for r in runs.values():
         r.pop("ldl", None)
+        r.pop("ldl_rank", None)
     ref = xs["exact"]
     out = {
         "metric": "PCG+BDDC solves/s at 1e-8 rel. residual, mixed/batched vs FP64 GPU",
@@ -672,7 +678,7 @@ def run_adaptive(args):
         "data": "synthetic",
         "config": {"workload": cfg + ": " + WORKLOADS[cfg], "subdomains": len(wl["subs"]),
                    "precision": "fp64"},
-        "roofline": ldl_roofline(ldl, PEAK_FP64_TFLOPS, "f64"),
+        "roofline": ldl_roofline(ldl, PEAK_FP64_TFLOPS, "f64", ldl_rank),
         "runs": runs,
         "speedup_vs_fp64": runs["learned"]["solves_per_s"] / runs["minimal"]["solves_per_s"],
         "speedup_vs_exact_adaptive": runs["learned"]["solves_per_s"] / runs["exact"]["solves_per_s"],
@@ -889,6 +895,7 @@ def run_batched(args):
         vb.vb_kernel_stats(ctx, 0, reset=True)
         run(ctx, 1)
         ldl = vb.vb_kernel_stats(ctx, 0)
+        ldl_rank = vb.vb_tuned_tile(ctx, 9)
         vb.vb_set_profile(ctx, 0)
         faces = vb.vb_adaptive_info(ctx)
         tiles = [vb.vb_tuned_tile(ctx, k) for k in range(5)]
@@ -955,7 +962,7 @@ def run_batched(args):
         "predicted_path_faces": sum(f["path"] == 1 for f in faces),
         "fallback_faces": sum(f["path"] == 2 for f in faces),
         "gemv_tiles": tiles,
-        "roofline": ldl_roofline(ldl, PEAK_FP32_TFLOPS, "f32"),
+        "roofline": ldl_roofline(ldl, PEAK_FP32_TFLOPS, "f32", ldl_rank),
         "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)

@@ -153,6 +153,12 @@ hipError_t symmetrize(void *const *mats, const int64_t *lds, const int32_t *ns, 
                       int max_n, bool fp32, hipStream_t s);
 hipError_t transpose_sq(void *const *mats, const int64_t *lds, const int32_t *ns, int batch,
                         int max_n, bool fp32, hipStream_t s);
+// T^T X per entity block from the left (contiguous column segments); *done
+// false when an entity is too large for it (the caller then uses apply_T_cols
+// on the transposed block).  max_rn: the largest min(n_con, n) * n over the
+// entities, max_rank the largest min(n_con, n).
+hipError_t apply_T_rows(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng, int max_ent,
+                        int max_en, int max_rn, int max_rank, bool fp32, bool *done, hipStream_t s);
 hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng,
                         int max_ent, int max_en, bool fp32, hipStream_t s);
 hipError_t transform_b0(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ent,

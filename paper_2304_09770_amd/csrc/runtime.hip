@@ -2773,14 +2773,33 @@ static int setup_impl(vb_ctx *ctx) {
       ld[s] = S.xld;
       n[s] = S.ng + 1;
     }
-    int max_en = 1;
-    for (const auto &H : ctx->ents) max_en = std::max(max_en, H.n);
+    // largest entity, and the bounds min(n_con, n) of its reflectors' count and
+    // min(n_con, n) * n of their entries
+    int max_en = 1, max_rn = 1, max_rank = 0;
+    for (const auto &H : ctx->ents) {
+      max_en = std::max(max_en, H.n);
+      max_rn = std::max(max_rn, std::min(H.ncon, H.n) * H.n);
+      max_rank = std::max(max_rank, std::min(H.ncon, H.n));
+    }
     int rc = run_symm(ctx, m, ld, n, false, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
+    // T^T X (contiguous entity segments of the columns), transposed to X T
+    // (X symmetric), T^T X T; entities too large for that kernel take the
+    // column kernel on both sides instead
+    bool rows = false;
+    CHK(apply_T_rows(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, max_rn, max_rank, f32, &rows,
+                     st));
+    if (!rows)
+      CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
     rc = run_symm(ctx, m, ld, n, true, f32);
     if (rc) return rc;
-    CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
+    if (rows) {
+      CHK(apply_T_rows(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, max_rn, max_rank, f32, &rows,
+                       st));
+      if (!rows) return ctx->fail(VB_ERR_DEVICE, "change of basis: second pass not launched");
+    } else {
+      CHK(apply_T_cols(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ng, ctx->max_ent, max_en, f32, st));
+    }
     CHK(transform_b0(ctx->d_subdev, ctx->d_entdev, nS, ctx->max_ent, st));
   }
   CHK(mark(4));

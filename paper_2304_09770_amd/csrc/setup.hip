@@ -456,6 +456,175 @@ hipError_t apply_T_cols(const SubDev *d_subs, const EntDev *d_ents, int nsub, in
               : apply_T_typed<double>(d_subs, d_ents, nsub, max_ng + 1, max_ent, max_en, s);
 }
 
+// T^T applied from the left to one entity's rows (ent_off .. ent_off + n) of
+// every column of the bordered block X.  The entity's segment of a column is
+// contiguous: a wave (n > 32: entries lane + 64 q, in the storage type) or a
+// group of G lanes (G the smallest power of two >= n: one entry each) reads
+// it with coalesced loads and keeps it in registers.  The (at most
+// APPLY_T_RK) reflectors act at once in their compact form,
+// H_{r-1} ... H_0 = I - V Tw^T V^T with Tw upper triangular (Tw_ii = tau_i,
+// Tw[0:i, i] = -tau_i Tw[0:i, 0:i] V[:, 0:i]^T v_i): w = V^T x (r dot
+// products, reduced in the group together), u = Tw^T w, x -= V u.  V and Tw
+// are staged in LDS once per workgroup of up to 256 columns (the reflectors
+// are stored with zeros above their leading entry).  (X T = (T^T X^T)^T for
+// the symmetric X: applied, transposed, applied.)
+constexpr int APPLY_T_EPL = 32, APPLY_T_RK = 4;
+
+// x -= V Tw^T V^T x on one segment of n <= 64 APPLY_T_EPL entries held by a
+// whole wave (entry lane + 64 q).
+template <typename T>
+__device__ __forceinline__ void seg_apply_wave(T *col, int n, int rk, const double *Vs, const double *Tw,
+                                               int lane) {
+  constexpr int EPL = APPLY_T_EPL, RK = APPLY_T_RK;
+  T x[EPL];
+#pragma unroll
+  for (int q = 0; q < EPL; ++q) x[q] = (64 * q < n && lane + 64 * q < n) ? col[lane + 64 * q] : T(0);
+  double wv[RK];
+#pragma unroll
+  for (int k = 0; k < RK; ++k) {
+    double t = 0.0;
+    if (k < rk) {
+      const double *v = Vs + k * n + lane;
+#pragma unroll
+      for (int q = 0; q < EPL; ++q)
+        if (64 * q < n && lane + 64 * q < n) t += (double)x[q] * v[64 * q];
+    }
+    wv[k] = t;
+  }
+#pragma unroll
+  for (int m = 32; m > 0; m >>= 1)
+#pragma unroll
+    for (int k = 0; k < RK; ++k) wv[k] += __shfl_xor(wv[k], m);
+  double u[RK];
+#pragma unroll
+  for (int i = 0; i < RK; ++i) {  // u = Tw^T w
+    double t = 0.0;
+#pragma unroll
+    for (int a = 0; a <= i; ++a) t += Tw[a + i * RK] * wv[a];
+    u[i] = i < rk ? t : 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < EPL; ++q)
+    if (64 * q < n && lane + 64 * q < n) {
+      double t = (double)x[q];
+#pragma unroll
+      for (int k = 0; k < RK; ++k)
+        if (k < rk) t -= Vs[k * n + lane + 64 * q] * u[k];
+      col[lane + 64 * q] = (T)t;
+    }
+}
+
+// The same for a segment of n <= G entries held by a group of G lanes (one
+// entry per lane).
+template <typename T>
+__device__ __forceinline__ void seg_apply_group(T *col, int n, int rk, const double *Vs, const double *Tw,
+                                                int gl, int G) {
+  constexpr int RK = APPLY_T_RK;
+  const bool in = gl < n;
+  const double x = in ? (double)col[gl] : 0.0;
+  double wv[RK];
+#pragma unroll
+  for (int k = 0; k < RK; ++k) wv[k] = (in && k < rk) ? x * Vs[k * n + gl] : 0.0;
+  for (int m = G / 2; m > 0; m >>= 1)
+#pragma unroll
+    for (int k = 0; k < RK; ++k) wv[k] += __shfl_xor(wv[k], m, G);
+  double t = x;
+#pragma unroll
+  for (int i = 0; i < RK; ++i) {
+    double ui = 0.0;
+#pragma unroll
+    for (int a = 0; a <= i; ++a) ui += Tw[a + i * RK] * wv[a];
+    if (in && i < rk) t -= Vs[i * n + gl] * ui;
+  }
+  if (in) col[gl] = (T)t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_apply_T_rows(const SubDev *subs, const EntDev *ents, int cols) {
+  constexpr int RK = APPLY_T_RK;
+  const SubDev S = subs[blockIdx.z];
+  if ((int)blockIdx.y >= S.n_ent) return;
+  const int nx = S.ng + 1;
+  const int c0 = blockIdx.x * cols;
+  if (c0 >= nx) return;
+  const EntDev E = ents[S.ent[blockIdx.y]];
+  const int rk = min(*E.rank, RK), n = E.n;  // the host checked rank <= RK
+  if (rk <= 0) return;  // uniform over the workgroup
+  extern __shared__ __align__(16) unsigned char smem_r[];
+  double *Vs = reinterpret_cast<double *>(smem_r);  // rk x n, reflector k at k * n
+  __shared__ double Gm[RK * RK], Tw[RK * RK];
+  for (int idx = threadIdx.x; idx < rk * n; idx += blockDim.x) Vs[idx] = E.V[idx];
+  if (threadIdx.x < RK * RK) Tw[threadIdx.x] = 0.0;
+  __syncthreads();
+  if (threadIdx.x < rk * rk) {  // Gram matrix V^T V (the strict upper part is used)
+    const int a = threadIdx.x % rk, b = threadIdx.x / rk;
+    double g = 0.0;
+    if (a < b)
+      for (int c = 0; c < n; ++c) g += Vs[a * n + c] * Vs[b * n + c];
+    Gm[a + b * RK] = g;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < rk; ++i) {
+      const double ti = E.tau[i];
+      for (int a = 0; a < i; ++a) {
+        double s = 0.0;
+        for (int b = a; b < i; ++b) s += Tw[a + b * RK] * Gm[b + i * RK];
+        Tw[a + i * RK] = -ti * s;
+      }
+      Tw[i + i * RK] = ti;
+    }
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  T *Xe = (T *)S.X + S.ent_off[blockIdx.y];
+  const int c1 = min(c0 + cols, nx);
+  if (n > 32) {  // a wave per column
+    for (int j = c0 + w; j < c1; j += 4) seg_apply_wave(Xe + (int64_t)j * S.xld, n, rk, Vs, Tw, lane);
+  } else {  // groups of G <= 32 lanes, one column each
+    int G = 1;
+    while (G < n) G *= 2;
+    const int gpw = 64 / G, g = lane / G, gl = lane % G;
+    for (int j = c0 + w * gpw + g; j < c1; j += 4 * gpw)  // uniform over each group
+      seg_apply_group(Xe + (int64_t)j * S.xld, n, rk, Vs, Tw, gl, G);
+  }
+}
+
+// Left application to every entity block when the largest entity fits the
+// registers (n <= 64 EPL), its reflectors the LDS and their count APPLY_T_RK
+// (bounded on the host by min(n_con, n)); false: the caller applies the
+// column kernel instead.
+hipError_t apply_T_rows(const SubDev *d_subs, const EntDev *d_ents, int nsub, int max_ng, int max_ent,
+                        int max_en, int max_rn, int max_rank, bool fp32, bool *done, hipStream_t s) {
+  *done = false;
+  if (!nsub || !max_ent) {
+    *done = true;
+    return hipSuccess;
+  }
+  const size_t lds = (size_t)std::max(max_rn, 1) * sizeof(double);
+  if (max_en > 64 * APPLY_T_EPL || max_rank > APPLY_T_RK || lds > 140 * 1024) return hipSuccess;
+  const int cols = 256, nx = max_ng + 1;
+  const dim3 grid((nx + cols - 1) / cols, max_ent, nsub);
+  hipError_t e = hipSuccess;
+  if (fp32) {
+    if (lds > 48 * 1024)
+      e = hipFuncSetAttribute((const void *)k_apply_T_rows<float>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL((k_apply_T_rows<float>), grid, dim3(256), lds, s, d_subs, d_ents, cols);
+  } else {
+    if (lds > 48 * 1024)
+      e = hipFuncSetAttribute((const void *)k_apply_T_rows<double>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                              (int)lds);
+    if (e == hipSuccess)
+      hipLaunchKernelGGL((k_apply_T_rows<double>), grid, dim3(256), lds, s, d_subs, d_ents, cols);
+  }
+  if (e != hipSuccess) return e;
+  e = hipGetLastError();
+  if (e == hipSuccess) *done = true;
+  return e;
+}
+
 // b0~ = T^T b0 (per local entity, reflectors in order H_0, H_1, ...).
 __global__ void k_transform_b0(const SubDev *subs, const EntDev *ents) {
   const SubDev S = subs[blockIdx.x];
