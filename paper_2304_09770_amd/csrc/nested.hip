@@ -14,9 +14,13 @@
 
 namespace vb {
 
-// W2 (both triangles) += D T D over the front's trailing block T (rows and
-// columns [e, e + m) of the front matrix, lower triangle read), D = diag(gamma,
-// 1, ..., 1), at the second-level positions map[0..m).  One thread per entry
+// W2 += D T D over the front's trailing block T (rows and columns [e, e + m)
+// of the front matrix, lower triangle read), D = diag(gamma, 1, ..., 1), at
+// the second-level positions map[0..m), into W2's lower triangle only (the
+// entry of a pair of positions goes to (max, min); the second level reads no
+// other: its LDL^T works on the lower triangle, and the pressure rotation that
+// precedes it reads the upper triangle only inside the sub-box constant
+// block, where a front adds its one diagonal entry).  One thread per entry
 // of the lower triangle's bounding square; a launch holds fronts of distinct
 // subdomains only, so no two threads add into the same entry.
 template <typename T>
@@ -32,8 +36,8 @@ __global__ __launch_bounds__(256) void k_front_scatter(const FrontJob *jobs) {
   const double v = (double)Wf[(int64_t)(J.e + a) + (int64_t)(J.e + b) * J.ldf] *
                    (a == 0 ? J.gamma : 1.0) * (b == 0 ? J.gamma : 1.0);
   const int64_t pa = J.map[a], pb = J.map[b];
-  W2[pa + pb * J.ld2] = (T)((double)W2[pa + pb * J.ld2] + v);
-  if (a != b) W2[pb + pa * J.ld2] = (T)((double)W2[pb + pa * J.ld2] + v);
+  const int64_t o = (pa >= pb) ? pa + pb * J.ld2 : pb + pa * J.ld2;
+  W2[o] = (T)((double)W2[o] + v);
 }
 
 hipError_t front_scatter(const FrontJob *d_jobs, int njobs, int max_m, bool fp32, hipStream_t s) {

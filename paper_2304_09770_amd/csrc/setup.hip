@@ -13,26 +13,29 @@ template <typename T> __device__ __forceinline__ T *Wp(const SubDev &S) { return
 
 // Scatter the local CSR (both triangles) and the right-hand side into the
 // dense bordered matrix [[K, r], [r^T, 0]] with the DoF order
-// [interior velocity | element pressures | interface | rhs].
+// [interior velocity | element pressures | interface | rhs].  One wave per
+// CSR row, the lanes over its nonzeros (all of a row's stores in flight).
 template <typename T>
-__global__ void k_densify(const SubDev *subs) {
+__global__ __launch_bounds__(256) void k_densify(const SubDev *subs) {
   const SubDev S = subs[blockIdx.y];
-  const int row = blockIdx.x * blockDim.x + threadIdx.x;
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), l = threadIdx.x & 63;
   if (row >= S.n_csr) return;
   T *W = Wp<T>(S);
   const int pr = S.pos[row];
-  for (int64_t q = S.indptr[row]; q < S.indptr[row + 1]; ++q) {
+  for (int64_t q = S.indptr[row] + l; q < S.indptr[row + 1]; q += 64) {
     const int pc = S.pos[S.indices[q]];
     W[(int64_t)pr + (int64_t)pc * S.ld] = (T)S.vals[q];
   }
-  const int last = S.N - 1;
-  W[(int64_t)pr + (int64_t)last * S.ld] = (T)S.rhs[row];
-  W[(int64_t)last + (int64_t)pr * S.ld] = (T)S.rhs[row];
+  if (l == 0) {
+    const int last = S.N - 1;
+    W[(int64_t)pr + (int64_t)last * S.ld] = (T)S.rhs[row];
+    W[(int64_t)last + (int64_t)pr * S.ld] = (T)S.rhs[row];
+  }
 }
 
 hipError_t densify(const SubDev *d_subs, int nsub, int max_rows, bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
-  dim3 g((max_rows + 255) / 256, nsub);
+  dim3 g((max_rows + 3) / 4, nsub);
   if (fp32)
     hipLaunchKernelGGL(k_densify<float>, g, dim3(256), 0, s, d_subs);
   else
@@ -673,26 +676,38 @@ hipError_t transform_vec(const EntDev *d_ents, int nent, double *x, int dir, hip
   return hipGetLastError();
 }
 
-// out[i + j*ldo] (+)= scale * in[ri[i] + ci[j]*ldi]
-__global__ void k_gather_blocks(const GatherJob *jobs) {
+// out[i + j*ldo] (+)= scale * in[ri[i] + ci[j]*ldi].  A workgroup takes a
+// 64 x 64 block, a lane a row, each wave 16 of the columns: all 16 source
+// loads are issued before the first store (clamped, unconditional addresses
+// for the rows and columns past the block's edge, which are not stored).
+__global__ __launch_bounds__(256) void k_gather_blocks(const GatherJob *jobs) {
+  constexpr int Q = 16;
   const GatherJob J = jobs[blockIdx.z];
+  if ((int)blockIdx.x * 64 >= J.m || (int)blockIdx.y * 64 >= J.n) return;  // uniform
   const int i = blockIdx.x * 64 + (threadIdx.x & 63);
-  const int j0 = blockIdx.y * 64;
-  if (i >= J.m) return;
-  const int ri = J.ri[i];
-  for (int jj = threadIdx.x >> 6; jj < 64; jj += blockDim.x >> 6) {
-    const int j = j0 + jj;
-    if (j >= J.n) break;
+  const int j0 = blockIdx.y * 64 + (threadIdx.x >> 6);
+  const bool row = i < J.m;
+  const int ri = J.ri[min(i, J.m - 1)];
+  double v[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = min(j0 + 4 * q, J.n - 1);
     const int64_t src = (int64_t)ri + (int64_t)J.ci[j] * J.ldi;
-    double v = J.in_f32 ? (double)((const float *)J.in)[src] : ((const double *)J.in)[src];
-    v *= J.scale;
+    v[q] = J.in_f32 ? (double)((const float *)J.in)[src] : ((const double *)J.in)[src];
+  }
+  if (!row) return;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int j = j0 + 4 * q;
+    if (j >= J.n) break;
+    const double x = v[q] * J.scale;
     const int64_t dst = (int64_t)i + (int64_t)j * J.ldo;
     if (J.out_f32) {
       float *o = (float *)J.out + dst;
-      *o = J.add ? (float)((double)*o + v) : (float)v;
+      *o = J.add ? (float)((double)*o + x) : (float)x;
     } else {
       double *o = (double *)J.out + dst;
-      *o = J.add ? *o + v : v;
+      *o = J.add ? *o + x : x;
     }
   }
 }
