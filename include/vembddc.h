@@ -137,11 +137,12 @@ typedef struct vb_options {
   double inner_tol;       /* VB_PREC_MIXED: the relative residual reduction each
                              inner PCG solve of the refinement aims at (on the
                              FP32 operators; the last step aims only at what the
-                             outer tolerance still needs).  0 = default 1e-3
-                             (each step then reduces the FP64 residual by about
-                             that much; looser values take more steps, tighter
-                             ones more iterations per step).  Otherwise in
-                             (0, 1).  See vb_refinement_history. */
+                             outer tolerance still needs); each step reduces
+                             the FP64 residual by about that much.  0 =
+                             default: 1e-3 for operators of 1e9 bytes or more
+                             (looser steps, fewer iterations in all), 1e-4 below
+                             (fewer steps: their fixed cost dominates).
+                             Otherwise in (0, 1).  See vb_refinement_history. */
 } vb_options;
 
 enum { VB_PCG_AUTO = 0, VB_PCG_GRAPH = 1, VB_PCG_PERSISTENT = 2 };

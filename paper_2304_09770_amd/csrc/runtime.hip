@@ -4200,7 +4200,13 @@ static int mixed_solve(vb_ctx *ctx, double *x_dev, vb_solve_info *info) {
   const int nE = (int)ctx->ents.size();
   const int P = (int)ctx->probs.size(), G = ctx->seg_G;
   const int max_outer = 30;
-  const double inner_floor = ctx->opt.inner_tol > 0.0 ? ctx->opt.inner_tol : 1e-3;
+  // default inner tolerance: on small operators (below 1e9 bytes, where the
+  // iterations run as one persistent launch) a refinement step's fixed cost
+  // (condensation, interior correction, host synchronisations) outweighs a
+  // few inner iterations, so fewer and tighter steps (1e-4); on large ones
+  // looser steps take fewer iterations in all (1e-3)
+  const double inner_floor =
+      ctx->opt.inner_tol > 0.0 ? ctx->opt.inner_tol : (ctx->schur_bytes < 1e9 ? 1e-4 : 1e-3);
   ctx->ref_rel.assign(ctx->probs.size(), {});
   ctx->ref_inner.assign(ctx->probs.size(), {});
   CHK(hipEventRecord(ctx->ev0, st));
