@@ -761,10 +761,14 @@ __device__ __forceinline__ void load4(const double *p, double v[4]) {
 // i = [i0, i0+b): z_i = inv(L_ii)^T y_i (every workgroup recomputes it from
 // the cached inverse, staged in LDS; workgroup 0 stores it), then
 // y_k -= L[i-block, k]^T z_i for the columns k < i0 of this workgroup's range
-// of 256.  The block rows of a column are contiguous in the column-major
+// of RS_COLS.  The block rows of a column are contiguous in the column-major
 // factor: 16 lanes cover them with 16-byte loads (4 rows each, z in
-// registers) and reduce with 4 shuffles, so a wave finishes 4 columns per
-// step.
+// registers) and reduce with 4 shuffles; each group of 16 lanes keeps four
+// columns in flight (loads issued together, clamped to a column of the
+// range, the reductions interleaved), so a wave finishes 16 columns per step.
+// (1,024 columns per workgroup amortised the z preamble better but left the
+// late steps of the largest matrices with too few workgroups: slower.)
+constexpr int RS_COLS = 256;
 template <typename T>
 __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const T *invL,
                                                       const int64_t *invoff, double *y,
@@ -772,7 +776,7 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
                                                       int nb) {
   const SubDev S = subs[blockIdx.y];
   if (i0 >= S.e) return;
-  const int k0 = blockIdx.x * 256;
+  const int k0 = blockIdx.x * RS_COLS;
   if (k0 > 0 && k0 >= i0) return;
   const int b = min(nb, S.e - i0);
   double *ys = y + yoff[blockIdx.y];
@@ -796,23 +800,33 @@ __global__ __launch_bounds__(256) void k_recover_step(const SubDev *subs, const 
   for (int t = 0; t < 4; ++t) zq[t] = (4 * q + t < b) ? zi[4 * q + t] : 0.0;
   const bool full = 4 * q + 3 < b;
   const T *W = Wp<T>(S) + i0 + 4 * q;
-  for (int kk = 4 * w + g; kk < 256; kk += 16) {
-    const int k = k0 + kk;
-    if (k >= i0) break;  // uniform over the 16 lanes of a column
-    const T *col = W + (int64_t)k * S.ld;
-    double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (full) {
-      load4(col, v);
-    } else {
-      for (int t = 0; t < 4; ++t)
-        if (4 * q + t < b) v[t] = (double)col[t];
+  const int kend = min(k0 + RS_COLS, i0);  // columns [k0, kend) of this workgroup
+  // group (w, g) takes columns k0 + 16 it + 4 w + g, four values of it at a time
+  for (int it = 0; k0 + 16 * it < kend; it += 4) {
+    double s[4];
+    int kk[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      kk[u] = k0 + 16 * (it + u) + 4 * w + g;
+      const T *col = W + (int64_t)min(kk[u], kend - 1) * S.ld;
+      double v[4] = {0.0, 0.0, 0.0, 0.0};
+      if (full) {
+        load4(col, v);
+      } else {
+        for (int t = 0; t < 4; ++t)
+          if (4 * q + t < b) v[t] = (double)col[t];
+      }
+      s[u] = v[0] * zq[0] + v[1] * zq[1] + v[2] * zq[2] + v[3] * zq[3];
     }
-    double s = v[0] * zq[0] + v[1] * zq[1] + v[2] * zq[2] + v[3] * zq[3];
-    s += __shfl_xor(s, 1, 16);
-    s += __shfl_xor(s, 2, 16);
-    s += __shfl_xor(s, 4, 16);
-    s += __shfl_xor(s, 8, 16);
-    if (q == 0) ys[k] -= s;
+#pragma unroll
+    for (int m = 1; m < 16; m *= 2)
+#pragma unroll
+      for (int u = 0; u < 4; ++u) s[u] += __shfl_xor(s[u], m, 16);
+    if (q == 0) {
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (kk[u] < kend) ys[kk[u]] -= s[u];
+    }
   }
 }
 
@@ -821,7 +835,7 @@ hipError_t recover_backsolve(const SubDev *d_subs, const void *invL, const int64
                              bool fp32, hipStream_t s) {
   if (!nsub) return hipSuccess;
   if (nb != 32 && nb != 64) return hipErrorInvalidValue;
-  const int gx = i0 > 0 ? (i0 + 255) / 256 : 1;
+  const int gx = i0 > 0 ? (i0 + RS_COLS - 1) / RS_COLS : 1;
   if (fp32)
     hipLaunchKernelGGL(k_recover_step<float>, dim3(gx, nsub), dim3(256), 0, s, d_subs,
                        (const float *)invL, invoff, y, z, yoff, i0, nb);
