@@ -207,9 +207,6 @@ hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *i
 // back-substitution right-hand side: y2_j = d_j z_j - sum_l L[e+1+l, j] dx[gid_l]
 hipError_t back_init(const SubDev *d_subs, const double *z, double *y2, const int64_t *yoff, int nsub,
                      int max_e, hipStream_t s);
-hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
-                    const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s);
-
 // ---- adaptive face eigenproblems (dense symmetric eigen-solver pieces)
 struct EigJob {
   double *A;      // n x n full symmetric (column-major); reflectors stored below the subdiagonal

@@ -976,28 +976,9 @@ hipError_t forward_step(const SubDev *d_subs, const void *invL, const int64_t *i
   return hipGetLastError();
 }
 
-// y2_j = d_j z_j - sum_l L[e+1+l, j] dx[gid_l] over the eliminated columns:
-// the right-hand side of L_II^T du_I = y2 (the interior correction).
-template <typename T>
-__global__ void k_back_rhs(const SubDev *subs, const double *z, const double *dx, double *y2,
-                           const int64_t *yoff) {
-  const SubDev S = subs[blockIdx.y];
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int j = blockIdx.x * (blockDim.x >> 6) + w;
-  if (j >= S.e) return;
-  const auto col = gptr(Wp<T>(S) + (int64_t)j * S.ld + (S.e + 1));
-  double s = 0.0;
-  if (dx)
-    for (int r = l; r < S.ng; r += 64) s += (double)col[r] * dx[S.gidl[r]];
-  s = warp_sum(s);
-  if (l == 0) {
-    const double d = (j < S.nv) ? 1.0 : -1.0;
-    y2[yoff[blockIdx.y] + j] = d * z[yoff[blockIdx.y] + j] - s;
-  }
-}
-
 // y2_j = d_j z_j over the eliminated columns (the interior correction's
-// right-hand side before the interface term, which a GEMV adds).
+// right-hand side before the interface term -L_GammaI^T dx, which a GEMV over
+// the factor's interface rows adds).
 __global__ void k_back_init(const SubDev *subs, const double *z, double *y2, const int64_t *yoff) {
   const SubDev S = subs[blockIdx.y];
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
@@ -1010,17 +991,6 @@ hipError_t back_init(const SubDev *d_subs, const double *z, double *y2, const in
                      int max_e, hipStream_t s) {
   if (!nsub || max_e <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_back_init, dim3((max_e + 255) / 256, nsub), dim3(256), 0, s, d_subs, z, y2, yoff);
-  return hipGetLastError();
-}
-
-hipError_t back_rhs(const SubDev *d_subs, const double *z, const double *dx, double *y2,
-                    const int64_t *yoff, int nsub, int max_e, bool fp32, hipStream_t s) {
-  if (!nsub) return hipSuccess;
-  dim3 g((max_e + 3) / 4, nsub);
-  if (fp32)
-    hipLaunchKernelGGL(k_back_rhs<float>, g, dim3(256), 0, s, d_subs, z, dx, y2, yoff);
-  else
-    hipLaunchKernelGGL(k_back_rhs<double>, g, dim3(256), 0, s, d_subs, z, dx, y2, yoff);
   return hipGetLastError();
 }
 
