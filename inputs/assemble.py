@@ -3,7 +3,13 @@
 Global velocity DoFs: 3 per vertex, 3(k-1) per edge, 3*dim P_{k-2}(f) per
 face, then the element-internal D4 and D5 moments; pressures: dim P_{k-1}
 per element (Sec. 3, Q_h).  Dirichlet DoFs (vertices, edges and faces on the
-boundary) are eliminated into the right-hand side.
+boundary) are eliminated into the right-hand side.  By default the whole
+boundary is no-slip; `neumann_sides` lists sides of the cube (0..5: x = 0,
+x = 1, y = 0, y = 1, z = 0, z = 1) that carry the natural condition with zero
+traction instead (Sec. 7 solves with Neumann conditions on two faces and
+no-slip on the other four): the entities inside such a side stay free, those
+on its boundary shared with a no-slip side stay Dirichlet.  With a Neumann
+side the constant pressure is no longer a kernel of the problem.
 
 Reduced scheme (the remark closing Sec. 3.2): the constraint rows of the
 non-constant pressures force D5(u_h) = 0, and those pressures only appear in
@@ -17,6 +23,30 @@ import scipy.sparse as sp
 from .vem import DofLayout, element_matrices, interpolate
 from .poly import dim3, eval3
 from .quadrature import tet_rule
+
+
+def dirichlet_entities(m, neumann_sides=()):
+    """Vertices, edges and faces of the cube mesh lying on a no-slip side
+    (side 2a + t: x_a = 0 for t = 0, x_a = n for t = 1): a vertex on any such
+    side, an edge with both endpoints on one, a boundary face on one."""
+    n = m.n
+    sides = [s for s in range(6) if s not in tuple(neumann_sides)]
+
+    def on(idx, s):
+        a, t = divmod(s, 2)
+        return idx[..., a] == (0 if t == 0 else n)
+
+    vb = np.zeros(m.nV, bool)
+    eb = np.zeros(m.nE, bool)
+    fb = np.zeros(m.nF, bool)
+    ev = m.edge_verts
+    for s in sides:
+        vb |= on(m.vidx, s)
+        eb |= on(m.vidx[ev[:, 0]], s) & on(m.vidx[ev[:, 1]], s)
+        a, t = divmod(s, 2)
+        sel = m.face_axis == a
+        fb[sel] |= m.face_start[sel, a] == (0 if t == 0 else n)
+    return vb, eb, fb
 
 
 def u_curl(X):
@@ -88,8 +118,12 @@ class Problem:
     """
 
     def __init__(self, mesh, k, nu=1.0, force=None, uD=None, divD=None, keep_full=False,
-                 chunk=None, workers=None, progress=None, element_data=None):
+                 chunk=None, workers=None, progress=None, element_data=None, neumann_sides=()):
         self.mesh, self.k = mesh, k
+        self.neumann_sides = tuple(sorted(set(int(s) for s in neumann_sides)))
+        assert all(0 <= s < 6 for s in self.neumann_sides) and len(self.neumann_sides) < 6
+        # the constant pressure is a kernel only with no-slip on the whole boundary
+        self.pressure_kernel = len(self.neumann_sides) == 0
         L = DofLayout(k)
         self.L = L
         nuK = np.asarray(nu, float) if np.ndim(nu) else np.full(mesh.nK, float(nu))
@@ -123,12 +157,13 @@ class Problem:
             gm[:, L.off4 + i] = self.offI + L.nI * np.arange(m.nK) + i
         self.gmap = gm
         dir_mask = np.zeros(self.Nv, bool)
+        vb, eb, fb = dirichlet_entities(m, self.neumann_sides)
         for c in range(3):
-            dir_mask[3 * np.nonzero(m.vert_bnd)[0] + c] = True
+            dir_mask[3 * np.nonzero(vb)[0] + c] = True
         for j in range(3 * (k - 1)):
-            dir_mask[self.offE + 3 * (k - 1) * np.nonzero(m.edge_bnd)[0] + j] = True
+            dir_mask[self.offE + 3 * (k - 1) * np.nonzero(eb)[0] + j] = True
         for j in range(3 * L.nf2):
-            dir_mask[self.offF + 3 * L.nf2 * np.nonzero(m.face_bnd)[0] + j] = True
+            dir_mask[self.offF + 3 * L.nf2 * np.nonzero(fb)[0] + j] = True
         self.dir_mask = dir_mask
         # ---------------- reduced numbering: velocity without D5, element constants
         keep_local = np.ones(L.N, bool)
@@ -243,26 +278,30 @@ class Problem:
         return self.mesh.elem_vol.copy()
 
     def solve_reduced_direct(self):
-        """Sparse direct solve of the reduced system with the mean-zero
-        pressure constraint as a Lagrange multiplier.  Returns the full
-        reduced vector (Dirichlet values included)."""
+        """Sparse direct solve of the reduced system, with the mean-zero
+        pressure constraint as a Lagrange multiplier when the constant
+        pressure is a kernel (no-slip everywhere).  Returns the full reduced
+        vector (Dirichlet values included)."""
         K, g, free = self.reduced_system()
         nfree = len(free)
-        w = np.zeros(nfree)
-        pf = free >= self.Nvr
-        w[pf] = self.mesh.elem_vol[free[pf] - self.Nvr]
-        Kb = sp.bmat([[K, sp.csr_matrix(w[:, None])], [sp.csr_matrix(w[None, :]), None]]).tocsc()
-        rhs = np.concatenate([g, [0.0]])
         from scipy.sparse.linalg import spsolve
-        x = spsolve(Kb, rhs)
+        if self.pressure_kernel:
+            w = np.zeros(nfree)
+            pf = free >= self.Nvr
+            w[pf] = self.mesh.elem_vol[free[pf] - self.Nvr]
+            Kb = sp.bmat([[K, sp.csr_matrix(w[:, None])], [sp.csr_matrix(w[None, :]), None]]).tocsc()
+            x = spsolve(Kb, np.concatenate([g, [0.0]]))
+        else:
+            x = spsolve(K.tocsc(), g)
         out = self.uD_red.copy()
         out[free] = x[:nfree]
         return out
 
     def full_system_direct(self):
         """Solve the unreduced system (all velocity DoFs incl. D5 and all
-        P_{k-1} pressures), mean-zero pressure by a multiplier.  Small
-        meshes only (requires keep_full).  Returns (u full, p full)."""
+        P_{k-1} pressures), mean-zero pressure by a multiplier when the
+        constant pressure is a kernel.  Small meshes only (requires
+        keep_full).  Returns (u full, p full)."""
         from scipy.sparse.linalg import spsolve
         m, L = self.mesh, self.L
         A, B, F = self.full["A"], self.full["B"], self.full["F"]
@@ -287,10 +326,15 @@ class Problem:
         P, W = element_quadrature(m, np.arange(m.nK), 2 * self.k)
         Mq = eval3((P - xK[:, None]) / hK[:, None, None], self.k - 1)
         wp = np.einsum("eq,eqa->ea", W, Mq).ravel()
-        Kf = sp.bmat([[Ag[free][:, free], Bg[:, free].T, None],
-                      [Bg[:, free], None, sp.csr_matrix(wp[:, None])],
-                      [None, sp.csr_matrix(wp[None, :]), None]]).tocsc()
-        rhs = np.concatenate([rhs_u[free], rhs_p, [0.0]])
+        if self.pressure_kernel:
+            Kf = sp.bmat([[Ag[free][:, free], Bg[:, free].T, None],
+                          [Bg[:, free], None, sp.csr_matrix(wp[:, None])],
+                          [None, sp.csr_matrix(wp[None, :]), None]]).tocsc()
+            rhs = np.concatenate([rhs_u[free], rhs_p, [0.0]])
+        else:
+            Kf = sp.bmat([[Ag[free][:, free], Bg[:, free].T],
+                          [Bg[:, free], sp.csr_matrix((self.Np, self.Np))]]).tocsc()
+            rhs = np.concatenate([rhs_u[free], rhs_p])
         x = spsolve(Kf, rhs)
         u = self.uD.copy()
         u[free] = x[: len(free)]

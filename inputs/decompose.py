@@ -117,6 +117,12 @@ class Decomposition:
     # ---------------------------------------------------------------------
     def _axis_pos_vertex(self, a, i):
         c = self.cuts[a]
+        # a Neumann side of the cube is not a cut: DoFs on it belong to the
+        # open faces and edges of the subdomains they touch
+        if i == c[0] and 2 * a in self.pb.neumann_sides:
+            return ("seg", 0)
+        if i == c[-1] and 2 * a + 1 in self.pb.neumann_sides:
+            return ("seg", len(c) - 2)
         j = np.searchsorted(c, i)
         if j < len(c) and c[j] == i:
             return ("cut", int(j))
@@ -350,4 +356,5 @@ class Decomposition:
         for e in range(len(self.ent_dofs)):
             ents.append({"kind": int(self.ent_kind[e]), "gids": self.ent_dofs[e].astype(np.int64),
                          "con": np.ascontiguousarray(self.ent_con[e], dtype=np.float64)})
-        return {"n_iface": int(self.n_iface), "subs": subs, "ents": ents}
+        return {"n_iface": int(self.n_iface), "subs": subs, "ents": ents,
+                "pressure_kernel": bool(self.pb.pressure_kernel)}

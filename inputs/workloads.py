@@ -20,6 +20,9 @@ eliminated columns per subdomain), t8k3 (8^3, k=3), t6k4 (6^3, k=4);
 adaptive cases: t6f (6^3 jittered, 3x3x3: a floating centre subdomain),
 t8f (8^3 jittered, 4x4x4: faces between two floating subdomains),
 t12s (12^3, 3x3x3, 4 sinkers of radius 0.25 with nu=1e4).
+With the paper's boundary conditions (zero-traction Neumann on the sides
+x = 0 and x = 1, no-slip on the other four; no constant-pressure kernel):
+t8n (8^3 jittered, 2x2x2), t12n (12^3 jittered, 3x3x3).
 The paper's optimality tables (32 subdomains as 4x4x2 boxes, minimal
 constraints): deg2, deg3, deg4 (8^3, k = 2, 3, 4: the degree test) and
 mesh16, mesh20, mesh24, mesh28, mesh32 (n^3, k = 2: the mesh test).
@@ -79,6 +82,8 @@ RECIPES = {
     "t16s": dict(n=16, jitter=0.0, k=2, parts=(4, 4, 4), cons=FULL, sinkers=True),
     # C5's shape at 12^3 per problem (a family on one jittered mesh, nu per problem)
     "c5s": dict(n=12, jitter=0.15, k=3, parts=(3, 3, 3), cons=FULL, nu_per_sub=True),
+    "t8n": dict(n=8, jitter=0.15, k=2, parts=(2, 2, 2), cons=FULL, neumann=(0, 1)),
+    "t12n": dict(n=12, jitter=0.15, k=2, parts=(3, 3, 3), cons=FULL, neumann=(0, 1)),
 }
 for _k in (2, 3, 4):
     RECIPES["deg%d" % _k] = dict(n=8, jitter=0.0, k=_k, parts=(4, 4, 2), cons=MIN)
@@ -102,7 +107,8 @@ def make_workload(name, seed=0, workers=None, progress=None, **over):
                               seed=seed)
     if r.get("nu_per_sub"):
         nu = subdomain_viscosity(mesh, cuts, seed)
-    pb = Problem(mesh, r["k"], nu, workers=workers, progress=progress)
+    pb = Problem(mesh, r["k"], nu, workers=workers, progress=progress,
+                 neumann_sides=r.get("neumann", ()))
     if progress:
         progress("element matrices done")
     dec = Decomposition(pb, cuts, r["cons"])
@@ -175,7 +181,8 @@ def scaled_family(name, seeds, element_data=None, workers=None, mesh_seed=0, bas
 def save_workload(path, wl):
     """Store a workload as one .npz of plain arrays (no pickles)."""
     arrs = {"n_iface": np.array([wl["n_iface"]]), "nsub": np.array([len(wl["subs"])]),
-            "nent": np.array([len(wl["ents"])])}
+            "nent": np.array([len(wl["ents"])]),
+            "pressure_kernel": np.array([int(wl.get("pressure_kernel", True))])}
     for i, sd in enumerate(wl["subs"]):
         for k, v in sd.items():
             arrs["s%d_%s" % (i, k)] = v
@@ -197,7 +204,8 @@ def load_workload(path):
     for e in range(int(z["nent"][0])):
         ents.append({"kind": int(z["e%d_kind" % e][0]), "gids": z["e%d_gids" % e],
                      "con": z["e%d_con" % e]})
-    return {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents}
+    pk = bool(z["pressure_kernel"][0]) if "pressure_kernel" in z else True
+    return {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents, "pressure_kernel": pk}
 
 
 def mlp_init_params(F, H, seed=0):

@@ -27,6 +27,13 @@ Steps, in the paper's order:
   Neumann solves and a coarse saddle problem in the primal variables and
   p0; with no-slip boundaries the coarse problem inherits the constant-p0
   kernel and is bordered with the constraint sum |Omega_i| p0_i = 0.
+
+The condensation assumes what no-slip boundaries give: a subdomain's
+constant pressure tests only the fluxes of its interface DoFs (the fluxes of
+its other DoFs cancel between its elements).  A subdomain touching a
+Neumann side of the domain (wl["pressure_kernel"] false) breaks that: the
+DoFs on the Neumann side carry flux too, so p0 couples to its interior
+problem.  Such workloads are refused.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -108,6 +115,11 @@ class OracleBDDC:
     def __init__(self, wl, scaling="deluxe", adaptive_theta=0.0, svd_tol=1e-10,
                  adaptive_edges=False, dense_local=False):
         self.wl = wl
+        self.pressure_kernel = bool(wl.get("pressure_kernel", True))
+        if not self.pressure_kernel:
+            raise NotImplementedError(
+                "workload with Neumann sides: the condensation keeps each subdomain's constant "
+                "pressure coupled only through its interface fluxes")
         self.nG = wl["n_iface"]
         self.loc = [LocalSchur(sd, dense=dense_local) for sd in wl["subs"]]
         self.N = len(self.loc)
@@ -202,7 +214,8 @@ class OracleBDDC:
         cidx = -np.ones(self.nG, np.int64)
         cidx[gprim] = np.arange(self.nc)
         self.cidx = cidx
-        Kc = np.zeros((self.nc + self.N + 1, self.nc + self.N + 1))
+        self.ncb = self.nc + self.N + (1 if self.pressure_kernel else 0)
+        Kc = np.zeros((self.ncb, self.ncb))
         for i, L in enumerate(self.loc):
             P = np.nonzero(L.prim)[0]
             Dl = np.nonzero(~L.prim)[0]
@@ -218,9 +231,10 @@ class OracleBDDC:
             Kc[self.nc + i, c] += L.B0t[P]
             Kc[c, self.nc + i] += L.B0t[P]
             L.B0_dual_norm = np.abs(L.B0t[Dl]).max() if len(Dl) else 0.0
-        vol = np.array([L.vol for L in self.loc])
-        Kc[-1, self.nc: self.nc + self.N] = vol
-        Kc[self.nc: self.nc + self.N, -1] = vol
+        if self.pressure_kernel:
+            vol = np.array([L.vol for L in self.loc])
+            Kc[-1, self.nc: self.nc + self.N] = vol
+            Kc[self.nc: self.nc + self.N, -1] = vol
         self.Kc = Kc
         self.Kc_lu = sla.lu_factor(Kc)
 
@@ -247,7 +261,7 @@ class OracleBDDC:
         """z = M^-1 r (eq. BDDCprec) in original coordinates."""
         rt = np.concatenate([self.T.T @ r[: self.nG], r[self.nG:]])
         # restriction: primal and p0 pass through, duals scaled
-        rc = np.zeros(self.nc + self.N + 1)
+        rc = np.zeros(self.ncb)
         gpr = np.nonzero(self.is_primal)[0]
         rc[self.cidx[gpr]] = rt[gpr]
         rc[self.nc: self.nc + self.N] = rt[self.nG:]

@@ -223,7 +223,12 @@ def vb_assemble(ctx, workload, nested=True):
     pweight, rhs[, part])], ents=[dict(kind, gids, con)]) (numpy arrays).
     nested: pass the sub-box labels `part` when the workload has them (the
     two-level local factorisation); False: one dense factorisation per
-    subdomain."""
+    subdomain.  A workload with Neumann sides (pressure_kernel false) is
+    refused: the library condenses each subdomain's constant pressure as
+    coupled only through its interface fluxes, and borders the coarse
+    problem against the constant-pressure kernel of no-slip boundaries."""
+    if not workload.get("pressure_kernel", True):
+        raise NotImplementedError("vb_assemble: workloads with Neumann sides are not supported")
     keep = []
     subs = (vb_subdomain * len(workload["subs"]))()
     for i, sd in enumerate(workload["subs"]):

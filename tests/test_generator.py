@@ -336,3 +336,67 @@ def test_scaled_family_equals_per_problem_decomposition():
             scale = np.abs(sb["data"]).max()
             assert np.abs(sa["data"] - sb["data"]).max() <= 1e-13 * scale
             assert np.abs(sa["rhs"] - sb["rhs"]).max() <= 1e-13 * np.abs(sb["rhs"]).max()
+
+
+def test_neumann_sides_free_their_open_interior():
+    """The paper's boundary conditions (Sec. 7: Neumann on two faces of the
+    cube, no-slip on the others): with the sides x = 0 and x = 1 natural, a
+    vertex is Dirichlet exactly when one of its other coordinates is on the
+    boundary; the default (no Neumann side) is the whole boundary."""
+    m = CubeMesh(4, jitter=0.0)
+    n = m.n
+    from inputs.assemble import dirichlet_entities
+    vb0, eb0, fb0 = dirichlet_entities(m)
+    assert np.array_equal(vb0, m.vert_bnd) and np.array_equal(eb0, m.edge_bnd)
+    assert np.array_equal(fb0, m.face_bnd)
+    vb, eb, fb = dirichlet_entities(m, (0, 1))
+    yz = m.vidx[:, 1:]
+    assert np.array_equal(vb, np.any((yz == 0) | (yz == n), axis=1))
+    # faces: the boundary faces with a y or z normal only
+    assert np.array_equal(fb, m.face_bnd & (m.face_axis != 0))
+    # edges: both endpoints on one no-slip side
+    ev = m.edge_verts
+    both = np.zeros(m.nE, bool)
+    for a in (1, 2):
+        for v in (0, n):
+            both |= (m.vidx[ev[:, 0], a] == v) & (m.vidx[ev[:, 1], a] == v)
+    assert np.array_equal(eb, both)
+
+
+def test_neumann_problem_has_no_pressure_kernel():
+    """With two Neumann sides the reduced system is nonsingular without the
+    mean-pressure constraint (the constant pressure is not in its kernel,
+    unlike the no-slip problem), and the direct solve satisfies it; the
+    workload carries the flag through decomposition and storage, and the
+    oracle and the library binding refuse it (their condensation assumes
+    the no-slip structure)."""
+    m = CubeMesh(4, jitter=0.15, seed=2)
+    pb = Problem(m, 2, neumann_sides=(0, 1))
+    assert not pb.pressure_kernel
+    K, g, free = pb.reduced_system()
+    ones_p = (free >= pb.Nvr).astype(float)
+    assert np.linalg.norm(K @ ones_p) > 1e-3 * np.sqrt(ones_p.sum())
+    pb0 = Problem(m, 2)
+    K0, g0, free0 = pb0.reduced_system()
+    ones0 = (free0 >= pb0.Nvr).astype(float)
+    assert np.linalg.norm(K0 @ ones0) < 1e-10 * np.sqrt(ones0.sum())
+    x = pb.solve_reduced_direct()
+    assert np.linalg.norm(K @ x[free] - g) <= 1e-10 * np.linalg.norm(g)
+    dec = Decomposition(pb, regular_cuts(4, (2, 2, 1)))
+    wl = dec.workload()
+    assert wl["pressure_kernel"] is False
+    # interface DoFs on the Neumann side belong to the open faces and edges of
+    # the cut planes (x = 0 is not a cut)
+    assert all(key[1][0] not in (("cut", 0), ("cut", 2)) for key in dec.ent_key)
+    import tempfile
+    from inputs.workloads import save_workload, load_workload
+    with tempfile.TemporaryDirectory() as d:
+        path = os.path.join(d, "wl.npz")
+        save_workload(path, wl)
+        assert load_workload(path)["pressure_kernel"] is False
+    from oracle.bddc import OracleBDDC
+    with pytest.raises(NotImplementedError):
+        OracleBDDC(wl)
+    from paper_2304_09770_amd import binding
+    with pytest.raises(NotImplementedError):
+        binding.vb_assemble(None, wl)
