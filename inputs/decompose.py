@@ -298,8 +298,24 @@ class Decomposition:
             sd = Subdomain()
             sd.dofs, sd.kind, sd.gid, sd.pweight, sd.K, sd.rhs, sd.elems = d, kind, g.astype(np.int64), pw, K, rhs, el
             sd.part = self._sub_boxes(s, el, lr, kind)
+            sd.has_p0 = self._sub_has_p0(s)
             self.subs.append(sd)
         self.sub_vol = np.array([pb.mesh.elem_vol[sd.elems].sum() for sd in self.subs])
+
+    def _sub_has_p0(self, s):
+        """Whether subdomain s keeps its constant pressure p0 as a global
+        unknown: true unless one of its sides lies on a Neumann side of the
+        cube.  There the open boundary DoFs carry flux, so the constant
+        pressure couples to the subdomain's own interior problem and is
+        eliminated with the other element pressures."""
+        px, py, pz = self.parts
+        seg = (s % px, (s // px) % py, s // (px * py))
+        for a in range(3):
+            if seg[a] == 0 and 2 * a in self.pb.neumann_sides:
+                return False
+            if seg[a] == self.parts[a] - 1 and 2 * a + 1 in self.pb.neumann_sides:
+                return False
+        return True
 
     def _sub_boxes(self, s, el, lr, kind):
         """Geometric one-level nested dissection of subdomain s: its box of
@@ -333,13 +349,14 @@ class Decomposition:
 
     # ---------------------------------------------------------------------
     def interface_solution(self, xred):
-        """(u_Gamma by interface id, p0 per subdomain) of a reduced-system
-        vector: p0_i is the volume-weighted mean pressure of subdomain i."""
+        """(u_Gamma by interface id, p0 per subdomain that keeps one) of a
+        reduced-system vector: p0_i is the volume-weighted mean pressure of
+        subdomain i."""
         pb = self.pb
         uG = xred[self.iface_red]
         pK = xred[pb.Nvr:]
         p0 = np.array([np.dot(pb.mesh.elem_vol[sd.elems], pK[sd.elems]) / self.sub_vol[i]
-                       for i, sd in enumerate(self.subs)])
+                       for i, sd in enumerate(self.subs) if sd.has_p0])
         return uG, p0
 
     # ---------------------------------------------------------------------
@@ -357,4 +374,5 @@ class Decomposition:
             ents.append({"kind": int(self.ent_kind[e]), "gids": self.ent_dofs[e].astype(np.int64),
                          "con": np.ascontiguousarray(self.ent_con[e], dtype=np.float64)})
         return {"n_iface": int(self.n_iface), "subs": subs, "ents": ents,
-                "pressure_kernel": bool(self.pb.pressure_kernel)}
+                "pressure_kernel": bool(self.pb.pressure_kernel),
+                "has_p0": np.array([int(sd.has_p0) for sd in self.subs], np.int32)}

@@ -183,6 +183,8 @@ def save_workload(path, wl):
     arrs = {"n_iface": np.array([wl["n_iface"]]), "nsub": np.array([len(wl["subs"])]),
             "nent": np.array([len(wl["ents"])]),
             "pressure_kernel": np.array([int(wl.get("pressure_kernel", True))])}
+    if "has_p0" in wl:
+        arrs["has_p0"] = np.asarray(wl["has_p0"], np.int32)
     for i, sd in enumerate(wl["subs"]):
         for k, v in sd.items():
             arrs["s%d_%s" % (i, k)] = v
@@ -205,7 +207,10 @@ def load_workload(path):
         ents.append({"kind": int(z["e%d_kind" % e][0]), "gids": z["e%d_gids" % e],
                      "con": z["e%d_con" % e]})
     pk = bool(z["pressure_kernel"][0]) if "pressure_kernel" in z else True
-    return {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents, "pressure_kernel": pk}
+    wl = {"n_iface": int(z["n_iface"][0]), "subs": subs, "ents": ents, "pressure_kernel": pk}
+    if "has_p0" in z:
+        wl["has_p0"] = np.array(z["has_p0"], np.int32)
+    return wl
 
 
 def mlp_init_params(F, H, seed=0):

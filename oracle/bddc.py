@@ -28,12 +28,16 @@ Steps, in the paper's order:
   p0; with no-slip boundaries the coarse problem inherits the constant-p0
   kernel and is bordered with the constraint sum |Omega_i| p0_i = 0.
 
-The condensation assumes what no-slip boundaries give: a subdomain's
-constant pressure tests only the fluxes of its interface DoFs (the fluxes of
-its other DoFs cancel between its elements).  A subdomain touching a
-Neumann side of the domain (wl["pressure_kernel"] false) breaks that: the
-DoFs on the Neumann side carry flux too, so p0 couples to its interior
-problem.  Such workloads are refused.
+Neumann sides (Sec. 7; wl["pressure_kernel"] false).  The split Q_I + Q_0
+rests on a subdomain's constant pressure testing only the fluxes of its
+interface DoFs, which holds when the rest of its boundary is no-slip (the
+fluxes of its other DoFs cancel between its elements).  A subdomain with a
+side on a Neumann face of the domain has open boundary DoFs whose flux the
+constant pressure also tests, so there p0 belongs to the subdomain's own
+Dirichlet problem: it keeps all its element pressures local and adds no p0
+to the interface problem (wl["has_p0"][i] = 0).  The coarse problem then
+has no constant-pressure kernel and no border row.  This reading is the
+oracle's own; the paper does not spell the split out for Neumann sides.
 """
 import numpy as np
 import scipy.sparse as sp
@@ -64,8 +68,9 @@ class LocalSchur:
     problems.
     """
 
-    def __init__(self, sd, condense=True, dense=False):
+    def __init__(self, sd, condense=True, dense=False, has_p0=True):
         n = len(sd["kind"])
+        self.has_p0 = bool(has_p0)
         K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(n, n))
         kind = sd["kind"]
         self.iv = np.nonzero(kind == KIND_INTERIOR)[0]
@@ -80,13 +85,18 @@ class LocalSchur:
         A_IG = K[self.iv][:, self.ig]
         Bp_G = K[self.ip][:, self.ig]
         self.A_GG = K[self.ig][:, self.ig].toarray()
-        # K_II' = [[A, Bp^T, 0], [Bp, 0, w], [0, w^T, 0]]: pressures in Q_I
-        Kii = sp.bmat([[A_II, Bp_I.T, None],
-                       [Bp_I, None, sp.csr_matrix(w[:, None])],
-                       [None, sp.csr_matrix(w[None, :]), None]]).tocsc()
+        if self.has_p0:
+            # K_II' = [[A, Bp^T, 0], [Bp, 0, w], [0, w^T, 0]]: pressures in Q_I
+            Kii = sp.bmat([[A_II, Bp_I.T, None],
+                           [Bp_I, None, sp.csr_matrix(w[:, None])],
+                           [None, sp.csr_matrix(w[None, :]), None]]).tocsc()
+            C = sp.vstack([A_IG, Bp_G, sp.csr_matrix((1, len(self.ig)))]).toarray()
+        else:
+            # all element pressures stay local: K_II = [[A, Bp^T], [Bp, 0]]
+            Kii = sp.bmat([[A_II, Bp_I.T], [Bp_I, None]]).tocsc()
+            C = sp.vstack([A_IG, Bp_G]).toarray()
         self.lu = _DenseLU(Kii) if dense else splu(Kii)
         self.nv, self.npr = nv, npr
-        C = sp.vstack([A_IG, Bp_G, sp.csr_matrix((1, len(self.ig)))]).toarray()
         self.C = C
         rhs = sd["rhs"]
         self.f_I = rhs[self.iv]
@@ -95,20 +105,24 @@ class LocalSchur:
         if condense:
             X = self.lu.solve(C)
             self.S = self.A_GG - C.T @ X
-            xb = self.lu.solve(np.concatenate([self.f_I, self.h_p, [0.0]]))
+            xb = self.lu.solve(self._rhs_I())
             self.g = self.f_G - C.T @ xb
         # p0 row: B0_Gamma = sum of the element flux rows on the interface
         self.B0 = np.asarray(Bp_G.sum(axis=0)).ravel()
         self.g0 = float(self.h_p.sum())
         self.vol = float(w.sum())
 
-    def recover(self, uG, p0):
-        """Interior velocity and element pressures from (u_Gamma, p0)."""
-        rhs = np.concatenate([self.f_I, self.h_p, [0.0]]) - self.C @ uG
-        x = self.lu.solve(rhs)
+    def _rhs_I(self):
+        tail = [0.0] if self.has_p0 else []
+        return np.concatenate([self.f_I, self.h_p, tail])
+
+    def recover(self, uG, p0=0.0):
+        """Interior velocity and element pressures from (u_Gamma, p0); p0 is
+        ignored for a subdomain that keeps its pressures local."""
+        x = self.lu.solve(self._rhs_I() - self.C @ uG)
         uI = x[: self.nv]
-        c = x[self.nv: self.nv + self.npr] + p0
-        return uI, c
+        c = x[self.nv: self.nv + self.npr]
+        return uI, (c + p0 if self.has_p0 else c)
 
 
 class OracleBDDC:
@@ -116,13 +130,18 @@ class OracleBDDC:
                  adaptive_edges=False, dense_local=False):
         self.wl = wl
         self.pressure_kernel = bool(wl.get("pressure_kernel", True))
-        if not self.pressure_kernel:
-            raise NotImplementedError(
-                "workload with Neumann sides: the condensation keeps each subdomain's constant "
-                "pressure coupled only through its interface fluxes")
+        nsub = len(wl["subs"])
+        has_p0 = np.asarray(wl.get("has_p0", np.ones(nsub)), bool)
+        if has_p0.shape != (nsub,) or bool(has_p0.all()) != self.pressure_kernel:
+            raise ValueError("has_p0 must flag every subdomain, and leave some subdomain "
+                             "without p0 exactly when the problem has Neumann sides")
         self.nG = wl["n_iface"]
-        self.loc = [LocalSchur(sd, dense=dense_local) for sd in wl["subs"]]
-        self.N = len(self.loc)
+        self.loc = [LocalSchur(sd, dense=dense_local, has_p0=h) for sd, h in zip(wl["subs"], has_p0)]
+        # p0 unknowns: one per subdomain that keeps its constant pressure
+        self.p0_sub = np.nonzero(has_p0)[0]
+        self.p0_pos = -np.ones(nsub, np.int64)
+        self.p0_pos[self.p0_sub] = np.arange(len(self.p0_sub))
+        self.N = len(self.p0_sub)
         self.n = self.nG + self.N  # global interface vector: u_Gamma then p0
         self.svd_tol = svd_tol
         self.scaling = scaling
@@ -227,12 +246,15 @@ class OracleBDDC:
             SPi = L.St[np.ix_(P, P)] + S_DP.T @ L.Phi
             c = cidx[L.gid[P]]
             Kc[np.ix_(c, c)] += SPi
+            if not L.has_p0:
+                continue
             # B0 in primal coordinates (the dual part vanishes: Assumption 1)
-            Kc[self.nc + i, c] += L.B0t[P]
-            Kc[c, self.nc + i] += L.B0t[P]
+            q = self.nc + self.p0_pos[i]
+            Kc[q, c] += L.B0t[P]
+            Kc[c, q] += L.B0t[P]
             L.B0_dual_norm = np.abs(L.B0t[Dl]).max() if len(Dl) else 0.0
         if self.pressure_kernel:
-            vol = np.array([L.vol for L in self.loc])
+            vol = np.array([self.loc[i].vol for i in self.p0_sub])
             Kc[-1, self.nc: self.nc + self.N] = vol
             Kc[self.nc: self.nc + self.N, -1] = vol
         self.Kc = Kc
@@ -244,7 +266,8 @@ class OracleBDDC:
         g = np.zeros(self.n)
         for i, L in enumerate(self.loc):
             np.add.at(g, L.gid, L.g)
-            g[self.nG + i] = L.g0
+            if L.has_p0:
+                g[self.nG + self.p0_pos[i]] = L.g0
         return g
 
     def apply_S(self, x):
@@ -252,9 +275,12 @@ class OracleBDDC:
         y = np.zeros(self.n)
         for i, L in enumerate(self.loc):
             xl = x[L.gid]
-            p0 = x[self.nG + i]
-            np.add.at(y, L.gid, L.S @ xl + L.B0 * p0)
-            y[self.nG + i] = L.B0 @ xl
+            if not L.has_p0:
+                np.add.at(y, L.gid, L.S @ xl)
+                continue
+            q = self.nG + self.p0_pos[i]
+            np.add.at(y, L.gid, L.S @ xl + L.B0 * x[q])
+            y[q] = L.B0 @ xl
         return y
 
     def apply_M(self, r):
@@ -302,7 +328,8 @@ class OracleBDDC:
         """Per-subdomain (u_I, element pressures) from the interface solution."""
         out = []
         for i, L in enumerate(self.loc):
-            out.append(L.recover(x[L.gid], x[self.nG + i]))
+            p0 = x[self.nG + self.p0_pos[i]] if L.has_p0 else 0.0
+            out.append(L.recover(x[L.gid], p0))
         return out
 
     def dense_S(self):
@@ -311,6 +338,8 @@ class OracleBDDC:
         for i, L in enumerate(self.loc):
             g = L.gid
             S[np.ix_(g, g)] += L.S
-            S[self.nG + i, g] += L.B0
-            S[g, self.nG + i] += L.B0
+            if L.has_p0:
+                q = self.nG + self.p0_pos[i]
+                S[q, g] += L.B0
+                S[g, q] += L.B0
         return S

@@ -367,9 +367,9 @@ def test_neumann_problem_has_no_pressure_kernel():
     """With two Neumann sides the reduced system is nonsingular without the
     mean-pressure constraint (the constant pressure is not in its kernel,
     unlike the no-slip problem), and the direct solve satisfies it; the
-    workload carries the flag through decomposition and storage, and the
-    oracle and the library binding refuse it (their condensation assumes
-    the no-slip structure)."""
+    workload carries the flags through decomposition and storage, and the
+    library binding refuses it (its condensation assumes the no-slip
+    structure)."""
     m = CubeMesh(4, jitter=0.15, seed=2)
     pb = Problem(m, 2, neumann_sides=(0, 1))
     assert not pb.pressure_kernel
@@ -393,10 +393,11 @@ def test_neumann_problem_has_no_pressure_kernel():
     with tempfile.TemporaryDirectory() as d:
         path = os.path.join(d, "wl.npz")
         save_workload(path, wl)
-        assert load_workload(path)["pressure_kernel"] is False
-    from oracle.bddc import OracleBDDC
-    with pytest.raises(NotImplementedError):
-        OracleBDDC(wl)
+        back = load_workload(path)
+        assert back["pressure_kernel"] is False
+        assert np.array_equal(back["has_p0"], wl["has_p0"])
+    # every subdomain of a 2 x 2 x 1 split has a side on x = 0 or x = 1
+    assert not wl["has_p0"].any()
     from paper_2304_09770_amd import binding
     with pytest.raises(NotImplementedError):
         binding.vb_assemble(None, wl)

@@ -6,6 +6,7 @@ case, the minimum eigenvalue 1 of Theorem teoEst, symmetry of M^-1 and the
 import numpy as np
 import pytest
 import scipy.linalg as sla
+import scipy.sparse as sp
 
 from inputs.mesh import CubeMesh
 from inputs.assemble import Problem
@@ -335,3 +336,41 @@ def test_dense_local_factors_agree_with_sparse(tiny_jit):
     assert rel(od.apply_S(x), o.apply_S(x)) < 1e-12
     r = o.apply_S(x)
     assert rel(od.apply_M(r)[: o.nG], o.apply_M(r)[: o.nG]) < 1e-11
+
+
+@pytest.mark.parametrize("parts", [(3, 2, 2), (2, 2, 1)])
+def test_neumann_sides_match_direct_solve(parts):
+    """Neumann sides x = 0 and x = 1 (Sec. 7): subdomains with a side on
+    them eliminate all their element pressures locally and keep no p0, the
+    others keep theirs, and the coarse problem has no border.  The flag
+    agrees with the flux structure it stands for (the summed pressure rows
+    of a subdomain vanish on its interior velocities exactly when it keeps
+    p0); PCG on the interface problem reaches the direct solve of the
+    assembled system, and recovery gives every subdomain's interior
+    velocity and pressures.  With (2, 2, 1) no subdomain keeps p0."""
+    n = 4
+    pb = Problem(CubeMesh(n, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=(0, 1))
+    dec = Decomposition(pb, regular_cuts(n, parts), FULL)
+    wl = dec.workload()
+    seg_x = np.arange(len(dec.subs)) % parts[0]
+    assert np.array_equal(wl["has_p0"], ((seg_x > 0) & (seg_x < parts[0] - 1)).astype(np.int32))
+    for sd, h in zip(wl["subs"], wl["has_p0"]):
+        m = len(sd["kind"])
+        K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(m, m))
+        flux = np.asarray(K[sd["kind"] == 2].sum(axis=0)).ravel()
+        inner = np.abs(flux[sd["kind"] == 0]).max()
+        assert (inner < 1e-12 * np.abs(flux).max()) == bool(h)
+    o = OracleBDDC(wl)
+    assert o.N == int(wl["has_p0"].sum()) and o.Kc.shape[0] == o.nc + o.N
+    x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-12)
+    u = pb.solve_reduced_direct()
+    uG, p0 = dec.interface_solution(u)
+    ref = np.concatenate([uG, p0])
+    assert np.linalg.norm(x - ref) < 1e-9 * np.linalg.norm(ref)
+    for sd, (uI, c) in zip(dec.subs, o.recover(x)):
+        ref_u = u[sd.dofs[sd.kind == 0]]
+        ref_p = u[sd.dofs[sd.kind == 2]]
+        assert np.linalg.norm(uI - ref_u) <= 1e-9 * np.linalg.norm(ref_u)
+        assert np.linalg.norm(c - ref_p) <= 1e-8 * max(np.linalg.norm(ref_u), np.linalg.norm(ref_p))
+    with pytest.raises(ValueError):
+        OracleBDDC(dict(wl, has_p0=np.ones(len(wl["subs"]), np.int32)))
