@@ -374,3 +374,26 @@ def test_neumann_sides_match_direct_solve(parts):
         assert np.linalg.norm(c - ref_p) <= 1e-8 * max(np.linalg.norm(ref_u), np.linalg.norm(ref_p))
     with pytest.raises(ValueError):
         OracleBDDC(dict(wl, has_p0=np.ones(len(wl["subs"]), np.int32)))
+
+
+@pytest.mark.parametrize("parts", [(3, 2, 2), (2, 2, 1)])
+def test_neumann_sides_spectrum(parts):
+    """With Neumann sides the interface problem loses the constant-p0
+    kernel: on the benign space (zero net flux out of every subdomain that
+    keeps p0; the whole space when none does, where S_hat is SPD) M^-1 S_hat
+    has no zero eigenvalue, and Theorem teoEst's bound lambda_min = 1 holds
+    as in the no-slip case.  The preconditioner stays symmetric."""
+    n = 4
+    pb = Problem(CubeMesh(n, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=(0, 1))
+    o = OracleBDDC(Decomposition(pb, regular_cuts(n, parts), FULL).workload())
+    M = np.array([o.apply_M(e) for e in np.eye(o.n)]).T
+    assert np.abs(M - M.T).max() < 1e-12 * np.abs(M).max()
+    S = o.dense_S()
+    if o.N == 0:
+        assert np.linalg.eigvalsh(S).min() > 0
+        V = np.eye(o.n)
+    else:
+        V = sla.null_space(S[o.nG:, :])
+    ev = sla.eigvals(V.T @ M @ S @ V)
+    assert np.abs(ev.imag).max() < 1e-9 * np.abs(ev).max()
+    assert ev.real.min() > 1 - 1e-10
