@@ -10,7 +10,7 @@ import scipy.sparse as sp
 
 from inputs.mesh import CubeMesh
 from inputs.assemble import Problem
-from inputs.decompose import Decomposition, regular_cuts
+from inputs.decompose import Decomposition, regular_cuts, random_cuts
 from oracle.bddc import OracleBDDC
 from oracle.pcg import pcg, lanczos_extremes
 
@@ -338,22 +338,35 @@ def test_dense_local_factors_agree_with_sparse(tiny_jit):
     assert rel(od.apply_M(r)[: o.nG], o.apply_M(r)[: o.nG]) < 1e-11
 
 
-@pytest.mark.parametrize("parts", [(3, 2, 2), (2, 2, 1)])
-def test_neumann_sides_match_direct_solve(parts):
-    """Neumann sides x = 0 and x = 1 (Sec. 7): subdomains with a side on
-    them eliminate all their element pressures locally and keep no p0, the
-    others keep theirs, and the coarse problem has no border.  The flag
-    agrees with the flux structure it stands for (the summed pressure rows
-    of a subdomain vanish on its interior velocities exactly when it keeps
-    p0); PCG on the interface problem reaches the direct solve of the
+NEUMANN_CASES = [  # (mesh size, Neumann sides, cuts)
+    (4, (0, 1), lambda: regular_cuts(4, (3, 2, 2))),  # 4 of 12 subdomains keep p0
+    (4, (0, 1), lambda: regular_cuts(4, (2, 2, 1))),  # none does
+    (4, (2, 5), lambda: regular_cuts(4, (2, 3, 2))),
+    (5, (4,), lambda: random_cuts(5, 1, 3, 2, 1)),    # uneven cuts
+]
+
+
+@pytest.mark.parametrize("case", range(len(NEUMANN_CASES)))
+def test_neumann_sides_match_direct_solve(case):
+    """Neumann sides (Sec. 7): subdomains with a side on them eliminate all
+    their element pressures locally and keep no p0, the others keep theirs,
+    and the coarse problem has no border.  The flag agrees with the box
+    position and with the flux structure it stands for (the summed pressure
+    rows of a subdomain vanish on its interior velocities exactly when it
+    keeps p0); PCG on the interface problem reaches the direct solve of the
     assembled system, and recovery gives every subdomain's interior
-    velocity and pressures.  With (2, 2, 1) no subdomain keeps p0."""
-    n = 4
-    pb = Problem(CubeMesh(n, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=(0, 1))
-    dec = Decomposition(pb, regular_cuts(n, parts), FULL)
+    velocity and pressures."""
+    n, sides, make_cuts = NEUMANN_CASES[case]
+    cuts = make_cuts()
+    pb = Problem(CubeMesh(n, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=sides)
+    dec = Decomposition(pb, cuts, FULL)
     wl = dec.workload()
-    seg_x = np.arange(len(dec.subs)) % parts[0]
-    assert np.array_equal(wl["has_p0"], ((seg_x > 0) & (seg_x < parts[0] - 1)).astype(np.int32))
+    parts = [len(c) - 1 for c in cuts]
+    for s, h in enumerate(wl["has_p0"]):
+        seg = (s % parts[0], (s // parts[0]) % parts[1], s // (parts[0] * parts[1]))
+        touched = {2 * a for a in range(3) if seg[a] == 0} | \
+                  {2 * a + 1 for a in range(3) if seg[a] == parts[a] - 1}
+        assert bool(h) == (not touched & set(sides))
     for sd, h in zip(wl["subs"], wl["has_p0"]):
         m = len(sd["kind"])
         K = sp.csr_matrix((sd["data"], sd["indices"], sd["indptr"]), shape=(m, m))
