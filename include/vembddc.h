@@ -252,7 +252,13 @@ const char *vb_last_error(const vb_ctx *ctx);
  * outside 0..n_iface-1 or not covered by exactly one entity, a subdomain
  * holding part of an entity, fewer than two pressures, or a pressure weight
  * (element volume) that is not positive; a failed call leaves the context
- * as it was.  VB_ERR_STATE after vb_setup. */
+ * as it was.  VB_ERR_STATE after vb_setup.
+ * The split of each subdomain's pressures into a mean-zero part and a
+ * global constant p0 (eq. discVQ) assumes no-slip boundaries: a subdomain's
+ * summed pressure rows must vanish on its interior velocity DoFs, so that
+ * p0 tests only interface fluxes.  Problems with natural (Neumann) boundary
+ * sides break that for the subdomains touching them and are not supported;
+ * the library does not detect them. */
 int vb_assemble(vb_ctx *ctx, int64_t n_iface, int n_sub, const vb_subdomain *subs,
                 int n_ent, const vb_entity *ents);
 
