@@ -401,3 +401,33 @@ def test_neumann_problem_has_no_pressure_kernel():
     from paper_2304_09770_amd import binding
     with pytest.raises(NotImplementedError):
         binding.vb_assemble(None, wl)
+
+
+@pytest.mark.parametrize("n,cuts,sides", [
+    (8, lambda: regular_cuts(8, (2, 2, 2)), ()),
+    (6, lambda: random_cuts(6, 1, 3, 3, 2), ()),
+    (6, lambda: regular_cuts(6, (3, 2, 2)), (0, 1)),
+    (5, lambda: random_cuts(5, 1, 3, 2, 1), (4,)),
+])
+def test_entities_are_the_classes_of_shared_dofs(n, cuts, sides):
+    """Interface entities (Sec. 5.1) are the classes of interface DoFs
+    shared by the same set of subdomains: the decomposition's geometric
+    classification (cut planes, their lines and points; Neumann sides
+    uncut) must give exactly that partition, and every entity's subdomain
+    list must be the set its DoFs are shared by."""
+    pb = Problem(CubeMesh(n, jitter=0.1, seed=1), 2, workers=1, neumann_sides=sides)
+    dec = Decomposition(pb, cuts(), ("vertex", "edge", "face", "flux"))
+    mask = {}
+    for s, sd in enumerate(dec.subs):
+        for d in sd.dofs[sd.kind == 1]:
+            mask[int(d)] = mask.get(int(d), 0) | (1 << s)
+    assert sorted(mask) == sorted(int(r) for r in dec.iface_red)
+    assert all(bin(m).count("1") >= 2 for m in mask.values())
+    classes = {}
+    for r, m in mask.items():
+        classes.setdefault(m, set()).add(r)
+    ents = [set(int(r) for r in dec.iface_red[g]) for g in dec.ent_dofs]
+    assert sorted(map(sorted, ents)) == sorted(map(sorted, classes.values()))
+    for e, g in enumerate(dec.ent_dofs):
+        m = mask[int(dec.iface_red[g[0]])]
+        assert set(dec.ent_subs[e].tolist()) == {s for s in range(len(dec.subs)) if m >> s & 1}
