@@ -416,7 +416,9 @@ def _preconditioner_by_definition(o, r):
     """M^-1 r of eq. BDDCprec written out densely: R~_D^T S~^-1 R~_D, with S~
     the partially assembled bordered operator on (global primal coordinates,
     each subdomain's own dual coordinates, each subdomain's p0), the
-    constant-p0 kernel fixed by the volume border, and R~_D passing primal
+    constant-p0 kernel fixed by the volume border (no-slip boundaries; with
+    Neumann sides only the subdomains away from them have p0 and there is
+    no border), and R~_D passing primal
     and p0 entries through and scaling the duals by D^T (all in the
     transformed coordinates)."""
     off, pos_of = [], []
@@ -432,16 +434,19 @@ def _preconditioner_by_definition(o, r):
         ix[L.prim] = o.cidx[L.gid[L.prim]]
         ix[~L.prim] = off[i] + np.arange(len(L.Dl))
         idx.append(ix)
-    St = np.zeros((m + 1, m + 1))
+    nb = m + (1 if o.pressure_kernel else 0)
+    St = np.zeros((nb, nb))
     for i, L in enumerate(o.loc):
         St[np.ix_(idx[i], idx[i])] += L.St
-        St[q0 + o.p0_pos[i], idx[i]] += L.B0t
-        St[idx[i], q0 + o.p0_pos[i]] += L.B0t
-    vol = np.array([o.loc[i].vol for i in o.p0_sub])
-    St[m, q0:m] = vol
-    St[q0:m, m] = vol
+        if L.has_p0:
+            St[q0 + o.p0_pos[i], idx[i]] += L.B0t
+            St[idx[i], q0 + o.p0_pos[i]] += L.B0t
+    if o.pressure_kernel:
+        vol = np.array([o.loc[i].vol for i in o.p0_sub])
+        St[m, q0:m] = vol
+        St[q0:m, m] = vol
     rt = np.concatenate([o.T.T @ r[:o.nG], r[o.nG:]])
-    Rd = np.zeros((m + 1, o.n))  # R~_D in the transformed coordinates
+    Rd = np.zeros((nb, o.n))  # R~_D in the transformed coordinates
     gpr = np.nonzero(o.is_primal)[0]
     Rd[o.cidx[gpr], gpr] = 1.0
     Rd[q0 + np.arange(o.N), o.nG + np.arange(o.N)] = 1.0
@@ -453,14 +458,20 @@ def _preconditioner_by_definition(o, r):
     return np.concatenate([o.T @ zt[:o.nG], zt[o.nG:]])
 
 
-@pytest.mark.parametrize("scaling", ["deluxe", "counting"])
-def test_preconditioner_equals_its_definition(scaling):
+@pytest.mark.parametrize("scaling,sides", [("deluxe", ()), ("counting", ()), ("deluxe", (0, 1))])
+def test_preconditioner_equals_its_definition(scaling, sides):
     """The oracle applies M^-1 as local constrained Neumann solves plus the
     coarse problem in the primal variables and p0; that split must equal
     eq. BDDCprec with S~^-1 taken whole (a dense solve of the partially
     assembled operator).  A dropped Phi term, a coarse matrix without the
     Schur complement part, or a wrong scaling side fails it."""
-    pb, dec, o = _setup(4, (2, 2, 2), FULL, jitter=0.15, seed=7, scaling=scaling)
+    if sides:
+        pb = Problem(CubeMesh(4, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=sides)
+        o = OracleBDDC(Decomposition(pb, regular_cuts(4, (3, 2, 2)), FULL).workload(),
+                       scaling=scaling)
+        assert 0 < o.N < len(o.loc)
+    else:
+        pb, dec, o = _setup(4, (2, 2, 2), FULL, jitter=0.15, seed=7, scaling=scaling)
     rng = np.random.default_rng(3)
     for _ in range(3):
         r = rng.standard_normal(o.n)
