@@ -478,3 +478,38 @@ def test_preconditioner_equals_its_definition(scaling, sides):
         got = o.apply_M(r)
         ref = _preconditioner_by_definition(o, r)
         assert np.linalg.norm(got - ref) <= 1e-10 * np.linalg.norm(ref)
+
+
+def test_change_of_basis_makes_constraints_explicit(tiny_jit):
+    """Sec. 4.3 and 5.1: per entity the basis [Q_Pi | Q_Delta] is orthogonal,
+    has as many primal columns as the constraint rows have rank (dependent
+    rows dropped; the rank counted here by Gram-Schmidt), every constraint
+    vanishes on the dual columns, and the constraint values of any vector
+    depend only on its primal coordinates.  The global T is orthogonal and
+    maps each entity's DoFs to themselves."""
+    pb, dec, o = tiny_jit
+    rng = np.random.default_rng(11)
+    for e, E in enumerate(o.ents):
+        C = np.asarray(E["con"])
+        Q = o.Q[e]
+        nE = len(E["gids"])
+        assert np.abs(Q.T @ Q - np.eye(nE)).max() < 1e-13
+        basis = []
+        for row in C:
+            v = row.copy()
+            for b in basis:
+                v -= (b @ v) * b
+            if np.linalg.norm(v) > 1e-9 * np.linalg.norm(row):
+                basis.append(v / np.linalg.norm(v))
+        assert o.npi[e] == len(basis)
+        if len(C):
+            scale = np.abs(C).max()
+            if o.npi[e] < nE:
+                assert np.abs(C @ Q[:, o.npi[e]:]).max() < 1e-12 * scale
+            u = rng.standard_normal(nE)
+            up = Q[:, :o.npi[e]] @ (Q[:, :o.npi[e]].T @ u)
+            assert np.abs(C @ u - C @ up).max() < 1e-12 * scale * np.abs(u).sum()
+    assert np.abs(o.T.T @ o.T - np.eye(o.nG)).max() < 1e-13
+    for e, E in enumerate(o.ents):
+        others = np.setdiff1d(np.arange(o.nG), E["gids"])
+        assert not np.any(o.T[np.ix_(others, E["gids"])])
