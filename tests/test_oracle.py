@@ -513,3 +513,30 @@ def test_change_of_basis_makes_constraints_explicit(tiny_jit):
     for e, E in enumerate(o.ents):
         others = np.setdiff1d(np.arange(o.nG), E["gids"])
         assert not np.any(o.T[np.ix_(others, E["gids"])])
+
+
+def test_pcg_iterates_minimise_energy_over_krylov_space():
+    """What defines the k-th PCG iterate (the GPU parity tests compare
+    against it): from x0 = 0 it minimises the A-norm of the error over the
+    Krylov space K_k(M^-1 A, M^-1 b).  Here it is computed independently by
+    a Galerkin solve on an orthonormal basis of that space, for a random SPD
+    A and SPD M^-1; the recorded residual is the true one.  A wrong alpha or
+    beta, or a preconditioner applied on the wrong side, fails it."""
+    rng = np.random.default_rng(8)
+    n = 40
+    G = rng.standard_normal((n, n))
+    A = G @ G.T + n * np.eye(n)
+    H = rng.standard_normal((n, n))
+    Minv = H @ H.T + 0.5 * n * np.eye(n)
+    b = rng.standard_normal(n)
+    xs = np.linalg.solve(A, b)
+    for k in range(1, 8):
+        x, info = pcg(lambda v: A @ v, lambda v: Minv @ v, b, fixed_iters=k)
+        K = [Minv @ b]
+        for _ in range(k - 1):
+            K.append(Minv @ (A @ K[-1]))
+        V, _ = np.linalg.qr(np.array(K).T)
+        ref = V @ np.linalg.solve(V.T @ A @ V, V.T @ b)
+        assert np.linalg.norm(x - ref) <= 1e-10 * np.linalg.norm(xs)
+        assert info["iters"] == k
+        assert abs(info["resid"][-1] - np.linalg.norm(b - A @ x) / np.linalg.norm(b)) <= 1e-10
