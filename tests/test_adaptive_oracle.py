@@ -170,3 +170,23 @@ def test_edge_enrichment_lowers_the_condition_number(floating):
         assert np.linalg.norm(x - ref) <= 1e-6 * np.linalg.norm(ref)
         k2[edges] = lmax / lmin
     assert k2[True] < k2[False], k2
+
+
+def test_adaptive_space_with_neumann_sides():
+    """Sec. 6 on the paper's boundary conditions (Neumann sides x = 0 and
+    x = 1, where subdomains touching them keep no p0): the enriched space
+    keeps the direct solve's solution and lowers the condition number of
+    the minimal space, with lambda_min still at least 1."""
+    pb = Problem(CubeMesh(4, jitter=0.15, seed=3), 2, 1.0, workers=1, neumann_sides=(0, 1))
+    dec = Decomposition(pb, regular_cuts(4, (3, 2, 2)), ("vertex", "edge", "flux"))
+    wl = dec.workload()
+    ref = np.concatenate(dec.interface_solution(pb.solve_reduced_direct()))
+    kappa = []
+    for theta in (0.0, 0.5):
+        o = OracleBDDC(wl, adaptive_theta=theta)
+        x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-12)
+        assert np.linalg.norm(x - ref) < 1e-9 * np.linalg.norm(ref)
+        lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
+        assert lmin > 1 - 1e-8
+        kappa.append(lmax / lmin)
+    assert kappa[1] < 0.75 * kappa[0]
