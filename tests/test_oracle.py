@@ -241,9 +241,10 @@ def test_min_eigenvalue_bound_degree_4():
 
 def test_ritz_lambda_min_and_log_trend():
     """Ritz values of the CG-Lanczos matrix stay >= 1 and, for the minimal
-    coarse space, k_2 / (1 + log(H/h))^2 does not grow along H/h = 2,4,6."""
+    coarse space, k_2 / (1 + log(H/h))^2 does not grow along H/h = 2, 4, 5
+    (k_2 itself grows from 2.3 to 9.1)."""
     ratios = []
-    for n in (4, 8, 12):
+    for n in (4, 8, 10):
         pb, dec, o = _setup(n, (2, 2, 2), MIN)
         x, info = pcg(o.apply_S, o.apply_M, o.rhs(), tol=1e-10)
         lmin, lmax = lanczos_extremes(info["alphas"], info["betas"])
